@@ -1,0 +1,294 @@
+"""ctypes binding of the FP64 CPU oracle (test infrastructure only).
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg import this
+module.  The product path (the HIP library and its Python binding) never does.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+P, H, N = 24, 4, 16
+
+
+class _Params(C.Structure):
+    _fields_ = [("gamma", C.c_double), ("B", C.c_double), ("cfl", C.c_double),
+                ("eps", C.c_double), ("scale_rho", C.c_double), ("scale_E", C.c_double),
+                ("dx0", C.c_double), ("lmax", C.c_int32), ("n0", C.c_int32 * 3),
+                ("bc", C.c_int32 * 3), ("adapt", C.c_int32)]
+
+
+IC_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                    C.POINTER(C.c_double))
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        path = os.path.join(HERE, "liborc.so")
+        if not os.path.exists(path):
+            from . import build as _b  # noqa: F401  (package-relative when imported as oracle.oracle)
+            _b.build()
+        L = C.CDLL(path)
+        d, i32, vp = C.c_double, C.c_int32, C.c_void_p
+        pd = C.POINTER(C.c_double)
+        L.orc_pressure.argtypes = [pd, d, d]
+        L.orc_pressure.restype = d
+        L.orc_flux_x.argtypes = [pd, d, d, pd]
+        L.orc_roe_matrices.argtypes = [pd, pd, d, d, pd, pd]
+        L.orc_weno5_minus.argtypes = [d] * 5
+        L.orc_weno5_minus.restype = d
+        L.orc_face_flux_x.argtypes = [pd, d, d, pd]
+        L.orc_face_flux_x.restype = C.c_int
+        L.orc_face_flux.argtypes = [C.c_int, pd, d, d, pd]
+        L.orc_face_flux.restype = C.c_int
+        L.orc_predict_cell.argtypes = [pd] + [C.c_int] * 6
+        L.orc_predict_cell.restype = d
+        L.orc_average8.argtypes = [pd]
+        L.orc_average8.restype = d
+        L.orc_ssprk3_stage.argtypes = [C.c_int, d, d, d, d]
+        L.orc_ssprk3_stage.restype = d
+        L.orc_exact_riemann.argtypes = [d] * 7 + [pd, C.c_int, pd]
+        L.orc_exact_riemann.restype = C.c_int
+        L.orc_sim_create.argtypes = [C.POINTER(_Params)]
+        L.orc_sim_create.restype = vp
+        L.orc_sim_free.argtypes = [vp]
+        L.orc_sim_init.argtypes = [vp, IC_FN, vp]
+        L.orc_sim_init.restype = C.c_int
+        L.orc_sim_step.argtypes = [vp, pd]
+        L.orc_sim_step.restype = C.c_int
+        L.orc_sim_nblocks.argtypes = [vp]
+        L.orc_sim_nblocks.restype = i32
+        L.orc_sim_blocks.argtypes = [vp, C.POINTER(C.c_int64)]
+        L.orc_sim_get_block.argtypes = [vp, i32, pd]
+        L.orc_sim_set_block.argtypes = [vp, i32, pd]
+        L.orc_sim_detail.argtypes = [vp, i32]
+        L.orc_sim_detail.restype = d
+        L.orc_sim_refine.argtypes = [vp, i32, i32, i32, i32]
+        L.orc_sim_refine.restype = C.c_int
+        L.orc_sim_coarsen.argtypes = [vp, i32, i32, i32, i32]
+        L.orc_sim_coarsen.restype = C.c_int
+        L.orc_sim_project.argtypes = [vp]
+        L.orc_sim_fill_halos.argtypes = [vp]
+        L.orc_sim_rhs.argtypes = [vp, pd]
+        L.orc_sim_rhs.restype = i32
+        L.orc_sim_details.argtypes = [vp, pd, C.POINTER(C.c_int8)]
+        L.orc_sim_dt.argtypes = [vp]
+        L.orc_sim_dt.restype = d
+        L.orc_sim_totals.argtypes = [vp, pd]
+        L.orc_sim_time.argtypes = [vp]
+        L.orc_sim_time.restype = d
+        L.orc_sim_llf_fraction.argtypes = [vp]
+        L.orc_sim_llf_fraction.restype = d
+        L.orc_morton_encode.argtypes = [i32] * 5
+        L.orc_morton_encode.restype = C.c_uint64
+        L.orc_morton_neighbor.argtypes = [C.c_uint64, i32, i32, C.POINTER(i32)]
+        L.orc_morton_neighbor.restype = C.c_uint64
+        L.orc_morton_level.argtypes = [C.c_uint64, i32]
+        L.orc_morton_level.restype = i32
+        _LIB = L
+    return _LIB
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+# ------------------------------------------------------------------- pointwise -------
+
+def pressure(U, gamma=1.4, B=0.0) -> float:
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    return lib().orc_pressure(_dp(U), gamma, B)
+
+
+def flux_x(U, gamma=1.4, B=0.0) -> np.ndarray:
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    F = np.zeros(5)
+    lib().orc_flux_x(_dp(U), gamma, B, _dp(F))
+    return F
+
+
+def roe_matrices(UL, UR, gamma=1.4, B=0.0):
+    UL = np.ascontiguousarray(UL, dtype=np.float64)
+    UR = np.ascontiguousarray(UR, dtype=np.float64)
+    R = np.zeros(25)
+    L = np.zeros(25)
+    lib().orc_roe_matrices(_dp(UL), _dp(UR), gamma, B, _dp(R), _dp(L))
+    return R.reshape(5, 5), L.reshape(5, 5)
+
+
+def weno5_minus(a, b, c, d, e) -> float:
+    return lib().orc_weno5_minus(float(a), float(b), float(c), float(d), float(e))
+
+
+def face_flux(d: int, st, gamma=1.4, B=0.0):
+    st = np.ascontiguousarray(st, dtype=np.float64).reshape(30)
+    F = np.zeros(5)
+    n = lib().orc_face_flux(d, _dp(st), gamma, B, _dp(F))
+    return F, n
+
+
+def predict_cell(parent_padded: np.ndarray, octant, i, j, k) -> float:
+    a = np.ascontiguousarray(parent_padded, dtype=np.float64)
+    assert a.shape == (P, P, P)
+    return lib().orc_predict_cell(_dp(a), int(octant[0]), int(octant[1]), int(octant[2]), i, j, k)
+
+
+def average8(c) -> float:
+    c = np.ascontiguousarray(c, dtype=np.float64).reshape(8)
+    return lib().orc_average8(_dp(c))
+
+
+def ssprk3_stage(stage, u0, us, L, dt) -> float:
+    return lib().orc_ssprk3_stage(stage, u0, us, L, dt)
+
+
+def exact_riemann(left, right, gamma, s) -> np.ndarray:
+    s = np.ascontiguousarray(s, dtype=np.float64)
+    out = np.zeros((len(s), 3))
+    rc = lib().orc_exact_riemann(*left, *right, gamma, _dp(s), len(s), _dp(out))
+    if rc != 0:
+        raise RuntimeError("exact Riemann solver did not converge")
+    return out
+
+
+def morton_encode(shadow, level, bx, by, bz) -> int:
+    return int(lib().orc_morton_encode(shadow, level, bx, by, bz))
+
+
+def morton_neighbor(mid: int, d: int, direction: int):
+    w = C.c_int32(0)
+    n = lib().orc_morton_neighbor(C.c_uint64(mid), d, direction, C.byref(w))
+    return int(n), bool(w.value)
+
+
+def morton_level(mid: int, shadow: int) -> int:
+    return int(lib().orc_morton_level(C.c_uint64(mid), shadow))
+
+
+# ------------------------------------------------------------------ simulation -------
+
+class Sim:
+    """One oracle MR simulation of a workloads.Problem."""
+
+    def __init__(self, problem, adapt=None):
+        self.problem = problem
+        p = _Params()
+        p.gamma, p.B, p.cfl, p.eps = problem.gamma, problem.B, problem.cfl, problem.eps
+        p.scale_rho, p.scale_E, p.dx0 = problem.scale_rho, problem.scale_E, problem.dx0
+        p.lmax = problem.lmax
+        for a in range(3):
+            p.n0[a] = problem.n0[a]
+            p.bc[a] = problem.bc[a]
+        p.adapt = problem.adapt if adapt is None else int(adapt)
+        self._p = p
+        self.h = lib().orc_sim_create(C.byref(p))
+        self._cb = None
+
+    def close(self):
+        if self.h:
+            lib().orc_sim_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init(self, ic=None):
+        """algo:Init with the problem's initial condition (or a custom ic(level,bx,by,bz))."""
+        gen = ic if ic is not None else self.problem.primitives
+
+        def cb(user, level, bx, by, bz, prim):
+            arr = np.ctypeslib.as_array(prim, shape=(5 * N * N * N,))
+            arr[:] = np.asarray(gen(level, bx, by, bz), dtype=np.float64).reshape(-1)
+
+        self._cb = IC_FN(cb)
+        rc = lib().orc_sim_init(self.h, self._cb, None)
+        if rc != 0:
+            raise RuntimeError(f"oracle init failed ({rc})")
+        return self
+
+    def step(self) -> float:
+        dt = C.c_double(0.0)
+        rc = lib().orc_sim_step(self.h, C.byref(dt))
+        if rc != 0:
+            raise RuntimeError(f"oracle step failed ({rc}): non-physical state")
+        return dt.value
+
+    def blocks(self) -> np.ndarray:
+        n = lib().orc_sim_nblocks(self.h)
+        info = np.zeros((n, 8), dtype=np.int64)
+        lib().orc_sim_blocks(self.h, info.ctypes.data_as(C.POINTER(C.c_int64)))
+        return info
+
+    def block_index(self):
+        """dict (level, bx, by, bz) -> block index."""
+        return {tuple(int(v) for v in r[:4]): n for n, r in enumerate(self.blocks())}
+
+    def get_block(self, idx: int) -> np.ndarray:
+        out = np.zeros((5, P, P, P))
+        lib().orc_sim_get_block(self.h, idx, _dp(out))
+        return out
+
+    def set_block(self, idx: int, data: np.ndarray):
+        a = np.ascontiguousarray(data, dtype=np.float64)
+        assert a.shape == (5, P, P, P)
+        lib().orc_sim_set_block(self.h, idx, _dp(a))
+
+    def refine(self, level, bx, by, bz):
+        if lib().orc_sim_refine(self.h, level, bx, by, bz) != 0:
+            raise ValueError("cannot refine")
+
+    def coarsen(self, level, bx, by, bz):
+        if lib().orc_sim_coarsen(self.h, level, bx, by, bz) != 0:
+            raise ValueError("cannot coarsen")
+
+    def project(self):
+        lib().orc_sim_project(self.h)
+
+    def fill_halos(self):
+        lib().orc_sim_fill_halos(self.h)
+
+    def rhs(self) -> np.ndarray:
+        nleaf = int((self.blocks()[:, 4] == 1).sum())
+        out = np.zeros((nleaf, 5, N, N, N))
+        lib().orc_sim_rhs(self.h, _dp(out))
+        return out
+
+    def details(self):
+        n = lib().orc_sim_nblocks(self.h)
+        det = np.zeros(n)
+        fl = np.zeros(n, dtype=np.int8)
+        lib().orc_sim_details(self.h, _dp(det), fl.ctypes.data_as(C.POINTER(C.c_int8)))
+        return det, fl
+
+    def dt(self) -> float:
+        return lib().orc_sim_dt(self.h)
+
+    def totals(self) -> np.ndarray:
+        t = np.zeros(5)
+        lib().orc_sim_totals(self.h, _dp(t))
+        return t
+
+    @property
+    def time(self) -> float:
+        return lib().orc_sim_time(self.h)
+
+    @property
+    def llf_fraction(self) -> float:
+        return lib().orc_sim_llf_fraction(self.h)
+
+    def leaf_states(self):
+        """dict (level,bx,by,bz) -> interior state [5][16][16][16] of every leaf."""
+        out = {}
+        for n, r in enumerate(self.blocks()):
+            if r[4] == 1:
+                out[tuple(int(v) for v in r[:4])] = self.get_block(n)[:, H:H + N, H:H + N, H:H + N]
+        return out

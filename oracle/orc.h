@@ -1,0 +1,156 @@
+/*
+ * orc.h -- FP64 CPU oracle for the block-based multiresolution (MR) finite-volume
+ * solver of Hoppe, Adami & Adams, "A modular massively parallel computing environment
+ * for three-dimensional multiresolution simulations of compressible flows"
+ * (arXiv 2012.04385).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the plain, slow, obviously-correct
+ * reference the GPU path is checked against.  Only the test suite, the smoke check and
+ * the CPU-baseline leg of the benchmark may load it.  It shares no code with the HIP
+ * library (no headers, helpers, tables or generators) and the GPU library never calls it.
+ *
+ * Everything is double precision, compiled without floating-point contraction or
+ * fast-math, and parallelised only over independent blocks so results do not depend
+ * on the thread count.
+ *
+ * Conventions (the paper's block concept, Sec. "Modular block-based MR algorithm"):
+ *   a block holds 16^3 interior cells plus 4 halo layers per side: a padded 24^3 array
+ *   per conserved quantity, stored [q][z][y][x] with x fastest; interior index 4..19.
+ *   q = (rho, rho*u, rho*v, rho*w, E).
+ *
+ * Parity status per function is stated in the oracle section of the design doc; every
+ * function here is pinned by a CPU test (tests/test_oracle_*.py) against closed forms,
+ * invariants, exact rational arithmetic or brute force.
+ */
+#ifndef ORACLE_ORC_API_H
+#define ORACLE_ORC_API_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORC_IC 16   /* interior cells per block edge            */
+#define ORC_H 4     /* halo layers per side                     */
+#define ORC_P 24    /* padded edge = ORC_IC + 2*ORC_H           */
+
+/* ---------------- pointwise numerics (Sec. "Numerical Scheme", eq:StiffenedGas) ---- */
+
+/* Pressure of a conservative state, stiffened-gas EOS p = (gamma-1) rho e - gamma B. */
+double orc_pressure(const double U[5], double gamma, double B);
+
+/* Physical Euler flux along x of a conservative state. */
+void orc_flux_x(const double U[5], double gamma, double B, double F[5]);
+
+/* Roe-averaged right (R, columns = eigenvectors) and left (L = R^-1) eigenvector matrices
+ * of the x-direction flux Jacobian between states UL and UR, row-major 5x5. */
+void orc_roe_matrices(const double UL[5], const double UR[5], double gamma, double B,
+                      double R[25], double L[25]);
+
+/* WENO5-JS (Jiang & Shu) value at the right face of the middle point, left-biased. */
+double orc_weno5_minus(double a, double b, double c, double d, double e);
+
+/* Numerical flux through the x-face between cells 2 and 3 of a 6-cell stencil
+ * st[6][5] (cells i-2..i+3): characteristic WENO5-JS with per-field Roe upwinding and
+ * local Lax-Friedrichs fallback.  Returns the number of fields that used LLF. */
+int orc_face_flux_x(const double st[30], double gamma, double B, double F[5]);
+
+/* Same along axis d (0,1,2) for a stencil given in the physical component order. */
+int orc_face_flux(int d, const double st[30], double gamma, double B, double F[5]);
+
+/* ---------------- MR operators (eq:Averaging, eq:Prediction + appendix Q-terms) ------ */
+
+/* Fifth-order conservative prediction of one fine cell from a padded 24^3 parent array
+ * (one component).  (ox,oy,oz) = octant of the child inside the parent, (i,j,k) = the
+ * child's padded cell index, each in [0,24).  Implements the appendix Q-term sums. */
+double orc_predict_cell(const double *parent, int ox, int oy, int oz, int i, int j, int k);
+
+/* Conservative average of 8 fine values given in (x,y,z) child-offset order c[z][y][x]. */
+double orc_average8(const double c[8]);
+
+/* SSP-RK3 (Shu-Osher) stage s = 0,1,2 in increment form:
+ * u^(s+1) = u0 + a_s ((u^(s) - u0) + dt L(u^(s))), a = (1, 1/4, 2/3). */
+double orc_ssprk3_stage(int stage, double u0, double us, double L, double dt);
+
+/* ---------------- exact Riemann solver (textbook, Toro ch. 4) for the Sod pin ------- */
+
+/* Samples the exact solution of the 1D Riemann problem (ideal gas, B = 0) at x/t = s
+ * values; out[3*i..] = (rho, u, p).  Returns 0, or -1 if Newton failed. */
+int orc_exact_riemann(double rl, double ul, double pl, double rr, double ur, double pr,
+                      double gamma, const double *s, int n, double *out);
+
+/* ---------------- the MR simulation (algo:Init, algo:ComputeLoop with global dt) ---- */
+
+typedef struct {
+    double gamma, B;       /* EOS                                              */
+    double cfl;            /* CFL number k of eq:Cfl                           */
+    double eps;            /* threshold at the finest level (eq:UserEpsilon)   */
+    double scale_rho;      /* normalisation of the rho details                 */
+    double scale_E;        /* normalisation of the E details                   */
+    double dx0;            /* cell size on level 0                             */
+    int32_t lmax;          /* finest level                                     */
+    int32_t n0[3];         /* level-0 blocks per axis                          */
+    int32_t bc[3];         /* per axis: 0 periodic, 1 zero-gradient            */
+    int32_t adapt;         /* 1: refine/coarsen after each step                */
+} orc_params;
+
+typedef struct orc_sim orc_sim;
+
+/* IC callback: fill prim[5][16][16][16] = (rho,u,v,w,p) at the cell centres of the
+ * interior of block (level, bx, by, bz). */
+typedef void (*orc_ic_fn)(void *user, int32_t level, int32_t bx, int32_t by, int32_t bz,
+                          double *prim);
+
+orc_sim *orc_sim_create(const orc_params *p);
+void orc_sim_free(orc_sim *s);
+
+/* Bottom-up initialisation of algo:Init. 0 on success. */
+int orc_sim_init(orc_sim *s, orc_ic_fn ic, void *user);
+
+/* One global time step: CFL dt, three SSP-RK3 stages, then MR adaptation.
+ * Returns 0, or -5 when a non-physical state (rho<=0, p+B<=0, NaN) appeared. */
+int orc_sim_step(orc_sim *s, double *dt_out);
+
+/* Block table: n blocks; info[n][8] = (level, bx, by, bz, is_leaf, flag, morton, 0). */
+int32_t orc_sim_nblocks(const orc_sim *s);
+void orc_sim_blocks(const orc_sim *s, int64_t *info);
+/* Padded state of block idx (order of orc_sim_blocks), 5*24^3 values. */
+void orc_sim_get_block(const orc_sim *s, int32_t idx, double *out);
+void orc_sim_set_block(orc_sim *s, int32_t idx, const double *in);
+/* Last detail value of block idx (-1 for level 0). */
+double orc_sim_detail(const orc_sim *s, int32_t idx);
+
+/* Explicit tree edits and single operators, for operator-level parity tests.
+ * refine: fills all halos, then leaf -> 8 children whose interiors are P(parent);
+ * coarsen: remove the 8
+ * (leaf) children of a block.  Return 0 or -1. */
+int orc_sim_refine(orc_sim *s, int32_t level, int32_t bx, int32_t by, int32_t bz);
+int orc_sim_coarsen(orc_sim *s, int32_t level, int32_t bx, int32_t by, int32_t bz);
+void orc_sim_project(orc_sim *s);            /* parents <- A(children), bottom-up      */
+void orc_sim_fill_halos(orc_sim *s);         /* all 26 halo regions, coarse to fine    */
+/* Right-hand side L (5*16^3 per leaf, leaves in block order) incl. jump flux correction;
+ * halos must be filled. Returns number of leaves written. */
+int32_t orc_sim_rhs(orc_sim *s, double *L_out);
+/* Details of all blocks and resulting flags (block order); flags: 1 refine, 0 keep,
+ * -1 coarsen, 2 not a leaf.  Halos must be filled (26 regions). */
+void orc_sim_details(orc_sim *s, double *det_out, int8_t *flag_out);
+/* CFL time step from the current leaf state. */
+double orc_sim_dt(const orc_sim *s);
+/* Volume-weighted totals over leaf interior cells: tot[5]. */
+void orc_sim_totals(const orc_sim *s, double *tot);
+double orc_sim_time(const orc_sim *s);
+/* Fraction of face-fields that took the LLF branch during the last rhs evaluation. */
+double orc_sim_llf_fraction(const orc_sim *s);
+
+/* Morton ids with headbit (Sec. "Modular block-based MR algorithm", eq:NeigboorLookup).
+ * shadow = number of 3-bit groups above level 0 (level-0 blocks per edge = 2^shadow). */
+uint64_t orc_morton_encode(int32_t shadow, int32_t level, int32_t bx, int32_t by, int32_t bz);
+/* neighbour id along axis d (0,1,2) in direction dir (+1/-1) by bit flipping;
+ * *wrapped = 1 when the lookup left the domain (and wrapped around). */
+uint64_t orc_morton_neighbor(uint64_t id, int32_t d, int32_t dir, int32_t *wrapped);
+int32_t orc_morton_level(uint64_t id, int32_t shadow);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,713 @@
+// orc_tree.cpp -- the oracle's block-based MR simulation (test infrastructure only).
+//
+// Plain FP64 transcription of the paper's method with a global time step:
+//   * octree of fixed-size blocks (16^3 interior + 4 halo layers), addressed by Morton ids
+//     with a headbit in a hash map (Sec. "Modular block-based MR algorithm");
+//   * halo fill: copy from a same-level neighbour, else prediction from the parent
+//     (eq:Prediction), external boundaries afterwards (periodic = wrap, zero-gradient);
+//   * right-hand side from one numerical flux per face, with the coarse flux at a
+//     resolution jump replaced by the average of the fine fluxes (algo:ComputeLoop,
+//     coarse cell adjustment; applied every stage because the step is global);
+//   * SSP-RK3 stages, CFL time step (eq:Cfl), conservative averaging of parents
+//     (eq:Averaging) before every stage;
+//   * after each step: details (eq:DetailFunction as u_l - P(u_{l-1})), level-wise
+//     thresholds (eq:Thresholding, eq:LevelWiseEpsilon with D = 3), refine/coarsen;
+//   * bottom-up initialisation of algo:Init (including level l_max).
+#include "orc.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <unordered_map>
+#include <vector>
+
+namespace {
+
+constexpr int P = ORC_P, H = ORC_H, N = ORC_IC;
+constexpr int CELLS = P * P * P;
+constexpr int ICELLS = N * N * N;
+constexpr int PLANE = N * N;
+
+inline int at(int q, int k, int j, int i) { return ((q * P + k) * P + j) * P + i; }
+inline int ati(int q, int k, int j, int i) { return ((q * N + k) * N + j) * N + i; }
+
+struct Block {
+    int level = 0, bx = 0, by = 0, bz = 0;
+    uint64_t id = 0;
+    bool leaf = true;
+    double detail = -1.0;
+    int flag = 0;
+    std::vector<double> u;     // 5 * 24^3 current (stage) state
+    std::vector<double> u0;    // 5 * 16^3 state at t^n
+    std::vector<double> rhs;   // 5 * 16^3
+    std::vector<double> face[6];  // boundary face fluxes, 5 * 16 * 16 each
+    Block() : u(5 * CELLS, 0.0) {}
+};
+
+}  // namespace
+
+struct orc_sim {
+    orc_params p{};
+    int shadow = 0;
+    double time = 0.0;
+    double llf_fraction = 0.0;
+    std::unordered_map<uint64_t, Block *> map;
+    std::vector<Block *> order;  // blocks sorted by (level, id); rebuilt after edits
+    ~orc_sim() {
+        for (auto &kv : map) delete kv.second;
+    }
+};
+
+extern "C" {
+
+// ------------------------------------------------------------------ Morton ids -------
+
+uint64_t orc_morton_encode(int32_t shadow, int32_t level, int32_t bx, int32_t by, int32_t bz) {
+    const int groups = shadow + level;
+    uint64_t id = 1;  // headbit
+    for (int g = groups - 1; g >= 0; --g) {
+        const uint64_t x = (uint64_t)((bx >> g) & 1), y = (uint64_t)((by >> g) & 1),
+                       z = (uint64_t)((bz >> g) & 1);
+        id = (id << 3) | (z << 2) | (y << 1) | x;
+    }
+    return id;
+}
+
+static int id_groups(uint64_t id) {
+    int msb = 63;
+    while (msb > 0 && !((id >> msb) & 1ull)) --msb;
+    return msb / 3;
+}
+
+int32_t orc_morton_level(uint64_t id, int32_t shadow) { return id_groups(id) - shadow; }
+
+uint64_t orc_morton_neighbor(uint64_t id, int32_t d, int32_t dir, int32_t *wrapped) {
+    // eq:NeigboorLookup: remove the headbit, walk every third bit of axis d from the
+    // least significant group upwards, flipping until the carry (or borrow) stops.
+    const int groups = id_groups(id);
+    const int nbits = 3 * groups;
+    const uint64_t head = 1ull << nbits;
+    uint64_t n = id ^ head;
+    int f = 0;
+    for (int i = d; i < nbits; i += 3) {
+        const int bit = (int)((n >> i) & 1ull);
+        const int nb = !(bit ^ f);  // XNOR
+        n = (n & ~(1ull << i)) | ((uint64_t)nb << i);
+        f = (dir > 0) ? (nb | f) : ((!nb) | f);
+    }
+    if (wrapped) *wrapped = (f == 0);
+    return n | head;
+}
+
+}  // extern "C"
+
+namespace {
+
+int level_extent(const orc_params &p, int axis, int level) { return p.n0[axis] << level; }
+
+Block *find(orc_sim *s, int level, int bx, int by, int bz) {
+    auto it = s->map.find(orc_morton_encode(s->shadow, level, bx, by, bz));
+    return it == s->map.end() ? nullptr : it->second;
+}
+
+// Same-level neighbour position with external boundary handling.
+// Returns false when the position lies outside a zero-gradient boundary.
+bool neighbor_pos(const orc_sim *s, const Block *b, int dx, int dy, int dz, int out[3]) {
+    const int d[3] = {dx, dy, dz};
+    const int c[3] = {b->bx, b->by, b->bz};
+    for (int a = 0; a < 3; ++a) {
+        const int n = level_extent(s->p, a, b->level);
+        int v = c[a] + d[a];
+        if (v < 0 || v >= n) {
+            if (s->p.bc[a] != 0) return false;
+            v = (v + n) % n;
+        }
+        out[a] = v;
+    }
+    return true;
+}
+
+Block *parent_of(orc_sim *s, const Block *b) {
+    if (b->level == 0) return nullptr;
+    return find(s, b->level - 1, b->bx >> 1, b->by >> 1, b->bz >> 1);
+}
+
+Block *child_of(orc_sim *s, const Block *b, int ox, int oy, int oz) {
+    return find(s, b->level + 1, 2 * b->bx + ox, 2 * b->by + oy, 2 * b->bz + oz);
+}
+
+void rebuild_order(orc_sim *s) {
+    s->order.clear();
+    for (auto &kv : s->map) s->order.push_back(kv.second);
+    std::sort(s->order.begin(), s->order.end(), [](const Block *a, const Block *b) {
+        if (a->level != b->level) return a->level < b->level;
+        return a->id < b->id;
+    });
+}
+
+std::vector<Block *> blocks_on_level(orc_sim *s, int level) {
+    std::vector<Block *> v;
+    for (Block *b : s->order)
+        if (b->level == level) v.push_back(b);
+    return v;
+}
+
+Block *add_block(orc_sim *s, int level, int bx, int by, int bz) {
+    Block *b = new Block();
+    b->level = level;
+    b->bx = bx;
+    b->by = by;
+    b->bz = bz;
+    b->id = orc_morton_encode(s->shadow, level, bx, by, bz);
+    s->map[b->id] = b;
+    return b;
+}
+
+double eps_level(const orc_params &p, int level) {
+    // eq:LevelWiseEpsilon with D = 3.
+    return std::ldexp(p.eps, -3 * (p.lmax - level));
+}
+
+double dx_level(const orc_params &p, int level) { return std::ldexp(p.dx0, -level); }
+
+// ---------------------------------------------------------------- operators ----------
+
+void predict_interior(const Block *parent, Block *child) {
+    const int ox = child->bx & 1, oy = child->by & 1, oz = child->bz & 1;
+    for (int q = 0; q < 5; ++q) {
+        const double *pu = parent->u.data() + q * CELLS;
+        for (int k = H; k < H + N; ++k)
+            for (int j = H; j < H + N; ++j)
+                for (int i = H; i < H + N; ++i)
+                    child->u[at(q, k, j, i)] = orc_predict_cell(pu, ox, oy, oz, i, j, k);
+    }
+}
+
+void average_into_parent(orc_sim *s, Block *parent) {
+    for (int oz = 0; oz < 2; ++oz)
+        for (int oy = 0; oy < 2; ++oy)
+            for (int ox = 0; ox < 2; ++ox) {
+                const Block *c = child_of(s, parent, ox, oy, oz);
+                for (int q = 0; q < 5; ++q)
+                    for (int K = 0; K < N / 2; ++K)
+                        for (int J = 0; J < N / 2; ++J)
+                            for (int I = 0; I < N / 2; ++I) {
+                                double v[8];
+                                for (int cz = 0; cz < 2; ++cz)
+                                    for (int cy = 0; cy < 2; ++cy)
+                                        for (int cx = 0; cx < 2; ++cx)
+                                            v[cz * 4 + cy * 2 + cx] =
+                                                c->u[at(q, H + 2 * K + cz, H + 2 * J + cy,
+                                                        H + 2 * I + cx)];
+                                parent->u[at(q, H + oz * N / 2 + K, H + oy * N / 2 + J,
+                                             H + ox * N / 2 + I)] = orc_average8(v);
+                            }
+            }
+}
+
+void project(orc_sim *s) {
+    for (int l = s->p.lmax - 1; l >= 0; --l) {
+        std::vector<Block *> lv = blocks_on_level(s, l);
+#pragma omp parallel for schedule(static)
+        for (long n = 0; n < (long)lv.size(); ++n)
+            if (!lv[n]->leaf) average_into_parent(s, lv[n]);
+    }
+}
+
+void fill_block_halos(orc_sim *s, Block *b) {
+    const int lo[3] = {0, H, H + N}, hi[3] = {H, H + N, P};
+    Block *parent = parent_of(s, b);
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                if (dx == 0 && dy == 0 && dz == 0) continue;
+                int np[3];
+                if (!neighbor_pos(s, b, dx, dy, dz, np)) continue;  // handled by the BC below
+                const Block *nb = find(s, b->level, np[0], np[1], np[2]);
+                for (int q = 0; q < 5; ++q)
+                    for (int k = lo[dz + 1]; k < hi[dz + 1]; ++k)
+                        for (int j = lo[dy + 1]; j < hi[dy + 1]; ++j)
+                            for (int i = lo[dx + 1]; i < hi[dx + 1]; ++i) {
+                                double v;
+                                if (nb)
+                                    v = nb->u[at(q, k - N * dz, j - N * dy, i - N * dx)];
+                                else
+                                    v = orc_predict_cell(parent->u.data() + q * CELLS, b->bx & 1,
+                                                         b->by & 1, b->bz & 1, i, j, k);
+                                b->u[at(q, k, j, i)] = v;
+                            }
+            }
+    // Zero-gradient boundaries, axis by axis over the full padded extent.
+    const int c[3] = {b->bx, b->by, b->bz};
+    for (int a = 0; a < 3; ++a) {
+        if (s->p.bc[a] == 0) continue;
+        const int n = level_extent(s->p, a, b->level);
+        for (int side = 0; side < 2; ++side) {
+            if (side == 0 && c[a] != 0) continue;
+            if (side == 1 && c[a] != n - 1) continue;
+            const int src = side == 0 ? H : H + N - 1;
+            for (int q = 0; q < 5; ++q)
+                for (int h = 0; h < H; ++h) {
+                    const int dst = side == 0 ? h : H + N + h;
+                    for (int m = 0; m < P; ++m)
+                        for (int r = 0; r < P; ++r) {
+                            int is[3], id[3];
+                            is[a] = src;
+                            id[a] = dst;
+                            const int o1 = (a + 1) % 3, o2 = (a + 2) % 3;
+                            is[o1] = id[o1] = r;
+                            is[o2] = id[o2] = m;
+                            b->u[at(q, id[2], id[1], id[0])] = b->u[at(q, is[2], is[1], is[0])];
+                        }
+                }
+        }
+    }
+}
+
+void fill_halos(orc_sim *s) {
+    for (int l = 0; l <= s->p.lmax; ++l) {
+        std::vector<Block *> lv = blocks_on_level(s, l);
+#pragma omp parallel for schedule(static)
+        for (long n = 0; n < (long)lv.size(); ++n) fill_block_halos(s, lv[n]);
+    }
+}
+
+// Face fluxes of one leaf along all three axes and its right-hand side (without jump
+// correction).  Returns the number of face-fields that used the LLF branch.
+long block_rhs(const orc_sim *s, Block *b) {
+    const double g = s->p.gamma, B = s->p.B;
+    const double dx = dx_level(s->p, b->level);
+    // F[d][q][m][r][f]: face f (0..16) along axis d; (r, m) = the other two interior
+    // indices in increasing axis order.
+    std::vector<double> F(3 * 5 * PLANE * (N + 1));
+    auto fidx = [](int d, int q, int m, int r, int f) {
+        return (((d * 5 + q) * N + m) * N + r) * (N + 1) + f;
+    };
+    long n_llf = 0;
+    for (int d = 0; d < 3; ++d)
+        for (int m = 0; m < N; ++m)
+            for (int r = 0; r < N; ++r)
+                for (int f = 0; f <= N; ++f) {
+                    double st[30], Fh[5];
+                    for (int j = 0; j < 6; ++j) {
+                        const int along = f + 1 + j;  // padded index of stencil cell j
+                        int c[3];
+                        c[d] = along;
+                        // the other two axes in increasing order: (o_lo, o_hi)
+                        const int o_lo = d == 0 ? 1 : 0, o_hi = d == 2 ? 1 : 2;
+                        c[o_lo] = H + r;
+                        c[o_hi] = H + m;
+                        for (int q = 0; q < 5; ++q) st[5 * j + q] = b->u[at(q, c[2], c[1], c[0])];
+                    }
+                    n_llf += orc_face_flux(d, st, g, B, Fh);
+                    for (int q = 0; q < 5; ++q) F[fidx(d, q, m, r, f)] = Fh[q];
+                }
+    b->rhs.assign(5 * ICELLS, 0.0);
+    for (int q = 0; q < 5; ++q)
+        for (int k = 0; k < N; ++k)
+            for (int j = 0; j < N; ++j)
+                for (int i = 0; i < N; ++i) {
+                    const double ddx = F[fidx(0, q, k, j, i + 1)] - F[fidx(0, q, k, j, i)];
+                    const double ddy = F[fidx(1, q, k, i, j + 1)] - F[fidx(1, q, k, i, j)];
+                    const double ddz = F[fidx(2, q, j, i, k + 1)] - F[fidx(2, q, j, i, k)];
+                    b->rhs[ati(q, k, j, i)] = -(ddx + ddy + ddz) / dx;
+                }
+    // Boundary face planes for the jump correction, stored [q][m][r].
+    for (int side = 0; side < 6; ++side) {
+        const int d = side / 2, f = (side % 2) ? N : 0;
+        b->face[side].assign(5 * PLANE, 0.0);
+        for (int q = 0; q < 5; ++q)
+            for (int m = 0; m < N; ++m)
+                for (int r = 0; r < N; ++r) b->face[side][(q * N + m) * N + r] = F[fidx(d, q, m, r, f)];
+    }
+    return n_llf;
+}
+
+// Face plane of block b on side `side`: its own flux if a leaf, else the area average of
+// its children's planes on that side (recursively).
+std::vector<double> face_plane(orc_sim *s, Block *b, int side) {
+    if (b->leaf) return b->face[side];
+    const int d = side / 2, hi = side % 2;
+    const int o_lo = d == 0 ? 1 : 0, o_hi = d == 2 ? 1 : 2;
+    std::vector<double> out(5 * PLANE, 0.0);
+    for (int cm = 0; cm < 2; ++cm)
+        for (int cr = 0; cr < 2; ++cr) {
+            int o[3];
+            o[d] = hi;
+            o[o_lo] = cr;
+            o[o_hi] = cm;
+            Block *c = child_of(s, b, o[0], o[1], o[2]);
+            const std::vector<double> cp = face_plane(s, c, side);
+            for (int q = 0; q < 5; ++q)
+                for (int M = 0; M < N / 2; ++M)
+                    for (int R = 0; R < N / 2; ++R) {
+                        auto v = [&](int a, int bb) {
+                            return cp[(q * N + 2 * M + bb) * N + 2 * R + a];
+                        };
+                        const double avg = ((v(0, 0) + v(1, 0)) + (v(0, 1) + v(1, 1))) / 4.0;
+                        out[(q * N + cm * N / 2 + M) * N + cr * N / 2 + R] = avg;
+                    }
+        }
+    return out;
+}
+
+// Replace the coarse flux at resolution jumps by the average of the fine fluxes.
+void jump_correction(orc_sim *s, Block *b) {
+    const double dx = dx_level(s->p, b->level);
+    for (int side = 0; side < 6; ++side) {
+        const int d = side / 2, hi = side % 2;
+        int off[3] = {0, 0, 0};
+        off[d] = hi ? 1 : -1;
+        int np[3];
+        if (!neighbor_pos(s, b, off[0], off[1], off[2], np)) continue;
+        Block *nb = find(s, b->level, np[0], np[1], np[2]);
+        if (!nb || nb->leaf) continue;
+        const std::vector<double> fine = face_plane(s, nb, side ^ 1);
+        const int o_lo = d == 0 ? 1 : 0, o_hi = d == 2 ? 1 : 2;
+        for (int q = 0; q < 5; ++q)
+            for (int m = 0; m < N; ++m)
+                for (int r = 0; r < N; ++r) {
+                    int c[3];
+                    c[d] = hi ? N - 1 : 0;
+                    c[o_lo] = r;
+                    c[o_hi] = m;
+                    const double own = b->face[side][(q * N + m) * N + r];
+                    const double fn = fine[(q * N + m) * N + r];
+                    const double corr = hi ? (own - fn) / dx : (fn - own) / dx;
+                    b->rhs[ati(q, c[2], c[1], c[0])] += corr;
+                }
+    }
+}
+
+std::vector<Block *> leaves(orc_sim *s) {
+    std::vector<Block *> v;
+    for (Block *b : s->order)
+        if (b->leaf) v.push_back(b);
+    return v;
+}
+
+void compute_rhs(orc_sim *s) {
+    std::vector<Block *> lv = leaves(s);
+    long n_llf = 0;
+#pragma omp parallel for schedule(static) reduction(+ : n_llf)
+    for (long n = 0; n < (long)lv.size(); ++n) n_llf += block_rhs(s, lv[n]);
+    const double fields = (double)lv.size() * 3.0 * PLANE * (N + 1) * 5.0;
+    s->llf_fraction = fields > 0 ? (double)n_llf / fields : 0.0;
+#pragma omp parallel for schedule(static)
+    for (long n = 0; n < (long)lv.size(); ++n) jump_correction(s, lv[n]);
+}
+
+bool physical(const orc_sim *s, const Block *b) {
+    for (int k = H; k < H + N; ++k)
+        for (int j = H; j < H + N; ++j)
+            for (int i = H; i < H + N; ++i) {
+                double U[5];
+                for (int q = 0; q < 5; ++q) U[q] = b->u[at(q, k, j, i)];
+                const double p = orc_pressure(U, s->p.gamma, s->p.B);
+                if (!(U[0] > 0.0) || !(p + s->p.B > 0.0) || !std::isfinite(U[4])) return false;
+            }
+    return true;
+}
+
+double block_detail(orc_sim *s, Block *b) {
+    Block *par = parent_of(s, b);
+    const int ox = b->bx & 1, oy = b->by & 1, oz = b->bz & 1;
+    double d = 0.0;
+    const int qs[2] = {0, 4};
+    const double sc[2] = {s->p.scale_rho, s->p.scale_E};
+    for (int n = 0; n < 2; ++n) {
+        const int q = qs[n];
+        const double *pu = par->u.data() + q * CELLS;
+        for (int k = 0; k < P; ++k)
+            for (int j = 0; j < P; ++j)
+                for (int i = 0; i < P; ++i) {
+                    const double pred = orc_predict_cell(pu, ox, oy, oz, i, j, k);
+                    const double v = std::fabs(b->u[at(q, k, j, i)] - pred) / sc[n];
+                    d = std::max(d, v);
+                }
+    }
+    return d;
+}
+
+void compute_details(orc_sim *s) {
+    std::vector<Block *> all = s->order;
+#pragma omp parallel for schedule(static)
+    for (long n = 0; n < (long)all.size(); ++n)
+        all[n]->detail = all[n]->level == 0 ? -1.0 : block_detail(s, all[n]);
+}
+
+// Refine/keep/coarsen decision for every leaf (non-leaves get 2).
+void compute_flags(orc_sim *s) {
+    for (Block *b : s->order) {
+        if (!b->leaf) { b->flag = 2; continue; }
+        const int l = b->level;
+        if (l < s->p.lmax && b->detail >= eps_level(s->p, l)) { b->flag = 1; continue; }
+        b->flag = 0;
+        if (l < 2) continue;
+        Block *par = parent_of(s, b);
+        bool all_small = true;
+        for (int o = 0; o < 8 && all_small; ++o) {
+            const Block *c = child_of(s, par, o & 1, (o >> 1) & 1, o >> 2);
+            if (!c->leaf || !(c->detail < eps_level(s->p, l))) all_small = false;
+        }
+        if (all_small && par->detail < eps_level(s->p, l - 1)) b->flag = -1;
+    }
+}
+
+void refine(orc_sim *s, Block *b) {
+    for (int o = 0; o < 8; ++o) {
+        Block *c = add_block(s, b->level + 1, 2 * b->bx + (o & 1), 2 * b->by + ((o >> 1) & 1),
+                             2 * b->bz + (o >> 2));
+        predict_interior(b, c);
+    }
+    b->leaf = false;
+}
+
+void coarsen(orc_sim *s, Block *par) {
+    for (int o = 0; o < 8; ++o) {
+        Block *c = child_of(s, par, o & 1, (o >> 1) & 1, o >> 2);
+        s->map.erase(c->id);
+        delete c;
+    }
+    par->leaf = true;
+}
+
+void commit_flags(orc_sim *s) {
+    std::vector<Block *> to_refine, to_coarsen;
+    for (Block *b : s->order) {
+        if (b->flag == 1) to_refine.push_back(b);
+        if (b->flag == -1 && (b->bx & 1) == 0 && (b->by & 1) == 0 && (b->bz & 1) == 0)
+            to_coarsen.push_back(parent_of(s, b));
+    }
+    for (Block *b : to_refine) refine(s, b);
+    for (Block *b : to_coarsen) coarsen(s, b);
+    rebuild_order(s);
+}
+
+void impose_ic(orc_sim *s, Block *b, orc_ic_fn ic, void *user) {
+    std::vector<double> prim(5 * ICELLS);
+    ic(user, b->level, b->bx, b->by, b->bz, prim.data());
+    const double g = s->p.gamma, B = s->p.B;
+    for (int k = 0; k < N; ++k)
+        for (int j = 0; j < N; ++j)
+            for (int i = 0; i < N; ++i) {
+                const double rho = prim[ati(0, k, j, i)], u = prim[ati(1, k, j, i)],
+                             v = prim[ati(2, k, j, i)], w = prim[ati(3, k, j, i)],
+                             p = prim[ati(4, k, j, i)];
+                b->u[at(0, H + k, H + j, H + i)] = rho;
+                b->u[at(1, H + k, H + j, H + i)] = rho * u;
+                b->u[at(2, H + k, H + j, H + i)] = rho * v;
+                b->u[at(3, H + k, H + j, H + i)] = rho * w;
+                b->u[at(4, H + k, H + j, H + i)] =
+                    (p + g * B) / (g - 1.0) + 0.5 * rho * (u * u + v * v + w * w);
+            }
+}
+
+}  // namespace
+
+extern "C" {
+
+orc_sim *orc_sim_create(const orc_params *p) {
+    orc_sim *s = new orc_sim();
+    s->p = *p;
+    int mx = std::max(p->n0[0], std::max(p->n0[1], p->n0[2]));
+    while ((1 << s->shadow) < mx) ++s->shadow;
+    return s;
+}
+
+void orc_sim_free(orc_sim *s) { delete s; }
+
+int orc_sim_init(orc_sim *s, orc_ic_fn ic, void *user) {
+    for (int z = 0; z < s->p.n0[2]; ++z)
+        for (int y = 0; y < s->p.n0[1]; ++y)
+            for (int x = 0; x < s->p.n0[0]; ++x) impose_ic(s, add_block(s, 0, x, y, z), ic, user);
+    rebuild_order(s);
+    for (int m = 1; m <= s->p.lmax; ++m) {
+        std::vector<Block *> parents = blocks_on_level(s, m - 1);
+        std::vector<Block *> fresh;
+        for (Block *b : parents) {
+            for (int o = 0; o < 8; ++o)
+                fresh.push_back(add_block(s, m, 2 * b->bx + (o & 1), 2 * b->by + ((o >> 1) & 1),
+                                          2 * b->bz + (o >> 2)));
+            b->leaf = false;
+        }
+        for (Block *c : fresh) impose_ic(s, c, ic, user);
+        rebuild_order(s);
+        if (m > 1) {
+            fill_halos(s);
+            std::vector<Block *> lv = blocks_on_level(s, m);
+#pragma omp parallel for schedule(static)
+            for (long n = 0; n < (long)lv.size(); ++n) lv[n]->detail = block_detail(s, lv[n]);
+            const double eps = eps_level(s->p, m);
+            std::vector<Block *> drop;
+            for (Block *b : parents) {
+                bool small = true;
+                for (int o = 0; o < 8; ++o)
+                    if (!(child_of(s, b, o & 1, (o >> 1) & 1, o >> 2)->detail < eps)) small = false;
+                if (small) drop.push_back(b);
+            }
+            for (Block *b : drop) coarsen(s, b);
+            rebuild_order(s);
+        }
+    }
+    project(s);
+    for (Block *b : s->order)
+        if (!physical(s, b)) return -5;
+    return 0;
+}
+
+double orc_sim_dt(const orc_sim *s) {
+    double mx[3] = {0.0, 0.0, 0.0};
+    for (const Block *b : s->order) {
+        if (!b->leaf) continue;
+        for (int k = H; k < H + N; ++k)
+            for (int j = H; j < H + N; ++j)
+                for (int i = H; i < H + N; ++i) {
+                    double U[5];
+                    for (int q = 0; q < 5; ++q) U[q] = b->u[at(q, k, j, i)];
+                    const double p = orc_pressure(U, s->p.gamma, s->p.B);
+                    const double c = std::sqrt(s->p.gamma * (p + s->p.B) / U[0]);
+                    for (int a = 0; a < 3; ++a)
+                        mx[a] = std::max(mx[a], std::fabs(U[1 + a] / U[0]) + c);
+                }
+    }
+    return s->p.cfl * dx_level(s->p, s->p.lmax) / (mx[0] + mx[1] + mx[2]);
+}
+
+double orc_ssprk3_stage(int stage, double u0, double us, double L, double dt) {
+    const double a[3] = {1.0, 0.25, 2.0 / 3.0};
+    return u0 + a[stage] * ((us - u0) + dt * L);
+}
+
+int orc_sim_step(orc_sim *s, double *dt_out) {
+    const double dt = orc_sim_dt(s);
+    if (dt_out) *dt_out = dt;
+    std::vector<Block *> lv = leaves(s);
+    for (Block *b : lv) {
+        b->u0.assign(5 * ICELLS, 0.0);
+        for (int q = 0; q < 5; ++q)
+            for (int k = 0; k < N; ++k)
+                for (int j = 0; j < N; ++j)
+                    for (int i = 0; i < N; ++i)
+                        b->u0[ati(q, k, j, i)] = b->u[at(q, H + k, H + j, H + i)];
+    }
+    int bad = 0;
+    for (int st = 0; st < 3; ++st) {
+        project(s);
+        fill_halos(s);
+        compute_rhs(s);
+#pragma omp parallel for schedule(static) reduction(+ : bad)
+        for (long n = 0; n < (long)lv.size(); ++n) {
+            Block *b = lv[n];
+            for (int q = 0; q < 5; ++q)
+                for (int k = 0; k < N; ++k)
+                    for (int j = 0; j < N; ++j)
+                        for (int i = 0; i < N; ++i) {
+                            const double u0 = b->u0[ati(q, k, j, i)];
+                            double &u = b->u[at(q, H + k, H + j, H + i)];
+                            u = orc_ssprk3_stage(st, u0, u, b->rhs[ati(q, k, j, i)], dt);
+                        }
+            if (!physical(s, b)) bad += 1;
+        }
+        if (bad) return -5;
+    }
+    s->time += dt;
+    if (s->p.adapt) {
+        project(s);
+        fill_halos(s);
+        compute_details(s);
+        compute_flags(s);
+        commit_flags(s);
+    }
+    return 0;
+}
+
+int32_t orc_sim_nblocks(const orc_sim *s) { return (int32_t)s->order.size(); }
+
+void orc_sim_blocks(const orc_sim *s, int64_t *info) {
+    for (size_t n = 0; n < s->order.size(); ++n) {
+        const Block *b = s->order[n];
+        int64_t *r = info + 8 * n;
+        r[0] = b->level;
+        r[1] = b->bx;
+        r[2] = b->by;
+        r[3] = b->bz;
+        r[4] = b->leaf ? 1 : 0;
+        r[5] = b->flag;
+        r[6] = (int64_t)b->id;
+        r[7] = 0;
+    }
+}
+
+void orc_sim_get_block(const orc_sim *s, int32_t idx, double *out) {
+    std::memcpy(out, s->order[idx]->u.data(), sizeof(double) * 5 * CELLS);
+}
+
+void orc_sim_set_block(orc_sim *s, int32_t idx, const double *in) {
+    std::memcpy(s->order[idx]->u.data(), in, sizeof(double) * 5 * CELLS);
+}
+
+double orc_sim_detail(const orc_sim *s, int32_t idx) { return s->order[idx]->detail; }
+
+int orc_sim_refine(orc_sim *s, int32_t level, int32_t bx, int32_t by, int32_t bz) {
+    Block *b = find(s, level, bx, by, bz);
+    if (!b || !b->leaf || level >= s->p.lmax) return -1;
+    fill_halos(s);  // the prediction reads the parent's halos
+    refine(s, b);
+    rebuild_order(s);
+    return 0;
+}
+
+int orc_sim_coarsen(orc_sim *s, int32_t level, int32_t bx, int32_t by, int32_t bz) {
+    Block *b = find(s, level, bx, by, bz);
+    if (!b || b->leaf) return -1;
+    for (int o = 0; o < 8; ++o)
+        if (!child_of(s, b, o & 1, (o >> 1) & 1, o >> 2)->leaf) return -1;
+    coarsen(s, b);
+    rebuild_order(s);
+    return 0;
+}
+
+void orc_sim_project(orc_sim *s) { project(s); }
+void orc_sim_fill_halos(orc_sim *s) { fill_halos(s); }
+
+int32_t orc_sim_rhs(orc_sim *s, double *L_out) {
+    compute_rhs(s);
+    int32_t n = 0;
+    for (Block *b : s->order) {
+        if (!b->leaf) continue;
+        if (L_out) std::memcpy(L_out + (size_t)n * 5 * ICELLS, b->rhs.data(), sizeof(double) * 5 * ICELLS);
+        ++n;
+    }
+    return n;
+}
+
+void orc_sim_details(orc_sim *s, double *det_out, int8_t *flag_out) {
+    compute_details(s);
+    compute_flags(s);
+    for (size_t n = 0; n < s->order.size(); ++n) {
+        if (det_out) det_out[n] = s->order[n]->detail;
+        if (flag_out) flag_out[n] = (int8_t)s->order[n]->flag;
+    }
+}
+
+void orc_sim_totals(const orc_sim *s, double *tot) {
+    for (int q = 0; q < 5; ++q) tot[q] = 0.0;
+    for (const Block *b : s->order) {
+        if (!b->leaf) continue;
+        const double dx = dx_level(s->p, b->level);
+        const double vol = dx * dx * dx;
+        for (int q = 0; q < 5; ++q) {
+            double sum = 0.0;
+            for (int k = H; k < H + N; ++k)
+                for (int j = H; j < H + N; ++j)
+                    for (int i = H; i < H + N; ++i) sum += b->u[at(q, k, j, i)];
+            tot[q] += sum * vol;
+        }
+    }
+}
+
+double orc_sim_time(const orc_sim *s) { return s->time; }
+double orc_sim_llf_fraction(const orc_sim *s) { return s->llf_fraction; }
+
+}  // extern "C"

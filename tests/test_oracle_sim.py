@@ -1,0 +1,348 @@
+"""Pins of the oracle's whole MR time step against facts independent of the oracle.
+
+* free-stream preservation, bitwise, on trees with resolution jumps;
+* conservation to round-off on a periodic domain with jumps and with adaptation (checks
+  the jump flux correction of algo:ComputeLoop and the conservative MR operators);
+* the exact Riemann solution of the Sod shock tube (the paper's verification case);
+* fifth-order convergence on a smooth entropy wave (point values, dt ~ dx^(5/3));
+* CFL time step (eq:Cfl) and totals in closed form;
+* halo fill exact for polynomial data away from the domain boundary;
+* details/flags (eq:DetailFunction, eq:Thresholding, eq:LevelWiseEpsilon): zero details
+  on polynomials, brute-force flag set for a planar step, no refine/coarsen thrash.
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+from paper_2012_04385_amd import workloads as W
+
+P, H, N = 24, 4, 16
+GAMMA = 1.4
+
+
+def cons_field(rho, u, v, w, p, gamma=GAMMA):
+    return np.stack([rho, rho * u, rho * v, rho * w,
+                     p / (gamma - 1) + 0.5 * rho * (u * u + v * v + w * w)])
+
+
+def centres(pb, level, bx, by, bz, padded=False):
+    lo, n = (-H, P) if padded else (0, N)
+    ar = np.arange(lo, lo + n)
+    h = pb.dx(level)
+    z, y, x = np.meshgrid((bz * N + ar + 0.5) * h, (by * N + ar + 0.5) * h,
+                          (bx * N + ar + 0.5) * h, indexing="ij")
+    return x, y, z
+
+
+def set_leaves(sim, fn):
+    """Write fn(x,y,z) -> conservative [5,...] at the interior cell centres of every block."""
+    pb = sim.problem
+    for n, r in enumerate(sim.blocks()):
+        lvl, bx, by, bz = (int(v) for v in r[:4])
+        x, y, z = centres(pb, lvl, bx, by, bz)
+        blk = sim.get_block(n)
+        blk[:, H:H + N, H:H + N, H:H + N] = fn(x, y, z)
+        sim.set_block(n, blk)
+
+
+def jump_tree(orc, lmax=3, n0=(2, 2, 2), state=(1.3, 0.3, -0.2, 0.1, 0.9)):
+    pb = W.uniform_flow(lmax=lmax, n0=n0, state=state)
+    sim = orc.Sim(pb, adapt=0).init()
+    # after algo:Init a uniform field keeps levels 0 and 1 only; add jumps by hand
+    sim.refine(1, 1, 1, 1)
+    sim.refine(1, 2, 1, 1)
+    sim.refine(2, 3, 2, 2)   # a child of (1,1,1,1) -> two-level jump next to level 1
+    sim.refine(1, 0, 3, 0)   # touches the periodic boundary
+    return sim
+
+
+def test_free_stream_bitwise(orc):
+    sim = jump_tree(orc)
+    before = sim.leaf_states()
+    for _ in range(5):
+        sim.step()
+    after = sim.leaf_states()
+    assert before.keys() == after.keys()
+    for k in before:
+        assert np.array_equal(before[k], after[k]), k
+
+
+def test_free_stream_with_adaptation(orc):
+    sim = jump_tree(orc)
+    ref = next(iter(sim.leaf_states().values()))[:, 0, 0, 0].copy()
+    sim2 = orc.Sim(sim.problem, adapt=1)
+    sim2.init()
+    sim2.refine(1, 1, 1, 1)
+    for _ in range(3):
+        sim2.step()
+    for v in sim2.leaf_states().values():
+        assert np.array_equal(v, np.broadcast_to(ref[:, None, None, None], v.shape))
+    # zero details: the refined group is coarsened again
+    assert (sim2.blocks()[:, 0] <= 1).all()
+
+
+def _bump(x, y, z):
+    r2 = (x - 0.45) ** 2 + (y - 0.5) ** 2 + (z - 0.55) ** 2
+    g = np.exp(-r2 / 0.01)
+    rho = 1.0 + 0.5 * g
+    p = 1.0 + 2.0 * g
+    return cons_field(rho, 0.4 + 0 * x, -0.2 + 0 * x, 0.3 + 0 * x, p)
+
+
+@pytest.mark.parametrize("adapt", [0, 1])
+def test_conservation_periodic_with_jumps(orc, adapt):
+    sim2 = orc.Sim(W.uniform_flow(lmax=3, n0=(2, 2, 2)), adapt=adapt)
+    sim2.init()
+    for args in [(1, 1, 1, 1), (1, 2, 1, 1), (2, 3, 2, 2), (1, 0, 3, 0)]:
+        sim2.refine(*args)
+    set_leaves(sim2, _bump)
+    sim2.project()
+    t0 = sim2.totals()
+    scale = np.array([1.5, 1.0, 1.0, 1.0, 5.0])
+    nb0 = len(sim2.blocks())
+    for _ in range(2 if adapt else 4):
+        sim2.step()
+    t1 = sim2.totals()
+    assert np.all(np.abs(t1 - t0) <= 2e-14 * scale), (t1 - t0)
+    if adapt:
+        assert len(sim2.blocks()) != nb0   # the tree changed and mass was still conserved
+
+
+def _sod_problem(n0x):
+    return W.Problem(name="sod", kind="sod", lmax=0, n0=(n0x, 1, 1), dx0=1.0 / (16 * n0x),
+                     bc=(1, 0, 0), noise=0.0, cfl=0.5,
+                     params={"axis": 0, "pos": 0.5, "left": (1.0, 1.0), "right": (0.125, 0.1)})
+
+
+def _sod_l1(orc, n0x, t_end=0.2):
+    pb = _sod_problem(n0x)
+    sim = orc.Sim(pb).init()
+    while sim.time < t_end:
+        sim.step()
+    t = sim.time
+    xs, rho, mt = [], [], 0.0
+    for key, u in sim.leaf_states().items():
+        lvl, bx, by, bz = key
+        x = (bx * N + np.arange(N) + 0.5) * pb.dx(0)
+        xs.append(x)
+        rho.append(u[0].mean(axis=(0, 1)))
+        mt = max(mt, np.abs(u[2]).max(), np.abs(u[3]).max())
+        # every y,z row is identical (1D problem)
+        assert np.ptp(u[0], axis=(0, 1)).max() < 1e-12
+    xs = np.concatenate(xs)
+    rho = np.concatenate(rho)
+    ex = orc.exact_riemann((1.0, 0.0, 1.0), (0.125, 0.0, 0.1), GAMMA, (xs - 0.5) / t)
+    return np.sum(np.abs(rho - ex[:, 0])) / len(xs), mt
+
+
+def test_sod_exact_solution(orc):
+    e64, m64 = _sod_l1(orc, 4)
+    e128, m128 = _sod_l1(orc, 8)
+    assert m64 < 1e-13 and m128 < 1e-13       # no spurious transverse momenta
+    # recorded bounds (measured 7.9e-3 and 4.2e-3, order 0.93); a first-order or
+    # inconsistent scheme exceeds them
+    assert e128 < 5.0e-3
+    assert e64 < 1.0e-2
+    assert math.log2(e64 / e128) > 0.6
+
+
+def _wave_error(orc, n_cells, t_end=0.1):
+    n0x = n_cells // N
+    cfl = 0.4 * (16.0 / n_cells) ** (2.0 / 3.0)
+
+    def prim(x, y, z):
+        return (1.0 + 0.2 * np.sin(2 * np.pi * x), 1.0 + 0 * x, 0 * x, 0 * x, 1.0 + 0 * x)
+
+    pb = W.Problem(name="wave", kind="custom", custom=prim, lmax=0, n0=(n0x, 1, 1),
+                   dx0=1.0 / n_cells, bc=(0, 0, 0), noise=0.0, cfl=cfl)
+    sim = orc.Sim(pb).init()
+    while sim.time < t_end:
+        sim.step()
+    t = sim.time
+    err = 0.0
+    for key, u in sim.leaf_states().items():
+        x = (key[1] * N + np.arange(N) + 0.5) / n_cells
+        exact = 1.0 + 0.2 * np.sin(2 * np.pi * (x - t))
+        err += np.abs(u[0] - exact[None, None, :]).sum()
+    return err / (n_cells * N * N)
+
+
+def test_fifth_order_convergence(orc):
+    e = [_wave_error(orc, n) for n in (16, 32, 64)]
+    o1 = math.log2(e[0] / e[1])
+    o2 = math.log2(e[1] / e[2])
+    assert o1 > 4.0, e
+    assert o2 > 4.5, e
+
+
+def test_cfl_and_totals_closed_form(orc):
+    state = (1.3, 0.3, -0.2, 0.1, 0.9)
+    pb = W.uniform_flow(lmax=1, n0=(1, 1, 1), state=state)
+    sim = orc.Sim(pb, adapt=0).init()
+    rho, u, v, w, p = state
+    c = math.sqrt(GAMMA * p / rho)
+    dt = pb.cfl * pb.dx(1) / ((abs(u) + c) + (abs(v) + c) + (abs(w) + c))
+    assert abs(sim.dt() - dt) < 1e-15
+    tot = sim.totals()
+    E = p / (GAMMA - 1) + 0.5 * rho * (u * u + v * v + w * w)
+    np.testing.assert_allclose(tot, [rho, rho * u, rho * v, rho * w, E], rtol=1e-13)
+
+
+_POLY_TERMS = [(1.0, 0, 0, 0), (0.3, 1, 0, 0), (-0.2, 0, 2, 0), (0.1, 1, 0, 3), (0.05, 4, 2, 0)]
+
+
+def _mono_avg(x, h, a):
+    """Mean of s^a over [x - h/2, x + h/2]."""
+    return ((x + h / 2) ** (a + 1) - (x - h / 2) ** (a + 1)) / ((a + 1) * h)
+
+
+def _poly(x, y, z, h):
+    """Cell averages (cell size h, centres x,y,z) of a polynomial of degree <= 4 per axis."""
+    return sum(c * _mono_avg(x, h, a) * _mono_avg(y, h, b) * _mono_avg(z, h, d)
+               for c, a, b, d in _POLY_TERMS)
+
+
+def test_halo_fill_polynomial_exact(orc):
+    # n0 = 4: level-0 blocks 1..2 per axis have unwrapped neighbourhoods, so every halo
+    # of a block descending from them is exact for polynomial data.
+    pb = W.uniform_flow(lmax=2, n0=(4, 4, 4))
+    sim = orc.Sim(pb, adapt=0).init()
+    sim.refine(1, 3, 3, 3)
+    sim.refine(1, 4, 3, 3)
+    sim.refine(1, 2, 4, 5)
+
+    def field(x, y, z, h):
+        f = _poly(x, y, z, h)
+        return np.stack([f, 2 * f, -f, 0.5 * f, 3 + f])
+
+    for n, r in enumerate(sim.blocks()):
+        lvl, bx, by, bz = (int(v) for v in r[:4])
+        x, y, z = centres(pb, lvl, bx, by, bz)
+        blk = sim.get_block(n)
+        blk[:, H:H + N, H:H + N, H:H + N] = field(x, y, z, pb.dx(lvl))
+        sim.set_block(n, blk)
+    sim.fill_halos()
+    checked = 0
+    for n, r in enumerate(sim.blocks()):
+        lvl, bx, by, bz = (int(v) for v in r[:4])
+        anc = np.array([bx, by, bz]) >> lvl
+        if not np.all((anc >= 1) & (anc <= 2)):
+            continue
+        x, y, z = centres(pb, lvl, bx, by, bz, padded=True)
+        got = sim.get_block(n)
+        np.testing.assert_allclose(got, field(x, y, z, pb.dx(lvl)), rtol=0, atol=1e-12)
+        checked += 1
+    assert checked > 20
+
+
+def test_halo_fill_zero_gradient(orc):
+    pb = W.uniform_flow(lmax=1, n0=(2, 2, 2))
+    pb.bc = (1, 1, 0)
+    sim = orc.Sim(pb, adapt=0).init()
+    rng = np.random.default_rng(3)
+    for n in range(len(sim.blocks())):
+        sim.set_block(n, rng.uniform(1, 2, size=(5, P, P, P)))
+    sim.fill_halos()
+    for n, r in enumerate(sim.blocks()):
+        lvl, bx, by, bz = (int(v) for v in r[:4])
+        u = sim.get_block(n)
+        ne = 2 << lvl
+        if bx == 0:
+            assert np.array_equal(u[:, :, :, :H], np.repeat(u[:, :, :, H:H + 1], H, axis=3))
+        if bx == ne - 1:
+            assert np.array_equal(u[:, :, :, H + N:], np.repeat(u[:, :, :, H + N - 1:H + N], H, axis=3))
+        if by == 0:
+            assert np.array_equal(u[:, :, :H, :], np.repeat(u[:, :, H:H + 1, :], H, axis=2))
+
+
+def test_details_zero_on_polynomials_and_coarsen(orc):
+    pb = W.uniform_flow(lmax=2, n0=(2, 2, 2))
+    sim = orc.Sim(pb, adapt=0).init()
+    sim.refine(1, 1, 1, 1)
+    # set every block's full padded array (halos included) to the polynomial samples
+    for n, r in enumerate(sim.blocks()):
+        lvl, bx, by, bz = (int(v) for v in r[:4])
+        x, y, z = centres(pb, lvl, bx, by, bz, padded=True)
+        f = _poly(x, y, z, pb.dx(lvl))
+        sim.set_block(n, np.stack([f, 0 * f, 0 * f, 0 * f, 2 + f]))
+    det, flags = sim.details()
+    info = sim.blocks()
+    assert np.all(det[info[:, 0] >= 1] < 1e-13)
+    lvl2 = info[:, 0] == 2
+    assert np.all(flags[lvl2] == -1)           # all eight siblings coarsen
+    assert np.all(flags[(info[:, 0] == 1) & (info[:, 4] == 1)] == 0)
+
+
+def _step_expected(pb, info, xs_parent_cells, level_eps):
+    """Brute-force detail support for a planar step at a parent-grid face: a block's
+    detail is non-zero iff the 5-point x-stencil of a padded cell's parent straddles it."""
+    out = {}
+    for r in info:
+        lvl, bx, by, bz, leaf = (int(v) for v in r[:5])
+        if lvl == 0:
+            continue
+        ox = bx & 1
+        parent_x0 = (bx >> 1) * N  # global index of the parent's interior cell 0
+        hit = False
+        for i in range(P):
+            ci = i - H
+            I = parent_x0 + ox * (N // 2) + (ci // 2)   # global parent cell index
+            lo, hi = I - 2, I + 2
+            if lo < xs_parent_cells[lvl] <= hi:
+                hit = True
+                break
+        out[(lvl, bx, by, bz)] = hit
+    return out
+
+
+def test_flags_planar_step_brute_force(orc):
+    pb = W.uniform_flow(lmax=3, n0=(2, 1, 1))
+    pb.bc = (1, 0, 0)
+    sim = orc.Sim(pb, adapt=0).init()
+    for by, bz in itertools.product(range(2), repeat=2):
+        for bx in range(4):
+            sim.refine(1, bx, by, bz)
+    x_step = 0.5 + 2.0 / 64   # on a level-1 cell face (level-1 dx = 1/64)
+
+    for n, r in enumerate(sim.blocks()):
+        lvl, bx, by, bz = (int(v) for v in r[:4])
+        x, y, z = centres(pb, lvl, bx, by, bz, padded=True)
+        f = np.where(x < x_step, 1.0, 0.5)
+        sim.set_block(n, np.stack([f, 0 * f, 0 * f, 0 * f, 2 + f]))
+    det, flags = sim.details()
+    info = sim.blocks()
+    # first parent-level cell right of the step, per child level
+    xs_parent = {l: int(round(x_step / pb.dx(l - 1))) for l in range(1, 4)}
+    expect = _step_expected(pb, info, xs_parent, None)
+    for n, r in enumerate(info):
+        key = tuple(int(v) for v in r[:4])
+        if key[0] == 0:
+            continue
+        assert (det[n] > 1e-12) == expect[key], (key, det[n])
+        if r[4] == 1 and key[0] < 3:
+            assert (flags[n] == 1) == expect[key]
+
+
+def test_no_thrash_after_refine(orc):
+    # A block with a large detail is refined; its children are P(parent) and have zero
+    # details, yet must not be coarsened while the parent's detail stays above eps.
+    pb = W.uniform_flow(lmax=2, n0=(1, 1, 1))
+    sim = orc.Sim(pb, adapt=0).init()
+    rng = np.random.default_rng(5)
+    for n, r in enumerate(sim.blocks()):
+        if r[0] == 1:
+            blk = sim.get_block(n)
+            blk[0, H:H + N, H:H + N, H:H + N] += 0.1 * rng.random((N, N, N))
+            sim.set_block(n, blk)
+    sim.fill_halos()
+    sim.refine(1, 0, 0, 0)
+    sim.fill_halos()
+    det, flags = sim.details()
+    info = sim.blocks()
+    kids = info[:, 0] == 2
+    assert np.all(det[kids] < 1e-6)                 # children = P(parent) in the interior
+    assert np.all(flags[kids] == 0)                 # KEEP, not COARSEN
+    par = [n for n, r in enumerate(info) if tuple(r[:4]) == (1, 0, 0, 0)][0]
+    assert det[par] > pb.eps
