@@ -1,0 +1,155 @@
+"""Benchmark: cell-updates per second per SSP-RK3 stage of the MR blast workload
+(3 levels, 128^3 effective, 16^3 blocks + 4 halo layers), FP32 batched path, one MI355X.
+
+One "step" is one global time step of the whole hot path: CFL reduction, three stages of
+{restriction, halo fill, fused right-hand side + stage update, jump correction}, then the
+MR adaptation (restriction, 26-region halo fill, details/flags, flag read-back, tree
+update, prediction of new children).  value = (leaf cells x 3 stages) summed over the timed
+steps / wall time, with the state resident in HBM.
+
+Also measured on the same workload: the FP64 plain path (speed-up), the L1 density
+difference and flag agreement between the two GPU paths, the dominant kernel's average
+duration from HIP events (roofline), and the FP64 CPU oracle on a bounded sample.
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic FLOPs of the fused right-hand side + update per cell-update (see the design doc,
+# "FLOP model"): per face 734 FLOPs with every characteristic field upwind, plus 110 per
+# field that takes the LLF split; 17/16 faces per cell per axis; 40 per cell for the update.
+FACE_BASE, LLF_EXTRA, UPDATE = 734.0, 110.0, 40.0
+PEAK_FP32_VECTOR = 157.3e12       # MI355X FP32 vector (FLOP/s)
+PEAK_HBM = 8.0e12                 # bytes/s
+
+
+def flops_per_cell_update(llf_fraction: float) -> float:
+    return 3.0 * (17.0 / 16.0) * (FACE_BASE + 5.0 * llf_fraction * LLF_EXTRA) + UPDATE
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_gpu(pb, dtype, batched, warmup, steps, timing=False, record_trees=False):
+    import torch
+    from paper_2012_04385_amd.mrfv import Solver
+    g = Solver([pb], dtype=dtype, batched=batched).init()
+    for _ in range(warmup):
+        g.step()
+    g.check()
+    if timing:
+        g.enable_kernel_timing(True)
+        g.kernel_time()
+    torch.cuda.synchronize()
+    trees, cells = [], 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        cells += g.leaf_cells() * 3
+        g.step()
+        if record_trees:
+            info = g.blocks()
+            trees.append(frozenset(tuple(int(v) for v in r[2:6]) for r in info if r[6] == 1))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    g.check()
+    kt = g.kernel_time() if timing else None
+    return g, cells, t1 - t0, trees, kt
+
+
+def cpu_baseline(pb, budget_s=15.0, max_steps=10):
+    from oracle import oracle
+    o = oracle.Sim(pb).init()
+    cells, n, llf = 0, 0, []
+    t0 = time.perf_counter()
+    while n < max_steps and (time.perf_counter() - t0) < budget_s:
+        leaves = int((o.blocks()[:, 4] == 1).sum())
+        o.step()
+        llf.append(o.llf_fraction)
+        cells += leaves * 16 ** 3 * 3
+        n += 1
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": cells / dt, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {n} of {pb.steps} steps of {pb.name} (FP64, OpenMP over blocks)"}, \
+        sum(llf) / len(llf)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=45)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 plain comparison")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2012_04385_amd import workloads as W
+
+    pb = W.blast_mr3(steps=args.warmup + args.steps)
+    log(f"[bench] workload {pb.name}: FP32 batched, warmup {args.warmup}, timed {args.steps}")
+    g32, cells, secs, trees32, kt = run_gpu(pb, "f32", True, args.warmup, args.steps,
+                                            timing=True, record_trees=True)
+    value = cells / secs
+    log(f"[bench] FP32 batched: {value:.4e} cell-updates/s, {1e3 * secs / args.steps:.3f} ms/step")
+
+    extra = {}
+    if not args.no_fp64:
+        log("[bench] FP64 plain path on the same workload")
+        g64, cells64, secs64, trees64, _ = run_gpu(pb, "f64", False, args.warmup, args.steps,
+                                                   record_trees=True)
+        v64 = cells64 / secs64
+        s32, s64 = g32.leaf_states(), g64.leaf_states()
+        common = set(s32) & set(s64)
+        l1 = sum(np.abs(s32[k][0] - s64[k][0]).sum() * pb.dx(k[0]) ** 3 for k in common)
+        extra = {"fp64_plain_value": v64, "speedup_vs_fp64_plain": value / v64,
+                 "l1_rho_fp32_vs_fp64": l1,
+                 "flags_identical_fp32_vs_fp64": trees32 == trees64}
+        log(f"[bench] FP64 plain: {v64:.4e} cell-updates/s; L1(rho) FP32 vs FP64 = {l1:.3e}; "
+            f"trees identical: {trees32 == trees64}")
+        del g64
+
+    cpu, llf = None, 0.5
+    if not args.no_cpu:
+        log("[bench] CPU oracle sample")
+        cpu, llf = cpu_baseline(W.blast_mr3(steps=args.warmup + args.steps))
+        log(f"[bench] oracle: {cpu['value']:.4e} cell-updates/s on {cpu['cores']} threads; "
+            f"LLF fraction {llf:.3f}")
+
+    launches, total_ms, kcells = kt
+    avg_s = total_ms / 1e3 / max(launches, 1)
+    cells_per_launch = kcells / max(launches, 1)
+    fpc = flops_per_cell_update(llf)
+    achieved = cells_per_launch * fpc / avg_s
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
+            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR, "traffic": None,
+            "kernel": "k_rhs_update<float>", "avg_launch_ms": avg_s * 1e3,
+            "cells_per_launch": cells_per_launch, "flop_per_cell_update": fpc,
+            "llf_fraction": llf}
+    ms_step = 1e3 * secs / args.steps
+    out = {"metric": "cell-updates/s per RK stage (FP32 batched MR RK3)", "value": value,
+           "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": pb.name, "levels": pb.lmax + 1, "effective_grid": 128,
+                      "block": "16^3 + 4 halo", "ic": "spherical blast r=0.1, (1,10)|(0.125,0.1), "
+                      "+-1e-3 rho noise", "eps": pb.eps, "cfl": pb.cfl, "path": "batched FP32"},
+           "roofline": roof, "cpu_baseline": cpu}
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,190 @@
+/*
+ * mrfv.h -- C ABI of the MI355X (gfx950) hot path of the block-based multiresolution
+ * finite-volume solver of Hoppe, Adami & Adams (arXiv 2012.04385) for the 3D
+ * compressible Euler equations (eq:Euler with the stiffened-gas EOS eq:StiffenedGas).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every function returns an mrfv_status (0 = success, negative = error), never throws,
+ *    never aborts.  On an argument error nothing is written to device memory and the
+ *    reason is available from mrfv_last_error().
+ *  - "dev" pointers are HIP device pointers owned by the caller (for instance the storage
+ *    of torch tensors); the library never frees them.  "host" pointers are ordinary host
+ *    memory.  Tables, work lists and scratch inside the context are owned by the library
+ *    and released by mrfv_destroy().
+ *  - Kernels are launched asynchronously on the stream given to mrfv_create().  Calls
+ *    that return host-visible results (mrfv_init_blocks, mrfv_commit_flags, mrfv_step when
+ *    it adapts the tree, mrfv_get_blocks) synchronise that stream.
+ *  - Block storage (the paper's block concept, Sec. "Modular block-based MR algorithm"):
+ *    a block is 16^3 interior cells plus 4 halo layers per side.  The state array U holds
+ *    one padded block per slot: U[slot][q][z][y][x], 24^3 per quantity, x fastest,
+ *    interior index 4..19, q = (rho, rho u, rho v, rho w, E).  U0 and L hold interiors
+ *    only: [slot][q][16][16][16].  The element type is the context dtype (float or
+ *    double).
+ *  - A context is used by one host thread at a time.
+ */
+#ifndef MRFV_H
+#define MRFV_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MRFV_OK = 0,
+    MRFV_EINVAL = -1,    /* bad argument (null pointer, size, index)                  */
+    MRFV_EHIP = -2,      /* a HIP runtime call failed                                 */
+    MRFV_ENOMEM = -3,    /* slot capacity or device memory exhausted                  */
+    MRFV_ESTATE = -4,    /* call out of order (e.g. step before init)                 */
+    MRFV_ENONPHYS = -5   /* rho <= 0, p + B <= 0 or a NaN appeared on the device       */
+} mrfv_status;
+
+typedef enum { MRFV_F32 = 0, MRFV_F64 = 1 } mrfv_dtype;
+typedef enum { MRFV_BC_PERIODIC = 0, MRFV_BC_ZEROGRAD = 1 } mrfv_bc;
+
+/* One independent MR problem (one forest of octrees on a box). */
+typedef struct {
+    double gamma, B;      /* stiffened-gas EOS parameters                               */
+    double cfl;           /* CFL number of eq:Cfl                                       */
+    double eps;           /* threshold on the finest level; eq:LevelWiseEpsilon scales it
+                             by 2^(-3 (lmax - l)) on level l                            */
+    double scale_rho;     /* normalisation of rho details                               */
+    double scale_E;       /* normalisation of E details                                 */
+    double dx0;           /* cell size on level 0                                       */
+    int32_t lmax;         /* finest level                                               */
+    int32_t n0[3];        /* level-0 blocks per axis                                    */
+    int32_t bc[3];        /* mrfv_bc per axis                                           */
+    int32_t adapt;        /* 1: refine/coarsen after each step                          */
+} mrfv_instance;
+
+typedef struct {
+    int32_t dtype;          /* mrfv_dtype of U, U0, L                                   */
+    int32_t n_instances;    /* >= 1                                                     */
+    int32_t slot_capacity;  /* maximum number of blocks over all instances              */
+    int32_t batched;        /* 0: plain path (one launch per tree level, unfused update);
+                               1: batched path (all leaves of all levels and instances in
+                               one fused rhs + update launch)                          */
+} mrfv_config;
+
+typedef struct mrfv_ctx mrfv_ctx;
+
+/* Initial-condition callback: fill prim[5][16][16][16] (rho,u,v,w,p at the interior cell
+ * centres, [q][z][y][x]) of block (instance, level, bx, by, bz). Host memory. */
+typedef void (*mrfv_ic_fn)(void *user, int32_t instance, int32_t level, int32_t bx,
+                           int32_t by, int32_t bz, double *prim);
+
+/* Create a context.  inst: host array of cfg->n_instances problems.  hip_stream: the
+ * stream every kernel is launched on (NULL = default stream).  Allocates the library's
+ * tables and scratch for cfg->slot_capacity slots. */
+int mrfv_create(mrfv_ctx **out, const mrfv_config *cfg, const mrfv_instance *inst,
+                void *hip_stream);
+int mrfv_destroy(mrfv_ctx *ctx);
+const char *mrfv_last_error(const mrfv_ctx *ctx);
+
+/* Size in bytes of U (padded) and of U0 / L (interiors) for the configured capacity. */
+int64_t mrfv_state_bytes(const mrfv_ctx *ctx);
+int64_t mrfv_interior_bytes(const mrfv_ctx *ctx);
+
+/* init_blocks -- bottom-up initialisation of algo:Init: level-0 forest, then level by
+ * level: refine all blocks of the previous level, impose the initial condition (ic,
+ * converted to conservative variables on the device), and on levels >= 2 remove sibling
+ * groups whose details are all below that level's threshold; finally parents are set to
+ * the average of their children (eq:Averaging).  U: dev, capacity-sized padded state. */
+int mrfv_init_blocks(mrfv_ctx *ctx, mrfv_ic_fn ic, void *user, void *U);
+
+/* fill_halos -- halo cells of every block, levels coarse to fine: copy from a same-level
+ * neighbour (periodic boundaries wrap), else fifth-order prediction from the parent
+ * (eq:Prediction), with zero-gradient boundaries clamped to the nearest interior cell.
+ * All 26 halo regions (4 layers) are filled. */
+int mrfv_fill_halos(mrfv_ctx *ctx, void *U);
+
+/* rhs_stage -- L = -div F for every leaf (eq:Euler, Sec. "Numerical Scheme"): one flux
+ * per face from characteristic WENO5-JS inside a Roe solver with local Lax-Friedrichs
+ * fallback per characteristic field, with the coarse flux at resolution jumps replaced by
+ * the area average of the fine fluxes (coarse cell adjustment of algo:ComputeLoop).
+ * Halos must be filled.  L: dev [slot][5][16^3] (written for leaves only). */
+int mrfv_rhs_stage(mrfv_ctx *ctx, const void *U, void *L);
+
+/* rk_update -- SSP-RK3 stage (increment form) on every leaf interior:
+ * U <- U0 + a_s ((U - U0) + dt L), a = (1, 1/4, 2/3); stage 0 first copies U into U0.
+ * dt_dev: dev double[n_instances] (from mrfv_cfl_dt).  Sets the device error word on a
+ * non-physical state (see mrfv_check). */
+int mrfv_rk_update(mrfv_ctx *ctx, int32_t stage, const double *dt_dev, void *U, void *U0,
+                   const void *L);
+
+/* mr_project -- every non-leaf block <- conservative average of its 8 children
+ * (eq:Averaging), levels fine to coarse, summed pairwise in double precision. */
+int mrfv_mr_project(mrfv_ctx *ctx, void *U);
+
+/* mr_predict -- interiors of the listed blocks <- fifth-order prediction from their
+ * parents (eq:Prediction); the parents' halos must be filled.  slots_host: host int32[n]. */
+int mrfv_mr_predict(mrfv_ctx *ctx, void *U, const int32_t *slots_host, int32_t n);
+
+/* mr_flag -- details d(B) = max over the 24^3 padded cells and q in {rho, E} of
+ * |u_q - P(u_parent)_q| / scale_q (eq:DetailFunction read as u_l - P(u_{l-1})), evaluated
+ * in double precision, and refine/keep/coarsen flags (eq:Thresholding with the level
+ * thresholds of eq:LevelWiseEpsilon): REFINE (1) if l < lmax and d >= eps_l; COARSEN (-1)
+ * if l >= 2, all 8 siblings are leaves with d < eps_l and the parent's d < eps_{l-1};
+ * else KEEP (0); non-leaves get 2.  All 26 halo regions must be filled.
+ * flags_dev: dev int8[capacity], det_dev: dev double[capacity] (indexed by slot). */
+int mrfv_mr_flag(mrfv_ctx *ctx, const void *U, int8_t *flags_dev, double *det_dev);
+
+/* cfl_dt -- eq:Cfl per instance: dt = cfl dx_lmax / sum_d max(|v_d| + c) over leaf
+ * interior cells, reduced in double precision.  dt_dev: dev double[n_instances]. */
+int mrfv_cfl_dt(mrfv_ctx *ctx, const void *U, double *dt_dev);
+
+/* totals -- per instance, sum over leaf interior cells of u_q dx_l^3 in double
+ * precision with a fixed reduction order.  tot_dev: dev double[n_instances][5]. */
+int mrfv_totals(mrfv_ctx *ctx, const void *U, double *tot_dev);
+
+/* commit_flags -- apply flags (host int8[capacity] by slot, as written by mr_flag) to
+ * the tree: refine creates 8 children (their interiors are NOT yet predicted), coarsen
+ * removes 8 leaf siblings; then rebuilds and uploads the device tables.  The new child
+ * slots are written to new_slots_host (capacity-sized host int32 array, may be NULL) and
+ * their number to *n_new. */
+int mrfv_commit_flags(mrfv_ctx *ctx, const int8_t *flags_host, int32_t *new_slots_host,
+                      int32_t *n_new);
+
+/* step -- one global time step of algo:ComputeLoop: cfl_dt; three stages of
+ * {mr_project, fill_halos, rhs + jump correction, rk_update}; then, for adaptive
+ * instances, mr_project, fill_halos, mr_flag, one device-to-host copy of the flags,
+ * commit_flags and mr_predict of the new children.  U0, L: dev scratch of
+ * mrfv_interior_bytes.  dt_dev: dev double[n_instances] receives this step's dt. */
+int mrfv_step(mrfv_ctx *ctx, void *U, void *U0, void *L, double *dt_dev);
+
+/* check -- reads and clears the device error word: MRFV_ENONPHYS if a stage produced a
+ * non-physical state since the last check, else MRFV_OK.  Synchronises the stream. */
+int mrfv_check(mrfv_ctx *ctx);
+
+/* Block table.  info_host: int64[n][8] = (slot, instance, level, bx, by, bz, is_leaf,
+ * morton id with headbit).  *n receives the number of blocks (info_host may be NULL). */
+int mrfv_get_blocks(mrfv_ctx *ctx, int64_t *info_host, int32_t *n);
+
+/* Explicit tree edits for tests: refine fills all halos of U, then creates the children
+ * of a leaf and predicts their interiors; coarsen removes the 8 leaf children of a block
+ * (the block's interior must already be their average). */
+int mrfv_refine_block(mrfv_ctx *ctx, void *U, int32_t instance, int32_t level, int32_t bx,
+                      int32_t by, int32_t bz);
+int mrfv_coarsen_block(mrfv_ctx *ctx, int32_t instance, int32_t level, int32_t bx,
+                       int32_t by, int32_t bz);
+
+/* Kernel timing: when enabled, every launch of the fused rhs + update kernel (batched
+ * path) or of the flux kernel (plain path) is bracketed by HIP events on the context
+ * stream; mrfv_kernel_time returns the number of timed launches, their total duration in
+ * ms and the leaf cells per launch summed over launches. */
+int mrfv_enable_kernel_timing(mrfv_ctx *ctx, int32_t on);
+int mrfv_kernel_time(mrfv_ctx *ctx, int64_t *launches, double *total_ms, int64_t *cells);
+
+/* Morton ids with a headbit (Sec. "Modular block-based MR algorithm"): 3-bit groups per
+ * level, finest group least significant, x = bit 0 of each group; shadow = number of
+ * groups above level 0.  Neighbour along axis d in direction dir (+1/-1); *wrapped = 1
+ * when the lookup crossed the domain edge (the result is the periodic image). */
+uint64_t mrfv_morton_encode(int32_t shadow, int32_t level, int32_t bx, int32_t by, int32_t bz);
+uint64_t mrfv_morton_neighbor(uint64_t id, int32_t shadow, int32_t d, int32_t dir,
+                              int32_t *wrapped);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MRFV_H */

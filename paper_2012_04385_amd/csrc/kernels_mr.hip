@@ -1,0 +1,455 @@
+// kernels_mr.hip -- gfx950 kernels for the MR operators and reductions.
+//
+//   prim2cons      initial condition (rho,u,v,w,p) -> conservative state (eq:StiffenedGas)
+//   fill_halos     same-level copy / prediction from the parent / zero-gradient clamp
+//   project        parents <- average of 8 children (eq:Averaging), FP64 pairwise sums
+//   predict        interiors of new children <- prediction from the parent (eq:Prediction)
+//   details/flags  Harten details and refine/keep/coarsen flags (eq:DetailFunction,
+//                  eq:Thresholding, eq:LevelWiseEpsilon), FP64 arithmetic
+//   cfl            eq:Cfl, FP64 max-reduction per block then per instance
+//   totals         FP64 sums per block then per instance (fixed order)
+//
+// The prediction is evaluated in its separable form: the appendix Q-terms are the
+// tensor products of the 1D operator D u = c0 (u[+1]-u[-1]) + c1 (u[+2]-u[-2]) with
+// c0 = -22/128, c1 = 3/128 (Q_x = D_x u, Q_xy = D_x D_y u, Q_xyz = D_x D_y D_z u), so the
+// child value is (1 + s_z D_z)(1 + s_y D_y)(1 + s_x D_x) u, s = +1 for the lower child.
+// Written in difference form it reproduces a uniform field exactly.
+#include "mrfv_internal.h"
+
+namespace mrfv {
+
+namespace {
+
+constexpr int TPB = 256;
+
+__device__ __forceinline__ int pidx(int q, int k, int j, int i) {
+    return ((q * NP + k) * NP + j) * NP + i;
+}
+
+// One 1D prediction step in difference form.
+template <typename C>
+__device__ __forceinline__ C pred1(C m2, C m1, C z0, C p1, C p2, C s) {
+    const C c0 = (C)(-22.0 / 128.0), c1 = (C)(3.0 / 128.0);
+    return z0 + s * (c0 * (p1 - m1) + c1 * (p2 - m2));
+}
+
+// Prediction of child padded cell (i,j,k) (octant o) from one component of the parent's
+// padded array pu, evaluated in arithmetic type C.
+template <typename C, typename T>
+__device__ C predict_cell(const T *__restrict__ pu, int ox, int oy, int oz, int i, int j,
+                          int k) {
+    const int ci = i - HW, cj = j - HW, ck = k - HW;
+    const int I = ox * (NI / 2) + (ci >> 1) + HW;   // arithmetic shift = floor division
+    const int J = oy * (NI / 2) + (cj >> 1) + HW;
+    const int K = oz * (NI / 2) + (ck >> 1) + HW;
+    const C sx = (ci & 1) ? (C)-1 : (C)1;
+    const C sy = (cj & 1) ? (C)-1 : (C)1;
+    const C sz = (ck & 1) ? (C)-1 : (C)1;
+    C r[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        C t[5];
+#pragma unroll
+        for (int b = 0; b < 5; ++b) {
+            const T *row = pu + ((K + c - 2) * NP + (J + b - 2)) * NP + I;
+            t[b] = pred1<C>((C)row[-2], (C)row[-1], (C)row[0], (C)row[1], (C)row[2], sx);
+        }
+        r[c] = pred1<C>(t[0], t[1], t[2], t[3], t[4], sy);
+    }
+    return pred1<C>(r[0], r[1], r[2], r[3], r[4], sz);
+}
+
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_prim2cons(const double *__restrict__ prim,
+                                                   const int32_t *__restrict__ slots, int n,
+                                                   T *__restrict__ U,
+                                                   const BlockMeta *__restrict__ meta,
+                                                   const InstDev *__restrict__ inst) {
+    const int b = blockIdx.x;
+    if (b >= n) return;
+    const int slot = slots[b];
+    const InstDev P = inst[meta[slot].inst];
+    const int k = blockIdx.y, j = threadIdx.x >> 4, i = threadIdx.x & 15;
+    const double *pr = prim + (size_t)b * 5 * CELLS_I;
+    const int c = (k * NI + j) * NI + i;
+    const double rho = pr[c], u = pr[CELLS_I + c], v = pr[2 * CELLS_I + c],
+                 w = pr[3 * CELLS_I + c], p = pr[4 * CELLS_I + c];
+    T *ub = U + (size_t)slot * 5 * CELLS_P;
+    const int o = pidx(0, k + HW, j + HW, i + HW);
+    ub[o] = (T)rho;
+    ub[o + CELLS_P] = (T)(rho * u);
+    ub[o + 2 * CELLS_P] = (T)(rho * v);
+    ub[o + 3 * CELLS_P] = (T)(rho * w);
+    ub[o + 4 * CELLS_P] = (T)((p + P.gamma * P.B) / (P.gamma - 1.0) +
+                              0.5 * rho * (u * u + v * v + w * w));
+}
+
+// One thread per padded cell; interior cells return immediately.
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_fill_halos(T *__restrict__ U,
+                                                    const int32_t *__restrict__ list, int n,
+                                                    const BlockMeta *__restrict__ meta,
+                                                    const int32_t *__restrict__ nbr) {
+    const int b = blockIdx.x;
+    if (b >= n) return;
+    const int cell = blockIdx.y * TPB + threadIdx.x;
+    if (cell >= CELLS_P) return;
+    const int slot = list[b];
+    int c[3] = {cell % NP, (cell / NP) % NP, cell / (NP * NP)};
+    const bool interior = c[0] >= HW && c[0] < HW + NI && c[1] >= HW && c[1] < HW + NI &&
+                          c[2] >= HW && c[2] < HW + NI;
+    if (interior) return;
+    const BlockMeta m = meta[slot];
+    int r[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        r[a] = c[a] < HW ? -1 : (c[a] >= HW + NI ? 1 : 0);
+        // zero-gradient boundary: clamp to the nearest interior cell of this block
+        if (r[a] < 0 && (m.zg & (1 << (2 * a)))) { c[a] = HW; r[a] = 0; }
+        if (r[a] > 0 && (m.zg & (1 << (2 * a + 1)))) { c[a] = HW + NI - 1; r[a] = 0; }
+    }
+    const int region = (r[2] + 1) * 9 + (r[1] + 1) * 3 + (r[0] + 1);
+    const int src = (region == 13) ? slot : nbr[(size_t)slot * 27 + region];
+    T *dst = U + (size_t)slot * 5 * CELLS_P;
+    const int o = pidx(0, (cell / (NP * NP)), (cell / NP) % NP, cell % NP);
+    if (src >= 0) {
+        const T *s = U + (size_t)src * 5 * CELLS_P;
+        const int so = pidx(0, c[2] - NI * r[2], c[1] - NI * r[1], c[0] - NI * r[0]);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) dst[o + q * CELLS_P] = s[so + q * CELLS_P];
+    } else {
+        const T *pu = U + (size_t)m.parent * 5 * CELLS_P;
+#pragma unroll 1
+        for (int q = 0; q < 5; ++q)
+            dst[o + q * CELLS_P] = predict_cell<T, T>(pu + q * CELLS_P, m.bx & 1, m.by & 1,
+                                                      m.bz & 1, c[0], c[1], c[2]);
+    }
+}
+
+// One thread per parent interior cell.
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_project(T *__restrict__ U,
+                                                 const int32_t *__restrict__ list, int n,
+                                                 const int32_t *__restrict__ child) {
+    const int b = blockIdx.x;
+    if (b >= n) return;
+    const int slot = list[b];
+    const int K = blockIdx.y, J = threadIdx.x >> 4, I = threadIdx.x & 15;
+    const int oct = ((K >> 3) << 2) | ((J >> 3) << 1) | (I >> 3);
+    const int cs = child[(size_t)slot * 8 + oct];
+    const T *cu = U + (size_t)cs * 5 * CELLS_P;
+    T *pu = U + (size_t)slot * 5 * CELLS_P;
+    const int ci = HW + 2 * (I & 7), cj = HW + 2 * (J & 7), ck = HW + 2 * (K & 7);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        const T *c0 = cu + pidx(q, ck, cj, ci);
+        const T *c1 = c0 + NP * NP;
+        const double s = (((double)c0[0] + (double)c0[1]) + ((double)c0[NP] + (double)c0[NP + 1])) +
+                         (((double)c1[0] + (double)c1[1]) + ((double)c1[NP] + (double)c1[NP + 1]));
+        pu[pidx(q, HW + K, HW + J, HW + I)] = (T)(s * 0.125);
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_predict(T *__restrict__ U,
+                                                 const int32_t *__restrict__ list, int n,
+                                                 const BlockMeta *__restrict__ meta) {
+    const int b = blockIdx.x;
+    if (b >= n) return;
+    const int slot = list[b];
+    const BlockMeta m = meta[slot];
+    const T *pu = U + (size_t)m.parent * 5 * CELLS_P;
+    T *cu = U + (size_t)slot * 5 * CELLS_P;
+    const int k = blockIdx.y + HW, j = (threadIdx.x >> 4) + HW, i = (threadIdx.x & 15) + HW;
+#pragma unroll 1
+    for (int q = 0; q < 5; ++q)
+        cu[pidx(q, k, j, i)] =
+            predict_cell<T, T>(pu + q * CELLS_P, m.bx & 1, m.by & 1, m.bz & 1, i, j, k);
+}
+
+// One workgroup per block (level >= 1): FP64 max over the padded cells of the rho and E
+// details.
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_details(const T *__restrict__ U,
+                                                 const int32_t *__restrict__ list, int n,
+                                                 const BlockMeta *__restrict__ meta,
+                                                 const InstDev *__restrict__ inst,
+                                                 double *__restrict__ det) {
+    __shared__ double red[TPB];
+    const int b = blockIdx.x;
+    if (b >= n) return;
+    const int slot = list[b];
+    const BlockMeta m = meta[slot];
+    const InstDev P = inst[m.inst];
+    const T *pu = U + (size_t)m.parent * 5 * CELLS_P;
+    const T *bu = U + (size_t)slot * 5 * CELLS_P;
+    const double inv_sr = 1.0 / P.scale_rho, inv_se = 1.0 / P.scale_E;
+    double d = 0.0;
+    for (int cell = threadIdx.x; cell < CELLS_P; cell += TPB) {
+        const int i = cell % NP, j = (cell / NP) % NP, k = cell / (NP * NP);
+        const double pr = predict_cell<double, T>(pu, m.bx & 1, m.by & 1, m.bz & 1, i, j, k);
+        const double pe =
+            predict_cell<double, T>(pu + 4 * CELLS_P, m.bx & 1, m.by & 1, m.bz & 1, i, j, k);
+        const double dr = fabs((double)bu[cell] - pr) * inv_sr;
+        const double de = fabs((double)bu[cell + 4 * CELLS_P] - pe) * inv_se;
+        d = fmax(d, fmax(dr, de));
+    }
+    red[threadIdx.x] = d;
+    __syncthreads();
+    for (int w = TPB / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) det[slot] = red[0];
+}
+
+__device__ __forceinline__ double eps_level(const InstDev &P, int l) {
+    return ldexp(P.eps, -3 * (P.lmax - l));
+}
+
+__global__ __launch_bounds__(TPB) void k_flags(const int32_t *__restrict__ list, int n,
+                                               const BlockMeta *__restrict__ meta,
+                                               const int32_t *__restrict__ child,
+                                               const InstDev *__restrict__ inst,
+                                               const double *__restrict__ det,
+                                               int8_t *__restrict__ flags) {
+    const int t = blockIdx.x * TPB + threadIdx.x;
+    if (t >= n) return;
+    const int slot = list[t];
+    const BlockMeta m = meta[slot];
+    if (!m.leaf) { flags[slot] = 2; return; }
+    const InstDev P = inst[m.inst];
+    const int l = m.level;
+    const double d = l >= 1 ? det[slot] : -1.0;
+    int8_t f = 0;
+    if (!P.adapt) {
+        f = 0;
+    } else if (l < P.lmax && d >= eps_level(P, l)) {
+        f = 1;
+    } else if (l >= 2) {
+        bool small = true;
+        const double e = eps_level(P, l);
+        for (int o = 0; o < 8; ++o) {
+            const int s = child[(size_t)m.parent * 8 + o];
+            if (!meta[s].leaf || !(det[s] < e)) small = false;
+        }
+        if (small && det[m.parent] < eps_level(P, l - 1)) f = -1;
+    }
+    flags[slot] = f;
+}
+
+// Per-block maxima of |v_d| + c over the interior, FP64.
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_cfl_block(const T *__restrict__ U,
+                                                   const int32_t *__restrict__ list, int n,
+                                                   const BlockMeta *__restrict__ meta,
+                                                   const InstDev *__restrict__ inst,
+                                                   double *__restrict__ bmax) {
+    __shared__ double red[3][TPB];
+    const int b = blockIdx.x;
+    if (b >= n) return;
+    const int slot = list[b];
+    const InstDev P = inst[meta[slot].inst];
+    const T *u = U + (size_t)slot * 5 * CELLS_P;
+    double mx[3] = {0.0, 0.0, 0.0};
+    for (int c = threadIdx.x; c < CELLS_I; c += TPB) {
+        const int o = pidx(0, HW + c / FACE, HW + (c / NI) % NI, HW + c % NI);
+        const double r = u[o], m0 = u[o + CELLS_P], m1 = u[o + 2 * CELLS_P],
+                     m2 = u[o + 3 * CELLS_P], E = u[o + 4 * CELLS_P];
+        const double ir = 1.0 / r;
+        const double p = (P.gamma - 1.0) * (E - 0.5 * (m0 * m0 + m1 * m1 + m2 * m2) * ir) -
+                         P.gamma * P.B;
+        const double cs = sqrt(P.gamma * (p + P.B) * ir);
+        mx[0] = fmax(mx[0], fabs(m0 * ir) + cs);
+        mx[1] = fmax(mx[1], fabs(m1 * ir) + cs);
+        mx[2] = fmax(mx[2], fabs(m2 * ir) + cs);
+    }
+    for (int a = 0; a < 3; ++a) red[a][threadIdx.x] = mx[a];
+    __syncthreads();
+    for (int w = TPB / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            for (int a = 0; a < 3; ++a)
+                red[a][threadIdx.x] = fmax(red[a][threadIdx.x], red[a][threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) bmax[(size_t)slot * 5 + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// One workgroup per instance over that instance's contiguous range of the leaf list.
+__global__ __launch_bounds__(TPB) void k_cfl_inst(const int32_t *__restrict__ list,
+                                                  const int32_t *__restrict__ off,
+                                                  const int32_t *__restrict__ cnt,
+                                                  const InstDev *__restrict__ inst,
+                                                  const double *__restrict__ bmax,
+                                                  double *__restrict__ dt) {
+    __shared__ double red[3][TPB];
+    const int ins = blockIdx.x;
+    double mx[3] = {0.0, 0.0, 0.0};
+    for (int t = threadIdx.x; t < cnt[ins]; t += TPB) {
+        const int slot = list[off[ins] + t];
+        for (int a = 0; a < 3; ++a) mx[a] = fmax(mx[a], bmax[(size_t)slot * 5 + a]);
+    }
+    for (int a = 0; a < 3; ++a) red[a][threadIdx.x] = mx[a];
+    __syncthreads();
+    for (int w = TPB / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            for (int a = 0; a < 3; ++a)
+                red[a][threadIdx.x] = fmax(red[a][threadIdx.x], red[a][threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const InstDev P = inst[ins];
+        const double dx = ldexp(P.dx0, -P.lmax);
+        dt[ins] = P.cfl * dx / (red[0][0] + red[1][0] + red[2][0]);
+    }
+}
+
+// Per-block FP64 sums of the 5 conserved quantities over the interior (fixed tree).
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_sum_block(const T *__restrict__ U,
+                                                   const int32_t *__restrict__ list, int n,
+                                                   double *__restrict__ bsum) {
+    __shared__ double red[TPB];
+    const int b = blockIdx.x;
+    if (b >= n) return;
+    const int slot = list[b];
+    const T *u = U + (size_t)slot * 5 * CELLS_P;
+    for (int q = 0; q < 5; ++q) {
+        double s = 0.0;
+        for (int c = threadIdx.x; c < CELLS_I; c += TPB)
+            s += (double)u[pidx(q, HW + c / FACE, HW + (c / NI) % NI, HW + c % NI)];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = TPB / 2; w > 0; w >>= 1) {
+            if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) bsum[(size_t)slot * 5 + q] = red[0];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(TPB) void k_sum_inst(const int32_t *__restrict__ list,
+                                                  const int32_t *__restrict__ off,
+                                                  const int32_t *__restrict__ cnt,
+                                                  const BlockMeta *__restrict__ meta,
+                                                  const InstDev *__restrict__ inst,
+                                                  const double *__restrict__ bsum,
+                                                  double *__restrict__ tot) {
+    __shared__ double red[TPB];
+    const int ins = blockIdx.x;
+    const InstDev P = inst[ins];
+    for (int q = 0; q < 5; ++q) {
+        double s = 0.0;
+        for (int t = threadIdx.x; t < cnt[ins]; t += TPB) {
+            const int slot = list[off[ins] + t];
+            const double dx = ldexp(P.dx0, -meta[slot].level);
+            s += bsum[(size_t)slot * 5 + q] * (dx * dx * dx);
+        }
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = TPB / 2; w > 0; w >>= 1) {
+            if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) tot[ins * 5 + q] = red[0];
+        __syncthreads();
+    }
+}
+
+inline dim3 grid2(int n, int y) { return dim3((unsigned)n, (unsigned)y, 1); }
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_prim2cons(const double *prim, const int32_t *slots, int n, T *U,
+                            const BlockMeta *meta, const InstDev *inst, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_prim2cons<T>, grid2(n, NI), dim3(TPB), 0, st, prim, slots, n, U, meta, inst);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fill_halos(T *U, const int32_t *list, int n, const DevTables &tb,
+                             hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_halos<T>, grid2(n, (CELLS_P + TPB - 1) / TPB), dim3(TPB), 0, st,
+                       U, list, n, tb.meta, tb.nbr);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_project(T *U, const int32_t *list, int n, const DevTables &tb,
+                          hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_project<T>, grid2(n, NI), dim3(TPB), 0, st, U, list, n, tb.child);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_predict(T *U, const int32_t *list, int n, const DevTables &tb,
+                          hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_predict<T>, grid2(n, NI), dim3(TPB), 0, st, U, list, n, tb.meta);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_details(const T *U, const int32_t *list, int n, const DevTables &tb,
+                          const InstDev *inst, double *det, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_details<T>, dim3(n), dim3(TPB), 0, st, U, list, n, tb.meta, inst, det);
+    return hipGetLastError();
+}
+
+hipError_t launch_flags(const int32_t *list, int n, const DevTables &tb, const InstDev *inst,
+                        const double *det, int8_t *flags, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_flags, dim3((n + TPB - 1) / TPB), dim3(TPB), 0, st, list, n, tb.meta,
+                       tb.child, inst, det, flags);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cfl(const T *U, const int32_t *leaves, int n, const DevTables &tb,
+                      const InstDev *inst, int n_inst, double *blockmax, double *dt,
+                      hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cfl_block<T>, dim3(n), dim3(TPB), 0, st, U, leaves, n, tb.meta, inst,
+                       blockmax);
+    // per-instance leaf ranges: the lists array starts with [offsets, counts]
+    hipLaunchKernelGGL(k_cfl_inst, dim3(n_inst), dim3(TPB), 0, st, tb.lists, tb.lists,
+                       tb.lists + n_inst, inst, blockmax, dt);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_totals(const T *U, const int32_t *leaves, int n, const DevTables &tb,
+                         const InstDev *inst, int n_inst, double *blocksum, double *tot,
+                         hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sum_block<T>, dim3(n), dim3(TPB), 0, st, U, leaves, n, blocksum);
+    hipLaunchKernelGGL(k_sum_inst, dim3(n_inst), dim3(TPB), 0, st, tb.lists, tb.lists,
+                       tb.lists + n_inst, tb.meta, inst, blocksum, tot);
+    return hipGetLastError();
+}
+
+#define MRFV_INST(T)                                                                        \
+    template hipError_t launch_prim2cons<T>(const double *, const int32_t *, int, T *,     \
+                                            const BlockMeta *, const InstDev *, hipStream_t); \
+    template hipError_t launch_fill_halos<T>(T *, const int32_t *, int, const DevTables &, \
+                                             hipStream_t);                                  \
+    template hipError_t launch_project<T>(T *, const int32_t *, int, const DevTables &,    \
+                                          hipStream_t);                                     \
+    template hipError_t launch_predict<T>(T *, const int32_t *, int, const DevTables &,    \
+                                          hipStream_t);                                     \
+    template hipError_t launch_details<T>(const T *, const int32_t *, int, const DevTables &, \
+                                          const InstDev *, double *, hipStream_t);          \
+    template hipError_t launch_cfl<T>(const T *, const int32_t *, int, const DevTables &,  \
+                                      const InstDev *, int, double *, double *, hipStream_t); \
+    template hipError_t launch_totals<T>(const T *, const int32_t *, int, const DevTables &, \
+                                         const InstDev *, int, double *, double *, hipStream_t);
+MRFV_INST(float)
+MRFV_INST(double)
+
+}  // namespace mrfv

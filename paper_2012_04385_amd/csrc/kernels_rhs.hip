@@ -1,0 +1,588 @@
+// kernels_rhs.hip -- gfx950 kernels of the per-block right-hand side and stage update.
+//
+// Flux (Sec. "Numerical Scheme"): one numerical flux per cell face from a Roe-type
+// solver with fifth-order WENO-JS reconstruction of the characteristic fluxes.  Per
+// characteristic field the eigenvalues of the two cells sharing the face decide: same
+// sign -> upwind WENO5 of the characteristic flux; otherwise a local Lax-Friedrichs
+// (Rusanov) split whose speed uses only those two cells, each half reconstructed by
+// WENO5.  The characteristic projection uses the closed-form left eigenvectors of the
+// Roe-averaged Jacobian (eq:StiffenedGas gives c^2 = (gamma-1)(H - |v|^2/2)).
+//
+// Work decomposition: a thread walks one pencil of 16 cells along one axis; the six-cell
+// stencil is a sliding window of cell states in registers, so each cell's primitive
+// quantities are computed once per pencil and each face flux once per block.  Stencils
+// are not contractions, so no MFMA is used here.
+//
+// Jump correction (algo:ComputeLoop, coarse cell adjustment): the boundary face fluxes of
+// every leaf are stored; non-leaf blocks receive the area average of their children's
+// (k_ff_restrict), and a coarse leaf next to a non-leaf same-level neighbour replaces its
+// own boundary flux by that average.  With one global dt per step the correction is
+// applied at every stage.
+#include "mrfv_internal.h"
+
+namespace mrfv {
+
+namespace {
+
+constexpr int TPB = 256;
+
+__device__ __forceinline__ float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_(double x) { return 1.0 / x; }
+__device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
+
+template <typename T>
+struct Gas {
+    T g, B, gm1;
+};
+
+// Cell state along the pencil, momentum rotated to (normal, t1, t2).
+template <typename T>
+struct CellState {
+    T r, mn, mt1, mt2, E, p, c, ir, sr;
+};
+
+template <int DIR>
+struct Axes {   // physical momentum component of the rotated (n, t1, t2) triple
+    static constexpr int N1 = DIR == 0 ? 1 : (DIR == 1 ? 2 : 3);
+    static constexpr int T1 = DIR == 0 ? 2 : (DIR == 1 ? 3 : 1);
+    static constexpr int T2 = DIR == 0 ? 3 : (DIR == 1 ? 1 : 2);
+    static constexpr int STRIDE = DIR == 0 ? 1 : (DIR == 1 ? NP : NP * NP);
+};
+
+template <typename T, int DIR>
+__device__ __forceinline__ void load_state(const T *__restrict__ u, int idx, const Gas<T> &G,
+                                           CellState<T> &s) {
+    s.r = u[idx];
+    s.mn = u[idx + Axes<DIR>::N1 * CELLS_P];
+    s.mt1 = u[idx + Axes<DIR>::T1 * CELLS_P];
+    s.mt2 = u[idx + Axes<DIR>::T2 * CELLS_P];
+    s.E = u[idx + 4 * CELLS_P];
+}
+
+template <typename T>
+__device__ __forceinline__ void derive_state(const Gas<T> &G, CellState<T> &s) {
+    s.ir = rcp_(s.r);
+    const T ke = (T)0.5 * (s.mn * s.mn + s.mt1 * s.mt1 + s.mt2 * s.mt2) * s.ir;
+    s.p = G.gm1 * (s.E - ke) - G.g * G.B;
+    s.c = sqrt_(G.g * (s.p + G.B) * s.ir);
+    s.sr = sqrt_(s.r);
+}
+
+// WENO5-JS value at the right face of c from (a,b,c,d,e); weights 0.1/0.6/0.3,
+// eps = 1e-6, power 2.  alpha_k = d_k / e_k^2 is normalised with one reciprocal:
+// the common factor e0^2 e1^2 e2^2 cancels.
+template <typename T>
+__device__ __forceinline__ T weno5(T a, T b, T c, T d, T e) {
+    const T q0 = ((T)2 * a - (T)7 * b + (T)11 * c) * (T)(1.0 / 6.0);
+    const T q1 = (-b + (T)5 * c + (T)2 * d) * (T)(1.0 / 6.0);
+    const T q2 = ((T)2 * c + (T)5 * d - e) * (T)(1.0 / 6.0);
+    const T t0 = a - (T)2 * b + c, s0 = a - (T)4 * b + (T)3 * c;
+    const T t1 = b - (T)2 * c + d, s1 = b - d;
+    const T t2 = c - (T)2 * d + e, s2 = (T)3 * c - (T)4 * d + e;
+    const T k13 = (T)(13.0 / 12.0);
+    const T e0 = (T)1e-6 + (k13 * t0 * t0 + (T)0.25 * s0 * s0);
+    const T e1 = (T)1e-6 + (k13 * t1 * t1 + (T)0.25 * s1 * s1);
+    const T e2 = (T)1e-6 + (k13 * t2 * t2 + (T)0.25 * s2 * s2);
+    const T E0 = e0 * e0, E1 = e1 * e1, E2 = e2 * e2;
+    const T a0 = (T)0.1 * (E1 * E2), a1 = (T)0.6 * (E0 * E2), a2 = (T)0.3 * (E0 * E1);
+    return (a0 * q0 + a1 * q1 + a2 * q2) * rcp_(a0 + a1 + a2);
+}
+
+// Characteristic flux of one field: upwind by the two face cells' eigenvalues, else LLF.
+template <typename T>
+__device__ __forceinline__ T char_flux(const T W[6], const T G[6], T lL, T lR) {
+    if (lL > (T)0 && lR > (T)0) return weno5(G[0], G[1], G[2], G[3], G[4]);
+    if (lL < (T)0 && lR < (T)0) return weno5(G[5], G[4], G[3], G[2], G[1]);
+    const T al = fmax(fabs(lL), fabs(lR));
+    T gp[6], gm[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        gp[j] = (T)0.5 * (G[j] + al * W[j]);
+        gm[j] = (T)0.5 * (G[j] - al * W[j]);
+    }
+    return weno5(gp[0], gp[1], gp[2], gp[3], gp[4]) + weno5(gm[5], gm[4], gm[3], gm[2], gm[1]);
+}
+
+// Numerical flux through the face between window cells 2 and 3 (rotated components).
+template <typename T>
+__device__ __forceinline__ void face_flux(const CellState<T> w[6], const Gas<T> &G, T F[5]) {
+    const CellState<T> &L = w[2], &R = w[3];
+    const T inv = rcp_(L.sr + R.sr);
+    const T wl = L.sr * inv, wr = R.sr * inv;
+    const T u = wl * (L.mn * L.ir) + wr * (R.mn * R.ir);
+    const T v = wl * (L.mt1 * L.ir) + wr * (R.mt1 * R.ir);
+    const T ww = wl * (L.mt2 * L.ir) + wr * (R.mt2 * R.ir);
+    const T H = wl * ((L.E + L.p) * L.ir) + wr * ((R.E + R.p) * R.ir);
+    const T q2 = u * u + v * v + ww * ww;
+    const T c2 = G.gm1 * (H - (T)0.5 * q2);
+    const T c = sqrt_(c2);
+    const T ic = rcp_(c);
+    const T b1 = G.gm1 * ic * ic;
+    const T b2 = (T)0.5 * q2 * b1;
+
+    // Projection onto the left eigenvectors: with t = b2 a0 + b1 (a4 - u a1 - v a2 - w a3)
+    // and x = (a1 - u a0)/c the five components are (t-x)/2, a0-t, a2-v a0, a3-w a0, (t+x)/2.
+    T tU[6], xU[6], tF[6], xF[6], a0[6], f0[6], wt1[6], wt2[6], gt1[6], gt2[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        const CellState<T> &s = w[j];
+        const T un = s.mn * s.ir;
+        const T f1 = s.mn * un + s.p, f2 = s.mt1 * un, f3 = s.mt2 * un, f4 = (s.E + s.p) * un;
+        tU[j] = b2 * s.r + b1 * (s.E - u * s.mn - v * s.mt1 - ww * s.mt2);
+        xU[j] = (s.mn - u * s.r) * ic;
+        tF[j] = b2 * s.mn + b1 * (f4 - u * f1 - v * f2 - ww * f3);
+        xF[j] = (f1 - u * s.mn) * ic;
+        a0[j] = s.r;
+        f0[j] = s.mn;
+        wt1[j] = s.mt1 - v * s.r;
+        wt2[j] = s.mt2 - ww * s.r;
+        gt1[j] = f2 - v * s.mn;
+        gt2[j] = f3 - ww * s.mn;
+    }
+    const T unL = L.mn * L.ir, unR = R.mn * R.ir;
+    T W[6], Gc[6], g[5];
+    // field 1: u - c
+#pragma unroll
+    for (int j = 0; j < 6; ++j) { W[j] = (T)0.5 * (tU[j] - xU[j]); Gc[j] = (T)0.5 * (tF[j] - xF[j]); }
+    g[0] = char_flux(W, Gc, unL - L.c, unR - R.c);
+    // field 2: entropy, u
+#pragma unroll
+    for (int j = 0; j < 6; ++j) { W[j] = a0[j] - tU[j]; Gc[j] = f0[j] - tF[j]; }
+    g[1] = char_flux(W, Gc, unL, unR);
+    // fields 3, 4: shear, u
+    g[2] = char_flux(wt1, gt1, unL, unR);
+    g[3] = char_flux(wt2, gt2, unL, unR);
+    // field 5: u + c
+#pragma unroll
+    for (int j = 0; j < 6; ++j) { W[j] = (T)0.5 * (tU[j] + xU[j]); Gc[j] = (T)0.5 * (tF[j] + xF[j]); }
+    g[4] = char_flux(W, Gc, unL + L.c, unR + R.c);
+
+    // Back to conservative components: F = R g.
+    const T s15 = g[0] + g[4];
+    F[0] = s15 + g[1];
+    F[1] = u * F[0] + c * (g[4] - g[0]);
+    F[2] = v * F[0] + g[2];
+    F[3] = ww * F[0] + g[3];
+    F[4] = H * s15 + u * c * (g[4] - g[0]) + (T)0.5 * q2 * g[1] + v * g[2] + ww * g[3];
+}
+
+// Interior cell index (z,y,x) of pencil position p for thread coordinates (r, m).
+template <int DIR>
+__device__ __forceinline__ int cell_of(int r, int m, int p) {
+    if (DIR == 0) return (m * NI + r) * NI + p;
+    if (DIR == 1) return (m * NI + p) * NI + r;
+    return (p * NI + m) * NI + r;
+}
+
+template <int DIR>
+__device__ __forceinline__ int pencil_base(int r, int m) {
+    if (DIR == 0) return ((m + HW) * NP + (r + HW)) * NP;
+    if (DIR == 1) return ((m + HW) * NP) * NP + (r + HW);
+    return (m + HW) * NP + (r + HW);
+}
+
+// Walks the pencil (r, m) along DIR: 17 faces, flux differences for 16 cells.
+// sink.cell(q_phys, cell, dF) and sink.face(side, q_phys, F) receive the results.
+template <typename T, int DIR, class Sink>
+__device__ __forceinline__ void pencil(const T *__restrict__ ub, int r, int m, const Gas<T> &G,
+                                       Sink &sink) {
+    constexpr int S = Axes<DIR>::STRIDE;
+    const int qmap[5] = {0, Axes<DIR>::N1, Axes<DIR>::T1, Axes<DIR>::T2, 4};
+    const int base = pencil_base<DIR>(r, m);
+    CellState<T> w[6];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        load_state<T, DIR>(ub, base + (j + 1) * S, G, w[j]);
+        derive_state(G, w[j]);
+    }
+    T Fp[5];
+#pragma unroll 1
+    for (int f = 0; f <= NI; ++f) {
+        load_state<T, DIR>(ub, base + (f + 6) * S, G, w[5]);
+        derive_state(G, w[5]);
+        T F[5];
+        face_flux(w, G, F);
+        if (f == 0) {
+#pragma unroll
+            for (int k = 0; k < 5; ++k) sink.face(2 * DIR, qmap[k], F[k]);
+        } else {
+            const int cell = cell_of<DIR>(r, m, f - 1);
+#pragma unroll
+            for (int k = 0; k < 5; ++k) sink.cell(qmap[k], cell, F[k] - Fp[k]);
+        }
+        if (f == NI) {
+#pragma unroll
+            for (int k = 0; k < 5; ++k) sink.face(2 * DIR + 1, qmap[k], F[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < 5; ++k) Fp[k] = F[k];
+#pragma unroll
+        for (int j = 0; j < 5; ++j) w[j] = w[j + 1];
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ Gas<T> gas_of(const InstDev &P) {
+    return Gas<T>{(T)P.gamma, (T)P.B, (T)(P.gamma - 1.0)};
+}
+
+// ---------------------------------------------------------------- plain path ---------
+
+template <typename T>
+struct GlobalSink {
+    T *D;      // this slot's D: [3][5][4096]
+    T *FF;     // this slot's FF: [6][5][256]
+    int dir, rm;
+    __device__ void cell(int q, int c, T v) { D[(dir * 5 + q) * CELLS_I + c] = v; }
+    __device__ void face(int side, int q, T v) { FF[(side * 5 + q) * FACE + rm] = v; }
+};
+
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_flux(const T *__restrict__ U,
+                                              const int32_t *__restrict__ leaves, int n,
+                                              const BlockMeta *__restrict__ meta,
+                                              const InstDev *__restrict__ inst, T *D, T *FF) {
+    const int b = blockIdx.x;
+    if (b >= n) return;
+    const int slot = leaves[b];
+    const Gas<T> G = gas_of<T>(inst[meta[slot].inst]);
+    const int r = threadIdx.x & 15, m = threadIdx.x >> 4;
+    const T *ub = U + (size_t)slot * 5 * CELLS_P;
+    GlobalSink<T> sink{D + (size_t)slot * 3 * 5 * CELLS_I, FF + (size_t)slot * 6 * 5 * FACE,
+                       (int)blockIdx.y, m * NI + r};
+    if (blockIdx.y == 0) pencil<T, 0>(ub, r, m, G, sink);
+    else if (blockIdx.y == 1) pencil<T, 1>(ub, r, m, G, sink);
+    else pencil<T, 2>(ub, r, m, G, sink);
+}
+
+// Non-leaf blocks: face-flux planes <- area average of the children's planes.
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_ff_restrict(T *FF, const int32_t *__restrict__ list,
+                                                     int n, const int32_t *__restrict__ child) {
+    const int b = blockIdx.x;
+    if (b >= n) return;
+    const int slot = list[b];
+    const int side = blockIdx.y, d = side >> 1, hi = side & 1;
+    const int M = threadIdx.x >> 4, R = threadIdx.x & 15;
+    const int cm = M >> 3, cr = R >> 3;
+    int o[3];
+    o[d] = hi;
+    o[d == 0 ? 1 : 0] = cr;
+    o[d == 2 ? 1 : 2] = cm;
+    const int cs = child[(size_t)slot * 8 + (o[2] << 2) + (o[1] << 1) + o[0]];
+    const T *cp = FF + ((size_t)cs * 6 + side) * 5 * FACE;
+    T *pp = FF + ((size_t)slot * 6 + side) * 5 * FACE;
+    const int m0 = 2 * (M & 7), r0 = 2 * (R & 7);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        const T *c = cp + q * FACE;
+        const T v00 = c[m0 * NI + r0], v10 = c[m0 * NI + r0 + 1];
+        const T v01 = c[(m0 + 1) * NI + r0], v11 = c[(m0 + 1) * NI + r0 + 1];
+        pp[q * FACE + M * NI + R] = ((v00 + v10) + (v01 + v11)) * (T)0.25;
+    }
+}
+
+// Region index of the face neighbour on `side` in the 27-entry neighbourhood.
+__device__ __forceinline__ int face_region(int side) {
+    const int d = side >> 1, s = (side & 1) ? 1 : -1;
+    int r[3] = {0, 0, 0};
+    r[d] = s;
+    return (r[2] + 1) * 9 + (r[1] + 1) * 3 + (r[0] + 1);
+}
+
+// Coarse leaves at resolution jumps: replace the own boundary flux by the fine average in
+// the flux differences D (plain path).
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_reflux(T *D, const T *__restrict__ FF,
+                                                const int32_t *__restrict__ leaves, int n,
+                                                const BlockMeta *__restrict__ meta,
+                                                const int32_t *__restrict__ nbr) {
+    const int b = blockIdx.x;
+    if (b >= n) return;
+    const int slot = leaves[b];
+    const int rm = threadIdx.x, m = rm >> 4, r = rm & 15;
+    for (int side = 0; side < 6; ++side) {
+        const int nb = nbr[(size_t)slot * 27 + face_region(side)];
+        if (nb < 0 || meta[nb].leaf) continue;
+        const int d = side >> 1, hi = side & 1;
+        const int p = hi ? NI - 1 : 0;
+        const int cell = d == 0 ? (m * NI + r) * NI + p : (d == 1 ? (m * NI + p) * NI + r : (p * NI + m) * NI + r);
+        T *Dd = D + ((size_t)slot * 3 + d) * 5 * CELLS_I;
+        const T *own = FF + ((size_t)slot * 6 + side) * 5 * FACE;
+        const T *fine = FF + ((size_t)nb * 6 + (side ^ 1)) * 5 * FACE;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            const T delta = fine[q * FACE + rm] - own[q * FACE + rm];
+            Dd[q * CELLS_I + cell] += hi ? delta : -delta;
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_combine(const T *__restrict__ D, T *L,
+                                                 const int32_t *__restrict__ leaves, int n,
+                                                 const BlockMeta *__restrict__ meta,
+                                                 const InstDev *__restrict__ inst) {
+    const int b = blockIdx.x;
+    if (b >= n) return;
+    const int slot = leaves[b];
+    const BlockMeta mt = meta[slot];
+    const T inv_dx = (T)(1.0 / ldexp(inst[mt.inst].dx0, -mt.level));
+    const T *Ds = D + (size_t)slot * 3 * 5 * CELLS_I;
+    T *Ls = L + (size_t)slot * 5 * CELLS_I;
+    const int c = blockIdx.y * TPB + threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        const T s = (Ds[q * CELLS_I + c] + Ds[(5 + q) * CELLS_I + c]) + Ds[(10 + q) * CELLS_I + c];
+        Ls[q * CELLS_I + c] = -s * inv_dx;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T stage_coef(int stage) {
+    return stage == 0 ? (T)1 : (stage == 1 ? (T)0.25 : (T)(2.0 / 3.0));
+}
+
+template <typename T>
+__device__ __forceinline__ bool physical_state(const T u[5], const Gas<T> &G) {
+    const T ke = (T)0.5 * (u[1] * u[1] + u[2] * u[2] + u[3] * u[3]) / u[0];
+    const T p = G.gm1 * (u[4] - ke) - G.g * G.B;
+    return u[0] > (T)0 && p + G.B > (T)0 && isfinite(u[4]) && isfinite(u[1] + u[2] + u[3]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_update(int stage, const double *__restrict__ dt, T *U,
+                                                T *U0, const T *__restrict__ L,
+                                                const int32_t *__restrict__ leaves, int n,
+                                                const BlockMeta *__restrict__ meta,
+                                                const InstDev *__restrict__ inst, int32_t *err) {
+    const int b = blockIdx.x;
+    if (b >= n) return;
+    const int slot = leaves[b];
+    const BlockMeta mt = meta[slot];
+    const Gas<T> G = gas_of<T>(inst[mt.inst]);
+    const T dtt = (T)dt[mt.inst];
+    const T a = stage_coef<T>(stage);
+    const int c = blockIdx.y * TPB + threadIdx.x;
+    const int o = ((c / FACE + HW) * NP + (c / NI) % NI + HW) * NP + c % NI + HW;
+    T *ub = U + (size_t)slot * 5 * CELLS_P;
+    T *u0b = U0 + (size_t)slot * 5 * CELLS_I;
+    const T *lb = L + (size_t)slot * 5 * CELLS_I;
+    T un[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        const T us = ub[o + q * CELLS_P];
+        T u0;
+        if (stage == 0) {
+            u0 = us;
+            u0b[q * CELLS_I + c] = us;
+        } else {
+            u0 = u0b[q * CELLS_I + c];
+        }
+        un[q] = u0 + a * ((us - u0) + dtt * lb[q * CELLS_I + c]);
+        ub[o + q * CELLS_P] = un[q];
+    }
+    if (!physical_state(un, G)) atomicOr(err, 1);
+}
+
+// ---------------------------------------------------------------- batched path -------
+
+template <typename T, bool ADD>
+struct LdsSink {
+    T *acc;    // [5][4096]
+    T *FF;     // this slot's FF
+    int rm;
+    __device__ void cell(int q, int c, T v) {
+        if (ADD) acc[q * CELLS_I + c] += v;
+        else acc[q * CELLS_I + c] = v;
+    }
+    __device__ void face(int side, int q, T v) { FF[(side * 5 + q) * FACE + rm] = v; }
+};
+
+// One workgroup per leaf: x-, y- and z-pencils accumulate the flux differences in LDS,
+// then each thread finishes its z-column with the SSP-RK3 stage update in place (no other
+// workgroup reads this block's array, and the thread's own z-pencil was the last reader of
+// its column).
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_rhs_update(int stage, const double *__restrict__ dt,
+                                                    T *U, T *U0,
+                                                    const int32_t *__restrict__ leaves, int n,
+                                                    const BlockMeta *__restrict__ meta,
+                                                    const InstDev *__restrict__ inst, T *FF,
+                                                    int32_t *err) {
+    __shared__ T acc[5 * CELLS_I];
+    const int b = blockIdx.x;
+    if (b >= n) return;
+    const int slot = leaves[b];
+    const BlockMeta mt = meta[slot];
+    const InstDev P = inst[mt.inst];
+    const Gas<T> G = gas_of<T>(P);
+    const int r = threadIdx.x & 15, m = threadIdx.x >> 4;
+    T *ub = U + (size_t)slot * 5 * CELLS_P;
+    T *ffs = FF + (size_t)slot * 6 * 5 * FACE;
+    {
+        LdsSink<T, false> s0{acc, ffs, m * NI + r};
+        pencil<T, 0>(ub, r, m, G, s0);
+    }
+    __syncthreads();
+    {
+        LdsSink<T, true> s1{acc, ffs, m * NI + r};
+        pencil<T, 1>(ub, r, m, G, s1);
+    }
+    __syncthreads();
+    {
+        LdsSink<T, true> s2{acc, ffs, m * NI + r};
+        pencil<T, 2>(ub, r, m, G, s2);
+    }
+    // the z-column (x = r, y = m) is complete in acc (written by this thread last)
+    const T inv_dx = (T)(1.0 / ldexp(P.dx0, -mt.level));
+    const T dtt = (T)dt[mt.inst];
+    const T a = stage_coef<T>(stage);
+    T *u0b = U0 + (size_t)slot * 5 * CELLS_I;
+    bool ok = true;
+#pragma unroll 1
+    for (int z = 0; z < NI; ++z) {
+        const int c = (z * NI + m) * NI + r;
+        const int o = ((z + HW) * NP + m + HW) * NP + r + HW;
+        T un[5];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            const T us = ub[o + q * CELLS_P];
+            T u0;
+            if (stage == 0) {
+                u0 = us;
+                u0b[q * CELLS_I + c] = us;
+            } else {
+                u0 = u0b[q * CELLS_I + c];
+            }
+            const T Lq = -acc[q * CELLS_I + c] * inv_dx;
+            un[q] = u0 + a * ((us - u0) + dtt * Lq);
+            ub[o + q * CELLS_P] = un[q];
+        }
+        ok = ok && physical_state(un, G);
+    }
+    if (!ok) atomicOr(err, 1);
+}
+
+// Batched path: the jump correction applied to the already-updated state,
+// U += a_s dt (L_corrected - L) on the boundary cells of coarse leaves at jumps.
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_reflux_update(int stage, const double *__restrict__ dt,
+                                                       T *U, const T *__restrict__ FF,
+                                                       const int32_t *__restrict__ leaves, int n,
+                                                       const BlockMeta *__restrict__ meta,
+                                                       const int32_t *__restrict__ nbr,
+                                                       const InstDev *__restrict__ inst) {
+    const int b = blockIdx.x;
+    if (b >= n) return;
+    const int slot = leaves[b];
+    const BlockMeta mt = meta[slot];
+    const InstDev P = inst[mt.inst];
+    const T coef = stage_coef<T>(stage) * (T)dt[mt.inst] * (T)(1.0 / ldexp(P.dx0, -mt.level));
+    const int rm = threadIdx.x, m = rm >> 4, r = rm & 15;
+    T *ub = U + (size_t)slot * 5 * CELLS_P;
+    for (int side = 0; side < 6; ++side) {
+        const int nb = nbr[(size_t)slot * 27 + face_region(side)];
+        if (nb < 0 || meta[nb].leaf) continue;
+        const int d = side >> 1, hi = side & 1;
+        const int p = (hi ? NI - 1 : 0) + HW;
+        const int o = d == 0 ? ((m + HW) * NP + r + HW) * NP + p
+                             : (d == 1 ? ((m + HW) * NP + p) * NP + r + HW
+                                       : (p * NP + m + HW) * NP + r + HW);
+        const T *own = FF + ((size_t)slot * 6 + side) * 5 * FACE;
+        const T *fine = FF + ((size_t)nb * 6 + (side ^ 1)) * 5 * FACE;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            const T delta = fine[q * FACE + rm] - own[q * FACE + rm];
+            // L changes by -(D_new - D)/dx with D_new - D = +delta (high) / -delta (low)
+            ub[o + q * CELLS_P] += coef * (hi ? -delta : delta);
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_flux(const T *U, const int32_t *leaves, int n, const DevTables &tb,
+                       const InstDev *inst, T *D, T *FF, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_flux<T>, dim3(n, 3), dim3(TPB), 0, st, U, leaves, n, tb.meta, inst, D, FF);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_ff_restrict(T *FF, const int32_t *parents, int n, const DevTables &tb,
+                              hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ff_restrict<T>, dim3(n, 6), dim3(TPB), 0, st, FF, parents, n, tb.child);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_reflux(T *D, const T *FF, const int32_t *leaves, int n, const DevTables &tb,
+                         hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reflux<T>, dim3(n), dim3(TPB), 0, st, D, FF, leaves, n, tb.meta, tb.nbr);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_combine(const T *D, T *L, const int32_t *leaves, int n, const DevTables &tb,
+                          const InstDev *inst, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_combine<T>, dim3(n, CELLS_I / TPB), dim3(TPB), 0, st, D, L, leaves, n,
+                       tb.meta, inst);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_update(int stage, const double *dt, T *U, T *U0, const T *L,
+                         const int32_t *leaves, int n, const DevTables &tb, const InstDev *inst,
+                         int32_t *err, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_update<T>, dim3(n, CELLS_I / TPB), dim3(TPB), 0, st, stage, dt, U, U0, L,
+                       leaves, n, tb.meta, inst, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_rhs_update_f32(int stage, const double *dt, float *U, float *U0,
+                                 const int32_t *leaves, int n, const DevTables &tb,
+                                 const InstDev *inst, float *FF, int32_t *err, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rhs_update<float>, dim3(n), dim3(TPB), 0, st, stage, dt, U, U0, leaves,
+                       n, tb.meta, inst, FF, err);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_reflux_update(int stage, const double *dt, T *U, const T *FF,
+                                const int32_t *leaves, int n, const DevTables &tb,
+                                const InstDev *inst, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reflux_update<T>, dim3(n), dim3(TPB), 0, st, stage, dt, U, FF, leaves, n,
+                       tb.meta, tb.nbr, inst);
+    return hipGetLastError();
+}
+
+#define MRFV_INST_RHS(T)                                                                    \
+    template hipError_t launch_flux<T>(const T *, const int32_t *, int, const DevTables &,  \
+                                       const InstDev *, T *, T *, hipStream_t);             \
+    template hipError_t launch_ff_restrict<T>(T *, const int32_t *, int, const DevTables &, \
+                                              hipStream_t);                                 \
+    template hipError_t launch_reflux<T>(T *, const T *, const int32_t *, int,              \
+                                         const DevTables &, hipStream_t);                   \
+    template hipError_t launch_combine<T>(const T *, T *, const int32_t *, int,             \
+                                          const DevTables &, const InstDev *, hipStream_t); \
+    template hipError_t launch_update<T>(int, const double *, T *, T *, const T *,          \
+                                         const int32_t *, int, const DevTables &,           \
+                                         const InstDev *, int32_t *, hipStream_t);          \
+    template hipError_t launch_reflux_update<T>(int, const double *, T *, const T *,        \
+                                                const int32_t *, int, const DevTables &,    \
+                                                const InstDev *, hipStream_t);
+MRFV_INST_RHS(float)
+MRFV_INST_RHS(double)
+
+}  // namespace mrfv

@@ -1,0 +1,241 @@
+// topology.cpp -- host-side octree of fixed-size blocks.
+//
+// Light-weight topology separated from the heavy block data (Sec. "Modular block-based
+// MR algorithm" and "Algorithm and Implementation"): nodes are identified by Morton ids
+// with a headbit and found through a hash map; the device only ever sees slot indices
+// and the tables built here (per-slot metadata, children, 27-entry same-level
+// neighbourhood, and work lists grouped by level).
+#include <algorithm>
+
+#include "mrfv_internal.h"
+
+namespace mrfv {
+
+// Spread the low 21 bits of v so that bit i lands at bit 3i.
+static uint64_t spread3(uint64_t v) {
+    v &= 0x1fffffull;
+    v = (v | (v << 32)) & 0x1f00000000ffffull;
+    v = (v | (v << 16)) & 0x1f0000ff0000ffull;
+    v = (v | (v << 8)) & 0x100f00f00f00f00full;
+    v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+    v = (v | (v << 2)) & 0x1249249249249249ull;
+    return v;
+}
+
+static uint64_t compact3(uint64_t v) {
+    v &= 0x1249249249249249ull;
+    v = (v ^ (v >> 2)) & 0x10c30c30c30c30c3ull;
+    v = (v ^ (v >> 4)) & 0x100f00f00f00f00full;
+    v = (v ^ (v >> 8)) & 0x1f0000ff0000ffull;
+    v = (v ^ (v >> 16)) & 0x1f00000000ffffull;
+    v = (v ^ (v >> 32)) & 0x1fffffull;
+    return v;
+}
+
+uint64_t morton_encode(int shadow, int level, int bx, int by, int bz) {
+    const int groups = shadow + level;
+    const uint64_t body = spread3((uint64_t)bx) | (spread3((uint64_t)by) << 1) |
+                          (spread3((uint64_t)bz) << 2);
+    return (1ull << (3 * groups)) | body;
+}
+
+uint64_t Topology::key(int inst, int level, int bx, int by, int bz) {
+    // 12 bits instance, 4 bits level, 16 bits per coordinate
+    return ((uint64_t)inst << 52) | ((uint64_t)level << 48) | ((uint64_t)bz << 32) |
+           ((uint64_t)by << 16) | (uint64_t)bx;
+}
+
+void Topology::reset(int capacity, const std::vector<mrfv_instance> &inst) {
+    blocks_.assign(capacity, HostBlock());
+    free_.clear();
+    for (int s = capacity - 1; s >= 0; --s) free_.push_back(s);
+    map_.clear();
+    map_.reserve(2 * capacity);
+    inst_ = inst;
+    shadow_.clear();
+    for (const auto &p : inst) {
+        int m = std::max(p.n0[0], std::max(p.n0[1], p.n0[2])), s = 0;
+        while ((1 << s) < m) ++s;
+        shadow_.push_back(s);
+    }
+    n_alive_ = 0;
+}
+
+int Topology::add_block(int inst, int level, int bx, int by, int bz) {
+    if (free_.empty()) return -1;
+    const int s = free_.back();
+    free_.pop_back();
+    HostBlock &b = blocks_[s];
+    b = HostBlock();
+    b.inst = inst;
+    b.level = level;
+    b.bx = bx;
+    b.by = by;
+    b.bz = bz;
+    b.alive = true;
+    b.leaf = true;
+    b.morton = morton_encode(shadow_[inst], level, bx, by, bz);
+    if (level > 0) b.parent = find(inst, level - 1, bx >> 1, by >> 1, bz >> 1);
+    map_[key(inst, level, bx, by, bz)] = s;
+    ++n_alive_;
+    return s;
+}
+
+int Topology::find(int inst, int level, int bx, int by, int bz) const {
+    auto it = map_.find(key(inst, level, bx, by, bz));
+    return it == map_.end() ? -1 : it->second;
+}
+
+bool Topology::refine(int slot, std::vector<int> *created) {
+    if ((int)free_.size() < 8) return false;
+    HostBlock &b = blocks_[slot];
+    for (int o = 0; o < 8; ++o) {
+        const int c = add_block(b.inst, b.level + 1, 2 * b.bx + (o & 1), 2 * b.by + ((o >> 1) & 1),
+                                2 * b.bz + (o >> 2));
+        blocks_[slot].child[o] = c;
+        if (created) created->push_back(c);
+    }
+    blocks_[slot].leaf = false;
+    return true;
+}
+
+void Topology::remove_block(int s) {
+    HostBlock &b = blocks_[s];
+    map_.erase(key(b.inst, b.level, b.bx, b.by, b.bz));
+    b.alive = false;
+    free_.push_back(s);
+    --n_alive_;
+}
+
+void Topology::coarsen(int p) {
+    for (int o = 0; o < 8; ++o) {
+        remove_block(blocks_[p].child[o]);
+        blocks_[p].child[o] = -1;
+    }
+    blocks_[p].leaf = true;
+}
+
+std::vector<int> Topology::alive_sorted() const {
+    std::vector<int> v;
+    v.reserve(n_alive_);
+    for (int s = 0; s < (int)blocks_.size(); ++s)
+        if (blocks_[s].alive) v.push_back(s);
+    std::sort(v.begin(), v.end(), [&](int a, int b) {
+        const HostBlock &A = blocks_[a], &B = blocks_[b];
+        if (A.inst != B.inst) return A.inst < B.inst;
+        if (A.level != B.level) return A.level < B.level;
+        return A.morton < B.morton;
+    });
+    return v;
+}
+
+void Topology::build(std::vector<BlockMeta> &meta, std::vector<int32_t> &child,
+                     std::vector<int32_t> &nbr, HostLists &L) const {
+    const int cap = capacity();
+    meta.assign(cap, BlockMeta{0, 0, 0, 0, 0, -1, 0, 0});
+    child.assign((size_t)cap * 8, -1);
+    nbr.assign((size_t)cap * 27, -2);
+    const std::vector<int> order = alive_sorted();
+    int maxl = 0;
+    for (int s : order) maxl = std::max(maxl, blocks_[s].level);
+    for (int s : order) {
+        const HostBlock &b = blocks_[s];
+        const mrfv_instance &p = inst_[b.inst];
+        BlockMeta m{b.inst, b.level, b.bx, b.by, b.bz, b.parent, b.leaf ? 1 : 0, 0};
+        const int c[3] = {b.bx, b.by, b.bz};
+        for (int a = 0; a < 3; ++a) {
+            const int n = p.n0[a] << b.level;
+            if (p.bc[a] == MRFV_BC_ZEROGRAD) {
+                if (c[a] == 0) m.zg |= 1 << (2 * a);
+                if (c[a] == n - 1) m.zg |= 1 << (2 * a + 1);
+            }
+        }
+        meta[s] = m;
+        for (int o = 0; o < 8; ++o) child[(size_t)s * 8 + o] = b.child[o];
+        for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int d[3] = {dx, dy, dz};
+                    int q[3];
+                    bool outside = false;
+                    for (int a = 0; a < 3; ++a) {
+                        const int n = p.n0[a] << b.level;
+                        int v = c[a] + d[a];
+                        if (v < 0 || v >= n) {
+                            if (p.bc[a] == MRFV_BC_ZEROGRAD) outside = true;
+                            v = (v + n) % n;
+                        }
+                        q[a] = v;
+                    }
+                    const int idx = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
+                    nbr[(size_t)s * 27 + idx] =
+                        outside ? -2 : find(b.inst, b.level, q[0], q[1], q[2]);
+                }
+    }
+    // work lists
+    const int n_inst = (int)inst_.size();
+    L.data.assign(2 * n_inst, 0);
+    L.max_level = maxl;
+    L.lvl_off.assign(maxl + 1, 0);
+    L.lvl_cnt.assign(maxl + 1, 0);
+    L.par_off.assign(maxl + 1, 0);
+    L.par_cnt.assign(maxl + 1, 0);
+    L.leaf_off.assign(maxl + 1, 0);
+    L.leaf_cnt.assign(maxl + 1, 0);
+    for (int l = 0; l <= maxl; ++l) {
+        L.lvl_off[l] = (int32_t)L.data.size();
+        for (int s : order)
+            if (blocks_[s].level == l) L.data.push_back(s);
+        L.lvl_cnt[l] = (int32_t)L.data.size() - L.lvl_off[l];
+        L.par_off[l] = (int32_t)L.data.size();
+        for (int s : order)
+            if (blocks_[s].level == l && !blocks_[s].leaf) L.data.push_back(s);
+        L.par_cnt[l] = (int32_t)L.data.size() - L.par_off[l];
+        L.leaf_off[l] = (int32_t)L.data.size();
+        for (int s : order)
+            if (blocks_[s].level == l && blocks_[s].leaf) L.data.push_back(s);
+        L.leaf_cnt[l] = (int32_t)L.data.size() - L.leaf_off[l];
+    }
+    L.all_leaves_off = (int32_t)L.data.size();
+    for (int i = 0; i < n_inst; ++i) {
+        L.data[i] = (int32_t)L.data.size();
+        for (int s : order)
+            if (blocks_[s].leaf && blocks_[s].inst == i) L.data.push_back(s);
+        L.data[n_inst + i] = (int32_t)L.data.size() - L.data[i];
+    }
+    L.all_leaves_cnt = (int32_t)L.data.size() - L.all_leaves_off;
+    L.all_blocks_off = (int32_t)L.data.size();
+    for (int s : order) L.data.push_back(s);
+    L.all_blocks_cnt = (int32_t)L.data.size() - L.all_blocks_off;
+    L.fine_off = (int32_t)L.data.size();
+    for (int s : order)
+        if (blocks_[s].level >= 1) L.data.push_back(s);
+    L.fine_cnt = (int32_t)L.data.size() - L.fine_off;
+}
+
+}  // namespace mrfv
+
+extern "C" uint64_t mrfv_morton_encode(int32_t shadow, int32_t level, int32_t bx, int32_t by,
+                                       int32_t bz) {
+    return mrfv::morton_encode(shadow, level, bx, by, bz);
+}
+
+extern "C" uint64_t mrfv_morton_neighbor(uint64_t id, int32_t shadow, int32_t d, int32_t dir,
+                                         int32_t *wrapped) {
+    // decode -> shift one block along axis d -> encode (periodic image at the edge)
+    int msb = 63;
+    while (msb > 0 && !((id >> msb) & 1ull)) --msb;
+    const int groups = msb / 3;
+    const uint64_t body = id & ((1ull << (3 * groups)) - 1);
+    int c[3] = {(int)mrfv::compact3(body), (int)mrfv::compact3(body >> 1),
+                (int)mrfv::compact3(body >> 2)};
+    const int n = 1 << groups;
+    c[d] += dir;
+    int w = 0;
+    if (c[d] < 0 || c[d] >= n) {
+        w = 1;
+        c[d] = (c[d] + n) % n;
+    }
+    if (wrapped) *wrapped = w;
+    return mrfv::morton_encode(shadow, groups - shadow, c[0], c[1], c[2]);
+}
