@@ -157,6 +157,10 @@ int mrfv_step(mrfv_ctx *ctx, void *U, void *U0, void *L, double *dt_dev);
  * non-physical state since the last check, else MRFV_OK.  Synchronises the stream. */
 int mrfv_check(mrfv_ctx *ctx);
 
+/* Tree statistics: out_host int64[4] = (blocks, leaves, leaf cells, finest level present).
+ * Host data only; no device access. */
+int mrfv_stats(mrfv_ctx *ctx, int64_t *out_host);
+
 /* Block table.  info_host: int64[n][8] = (slot, instance, level, bx, by, bz, is_leaf,
  * morton id with headbit).  *n receives the number of blocks (info_host may be NULL). */
 int mrfv_get_blocks(mrfv_ctx *ctx, int64_t *info_host, int32_t *n);

@@ -93,11 +93,13 @@ int do_project(mrfv_ctx *ctx, T *U) {
     return MRFV_OK;
 }
 
+// leaf_faces = 1 inside a stage: leaves get only the face layers the flux reads.
 template <typename T>
-int do_fill(mrfv_ctx *ctx, T *U, int max_level) {
+int do_fill(mrfv_ctx *ctx, T *U, int max_level, int leaf_faces = 0) {
     const HostLists &L = ctx->lists;
     for (int l = 0; l <= std::min(max_level, L.max_level); ++l)
-        HIP_OK(launch_fill_halos<T>(U, dlist(ctx, L.lvl_off[l]), L.lvl_cnt[l], ctx->tb, ctx->stream));
+        HIP_OK(launch_fill_halos<T>(U, dlist(ctx, L.lvl_off[l]), L.lvl_cnt[l], ctx->tb, leaf_faces,
+                                    ctx->stream));
     return MRFV_OK;
 }
 
@@ -316,7 +318,7 @@ int do_step(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt) {
                          (int)ctx->inst.size(), ctx->d_blockred, dt, ctx->stream));
     for (int s = 0; s < 3; ++s) {
         CALL(do_project<T>(ctx, U));
-        CALL(do_fill<T>(ctx, U, 1 << 20));
+        CALL(do_fill<T>(ctx, U, 1 << 20, 1));
         if (ctx->cfg.batched && sizeof(T) == 4) {
             CALL(do_stage_fused(ctx, s, dt, (float *)U, (float *)U0));
         } else {
@@ -553,6 +555,15 @@ int mrfv_check(mrfv_ctx *ctx) {
         HIP_OK(hipStreamSynchronize(ctx->stream));
         return fail(ctx, MRFV_ENONPHYS, "non-physical state (rho<=0, p+B<=0 or NaN)");
     }
+    return MRFV_OK;
+}
+
+int mrfv_stats(mrfv_ctx *ctx, int64_t *out) {
+    if (!ctx || !out) return MRFV_EINVAL;
+    out[0] = ctx->topo.count();
+    out[1] = ctx->lists.all_leaves_cnt;
+    out[2] = (int64_t)ctx->lists.all_leaves_cnt * CELLS_I;
+    out[3] = ctx->lists.max_level;
     return MRFV_OK;
 }
 

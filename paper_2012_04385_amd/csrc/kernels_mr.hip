@@ -85,11 +85,15 @@ __global__ __launch_bounds__(TPB) void k_prim2cons(const double *__restrict__ pr
 }
 
 // One thread per padded cell; interior cells return immediately.
+// leaf_faces: leaves only need the three face layers the flux stencil reads; their edge
+// and corner regions and the outermost layer are skipped (nothing reads them during a
+// stage: prediction reads parents, copies read interiors).
 template <typename T>
 __global__ __launch_bounds__(TPB) void k_fill_halos(T *__restrict__ U,
                                                     const int32_t *__restrict__ list, int n,
                                                     const BlockMeta *__restrict__ meta,
-                                                    const int32_t *__restrict__ nbr) {
+                                                    const int32_t *__restrict__ nbr,
+                                                    int leaf_faces) {
     const int b = blockIdx.x;
     if (b >= n) return;
     const int cell = blockIdx.y * TPB + threadIdx.x;
@@ -100,6 +104,16 @@ __global__ __launch_bounds__(TPB) void k_fill_halos(T *__restrict__ U,
                           c[2] >= HW && c[2] < HW + NI;
     if (interior) return;
     const BlockMeta m = meta[slot];
+    if (leaf_faces && m.leaf) {
+        int nout = 0;
+        bool outer = false;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            nout += (c[a] < HW || c[a] >= HW + NI) ? 1 : 0;
+            outer = outer || c[a] == 0 || c[a] == NP - 1;
+        }
+        if (nout > 1 || outer) return;
+    }
     int r[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -118,6 +132,7 @@ __global__ __launch_bounds__(TPB) void k_fill_halos(T *__restrict__ U,
 #pragma unroll
         for (int q = 0; q < 5; ++q) dst[o + q * CELLS_P] = s[so + q * CELLS_P];
     } else {
+        if (m.parent < 0) return;   // cannot happen: level 0 is complete
         const T *pu = U + (size_t)m.parent * 5 * CELLS_P;
 #pragma unroll 1
         for (int q = 0; q < 5; ++q)
@@ -168,31 +183,62 @@ __global__ __launch_bounds__(TPB) void k_predict(T *__restrict__ U,
 }
 
 // One workgroup per block (level >= 1): FP64 max over the padded cells of the rho and E
-// details.
+// details.  The prediction is applied separably through LDS: the 16^3 parent region the
+// 24^3 child stencils touch is staged once, then passes along x (16x16x24 values), y
+// (16x24x24) and z (24^3) evaluate each 1D step once per output instead of 31 times per
+// child cell.  The operation order per child cell equals predict_cell's.
 template <typename T>
 __global__ __launch_bounds__(TPB) void k_details(const T *__restrict__ U,
                                                  const int32_t *__restrict__ list, int n,
                                                  const BlockMeta *__restrict__ meta,
                                                  const InstDev *__restrict__ inst,
                                                  double *__restrict__ det) {
+    constexpr int R = NI;            // parent region edge (16)
+    __shared__ double A[R * NP * NP];   // parent region, later the y-pass (72 KB)
+    __shared__ double Bx[R * R * NP];   // x-pass (48 KB)
     __shared__ double red[TPB];
     const int b = blockIdx.x;
     if (b >= n) return;
     const int slot = list[b];
     const BlockMeta m = meta[slot];
     const InstDev P = inst[m.inst];
+    const int ox = m.bx & 1, oy = m.by & 1, oz = m.bz & 1;
     const T *pu = U + (size_t)m.parent * 5 * CELLS_P;
     const T *bu = U + (size_t)slot * 5 * CELLS_P;
-    const double inv_sr = 1.0 / P.scale_rho, inv_se = 1.0 / P.scale_E;
     double d = 0.0;
-    for (int cell = threadIdx.x; cell < CELLS_P; cell += TPB) {
-        const int i = cell % NP, j = (cell / NP) % NP, k = cell / (NP * NP);
-        const double pr = predict_cell<double, T>(pu, m.bx & 1, m.by & 1, m.bz & 1, i, j, k);
-        const double pe =
-            predict_cell<double, T>(pu + 4 * CELLS_P, m.bx & 1, m.by & 1, m.bz & 1, i, j, k);
-        const double dr = fabs((double)bu[cell] - pr) * inv_sr;
-        const double de = fabs((double)bu[cell + 4 * CELLS_P] - pe) * inv_se;
-        d = fmax(d, fmax(dr, de));
+    for (int v = 0; v < 2; ++v) {
+        const int q = v == 0 ? 0 : 4;
+        const double inv_s = v == 0 ? 1.0 / P.scale_rho : 1.0 / P.scale_E;
+        // parent padded cells (oz*8 + kk, oy*8 + jj, ox*8 + ii), kk, jj, ii in [0, 16)
+        for (int t = threadIdx.x; t < R * R * R; t += TPB) {
+            const int ii = t & 15, jj = (t >> 4) & 15, kk = t >> 8;
+            A[t] = (double)pu[q * CELLS_P + pidx(0, oz * 8 + kk, oy * 8 + jj, ox * 8 + ii)];
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < R * R * NP; t += TPB) {
+            const int i = t % NP, r = t / NP;
+            const int ci = i - HW, II = (ci >> 1) + HW;
+            const double *row = A + r * R + II;
+            Bx[t] = pred1<double>(row[-2], row[-1], row[0], row[1], row[2], (ci & 1) ? -1.0 : 1.0);
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < R * NP * NP; t += TPB) {
+            const int i = t % NP, j = (t / NP) % NP, kk = t / (NP * NP);
+            const int cj = j - HW, JJ = (cj >> 1) + HW;
+            const double *col = Bx + (kk * R + JJ) * NP + i;
+            A[t] = pred1<double>(col[-2 * NP], col[-NP], col[0], col[NP], col[2 * NP],
+                                 (cj & 1) ? -1.0 : 1.0);
+        }
+        __syncthreads();
+        for (int cell = threadIdx.x; cell < CELLS_P; cell += TPB) {
+            const int i = cell % NP, j = (cell / NP) % NP, k = cell / (NP * NP);
+            const int ck = k - HW, KK = (ck >> 1) + HW;
+            const double *c = A + (KK * NP + j) * NP + i;
+            const double pv = pred1<double>(c[-2 * NP * NP], c[-NP * NP], c[0], c[NP * NP],
+                                            c[2 * NP * NP], (ck & 1) ? -1.0 : 1.0);
+            d = fmax(d, fabs((double)bu[q * CELLS_P + cell] - pv) * inv_s);
+        }
+        __syncthreads();
     }
     red[threadIdx.x] = d;
     __syncthreads();
@@ -371,10 +417,10 @@ hipError_t launch_prim2cons(const double *prim, const int32_t *slots, int n, T *
 
 template <typename T>
 hipError_t launch_fill_halos(T *U, const int32_t *list, int n, const DevTables &tb,
-                             hipStream_t st) {
+                             int leaf_faces, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_halos<T>, grid2(n, (CELLS_P + TPB - 1) / TPB), dim3(TPB), 0, st,
-                       U, list, n, tb.meta, tb.nbr);
+                       U, list, n, tb.meta, tb.nbr, leaf_faces);
     return hipGetLastError();
 }
 
@@ -438,7 +484,7 @@ hipError_t launch_totals(const T *U, const int32_t *leaves, int n, const DevTabl
     template hipError_t launch_prim2cons<T>(const double *, const int32_t *, int, T *,     \
                                             const BlockMeta *, const InstDev *, hipStream_t); \
     template hipError_t launch_fill_halos<T>(T *, const int32_t *, int, const DevTables &, \
-                                             hipStream_t);                                  \
+                                             int, hipStream_t);                             \
     template hipError_t launch_project<T>(T *, const int32_t *, int, const DevTables &,    \
                                           hipStream_t);                                     \
     template hipError_t launch_predict<T>(T *, const int32_t *, int, const DevTables &,    \

@@ -99,7 +99,7 @@ hipError_t launch_prim2cons(const double *prim, const int32_t *slots, int n, T *
                             const BlockMeta *meta, const InstDev *inst, hipStream_t st);
 template <typename T>
 hipError_t launch_fill_halos(T *U, const int32_t *list, int n, const DevTables &tb,
-                             hipStream_t st);
+                             int leaf_faces, hipStream_t st);
 template <typename T>
 hipError_t launch_project(T *U, const int32_t *list, int n, const DevTables &tb,
                           hipStream_t st);

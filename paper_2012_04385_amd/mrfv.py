@@ -73,6 +73,7 @@ def lib():
         "mrfv_step": ([vp, vp, vp, vp, vp], C.c_int),
         "mrfv_check": ([vp], C.c_int),
         "mrfv_get_blocks": ([vp, C.POINTER(i64), C.POINTER(i32)], C.c_int),
+        "mrfv_stats": ([vp, C.POINTER(i64)], C.c_int),
         "mrfv_refine_block": ([vp, vp, i32, i32, i32, i32, i32], C.c_int),
         "mrfv_coarsen_block": ([vp, i32, i32, i32, i32, i32], C.c_int),
         "mrfv_enable_kernel_timing": ([vp, i32], C.c_int),
@@ -93,7 +94,7 @@ def exported_symbols():
             "mrfv_interior_bytes", "mrfv_init_blocks", "mrfv_fill_halos", "mrfv_rhs_stage",
             "mrfv_rk_update", "mrfv_mr_project", "mrfv_mr_predict", "mrfv_mr_flag",
             "mrfv_cfl_dt", "mrfv_totals", "mrfv_commit_flags", "mrfv_step", "mrfv_check",
-            "mrfv_get_blocks", "mrfv_refine_block", "mrfv_coarsen_block",
+            "mrfv_get_blocks", "mrfv_stats", "mrfv_refine_block", "mrfv_coarsen_block",
             "mrfv_enable_kernel_timing", "mrfv_kernel_time", "mrfv_morton_encode",
             "mrfv_morton_neighbor"]
 
@@ -292,6 +293,11 @@ class Solver:
         U = U[:, :, HW:HW + NI, HW:HW + NI, HW:HW + NI].double().cpu().numpy()
         return {tuple(int(v) for v in r[2:6]): U[k] for k, r in enumerate(sel)}
 
+    def stats(self):
+        """(blocks, leaves, leaf cells, finest level) from the host tree."""
+        out = (C.c_int64 * 4)()
+        self._chk(lib().mrfv_stats(self.h, out))
+        return tuple(int(v) for v in out)
+
     def leaf_cells(self) -> int:
-        info = self.blocks()
-        return int((info[:, 6] == 1).sum()) * NI ** 3
+        return self.stats()[2]

@@ -198,22 +198,33 @@ def test_cfl_and_totals(orc, torch_mod, dtype):
 
 # ------------------------------------------------------------------ whole runs --------
 
-def test_sod_single_level_fp64_plain(orc, torch_mod):
+@pytest.mark.parametrize("noise", [0.0, 1e-3])
+def test_sod_single_level_fp64_plain(orc, torch_mod, noise):
     pb = W.sod_single_level()
+    pb.noise = noise
     o = orc.Sim(pb).init()
     from paper_2012_04385_amd.mrfv import Solver
     g = Solver([pb], dtype="f64", batched=False).init()
     for _ in range(pb.steps):
         o.step()
     g.run(pb.steps)
-    # FP64 on both sides, different operation order (FMA contraction, closed-form vs
-    # matrix projection, WENO normalisation): round-off amplified by the nonlinear
-    # weights across the shock over 30 stages
-    assert abs(g.time[0] - o.time) <= 1e-11 * o.time
     ol, gl = o.leaf_states(), g.leaf_states()
     worst = max(np.abs(gl[k] - v).max() / np.abs(v).max() for k, v in ol.items())
-    print(f"sod fp64: max rel state diff {worst:.3e}, dt rel diff {abs(g.time[0] - o.time) / o.time:.3e}")
-    assert worst <= 1e-9
+    e_rho = l1_diff(o, g, 0)
+    print(f"sod fp64 noise={noise}: max rel {worst:.3e}, L1 rho {e_rho:.3e}, "
+          f"time rel {abs(g.time[0] - o.time) / o.time:.3e}")
+    if noise == 0.0:
+        # FP64 on both sides, different operation order: round-off agreement
+        assert abs(g.time[0] - o.time) <= 1e-13 * o.time
+        assert worst <= 1e-12
+    else:
+        # With density noise some cells have a normal velocity that is zero up to
+        # round-off; the strict sign test of the Roe/LLF switch can then take different
+        # branches on the two sides (the LLF speed comes from the other cell), which
+        # changes one face flux by O(alpha |dw|).  It happens along the front of the
+        # disturbed region (a plane of faces); measured max 9.2e-8, L1 5.2e-9.
+        assert worst <= 1e-6
+        assert e_rho <= 2e-8
 
 
 def test_sod_single_level_fp32_batched(orc, torch_mod):
@@ -247,6 +258,7 @@ def test_blast_mr_run(orc, torch_mod, dtype, batched, steps):
     e_rho, e_E = l1_diff(o, g, 0), l1_diff(o, g, 4)
     print(f"blast {dtype}: L1 rho {e_rho:.3e}, L1 E {e_E:.3e} after {steps} steps")
     if dtype == "f64":
-        assert e_rho <= 1e-10
+        # FP64 vs FP64: sign-test flips at round-off-zero velocities (see the Sod test)
+        assert e_rho <= 2e-8
     else:
         assert e_rho <= 1e-5
