@@ -8,10 +8,11 @@
 // WENO5.  The characteristic projection uses the closed-form left eigenvectors of the
 // Roe-averaged Jacobian (eq:StiffenedGas gives c^2 = (gamma-1)(H - |v|^2/2)).
 //
-// Work decomposition: a thread walks one pencil of 16 cells along one axis; the six-cell
-// stencil is a sliding window of cell states in registers, so each cell's primitive
-// quantities are computed once per pencil and each face flux once per block.  Stencils
-// are not contractions, so no MFMA is used here.
+// Work decomposition.  Plain path (k_flux): a thread walks one pencil of 16 cells along
+// one axis with a six-cell register window, so each cell's primitives are computed once
+// per pencil.  Batched path (k_rhs_update): one face per thread inside groups of z-planes,
+// fluxes staged in LDS, fused with the stage update.  Each face flux is computed once per
+// block on both paths.  Stencils are not contractions, so no MFMA is used here.
 //
 // Jump correction (algo:ComputeLoop, coarse cell adjustment): the boundary face fluxes of
 // every leaf are stored; non-leaf blocks receive the area average of their children's
@@ -104,8 +105,36 @@ __device__ __forceinline__ T char_flux(const T W[6], const T G[6], T lL, T lR) {
     return weno5(gp[0], gp[1], gp[2], gp[3], gp[4]) + weno5(gm[5], gm[4], gm[3], gm[2], gm[1]);
 }
 
-// Numerical flux through the face between window cells 2 and 3 (rotated components).
+// Same result with at most two WENO evaluations per wavefront: if any lane of the wave
+// needs the LLF split, every lane evaluates W-(g+) + W+(g-) with g+ = g, g- = 0 for
+// upwind-right lanes and g+ = 0, g- = g for upwind-left lanes (a WENO of zeros is exactly
+// zero); otherwise one WENO with the input order picked per lane.  Bitwise equal to
+// char_flux, but mixed waves no longer execute all three branches.
 template <typename T>
+__device__ __forceinline__ T char_flux_uniform(const T W[6], const T G[6], T lL, T lR) {
+    const bool up = lL > (T)0 && lR > (T)0;
+    const bool dn = lL < (T)0 && lR < (T)0;
+    const bool llf = !(up || dn);
+    if (!__any(llf)) {
+        T a[5];
+#pragma unroll
+        for (int j = 0; j < 5; ++j) a[j] = up ? G[j] : G[5 - j];
+        return weno5(a[0], a[1], a[2], a[3], a[4]);
+    }
+    const T al = fmax(fabs(lL), fabs(lR));
+    T gp[6], gm[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        const T p = (T)0.5 * (G[j] + al * W[j]);
+        const T m = (T)0.5 * (G[j] - al * W[j]);
+        gp[j] = up ? G[j] : (dn ? (T)0 : p);
+        gm[j] = dn ? G[j] : (up ? (T)0 : m);
+    }
+    return weno5(gp[0], gp[1], gp[2], gp[3], gp[4]) + weno5(gm[5], gm[4], gm[3], gm[2], gm[1]);
+}
+
+// Numerical flux through the face between window cells 2 and 3 (rotated components).
+template <typename T, bool UNIFORM = false>
 __device__ __forceinline__ void face_flux(const CellState<T> w[6], const Gas<T> &G, T F[5]) {
     const CellState<T> &L = w[2], &R = w[3];
     const T inv = rcp_(L.sr + R.sr);
@@ -145,18 +174,20 @@ __device__ __forceinline__ void face_flux(const CellState<T> w[6], const Gas<T> 
     // field 1: u - c
 #pragma unroll
     for (int j = 0; j < 6; ++j) { W[j] = (T)0.5 * (tU[j] - xU[j]); Gc[j] = (T)0.5 * (tF[j] - xF[j]); }
-    g[0] = char_flux(W, Gc, unL - L.c, unR - R.c);
+#define MRFV_CF(W_, G_, a_, b_) (UNIFORM ? char_flux_uniform(W_, G_, a_, b_) : char_flux(W_, G_, a_, b_))
+    g[0] = MRFV_CF(W, Gc, unL - L.c, unR - R.c);
     // field 2: entropy, u
 #pragma unroll
     for (int j = 0; j < 6; ++j) { W[j] = a0[j] - tU[j]; Gc[j] = f0[j] - tF[j]; }
-    g[1] = char_flux(W, Gc, unL, unR);
+    g[1] = MRFV_CF(W, Gc, unL, unR);
     // fields 3, 4: shear, u
-    g[2] = char_flux(wt1, gt1, unL, unR);
-    g[3] = char_flux(wt2, gt2, unL, unR);
+    g[2] = MRFV_CF(wt1, gt1, unL, unR);
+    g[3] = MRFV_CF(wt2, gt2, unL, unR);
     // field 5: u + c
 #pragma unroll
     for (int j = 0; j < 6; ++j) { W[j] = (T)0.5 * (tU[j] + xU[j]); Gc[j] = (T)0.5 * (tF[j] + xF[j]); }
-    g[4] = char_flux(W, Gc, unL + L.c, unR + R.c);
+    g[4] = MRFV_CF(W, Gc, unL + L.c, unR + R.c);
+#undef MRFV_CF
 
     // Back to conservative components: F = R g.
     const T s15 = g[0] + g[4];
@@ -401,68 +432,166 @@ struct LdsSink {
     __device__ void face(int side, int q, T v) { FF[(side * 5 + q) * FACE + rm] = v; }
 };
 
-// One workgroup per leaf: x-, y- and z-pencils accumulate the flux differences in LDS,
-// then each thread finishes its z-column with the SSP-RK3 stage update in place (no other
-// workgroup reads this block's array, and the thread's own z-pencil was the last reader of
-// its column).
+// One workgroup per leaf.  The block is walked in groups of GP z-planes; for each group
+// every x-, y- and z-face flux the group's cells need is computed once, one face per
+// thread (coalesced, L1-resident six-cell stencils; all axes share one code path), and
+// staged in LDS.  Each thread then owns one (x, y) column: it forms
+// D = ((Dx + Dy) + Dz) for the group's cells and applies the SSP-RK3 stage update in
+// place.  The update of a group is deferred until the next group's faces are done,
+// because z-faces up to two and a half planes away still read the old values.
+constexpr int GP = 2;                         // z-planes per group
+constexpr int TPB_F = 320;                    // 1600 faces per group = 5 rounds
+constexpr int NFX = GP * NI * (NI + 1);       // x-faces per group (544)
+constexpr int NFZ = NI * NI;                  // z-faces per face plane (256)
+
 template <typename T>
-__global__ __launch_bounds__(TPB) void k_rhs_update(int stage, const double *__restrict__ dt,
-                                                    T *U, T *U0,
-                                                    const int32_t *__restrict__ leaves, int n,
-                                                    const BlockMeta *__restrict__ meta,
-                                                    const InstDev *__restrict__ inst, T *FF,
-                                                    int32_t *err) {
-    __shared__ T acc[5 * CELLS_I];
+__device__ __forceinline__ void load_cell_rt(const T *__restrict__ u, int idx, int n1, int t1,
+                                             int t2, CellState<T> &s) {
+    s.r = u[idx];
+    s.mn = u[idx + n1 * CELLS_P];
+    s.mt1 = u[idx + t1 * CELLS_P];
+    s.mt2 = u[idx + t2 * CELLS_P];
+    s.E = u[idx + 4 * CELLS_P];
+}
+
+// Face flux along axis d for the stencil starting at padded index base (six cells at
+// base + j*stride); the result is returned in physical component order.
+template <typename T>
+__device__ __forceinline__ void face_flux_at(const T *__restrict__ ub, int d, int base,
+                                             const Gas<T> &G, T Fp[5]) {
+    const int stride = d == 0 ? 1 : (d == 1 ? NP : NP * NP);
+    const int n1 = d + 1, t1 = d == 0 ? 2 : (d == 1 ? 3 : 1), t2 = d == 0 ? 3 : (d == 1 ? 1 : 2);
+    CellState<T> w[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        load_cell_rt(ub, base + j * stride, n1, t1, t2, w[j]);
+        derive_state(G, w[j]);
+    }
+    T F[5];
+    face_flux<T, true>(w, G, F);
+    Fp[0] = F[0];
+    Fp[4] = F[4];
+    Fp[n1] = F[1];
+    Fp[t1] = F[2];
+    Fp[t2] = F[3];
+}
+
+template <typename T>
+__global__ __launch_bounds__(TPB_F) void k_rhs_update(int stage, const double *__restrict__ dt,
+                                                      T *U, T *U0,
+                                                      const int32_t *__restrict__ leaves, int n,
+                                                      const BlockMeta *__restrict__ meta,
+                                                      const InstDev *__restrict__ inst, T *FF,
+                                                      int32_t *err) {
+    __shared__ T Fx[GP][NI][NI + 1][5];   // [plane][y][face x][q]
+    __shared__ T Fy[GP][NI + 1][NI][5];   // [plane][face y][x][q]
+    __shared__ T Fz[GP + 1][NI][NI][5];   // [face plane][y][x][q]; plane j = face k0 + j - 1/2
     const int b = blockIdx.x;
     if (b >= n) return;
     const int slot = leaves[b];
     const BlockMeta mt = meta[slot];
     const InstDev P = inst[mt.inst];
     const Gas<T> G = gas_of<T>(P);
-    const int r = threadIdx.x & 15, m = threadIdx.x >> 4;
     T *ub = U + (size_t)slot * 5 * CELLS_P;
     T *ffs = FF + (size_t)slot * 6 * 5 * FACE;
-    {
-        LdsSink<T, false> s0{acc, ffs, m * NI + r};
-        pencil<T, 0>(ub, r, m, G, s0);
-    }
-    __syncthreads();
-    {
-        LdsSink<T, true> s1{acc, ffs, m * NI + r};
-        pencil<T, 1>(ub, r, m, G, s1);
-    }
-    __syncthreads();
-    {
-        LdsSink<T, true> s2{acc, ffs, m * NI + r};
-        pencil<T, 2>(ub, r, m, G, s2);
-    }
-    // the z-column (x = r, y = m) is complete in acc (written by this thread last)
+    T *u0b = U0 + (size_t)slot * 5 * CELLS_I;
     const T inv_dx = (T)(1.0 / ldexp(P.dx0, -mt.level));
     const T dtt = (T)dt[mt.inst];
     const T a = stage_coef<T>(stage);
-    T *u0b = U0 + (size_t)slot * 5 * CELLS_I;
+    const int tid = threadIdx.x;
+    const bool owner = tid < FACE;              // column owners (x = tid & 15, y = tid >> 4)
+    const int cx = tid & 15, cy = tid >> 4;
+    T Dpend[GP][5];                             // D of the previous group, awaiting update
     bool ok = true;
-#pragma unroll 1
-    for (int z = 0; z < NI; ++z) {
-        const int c = (z * NI + m) * NI + r;
-        const int o = ((z + HW) * NP + m + HW) * NP + r + HW;
-        T un[5];
+
+    auto update_group = [&](int k0, T D[GP][5]) {
 #pragma unroll
-        for (int q = 0; q < 5; ++q) {
-            const T us = ub[o + q * CELLS_P];
-            T u0;
-            if (stage == 0) {
-                u0 = us;
-                u0b[q * CELLS_I + c] = us;
-            } else {
-                u0 = u0b[q * CELLS_I + c];
+        for (int p = 0; p < GP; ++p) {
+            const int z = k0 + p;
+            const int c = (z * NI + cy) * NI + cx;
+            const int o = ((z + HW) * NP + cy + HW) * NP + cx + HW;
+            T un[5];
+#pragma unroll
+            for (int q = 0; q < 5; ++q) {
+                const T us = ub[o + q * CELLS_P];
+                T u0;
+                if (stage == 0) {
+                    u0 = us;
+                    u0b[q * CELLS_I + c] = us;
+                } else {
+                    u0 = u0b[q * CELLS_I + c];
+                }
+                un[q] = u0 + a * ((us - u0) + dtt * (-D[p][q] * inv_dx));
+                ub[o + q * CELLS_P] = un[q];
             }
-            const T Lq = -acc[q * CELLS_I + c] * inv_dx;
-            un[q] = u0 + a * ((us - u0) + dtt * Lq);
-            ub[o + q * CELLS_P] = un[q];
+            ok = ok && physical_state(un, G);
         }
-        ok = ok && physical_state(un, G);
+    };
+
+    for (int g = 0; g < NI / GP; ++g) {
+        const int k0 = g * GP;
+        const int first_z = g == 0 ? 0 : 1;     // face planes already known from the last group
+        const int nz = (GP + 1 - first_z) * NFZ;
+        const int total = 2 * NFX + nz;
+        for (int t = tid; t < total; t += TPB_F) {
+            T F[5];
+            if (t < NFX) {                      // x-faces: (plane p, row y, face f)
+                const int f = t % (NI + 1), y = (t / (NI + 1)) % NI, p = t / ((NI + 1) * NI);
+                const int base = ((k0 + p + HW) * NP + y + HW) * NP + f + 1;
+                face_flux_at(ub, 0, base, G, F);
+#pragma unroll
+                for (int q = 0; q < 5; ++q) Fx[p][y][f][q] = F[q];
+                if (f == 0 || f == NI) {
+#pragma unroll
+                    for (int q = 0; q < 5; ++q) ffs[((f ? 1 : 0) * 5 + q) * FACE + (k0 + p) * NI + y] = F[q];
+                }
+            } else if (t < 2 * NFX) {           // y-faces: (plane p, face f, column x)
+                const int u = t - NFX;
+                const int x = u % NI, f = (u / NI) % (NI + 1), p = u / (NI * (NI + 1));
+                const int base = ((k0 + p + HW) * NP + f + 1) * NP + x + HW;
+                face_flux_at(ub, 1, base, G, F);
+#pragma unroll
+                for (int q = 0; q < 5; ++q) Fy[p][f][x][q] = F[q];
+                if (f == 0 || f == NI) {
+#pragma unroll
+                    for (int q = 0; q < 5; ++q) ffs[((2 + (f ? 1 : 0)) * 5 + q) * FACE + (k0 + p) * NI + x] = F[q];
+                }
+            } else {                            // z-faces: (face plane j, y, x)
+                const int u = t - 2 * NFX;
+                const int x = u % NI, y = (u / NI) % NI, j = u / NFZ + first_z;
+                const int kf = k0 + j;          // face between interior planes kf-1 and kf
+                const int base = ((kf + 1) * NP + y + HW) * NP + x + HW;   // padded z = kf+1 .. kf+6
+                face_flux_at(ub, 2, base, G, F);
+#pragma unroll
+                for (int q = 0; q < 5; ++q) Fz[j][y][x][q] = F[q];
+                if (kf == 0 || kf == NI) {
+#pragma unroll
+                    for (int q = 0; q < 5; ++q) ffs[((4 + (kf ? 1 : 0)) * 5 + q) * FACE + y * NI + x] = F[q];
+                }
+            }
+        }
+        __syncthreads();
+        if (owner) {
+            if (g > 0) update_group(k0 - GP, Dpend);
+#pragma unroll
+            for (int p = 0; p < GP; ++p)
+#pragma unroll
+                for (int q = 0; q < 5; ++q) {
+                    const T dxq = Fx[p][cy][cx + 1][q] - Fx[p][cy][cx][q];
+                    const T dyq = Fy[p][cy + 1][cx][q] - Fy[p][cy][cx][q];
+                    const T dzq = Fz[p + 1][cy][cx][q] - Fz[p][cy][cx][q];
+                    Dpend[p][q] = (dxq + dyq) + dzq;
+                }
+        }
+        __syncthreads();
+        // the last face plane of this group is the first one of the next
+        for (int t = tid; t < NFZ * 5; t += TPB_F) {
+            const int q = t % 5, x = (t / 5) % NI, y = t / (5 * NI);
+            Fz[0][y][x][q] = Fz[GP][y][x][q];
+        }
+        __syncthreads();
     }
+    if (owner) update_group(NI - GP, Dpend);
     if (!ok) atomicOr(err, 1);
 }
 
@@ -552,7 +681,7 @@ hipError_t launch_rhs_update_f32(int stage, const double *dt, float *U, float *U
                                  const int32_t *leaves, int n, const DevTables &tb,
                                  const InstDev *inst, float *FF, int32_t *err, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_rhs_update<float>, dim3(n), dim3(TPB), 0, st, stage, dt, U, U0, leaves,
+    hipLaunchKernelGGL(k_rhs_update<float>, dim3(n), dim3(TPB_F), 0, st, stage, dt, U, U0, leaves,
                        n, tb.meta, inst, FF, err);
     return hipGetLastError();
 }
