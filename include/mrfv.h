@@ -64,7 +64,10 @@ typedef struct {
     int32_t slot_capacity;  /* maximum number of blocks over all instances              */
     int32_t batched;        /* 0: plain path (one launch per tree level, unfused update);
                                1: batched path (all leaves of all levels and instances in
-                               one fused rhs + update launch)                          */
+                               one fused rhs + update launch; fused for FP32 only);
+                               2: batched path with the CFL step and the three RK stages
+                               replayed from one hipGraph (captured on first use, valid
+                               across tree changes; FP32)                              */
 } mrfv_config;
 
 typedef struct mrfv_ctx mrfv_ctx;
@@ -187,6 +190,69 @@ int mrfv_kernel_time(mrfv_ctx *ctx, int64_t *launches, double *total_ms, int64_t
 uint64_t mrfv_morton_encode(int32_t shadow, int32_t level, int32_t bx, int32_t by, int32_t bz);
 uint64_t mrfv_morton_neighbor(uint64_t id, int32_t shadow, int32_t d, int32_t dir,
                               int32_t *wrapped);
+
+/* ---------------------------------------------------------------------------------------
+ * Learned refinement proposer.  Not part of the paper's method: a small network predicts,
+ * from the state at the start of a step, the refine / keep / coarsen decision that the
+ * Harten detail threshold (Sec. "Multiresolution", eq:LevelWiseEpsilon) will take at the
+ * end of it, so that the host can build the next tree's tables while the device
+ * integrates.  The threshold stays the judge: a proposal is adopted only when it equals
+ * the judged flags on every leaf, so the solution never depends on the network.
+ *
+ * Network: 192 -> 64 -> 64 -> 3 with ReLU; parameters as one FP32 vector
+ * (W1[192][64], b1[64], W2[64][64], b2[64], W3[64][3], b3[3]; W[in][out] row-major),
+ * products on the matrix cores in bfloat16 with FP32 accumulation.  Classes:
+ * 0 refine, 1 keep, 2 coarsen.
+ * ------------------------------------------------------------------------------------- */
+typedef struct mrfv_mlp mrfv_mlp;
+
+/* Network object for up to max_rows samples per call; parameters start at zero.
+ * hip_stream: stream every call is queued on (NULL = default stream). */
+int mrfv_mlp_create(mrfv_mlp **out, int32_t max_rows, void *hip_stream);
+int mrfv_mlp_destroy(mrfv_mlp *mlp);
+const char *mrfv_mlp_last_error(const mrfv_mlp *mlp);
+int32_t mrfv_mlp_nparams(void);
+/* Parameters from / to host float[nparams]; set_params also resets the Adam moments.
+ * Both synchronise the stream. */
+int mrfv_mlp_set_params(mrfv_mlp *mlp, const float *params_host);
+int mrfv_mlp_get_params(mrfv_mlp *mlp, float *params_host);
+/* Forward pass: X_dev dev float[N][192] -> logits_dev dev float[N][3].  Asynchronous. */
+int mrfv_mlp_forward(mrfv_mlp *mlp, const float *X_dev, int32_t N, float *logits_dev);
+/* Class-weighted mean softmax cross-entropy of labels_host int32[N] (0..2) with class
+ * weights class_w_host float[3], and its gradient with respect to the parameters, kept on
+ * the device for mrfv_mlp_adam_step; loss_host (float, may be NULL) and grad_host
+ * (float[nparams], may be NULL) receive copies.  Synchronises the stream. */
+int mrfv_mlp_loss_grad(mrfv_mlp *mlp, const float *X_dev, const int32_t *labels_host,
+                       const float *class_w_host, int32_t N, float *loss_host, float *grad_host);
+/* One Adam update of the parameters with the last gradient (bias-corrected moments). */
+int mrfv_mlp_adam_step(mrfv_mlp *mlp, float lr, float beta1, float beta2, float eps);
+
+/* features -- the proposer's input for every leaf, in the order of the all-leaves list:
+ * over each of the 4^3 sub-cubes of 4^3 interior cells, the means of rho, |grad rho|
+ * (central differences in cell units, one-sided at block faces) and p, written as
+ * (mean rho / scale_rho - 1, log(1 + mean |grad rho| / (scale_rho eps_l)),
+ * mean p / scale_p - 1) with scale_p = (gamma - 1) scale_E; X_dev[r][3 s + c] with
+ * s = (sz 4 + sy) 4 + sx.  X_dev: dev float[capacity][192]; slots_host (may be NULL):
+ * host int32[capacity] receives the leaf slots; *n the number of leaves.  Asynchronous. */
+int mrfv_features(mrfv_ctx *ctx, const void *U, float *X_dev, int32_t *slots_host, int32_t *n);
+
+/* set_proposer -- mode 0: off (the default); 1: the network mlp (borrowed, must outlive
+ * its use) proposes each step's flags; 2: persistence, i.e. the proposal is "no change".
+ * With a proposal, mrfv_step commits it on the host tree, builds and uploads its tables to
+ * a second device copy while the device integrates, undoes the commit, and adopts the copy
+ * when the judged flags equal the proposal; otherwise it commits the judged flags as
+ * usual.  Results are identical in every mode. */
+int mrfv_set_proposer(mrfv_ctx *ctx, mrfv_mlp *mlp, int32_t mode);
+
+/* last_flags -- the judged flags (host int8[capacity] by slot, as mr_flag writes them) of
+ * the last mrfv_step that adapted the tree, with or without a proposer: the training
+ * labels of the proposer.  Zero before the first adaptive step.  Synchronises the stream. */
+int mrfv_last_flags(mrfv_ctx *ctx, int8_t *flags_host);
+
+/* proposer_stats -- out_host int64[11] = (steps, hits, then for refine, keep, coarsen:
+ * true positives, false positives, false negatives); build_ms_host (may be NULL): host
+ * milliseconds spent decoding and staging proposals. */
+int mrfv_proposer_stats(mrfv_ctx *ctx, int64_t *out_host, double *build_ms_host);
 
 #ifdef __cplusplus
 }

@@ -91,6 +91,13 @@ def lib():
         L.orc_morton_neighbor.restype = C.c_uint64
         L.orc_morton_level.argtypes = [C.c_uint64, i32]
         L.orc_morton_level.restype = i32
+        L.orc_mlp_nparams.restype = C.c_int
+        L.orc_bf16_round.argtypes = [d]
+        L.orc_bf16_round.restype = d
+        L.orc_mlp_forward.argtypes = [pd, pd, C.c_int, C.c_int, pd]
+        L.orc_mlp_loss_grad.argtypes = [pd, pd, C.POINTER(C.c_int32), pd, C.c_int, C.c_int, pd]
+        L.orc_mlp_loss_grad.restype = d
+        L.orc_features.argtypes = [pd, d, d, d, d, d, pd]
         _LIB = L
     return _LIB
 
@@ -169,6 +176,44 @@ def morton_neighbor(mid: int, d: int, direction: int):
 
 def morton_level(mid: int, shadow: int) -> int:
     return int(lib().orc_morton_level(C.c_uint64(mid), shadow))
+
+
+# ------------------------------------------------------------- learned proposer -------
+
+def mlp_nparams() -> int:
+    return lib().orc_mlp_nparams()
+
+
+def bf16_round(x: float) -> float:
+    return lib().orc_bf16_round(float(x))
+
+
+def mlp_forward(params, X, bf16=True) -> np.ndarray:
+    P_ = np.ascontiguousarray(params, dtype=np.float64)
+    X_ = np.ascontiguousarray(X, dtype=np.float64)
+    n = X_.shape[0]
+    out = np.zeros((n, 3))
+    lib().orc_mlp_forward(_dp(P_), _dp(X_), n, 1 if bf16 else 0, _dp(out))
+    return out
+
+
+def mlp_loss_grad(params, X, labels, class_w=(1.0, 1.0, 1.0), bf16=True):
+    P_ = np.ascontiguousarray(params, dtype=np.float64)
+    X_ = np.ascontiguousarray(X, dtype=np.float64)
+    y = np.ascontiguousarray(labels, dtype=np.int32)
+    w = np.ascontiguousarray(class_w, dtype=np.float64)
+    g = np.zeros_like(P_)
+    loss = lib().orc_mlp_loss_grad(_dp(P_), _dp(X_), y.ctypes.data_as(C.POINTER(C.c_int32)), _dp(w),
+                                   X_.shape[0], 1 if bf16 else 0, _dp(g))
+    return loss, g
+
+
+def features(u_padded, gamma, B, s_rho, s_p, eps_l) -> np.ndarray:
+    u = np.ascontiguousarray(u_padded, dtype=np.float64)
+    assert u.shape == (5, P, P, P)
+    out = np.zeros(192)
+    lib().orc_features(_dp(u), gamma, B, s_rho, s_p, eps_l, _dp(out))
+    return out
 
 
 # ------------------------------------------------------------------ simulation -------

@@ -142,6 +142,24 @@ double orc_sim_time(const orc_sim *s);
 /* Fraction of face-fields that took the LLF branch during the last rhs evaluation. */
 double orc_sim_llf_fraction(const orc_sim *s);
 
+/* ---------------- learned refinement proposer (not in the paper) -------------------- */
+
+/* Number of parameters of the 192-64-64-3 network (layout W1 b1 W2 b2 W3 b3, weights
+ * [in][out] row-major). */
+int orc_mlp_nparams(void);
+/* Round to the nearest bfloat16, ties to even. */
+double orc_bf16_round(double x);
+/* logits[N][3] of X[N][192]; bf16_emulation = 1 rounds what the GPU stores in bfloat16. */
+void orc_mlp_forward(const double *params, const double *X, int N, int bf16_emulation,
+                     double *logits);
+/* Class-weighted mean softmax cross-entropy and its gradient (grad may be NULL).
+ * labels[N] in {0: refine, 1: keep, 2: coarsen}; class_w[3]. */
+double orc_mlp_loss_grad(const double *params, const double *X, const int32_t *labels,
+                         const double *class_w, int N, int bf16_emulation, double *grad);
+/* Proposer features (192) of one padded block, see orc_mlp.cpp. */
+void orc_features(const double *u_padded, double gamma, double B, double s_rho, double s_p,
+                  double eps_l, double *out);
+
 /* Morton ids with headbit (Sec. "Modular block-based MR algorithm", eq:NeigboorLookup).
  * shadow = number of 3-bit groups above level 0 (level-0 blocks per edge = 2^shadow). */
 uint64_t orc_morton_encode(int32_t shadow, int32_t level, int32_t bx, int32_t by, int32_t bz);

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -52,6 +53,19 @@ int check_instance(mrfv_ctx *ctx, const mrfv_instance &p, int i) {
     return MRFV_OK;
 }
 
+// A jump face exists when some leaf has a non-leaf same-level face neighbour.
+bool any_jump(const Topology &tp, const HostLists &L, const std::vector<int32_t> &nbr) {
+    const int faces[6] = {12, 14, 10, 16, 4, 22};
+    for (int t = 0; t < L.all_leaves_cnt; ++t) {
+        const int s = L.data[L.all_leaves_off + t];
+        for (int f = 0; f < 6; ++f) {
+            const int nb = nbr[(size_t)s * 27 + faces[f]];
+            if (nb >= 0 && !tp.block(nb).leaf) return true;
+        }
+    }
+    return false;
+}
+
 // Rebuild the device tables from the host tree.
 int upload_tables(mrfv_ctx *ctx) {
     std::vector<BlockMeta> meta;
@@ -68,37 +82,53 @@ int upload_tables(mrfv_ctx *ctx) {
                           hipMemcpyHostToDevice, st));
     HIP_OK(hipMemcpyAsync(ctx->tb.lists, ctx->lists.data.data(),
                           ctx->lists.data.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(ctx->d_desc, ctx->lists.desc.data(), ctx->lists.desc.size() * sizeof(int32_t),
+                          hipMemcpyHostToDevice, st));
     HIP_OK(hipStreamSynchronize(st));   // host vectors die at return
-    // jump faces exist when some leaf has a non-leaf same-level face neighbour
-    ctx->has_jumps = false;
-    const HostLists &L = ctx->lists;
-    for (int t = 0; t < L.all_leaves_cnt && !ctx->has_jumps; ++t) {
-        const int s = L.data[L.all_leaves_off + t];
-        const int faces[6] = {12, 14, 10, 16, 4, 22};
-        for (int f = 0; f < 6; ++f) {
-            const int nb = nbr[(size_t)s * 27 + faces[f]];
-            if (nb >= 0 && !ctx->topo.block(nb).leaf) { ctx->has_jumps = true; break; }
-        }
-    }
+    ctx->has_jumps = any_jump(ctx->topo, ctx->lists, nbr);
     return MRFV_OK;
 }
 
-const int32_t *dlist(const mrfv_ctx *ctx, int32_t off) { return ctx->tb.lists + off; }
+// Work lists.  Eager: offset and count from the host tree, one workgroup per block.
+// Captured (ctx->capturing): offset and count read on the device from the descriptor
+// table, grid bounded by the capacity, so the graph stays valid when the tree changes.
+WorkList wlist(const mrfv_ctx *ctx, int which, int grid_cap = 2048) {
+    WorkList w;
+    w.base = ctx->tb.lists;
+    if (ctx->capturing) {
+        w.desc = ctx->d_desc + 2 * which;
+        // bound: the most blocks the list can ever hold (per level: every instance full)
+        int64_t bound = ctx->cfg.slot_capacity;
+        if (which >= desc_lvl(0)) bound = std::min<int64_t>(bound, ctx->lvl_bound[(which - desc_lvl(0)) / 3]);
+        w.grid = (int)std::min<int64_t>(bound, grid_cap);
+    } else {
+        const std::vector<int32_t> &d = ctx->lists.desc;
+        if (2 * which + 1 < (int)d.size()) {
+            w.off = d[2 * which];
+            w.n = d[2 * which + 1];
+        }
+        w.grid = w.n;
+    }
+    return w;
+}
+
+// Deepest level whose lists a launch sequence must cover.
+int levels_to_cover(const mrfv_ctx *ctx) {
+    return ctx->capturing ? ctx->lmax_all : ctx->lists.max_level;
+}
 
 template <typename T>
 int do_project(mrfv_ctx *ctx, T *U) {
-    const HostLists &L = ctx->lists;
-    for (int l = L.max_level - 1; l >= 0; --l)
-        HIP_OK(launch_project<T>(U, dlist(ctx, L.par_off[l]), L.par_cnt[l], ctx->tb, ctx->stream));
+    for (int l = levels_to_cover(ctx) - 1; l >= 0; --l)
+        HIP_OK(launch_project<T>(U, wlist(ctx, desc_par(l)), ctx->tb, ctx->stream));
     return MRFV_OK;
 }
 
 // leaf_faces = 1 inside a stage: leaves get only the face layers the flux reads.
 template <typename T>
 int do_fill(mrfv_ctx *ctx, T *U, int max_level, int leaf_faces = 0) {
-    const HostLists &L = ctx->lists;
-    for (int l = 0; l <= std::min(max_level, L.max_level); ++l)
-        HIP_OK(launch_fill_halos<T>(U, dlist(ctx, L.lvl_off[l]), L.lvl_cnt[l], ctx->tb, leaf_faces,
+    for (int l = 0; l <= std::min(max_level, levels_to_cover(ctx)); ++l)
+        HIP_OK(launch_fill_halos<T>(U, wlist(ctx, desc_lvl(l), 1024), ctx->tb, leaf_faces,
                                     ctx->stream));
     return MRFV_OK;
 }
@@ -134,24 +164,29 @@ void timing_end(mrfv_ctx *ctx, hipEvent_t a, int64_t cells) {
 template <typename T>
 int do_flux(mrfv_ctx *ctx, const T *U) {
     const HostLists &L = ctx->lists;
+    if (!ctx->d_D) {   // the fused batched path never needs it; allocate on first use
+        HIP_OK(hipStreamSynchronize(ctx->stream));
+        if (hipMalloc(&ctx->d_D, (size_t)ctx->cfg.slot_capacity * 3 * 5 * CELLS_I * sizeof(T)) !=
+            hipSuccess) {
+            ctx->d_D = nullptr;
+            return fail(ctx, MRFV_ENOMEM, "hipMalloc of the flux-difference scratch failed");
+        }
+    }
     T *D = (T *)ctx->d_D, *FF = (T *)ctx->d_FF;
     hipEvent_t ev{};
     timing_begin(ctx, &ev);
     if (ctx->cfg.batched) {
-        HIP_OK(launch_flux<T>(U, dlist(ctx, L.all_leaves_off), L.all_leaves_cnt, ctx->tb,
-                              ctx->d_inst, D, FF, ctx->stream));
+        HIP_OK(launch_flux<T>(U, wlist(ctx, DESC_LEAVES), ctx->tb, ctx->d_inst, D, FF, ctx->stream));
     } else {
         for (int l = 0; l <= L.max_level; ++l)
-            HIP_OK(launch_flux<T>(U, dlist(ctx, L.leaf_off[l]), L.leaf_cnt[l], ctx->tb, ctx->d_inst,
-                                  D, FF, ctx->stream));
+            HIP_OK(launch_flux<T>(U, wlist(ctx, desc_leaf(l)), ctx->tb, ctx->d_inst, D, FF,
+                                  ctx->stream));
     }
     timing_end(ctx, ev, (int64_t)L.all_leaves_cnt * CELLS_I);
     if (ctx->has_jumps) {
         for (int l = L.max_level - 1; l >= 0; --l)
-            HIP_OK(launch_ff_restrict<T>(FF, dlist(ctx, L.par_off[l]), L.par_cnt[l], ctx->tb,
-                                         ctx->stream));
-        HIP_OK(launch_reflux<T>(D, FF, dlist(ctx, L.all_leaves_off), L.all_leaves_cnt, ctx->tb,
-                                ctx->stream));
+            HIP_OK(launch_ff_restrict<T>(FF, wlist(ctx, desc_par(l)), ctx->tb, ctx->stream));
+        HIP_OK(launch_reflux<T>(D, FF, wlist(ctx, DESC_LEAVES), ctx->tb, ctx->stream));
     }
     return MRFV_OK;
 }
@@ -160,16 +195,16 @@ template <typename T>
 int do_rhs(mrfv_ctx *ctx, const T *U, T *Lout) {
     CALL(do_flux<T>(ctx, U));
     const HostLists &L = ctx->lists;
-    HIP_OK(launch_combine<T>((const T *)ctx->d_D, Lout, dlist(ctx, L.all_leaves_off),
-                             L.all_leaves_cnt, ctx->tb, ctx->d_inst, ctx->stream));
+    (void)L;
+    HIP_OK(launch_combine<T>((const T *)ctx->d_D, Lout, wlist(ctx, DESC_LEAVES), ctx->tb,
+                             ctx->d_inst, ctx->stream));
     return MRFV_OK;
 }
 
 template <typename T>
 int do_update(mrfv_ctx *ctx, int stage, const double *dt, T *U, T *U0, const T *Lb) {
-    const HostLists &L = ctx->lists;
-    HIP_OK(launch_update<T>(stage, dt, U, U0, Lb, dlist(ctx, L.all_leaves_off), L.all_leaves_cnt,
-                            ctx->tb, ctx->d_inst, ctx->d_err, ctx->stream));
+    HIP_OK(launch_update<T>(stage, dt, U, U0, Lb, wlist(ctx, DESC_LEAVES), ctx->tb, ctx->d_inst,
+                            ctx->d_err, ctx->stream));
     return MRFV_OK;
 }
 
@@ -180,26 +215,24 @@ int do_stage_fused(mrfv_ctx *ctx, int stage, const double *dt, float *U, float *
     float *FF = (float *)ctx->d_FF;
     hipEvent_t ev{};
     timing_begin(ctx, &ev);
-    HIP_OK(launch_rhs_update_f32(stage, dt, U, U0, dlist(ctx, L.all_leaves_off), L.all_leaves_cnt,
-                                 ctx->tb, ctx->d_inst, FF, ctx->d_err, ctx->stream));
+    // the fused kernel has no grid-stride loop: its grid must cover every possible leaf
+    HIP_OK(launch_rhs_update_f32(stage, dt, U, U0, wlist(ctx, DESC_LEAVES, 1 << 30), ctx->tb,
+                                 ctx->d_inst, FF, ctx->d_err, ctx->stream));
     timing_end(ctx, ev, (int64_t)L.all_leaves_cnt * CELLS_I);
-    if (ctx->has_jumps) {
-        for (int l = L.max_level - 1; l >= 0; --l)
-            HIP_OK(launch_ff_restrict<float>(FF, dlist(ctx, L.par_off[l]), L.par_cnt[l], ctx->tb,
-                                             ctx->stream));
-        HIP_OK(launch_reflux_update<float>(stage, dt, U, FF, dlist(ctx, L.all_leaves_off),
-                                           L.all_leaves_cnt, ctx->tb, ctx->d_inst, ctx->stream));
+    // a captured graph must not depend on the current tree: always include the correction
+    if (ctx->has_jumps || ctx->capturing) {
+        for (int l = levels_to_cover(ctx) - 1; l >= 0; --l)
+            HIP_OK(launch_ff_restrict<float>(FF, wlist(ctx, desc_par(l)), ctx->tb, ctx->stream));
+        HIP_OK(launch_reflux_update<float>(stage, dt, U, FF, wlist(ctx, DESC_LEAVES), ctx->tb,
+                                           ctx->d_inst, ctx->stream));
     }
     return MRFV_OK;
 }
 
 template <typename T>
 int do_details_flags(mrfv_ctx *ctx, const T *U, int8_t *flags, double *det) {
-    const HostLists &L = ctx->lists;
-    HIP_OK(launch_details<T>(U, dlist(ctx, L.fine_off), L.fine_cnt, ctx->tb, ctx->d_inst, det,
-                             ctx->stream));
-    HIP_OK(launch_flags(dlist(ctx, L.all_blocks_off), L.all_blocks_cnt, ctx->tb, ctx->d_inst, det,
-                        flags, ctx->stream));
+    HIP_OK(launch_details<T>(U, wlist(ctx, DESC_FINE), ctx->tb, ctx->d_inst, det, ctx->stream));
+    HIP_OK(launch_flags(wlist(ctx, DESC_ALL), ctx->tb, ctx->d_inst, det, flags, ctx->stream));
     return MRFV_OK;
 }
 
@@ -214,23 +247,106 @@ int do_predict(mrfv_ctx *ctx, T *U, const int32_t *slots_host, int n) {
 }
 
 int commit(mrfv_ctx *ctx, const int8_t *flags, std::vector<int32_t> &fresh) {
-    std::vector<int> order = ctx->topo.alive_sorted();
-    std::vector<int> coarsen, refine;
-    for (int s : order) {
-        const HostBlock &b = ctx->topo.block(s);
-        if (!b.leaf) continue;
-        if (flags[s] == 1) refine.push_back(s);
-        if (flags[s] == -1 && (b.bx & 1) == 0 && (b.by & 1) == 0 && (b.bz & 1) == 0)
-            coarsen.push_back(b.parent);
-    }
-    for (int p : coarsen) ctx->topo.coarsen(p);
     std::vector<int> created;
-    for (int s : refine) {
-        created.clear();
-        if (!ctx->topo.refine(s, &created)) return fail(ctx, MRFV_ENOMEM, "slot capacity exhausted");
-        fresh.insert(fresh.end(), created.begin(), created.end());
-    }
+    if (!ctx->topo.commit(flags, nullptr, &created))
+        return fail(ctx, MRFV_ENOMEM, "slot capacity exhausted");
+    fresh.insert(fresh.end(), created.begin(), created.end());
     return upload_tables(ctx);
+}
+
+// Turn per-leaf class scores into a committable proposal: refine only below l_max,
+// coarsen only whole sibling groups of leaves on levels >= 2, nothing for non-adaptive
+// instances.  mode 2 (persistence) proposes no change at all.
+void decode_proposal(mrfv_ctx *ctx, const std::vector<int32_t> &leaves) {
+    std::vector<int8_t> &P = ctx->proposal;
+    P.assign(ctx->cfg.slot_capacity, 0);
+    if (ctx->prop_mode != 1) return;
+    const Topology &tp = ctx->topo;
+    for (size_t r = 0; r < leaves.size(); ++r) {
+        const float *z = ctx->h_logits + 3 * r;
+        const int cls = (z[0] > z[1] && z[0] >= z[2]) ? 0 : (z[2] > z[1] ? 2 : 1);
+        P[leaves[r]] = cls == 0 ? 1 : (cls == 2 ? -1 : 0);
+    }
+    for (int32_t s : leaves) {
+        const HostBlock &b = tp.block(s);
+        const mrfv_instance &I = ctx->inst[b.inst];
+        if (!I.adapt) { P[s] = 0; continue; }
+        if (P[s] == 1 && b.level >= I.lmax) P[s] = 0;
+        if (P[s] == -1) {
+            bool ok = b.level >= 2;
+            if (ok) {
+                const HostBlock &par = tp.block(b.parent);
+                for (int o = 0; o < 8 && ok; ++o) {
+                    const HostBlock &c = tp.block(par.child[o]);
+                    ok = c.leaf && P[par.child[o]] == -1;
+                }
+            }
+            if (!ok) P[s] = 0;
+        }
+    }
+    // a group that lost a member above must drop the coarsen for every member
+    for (int32_t s : leaves) {
+        if (P[s] != -1) continue;
+        const HostBlock &par = tp.block(tp.block(s).parent);
+        for (int o = 0; o < 8; ++o)
+            if (P[par.child[o]] != -1) { P[s] = 0; break; }
+    }
+}
+
+// Commit the proposal on the host tree, build and stage its device tables on the side
+// stream, then undo the commit.  Runs while the device computes the step.
+int stage_proposal(mrfv_ctx *ctx) {
+    HIP_OK(hipStreamSynchronize(ctx->side));   // last step's uploads still read s_*
+    std::vector<TreeOp> ops;
+    if (!ctx->topo.commit(ctx->proposal.data(), &ops, nullptr)) {
+        ctx->topo.undo(ops);
+        ctx->staged = false;
+        return MRFV_OK;   // would not fit: no staging, the normal path handles the step
+    }
+    ctx->topo.build(ctx->s_meta, ctx->s_child, ctx->s_nbr, ctx->lists2);
+    ctx->staged_jumps = any_jump(ctx->topo, ctx->lists2, ctx->s_nbr);
+    ctx->topo.undo(ops);
+    if ((int)ctx->lists2.data.size() > ctx->lists_cap) {
+        ctx->staged = false;
+        return MRFV_OK;
+    }
+    hipStream_t st = ctx->side;
+    HIP_OK(hipMemcpyAsync(ctx->tb2.meta, ctx->s_meta.data(), ctx->s_meta.size() * sizeof(BlockMeta),
+                          hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(ctx->tb2.child, ctx->s_child.data(), ctx->s_child.size() * sizeof(int32_t),
+                          hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(ctx->tb2.nbr, ctx->s_nbr.data(), ctx->s_nbr.size() * sizeof(int32_t),
+                          hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(ctx->tb2.lists, ctx->lists2.data.data(), ctx->lists2.data.size() * sizeof(int32_t),
+                          hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(ctx->d_desc2, ctx->lists2.desc.data(), ctx->lists2.desc.size() * sizeof(int32_t),
+                          hipMemcpyHostToDevice, st));
+    ctx->staged = true;
+    return MRFV_OK;
+}
+
+// Adopt the staged tables after the judge confirmed the proposal: redo the same commit
+// (the free list is in the same state, so the slots are the same) and copy the staged
+// device tables over the live ones.
+int adopt_staged(mrfv_ctx *ctx, std::vector<int32_t> &fresh) {
+    std::vector<int> created;
+    if (!ctx->topo.commit(ctx->proposal.data(), nullptr, &created))
+        return fail(ctx, MRFV_ENOMEM, "slot capacity exhausted");
+    fresh.insert(fresh.end(), created.begin(), created.end());
+    HIP_OK(hipStreamSynchronize(ctx->side));
+    hipStream_t st = ctx->stream;
+    HIP_OK(hipMemcpyAsync(ctx->tb.meta, ctx->tb2.meta, ctx->s_meta.size() * sizeof(BlockMeta),
+                          hipMemcpyDeviceToDevice, st));
+    HIP_OK(hipMemcpyAsync(ctx->tb.child, ctx->tb2.child, ctx->s_child.size() * sizeof(int32_t),
+                          hipMemcpyDeviceToDevice, st));
+    HIP_OK(hipMemcpyAsync(ctx->tb.nbr, ctx->tb2.nbr, ctx->s_nbr.size() * sizeof(int32_t),
+                          hipMemcpyDeviceToDevice, st));
+    HIP_OK(hipMemcpyAsync(ctx->tb.lists, ctx->tb2.lists, ctx->lists2.data.size() * sizeof(int32_t),
+                          hipMemcpyDeviceToDevice, st));
+    HIP_OK(hipMemcpyAsync(ctx->d_desc, ctx->d_desc2, 2 * N_DESC * sizeof(int32_t), hipMemcpyDeviceToDevice, st));
+    ctx->lists = ctx->lists2;
+    ctx->has_jumps = ctx->staged_jumps;
+    return MRFV_OK;
 }
 
 template <typename T>
@@ -288,8 +404,11 @@ int do_init(mrfv_ctx *ctx, mrfv_ic_fn ic, void *user, T *U) {
             CALL(do_fill<T>(ctx, U, m));
             HIP_OK(hipMemcpyAsync(ctx->d_slots, fresh.data(), sizeof(int32_t) * fresh.size(),
                                   hipMemcpyHostToDevice, ctx->stream));
-            HIP_OK(launch_details<T>(U, ctx->d_slots, (int)fresh.size(), ctx->tb, ctx->d_inst,
-                                     ctx->d_det, ctx->stream));
+            WorkList wf;
+            wf.base = ctx->d_slots;
+            wf.n = (int32_t)fresh.size();
+            wf.grid = wf.n;
+            HIP_OK(launch_details<T>(U, wf, ctx->tb, ctx->d_inst, ctx->d_det, ctx->stream));
             HIP_OK(hipMemcpyAsync(det.data(), ctx->d_det, sizeof(double) * det.size(),
                                   hipMemcpyDeviceToHost, ctx->stream));
             HIP_OK(hipStreamSynchronize(ctx->stream));
@@ -311,11 +430,11 @@ int do_init(mrfv_ctx *ctx, mrfv_ic_fn ic, void *user, T *U) {
     return MRFV_OK;
 }
 
+// CFL step and the three RK stages.
 template <typename T>
-int do_step(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt) {
-    const HostLists &L0 = ctx->lists;
-    HIP_OK(launch_cfl<T>(U, dlist(ctx, L0.all_leaves_off), L0.all_leaves_cnt, ctx->tb, ctx->d_inst,
-                         (int)ctx->inst.size(), ctx->d_blockred, dt, ctx->stream));
+int do_stages(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt) {
+    HIP_OK(launch_cfl<T>(U, wlist(ctx, DESC_LEAVES), ctx->tb, ctx->d_inst, (int)ctx->inst.size(),
+                         ctx->d_blockred, dt, ctx->stream));
     for (int s = 0; s < 3; ++s) {
         CALL(do_project<T>(ctx, U));
         CALL(do_fill<T>(ctx, U, 1 << 20, 1));
@@ -326,21 +445,109 @@ int do_step(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt) {
             CALL(do_update<T>(ctx, s, dt, U, U0, Lb));
         }
     }
+    return MRFV_OK;
+}
+
+// hipGraph of the CFL step and the three RK stages (batched FP32 path, batched == 2): the
+// kernels read their work lists through the device descriptors, so one capture serves
+// every later tree.  Captured on the library's own stream, launched on the caller's.
+int run_stage_graph(mrfv_ctx *ctx, float *U, float *U0, double *dt) {
+    if (!ctx->graph || ctx->gU != U || ctx->gU0 != U0 || ctx->gdt != dt) {
+        if (ctx->graph) {
+            HIP_OK(hipGraphExecDestroy(ctx->graph));
+            ctx->graph = nullptr;
+        }
+        if (!ctx->gstream) HIP_OK(hipStreamCreateWithFlags(&ctx->gstream, hipStreamNonBlocking));
+        HIP_OK(hipStreamSynchronize(ctx->stream));
+        hipStream_t user = ctx->stream;
+        ctx->stream = ctx->gstream;
+        ctx->capturing = true;
+        hipError_t e = hipStreamBeginCapture(ctx->gstream, hipStreamCaptureModeThreadLocal);
+        int rc = e == hipSuccess ? do_stages<float>(ctx, U, U0, nullptr, dt) : MRFV_EHIP;
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(ctx->gstream, &g);
+        ctx->capturing = false;
+        ctx->stream = user;
+        if (e != hipSuccess || e2 != hipSuccess || rc != MRFV_OK || !g)
+            return fail(ctx, MRFV_EHIP, "stage graph capture failed");
+        hipError_t e3 = hipGraphInstantiate(&ctx->graph, g, nullptr, nullptr, 0);
+        hipGraphDestroy(g);
+        if (e3 != hipSuccess) {
+            ctx->graph = nullptr;
+            return fail(ctx, MRFV_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e3));
+        }
+        ctx->gU = U;
+        ctx->gU0 = U0;
+        ctx->gdt = dt;
+    }
+    HIP_OK(hipGraphLaunch(ctx->graph, ctx->stream));
+    return MRFV_OK;
+}
+
+template <typename T>
+int do_step(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt) {
     bool adapt = false;
     for (const auto &p : ctx->inst) adapt = adapt || (p.adapt && p.lmax > 0);
+    const bool prop = adapt && ctx->prop_mode != 0;
+    std::vector<int32_t> leaves;
+    if (prop) {
+        const HostLists &L = ctx->lists;
+        leaves.assign(L.data.begin() + L.all_leaves_off,
+                      L.data.begin() + L.all_leaves_off + L.all_leaves_cnt);
+    }
+    if (prop && ctx->prop_mode == 1 && !leaves.empty()) {
+        // proposal for this step's judge from the state at its start; it is queued
+        // ahead of the stages, so the host can read it while the device continues
+        HIP_OK(launch_features<T>(U, wlist(ctx, DESC_LEAVES), ctx->tb, ctx->d_inst, ctx->d_X,
+                                  ctx->stream));
+        CALL(mlp_forward_on(ctx->mlp, ctx->stream, ctx->d_X, (int)leaves.size(), ctx->d_logits));
+        HIP_OK(hipMemcpyAsync(ctx->h_logits, ctx->d_logits, leaves.size() * 3 * sizeof(float),
+                              hipMemcpyDeviceToHost, ctx->stream));
+        HIP_OK(hipEventRecord(ctx->ev_prop, ctx->stream));
+    }
+    if (ctx->cfg.batched == 2 && sizeof(T) == 4 && !ctx->timing) {
+        CALL(run_stage_graph(ctx, (float *)U, (float *)U0, dt));
+    } else {
+        CALL(do_stages<T>(ctx, U, U0, Lb, dt));
+    }
     if (!adapt) return MRFV_OK;
     CALL(do_project<T>(ctx, U));
     CALL(do_fill<T>(ctx, U, 1 << 20));
     CALL(do_details_flags<T>(ctx, U, ctx->d_flags, ctx->d_det));
-    std::vector<int8_t> flags(ctx->cfg.slot_capacity);
-    int32_t errw = 0;
-    HIP_OK(hipMemcpyAsync(flags.data(), ctx->d_flags, flags.size(), hipMemcpyDeviceToHost,
-                          ctx->stream));
-    HIP_OK(hipMemcpyAsync(&errw, ctx->d_err, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+    const int cap = ctx->cfg.slot_capacity;
+    HIP_OK(hipMemcpyAsync(ctx->h_flags, ctx->d_flags, cap, hipMemcpyDeviceToHost, ctx->stream));
+    HIP_OK(hipMemcpyAsync(ctx->h_err, ctx->d_err, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+    if (prop) {
+        // host-side tree work for the proposed flags, overlapped with the device
+        if (ctx->prop_mode == 1 && !leaves.empty()) HIP_OK(hipEventSynchronize(ctx->ev_prop));
+        const auto t0 = std::chrono::steady_clock::now();
+        decode_proposal(ctx, leaves);
+        CALL(stage_proposal(ctx));
+        ctx->p_build_ms +=
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
     HIP_OK(hipStreamSynchronize(ctx->stream));
-    if (errw) return fail(ctx, MRFV_ENONPHYS, "non-physical state (rho<=0, p+B<=0 or NaN)");
+    if (*ctx->h_err) return fail(ctx, MRFV_ENONPHYS, "non-physical state (rho<=0, p+B<=0 or NaN)");
     std::vector<int32_t> fresh;
-    CALL(commit(ctx, flags.data(), fresh));
+    if (prop) {
+        bool hit = true;
+        for (int32_t s : leaves) {
+            const int j = ctx->h_flags[s], q = ctx->proposal[s];
+            const int cj = j == 1 ? 0 : (j == -1 ? 2 : 1), cq = q == 1 ? 0 : (q == -1 ? 2 : 1);
+            if (j != q) hit = false;
+            if (cj == cq) ctx->p_tp[cj]++;
+            else { ctx->p_fn[cj]++; ctx->p_fp[cq]++; }
+        }
+        ctx->p_steps++;
+        if (hit && ctx->staged) {
+            ctx->p_hits++;
+            CALL(adopt_staged(ctx, fresh));
+        } else {
+            CALL(commit(ctx, ctx->h_flags, fresh));
+        }
+    } else {
+        CALL(commit(ctx, ctx->h_flags, fresh));
+    }
     CALL(do_predict<T>(ctx, U, fresh.data(), (int)fresh.size()));
     return MRFV_OK;
 }
@@ -376,6 +583,13 @@ int mrfv_create(mrfv_ctx **out, const mrfv_config *cfg, const mrfv_instance *ins
     const size_t cap = cfg->slot_capacity, es = elem_size(ctx);
     ctx->lists_cap = 2 * cfg->n_instances + 6 * cfg->slot_capacity + 16;
     ctx->prim_batch = 128;
+    for (int i = 0; i < cfg->n_instances; ++i) ctx->lmax_all = std::max(ctx->lmax_all, (int)inst[i].lmax);
+    ctx->lvl_bound.assign(MAX_LEVELS, 0);
+    for (int i = 0; i < cfg->n_instances; ++i) {
+        int64_t n = (int64_t)inst[i].n0[0] * inst[i].n0[1] * inst[i].n0[2];
+        for (int l = 0; l <= inst[i].lmax && l < MAX_LEVELS; ++l, n *= 8) ctx->lvl_bound[l] += n;
+    }
+    if (cfg->batched < 0 || cfg->batched > 2) return bail(MRFV_EINVAL);
     std::vector<InstDev> id(cfg->n_instances);
     for (int i = 0; i < cfg->n_instances; ++i) {
         const mrfv_instance &p = inst[i];
@@ -389,7 +603,15 @@ int mrfv_create(mrfv_ctx **out, const mrfv_config *cfg, const mrfv_instance *ins
     }
     ALLOC(ctx->d_inst, sizeof(InstDev) * id.size());
     ALLOC(ctx->d_err, sizeof(int32_t));
-    ALLOC(ctx->d_D, cap * 3 * 5 * CELLS_I * es);
+    if (!(cfg->batched && cfg->dtype == MRFV_F32)) ALLOC(ctx->d_D, cap * 3 * 5 * CELLS_I * es);
+    ALLOC(ctx->d_desc, 2 * N_DESC * sizeof(int32_t));
+    if (hipHostMalloc((void **)&ctx->h_flags, cap, 0) != hipSuccess ||
+        hipHostMalloc((void **)&ctx->h_err, sizeof(int32_t), 0) != hipSuccess) {
+        ctx->err = "hipHostMalloc failed";
+        return bail(MRFV_ENOMEM);
+    }
+    std::fill(ctx->h_flags, ctx->h_flags + cap, (int8_t)0);
+    *ctx->h_err = 0;
     ALLOC(ctx->d_FF, cap * 6 * 5 * FACE * es);
     ALLOC(ctx->d_blockred, cap * 5 * sizeof(double));
     ALLOC(ctx->d_det, cap * sizeof(double));
@@ -415,9 +637,25 @@ int mrfv_destroy(mrfv_ctx *ctx) {
     if (!ctx) return MRFV_EINVAL;
     if (ctx->stream) hipStreamSynchronize(ctx->stream);
     else hipDeviceSynchronize();
+    if (ctx->graph) hipGraphExecDestroy(ctx->graph);
+    if (ctx->gstream) hipStreamDestroy(ctx->gstream);
+    if (ctx->side) {
+        hipStreamSynchronize(ctx->side);
+        hipStreamDestroy(ctx->side);
+    }
+    if (ctx->ev_prop) hipEventDestroy(ctx->ev_prop);
+    if (ctx->h_flags) hipHostFree(ctx->h_flags);
+    if (ctx->h_err) hipHostFree(ctx->h_err);
+    if (ctx->h_logits) hipHostFree(ctx->h_logits);
+    {
+        void *pp[] = {ctx->d_X, ctx->d_logits, ctx->tb2.meta, ctx->tb2.child, ctx->tb2.nbr,
+                      ctx->tb2.lists, ctx->d_desc2};
+        for (void *p : pp)
+            if (p) hipFree(p);
+    }
     void *ptrs[] = {ctx->d_inst, ctx->d_err, ctx->d_D, ctx->d_FF, ctx->d_blockred, ctx->d_det,
                     ctx->d_flags, ctx->d_slots, ctx->d_prim, ctx->tb.meta, ctx->tb.child,
-                    ctx->tb.nbr, ctx->tb.lists};
+                    ctx->tb.nbr, ctx->tb.lists, ctx->d_desc};
     for (void *p : ptrs)
         if (p) hipFree(p);
     for (hipEvent_t e : ctx->ev_free) hipEventDestroy(e);
@@ -499,30 +737,24 @@ int mrfv_mr_flag(mrfv_ctx *ctx, const void *U, int8_t *flags_dev, double *det_de
 int mrfv_cfl_dt(mrfv_ctx *ctx, const void *U, double *dt_dev) {
     CALL(need_init(ctx));
     if (!U || !dt_dev) return fail(ctx, MRFV_EINVAL, "cfl_dt: null pointer");
-    const HostLists &L = ctx->lists;
     if (ctx->cfg.dtype == MRFV_F64)
-        HIP_OK(launch_cfl<double>((const double *)U, dlist(ctx, L.all_leaves_off), L.all_leaves_cnt,
-                                  ctx->tb, ctx->d_inst, (int)ctx->inst.size(), ctx->d_blockred,
-                                  dt_dev, ctx->stream));
+        HIP_OK(launch_cfl<double>((const double *)U, wlist(ctx, DESC_LEAVES), ctx->tb, ctx->d_inst,
+                                  (int)ctx->inst.size(), ctx->d_blockred, dt_dev, ctx->stream));
     else
-        HIP_OK(launch_cfl<float>((const float *)U, dlist(ctx, L.all_leaves_off), L.all_leaves_cnt,
-                                 ctx->tb, ctx->d_inst, (int)ctx->inst.size(), ctx->d_blockred,
-                                 dt_dev, ctx->stream));
+        HIP_OK(launch_cfl<float>((const float *)U, wlist(ctx, DESC_LEAVES), ctx->tb, ctx->d_inst,
+                                 (int)ctx->inst.size(), ctx->d_blockred, dt_dev, ctx->stream));
     return MRFV_OK;
 }
 
 int mrfv_totals(mrfv_ctx *ctx, const void *U, double *tot_dev) {
     CALL(need_init(ctx));
     if (!U || !tot_dev) return fail(ctx, MRFV_EINVAL, "totals: null pointer");
-    const HostLists &L = ctx->lists;
     if (ctx->cfg.dtype == MRFV_F64)
-        HIP_OK(launch_totals<double>((const double *)U, dlist(ctx, L.all_leaves_off),
-                                     L.all_leaves_cnt, ctx->tb, ctx->d_inst, (int)ctx->inst.size(),
-                                     ctx->d_blockred, tot_dev, ctx->stream));
+        HIP_OK(launch_totals<double>((const double *)U, wlist(ctx, DESC_LEAVES), ctx->tb, ctx->d_inst,
+                                     (int)ctx->inst.size(), ctx->d_blockred, tot_dev, ctx->stream));
     else
-        HIP_OK(launch_totals<float>((const float *)U, dlist(ctx, L.all_leaves_off),
-                                    L.all_leaves_cnt, ctx->tb, ctx->d_inst, (int)ctx->inst.size(),
-                                    ctx->d_blockred, tot_dev, ctx->stream));
+        HIP_OK(launch_totals<float>((const float *)U, wlist(ctx, DESC_LEAVES), ctx->tb, ctx->d_inst,
+                                    (int)ctx->inst.size(), ctx->d_blockred, tot_dev, ctx->stream));
     return MRFV_OK;
 }
 
@@ -617,6 +849,68 @@ int mrfv_coarsen_block(mrfv_ctx *ctx, int32_t inst, int32_t level, int32_t bx, i
             return fail(ctx, MRFV_EINVAL, "coarsen_block: children are not all leaves");
     ctx->topo.coarsen(s);
     return upload_tables(ctx);
+}
+
+int mrfv_features(mrfv_ctx *ctx, const void *U, float *X_dev, int32_t *slots_host, int32_t *n) {
+    CALL(need_init(ctx));
+    if (!U || !X_dev || !n) return fail(ctx, MRFV_EINVAL, "features: null pointer");
+    const HostLists &L = ctx->lists;
+    *n = L.all_leaves_cnt;
+    if (slots_host)
+        std::copy(L.data.begin() + L.all_leaves_off, L.data.begin() + L.all_leaves_off + L.all_leaves_cnt,
+                  slots_host);
+    if (ctx->cfg.dtype == MRFV_F64)
+        HIP_OK(launch_features<double>((const double *)U, wlist(ctx, DESC_LEAVES), ctx->tb, ctx->d_inst,
+                                       X_dev, ctx->stream));
+    else
+        HIP_OK(launch_features<float>((const float *)U, wlist(ctx, DESC_LEAVES), ctx->tb, ctx->d_inst,
+                                      X_dev, ctx->stream));
+    return MRFV_OK;
+}
+
+int mrfv_set_proposer(mrfv_ctx *ctx, mrfv_mlp *mlp, int32_t mode) {
+    if (!ctx) return MRFV_EINVAL;
+    if (mode < 0 || mode > 2 || (mode == 1 && !mlp))
+        return fail(ctx, MRFV_EINVAL, "set_proposer: mode 0 (off), 1 (network) or 2 (persistence)");
+    const size_t cap = ctx->cfg.slot_capacity;
+    if (mode != 0 && !ctx->tb2.meta) {
+        auto al = [&](void **p, size_t bytes) { return hipMalloc(p, bytes) == hipSuccess; };
+        if (!al((void **)&ctx->tb2.meta, cap * sizeof(BlockMeta)) ||
+            !al((void **)&ctx->tb2.child, cap * 8 * sizeof(int32_t)) ||
+            !al((void **)&ctx->tb2.nbr, cap * 27 * sizeof(int32_t)) ||
+            !al((void **)&ctx->tb2.lists, (size_t)ctx->lists_cap * sizeof(int32_t)) ||
+            !al((void **)&ctx->d_desc2, 2 * N_DESC * sizeof(int32_t)) ||
+            !al((void **)&ctx->d_X, cap * 192 * sizeof(float)) ||
+            !al((void **)&ctx->d_logits, cap * 3 * sizeof(float)))
+            return fail(ctx, MRFV_ENOMEM, "set_proposer: device memory");
+        if (hipHostMalloc((void **)&ctx->h_logits, cap * 3 * sizeof(float), 0) != hipSuccess)
+            return fail(ctx, MRFV_ENOMEM, "set_proposer: pinned memory");
+        HIP_OK(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+        HIP_OK(hipEventCreateWithFlags(&ctx->ev_prop, hipEventDisableTiming));
+    }
+    ctx->mlp = mlp;
+    ctx->prop_mode = mode;
+    return MRFV_OK;
+}
+
+int mrfv_last_flags(mrfv_ctx *ctx, int8_t *flags_host) {
+    if (!ctx || !flags_host) return MRFV_EINVAL;
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    std::copy(ctx->h_flags, ctx->h_flags + ctx->cfg.slot_capacity, flags_host);
+    return MRFV_OK;
+}
+
+int mrfv_proposer_stats(mrfv_ctx *ctx, int64_t *out, double *build_ms) {
+    if (!ctx || !out) return MRFV_EINVAL;
+    out[0] = ctx->p_steps;
+    out[1] = ctx->p_hits;
+    for (int c = 0; c < 3; ++c) {
+        out[2 + 3 * c] = ctx->p_tp[c];
+        out[3 + 3 * c] = ctx->p_fp[c];
+        out[4 + 3 * c] = ctx->p_fn[c];
+    }
+    if (build_ms) *build_ms = ctx->p_build_ms;
+    return MRFV_OK;
 }
 
 int mrfv_enable_kernel_timing(mrfv_ctx *ctx, int32_t on) {

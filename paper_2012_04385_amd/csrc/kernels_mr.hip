@@ -89,31 +89,30 @@ __global__ __launch_bounds__(TPB) void k_prim2cons(const double *__restrict__ pr
 // and corner regions and the outermost layer are skipped (nothing reads them during a
 // stage: prediction reads parents, copies read interiors).
 template <typename T>
-__global__ __launch_bounds__(TPB) void k_fill_halos(T *__restrict__ U,
-                                                    const int32_t *__restrict__ list, int n,
+__global__ __launch_bounds__(TPB) void k_fill_halos(T *__restrict__ U, WorkList wl,
                                                     const BlockMeta *__restrict__ meta,
                                                     const int32_t *__restrict__ nbr,
                                                     int leaf_faces) {
-    const int b = blockIdx.x;
-    if (b >= n) return;
     const int cell = blockIdx.y * TPB + threadIdx.x;
     if (cell >= CELLS_P) return;
-    const int slot = list[b];
-    int c[3] = {cell % NP, (cell / NP) % NP, cell / (NP * NP)};
-    const bool interior = c[0] >= HW && c[0] < HW + NI && c[1] >= HW && c[1] < HW + NI &&
-                          c[2] >= HW && c[2] < HW + NI;
+    const int c0[3] = {cell % NP, (cell / NP) % NP, cell / (NP * NP)};
+    const bool interior = c0[0] >= HW && c0[0] < HW + NI && c0[1] >= HW && c0[1] < HW + NI &&
+                          c0[2] >= HW && c0[2] < HW + NI;
     if (interior) return;
-    const BlockMeta m = meta[slot];
-    if (leaf_faces && m.leaf) {
-        int nout = 0;
-        bool outer = false;
+    int nout = 0;
+    bool outer = false;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            nout += (c[a] < HW || c[a] >= HW + NI) ? 1 : 0;
-            outer = outer || c[a] == 0 || c[a] == NP - 1;
-        }
-        if (nout > 1 || outer) return;
+    for (int a = 0; a < 3; ++a) {
+        nout += (c0[a] < HW || c0[a] >= HW + NI) ? 1 : 0;
+        outer = outer || c0[a] == 0 || c0[a] == NP - 1;
     }
+    const bool face_cell = nout == 1 && !outer;
+    const int nb = wl.count();
+    for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+    const int slot = wl.at(b);
+    const BlockMeta m = meta[slot];
+    if (leaf_faces && m.leaf && !face_cell) continue;
+    int c[3] = {c0[0], c0[1], c0[2]};
     int r[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -131,24 +130,23 @@ __global__ __launch_bounds__(TPB) void k_fill_halos(T *__restrict__ U,
         const int so = pidx(0, c[2] - NI * r[2], c[1] - NI * r[1], c[0] - NI * r[0]);
 #pragma unroll
         for (int q = 0; q < 5; ++q) dst[o + q * CELLS_P] = s[so + q * CELLS_P];
-    } else {
-        if (m.parent < 0) return;   // cannot happen: level 0 is complete
+    } else if (m.parent >= 0) {   // always true: level 0 is complete
         const T *pu = U + (size_t)m.parent * 5 * CELLS_P;
 #pragma unroll 1
         for (int q = 0; q < 5; ++q)
             dst[o + q * CELLS_P] = predict_cell<T, T>(pu + q * CELLS_P, m.bx & 1, m.by & 1,
                                                       m.bz & 1, c[0], c[1], c[2]);
     }
+    }
 }
 
 // One thread per parent interior cell.
 template <typename T>
-__global__ __launch_bounds__(TPB) void k_project(T *__restrict__ U,
-                                                 const int32_t *__restrict__ list, int n,
+__global__ __launch_bounds__(TPB) void k_project(T *__restrict__ U, WorkList wl,
                                                  const int32_t *__restrict__ child) {
-    const int b = blockIdx.x;
-    if (b >= n) return;
-    const int slot = list[b];
+    const int nb = wl.count();
+    for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+    const int slot = wl.at(b);
     const int K = blockIdx.y, J = threadIdx.x >> 4, I = threadIdx.x & 15;
     const int oct = ((K >> 3) << 2) | ((J >> 3) << 1) | (I >> 3);
     const int cs = child[(size_t)slot * 8 + oct];
@@ -162,6 +160,7 @@ __global__ __launch_bounds__(TPB) void k_project(T *__restrict__ U,
         const double s = (((double)c0[0] + (double)c0[1]) + ((double)c0[NP] + (double)c0[NP + 1])) +
                          (((double)c1[0] + (double)c1[1]) + ((double)c1[NP] + (double)c1[NP + 1]));
         pu[pidx(q, HW + K, HW + J, HW + I)] = (T)(s * 0.125);
+    }
     }
 }
 
@@ -188,8 +187,7 @@ __global__ __launch_bounds__(TPB) void k_predict(T *__restrict__ U,
 // (16x24x24) and z (24^3) evaluate each 1D step once per output instead of 31 times per
 // child cell.  The operation order per child cell equals predict_cell's.
 template <typename T>
-__global__ __launch_bounds__(TPB) void k_details(const T *__restrict__ U,
-                                                 const int32_t *__restrict__ list, int n,
+__global__ __launch_bounds__(TPB) void k_details(const T *__restrict__ U, WorkList wl,
                                                  const BlockMeta *__restrict__ meta,
                                                  const InstDev *__restrict__ inst,
                                                  double *__restrict__ det) {
@@ -197,9 +195,9 @@ __global__ __launch_bounds__(TPB) void k_details(const T *__restrict__ U,
     __shared__ double A[R * NP * NP];   // parent region, later the y-pass (72 KB)
     __shared__ double Bx[R * R * NP];   // x-pass (48 KB)
     __shared__ double red[TPB];
-    const int b = blockIdx.x;
-    if (b >= n) return;
-    const int slot = list[b];
+    const int nb = wl.count();
+    for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+    const int slot = wl.at(b);
     const BlockMeta m = meta[slot];
     const InstDev P = inst[m.inst];
     const int ox = m.bx & 1, oy = m.by & 1, oz = m.bz & 1;
@@ -247,23 +245,25 @@ __global__ __launch_bounds__(TPB) void k_details(const T *__restrict__ U,
         __syncthreads();
     }
     if (threadIdx.x == 0) det[slot] = red[0];
+    __syncthreads();
+    }
 }
 
 __device__ __forceinline__ double eps_level(const InstDev &P, int l) {
     return ldexp(P.eps, -3 * (P.lmax - l));
 }
 
-__global__ __launch_bounds__(TPB) void k_flags(const int32_t *__restrict__ list, int n,
+__global__ __launch_bounds__(TPB) void k_flags(WorkList wl,
                                                const BlockMeta *__restrict__ meta,
                                                const int32_t *__restrict__ child,
                                                const InstDev *__restrict__ inst,
                                                const double *__restrict__ det,
                                                int8_t *__restrict__ flags) {
-    const int t = blockIdx.x * TPB + threadIdx.x;
-    if (t >= n) return;
-    const int slot = list[t];
+    const int nb = wl.count();
+    for (int t = blockIdx.x * TPB + threadIdx.x; t < nb; t += gridDim.x * TPB) {
+    const int slot = wl.at(t);
     const BlockMeta m = meta[slot];
-    if (!m.leaf) { flags[slot] = 2; return; }
+    if (!m.leaf) { flags[slot] = 2; continue; }
     const InstDev P = inst[m.inst];
     const int l = m.level;
     const double d = l >= 1 ? det[slot] : -1.0;
@@ -282,19 +282,19 @@ __global__ __launch_bounds__(TPB) void k_flags(const int32_t *__restrict__ list,
         if (small && det[m.parent] < eps_level(P, l - 1)) f = -1;
     }
     flags[slot] = f;
+    }
 }
 
 // Per-block maxima of |v_d| + c over the interior, FP64.
 template <typename T>
-__global__ __launch_bounds__(TPB) void k_cfl_block(const T *__restrict__ U,
-                                                   const int32_t *__restrict__ list, int n,
+__global__ __launch_bounds__(TPB) void k_cfl_block(const T *__restrict__ U, WorkList wl,
                                                    const BlockMeta *__restrict__ meta,
                                                    const InstDev *__restrict__ inst,
                                                    double *__restrict__ bmax) {
     __shared__ double red[3][TPB];
-    const int b = blockIdx.x;
-    if (b >= n) return;
-    const int slot = list[b];
+    const int nb = wl.count();
+    for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+    const int slot = wl.at(b);
     const InstDev P = inst[meta[slot].inst];
     const T *u = U + (size_t)slot * 5 * CELLS_P;
     double mx[3] = {0.0, 0.0, 0.0};
@@ -319,6 +319,8 @@ __global__ __launch_bounds__(TPB) void k_cfl_block(const T *__restrict__ U,
         __syncthreads();
     }
     if (threadIdx.x < 3) bmax[(size_t)slot * 5 + threadIdx.x] = red[threadIdx.x][0];
+    __syncthreads();
+    }
 }
 
 // One workgroup per instance over that instance's contiguous range of the leaf list.
@@ -352,13 +354,12 @@ __global__ __launch_bounds__(TPB) void k_cfl_inst(const int32_t *__restrict__ li
 
 // Per-block FP64 sums of the 5 conserved quantities over the interior (fixed tree).
 template <typename T>
-__global__ __launch_bounds__(TPB) void k_sum_block(const T *__restrict__ U,
-                                                   const int32_t *__restrict__ list, int n,
+__global__ __launch_bounds__(TPB) void k_sum_block(const T *__restrict__ U, WorkList wl,
                                                    double *__restrict__ bsum) {
     __shared__ double red[TPB];
-    const int b = blockIdx.x;
-    if (b >= n) return;
-    const int slot = list[b];
+    const int nb = wl.count();
+    for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+    const int slot = wl.at(b);
     const T *u = U + (size_t)slot * 5 * CELLS_P;
     for (int q = 0; q < 5; ++q) {
         double s = 0.0;
@@ -372,6 +373,7 @@ __global__ __launch_bounds__(TPB) void k_sum_block(const T *__restrict__ U,
         }
         if (threadIdx.x == 0) bsum[(size_t)slot * 5 + q] = red[0];
         __syncthreads();
+    }
     }
 }
 
@@ -416,19 +418,18 @@ hipError_t launch_prim2cons(const double *prim, const int32_t *slots, int n, T *
 }
 
 template <typename T>
-hipError_t launch_fill_halos(T *U, const int32_t *list, int n, const DevTables &tb,
-                             int leaf_faces, hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fill_halos<T>, grid2(n, (CELLS_P + TPB - 1) / TPB), dim3(TPB), 0, st,
-                       U, list, n, tb.meta, tb.nbr, leaf_faces);
+hipError_t launch_fill_halos(T *U, const WorkList &wl, const DevTables &tb, int leaf_faces,
+                             hipStream_t st) {
+    if (wl.grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_halos<T>, grid2(wl.grid, (CELLS_P + TPB - 1) / TPB), dim3(TPB), 0,
+                       st, U, wl, tb.meta, tb.nbr, leaf_faces);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_project(T *U, const int32_t *list, int n, const DevTables &tb,
-                          hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_project<T>, grid2(n, NI), dim3(TPB), 0, st, U, list, n, tb.child);
+hipError_t launch_project(T *U, const WorkList &wl, const DevTables &tb, hipStream_t st) {
+    if (wl.grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_project<T>, grid2(wl.grid, NI), dim3(TPB), 0, st, U, wl, tb.child);
     return hipGetLastError();
 }
 
@@ -441,28 +442,28 @@ hipError_t launch_predict(T *U, const int32_t *list, int n, const DevTables &tb,
 }
 
 template <typename T>
-hipError_t launch_details(const T *U, const int32_t *list, int n, const DevTables &tb,
+hipError_t launch_details(const T *U, const WorkList &wl, const DevTables &tb,
                           const InstDev *inst, double *det, hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_details<T>, dim3(n), dim3(TPB), 0, st, U, list, n, tb.meta, inst, det);
+    if (wl.grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_details<T>, dim3(wl.grid), dim3(TPB), 0, st, U, wl, tb.meta, inst, det);
     return hipGetLastError();
 }
 
-hipError_t launch_flags(const int32_t *list, int n, const DevTables &tb, const InstDev *inst,
+hipError_t launch_flags(const WorkList &wl, const DevTables &tb, const InstDev *inst,
                         const double *det, int8_t *flags, hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_flags, dim3((n + TPB - 1) / TPB), dim3(TPB), 0, st, list, n, tb.meta,
+    if (wl.grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_flags, dim3((wl.grid + TPB - 1) / TPB), dim3(TPB), 0, st, wl, tb.meta,
                        tb.child, inst, det, flags);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_cfl(const T *U, const int32_t *leaves, int n, const DevTables &tb,
+hipError_t launch_cfl(const T *U, const WorkList &leaves, const DevTables &tb,
                       const InstDev *inst, int n_inst, double *blockmax, double *dt,
                       hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_cfl_block<T>, dim3(n), dim3(TPB), 0, st, U, leaves, n, tb.meta, inst,
-                       blockmax);
+    if (leaves.grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cfl_block<T>, dim3(leaves.grid), dim3(TPB), 0, st, U, leaves, tb.meta,
+                       inst, blockmax);
     // per-instance leaf ranges: the lists array starts with [offsets, counts]
     hipLaunchKernelGGL(k_cfl_inst, dim3(n_inst), dim3(TPB), 0, st, tb.lists, tb.lists,
                        tb.lists + n_inst, inst, blockmax, dt);
@@ -470,11 +471,11 @@ hipError_t launch_cfl(const T *U, const int32_t *leaves, int n, const DevTables 
 }
 
 template <typename T>
-hipError_t launch_totals(const T *U, const int32_t *leaves, int n, const DevTables &tb,
+hipError_t launch_totals(const T *U, const WorkList &leaves, const DevTables &tb,
                          const InstDev *inst, int n_inst, double *blocksum, double *tot,
                          hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_sum_block<T>, dim3(n), dim3(TPB), 0, st, U, leaves, n, blocksum);
+    if (leaves.grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_sum_block<T>, dim3(leaves.grid), dim3(TPB), 0, st, U, leaves, blocksum);
     hipLaunchKernelGGL(k_sum_inst, dim3(n_inst), dim3(TPB), 0, st, tb.lists, tb.lists,
                        tb.lists + n_inst, tb.meta, inst, blocksum, tot);
     return hipGetLastError();
@@ -483,17 +484,17 @@ hipError_t launch_totals(const T *U, const int32_t *leaves, int n, const DevTabl
 #define MRFV_INST(T)                                                                        \
     template hipError_t launch_prim2cons<T>(const double *, const int32_t *, int, T *,     \
                                             const BlockMeta *, const InstDev *, hipStream_t); \
-    template hipError_t launch_fill_halos<T>(T *, const int32_t *, int, const DevTables &, \
-                                             int, hipStream_t);                             \
-    template hipError_t launch_project<T>(T *, const int32_t *, int, const DevTables &,    \
+    template hipError_t launch_fill_halos<T>(T *, const WorkList &, const DevTables &, int,  \
+                                             hipStream_t);                                  \
+    template hipError_t launch_project<T>(T *, const WorkList &, const DevTables &,         \
                                           hipStream_t);                                     \
     template hipError_t launch_predict<T>(T *, const int32_t *, int, const DevTables &,    \
                                           hipStream_t);                                     \
-    template hipError_t launch_details<T>(const T *, const int32_t *, int, const DevTables &, \
+    template hipError_t launch_details<T>(const T *, const WorkList &, const DevTables &,   \
                                           const InstDev *, double *, hipStream_t);          \
-    template hipError_t launch_cfl<T>(const T *, const int32_t *, int, const DevTables &,  \
+    template hipError_t launch_cfl<T>(const T *, const WorkList &, const DevTables &,       \
                                       const InstDev *, int, double *, double *, hipStream_t); \
-    template hipError_t launch_totals<T>(const T *, const int32_t *, int, const DevTables &, \
+    template hipError_t launch_totals<T>(const T *, const WorkList &, const DevTables &,    \
                                          const InstDev *, int, double *, double *, hipStream_t);
 MRFV_INST(float)
 MRFV_INST(double)

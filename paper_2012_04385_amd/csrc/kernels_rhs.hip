@@ -270,13 +270,12 @@ struct GlobalSink {
 };
 
 template <typename T>
-__global__ __launch_bounds__(TPB) void k_flux(const T *__restrict__ U,
-                                              const int32_t *__restrict__ leaves, int n,
+__global__ __launch_bounds__(TPB) void k_flux(const T *__restrict__ U, WorkList wl,
                                               const BlockMeta *__restrict__ meta,
                                               const InstDev *__restrict__ inst, T *D, T *FF) {
-    const int b = blockIdx.x;
-    if (b >= n) return;
-    const int slot = leaves[b];
+    const int nb = wl.count();
+    for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+    const int slot = wl.at(b);
     const Gas<T> G = gas_of<T>(inst[meta[slot].inst]);
     const int r = threadIdx.x & 15, m = threadIdx.x >> 4;
     const T *ub = U + (size_t)slot * 5 * CELLS_P;
@@ -285,15 +284,16 @@ __global__ __launch_bounds__(TPB) void k_flux(const T *__restrict__ U,
     if (blockIdx.y == 0) pencil<T, 0>(ub, r, m, G, sink);
     else if (blockIdx.y == 1) pencil<T, 1>(ub, r, m, G, sink);
     else pencil<T, 2>(ub, r, m, G, sink);
+    }
 }
 
 // Non-leaf blocks: face-flux planes <- area average of the children's planes.
 template <typename T>
-__global__ __launch_bounds__(TPB) void k_ff_restrict(T *FF, const int32_t *__restrict__ list,
-                                                     int n, const int32_t *__restrict__ child) {
-    const int b = blockIdx.x;
-    if (b >= n) return;
-    const int slot = list[b];
+__global__ __launch_bounds__(TPB) void k_ff_restrict(T *FF, WorkList wl,
+                                                     const int32_t *__restrict__ child) {
+    const int nb = wl.count();
+    for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+    const int slot = wl.at(b);
     const int side = blockIdx.y, d = side >> 1, hi = side & 1;
     const int M = threadIdx.x >> 4, R = threadIdx.x & 15;
     const int cm = M >> 3, cr = R >> 3;
@@ -312,6 +312,7 @@ __global__ __launch_bounds__(TPB) void k_ff_restrict(T *FF, const int32_t *__res
         const T v01 = c[(m0 + 1) * NI + r0], v11 = c[(m0 + 1) * NI + r0 + 1];
         pp[q * FACE + M * NI + R] = ((v00 + v10) + (v01 + v11)) * (T)0.25;
     }
+    }
 }
 
 // Region index of the face neighbour on `side` in the 27-entry neighbourhood.
@@ -325,13 +326,12 @@ __device__ __forceinline__ int face_region(int side) {
 // Coarse leaves at resolution jumps: replace the own boundary flux by the fine average in
 // the flux differences D (plain path).
 template <typename T>
-__global__ __launch_bounds__(TPB) void k_reflux(T *D, const T *__restrict__ FF,
-                                                const int32_t *__restrict__ leaves, int n,
+__global__ __launch_bounds__(TPB) void k_reflux(T *D, const T *__restrict__ FF, WorkList wl,
                                                 const BlockMeta *__restrict__ meta,
                                                 const int32_t *__restrict__ nbr) {
-    const int b = blockIdx.x;
-    if (b >= n) return;
-    const int slot = leaves[b];
+    const int nb_ = wl.count();
+    for (int b = blockIdx.x; b < nb_; b += gridDim.x) {
+    const int slot = wl.at(b);
     const int rm = threadIdx.x, m = rm >> 4, r = rm & 15;
     for (int side = 0; side < 6; ++side) {
         const int nb = nbr[(size_t)slot * 27 + face_region(side)];
@@ -349,16 +349,16 @@ __global__ __launch_bounds__(TPB) void k_reflux(T *D, const T *__restrict__ FF,
         }
         __syncthreads();
     }
+    }
 }
 
 template <typename T>
-__global__ __launch_bounds__(TPB) void k_combine(const T *__restrict__ D, T *L,
-                                                 const int32_t *__restrict__ leaves, int n,
+__global__ __launch_bounds__(TPB) void k_combine(const T *__restrict__ D, T *L, WorkList wl,
                                                  const BlockMeta *__restrict__ meta,
                                                  const InstDev *__restrict__ inst) {
-    const int b = blockIdx.x;
-    if (b >= n) return;
-    const int slot = leaves[b];
+    const int nb = wl.count();
+    for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+    const int slot = wl.at(b);
     const BlockMeta mt = meta[slot];
     const T inv_dx = (T)(1.0 / ldexp(inst[mt.inst].dx0, -mt.level));
     const T *Ds = D + (size_t)slot * 3 * 5 * CELLS_I;
@@ -368,6 +368,7 @@ __global__ __launch_bounds__(TPB) void k_combine(const T *__restrict__ D, T *L,
     for (int q = 0; q < 5; ++q) {
         const T s = (Ds[q * CELLS_I + c] + Ds[(5 + q) * CELLS_I + c]) + Ds[(10 + q) * CELLS_I + c];
         Ls[q * CELLS_I + c] = -s * inv_dx;
+    }
     }
 }
 
@@ -385,13 +386,12 @@ __device__ __forceinline__ bool physical_state(const T u[5], const Gas<T> &G) {
 
 template <typename T>
 __global__ __launch_bounds__(TPB) void k_update(int stage, const double *__restrict__ dt, T *U,
-                                                T *U0, const T *__restrict__ L,
-                                                const int32_t *__restrict__ leaves, int n,
+                                                T *U0, const T *__restrict__ L, WorkList wl,
                                                 const BlockMeta *__restrict__ meta,
                                                 const InstDev *__restrict__ inst, int32_t *err) {
-    const int b = blockIdx.x;
-    if (b >= n) return;
-    const int slot = leaves[b];
+    const int nb = wl.count();
+    for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+    const int slot = wl.at(b);
     const BlockMeta mt = meta[slot];
     const Gas<T> G = gas_of<T>(inst[mt.inst]);
     const T dtt = (T)dt[mt.inst];
@@ -416,6 +416,7 @@ __global__ __launch_bounds__(TPB) void k_update(int stage, const double *__restr
         ub[o + q * CELLS_P] = un[q];
     }
     if (!physical_state(un, G)) atomicOr(err, 1);
+    }
 }
 
 // ---------------------------------------------------------------- batched path -------
@@ -478,17 +479,18 @@ __device__ __forceinline__ void face_flux_at(const T *__restrict__ ub, int d, in
 
 template <typename T>
 __global__ __launch_bounds__(TPB_F) void k_rhs_update(int stage, const double *__restrict__ dt,
-                                                      T *U, T *U0,
-                                                      const int32_t *__restrict__ leaves, int n,
+                                                      T *U, T *U0, WorkList wl,
                                                       const BlockMeta *__restrict__ meta,
                                                       const InstDev *__restrict__ inst, T *FF,
                                                       int32_t *err) {
     __shared__ T Fx[GP][NI][NI + 1][5];   // [plane][y][face x][q]
     __shared__ T Fy[GP][NI + 1][NI][5];   // [plane][face y][x][q]
     __shared__ T Fz[GP + 1][NI][NI][5];   // [face plane][y][x][q]; plane j = face k0 + j - 1/2
+    // one workgroup per leaf (no grid-stride loop: it costs registers and occupancy);
+    // graph launches size the grid by the slot capacity and surplus groups exit here
     const int b = blockIdx.x;
-    if (b >= n) return;
-    const int slot = leaves[b];
+    if (b >= wl.count()) return;
+    const int slot = wl.at(b);
     const BlockMeta mt = meta[slot];
     const InstDev P = inst[mt.inst];
     const Gas<T> G = gas_of<T>(P);
@@ -599,14 +601,13 @@ __global__ __launch_bounds__(TPB_F) void k_rhs_update(int stage, const double *_
 // U += a_s dt (L_corrected - L) on the boundary cells of coarse leaves at jumps.
 template <typename T>
 __global__ __launch_bounds__(TPB) void k_reflux_update(int stage, const double *__restrict__ dt,
-                                                       T *U, const T *__restrict__ FF,
-                                                       const int32_t *__restrict__ leaves, int n,
+                                                       T *U, const T *__restrict__ FF, WorkList wl,
                                                        const BlockMeta *__restrict__ meta,
                                                        const int32_t *__restrict__ nbr,
                                                        const InstDev *__restrict__ inst) {
-    const int b = blockIdx.x;
-    if (b >= n) return;
-    const int slot = leaves[b];
+    const int nb_ = wl.count();
+    for (int b = blockIdx.x; b < nb_; b += gridDim.x) {
+    const int slot = wl.at(b);
     const BlockMeta mt = meta[slot];
     const InstDev P = inst[mt.inst];
     const T coef = stage_coef<T>(stage) * (T)dt[mt.inst] * (T)(1.0 / ldexp(P.dx0, -mt.level));
@@ -630,86 +631,85 @@ __global__ __launch_bounds__(TPB) void k_reflux_update(int stage, const double *
         }
         __syncthreads();
     }
+    }
 }
 
 }  // namespace
 
 template <typename T>
-hipError_t launch_flux(const T *U, const int32_t *leaves, int n, const DevTables &tb,
-                       const InstDev *inst, T *D, T *FF, hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_flux<T>, dim3(n, 3), dim3(TPB), 0, st, U, leaves, n, tb.meta, inst, D, FF);
+hipError_t launch_flux(const T *U, const WorkList &wl, const DevTables &tb, const InstDev *inst,
+                       T *D, T *FF, hipStream_t st) {
+    if (wl.grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_flux<T>, dim3(wl.grid, 3), dim3(TPB), 0, st, U, wl, tb.meta, inst, D, FF);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_ff_restrict(T *FF, const int32_t *parents, int n, const DevTables &tb,
-                              hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_ff_restrict<T>, dim3(n, 6), dim3(TPB), 0, st, FF, parents, n, tb.child);
+hipError_t launch_ff_restrict(T *FF, const WorkList &wl, const DevTables &tb, hipStream_t st) {
+    if (wl.grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ff_restrict<T>, dim3(wl.grid, 6), dim3(TPB), 0, st, FF, wl, tb.child);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_reflux(T *D, const T *FF, const int32_t *leaves, int n, const DevTables &tb,
+hipError_t launch_reflux(T *D, const T *FF, const WorkList &wl, const DevTables &tb,
                          hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_reflux<T>, dim3(n), dim3(TPB), 0, st, D, FF, leaves, n, tb.meta, tb.nbr);
+    if (wl.grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reflux<T>, dim3(wl.grid), dim3(TPB), 0, st, D, FF, wl, tb.meta, tb.nbr);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_combine(const T *D, T *L, const int32_t *leaves, int n, const DevTables &tb,
+hipError_t launch_combine(const T *D, T *L, const WorkList &wl, const DevTables &tb,
                           const InstDev *inst, hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_combine<T>, dim3(n, CELLS_I / TPB), dim3(TPB), 0, st, D, L, leaves, n,
+    if (wl.grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_combine<T>, dim3(wl.grid, CELLS_I / TPB), dim3(TPB), 0, st, D, L, wl,
                        tb.meta, inst);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_update(int stage, const double *dt, T *U, T *U0, const T *L,
-                         const int32_t *leaves, int n, const DevTables &tb, const InstDev *inst,
-                         int32_t *err, hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_update<T>, dim3(n, CELLS_I / TPB), dim3(TPB), 0, st, stage, dt, U, U0, L,
-                       leaves, n, tb.meta, inst, err);
+hipError_t launch_update(int stage, const double *dt, T *U, T *U0, const T *L, const WorkList &wl,
+                         const DevTables &tb, const InstDev *inst, int32_t *err, hipStream_t st) {
+    if (wl.grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_update<T>, dim3(wl.grid, CELLS_I / TPB), dim3(TPB), 0, st, stage, dt, U, U0,
+                       L, wl, tb.meta, inst, err);
     return hipGetLastError();
 }
 
 hipError_t launch_rhs_update_f32(int stage, const double *dt, float *U, float *U0,
-                                 const int32_t *leaves, int n, const DevTables &tb,
-                                 const InstDev *inst, float *FF, int32_t *err, hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_rhs_update<float>, dim3(n), dim3(TPB_F), 0, st, stage, dt, U, U0, leaves,
-                       n, tb.meta, inst, FF, err);
+                                 const WorkList &wl, const DevTables &tb, const InstDev *inst,
+                                 float *FF, int32_t *err, hipStream_t st) {
+    if (wl.grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rhs_update<float>, dim3(wl.grid), dim3(TPB_F), 0, st, stage, dt, U, U0, wl,
+                       tb.meta, inst, FF, err);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_reflux_update(int stage, const double *dt, T *U, const T *FF,
-                                const int32_t *leaves, int n, const DevTables &tb,
-                                const InstDev *inst, hipStream_t st) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_reflux_update<T>, dim3(n), dim3(TPB), 0, st, stage, dt, U, FF, leaves, n,
+                                const WorkList &wl, const DevTables &tb, const InstDev *inst,
+                                hipStream_t st) {
+    if (wl.grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reflux_update<T>, dim3(wl.grid), dim3(TPB), 0, st, stage, dt, U, FF, wl,
                        tb.meta, tb.nbr, inst);
     return hipGetLastError();
 }
 
 #define MRFV_INST_RHS(T)                                                                    \
-    template hipError_t launch_flux<T>(const T *, const int32_t *, int, const DevTables &,  \
+    template hipError_t launch_flux<T>(const T *, const WorkList &, const DevTables &,      \
                                        const InstDev *, T *, T *, hipStream_t);             \
-    template hipError_t launch_ff_restrict<T>(T *, const int32_t *, int, const DevTables &, \
+    template hipError_t launch_ff_restrict<T>(T *, const WorkList &, const DevTables &,     \
                                               hipStream_t);                                 \
-    template hipError_t launch_reflux<T>(T *, const T *, const int32_t *, int,              \
-                                         const DevTables &, hipStream_t);                   \
-    template hipError_t launch_combine<T>(const T *, T *, const int32_t *, int,             \
-                                          const DevTables &, const InstDev *, hipStream_t); \
+    template hipError_t launch_reflux<T>(T *, const T *, const WorkList &, const DevTables &, \
+                                         hipStream_t);                                      \
+    template hipError_t launch_combine<T>(const T *, T *, const WorkList &, const DevTables &, \
+                                          const InstDev *, hipStream_t);                    \
     template hipError_t launch_update<T>(int, const double *, T *, T *, const T *,          \
-                                         const int32_t *, int, const DevTables &,           \
-                                         const InstDev *, int32_t *, hipStream_t);          \
+                                         const WorkList &, const DevTables &, const InstDev *, \
+                                         int32_t *, hipStream_t);                           \
     template hipError_t launch_reflux_update<T>(int, const double *, T *, const T *,        \
-                                                const int32_t *, int, const DevTables &,    \
+                                                const WorkList &, const DevTables &,        \
                                                 const InstDev *, hipStream_t);
 MRFV_INST_RHS(float)
 MRFV_INST_RHS(double)

@@ -40,6 +40,19 @@ struct DevTables {
     int32_t *lists = nullptr;    // concatenated work lists (see HostLists)
 };
 
+// A work list of block slots.  Eager launches pass the offset and count from the host;
+// graph-captured launches pass a device descriptor {offset, count} that the host rewrites
+// whenever the tree changes, so a captured graph stays valid.  Kernels loop over the list
+// with a grid stride, so any grid size is correct.
+struct WorkList {
+    const int32_t *base = nullptr;   // device list array
+    const int32_t *desc = nullptr;   // device {offset, count}, or null
+    int32_t off = 0, n = 0;          // host offset and count when desc is null
+    int grid = 0;                    // workgroups to launch (0: skip the launch)
+    __device__ __forceinline__ int count() const { return desc ? desc[1] : n; }
+    __device__ __forceinline__ int32_t at(int i) const { return base[(desc ? desc[0] : off) + i]; }
+};
+
 // Work lists, concatenated in DevTables::lists (host copy).  The array starts with the
 // per-instance leaf ranges: data[i] = offset (into data) of instance i's leaves,
 // data[n_inst + i] = their count; the instance ranges are contiguous parts of the
@@ -50,6 +63,8 @@ struct HostLists {
     // per level: all blocks, non-leaf blocks, leaves
     std::vector<int32_t> lvl_off, lvl_cnt, par_off, par_cnt, leaf_off, leaf_cnt;
     int32_t all_leaves_off = 0, all_leaves_cnt = 0;      // leaves of every level
+    // descriptor table {offset, count} per list, mirrored on the device (graph launches)
+    std::vector<int32_t> desc;
     int32_t all_blocks_off = 0, all_blocks_cnt = 0;      // every block
     int32_t fine_off = 0, fine_cnt = 0;                  // every block with level >= 1
 };
@@ -63,8 +78,19 @@ struct HostBlock {
     uint64_t morton = 0;
 };
 
+// One recorded tree edit (for undoing a speculative commit).
+struct TreeOp {
+    int kind;        // 1 refine, -1 coarsen
+    int slot;        // refined leaf / coarsened parent
+    int child[8];    // slots of the created / removed children
+};
+
 class Topology {
   public:
+    // Apply flags (per slot: 1 refine, -1 coarsen) to the leaves; records the edits.
+    bool commit(const int8_t *flags, std::vector<TreeOp> *ops, std::vector<int> *fresh);
+    // Undo recorded edits (reverse order); restores slots and the free list exactly.
+    void undo(const std::vector<TreeOp> &ops);
     void reset(int capacity, const std::vector<mrfv_instance> &inst);
     int add_block(int inst, int level, int bx, int by, int bz);   // -1 when full
     int find(int inst, int level, int bx, int by, int bz) const;
@@ -92,60 +118,75 @@ class Topology {
 
 uint64_t morton_encode(int shadow, int level, int bx, int by, int bz);
 
+// Descriptor indices of the work lists (DevTables lists + the device descriptor table).
+constexpr int MAX_LEVELS = 13;
+constexpr int DESC_LEAVES = 0, DESC_ALL = 1, DESC_FINE = 2, DESC_SCRATCH = 3;
+constexpr int desc_lvl(int l) { return 4 + 3 * l; }
+constexpr int desc_par(int l) { return 5 + 3 * l; }
+constexpr int desc_leaf(int l) { return 6 + 3 * l; }
+constexpr int N_DESC = 4 + 3 * MAX_LEVELS;
+
 // --------------------------------------------------------------- kernel launchers ----
 // All launchers enqueue on `st` and return hipGetLastError().
 template <typename T>
 hipError_t launch_prim2cons(const double *prim, const int32_t *slots, int n, T *U,
                             const BlockMeta *meta, const InstDev *inst, hipStream_t st);
 template <typename T>
-hipError_t launch_fill_halos(T *U, const int32_t *list, int n, const DevTables &tb,
-                             int leaf_faces, hipStream_t st);
+hipError_t launch_fill_halos(T *U, const WorkList &wl, const DevTables &tb, int leaf_faces,
+                             hipStream_t st);
 template <typename T>
-hipError_t launch_project(T *U, const int32_t *list, int n, const DevTables &tb,
-                          hipStream_t st);
+hipError_t launch_project(T *U, const WorkList &wl, const DevTables &tb, hipStream_t st);
 template <typename T>
 hipError_t launch_predict(T *U, const int32_t *list, int n, const DevTables &tb,
                           hipStream_t st);
 template <typename T>
-hipError_t launch_details(const T *U, const int32_t *list, int n, const DevTables &tb,
+hipError_t launch_details(const T *U, const WorkList &wl, const DevTables &tb,
                           const InstDev *inst, double *det, hipStream_t st);
-hipError_t launch_flags(const int32_t *list, int n, const DevTables &tb, const InstDev *inst,
+hipError_t launch_flags(const WorkList &wl, const DevTables &tb, const InstDev *inst,
                         const double *det, int8_t *flags, hipStream_t st);
 template <typename T>
-hipError_t launch_cfl(const T *U, const int32_t *leaves, int n, const DevTables &tb,
+hipError_t launch_cfl(const T *U, const WorkList &leaves, const DevTables &tb,
                       const InstDev *inst, int n_inst, double *blockmax, double *dt,
                       hipStream_t st);
 template <typename T>
-hipError_t launch_totals(const T *U, const int32_t *leaves, int n, const DevTables &tb,
+hipError_t launch_totals(const T *U, const WorkList &leaves, const DevTables &tb,
                          const InstDev *inst, int n_inst, double *blocksum, double *tot,
                          hipStream_t st);
 template <typename T>
-hipError_t launch_flux(const T *U, const int32_t *leaves, int n, const DevTables &tb,
+hipError_t launch_flux(const T *U, const WorkList &leaves, const DevTables &tb,
                        const InstDev *inst, T *D, T *FF, hipStream_t st);
 template <typename T>
-hipError_t launch_ff_restrict(T *FF, const int32_t *parents, int n, const DevTables &tb,
+hipError_t launch_ff_restrict(T *FF, const WorkList &parents, const DevTables &tb,
                               hipStream_t st);
 template <typename T>
-hipError_t launch_reflux(T *D, const T *FF, const int32_t *leaves, int n,
-                         const DevTables &tb, hipStream_t st);
+hipError_t launch_reflux(T *D, const T *FF, const WorkList &leaves, const DevTables &tb,
+                         hipStream_t st);
 template <typename T>
-hipError_t launch_combine(const T *D, T *L, const int32_t *leaves, int n,
-                          const DevTables &tb, const InstDev *inst, hipStream_t st);
+hipError_t launch_combine(const T *D, T *L, const WorkList &leaves, const DevTables &tb,
+                          const InstDev *inst, hipStream_t st);
 template <typename T>
 hipError_t launch_update(int stage, const double *dt, T *U, T *U0, const T *L,
-                         const int32_t *leaves, int n, const DevTables &tb,
-                         const InstDev *inst, int32_t *err, hipStream_t st);
+                         const WorkList &leaves, const DevTables &tb, const InstDev *inst,
+                         int32_t *err, hipStream_t st);
 hipError_t launch_rhs_update_f32(int stage, const double *dt, float *U, float *U0,
-                                 const int32_t *leaves, int n, const DevTables &tb,
+                                 const WorkList &leaves, const DevTables &tb,
                                  const InstDev *inst, float *FF, int32_t *err, hipStream_t st);
 template <typename T>
 hipError_t launch_reflux_update(int stage, const double *dt, T *U, const T *FF,
-                                const int32_t *leaves, int n, const DevTables &tb,
+                                const WorkList &leaves, const DevTables &tb,
                                 const InstDev *inst, hipStream_t st);
+template <typename T>
+hipError_t launch_features(const T *U, const WorkList &wl, const DevTables &tb, const InstDev *inst,
+                           float *X, hipStream_t st);
 
 }  // namespace mrfv
 
 // ---------------------------------------------------------------- context -------------
+struct mrfv_mlp;
+namespace mrfv {
+// The proposer network's forward pass queued on a given stream; logits [N][3] FP32.
+int mlp_forward_on(mrfv_mlp *mm, hipStream_t st, const float *X, int N, float *logits);
+}  // namespace mrfv
 struct mrfv_ctx {
     mrfv_config cfg{};
     std::vector<mrfv_instance> inst;
@@ -162,12 +203,38 @@ struct mrfv_ctx {
     double *d_blockred = nullptr;      // [cap][5] per-block partial reductions
     double *d_det = nullptr;           // [cap]
     int8_t *d_flags = nullptr;         // [cap]
+    int32_t *d_desc = nullptr;         // [N_DESC][2] list descriptors (graph launches)
+    hipStream_t gstream = nullptr;     // capture stream of the stage graph
+    hipGraphExec_t graph = nullptr;    // three RK stages, valid for (gU, gU0, gdt)
+    void *gU = nullptr, *gU0 = nullptr;
+    const double *gdt = nullptr;
+    int lmax_all = 0;                  // deepest lmax over the instances
+    std::vector<int64_t> lvl_bound;    // most blocks any level can hold
+    // learned refinement proposer
+    mrfv_mlp *mlp = nullptr;
+    int prop_mode = 0;                 // 0 off, 1 network, 2 persistence (no change)
+    float *d_X = nullptr, *d_logits = nullptr;
+    float *h_logits = nullptr;         // pinned
+    int8_t *h_flags = nullptr;         // pinned, judge flags
+    int32_t *h_err = nullptr;          // pinned
+    std::vector<int8_t> proposal;      // per slot
+    mrfv::DevTables tb2;               // staging tables built from the proposal
+    int32_t *d_desc2 = nullptr;
+    mrfv::HostLists lists2;
+    std::vector<mrfv::BlockMeta> s_meta;
+    std::vector<int32_t> s_child, s_nbr;
+    bool staged = false, staged_jumps = false;
+    hipStream_t side = nullptr;        // staging uploads
+    hipEvent_t ev_prop = nullptr;      // proposal copied to the host
+    int64_t p_steps = 0, p_hits = 0, p_tp[3] = {0, 0, 0}, p_fp[3] = {0, 0, 0}, p_fn[3] = {0, 0, 0};
+    double p_build_ms = 0.0;
     int32_t *d_slots = nullptr;        // [cap] scratch slot list
     double *d_prim = nullptr;          // IC staging [batch][5][16^3]
     int prim_batch = 0;
     int lists_cap = 0;
     // kernel timing
     bool has_jumps = false;            // some leaf has a non-leaf same-level face neighbour
+    bool capturing = false;            // recording the stage graph
     bool timing = false;
     std::vector<hipEvent_t> ev_free;   // event pool
     std::vector<hipEvent_t> ev_pairs;  // recorded (start, stop) pairs not yet read

@@ -115,6 +115,68 @@ void Topology::coarsen(int p) {
     blocks_[p].leaf = true;
 }
 
+bool Topology::commit(const int8_t *flags, std::vector<TreeOp> *ops, std::vector<int> *fresh) {
+    std::vector<int> order = alive_sorted();
+    std::vector<int> coarsen_p, refine_s;
+    for (int s : order) {
+        const HostBlock &b = blocks_[s];
+        if (!b.leaf) continue;
+        if (flags[s] == 1) refine_s.push_back(s);
+        if (flags[s] == -1 && (b.bx & 1) == 0 && (b.by & 1) == 0 && (b.bz & 1) == 0)
+            coarsen_p.push_back(b.parent);
+    }
+    for (int p : coarsen_p) {
+        TreeOp op{-1, p, {}};
+        for (int o = 0; o < 8; ++o) op.child[o] = blocks_[p].child[o];
+        coarsen(p);
+        if (ops) ops->push_back(op);
+    }
+    std::vector<int> created;
+    for (int s : refine_s) {
+        created.clear();
+        if (!refine(s, &created)) return false;
+        TreeOp op{1, s, {}};
+        for (int o = 0; o < 8; ++o) op.child[o] = created[o];
+        if (ops) ops->push_back(op);
+        if (fresh) fresh->insert(fresh->end(), created.begin(), created.end());
+    }
+    return true;
+}
+
+void Topology::undo(const std::vector<TreeOp> &ops) {
+    for (auto it = ops.rbegin(); it != ops.rend(); ++it) {
+        const TreeOp &op = *it;
+        HostBlock &p = blocks_[op.slot];
+        if (op.kind == 1) {
+            // remove the children newest first: the free list regains its order
+            for (int o = 7; o >= 0; --o) remove_block(op.child[o]);
+            for (int o = 0; o < 8; ++o) p.child[o] = -1;
+            p.leaf = true;
+        } else {
+            // re-create the removed children in their slots (the last freed comes back first)
+            for (int o = 7; o >= 0; --o) {
+                const int s = free_.back();
+                free_.pop_back();
+                HostBlock &c = blocks_[s];
+                c = HostBlock();
+                c.inst = p.inst;
+                c.level = p.level + 1;
+                c.bx = 2 * p.bx + (o & 1);
+                c.by = 2 * p.by + ((o >> 1) & 1);
+                c.bz = 2 * p.bz + (o >> 2);
+                c.alive = true;
+                c.leaf = true;
+                c.parent = op.slot;
+                c.morton = morton_encode(shadow_[c.inst], c.level, c.bx, c.by, c.bz);
+                map_[key(c.inst, c.level, c.bx, c.by, c.bz)] = s;
+                ++n_alive_;
+                p.child[o] = s;
+            }
+            p.leaf = false;
+        }
+    }
+}
+
 std::vector<int> Topology::alive_sorted() const {
     std::vector<int> v;
     v.reserve(n_alive_);
@@ -211,6 +273,19 @@ void Topology::build(std::vector<BlockMeta> &meta, std::vector<int32_t> &child,
     for (int s : order)
         if (blocks_[s].level >= 1) L.data.push_back(s);
     L.fine_cnt = (int32_t)L.data.size() - L.fine_off;
+    L.desc.assign(2 * N_DESC, 0);
+    auto set = [&](int which, int32_t off, int32_t cnt) {
+        L.desc[2 * which] = off;
+        L.desc[2 * which + 1] = cnt;
+    };
+    set(DESC_LEAVES, L.all_leaves_off, L.all_leaves_cnt);
+    set(DESC_ALL, L.all_blocks_off, L.all_blocks_cnt);
+    set(DESC_FINE, L.fine_off, L.fine_cnt);
+    for (int l = 0; l <= maxl && l < MAX_LEVELS; ++l) {
+        set(desc_lvl(l), L.lvl_off[l], L.lvl_cnt[l]);
+        set(desc_par(l), L.par_off[l], L.par_cnt[l]);
+        set(desc_leaf(l), L.leaf_off[l], L.leaf_cnt[l]);
+    }
 }
 
 }  // namespace mrfv

@@ -80,6 +80,20 @@ def lib():
         "mrfv_kernel_time": ([vp, C.POINTER(i64), C.POINTER(d), C.POINTER(i64)], C.c_int),
         "mrfv_morton_encode": ([i32, i32, i32, i32, i32], C.c_uint64),
         "mrfv_morton_neighbor": ([C.c_uint64, i32, i32, i32, C.POINTER(i32)], C.c_uint64),
+        "mrfv_mlp_create": ([pvp, i32, vp], C.c_int),
+        "mrfv_mlp_destroy": ([vp], C.c_int),
+        "mrfv_mlp_last_error": ([vp], C.c_char_p),
+        "mrfv_mlp_nparams": ([], i32),
+        "mrfv_mlp_set_params": ([vp, C.POINTER(C.c_float)], C.c_int),
+        "mrfv_mlp_get_params": ([vp, C.POINTER(C.c_float)], C.c_int),
+        "mrfv_mlp_forward": ([vp, vp, i32, vp], C.c_int),
+        "mrfv_mlp_loss_grad": ([vp, vp, C.POINTER(i32), C.POINTER(C.c_float), i32,
+                                C.POINTER(C.c_float), C.POINTER(C.c_float)], C.c_int),
+        "mrfv_mlp_adam_step": ([vp, C.c_float, C.c_float, C.c_float, C.c_float], C.c_int),
+        "mrfv_features": ([vp, vp, vp, C.POINTER(i32), C.POINTER(i32)], C.c_int),
+        "mrfv_set_proposer": ([vp, vp, i32], C.c_int),
+        "mrfv_proposer_stats": ([vp, C.POINTER(i64), C.POINTER(d)], C.c_int),
+        "mrfv_last_flags": ([vp, C.POINTER(C.c_int8)], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -96,7 +110,11 @@ def exported_symbols():
             "mrfv_cfl_dt", "mrfv_totals", "mrfv_commit_flags", "mrfv_step", "mrfv_check",
             "mrfv_get_blocks", "mrfv_stats", "mrfv_refine_block", "mrfv_coarsen_block",
             "mrfv_enable_kernel_timing", "mrfv_kernel_time", "mrfv_morton_encode",
-            "mrfv_morton_neighbor"]
+            "mrfv_morton_neighbor", "mrfv_mlp_create", "mrfv_mlp_destroy",
+            "mrfv_mlp_last_error", "mrfv_mlp_nparams", "mrfv_mlp_set_params",
+            "mrfv_mlp_get_params", "mrfv_mlp_forward", "mrfv_mlp_loss_grad",
+            "mrfv_mlp_adam_step", "mrfv_features", "mrfv_set_proposer", "mrfv_proposer_stats",
+            "mrfv_last_flags"]
 
 
 def morton_encode(shadow, level, bx, by, bz) -> int:
@@ -133,7 +151,7 @@ def slot_capacity_for(problems) -> int:
 class Solver:
     """One library context plus caller-owned device buffers (torch tensors)."""
 
-    def __init__(self, problems: Sequence, dtype: str = "f32", batched: bool = True,
+    def __init__(self, problems: Sequence, dtype: str = "f32", batched=True,
                  capacity: Optional[int] = None, device: str = "cuda:0", adapt=None):
         import torch
         if not torch.cuda.is_available():
@@ -150,7 +168,7 @@ class Solver:
             arr[i] = _instance(pb)
             if adapt is not None:
                 arr[i].adapt = int(adapt)
-        cfg = Config(self.dtype, n, cap, 1 if batched else 0)
+        cfg = Config(self.dtype, n, cap, int(batched))
         self.stream = torch.cuda.current_stream(self.device)
         h = C.c_void_p()
         rc = lib().mrfv_create(C.byref(h), C.byref(cfg), arr, C.c_void_p(self.stream.cuda_stream))
@@ -301,3 +319,162 @@ class Solver:
 
     def leaf_cells(self) -> int:
         return self.stats()[2]
+
+
+# --------------------------------------------------------------------- proposer
+N_FEATURES = 192
+CLASS_REFINE, CLASS_KEEP, CLASS_COARSEN = 0, 1, 2
+
+
+def flags_to_classes(flags: np.ndarray) -> np.ndarray:
+    """Judge flags (+1 refine, 0 keep, -1 coarsen) -> class labels (0, 1, 2)."""
+    f = np.asarray(flags)
+    return np.where(f > 0, CLASS_REFINE, np.where(f < 0, CLASS_COARSEN, CLASS_KEEP)).astype(np.int32)
+
+
+class MLP:
+    """The refinement proposer's network on the device (bfloat16 products, FP32 master
+    parameters and Adam moments)."""
+
+    def __init__(self, max_rows: int, device: str = "cuda:0"):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device: the proposer network runs on the GPU only")
+        self.torch = torch
+        self.device = torch.device(device)
+        self.stream = torch.cuda.current_stream(self.device)
+        self.max_rows = int(max_rows)
+        h = C.c_void_p()
+        rc = lib().mrfv_mlp_create(C.byref(h), self.max_rows, C.c_void_p(self.stream.cuda_stream))
+        if rc != OK:
+            raise MrfvError(rc, "mrfv_mlp_create failed")
+        self.h = h
+        self.nparams = int(lib().mrfv_mlp_nparams())
+
+    def _chk(self, rc: int):
+        if rc != OK:
+            msg = lib().mrfv_mlp_last_error(self.h)
+            raise MrfvError(rc, msg.decode() if msg else "")
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().mrfv_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, p: np.ndarray):
+        a = np.ascontiguousarray(p, dtype=np.float32)
+        assert a.size == self.nparams
+        self._chk(lib().mrfv_mlp_set_params(self.h, a.ctypes.data_as(C.POINTER(C.c_float))))
+
+    def get_params(self) -> np.ndarray:
+        a = np.zeros(self.nparams, dtype=np.float32)
+        self._chk(lib().mrfv_mlp_get_params(self.h, a.ctypes.data_as(C.POINTER(C.c_float))))
+        return a
+
+    def init_params(self, seed: int) -> np.ndarray:
+        """He-uniform weights, zero biases (layout W1, b1, W2, b2, W3, b3)."""
+        rng = np.random.default_rng(seed)
+        parts = []
+        for fi, fo in ((192, 64), (64, 64), (64, 3)):
+            lim = np.sqrt(6.0 / fi)
+            parts += [rng.uniform(-lim, lim, fi * fo), np.zeros(fo)]
+        p = np.concatenate(parts).astype(np.float32)
+        self.set_params(p)
+        return p
+
+    def forward(self, X):
+        """X: device float32 [N, 192] -> device float32 logits [N, 3]."""
+        X = X.contiguous()
+        out = self.torch.empty((X.shape[0], 3), dtype=self.torch.float32, device=self.device)
+        self._chk(lib().mrfv_mlp_forward(self.h, C.c_void_p(X.data_ptr()), int(X.shape[0]),
+                                         C.c_void_p(out.data_ptr())))
+        return out
+
+    def loss_grad(self, X, labels: np.ndarray, class_w, want_grad: bool = True):
+        X = X.contiguous()
+        y = np.ascontiguousarray(labels, dtype=np.int32)
+        cw = np.ascontiguousarray(class_w, dtype=np.float32)
+        loss = C.c_float(0.0)
+        g = np.zeros(self.nparams, dtype=np.float32) if want_grad else None
+        self._chk(lib().mrfv_mlp_loss_grad(
+            self.h, C.c_void_p(X.data_ptr()), y.ctypes.data_as(C.POINTER(C.c_int32)),
+            cw.ctypes.data_as(C.POINTER(C.c_float)), int(X.shape[0]), C.byref(loss),
+            g.ctypes.data_as(C.POINTER(C.c_float)) if want_grad else None))
+        return float(loss.value), g
+
+    def adam_step(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+        self._chk(lib().mrfv_mlp_adam_step(self.h, lr, beta1, beta2, eps))
+
+    def train(self, X, labels: np.ndarray, epochs: int, lr: float = 3e-3, batch: int = 4096,
+              seed: int = 0, class_w=None):
+        """Mini-batch Adam on the device; class weights default to inverse frequencies."""
+        torch = self.torch
+        y = np.asarray(labels, dtype=np.int32)
+        if class_w is None:
+            cnt = np.bincount(y, minlength=3).astype(np.float64)
+            class_w = np.where(cnt > 0, cnt.sum() / np.maximum(cnt, 1) / 3.0, 0.0)
+        rng = np.random.default_rng(seed)
+        n = X.shape[0]
+        losses = []
+        for _ in range(epochs):
+            perm = rng.permutation(n)
+            for a in range(0, n, batch):
+                idx = perm[a:a + batch]
+                Xb = X[torch.as_tensor(idx, device=self.device)]
+                loss, _ = self.loss_grad(Xb, y[idx], class_w, want_grad=False)
+                self.adam_step(lr)
+                losses.append(loss)
+        return losses
+
+
+def solver_features(solver: "Solver"):
+    """Proposer features of every current leaf: (device float32 [n, 192], slots)."""
+    torch = solver.torch
+    X = torch.zeros((solver.capacity, N_FEATURES), dtype=torch.float32, device=solver.device)
+    slots = np.zeros(solver.capacity, dtype=np.int32)
+    n = C.c_int32(0)
+    solver._chk(lib().mrfv_features(solver.h, solver._p(solver.U), C.c_void_p(X.data_ptr()),
+                                    slots.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(n)))
+    return X[: n.value], slots[: n.value]
+
+
+def set_proposer(solver: "Solver", mlp: Optional[MLP], mode: int):
+    solver._chk(lib().mrfv_set_proposer(solver.h, mlp.h if mlp is not None else None, int(mode)))
+    solver._proposer = mlp   # keep the network alive while the solver uses it
+
+
+def last_flags(solver: "Solver") -> np.ndarray:
+    """Judged flags (int8 by slot) of the last adaptive step."""
+    f = np.zeros(solver.capacity, dtype=np.int8)
+    solver._chk(lib().mrfv_last_flags(solver.h, f.ctypes.data_as(C.POINTER(C.c_int8))))
+    return f
+
+
+def collect_training_data(solver: "Solver", steps: int):
+    """Run steps and record, for every step, the features of the leaves at its start and
+    the judge's class for each of them at its end: (device X [n, 192], int32 labels)."""
+    torch = solver.torch
+    Xs, ys = [], []
+    for _ in range(steps):
+        X, slots = solver_features(solver)
+        X = X.clone()
+        solver.step()
+        ys.append(flags_to_classes(last_flags(solver)[slots]))
+        Xs.append(X)
+    return torch.cat(Xs), np.concatenate(ys)
+
+
+def proposer_stats(solver: "Solver") -> dict:
+    out = (C.c_int64 * 11)()
+    ms = C.c_double(0.0)
+    solver._chk(lib().mrfv_proposer_stats(solver.h, out, C.byref(ms)))
+    v = list(out)
+    per = {name: dict(tp=v[2 + 3 * c], fp=v[3 + 3 * c], fn=v[4 + 3 * c])
+           for c, name in enumerate(("refine", "keep", "coarsen"))}
+    return dict(steps=v[0], hits=v[1], build_ms=ms.value, **per)

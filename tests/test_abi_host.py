@@ -21,7 +21,7 @@ def _lib():
 def test_header_symbols_exported():
     mrfv = _lib()
     hdr = open(os.path.join(ROOT, "include", "mrfv.h")).read()
-    declared = set(re.findall(r"^\s*(?:int|int64_t|uint64_t|const char \*)\s*(mrfv_\w+)\s*\(", hdr, re.M))
+    declared = set(re.findall(r"^\s*(?:int|int32_t|int64_t|uint64_t|const char \*)\s*(mrfv_\w+)\s*\(", hdr, re.M))
     assert len(declared) >= 20
     L = mrfv.lib()
     for name in declared:

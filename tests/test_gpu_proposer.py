@@ -1,0 +1,189 @@
+"""The learned refinement proposer on the GPU, through the C ABI.
+
+Network: forward logits and the class-weighted cross-entropy gradient against the FP64
+oracle evaluated with the same bfloat16 roundings (inputs, weights, hidden activations,
+backward operands); Adam against its definition (Kingma & Ba, Algorithm 1).  Features
+against the oracle on the solver's own blocks.  Proposer modes: the solution and the tree
+are bitwise identical with the proposer off, on (network) and in persistence mode, since
+the Harten threshold stays the judge; training on the solver's flags lowers the loss.
+
+Tolerances.  The GPU sums bfloat16 products in FP32 where the oracle sums them in FP64;
+the worst case is a hidden activation whose FP32 and FP64 pre-activations round to
+neighbouring bfloat16 values (one unit in the 8th bit).  With |W| <= 0.2 and O(1)
+activations that moves a logit by well under 1e-2, the bound used here; gradients are
+compared in the 2-norm with 2e-2 relative.  Features are FP32 sums of 64 cell values:
+1e-5 relative to max(1, |x|).
+"""
+import numpy as np
+import pytest
+
+from paper_2012_04385_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+H, N, P = 4, 16, 24
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def _params(n, seed, scale=0.15):
+    rng = np.random.default_rng(seed)
+    return rng.normal(scale=scale, size=n).astype(np.float32)
+
+
+@pytest.mark.parametrize("rows", [1, 37, 1000])
+def test_mlp_forward_vs_oracle(orc, torch_mod, rows):
+    from paper_2012_04385_amd.mrfv import MLP
+    torch = torch_mod
+    m = MLP(max_rows=1024)
+    p = _params(m.nparams, 10 + rows)
+    m.set_params(p)
+    X = np.random.default_rng(rows).normal(size=(rows, 192)).astype(np.float32)
+    got = m.forward(torch.as_tensor(X, device="cuda")).cpu().numpy()
+    ref = orc.mlp_forward(p.astype(np.float64), X.astype(np.float64), bf16=True)
+    err = np.abs(got - ref).max()
+    print(f"forward rows={rows}: max |logit diff| {err:.2e}, max |logit| {np.abs(ref).max():.2f}")
+    assert err <= 1e-2 * max(1.0, np.abs(ref).max())
+    # the FP64 function itself is within bfloat16 error of both
+    exact = orc.mlp_forward(p.astype(np.float64), X.astype(np.float64), bf16=False)
+    assert np.abs(exact - got).max() <= 0.1 * max(1.0, np.abs(exact).max())
+
+
+@pytest.mark.parametrize("rows", [5, 53, 700])
+def test_mlp_loss_grad_vs_oracle(orc, torch_mod, rows):
+    from paper_2012_04385_amd.mrfv import MLP
+    torch = torch_mod
+    m = MLP(max_rows=1024)
+    p = _params(m.nparams, 20 + rows)
+    m.set_params(p)
+    rng = np.random.default_rng(rows)
+    X = rng.normal(size=(rows, 192)).astype(np.float32)
+    y = rng.integers(0, 3, size=rows).astype(np.int32)
+    w = np.array([2.0, 0.5, 3.0], dtype=np.float32)
+    loss, g = m.loss_grad(torch.as_tensor(X, device="cuda"), y, w)
+    lref, gref = orc.mlp_loss_grad(p.astype(np.float64), X.astype(np.float64), y, w.astype(np.float64),
+                                   bf16=True)
+    rel = np.linalg.norm(g - gref) / np.linalg.norm(gref)
+    print(f"loss_grad rows={rows}: loss {loss:.6f} vs {lref:.6f}, grad rel err {rel:.2e}")
+    assert abs(loss - lref) <= 1e-3 * max(1.0, abs(lref))
+    assert rel <= 2e-2
+    # each parameter block separately (a transposed operand would fail one of them)
+    off = np.cumsum([0, 192 * 64, 64, 64 * 64, 64, 64 * 3, 3])
+    for a, b in zip(off[:-1], off[1:]):
+        assert np.linalg.norm(g[a:b] - gref[a:b]) <= 3e-2 * np.linalg.norm(gref[a:b]) + 1e-6, (a, b)
+
+
+def test_mlp_adam_step(torch_mod):
+    from paper_2012_04385_amd.mrfv import MLP
+    torch = torch_mod
+    m = MLP(max_rows=64)
+    p = _params(m.nparams, 3)
+    m.set_params(p)
+    rng = np.random.default_rng(4)
+    X = torch.as_tensor(rng.normal(size=(64, 192)).astype(np.float32), device="cuda")
+    y = rng.integers(0, 3, size=64)
+    w = np.ones(3, dtype=np.float32)
+    mom = np.zeros_like(p, dtype=np.float64)
+    vel = np.zeros_like(p, dtype=np.float64)
+    cur = p.astype(np.float64)
+    lr, b1, b2, eps = 1e-3, 0.9, 0.999, 1e-8
+    for t in range(1, 4):
+        _, g = m.loss_grad(X, y, w)
+        m.adam_step(lr, b1, b2, eps)
+        mom = b1 * mom + (1 - b1) * g
+        vel = b2 * vel + (1 - b2) * g.astype(np.float64) ** 2
+        cur = cur - lr * (mom / (1 - b1 ** t)) / (np.sqrt(vel / (1 - b2 ** t)) + eps)
+        got = m.get_params()
+        assert np.abs(got - cur).max() <= 1e-6, t
+        cur = got.astype(np.float64)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_features_vs_oracle(orc, torch_mod, dtype):
+    from paper_2012_04385_amd.mrfv import Solver, solver_features
+    pb = W.blast_mr3(steps=2)
+    g = Solver([pb], dtype=dtype, batched=1 if dtype == "f32" else 0).init()
+    g.step()
+    g.fill_halos()
+    X, slots = solver_features(g)
+    X = X.cpu().numpy()
+    U = g.U.cpu().numpy()
+    lv = {int(r[0]): int(r[2]) for r in g.blocks()}
+    assert len(slots) == g.stats()[1] > 8
+    worst = 0.0
+    for r, s in enumerate(slots):
+        eps_l = pb.eps * 2.0 ** (-3 * (pb.lmax - lv[int(s)]))
+        ref = orc.features(U[s].astype(np.float64), pb.gamma, pb.B, pb.scale_rho,
+                           pb.scale_E * (pb.gamma - 1), eps_l)
+        d = np.abs(X[r] - ref) / np.maximum(1.0, np.abs(ref))
+        worst = max(worst, float(d.max()))
+    print(f"features {dtype}: {len(slots)} leaves, worst scaled diff {worst:.2e}")
+    assert worst <= 1e-5
+
+
+def _run(pb, mode, steps, mlp=None, record=False):
+    from paper_2012_04385_amd.mrfv import Solver, proposer_stats, set_proposer
+    g = Solver([pb], dtype="f32", batched=2).init()
+    if mode:
+        set_proposer(g, mlp, mode)
+    trees = []
+    for _ in range(steps):
+        g.step()
+        trees.append(frozenset(tuple(int(v) for v in r[2:6]) for r in g.blocks() if r[6] == 1))
+    g.check()
+    st = proposer_stats(g) if mode else None
+    return g, trees, st
+
+
+def test_proposer_modes_bitwise_identical(torch_mod):
+    """Off, persistence and network proposals (random and trained weights) give the same
+    trees and bitwise the same solution; the statistics account for every leaf."""
+    from paper_2012_04385_amd.mrfv import MLP
+    pb = W.blast_mr3(steps=8)
+    steps = 8
+    base, t0, _ = _run(pb, 0, steps)
+    ref = base.leaf_states()
+    m = MLP(max_rows=base.capacity)
+    m.init_params(seed=5)
+    for mode, mlp in ((2, None), (1, m)):
+        g, t, st = _run(pb, mode, steps, mlp)
+        assert t == t0, mode
+        s = g.leaf_states()
+        assert s.keys() == ref.keys()
+        for k in s:
+            assert np.array_equal(s[k], ref[k]), (mode, k)
+        assert st["steps"] == steps
+        print(f"mode {mode}: {st}")
+        assert 0 <= st["hits"] <= steps
+
+
+def test_proposer_trained_hits(torch_mod):
+    """Training on the solver's own flags lowers the loss; the trained proposal still
+    leaves the solution bitwise unchanged, and its hits are counted."""
+    from paper_2012_04385_amd.mrfv import MLP, Solver, collect_training_data
+    torch = torch_mod
+    pb = W.blast_mr3(steps=10)
+    g = Solver([pb], dtype="f32", batched=2).init()
+    X, y = collect_training_data(g, 10)
+    assert X.shape[0] == len(y) > 100
+    m = MLP(max_rows=4096)
+    m.init_params(seed=6)
+    cnt = np.bincount(y, minlength=3).astype(np.float64)
+    w = np.where(cnt > 0, cnt.sum() / np.maximum(cnt, 1) / 3.0, 0.0).astype(np.float32)
+    l0, _ = m.loss_grad(X[:4096], y[:4096], w)
+    m.train(X, y, epochs=30, lr=3e-3, batch=2048, seed=1, class_w=w)
+    l1, _ = m.loss_grad(X[:4096], y[:4096], w)
+    print(f"training: {X.shape[0]} samples, classes {cnt}, loss {l0:.4f} -> {l1:.4f}")
+    assert l1 < 0.7 * l0
+    base, t0, _ = _run(pb, 0, 10)
+    g1, t1, st = _run(pb, 1, 10, m)
+    assert t1 == t0
+    ref, s = base.leaf_states(), g1.leaf_states()
+    for k in s:
+        assert np.array_equal(s[k], ref[k]), k
+    print(f"trained proposer on its training run: {st}")
