@@ -183,6 +183,11 @@ int mrfv_coarsen_block(mrfv_ctx *ctx, int32_t instance, int32_t level, int32_t b
 int mrfv_enable_kernel_timing(mrfv_ctx *ctx, int32_t on);
 int mrfv_kernel_time(mrfv_ctx *ctx, int64_t *launches, double *total_ms, int64_t *cells);
 
+/* step_timing -- host clock of the adaptation phase of mrfv_step, summed over adaptive
+ * steps: out_host double[4] = (steps, ms waiting for the judged flags, ms committing the
+ * tree and uploading its tables (or adopting staged ones), ms predicting new children). */
+int mrfv_step_timing(mrfv_ctx *ctx, double *out_host);
+
 /* Morton ids with a headbit (Sec. "Modular block-based MR algorithm"): 3-bit groups per
  * level, finest group least significant, x = bit 0 of each group; shadow = number of
  * groups above level 0.  Neighbour along axis d in direction dir (+1/-1); *wrapped = 1

@@ -99,7 +99,7 @@ WorkList wlist(const mrfv_ctx *ctx, int which, int grid_cap = 2048) {
         w.desc = ctx->d_desc + 2 * which;
         // bound: the most blocks the list can ever hold (per level: every instance full)
         int64_t bound = ctx->cfg.slot_capacity;
-        if (which >= desc_lvl(0)) bound = std::min<int64_t>(bound, ctx->lvl_bound[(which - desc_lvl(0)) / 3]);
+        if (which >= desc_lvl(0)) bound = std::min<int64_t>(bound, ctx->lvl_bound[(which - desc_lvl(0)) / DESC_PER_LEVEL]);
         w.grid = (int)std::min<int64_t>(bound, grid_cap);
     } else {
         const std::vector<int32_t> &d = ctx->lists.desc;
@@ -124,12 +124,23 @@ int do_project(mrfv_ctx *ctx, T *U) {
     return MRFV_OK;
 }
 
-// leaf_faces = 1 inside a stage: leaves get only the face layers the flux reads.
+// Halo fill, levels coarse to fine (a prediction reads the parent's filled halo).
+//   FILL_ALL: all 26 regions of every block (details, refinement);
+//   FILL_FACES: non-leaf blocks complete, leaves the face layers the flux reads (plain
+//   stages);
+//   FILL_MISSING_FACES: non-leaf blocks complete, leaves only faces without a same-level
+//   neighbour (fused stages read same-level neighbours in place).
 template <typename T>
-int do_fill(mrfv_ctx *ctx, T *U, int max_level, int leaf_faces = 0) {
-    for (int l = 0; l <= std::min(max_level, levels_to_cover(ctx)); ++l)
-        HIP_OK(launch_fill_halos<T>(U, wlist(ctx, desc_lvl(l), 1024), ctx->tb, leaf_faces,
-                                    ctx->stream));
+int do_fill(mrfv_ctx *ctx, T *U, int max_level, FillMode mode = FILL_ALL) {
+    for (int l = 0; l <= std::min(max_level, levels_to_cover(ctx)); ++l) {
+        if (mode == FILL_ALL) {
+            HIP_OK(launch_fill_halos<T>(U, wlist(ctx, desc_lvl(l), 1024), ctx->tb, FILL_ALL, ctx->stream));
+        } else {
+            HIP_OK(launch_fill_halos<T>(U, wlist(ctx, desc_par(l), 1024), ctx->tb, FILL_ALL, ctx->stream));
+            const int which = mode == FILL_FACES ? desc_leaf(l) : desc_jleaf(l);
+            HIP_OK(launch_fill_halos<T>(U, wlist(ctx, which, 1024), ctx->tb, mode, ctx->stream));
+        }
+    }
     return MRFV_OK;
 }
 
@@ -210,20 +221,21 @@ int do_update(mrfv_ctx *ctx, int stage, const double *dt, T *U, T *U0, const T *
 
 // One stage of the batched path: fused rhs + update over all leaves, then the jump
 // correction on the updated state.
-int do_stage_fused(mrfv_ctx *ctx, int stage, const double *dt, float *U, float *U0) {
+int do_stage_fused(mrfv_ctx *ctx, int stage, const double *dt, const float *Uin, float *Uout,
+                   float *U0) {
     const HostLists &L = ctx->lists;
     float *FF = (float *)ctx->d_FF;
     hipEvent_t ev{};
     timing_begin(ctx, &ev);
     // the fused kernel has no grid-stride loop: its grid must cover every possible leaf
-    HIP_OK(launch_rhs_update_f32(stage, dt, U, U0, wlist(ctx, DESC_LEAVES, 1 << 30), ctx->tb,
+    HIP_OK(launch_rhs_update_f32(stage, dt, Uin, Uout, U0, wlist(ctx, DESC_LEAVES, 1 << 30), ctx->tb,
                                  ctx->d_inst, FF, ctx->d_err, ctx->stream));
     timing_end(ctx, ev, (int64_t)L.all_leaves_cnt * CELLS_I);
     // a captured graph must not depend on the current tree: always include the correction
     if (ctx->has_jumps || ctx->capturing) {
         for (int l = levels_to_cover(ctx) - 1; l >= 0; --l)
             HIP_OK(launch_ff_restrict<float>(FF, wlist(ctx, desc_par(l)), ctx->tb, ctx->stream));
-        HIP_OK(launch_reflux_update<float>(stage, dt, U, FF, wlist(ctx, DESC_LEAVES), ctx->tb,
+        HIP_OK(launch_reflux_update<float>(stage, dt, Uout, FF, wlist(ctx, DESC_LEAVES), ctx->tb,
                                            ctx->d_inst, ctx->stream));
     }
     return MRFV_OK;
@@ -435,15 +447,23 @@ template <typename T>
 int do_stages(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt) {
     HIP_OK(launch_cfl<T>(U, wlist(ctx, DESC_LEAVES), ctx->tb, ctx->d_inst, (int)ctx->inst.size(),
                          ctx->d_blockred, dt, ctx->stream));
+    if (ctx->cfg.batched && sizeof(T) == 4) {
+        // fused stages, out of place: U -> W -> U -> W, then the leaves' interiors back
+        float *X = (float *)U, *W = (float *)ctx->d_W;
+        for (int s = 0; s < 3; ++s) {
+            float *in = (s & 1) ? W : X, *out = (s & 1) ? X : W;
+            CALL(do_project<float>(ctx, in));
+            CALL(do_fill<float>(ctx, in, 1 << 20, FILL_MISSING_FACES));
+            CALL(do_stage_fused(ctx, s, dt, in, out, (float *)U0));
+        }
+        HIP_OK(launch_copy_interiors<float>(W, X, wlist(ctx, DESC_LEAVES, 4096), ctx->stream));
+        return MRFV_OK;
+    }
     for (int s = 0; s < 3; ++s) {
         CALL(do_project<T>(ctx, U));
-        CALL(do_fill<T>(ctx, U, 1 << 20, 1));
-        if (ctx->cfg.batched && sizeof(T) == 4) {
-            CALL(do_stage_fused(ctx, s, dt, (float *)U, (float *)U0));
-        } else {
-            CALL(do_rhs<T>(ctx, U, Lb));
-            CALL(do_update<T>(ctx, s, dt, U, U0, Lb));
-        }
+        CALL(do_fill<T>(ctx, U, 1 << 20, FILL_FACES));
+        CALL(do_rhs<T>(ctx, U, Lb));
+        CALL(do_update<T>(ctx, s, dt, U, U0, Lb));
     }
     return MRFV_OK;
 }
@@ -526,7 +546,13 @@ int do_step(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt) {
         ctx->p_build_ms +=
             std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     }
+    using clk = std::chrono::steady_clock;
+    auto ms = [](clk::time_point a, clk::time_point b) {
+        return std::chrono::duration<double, std::milli>(b - a).count();
+    };
+    const auto w0 = clk::now();
     HIP_OK(hipStreamSynchronize(ctx->stream));
+    const auto w1 = clk::now();
     if (*ctx->h_err) return fail(ctx, MRFV_ENONPHYS, "non-physical state (rho<=0, p+B<=0 or NaN)");
     std::vector<int32_t> fresh;
     if (prop) {
@@ -548,7 +574,13 @@ int do_step(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt) {
     } else {
         CALL(commit(ctx, ctx->h_flags, fresh));
     }
+    const auto w2 = clk::now();
     CALL(do_predict<T>(ctx, U, fresh.data(), (int)fresh.size()));
+    const auto w3 = clk::now();
+    ctx->h_wait_ms += ms(w0, w1);
+    ctx->h_commit_ms += ms(w1, w2);
+    ctx->h_predict_ms += ms(w2, w3);
+    ctx->h_steps++;
     return MRFV_OK;
 }
 
@@ -581,7 +613,7 @@ int mrfv_create(mrfv_ctx **out, const mrfv_config *cfg, const mrfv_instance *ins
     }
     ctx->stream = (hipStream_t)hip_stream;
     const size_t cap = cfg->slot_capacity, es = elem_size(ctx);
-    ctx->lists_cap = 2 * cfg->n_instances + 6 * cfg->slot_capacity + 16;
+    ctx->lists_cap = 2 * cfg->n_instances + 8 * cfg->slot_capacity + 16;
     ctx->prim_batch = 128;
     for (int i = 0; i < cfg->n_instances; ++i) ctx->lmax_all = std::max(ctx->lmax_all, (int)inst[i].lmax);
     ctx->lvl_bound.assign(MAX_LEVELS, 0);
@@ -603,7 +635,11 @@ int mrfv_create(mrfv_ctx **out, const mrfv_config *cfg, const mrfv_instance *ins
     }
     ALLOC(ctx->d_inst, sizeof(InstDev) * id.size());
     ALLOC(ctx->d_err, sizeof(int32_t));
-    if (!(cfg->batched && cfg->dtype == MRFV_F32)) ALLOC(ctx->d_D, cap * 3 * 5 * CELLS_I * es);
+    if (!(cfg->batched && cfg->dtype == MRFV_F32)) {
+        ALLOC(ctx->d_D, cap * 3 * 5 * CELLS_I * es);
+    } else {
+        ALLOC(ctx->d_W, cap * 5 * CELLS_P * es);   // second state buffer of the fused stages
+    }
     ALLOC(ctx->d_desc, 2 * N_DESC * sizeof(int32_t));
     if (hipHostMalloc((void **)&ctx->h_flags, cap, 0) != hipSuccess ||
         hipHostMalloc((void **)&ctx->h_err, sizeof(int32_t), 0) != hipSuccess) {
@@ -653,7 +689,7 @@ int mrfv_destroy(mrfv_ctx *ctx) {
         for (void *p : pp)
             if (p) hipFree(p);
     }
-    void *ptrs[] = {ctx->d_inst, ctx->d_err, ctx->d_D, ctx->d_FF, ctx->d_blockred, ctx->d_det,
+    void *ptrs[] = {ctx->d_inst, ctx->d_err, ctx->d_D, ctx->d_W, ctx->d_FF, ctx->d_blockred, ctx->d_det,
                     ctx->d_flags, ctx->d_slots, ctx->d_prim, ctx->tb.meta, ctx->tb.child,
                     ctx->tb.nbr, ctx->tb.lists, ctx->d_desc};
     for (void *p : ptrs)
@@ -890,6 +926,15 @@ int mrfv_set_proposer(mrfv_ctx *ctx, mrfv_mlp *mlp, int32_t mode) {
     }
     ctx->mlp = mlp;
     ctx->prop_mode = mode;
+    return MRFV_OK;
+}
+
+int mrfv_step_timing(mrfv_ctx *ctx, double *out) {
+    if (!ctx || !out) return MRFV_EINVAL;
+    out[0] = (double)ctx->h_steps;
+    out[1] = ctx->h_wait_ms;
+    out[2] = ctx->h_commit_ms;
+    out[3] = ctx->h_predict_ms;
     return MRFV_OK;
 }
 

@@ -84,59 +84,154 @@ __global__ __launch_bounds__(TPB) void k_prim2cons(const double *__restrict__ pr
                               0.5 * rho * (u * u + v * v + w * w));
 }
 
-// One thread per padded cell; interior cells return immediately.
-// leaf_faces: leaves only need the three face layers the flux stencil reads; their edge
-// and corner regions and the outermost layer are skipped (nothing reads them during a
-// stage: prediction reads parents, copies read interiors).
+// Halo regions.  Region (rx, ry, rz) in {-1, 0, 1}^3 \ {0} covers padded indices
+// [0, 4) / [4, 20) / [20, 24) along each axis; in the face modes only the 3 layers the
+// flux stencils read ([1, 4) and [20, 23)).  One workgroup per (block, region): a region
+// is either copied from the same-level neighbour's interior, clamped (zero-gradient
+// boundary) or predicted from the parent, never a mix.
+struct Region {
+    int r[3];       // region direction after zero-gradient clamping (0 on clamped axes)
+    int lo[3], n[3];
+    int clamp[3];   // -1, or the padded index every cell of the axis copies/predicts from
+};
+
+__device__ __forceinline__ Region make_region(int mode, int ridx, int zg) {
+    Region g;
+    int r[3];
+    if (mode == FILL_ALL) {
+        const int reg = ridx < 13 ? ridx : ridx + 1;
+        r[0] = reg % 3 - 1;
+        r[1] = (reg / 3) % 3 - 1;
+        r[2] = reg / 9 - 1;
+    } else {
+        r[0] = r[1] = r[2] = 0;
+        r[ridx >> 1] = (ridx & 1) ? 1 : -1;
+    }
+    const bool faces = mode != FILL_ALL;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        g.lo[a] = r[a] < 0 ? (faces ? 1 : 0) : (r[a] == 0 ? HW : HW + NI);
+        g.n[a] = r[a] == 0 ? NI : (faces ? 3 : HW);
+        g.clamp[a] = -1;
+        g.r[a] = r[a];
+        if (r[a] < 0 && (zg & (1 << (2 * a)))) { g.clamp[a] = HW; g.r[a] = 0; }
+        if (r[a] > 0 && (zg & (1 << (2 * a + 1)))) { g.clamp[a] = HW + NI - 1; g.r[a] = 0; }
+    }
+    return g;
+}
+
+// Parent padded index of child padded index c in octant half o.
+__device__ __forceinline__ int parent_of(int c, int o) { return o * (NI / 2) + ((c - HW) >> 1) + HW; }
+
+// LDS of the separable prediction, sized for the worst of the 26 region shapes: parent
+// region (a region spans 16 child cells = 12 parent cells on at most two axes and 2 + 4
+// on the others: 12 x 12 x 6), x pass (16 x 12 x 6, or 4 x 12 x 12 for x-normal
+// regions), y pass (16 x 16 x 6 for z-normal regions, else 16 x 4 x 12).
+constexpr int PR_A = 6 * 12 * 12, PR_X = 16 * 12 * 6, PR_Y = 16 * 16 * 6;
+
 template <typename T>
 __global__ __launch_bounds__(TPB) void k_fill_halos(T *__restrict__ U, WorkList wl,
                                                     const BlockMeta *__restrict__ meta,
-                                                    const int32_t *__restrict__ nbr,
-                                                    int leaf_faces) {
-    const int cell = blockIdx.y * TPB + threadIdx.x;
-    if (cell >= CELLS_P) return;
-    const int c0[3] = {cell % NP, (cell / NP) % NP, cell / (NP * NP)};
-    const bool interior = c0[0] >= HW && c0[0] < HW + NI && c0[1] >= HW && c0[1] < HW + NI &&
-                          c0[2] >= HW && c0[2] < HW + NI;
-    if (interior) return;
-    int nout = 0;
-    bool outer = false;
+                                                    const int32_t *__restrict__ nbr, int mode) {
+    __shared__ T A[PR_A];
+    __shared__ T X[PR_X];
+    __shared__ T Y[PR_Y];
+    const int nb = wl.count();
+    const int tid = threadIdx.x;
+    for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+        const int slot = wl.at(b);
+        const BlockMeta m = meta[slot];
+        const Region g = make_region(mode, blockIdx.y, m.zg);
+        const bool clamped = g.clamp[0] >= 0 || g.clamp[1] >= 0 || g.clamp[2] >= 0;
+        const bool own = g.r[0] == 0 && g.r[1] == 0 && g.r[2] == 0;
+        const int src = own ? slot : nbr[(size_t)slot * 27 + (g.r[2] + 1) * 9 + (g.r[1] + 1) * 3 + (g.r[0] + 1)];
+        if (mode == FILL_MISSING_FACES && src >= 0 && !clamped) continue;   // read in place
+        T *dst = U + (size_t)slot * 5 * CELLS_P;
+        const int ncell = g.n[0] * g.n[1] * g.n[2];
+        if (src >= 0) {
+            const T *sb = U + (size_t)src * 5 * CELLS_P;
+            for (int t = tid; t < 5 * ncell; t += TPB) {
+                const int q = t / ncell, e = t - q * ncell;
+                const int i = g.lo[0] + e % g.n[0], j = g.lo[1] + (e / g.n[0]) % g.n[1],
+                          k = g.lo[2] + e / (g.n[0] * g.n[1]);
+                const int si = g.clamp[0] >= 0 ? g.clamp[0] : i - NI * g.r[0];
+                const int sj = g.clamp[1] >= 0 ? g.clamp[1] : j - NI * g.r[1];
+                const int sk = g.clamp[2] >= 0 ? g.clamp[2] : k - NI * g.r[2];
+                dst[pidx(q, k, j, i)] = sb[pidx(q, sk, sj, si)];
+            }
+            continue;
+        }
+        if (m.parent < 0) continue;   // level 0 is complete: does not happen
+        // prediction from the parent, separably through LDS (x, then y, then z: the
+        // operation order of predict_cell)
+        const int o[3] = {m.bx & 1, m.by & 1, m.bz & 1};
+        int me[3], c0[3], p0[3], np[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        nout += (c0[a] < HW || c0[a] >= HW + NI) ? 1 : 0;
-        outer = outer || c0[a] == 0 || c0[a] == NP - 1;
+        for (int a = 0; a < 3; ++a) {
+            me[a] = g.clamp[a] >= 0 ? 1 : g.n[a];                  // evaluation points
+            c0[a] = g.clamp[a] >= 0 ? g.clamp[a] : g.lo[a];        // first child index
+            p0[a] = parent_of(c0[a], o[a]) - 2;
+            np[a] = parent_of(c0[a] + me[a] - 1, o[a]) + 2 - p0[a] + 1;
+        }
+        const T *pu = U + (size_t)m.parent * 5 * CELLS_P;
+        for (int q = 0; q < 5; ++q) {
+            const int na = np[0] * np[1] * np[2];
+            for (int t = tid; t < na; t += TPB) {
+                const int ii = t % np[0], jj = (t / np[0]) % np[1], kk = t / (np[0] * np[1]);
+                A[t] = pu[pidx(q, p0[2] + kk, p0[1] + jj, p0[0] + ii)];
+            }
+            __syncthreads();
+            const int nx = np[2] * np[1] * me[0];
+            for (int t = tid; t < nx; t += TPB) {
+                const int ex = t % me[0], jj = (t / me[0]) % np[1], kk = t / (me[0] * np[1]);
+                const int c = c0[0] + ex;
+                const int I = parent_of(c, o[0]) - p0[0];
+                const T *row = A + (kk * np[1] + jj) * np[0] + I;
+                const T sx = ((c - HW) & 1) ? (T)-1 : (T)1;
+                X[t] = pred1<T>(row[-2], row[-1], row[0], row[1], row[2], sx);
+            }
+            __syncthreads();
+            const int ny = np[2] * me[1] * me[0];
+            for (int t = tid; t < ny; t += TPB) {
+                const int ex = t % me[0], ey = (t / me[0]) % me[1], kk = t / (me[0] * me[1]);
+                const int c = c0[1] + ey;
+                const int J = parent_of(c, o[1]) - p0[1];
+                const T *col = X + (kk * np[1] + J) * me[0] + ex;
+                const int st = me[0];
+                const T sy = ((c - HW) & 1) ? (T)-1 : (T)1;
+                Y[t] = pred1<T>(col[-2 * st], col[-st], col[0], col[st], col[2 * st], sy);
+            }
+            __syncthreads();
+            for (int t = tid; t < ncell; t += TPB) {
+                const int dx = t % g.n[0], dy = (t / g.n[0]) % g.n[1], dz = t / (g.n[0] * g.n[1]);
+                const int ex = g.clamp[0] >= 0 ? 0 : dx, ey = g.clamp[1] >= 0 ? 0 : dy,
+                          ez = g.clamp[2] >= 0 ? 0 : dz;
+                const int c = c0[2] + ez;
+                const int K = parent_of(c, o[2]) - p0[2];
+                const int st = me[0] * me[1];
+                const T *col = Y + (K * me[1] + ey) * me[0] + ex;
+                const T sz = ((c - HW) & 1) ? (T)-1 : (T)1;
+                dst[pidx(q, g.lo[2] + dz, g.lo[1] + dy, g.lo[0] + dx)] =
+                    pred1<T>(col[-2 * st], col[-st], col[0], col[st], col[2 * st], sz);
+            }
+            __syncthreads();
+        }
     }
-    const bool face_cell = nout == 1 && !outer;
+}
+
+// Interiors of the listed blocks: dst <- src (the fused stages' ping-pong buffer).
+template <typename T>
+__global__ __launch_bounds__(TPB) void k_copy_interiors(const T *__restrict__ src, T *__restrict__ dst,
+                                                        WorkList wl) {
     const int nb = wl.count();
     for (int b = blockIdx.x; b < nb; b += gridDim.x) {
-    const int slot = wl.at(b);
-    const BlockMeta m = meta[slot];
-    if (leaf_faces && m.leaf && !face_cell) continue;
-    int c[3] = {c0[0], c0[1], c0[2]};
-    int r[3];
+        const size_t base = (size_t)wl.at(b) * 5 * CELLS_P;
+        const int k = blockIdx.y, j = threadIdx.x >> 4, i = threadIdx.x & 15;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        r[a] = c[a] < HW ? -1 : (c[a] >= HW + NI ? 1 : 0);
-        // zero-gradient boundary: clamp to the nearest interior cell of this block
-        if (r[a] < 0 && (m.zg & (1 << (2 * a)))) { c[a] = HW; r[a] = 0; }
-        if (r[a] > 0 && (m.zg & (1 << (2 * a + 1)))) { c[a] = HW + NI - 1; r[a] = 0; }
-    }
-    const int region = (r[2] + 1) * 9 + (r[1] + 1) * 3 + (r[0] + 1);
-    const int src = (region == 13) ? slot : nbr[(size_t)slot * 27 + region];
-    T *dst = U + (size_t)slot * 5 * CELLS_P;
-    const int o = pidx(0, (cell / (NP * NP)), (cell / NP) % NP, cell % NP);
-    if (src >= 0) {
-        const T *s = U + (size_t)src * 5 * CELLS_P;
-        const int so = pidx(0, c[2] - NI * r[2], c[1] - NI * r[1], c[0] - NI * r[0]);
-#pragma unroll
-        for (int q = 0; q < 5; ++q) dst[o + q * CELLS_P] = s[so + q * CELLS_P];
-    } else if (m.parent >= 0) {   // always true: level 0 is complete
-        const T *pu = U + (size_t)m.parent * 5 * CELLS_P;
-#pragma unroll 1
-        for (int q = 0; q < 5; ++q)
-            dst[o + q * CELLS_P] = predict_cell<T, T>(pu + q * CELLS_P, m.bx & 1, m.by & 1,
-                                                      m.bz & 1, c[0], c[1], c[2]);
-    }
+        for (int q = 0; q < 5; ++q) {
+            const int o = pidx(q, k + HW, j + HW, i + HW);
+            dst[base + o] = src[base + o];
+        }
     }
 }
 
@@ -418,11 +513,18 @@ hipError_t launch_prim2cons(const double *prim, const int32_t *slots, int n, T *
 }
 
 template <typename T>
-hipError_t launch_fill_halos(T *U, const WorkList &wl, const DevTables &tb, int leaf_faces,
+hipError_t launch_fill_halos(T *U, const WorkList &wl, const DevTables &tb, FillMode mode,
                              hipStream_t st) {
     if (wl.grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fill_halos<T>, grid2(wl.grid, (CELLS_P + TPB - 1) / TPB), dim3(TPB), 0,
-                       st, U, wl, tb.meta, tb.nbr, leaf_faces);
+    hipLaunchKernelGGL(k_fill_halos<T>, grid2(wl.grid, mode == FILL_ALL ? 26 : 6), dim3(TPB), 0,
+                       st, U, wl, tb.meta, tb.nbr, (int)mode);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_copy_interiors(const T *src, T *dst, const WorkList &wl, hipStream_t st) {
+    if (wl.grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy_interiors<T>, grid2(wl.grid, NI), dim3(TPB), 0, st, src, dst, wl);
     return hipGetLastError();
 }
 
@@ -484,8 +586,10 @@ hipError_t launch_totals(const T *U, const WorkList &leaves, const DevTables &tb
 #define MRFV_INST(T)                                                                        \
     template hipError_t launch_prim2cons<T>(const double *, const int32_t *, int, T *,     \
                                             const BlockMeta *, const InstDev *, hipStream_t); \
-    template hipError_t launch_fill_halos<T>(T *, const WorkList &, const DevTables &, int,  \
-                                             hipStream_t);                                  \
+    template hipError_t launch_fill_halos<T>(T *, const WorkList &, const DevTables &,       \
+                                             FillMode, hipStream_t);                        \
+    template hipError_t launch_copy_interiors<T>(const T *, T *, const WorkList &,         \
+                                                 hipStream_t);                              \
     template hipError_t launch_project<T>(T *, const WorkList &, const DevTables &,         \
                                           hipStream_t);                                     \
     template hipError_t launch_predict<T>(T *, const int32_t *, int, const DevTables &,    \

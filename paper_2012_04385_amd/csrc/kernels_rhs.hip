@@ -437,9 +437,10 @@ struct LdsSink {
 // every x-, y- and z-face flux the group's cells need is computed once, one face per
 // thread (coalesced, L1-resident six-cell stencils; all axes share one code path), and
 // staged in LDS.  Each thread then owns one (x, y) column: it forms
-// D = ((Dx + Dy) + Dz) for the group's cells and applies the SSP-RK3 stage update in
-// place.  The update of a group is deferred until the next group's faces are done,
-// because z-faces up to two and a half planes away still read the old values.
+// D = ((Dx + Dy) + Dz) for the group's cells and writes the SSP-RK3 stage result to the
+// other state buffer.  Stencil cells outside the block are read from the same-level
+// neighbour's interior where one exists (no halo copy), else from the own halo, which
+// the fill has predicted from the parent or clamped at a zero-gradient boundary.
 constexpr int GP = 2;                         // z-planes per group
 constexpr int TPB_F = 320;                    // 1600 faces per group = 5 rounds
 constexpr int NFX = GP * NI * (NI + 1);       // x-faces per group (544)
@@ -456,16 +457,21 @@ __device__ __forceinline__ void load_cell_rt(const T *__restrict__ u, int idx, i
 }
 
 // Face flux along axis d for the stencil starting at padded index base (six cells at
-// base + j*stride); the result is returned in physical component order.
+// base + j*stride, padded coordinate pos0 + j along d); cells below / above the interior
+// come from lo / hi, which are the neighbour's block shifted by -+16 cells along d (or
+// the own block).  The result is returned in physical component order.
 template <typename T>
-__device__ __forceinline__ void face_flux_at(const T *__restrict__ ub, int d, int base,
+__device__ __forceinline__ void face_flux_at(const T *__restrict__ ub, const T *__restrict__ lo,
+                                             const T *__restrict__ hi, int d, int base, int pos0,
                                              const Gas<T> &G, T Fp[5]) {
     const int stride = d == 0 ? 1 : (d == 1 ? NP : NP * NP);
     const int n1 = d + 1, t1 = d == 0 ? 2 : (d == 1 ? 3 : 1), t2 = d == 0 ? 3 : (d == 1 ? 1 : 2);
     CellState<T> w[6];
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
-        load_cell_rt(ub, base + j * stride, n1, t1, t2, w[j]);
+        const int pos = pos0 + j;
+        const T *src = pos < HW ? lo : (pos >= HW + NI ? hi : ub);
+        load_cell_rt(src, base + j * stride, n1, t1, t2, w[j]);
         derive_state(G, w[j]);
     }
     T F[5];
@@ -479,8 +485,10 @@ __device__ __forceinline__ void face_flux_at(const T *__restrict__ ub, int d, in
 
 template <typename T>
 __global__ __launch_bounds__(TPB_F) void k_rhs_update(int stage, const double *__restrict__ dt,
-                                                      T *U, T *U0, WorkList wl,
+                                                      const T *__restrict__ Uin, T *__restrict__ Uout,
+                                                      T *U0, WorkList wl,
                                                       const BlockMeta *__restrict__ meta,
+                                                      const int32_t *__restrict__ nbr,
                                                       const InstDev *__restrict__ inst, T *FF,
                                                       int32_t *err) {
     __shared__ T Fx[GP][NI][NI + 1][5];   // [plane][y][face x][q]
@@ -494,7 +502,22 @@ __global__ __launch_bounds__(TPB_F) void k_rhs_update(int stage, const double *_
     const BlockMeta mt = meta[slot];
     const InstDev P = inst[mt.inst];
     const Gas<T> G = gas_of<T>(P);
-    T *ub = U + (size_t)slot * 5 * CELLS_P;
+    const T *ub = Uin + (size_t)slot * 5 * CELLS_P;
+    T *ob = Uout + (size_t)slot * 5 * CELLS_P;
+    // per face side: the same-level neighbour shifted so that own padded indices address
+    // its interior, or the own block (halo filled) at jumps and zero-gradient boundaries
+    const T *nlo[3], *nhi[3];
+    {
+        const int freg[6] = {12, 14, 10, 16, 4, 22};
+        const int strd[3] = {1, NP, NP * NP};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int sl = (mt.zg >> (2 * a)) & 1 ? -1 : nbr[(size_t)slot * 27 + freg[2 * a]];
+            const int sh = (mt.zg >> (2 * a + 1)) & 1 ? -1 : nbr[(size_t)slot * 27 + freg[2 * a + 1]];
+            nlo[a] = sl >= 0 ? Uin + (size_t)sl * 5 * CELLS_P + NI * strd[a] : ub;
+            nhi[a] = sh >= 0 ? Uin + (size_t)sh * 5 * CELLS_P - NI * strd[a] : ub;
+        }
+    }
     T *ffs = FF + (size_t)slot * 6 * 5 * FACE;
     T *u0b = U0 + (size_t)slot * 5 * CELLS_I;
     const T inv_dx = (T)(1.0 / ldexp(P.dx0, -mt.level));
@@ -503,7 +526,6 @@ __global__ __launch_bounds__(TPB_F) void k_rhs_update(int stage, const double *_
     const int tid = threadIdx.x;
     const bool owner = tid < FACE;              // column owners (x = tid & 15, y = tid >> 4)
     const int cx = tid & 15, cy = tid >> 4;
-    T Dpend[GP][5];                             // D of the previous group, awaiting update
     bool ok = true;
 
     auto update_group = [&](int k0, T D[GP][5]) {
@@ -524,7 +546,7 @@ __global__ __launch_bounds__(TPB_F) void k_rhs_update(int stage, const double *_
                     u0 = u0b[q * CELLS_I + c];
                 }
                 un[q] = u0 + a * ((us - u0) + dtt * (-D[p][q] * inv_dx));
-                ub[o + q * CELLS_P] = un[q];
+                ob[o + q * CELLS_P] = un[q];
             }
             ok = ok && physical_state(un, G);
         }
@@ -540,7 +562,7 @@ __global__ __launch_bounds__(TPB_F) void k_rhs_update(int stage, const double *_
             if (t < NFX) {                      // x-faces: (plane p, row y, face f)
                 const int f = t % (NI + 1), y = (t / (NI + 1)) % NI, p = t / ((NI + 1) * NI);
                 const int base = ((k0 + p + HW) * NP + y + HW) * NP + f + 1;
-                face_flux_at(ub, 0, base, G, F);
+                face_flux_at(ub, nlo[0], nhi[0], 0, base, f + 1, G, F);
 #pragma unroll
                 for (int q = 0; q < 5; ++q) Fx[p][y][f][q] = F[q];
                 if (f == 0 || f == NI) {
@@ -551,7 +573,7 @@ __global__ __launch_bounds__(TPB_F) void k_rhs_update(int stage, const double *_
                 const int u = t - NFX;
                 const int x = u % NI, f = (u / NI) % (NI + 1), p = u / (NI * (NI + 1));
                 const int base = ((k0 + p + HW) * NP + f + 1) * NP + x + HW;
-                face_flux_at(ub, 1, base, G, F);
+                face_flux_at(ub, nlo[1], nhi[1], 1, base, f + 1, G, F);
 #pragma unroll
                 for (int q = 0; q < 5; ++q) Fy[p][f][x][q] = F[q];
                 if (f == 0 || f == NI) {
@@ -563,7 +585,7 @@ __global__ __launch_bounds__(TPB_F) void k_rhs_update(int stage, const double *_
                 const int x = u % NI, y = (u / NI) % NI, j = u / NFZ + first_z;
                 const int kf = k0 + j;          // face between interior planes kf-1 and kf
                 const int base = ((kf + 1) * NP + y + HW) * NP + x + HW;   // padded z = kf+1 .. kf+6
-                face_flux_at(ub, 2, base, G, F);
+                face_flux_at(ub, nlo[2], nhi[2], 2, base, kf + 1, G, F);
 #pragma unroll
                 for (int q = 0; q < 5; ++q) Fz[j][y][x][q] = F[q];
                 if (kf == 0 || kf == NI) {
@@ -574,7 +596,7 @@ __global__ __launch_bounds__(TPB_F) void k_rhs_update(int stage, const double *_
         }
         __syncthreads();
         if (owner) {
-            if (g > 0) update_group(k0 - GP, Dpend);
+            T D[GP][5];
 #pragma unroll
             for (int p = 0; p < GP; ++p)
 #pragma unroll
@@ -582,8 +604,9 @@ __global__ __launch_bounds__(TPB_F) void k_rhs_update(int stage, const double *_
                     const T dxq = Fx[p][cy][cx + 1][q] - Fx[p][cy][cx][q];
                     const T dyq = Fy[p][cy + 1][cx][q] - Fy[p][cy][cx][q];
                     const T dzq = Fz[p + 1][cy][cx][q] - Fz[p][cy][cx][q];
-                    Dpend[p][q] = (dxq + dyq) + dzq;
+                    D[p][q] = (dxq + dyq) + dzq;
                 }
+            update_group(k0, D);
         }
         __syncthreads();
         // the last face plane of this group is the first one of the next
@@ -593,7 +616,6 @@ __global__ __launch_bounds__(TPB_F) void k_rhs_update(int stage, const double *_
         }
         __syncthreads();
     }
-    if (owner) update_group(NI - GP, Dpend);
     if (!ok) atomicOr(err, 1);
 }
 
@@ -677,12 +699,13 @@ hipError_t launch_update(int stage, const double *dt, T *U, T *U0, const T *L, c
     return hipGetLastError();
 }
 
-hipError_t launch_rhs_update_f32(int stage, const double *dt, float *U, float *U0,
-                                 const WorkList &wl, const DevTables &tb, const InstDev *inst,
-                                 float *FF, int32_t *err, hipStream_t st) {
+hipError_t launch_rhs_update_f32(int stage, const double *dt, const float *Uin, float *Uout,
+                                 float *U0, const WorkList &wl, const DevTables &tb,
+                                 const InstDev *inst, float *FF, int32_t *err, hipStream_t st) {
     if (wl.grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_rhs_update<float>, dim3(wl.grid), dim3(TPB_F), 0, st, stage, dt, U, U0, wl,
-                       tb.meta, inst, FF, err);
+    if (Uin == Uout) return hipErrorInvalidValue;   // neighbours' interiors are read
+    hipLaunchKernelGGL(k_rhs_update<float>, dim3(wl.grid), dim3(TPB_F), 0, st, stage, dt, Uin, Uout,
+                       U0, wl, tb.meta, tb.nbr, inst, FF, err);
     return hipGetLastError();
 }
 

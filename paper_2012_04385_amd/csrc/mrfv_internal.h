@@ -61,7 +61,7 @@ struct HostLists {
     std::vector<int32_t> data;
     int max_level = 0;
     // per level: all blocks, non-leaf blocks, leaves
-    std::vector<int32_t> lvl_off, lvl_cnt, par_off, par_cnt, leaf_off, leaf_cnt;
+    std::vector<int32_t> lvl_off, lvl_cnt, par_off, par_cnt, leaf_off, leaf_cnt, jleaf_off, jleaf_cnt;
     int32_t all_leaves_off = 0, all_leaves_cnt = 0;      // leaves of every level
     // descriptor table {offset, count} per list, mirrored on the device (graph launches)
     std::vector<int32_t> desc;
@@ -121,10 +121,19 @@ uint64_t morton_encode(int shadow, int level, int bx, int by, int bz);
 // Descriptor indices of the work lists (DevTables lists + the device descriptor table).
 constexpr int MAX_LEVELS = 13;
 constexpr int DESC_LEAVES = 0, DESC_ALL = 1, DESC_FINE = 2, DESC_SCRATCH = 3;
-constexpr int desc_lvl(int l) { return 4 + 3 * l; }
-constexpr int desc_par(int l) { return 5 + 3 * l; }
-constexpr int desc_leaf(int l) { return 6 + 3 * l; }
-constexpr int N_DESC = 4 + 3 * MAX_LEVELS;
+constexpr int DESC_PER_LEVEL = 4;
+constexpr int desc_lvl(int l) { return 4 + DESC_PER_LEVEL * l; }
+constexpr int desc_par(int l) { return 5 + DESC_PER_LEVEL * l; }
+constexpr int desc_leaf(int l) { return 6 + DESC_PER_LEVEL * l; }
+// leaves of level l with at least one face that has no same-level neighbour or lies on a
+// zero-gradient boundary: the only leaves whose halos a fused stage must fill
+constexpr int desc_jleaf(int l) { return 7 + DESC_PER_LEVEL * l; }
+constexpr int N_DESC = 4 + DESC_PER_LEVEL * MAX_LEVELS;
+
+// Halo fill modes: every one of the 26 halo regions; the 6 face regions (3 layers deep,
+// all the flux stencils read); only the face regions without a same-level neighbour
+// (the fused stage reads same-level neighbours' interiors directly).
+enum FillMode { FILL_ALL = 0, FILL_FACES = 1, FILL_MISSING_FACES = 2 };
 
 // --------------------------------------------------------------- kernel launchers ----
 // All launchers enqueue on `st` and return hipGetLastError().
@@ -132,8 +141,10 @@ template <typename T>
 hipError_t launch_prim2cons(const double *prim, const int32_t *slots, int n, T *U,
                             const BlockMeta *meta, const InstDev *inst, hipStream_t st);
 template <typename T>
-hipError_t launch_fill_halos(T *U, const WorkList &wl, const DevTables &tb, int leaf_faces,
+hipError_t launch_fill_halos(T *U, const WorkList &wl, const DevTables &tb, FillMode mode,
                              hipStream_t st);
+template <typename T>
+hipError_t launch_copy_interiors(const T *src, T *dst, const WorkList &wl, hipStream_t st);
 template <typename T>
 hipError_t launch_project(T *U, const WorkList &wl, const DevTables &tb, hipStream_t st);
 template <typename T>
@@ -168,8 +179,10 @@ template <typename T>
 hipError_t launch_update(int stage, const double *dt, T *U, T *U0, const T *L,
                          const WorkList &leaves, const DevTables &tb, const InstDev *inst,
                          int32_t *err, hipStream_t st);
-hipError_t launch_rhs_update_f32(int stage, const double *dt, float *U, float *U0,
-                                 const WorkList &leaves, const DevTables &tb,
+// Fused stage: reads the state from Uin (same-level neighbours' interiors directly, the
+// own halo elsewhere) and writes the new interior state to Uout != Uin.
+hipError_t launch_rhs_update_f32(int stage, const double *dt, const float *Uin, float *Uout,
+                                 float *U0, const WorkList &leaves, const DevTables &tb,
                                  const InstDev *inst, float *FF, int32_t *err, hipStream_t st);
 template <typename T>
 hipError_t launch_reflux_update(int stage, const double *dt, T *U, const T *FF,
@@ -198,6 +211,7 @@ struct mrfv_ctx {
     mrfv::DevTables tb;
     mrfv::InstDev *d_inst = nullptr;
     int32_t *d_err = nullptr;          // device error word
+    void *d_W = nullptr;               // second padded state buffer (fused FP32 stages)
     void *d_D = nullptr;               // flux differences [cap][3][5][16^3]
     void *d_FF = nullptr;              // boundary face fluxes [cap][6][5][16][16]
     double *d_blockred = nullptr;      // [cap][5] per-block partial reductions
@@ -228,6 +242,10 @@ struct mrfv_ctx {
     hipEvent_t ev_prop = nullptr;      // proposal copied to the host
     int64_t p_steps = 0, p_hits = 0, p_tp[3] = {0, 0, 0}, p_fp[3] = {0, 0, 0}, p_fn[3] = {0, 0, 0};
     double p_build_ms = 0.0;
+    // host time of the adaptation phase of mrfv_step: waiting for the judged flags, tree
+    // commit + table build + upload (or adoption of staged tables), prediction; steps
+    double h_wait_ms = 0.0, h_commit_ms = 0.0, h_predict_ms = 0.0;
+    int64_t h_steps = 0;
     int32_t *d_slots = nullptr;        // [cap] scratch slot list
     double *d_prim = nullptr;          // IC staging [batch][5][16^3]
     int prim_batch = 0;

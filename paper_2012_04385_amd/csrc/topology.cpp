@@ -244,6 +244,15 @@ void Topology::build(std::vector<BlockMeta> &meta, std::vector<int32_t> &child,
     L.par_cnt.assign(maxl + 1, 0);
     L.leaf_off.assign(maxl + 1, 0);
     L.leaf_cnt.assign(maxl + 1, 0);
+    L.jleaf_off.assign(maxl + 1, 0);
+    L.jleaf_cnt.assign(maxl + 1, 0);
+    const int face_region[6] = {12, 14, 10, 16, 4, 22};
+    auto needs_face_fill = [&](int s) {
+        const BlockMeta &m = meta[s];
+        for (int f = 0; f < 6; ++f)
+            if ((m.zg >> f) & 1 || nbr[(size_t)s * 27 + face_region[f]] < 0) return true;
+        return false;
+    };
     for (int l = 0; l <= maxl; ++l) {
         L.lvl_off[l] = (int32_t)L.data.size();
         for (int s : order)
@@ -257,6 +266,10 @@ void Topology::build(std::vector<BlockMeta> &meta, std::vector<int32_t> &child,
         for (int s : order)
             if (blocks_[s].level == l && blocks_[s].leaf) L.data.push_back(s);
         L.leaf_cnt[l] = (int32_t)L.data.size() - L.leaf_off[l];
+        L.jleaf_off[l] = (int32_t)L.data.size();
+        for (int s : order)
+            if (blocks_[s].level == l && blocks_[s].leaf && needs_face_fill(s)) L.data.push_back(s);
+        L.jleaf_cnt[l] = (int32_t)L.data.size() - L.jleaf_off[l];
     }
     L.all_leaves_off = (int32_t)L.data.size();
     for (int i = 0; i < n_inst; ++i) {
@@ -285,6 +298,7 @@ void Topology::build(std::vector<BlockMeta> &meta, std::vector<int32_t> &child,
         set(desc_lvl(l), L.lvl_off[l], L.lvl_cnt[l]);
         set(desc_par(l), L.par_off[l], L.par_cnt[l]);
         set(desc_leaf(l), L.leaf_off[l], L.leaf_cnt[l]);
+        set(desc_jleaf(l), L.jleaf_off[l], L.jleaf_cnt[l]);
     }
 }
 

@@ -94,6 +94,7 @@ def lib():
         "mrfv_set_proposer": ([vp, vp, i32], C.c_int),
         "mrfv_proposer_stats": ([vp, C.POINTER(i64), C.POINTER(d)], C.c_int),
         "mrfv_last_flags": ([vp, C.POINTER(C.c_int8)], C.c_int),
+        "mrfv_step_timing": ([vp, C.POINTER(d)], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -114,7 +115,7 @@ def exported_symbols():
             "mrfv_mlp_last_error", "mrfv_mlp_nparams", "mrfv_mlp_set_params",
             "mrfv_mlp_get_params", "mrfv_mlp_forward", "mrfv_mlp_loss_grad",
             "mrfv_mlp_adam_step", "mrfv_features", "mrfv_set_proposer", "mrfv_proposer_stats",
-            "mrfv_last_flags"]
+            "mrfv_last_flags", "mrfv_step_timing"]
 
 
 def morton_encode(shadow, level, bx, by, bz) -> int:
@@ -319,6 +320,12 @@ class Solver:
 
     def leaf_cells(self) -> int:
         return self.stats()[2]
+
+    def step_timing(self) -> dict:
+        """Host clock of the adaptation phase, summed over adaptive steps (ms)."""
+        out = (C.c_double * 4)()
+        self._chk(lib().mrfv_step_timing(self.h, out))
+        return dict(steps=int(out[0]), wait_ms=out[1], commit_ms=out[2], predict_ms=out[3])
 
 
 # --------------------------------------------------------------------- proposer
