@@ -125,11 +125,13 @@ int do_project(mrfv_ctx *ctx, T *U) {
 }
 
 // Halo fill, levels coarse to fine (a prediction reads the parent's filled halo).
-//   FILL_ALL: all 26 regions of every block (details, refinement);
-//   FILL_FACES: non-leaf blocks complete, leaves the face layers the flux reads (plain
-//   stages);
-//   FILL_MISSING_FACES: non-leaf blocks complete, leaves only faces without a same-level
-//   neighbour (fused stages read same-level neighbours in place).
+// Non-leaf blocks always get all 26 regions (they are prediction sources); leaves get
+//   FILL_ALL: all 26 regions (explicit fill, refinement);
+//   FILL_FACES: the face layers the flux reads (plain stages);
+//   FILL_MISSING_FACES: faces without a same-level neighbour (fused stages, which read
+//   same-level neighbours in place);
+//   FILL_MISSING: all regions without a same-level neighbour (before the details, which
+//   read same-level neighbours in place too).
 template <typename T>
 int do_fill(mrfv_ctx *ctx, T *U, int max_level, FillMode mode = FILL_ALL) {
     for (int l = 0; l <= std::min(max_level, levels_to_cover(ctx)); ++l) {
@@ -137,7 +139,8 @@ int do_fill(mrfv_ctx *ctx, T *U, int max_level, FillMode mode = FILL_ALL) {
             HIP_OK(launch_fill_halos<T>(U, wlist(ctx, desc_lvl(l), 1024), ctx->tb, FILL_ALL, ctx->stream));
         } else {
             HIP_OK(launch_fill_halos<T>(U, wlist(ctx, desc_par(l), 1024), ctx->tb, FILL_ALL, ctx->stream));
-            const int which = mode == FILL_FACES ? desc_leaf(l) : desc_jleaf(l);
+            const int which = mode == FILL_FACES ? desc_leaf(l)
+                              : mode == FILL_MISSING_FACES ? desc_jleaf(l) : desc_jleaf26(l);
             HIP_OK(launch_fill_halos<T>(U, wlist(ctx, which, 1024), ctx->tb, mode, ctx->stream));
         }
     }
@@ -243,6 +246,7 @@ int do_stage_fused(mrfv_ctx *ctx, int stage, const double *dt, const float *Uin,
 
 template <typename T>
 int do_details_flags(mrfv_ctx *ctx, const T *U, int8_t *flags, double *det) {
+    HIP_OK(launch_zero_f64(det, wlist(ctx, DESC_FINE), ctx->stream));
     HIP_OK(launch_details<T>(U, wlist(ctx, DESC_FINE), ctx->tb, ctx->d_inst, det, ctx->stream));
     HIP_OK(launch_flags(wlist(ctx, DESC_ALL), ctx->tb, ctx->d_inst, det, flags, ctx->stream));
     return MRFV_OK;
@@ -251,6 +255,23 @@ int do_details_flags(mrfv_ctx *ctx, const T *U, int8_t *flags, double *det) {
 template <typename T>
 int do_predict(mrfv_ctx *ctx, T *U, const int32_t *slots_host, int n) {
     if (n <= 0) return MRFV_OK;
+    // the parents' halos complete first: the prediction stencils reach 2 parent cells
+    // beyond the child's octant, and a parent that was a leaf may have had only the
+    // regions without a same-level neighbour filled
+    std::vector<int32_t> par;
+    for (int i = 0; i < n; ++i) {
+        const int p = ctx->topo.block(slots_host[i]).parent;
+        if (par.empty() || par.back() != p) par.push_back(p);
+    }
+    std::sort(par.begin(), par.end());
+    par.erase(std::unique(par.begin(), par.end()), par.end());
+    HIP_OK(hipMemcpyAsync(ctx->d_slots2, par.data(), sizeof(int32_t) * par.size(),
+                          hipMemcpyHostToDevice, ctx->stream));
+    WorkList wp;
+    wp.base = ctx->d_slots2;
+    wp.n = (int32_t)par.size();
+    wp.grid = std::min<int>(wp.n, 1024);
+    HIP_OK(launch_fill_halos<T>(U, wp, ctx->tb, FILL_ALL, ctx->stream));
     HIP_OK(hipMemcpyAsync(ctx->d_slots, slots_host, sizeof(int32_t) * n, hipMemcpyHostToDevice,
                           ctx->stream));
     HIP_OK(launch_predict<T>(U, ctx->d_slots, n, ctx->tb, ctx->stream));
@@ -260,8 +281,10 @@ int do_predict(mrfv_ctx *ctx, T *U, const int32_t *slots_host, int n) {
 
 int commit(mrfv_ctx *ctx, const int8_t *flags, std::vector<int32_t> &fresh) {
     std::vector<int> created;
-    if (!ctx->topo.commit(flags, nullptr, &created))
+    std::vector<TreeOp> ops;
+    if (!ctx->topo.commit(flags, &ops, &created))
         return fail(ctx, MRFV_ENOMEM, "slot capacity exhausted");
+    if (ops.empty()) return MRFV_OK;   // tree unchanged: the device tables stay valid
     fresh.insert(fresh.end(), created.begin(), created.end());
     return upload_tables(ctx);
 }
@@ -310,10 +333,10 @@ void decode_proposal(mrfv_ctx *ctx, const std::vector<int32_t> &leaves) {
 int stage_proposal(mrfv_ctx *ctx) {
     HIP_OK(hipStreamSynchronize(ctx->side));   // last step's uploads still read s_*
     std::vector<TreeOp> ops;
-    if (!ctx->topo.commit(ctx->proposal.data(), &ops, nullptr)) {
+    if (!ctx->topo.commit(ctx->proposal.data(), &ops, nullptr) || ops.empty()) {
         ctx->topo.undo(ops);
-        ctx->staged = false;
-        return MRFV_OK;   // would not fit: no staging, the normal path handles the step
+        ctx->staged = false;   // no change proposed, or it would not fit
+        return MRFV_OK;
     }
     ctx->topo.build(ctx->s_meta, ctx->s_child, ctx->s_nbr, ctx->lists2);
     ctx->staged_jumps = any_jump(ctx->topo, ctx->lists2, ctx->s_nbr);
@@ -420,6 +443,7 @@ int do_init(mrfv_ctx *ctx, mrfv_ic_fn ic, void *user, T *U) {
             wf.base = ctx->d_slots;
             wf.n = (int32_t)fresh.size();
             wf.grid = wf.n;
+            HIP_OK(launch_zero_f64(ctx->d_det, wf, ctx->stream));
             HIP_OK(launch_details<T>(U, wf, ctx->tb, ctx->d_inst, ctx->d_det, ctx->stream));
             HIP_OK(hipMemcpyAsync(det.data(), ctx->d_det, sizeof(double) * det.size(),
                                   hipMemcpyDeviceToHost, ctx->stream));
@@ -532,7 +556,7 @@ int do_step(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt) {
     }
     if (!adapt) return MRFV_OK;
     CALL(do_project<T>(ctx, U));
-    CALL(do_fill<T>(ctx, U, 1 << 20));
+    CALL(do_fill<T>(ctx, U, 1 << 20, FILL_MISSING));
     CALL(do_details_flags<T>(ctx, U, ctx->d_flags, ctx->d_det));
     const int cap = ctx->cfg.slot_capacity;
     HIP_OK(hipMemcpyAsync(ctx->h_flags, ctx->d_flags, cap, hipMemcpyDeviceToHost, ctx->stream));
@@ -565,8 +589,12 @@ int do_step(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt) {
             else { ctx->p_fn[cj]++; ctx->p_fp[cq]++; }
         }
         ctx->p_steps++;
-        if (hit && ctx->staged) {
-            ctx->p_hits++;
+        bool change = false;
+        for (int32_t sl : leaves) change = change || ctx->proposal[sl] != 0;
+        if (hit) ctx->p_hits++;
+        if (hit && !change) {
+            // nothing to commit
+        } else if (hit && ctx->staged) {
             CALL(adopt_staged(ctx, fresh));
         } else {
             CALL(commit(ctx, ctx->h_flags, fresh));
@@ -653,6 +681,7 @@ int mrfv_create(mrfv_ctx **out, const mrfv_config *cfg, const mrfv_instance *ins
     ALLOC(ctx->d_det, cap * sizeof(double));
     ALLOC(ctx->d_flags, cap);
     ALLOC(ctx->d_slots, cap * sizeof(int32_t));
+    ALLOC(ctx->d_slots2, cap * sizeof(int32_t));
     ALLOC(ctx->d_prim, (size_t)ctx->prim_batch * 5 * CELLS_I * sizeof(double));
     ALLOC(ctx->tb.meta, cap * sizeof(BlockMeta));
     ALLOC(ctx->tb.child, cap * 8 * sizeof(int32_t));
@@ -690,7 +719,7 @@ int mrfv_destroy(mrfv_ctx *ctx) {
             if (p) hipFree(p);
     }
     void *ptrs[] = {ctx->d_inst, ctx->d_err, ctx->d_D, ctx->d_W, ctx->d_FF, ctx->d_blockred, ctx->d_det,
-                    ctx->d_flags, ctx->d_slots, ctx->d_prim, ctx->tb.meta, ctx->tb.child,
+                    ctx->d_flags, ctx->d_slots, ctx->d_slots2, ctx->d_prim, ctx->tb.meta, ctx->tb.child,
                     ctx->tb.nbr, ctx->tb.lists, ctx->d_desc};
     for (void *p : ptrs)
         if (p) hipFree(p);

@@ -98,7 +98,8 @@ struct Region {
 __device__ __forceinline__ Region make_region(int mode, int ridx, int zg) {
     Region g;
     int r[3];
-    if (mode == FILL_ALL) {
+    const bool faces = (mode & FILL_FACES) != 0;
+    if (!faces) {
         const int reg = ridx < 13 ? ridx : ridx + 1;
         r[0] = reg % 3 - 1;
         r[1] = (reg / 3) % 3 - 1;
@@ -107,7 +108,6 @@ __device__ __forceinline__ Region make_region(int mode, int ridx, int zg) {
         r[0] = r[1] = r[2] = 0;
         r[ridx >> 1] = (ridx & 1) ? 1 : -1;
     }
-    const bool faces = mode != FILL_ALL;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         g.lo[a] = r[a] < 0 ? (faces ? 1 : 0) : (r[a] == 0 ? HW : HW + NI);
@@ -145,7 +145,7 @@ __global__ __launch_bounds__(TPB) void k_fill_halos(T *__restrict__ U, WorkList 
         const bool clamped = g.clamp[0] >= 0 || g.clamp[1] >= 0 || g.clamp[2] >= 0;
         const bool own = g.r[0] == 0 && g.r[1] == 0 && g.r[2] == 0;
         const int src = own ? slot : nbr[(size_t)slot * 27 + (g.r[2] + 1) * 9 + (g.r[1] + 1) * 3 + (g.r[0] + 1)];
-        if (mode == FILL_MISSING_FACES && src >= 0 && !clamped) continue;   // read in place
+        if ((mode & FILL_MISSING) && src >= 0 && !clamped) continue;   // read in place
         T *dst = U + (size_t)slot * 5 * CELLS_P;
         const int ncell = g.n[0] * g.n[1] * g.n[2];
         if (src >= 0) {
@@ -276,72 +276,105 @@ __global__ __launch_bounds__(TPB) void k_predict(T *__restrict__ U,
             predict_cell<T, T>(pu + q * CELLS_P, m.bx & 1, m.by & 1, m.bz & 1, i, j, k);
 }
 
-// One workgroup per block (level >= 1): FP64 max over the padded cells of the rho and E
-// details.  The prediction is applied separably through LDS: the 16^3 parent region the
-// 24^3 child stencils touch is staged once, then passes along x (16x16x24 values), y
-// (16x24x24) and z (24^3) evaluate each 1D step once per output instead of 31 times per
-// child cell.  The operation order per child cell equals predict_cell's.
+// Details, FP64.  DZ workgroups per block (level >= 1), each for a slab of 24/DZ padded
+// z-planes, write their maxima of the rho and E details over the slab; det[slot] is the
+// maximum over the slabs (atomicMax on the bit patterns of non-negative doubles, after
+// the list's entries were zeroed).  The prediction is applied separably through LDS:
+// the parent planes the slab's stencils touch are staged once, then passes along x, y
+// and z evaluate each 1D step once per output (operation order of predict_cell).
+// Cells outside the interior are read from the same-level neighbour's interior where
+// one exists (else from the own halo, filled for such regions).
+constexpr int DZ = 4;                          // slabs per block
+constexpr int SZ = NP / DZ;                    // padded z-planes per slab (6)
+constexpr int PZ = SZ / 2 + 4;                 // parent planes per slab (7)
+
 template <typename T>
 __global__ __launch_bounds__(TPB) void k_details(const T *__restrict__ U, WorkList wl,
                                                  const BlockMeta *__restrict__ meta,
+                                                 const int32_t *__restrict__ nbr,
                                                  const InstDev *__restrict__ inst,
                                                  double *__restrict__ det) {
-    constexpr int R = NI;            // parent region edge (16)
-    __shared__ double A[R * NP * NP];   // parent region, later the y-pass (72 KB)
-    __shared__ double Bx[R * R * NP];   // x-pass (48 KB)
-    __shared__ double red[TPB];
+    constexpr int R = NI;                       // parent region edge in x and y (16)
+    __shared__ double A[PZ * R * R];            // parent planes (14 KB)
+    __shared__ double Bx[PZ * R * NP];          // x pass (21 KB)
+    __shared__ double By[PZ * NP * NP];         // y pass (32 KB)
+    __shared__ long long src27[27];             // element offsets of the 27 sources
+    __shared__ double red[TPB / 64];
     const int nb = wl.count();
+    const int part = blockIdx.y;
+    const int k_lo = part * SZ;                 // first padded output plane
+    const int kk0 = ((k_lo - HW) >> 1) + HW - 2;   // first parent plane (region coordinates)
     for (int b = blockIdx.x; b < nb; b += gridDim.x) {
     const int slot = wl.at(b);
     const BlockMeta m = meta[slot];
     const InstDev P = inst[m.inst];
     const int ox = m.bx & 1, oy = m.by & 1, oz = m.bz & 1;
     const T *pu = U + (size_t)m.parent * 5 * CELLS_P;
-    const T *bu = U + (size_t)slot * 5 * CELLS_P;
+    if (threadIdx.x < 27) {
+        const int r = threadIdx.x;
+        const int rx = r % 3 - 1, ry = (r / 3) % 3 - 1, rz = r / 9 - 1;
+        const bool zg = (rx < 0 && (m.zg & 1)) || (rx > 0 && (m.zg & 2)) ||
+                        (ry < 0 && (m.zg & 4)) || (ry > 0 && (m.zg & 8)) ||
+                        (rz < 0 && (m.zg & 16)) || (rz > 0 && (m.zg & 32));
+        const int s = (r == 13 || zg) ? -1 : nbr[(size_t)slot * 27 + r];
+        src27[r] = s >= 0 ? (long long)s * 5 * CELLS_P - NI * (rx + NP * (ry + NP * rz))
+                          : (long long)slot * 5 * CELLS_P;
+    }
     double d = 0.0;
     for (int v = 0; v < 2; ++v) {
         const int q = v == 0 ? 0 : 4;
         const double inv_s = v == 0 ? 1.0 / P.scale_rho : 1.0 / P.scale_E;
-        // parent padded cells (oz*8 + kk, oy*8 + jj, ox*8 + ii), kk, jj, ii in [0, 16)
-        for (int t = threadIdx.x; t < R * R * R; t += TPB) {
+        // parent padded cells (oz*8 + kk0 + kk, oy*8 + jj, ox*8 + ii)
+        for (int t = threadIdx.x; t < PZ * R * R; t += TPB) {
             const int ii = t & 15, jj = (t >> 4) & 15, kk = t >> 8;
-            A[t] = (double)pu[q * CELLS_P + pidx(0, oz * 8 + kk, oy * 8 + jj, ox * 8 + ii)];
+            A[t] = (double)pu[q * CELLS_P + pidx(0, oz * 8 + kk0 + kk, oy * 8 + jj, ox * 8 + ii)];
         }
         __syncthreads();
-        for (int t = threadIdx.x; t < R * R * NP; t += TPB) {
+        for (int t = threadIdx.x; t < PZ * R * NP; t += TPB) {
             const int i = t % NP, r = t / NP;
             const int ci = i - HW, II = (ci >> 1) + HW;
             const double *row = A + r * R + II;
             Bx[t] = pred1<double>(row[-2], row[-1], row[0], row[1], row[2], (ci & 1) ? -1.0 : 1.0);
         }
         __syncthreads();
-        for (int t = threadIdx.x; t < R * NP * NP; t += TPB) {
+        for (int t = threadIdx.x; t < PZ * NP * NP; t += TPB) {
             const int i = t % NP, j = (t / NP) % NP, kk = t / (NP * NP);
             const int cj = j - HW, JJ = (cj >> 1) + HW;
             const double *col = Bx + (kk * R + JJ) * NP + i;
-            A[t] = pred1<double>(col[-2 * NP], col[-NP], col[0], col[NP], col[2 * NP],
-                                 (cj & 1) ? -1.0 : 1.0);
+            By[t] = pred1<double>(col[-2 * NP], col[-NP], col[0], col[NP], col[2 * NP],
+                                  (cj & 1) ? -1.0 : 1.0);
         }
         __syncthreads();
-        for (int cell = threadIdx.x; cell < CELLS_P; cell += TPB) {
-            const int i = cell % NP, j = (cell / NP) % NP, k = cell / (NP * NP);
-            const int ck = k - HW, KK = (ck >> 1) + HW;
-            const double *c = A + (KK * NP + j) * NP + i;
+        for (int cell = threadIdx.x; cell < SZ * NP * NP; cell += TPB) {
+            const int i = cell % NP, j = (cell / NP) % NP, k = k_lo + cell / (NP * NP);
+            const int ck = k - HW, KK = (ck >> 1) + HW - kk0;
+            const double *c = By + (KK * NP + j) * NP + i;
             const double pv = pred1<double>(c[-2 * NP * NP], c[-NP * NP], c[0], c[NP * NP],
                                             c[2 * NP * NP], (ck & 1) ? -1.0 : 1.0);
-            d = fmax(d, fabs((double)bu[q * CELLS_P + cell] - pv) * inv_s);
+            const int rx = i < HW ? 0 : (i < HW + NI ? 1 : 2), ry = j < HW ? 0 : (j < HW + NI ? 1 : 2),
+                      rz = k < HW ? 0 : (k < HW + NI ? 1 : 2);
+            const long long so = src27[(rz * 3 + ry) * 3 + rx];
+            const double u = (double)U[so + q * CELLS_P + pidx(0, k, j, i)];
+            d = fmax(d, fabs(u - pv) * inv_s);
         }
         __syncthreads();
     }
-    red[threadIdx.x] = d;
+    // wavefront max, then across the workgroup's waves
+    for (int off = 32; off > 0; off >>= 1) d = fmax(d, __shfl_xor(d, off));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = d;
     __syncthreads();
-    for (int w = TPB / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
-        __syncthreads();
+    if (threadIdx.x == 0) {
+        double mx = red[0];
+        for (int w = 1; w < TPB / 64; ++w) mx = fmax(mx, red[w]);
+        atomicMax((unsigned long long *)(det + slot), (unsigned long long)__double_as_longlong(mx));
     }
-    if (threadIdx.x == 0) det[slot] = red[0];
     __syncthreads();
     }
+}
+
+__global__ __launch_bounds__(TPB) void k_zero_f64(double *__restrict__ p, WorkList wl) {
+    const int nb = wl.count();
+    for (int t = blockIdx.x * TPB + threadIdx.x; t < nb; t += gridDim.x * TPB) p[wl.at(t)] = 0.0;
 }
 
 __device__ __forceinline__ double eps_level(const InstDev &P, int l) {
@@ -516,7 +549,7 @@ template <typename T>
 hipError_t launch_fill_halos(T *U, const WorkList &wl, const DevTables &tb, FillMode mode,
                              hipStream_t st) {
     if (wl.grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fill_halos<T>, grid2(wl.grid, mode == FILL_ALL ? 26 : 6), dim3(TPB), 0,
+    hipLaunchKernelGGL(k_fill_halos<T>, grid2(wl.grid, (mode & FILL_FACES) ? 6 : 26), dim3(TPB), 0,
                        st, U, wl, tb.meta, tb.nbr, (int)mode);
     return hipGetLastError();
 }
@@ -547,7 +580,14 @@ template <typename T>
 hipError_t launch_details(const T *U, const WorkList &wl, const DevTables &tb,
                           const InstDev *inst, double *det, hipStream_t st) {
     if (wl.grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_details<T>, dim3(wl.grid), dim3(TPB), 0, st, U, wl, tb.meta, inst, det);
+    hipLaunchKernelGGL(k_details<T>, grid2(wl.grid, DZ), dim3(TPB), 0, st, U, wl, tb.meta, tb.nbr,
+                       inst, det);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_f64(double *p, const WorkList &wl, hipStream_t st) {
+    if (wl.grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_f64, dim3((wl.grid + TPB - 1) / TPB), dim3(TPB), 0, st, p, wl);
     return hipGetLastError();
 }
 

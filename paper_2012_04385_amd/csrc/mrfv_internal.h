@@ -61,7 +61,8 @@ struct HostLists {
     std::vector<int32_t> data;
     int max_level = 0;
     // per level: all blocks, non-leaf blocks, leaves
-    std::vector<int32_t> lvl_off, lvl_cnt, par_off, par_cnt, leaf_off, leaf_cnt, jleaf_off, jleaf_cnt;
+    std::vector<int32_t> lvl_off, lvl_cnt, par_off, par_cnt, leaf_off, leaf_cnt, jleaf_off, jleaf_cnt,
+        j26_off, j26_cnt;
     int32_t all_leaves_off = 0, all_leaves_cnt = 0;      // leaves of every level
     // descriptor table {offset, count} per list, mirrored on the device (graph launches)
     std::vector<int32_t> desc;
@@ -121,19 +122,23 @@ uint64_t morton_encode(int shadow, int level, int bx, int by, int bz);
 // Descriptor indices of the work lists (DevTables lists + the device descriptor table).
 constexpr int MAX_LEVELS = 13;
 constexpr int DESC_LEAVES = 0, DESC_ALL = 1, DESC_FINE = 2, DESC_SCRATCH = 3;
-constexpr int DESC_PER_LEVEL = 4;
+constexpr int DESC_PER_LEVEL = 5;
 constexpr int desc_lvl(int l) { return 4 + DESC_PER_LEVEL * l; }
 constexpr int desc_par(int l) { return 5 + DESC_PER_LEVEL * l; }
 constexpr int desc_leaf(int l) { return 6 + DESC_PER_LEVEL * l; }
 // leaves of level l with at least one face that has no same-level neighbour or lies on a
 // zero-gradient boundary: the only leaves whose halos a fused stage must fill
 constexpr int desc_jleaf(int l) { return 7 + DESC_PER_LEVEL * l; }
+// leaves of level l with at least one of the 26 halo regions lacking a same-level
+// neighbour or on a zero-gradient boundary (filled before the details)
+constexpr int desc_jleaf26(int l) { return 8 + DESC_PER_LEVEL * l; }
 constexpr int N_DESC = 4 + DESC_PER_LEVEL * MAX_LEVELS;
 
-// Halo fill modes: every one of the 26 halo regions; the 6 face regions (3 layers deep,
-// all the flux stencils read); only the face regions without a same-level neighbour
-// (the fused stage reads same-level neighbours' interiors directly).
-enum FillMode { FILL_ALL = 0, FILL_FACES = 1, FILL_MISSING_FACES = 2 };
+// Halo fill modes, two flags: FACES restricts the fill to the 6 face regions, 3 layers
+// deep (all the flux stencils read); MISSING to the regions without a same-level
+// neighbour or on a zero-gradient boundary (the other regions are read in place from
+// the neighbour's interior by the fused stage and the details).
+enum FillMode { FILL_ALL = 0, FILL_FACES = 1, FILL_MISSING = 2, FILL_MISSING_FACES = 3 };
 
 // --------------------------------------------------------------- kernel launchers ----
 // All launchers enqueue on `st` and return hipGetLastError().
@@ -153,6 +158,7 @@ hipError_t launch_predict(T *U, const int32_t *list, int n, const DevTables &tb,
 template <typename T>
 hipError_t launch_details(const T *U, const WorkList &wl, const DevTables &tb,
                           const InstDev *inst, double *det, hipStream_t st);
+hipError_t launch_zero_f64(double *p, const WorkList &wl, hipStream_t st);
 hipError_t launch_flags(const WorkList &wl, const DevTables &tb, const InstDev *inst,
                         const double *det, int8_t *flags, hipStream_t st);
 template <typename T>
@@ -247,6 +253,7 @@ struct mrfv_ctx {
     double h_wait_ms = 0.0, h_commit_ms = 0.0, h_predict_ms = 0.0;
     int64_t h_steps = 0;
     int32_t *d_slots = nullptr;        // [cap] scratch slot list
+    int32_t *d_slots2 = nullptr;       // [cap] second scratch slot list
     double *d_prim = nullptr;          // IC staging [batch][5][16^3]
     int prim_batch = 0;
     int lists_cap = 0;

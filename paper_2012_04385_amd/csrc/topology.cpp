@@ -246,11 +246,20 @@ void Topology::build(std::vector<BlockMeta> &meta, std::vector<int32_t> &child,
     L.leaf_cnt.assign(maxl + 1, 0);
     L.jleaf_off.assign(maxl + 1, 0);
     L.jleaf_cnt.assign(maxl + 1, 0);
+    L.j26_off.assign(maxl + 1, 0);
+    L.j26_cnt.assign(maxl + 1, 0);
     const int face_region[6] = {12, 14, 10, 16, 4, 22};
     auto needs_face_fill = [&](int s) {
         const BlockMeta &m = meta[s];
         for (int f = 0; f < 6; ++f)
             if ((m.zg >> f) & 1 || nbr[(size_t)s * 27 + face_region[f]] < 0) return true;
+        return false;
+    };
+    auto needs_region_fill = [&](int s) {
+        const BlockMeta &m = meta[s];
+        if (m.zg) return true;
+        for (int r = 0; r < 27; ++r)
+            if (r != 13 && nbr[(size_t)s * 27 + r] < 0) return true;
         return false;
     };
     for (int l = 0; l <= maxl; ++l) {
@@ -270,6 +279,10 @@ void Topology::build(std::vector<BlockMeta> &meta, std::vector<int32_t> &child,
         for (int s : order)
             if (blocks_[s].level == l && blocks_[s].leaf && needs_face_fill(s)) L.data.push_back(s);
         L.jleaf_cnt[l] = (int32_t)L.data.size() - L.jleaf_off[l];
+        L.j26_off[l] = (int32_t)L.data.size();
+        for (int s : order)
+            if (blocks_[s].level == l && blocks_[s].leaf && needs_region_fill(s)) L.data.push_back(s);
+        L.j26_cnt[l] = (int32_t)L.data.size() - L.j26_off[l];
     }
     L.all_leaves_off = (int32_t)L.data.size();
     for (int i = 0; i < n_inst; ++i) {
@@ -299,6 +312,7 @@ void Topology::build(std::vector<BlockMeta> &meta, std::vector<int32_t> &child,
         set(desc_par(l), L.par_off[l], L.par_cnt[l]);
         set(desc_leaf(l), L.leaf_off[l], L.leaf_cnt[l]);
         set(desc_jleaf(l), L.jleaf_off[l], L.jleaf_cnt[l]);
+        set(desc_jleaf26(l), L.j26_off[l], L.j26_cnt[l]);
     }
 }
 
