@@ -91,12 +91,16 @@ int upload_tables(mrfv_ctx *ctx) {
 
 // Work lists.  Eager: offset and count from the host tree, one workgroup per block.
 // Captured (ctx->capturing): offset and count read on the device from the descriptor
-// table, grid bounded by the capacity, so the graph stays valid when the tree changes.
+// table, grid bounded by the capacity, so the graph stays valid when the tree changes
+// as long as the same lists are empty (the graph's key, graph_key); lists empty at
+// capture are left out of the graph.
 WorkList wlist(const mrfv_ctx *ctx, int which, int grid_cap = 2048) {
     WorkList w;
     w.base = ctx->tb.lists;
     if (ctx->capturing) {
         w.desc = ctx->d_desc + 2 * which;
+        const std::vector<int32_t> &d = ctx->lists.desc;
+        if (2 * which + 1 >= (int)d.size() || d[2 * which + 1] == 0) return w;   // grid 0: skipped
         // bound: the most blocks the list can ever hold (per level: every instance full)
         int64_t bound = ctx->cfg.slot_capacity;
         if (which >= desc_lvl(0)) bound = std::min<int64_t>(bound, ctx->lvl_bound[(which - desc_lvl(0)) / DESC_PER_LEVEL]);
@@ -114,7 +118,7 @@ WorkList wlist(const mrfv_ctx *ctx, int which, int grid_cap = 2048) {
 
 // Deepest level whose lists a launch sequence must cover.
 int levels_to_cover(const mrfv_ctx *ctx) {
-    return ctx->capturing ? ctx->lmax_all : ctx->lists.max_level;
+    return ctx->lists.max_level;
 }
 
 template <typename T>
@@ -234,8 +238,7 @@ int do_stage_fused(mrfv_ctx *ctx, int stage, const double *dt, const float *Uin,
     HIP_OK(launch_rhs_update_f32(stage, dt, Uin, Uout, U0, wlist(ctx, DESC_LEAVES, 1 << 30), ctx->tb,
                                  ctx->d_inst, FF, ctx->d_err, ctx->stream));
     timing_end(ctx, ev, (int64_t)L.all_leaves_cnt * CELLS_I);
-    // a captured graph must not depend on the current tree: always include the correction
-    if (ctx->has_jumps || ctx->capturing) {
+    if (ctx->has_jumps) {
         for (int l = levels_to_cover(ctx) - 1; l >= 0; --l)
             HIP_OK(launch_ff_restrict<float>(FF, wlist(ctx, desc_par(l)), ctx->tb, ctx->stream));
         HIP_OK(launch_reflux_update<float>(stage, dt, Uout, FF, wlist(ctx, DESC_LEAVES), ctx->tb,
@@ -495,12 +498,31 @@ int do_stages(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt) {
 // hipGraph of the CFL step and the three RK stages (batched FP32 path, batched == 2): the
 // kernels read their work lists through the device descriptors, so one capture serves
 // every later tree.  Captured on the library's own stream, launched on the caller's.
+// Which launches a captured stage graph contains: the finest level present, whether
+// resolution jumps exist, and which per-level lists are non-empty.  Counts and list
+// contents are read on the device, so one graph serves every tree with the same key.
+uint64_t graph_key(const mrfv_ctx *ctx) {
+    const HostLists &L = ctx->lists;
+    uint64_t k = (uint64_t)L.max_level | ((uint64_t)ctx->has_jumps << 4);
+    for (int l = 0; l <= L.max_level && l < MAX_LEVELS; ++l) {
+        if (L.desc[2 * desc_par(l) + 1] > 0) k |= 1ull << (5 + l);
+        if (L.desc[2 * desc_jleaf(l) + 1] > 0) k |= 1ull << (5 + MAX_LEVELS + l);
+    }
+    return k;
+}
+
+void drop_graphs(mrfv_ctx *ctx) {
+    for (auto &kv : ctx->graphs) hipGraphExecDestroy(kv.second);
+    ctx->graphs.clear();
+}
+
 int run_stage_graph(mrfv_ctx *ctx, float *U, float *U0, double *dt) {
-    if (!ctx->graph || ctx->gU != U || ctx->gU0 != U0 || ctx->gdt != dt) {
-        if (ctx->graph) {
-            HIP_OK(hipGraphExecDestroy(ctx->graph));
-            ctx->graph = nullptr;
-        }
+    if (ctx->gU != U || ctx->gU0 != U0 || ctx->gdt != dt) drop_graphs(ctx);
+    const uint64_t key = graph_key(ctx);
+    auto it = ctx->graphs.find(key);
+    if (it == ctx->graphs.end()) {
+        if (ctx->graphs.size() >= 32) drop_graphs(ctx);   // bound the cache
+        ctx->graph = nullptr;
         if (!ctx->gstream) HIP_OK(hipStreamCreateWithFlags(&ctx->gstream, hipStreamNonBlocking));
         HIP_OK(hipStreamSynchronize(ctx->stream));
         hipStream_t user = ctx->stream;
@@ -523,8 +545,10 @@ int run_stage_graph(mrfv_ctx *ctx, float *U, float *U0, double *dt) {
         ctx->gU = U;
         ctx->gU0 = U0;
         ctx->gdt = dt;
+        it = ctx->graphs.emplace(key, ctx->graph).first;
+        ctx->graph = nullptr;
     }
-    HIP_OK(hipGraphLaunch(ctx->graph, ctx->stream));
+    HIP_OK(hipGraphLaunch(it->second, ctx->stream));
     return MRFV_OK;
 }
 
@@ -702,7 +726,7 @@ int mrfv_destroy(mrfv_ctx *ctx) {
     if (!ctx) return MRFV_EINVAL;
     if (ctx->stream) hipStreamSynchronize(ctx->stream);
     else hipDeviceSynchronize();
-    if (ctx->graph) hipGraphExecDestroy(ctx->graph);
+    drop_graphs(ctx);
     if (ctx->gstream) hipStreamDestroy(ctx->gstream);
     if (ctx->side) {
         hipStreamSynchronize(ctx->side);

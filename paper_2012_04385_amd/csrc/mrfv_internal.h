@@ -5,6 +5,7 @@
 #include <cstdint>
 #include <string>
 #include <unordered_map>
+#include <map>
 #include <vector>
 
 #include "../../include/mrfv.h"
@@ -225,7 +226,9 @@ struct mrfv_ctx {
     int8_t *d_flags = nullptr;         // [cap]
     int32_t *d_desc = nullptr;         // [N_DESC][2] list descriptors (graph launches)
     hipStream_t gstream = nullptr;     // capture stream of the stage graph
-    hipGraphExec_t graph = nullptr;    // three RK stages, valid for (gU, gU0, gdt)
+    hipGraphExec_t graph = nullptr;    // graph being instantiated
+    std::map<uint64_t, hipGraphExec_t> graphs;   // CFL + three RK stages by graph key,
+                                                 // valid for (gU, gU0, gdt)
     void *gU = nullptr, *gU0 = nullptr;
     const double *gdt = nullptr;
     int lmax_all = 0;                  // deepest lmax over the instances
