@@ -183,6 +183,23 @@ int mrfv_coarsen_block(mrfv_ctx *ctx, int32_t instance, int32_t level, int32_t b
 int mrfv_enable_kernel_timing(mrfv_ctx *ctx, int32_t on);
 int mrfv_kernel_time(mrfv_ctx *ctx, int64_t *launches, double *total_ms, int64_t *cells);
 
+/* Launch shapes of the fused rhs + update kernel (batched FP32 path): variant v groups
+ * the block's z-planes by shapes_host[2v] and uses shapes_host[2v+1] threads per
+ * workgroup; every variant gives bitwise the same result.  rhs_variant sets the variant
+ * when set >= 0 (captured stage graphs are re-captured), writes the number of variants
+ * and their shapes (each may be NULL) and returns the current variant (>= 0) or an
+ * error.  Host only. */
+int mrfv_rhs_variant(mrfv_ctx *ctx, int32_t set, int32_t *n_variants_host, int32_t *shapes_host);
+
+/* autotune -- times every variant on the current tree and state (reps launches each,
+ * after one warm-up) and keeps the fastest.  The state U is not modified; U0, the second
+ * state buffer and dt_dev (dev double[n_instances], receives the CFL step) are used as
+ * scratch.  ms_host (may be NULL): host float[n_variants] receives the mean launch time
+ * of each variant; *choice_host the chosen variant.  Batched FP32 contexts only.
+ * Synchronises the stream. */
+int mrfv_autotune(mrfv_ctx *ctx, void *U, void *U0, double *dt_dev, int32_t reps, float *ms_host,
+                  int32_t *choice_host);
+
 /* step_timing -- host clock of the adaptation phase of mrfv_step, summed over adaptive
  * steps: out_host double[4] = (steps, ms waiting for the judged flags, ms committing the
  * tree and uploading its tables (or adopting staged ones), ms predicting new children). */

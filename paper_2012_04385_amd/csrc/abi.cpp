@@ -235,7 +235,7 @@ int do_stage_fused(mrfv_ctx *ctx, int stage, const double *dt, const float *Uin,
     hipEvent_t ev{};
     timing_begin(ctx, &ev);
     // the fused kernel has no grid-stride loop: its grid must cover every possible leaf
-    HIP_OK(launch_rhs_update_f32(stage, dt, Uin, Uout, U0, wlist(ctx, DESC_LEAVES, 1 << 30), ctx->tb,
+    HIP_OK(launch_rhs_update_f32(ctx->rhs_variant, stage, dt, Uin, Uout, U0, wlist(ctx, DESC_LEAVES, 1 << 30), ctx->tb,
                                  ctx->d_inst, FF, ctx->d_err, ctx->stream));
     timing_end(ctx, ev, (int64_t)L.all_leaves_cnt * CELLS_I);
     if (ctx->has_jumps) {
@@ -979,6 +979,69 @@ int mrfv_set_proposer(mrfv_ctx *ctx, mrfv_mlp *mlp, int32_t mode) {
     }
     ctx->mlp = mlp;
     ctx->prop_mode = mode;
+    return MRFV_OK;
+}
+
+int mrfv_rhs_variant(mrfv_ctx *ctx, int32_t set, int32_t *n_variants, int32_t *shapes) {
+    if (!ctx) return MRFV_EINVAL;
+    const int n = rhs_variants();
+    if (n_variants) *n_variants = n;
+    if (shapes)
+        for (int v = 0; v < n; ++v) rhs_variant_shape(v, shapes + 2 * v, shapes + 2 * v + 1);
+    if (set >= n) return fail(ctx, MRFV_EINVAL, "rhs_variant: index out of range");
+    if (set >= 0 && set != ctx->rhs_variant) {
+        ctx->rhs_variant = set;
+        drop_graphs(ctx);   // captured graphs hold the old launch shape
+    }
+    return ctx->rhs_variant;
+}
+
+int mrfv_autotune(mrfv_ctx *ctx, void *U, void *U0, double *dt_dev, int32_t reps, float *ms_host,
+                  int32_t *choice) {
+    CALL(need_init(ctx));
+    if (!U || !U0 || !dt_dev) return fail(ctx, MRFV_EINVAL, "autotune: null pointer");
+    if (!(ctx->cfg.batched && ctx->cfg.dtype == MRFV_F32))
+        return fail(ctx, MRFV_EINVAL, "autotune: only the batched FP32 path has launch variants");
+    if (reps < 1 || reps > 1000) return fail(ctx, MRFV_EINVAL, "autotune: reps must be 1..1000");
+    float *X = (float *)U, *W = (float *)ctx->d_W;
+    hipStream_t st = ctx->stream;
+    // a valid first stage: CFL step, restriction, fills; each variant then runs stage 0
+    // from U into the second state buffer (U, the state, is not written)
+    HIP_OK(launch_cfl<float>(X, wlist(ctx, DESC_LEAVES), ctx->tb, ctx->d_inst, (int)ctx->inst.size(),
+                             ctx->d_blockred, dt_dev, st));
+    CALL(do_project<float>(ctx, X));
+    CALL(do_fill<float>(ctx, X, 1 << 20, FILL_MISSING_FACES));
+    const WorkList wl = wlist(ctx, DESC_LEAVES, 1 << 30);
+    hipEvent_t a, b;
+    HIP_OK(hipEventCreate(&a));
+    HIP_OK(hipEventCreate(&b));
+    int best = -1;
+    float best_ms = 0.f;
+    for (int v = 0; v < rhs_variants(); ++v) {
+        HIP_OK(launch_rhs_update_f32(v, 0, dt_dev, X, W, (float *)U0, wl, ctx->tb, ctx->d_inst,
+                                     (float *)ctx->d_FF, ctx->d_err, st));
+        HIP_OK(hipEventRecord(a, st));
+        for (int r = 0; r < reps; ++r)
+            HIP_OK(launch_rhs_update_f32(v, 0, dt_dev, X, W, (float *)U0, wl, ctx->tb, ctx->d_inst,
+                                         (float *)ctx->d_FF, ctx->d_err, st));
+        HIP_OK(hipEventRecord(b, st));
+        HIP_OK(hipEventSynchronize(b));
+        float ms = 0.f;
+        HIP_OK(hipEventElapsedTime(&ms, a, b));
+        ms /= reps;
+        if (ms_host) ms_host[v] = ms;
+        if (best < 0 || ms < best_ms) {
+            best = v;
+            best_ms = ms;
+        }
+    }
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    if (best != ctx->rhs_variant) {
+        ctx->rhs_variant = best;
+        drop_graphs(ctx);
+    }
+    if (choice) *choice = best;
     return MRFV_OK;
 }
 

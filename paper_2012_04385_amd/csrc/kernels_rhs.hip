@@ -441,9 +441,10 @@ struct LdsSink {
 // other state buffer.  Stencil cells outside the block are read from the same-level
 // neighbour's interior where one exists (no halo copy), else from the own halo, which
 // the fill has predicted from the parent or clamped at a zero-gradient boundary.
-constexpr int GP = 2;                         // z-planes per group
-constexpr int TPB_F = 320;                    // 1600 faces per group = 5 rounds
-constexpr int NFX = GP * NI * (NI + 1);       // x-faces per group (544)
+// Template parameters: GP z-planes per group (1, 2, 4) and TPB_F threads (>= 256, the
+// column owners); the launch shape is chosen by the autotuner among the instantiated
+// variants.  Every variant evaluates each face by the same instruction sequence and sums
+// D in the same order, so all give bitwise the same result.
 constexpr int NFZ = NI * NI;                  // z-faces per face plane (256)
 
 template <typename T>
@@ -483,7 +484,7 @@ __device__ __forceinline__ void face_flux_at(const T *__restrict__ ub, const T *
     Fp[t2] = F[3];
 }
 
-template <typename T>
+template <typename T, int GP, int TPB_F>
 __global__ __launch_bounds__(TPB_F) void k_rhs_update(int stage, const double *__restrict__ dt,
                                                       const T *__restrict__ Uin, T *__restrict__ Uout,
                                                       T *U0, WorkList wl,
@@ -491,6 +492,7 @@ __global__ __launch_bounds__(TPB_F) void k_rhs_update(int stage, const double *_
                                                       const int32_t *__restrict__ nbr,
                                                       const InstDev *__restrict__ inst, T *FF,
                                                       int32_t *err) {
+    constexpr int NFX = GP * NI * (NI + 1);   // x-faces per group
     __shared__ T Fx[GP][NI][NI + 1][5];   // [plane][y][face x][q]
     __shared__ T Fy[GP][NI + 1][NI][5];   // [plane][face y][x][q]
     __shared__ T Fz[GP + 1][NI][NI][5];   // [face plane][y][x][q]; plane j = face k0 + j - 1/2
@@ -699,13 +701,44 @@ hipError_t launch_update(int stage, const double *dt, T *U, T *U0, const T *L, c
     return hipGetLastError();
 }
 
-hipError_t launch_rhs_update_f32(int stage, const double *dt, const float *Uin, float *Uout,
-                                 float *U0, const WorkList &wl, const DevTables &tb,
+// Launch shapes of the fused kernel: (z-planes per group, threads per workgroup).
+constexpr int N_RHS_VARIANTS = 9;
+constexpr int RHS_GP[N_RHS_VARIANTS] = {2, 1, 2, 2, 4, 4, 2, 2, 1};
+constexpr int RHS_TPB[N_RHS_VARIANTS] = {320, 256, 256, 384, 320, 512, 448, 512, 320};
+
+template <int V>
+static void launch_variant(int stage, const double *dt, const float *Uin, float *Uout, float *U0,
+                    const WorkList &wl, const DevTables &tb, const InstDev *inst, float *FF,
+                    int32_t *err, hipStream_t st) {
+    constexpr int G = RHS_GP[V], B = RHS_TPB[V];
+    hipLaunchKernelGGL((k_rhs_update<float, G, B>), dim3(wl.grid), dim3(B), 0, st, stage, dt, Uin,
+                       Uout, U0, wl, tb.meta, tb.nbr, inst, FF, err);
+}
+
+int rhs_variants() { return N_RHS_VARIANTS; }
+
+void rhs_variant_shape(int v, int *gp, int *tpb) {
+    *gp = RHS_GP[v];
+    *tpb = RHS_TPB[v];
+}
+
+hipError_t launch_rhs_update_f32(int variant, int stage, const double *dt, const float *Uin,
+                                 float *Uout, float *U0, const WorkList &wl, const DevTables &tb,
                                  const InstDev *inst, float *FF, int32_t *err, hipStream_t st) {
     if (wl.grid <= 0) return hipSuccess;
     if (Uin == Uout) return hipErrorInvalidValue;   // neighbours' interiors are read
-    hipLaunchKernelGGL(k_rhs_update<float>, dim3(wl.grid), dim3(TPB_F), 0, st, stage, dt, Uin, Uout,
-                       U0, wl, tb.meta, tb.nbr, inst, FF, err);
+    switch (variant) {
+        case 0: launch_variant<0>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, st); break;
+        case 1: launch_variant<1>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, st); break;
+        case 2: launch_variant<2>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, st); break;
+        case 3: launch_variant<3>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, st); break;
+        case 4: launch_variant<4>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, st); break;
+        case 5: launch_variant<5>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, st); break;
+        case 6: launch_variant<6>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, st); break;
+        case 7: launch_variant<7>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, st); break;
+        case 8: launch_variant<8>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, st); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -188,9 +188,12 @@ hipError_t launch_update(int stage, const double *dt, T *U, T *U0, const T *L,
                          int32_t *err, hipStream_t st);
 // Fused stage: reads the state from Uin (same-level neighbours' interiors directly, the
 // own halo elsewhere) and writes the new interior state to Uout != Uin.
-hipError_t launch_rhs_update_f32(int stage, const double *dt, const float *Uin, float *Uout,
-                                 float *U0, const WorkList &leaves, const DevTables &tb,
+// variant: launch shape index in [0, rhs_variants()) (all give the same result).
+hipError_t launch_rhs_update_f32(int variant, int stage, const double *dt, const float *Uin,
+                                 float *Uout, float *U0, const WorkList &leaves, const DevTables &tb,
                                  const InstDev *inst, float *FF, int32_t *err, hipStream_t st);
+int rhs_variants();
+void rhs_variant_shape(int v, int *gp, int *tpb);
 template <typename T>
 hipError_t launch_reflux_update(int stage, const double *dt, T *U, const T *FF,
                                 const WorkList &leaves, const DevTables &tb,
@@ -257,6 +260,7 @@ struct mrfv_ctx {
     int64_t h_steps = 0;
     int32_t *d_slots = nullptr;        // [cap] scratch slot list
     int32_t *d_slots2 = nullptr;       // [cap] second scratch slot list
+    int rhs_variant = 0;               // launch shape of the fused kernel (autotuned)
     double *d_prim = nullptr;          // IC staging [batch][5][16^3]
     int prim_batch = 0;
     int lists_cap = 0;

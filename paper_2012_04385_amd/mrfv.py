@@ -95,6 +95,8 @@ def lib():
         "mrfv_proposer_stats": ([vp, C.POINTER(i64), C.POINTER(d)], C.c_int),
         "mrfv_last_flags": ([vp, C.POINTER(C.c_int8)], C.c_int),
         "mrfv_step_timing": ([vp, C.POINTER(d)], C.c_int),
+        "mrfv_rhs_variant": ([vp, i32, C.POINTER(i32), C.POINTER(i32)], C.c_int),
+        "mrfv_autotune": ([vp, vp, vp, vp, i32, C.POINTER(C.c_float), C.POINTER(i32)], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -115,7 +117,7 @@ def exported_symbols():
             "mrfv_mlp_last_error", "mrfv_mlp_nparams", "mrfv_mlp_set_params",
             "mrfv_mlp_get_params", "mrfv_mlp_forward", "mrfv_mlp_loss_grad",
             "mrfv_mlp_adam_step", "mrfv_features", "mrfv_set_proposer", "mrfv_proposer_stats",
-            "mrfv_last_flags", "mrfv_step_timing"]
+            "mrfv_last_flags", "mrfv_step_timing", "mrfv_rhs_variant", "mrfv_autotune"]
 
 
 def morton_encode(shadow, level, bx, by, bz) -> int:
@@ -320,6 +322,29 @@ class Solver:
 
     def leaf_cells(self) -> int:
         return self.stats()[2]
+
+    def rhs_variants(self):
+        """[(z-planes per group, threads per workgroup)] of the fused kernel's variants."""
+        n = C.c_int32(0)
+        lib().mrfv_rhs_variant(self.h, -1, C.byref(n), None)
+        shp = (C.c_int32 * (2 * n.value))()
+        lib().mrfv_rhs_variant(self.h, -1, None, shp)
+        return [(shp[2 * v], shp[2 * v + 1]) for v in range(n.value)]
+
+    def set_rhs_variant(self, v: int) -> int:
+        rc = lib().mrfv_rhs_variant(self.h, int(v), None, None)
+        self._chk(min(rc, 0))
+        return rc
+
+    def autotune(self, reps: int = 5):
+        """Times every fused-kernel variant on the current state and keeps the fastest;
+        returns (choice, [ms per variant])."""
+        nv = len(self.rhs_variants())
+        ms = (C.c_float * nv)()
+        ch = C.c_int32(-1)
+        self._chk(lib().mrfv_autotune(self.h, self._p(self.U), self._p(self.U0), self._p(self.dt),
+                                      int(reps), ms, C.byref(ch)))
+        return ch.value, list(ms)
 
     def step_timing(self) -> dict:
         """Host clock of the adaptation phase, summed over adaptive steps (ms)."""

@@ -330,3 +330,43 @@ def test_multi_instance_batch(orc, torch_mod, batched):
         l1 = sum(np.abs(s_multi[k][0] - v[0]).sum() * pb.dx(k[0]) ** 3 for k, v in ol.items())
         print(f"instance {i} ({pb.name}): L1 rho vs oracle {l1:.3e}")
         assert l1 <= 1e-5
+
+
+def test_rhs_variants_bitwise_and_autotune(torch_mod):
+    """Every launch shape of the fused kernel gives bitwise the same run (eager and graph
+    launches); the autotuner leaves the state untouched and keeps a valid variant."""
+    from paper_2012_04385_amd.mrfv import Solver
+    pb = W.blast_mr3(steps=3)
+    ref = None
+    shapes = None
+    for batched in (1, 2):
+        g0 = Solver([pb], dtype="f32", batched=batched).init()
+        shapes = g0.rhs_variants()
+        assert len(shapes) >= 4 and all(t >= 256 and 16 % gp == 0 for gp, t in shapes)
+        del g0
+        for v in range(len(shapes)):
+            g = Solver([pb], dtype="f32", batched=batched).init()
+            assert g.set_rhs_variant(v) == v
+            for _ in range(3):
+                g.step()
+            g.check()
+            s = g.leaf_states()
+            if ref is None:
+                ref = s
+            assert s.keys() == ref.keys()
+            for k in s:
+                assert np.array_equal(s[k], ref[k]), (batched, v, shapes[v], k)
+    g = Solver([pb], dtype="f32", batched=2).init()
+    g.step()
+    before = g.U.clone()
+    choice, ms = g.autotune(reps=2)
+    assert torch_mod.equal(before, g.U)
+    assert 0 <= choice < len(shapes) and len(ms) == len(shapes) and all(m > 0 for m in ms)
+    assert ms[choice] == min(ms)
+    print(f"autotune: {choice} {shapes[choice]}, ms {ms}")
+    g.step()
+    g.step()
+    g.check()
+    s = g.leaf_states()
+    for k in s:
+        assert np.array_equal(s[k], ref[k]), k
