@@ -126,7 +126,13 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 plain comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device copy of 512 MiB (calibrates HBM byte counters)")
+    ap.add_argument("--proposer-gain", action="store_true",
+                    help="only run the learned-proposer gain test (6-level shock-blobs workload)")
     args = ap.parse_args()
+    if args.proposer_gain:
+        from paper_2012_04385_amd.proposer import gain_test
+        print(json.dumps(gain_test(log=log)), flush=True)
+        return
     if args.copy_calibration:
         import torch
         src = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda:0")

@@ -183,6 +183,15 @@ int mrfv_coarsen_block(mrfv_ctx *ctx, int32_t instance, int32_t level, int32_t b
 int mrfv_enable_kernel_timing(mrfv_ctx *ctx, int32_t on);
 int mrfv_kernel_time(mrfv_ctx *ctx, int64_t *launches, double *total_ms, int64_t *cells);
 
+/* fused_stage -- one SSP-RK3 stage of the batched FP32 path exactly as mrfv_step runs it:
+ * mr_project and the stage halo fill on Uin (regions without a same-level neighbour),
+ * then the fused rhs + update kernel reading Uin (same-level neighbours' interiors in
+ * place) and writing the leaves' new interiors to Uout, with the jump correction.  Uin,
+ * Uout: dev, state_bytes each, distinct; U0: dev, interior_bytes (written at stage 0, read
+ * at stages 1 and 2); dt_dev: dev double[n_instances].  Batched FP32 contexts only. */
+int mrfv_fused_stage(mrfv_ctx *ctx, int32_t stage, const double *dt_dev, void *Uin, void *Uout,
+                     void *U0);
+
 /* Launch shapes of the fused rhs + update kernel (batched FP32 path): variant v groups
  * the block's z-planes by shapes_host[2v] and uses shapes_host[2v+1] threads per
  * workgroup; every variant gives bitwise the same result.  rhs_variant sets the variant
@@ -271,8 +280,9 @@ int mrfv_set_proposer(mrfv_ctx *ctx, mrfv_mlp *mlp, int32_t mode);
  * labels of the proposer.  Zero before the first adaptive step.  Synchronises the stream. */
 int mrfv_last_flags(mrfv_ctx *ctx, int8_t *flags_host);
 
-/* proposer_stats -- out_host int64[11] = (steps, hits, then for refine, keep, coarsen:
- * true positives, false positives, false negatives); build_ms_host (may be NULL): host
+/* proposer_stats -- out_host int64[13] = (steps, hits, then for refine, keep, coarsen:
+ * true positives, false positives, false negatives, then steps whose proposal changed the
+ * tree and was staged, staged proposals adopted); build_ms_host (may be NULL): host
  * milliseconds spent decoding and staging proposals. */
 int mrfv_proposer_stats(mrfv_ctx *ctx, int64_t *out_host, double *build_ms_host);
 

@@ -98,6 +98,10 @@ def lib():
         L.orc_mlp_loss_grad.argtypes = [pd, pd, C.POINTER(C.c_int32), pd, C.c_int, C.c_int, pd]
         L.orc_mlp_loss_grad.restype = d
         L.orc_features.argtypes = [pd, d, d, d, d, d, pd]
+        L.orc_block_rhs.argtypes = [pd, d, d, d, pd]
+        L.orc_block_rhs.restype = None
+        L.orc_block_detail.argtypes = [pd, pd, C.c_int, C.c_int, C.c_int, d, d]
+        L.orc_block_detail.restype = d
         _LIB = L
     return _LIB
 
@@ -214,6 +218,23 @@ def features(u_padded, gamma, B, s_rho, s_p, eps_l) -> np.ndarray:
     out = np.zeros(192)
     lib().orc_features(_dp(u), gamma, B, s_rho, s_p, eps_l, _dp(out))
     return out
+
+
+def block_rhs(u_padded, gamma, B, dx) -> np.ndarray:
+    """-div F of one padded block [5,24,24,24] -> [5,16,16,16] (no jump correction)."""
+    u = np.ascontiguousarray(u_padded, dtype=np.float64)
+    assert u.shape == (5, P, P, P)
+    out = np.zeros((5, 16, 16, 16))
+    lib().orc_block_rhs(_dp(u), gamma, B, dx, _dp(out))
+    return out
+
+
+def block_detail(u_padded, parent_padded, octant, s_rho, s_E) -> float:
+    u = np.ascontiguousarray(u_padded, dtype=np.float64)
+    pu = np.ascontiguousarray(parent_padded, dtype=np.float64)
+    assert u.shape == (5, P, P, P) and pu.shape == (5, P, P, P)
+    return lib().orc_block_detail(_dp(u), _dp(pu), int(octant[0]), int(octant[1]), int(octant[2]),
+                                  s_rho, s_E)
 
 
 # ------------------------------------------------------------------ simulation -------

@@ -117,6 +117,14 @@ void orc_sim_blocks(const orc_sim *s, int64_t *info);
 /* Padded state of block idx (order of orc_sim_blocks), 5*24^3 values. */
 void orc_sim_get_block(const orc_sim *s, int32_t idx, double *out);
 void orc_sim_set_block(orc_sim *s, int32_t idx, const double *in);
+/* Per-block pieces of the step for sampled checks at full size (same code as the
+ * simulation's): the right-hand side -div F of one padded block (no jump correction),
+ * L[5][16][16][16], with cell size dx; and the detail of eq:DetailFunction of a padded
+ * child block against its padded parent (octant ox, oy, oz). */
+void orc_block_rhs(const double *u_padded, double gamma, double B, double dx, double *L);
+double orc_block_detail(const double *u_padded, const double *parent_padded, int ox, int oy,
+                        int oz, double s_rho, double s_E);
+
 /* Last detail value of block idx (-1 for level 0). */
 double orc_sim_detail(const orc_sim *s, int32_t idx);
 

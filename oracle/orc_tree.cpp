@@ -409,24 +409,31 @@ bool physical(const orc_sim *s, const Block *b) {
     return true;
 }
 
-double block_detail(orc_sim *s, Block *b) {
-    Block *par = parent_of(s, b);
-    const int ox = b->bx & 1, oy = b->by & 1, oz = b->bz & 1;
+// eq:DetailFunction on the padded block: max over the 24^3 cells and q in {rho, E} of
+// |u - P(u_parent)| / scale_q.
+double detail_of(const double *u, const double *parent, int ox, int oy, int oz, double s_rho,
+                 double s_E) {
     double d = 0.0;
     const int qs[2] = {0, 4};
-    const double sc[2] = {s->p.scale_rho, s->p.scale_E};
+    const double sc[2] = {s_rho, s_E};
     for (int n = 0; n < 2; ++n) {
         const int q = qs[n];
-        const double *pu = par->u.data() + q * CELLS;
+        const double *pu = parent + q * CELLS;
         for (int k = 0; k < P; ++k)
             for (int j = 0; j < P; ++j)
                 for (int i = 0; i < P; ++i) {
                     const double pred = orc_predict_cell(pu, ox, oy, oz, i, j, k);
-                    const double v = std::fabs(b->u[at(q, k, j, i)] - pred) / sc[n];
+                    const double v = std::fabs(u[at(q, k, j, i)] - pred) / sc[n];
                     d = std::max(d, v);
                 }
     }
     return d;
+}
+
+double block_detail(orc_sim *s, Block *b) {
+    Block *par = parent_of(s, b);
+    return detail_of(b->u.data(), par->u.data(), b->bx & 1, b->by & 1, b->bz & 1, s->p.scale_rho,
+                     s->p.scale_E);
 }
 
 void compute_details(orc_sim *s) {
@@ -648,6 +655,23 @@ void orc_sim_set_block(orc_sim *s, int32_t idx, const double *in) {
 }
 
 double orc_sim_detail(const orc_sim *s, int32_t idx) { return s->order[idx]->detail; }
+
+void orc_block_rhs(const double *u_padded, double gamma, double B, double dx, double *L) {
+    orc_sim tmp;
+    tmp.p.gamma = gamma;
+    tmp.p.B = B;
+    tmp.p.dx0 = dx;
+    Block b;
+    b.level = 0;
+    b.u.assign(u_padded, u_padded + 5 * CELLS);
+    block_rhs(&tmp, &b);
+    std::memcpy(L, b.rhs.data(), sizeof(double) * 5 * ICELLS);
+}
+
+double orc_block_detail(const double *u_padded, const double *parent_padded, int ox, int oy, int oz,
+                        double s_rho, double s_E) {
+    return detail_of(u_padded, parent_padded, ox, oy, oz, s_rho, s_E);
+}
 
 int orc_sim_refine(orc_sim *s, int32_t level, int32_t bx, int32_t by, int32_t bz) {
     Block *b = find(s, level, bx, by, bz);

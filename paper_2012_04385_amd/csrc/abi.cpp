@@ -616,9 +616,11 @@ int do_step(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt) {
         bool change = false;
         for (int32_t sl : leaves) change = change || ctx->proposal[sl] != 0;
         if (hit) ctx->p_hits++;
+        if (ctx->staged) ctx->p_staged++;
         if (hit && !change) {
             // nothing to commit
         } else if (hit && ctx->staged) {
+            ctx->p_adopted++;
             CALL(adopt_staged(ctx, fresh));
         } else {
             CALL(commit(ctx, ctx->h_flags, fresh));
@@ -982,6 +984,19 @@ int mrfv_set_proposer(mrfv_ctx *ctx, mrfv_mlp *mlp, int32_t mode) {
     return MRFV_OK;
 }
 
+int mrfv_fused_stage(mrfv_ctx *ctx, int32_t stage, const double *dt_dev, void *Uin, void *Uout,
+                     void *U0) {
+    CALL(need_init(ctx));
+    if (!(ctx->cfg.batched && ctx->cfg.dtype == MRFV_F32))
+        return fail(ctx, MRFV_EINVAL, "fused_stage: batched FP32 contexts only");
+    if (stage < 0 || stage > 2) return fail(ctx, MRFV_EINVAL, "fused_stage: stage must be 0..2");
+    if (!dt_dev || !Uin || !Uout || !U0) return fail(ctx, MRFV_EINVAL, "fused_stage: null pointer");
+    if (Uin == Uout) return fail(ctx, MRFV_EINVAL, "fused_stage: Uin and Uout must differ");
+    CALL(do_project<float>(ctx, (float *)Uin));
+    CALL(do_fill<float>(ctx, (float *)Uin, 1 << 20, FILL_MISSING_FACES));
+    return do_stage_fused(ctx, stage, dt_dev, (const float *)Uin, (float *)Uout, (float *)U0);
+}
+
 int mrfv_rhs_variant(mrfv_ctx *ctx, int32_t set, int32_t *n_variants, int32_t *shapes) {
     if (!ctx) return MRFV_EINVAL;
     const int n = rhs_variants();
@@ -1070,6 +1085,8 @@ int mrfv_proposer_stats(mrfv_ctx *ctx, int64_t *out, double *build_ms) {
         out[3 + 3 * c] = ctx->p_fp[c];
         out[4 + 3 * c] = ctx->p_fn[c];
     }
+    out[11] = ctx->p_staged;
+    out[12] = ctx->p_adopted;
     if (build_ms) *build_ms = ctx->p_build_ms;
     return MRFV_OK;
 }

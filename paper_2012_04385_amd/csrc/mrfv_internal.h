@@ -253,6 +253,7 @@ struct mrfv_ctx {
     hipStream_t side = nullptr;        // staging uploads
     hipEvent_t ev_prop = nullptr;      // proposal copied to the host
     int64_t p_steps = 0, p_hits = 0, p_tp[3] = {0, 0, 0}, p_fp[3] = {0, 0, 0}, p_fn[3] = {0, 0, 0};
+    int64_t p_staged = 0, p_adopted = 0;
     double p_build_ms = 0.0;
     // host time of the adaptation phase of mrfv_step: waiting for the judged flags, tree
     // commit + table build + upload (or adoption of staged tables), prediction; steps

@@ -96,6 +96,7 @@ def lib():
         "mrfv_last_flags": ([vp, C.POINTER(C.c_int8)], C.c_int),
         "mrfv_step_timing": ([vp, C.POINTER(d)], C.c_int),
         "mrfv_rhs_variant": ([vp, i32, C.POINTER(i32), C.POINTER(i32)], C.c_int),
+        "mrfv_fused_stage": ([vp, i32, vp, vp, vp, vp], C.c_int),
         "mrfv_autotune": ([vp, vp, vp, vp, i32, C.POINTER(C.c_float), C.POINTER(i32)], C.c_int),
     }
     for name, (args, res) in sig.items():
@@ -117,7 +118,8 @@ def exported_symbols():
             "mrfv_mlp_last_error", "mrfv_mlp_nparams", "mrfv_mlp_set_params",
             "mrfv_mlp_get_params", "mrfv_mlp_forward", "mrfv_mlp_loss_grad",
             "mrfv_mlp_adam_step", "mrfv_features", "mrfv_set_proposer", "mrfv_proposer_stats",
-            "mrfv_last_flags", "mrfv_step_timing", "mrfv_rhs_variant", "mrfv_autotune"]
+            "mrfv_last_flags", "mrfv_step_timing", "mrfv_rhs_variant", "mrfv_autotune",
+            "mrfv_fused_stage"]
 
 
 def morton_encode(shadow, level, bx, by, bz) -> int:
@@ -323,6 +325,12 @@ class Solver:
     def leaf_cells(self) -> int:
         return self.stats()[2]
 
+    def fused_stage(self, stage: int, Uout, Uin=None):
+        """One stage of the batched FP32 path from Uin (default: the state) into Uout."""
+        Uin = self.U if Uin is None else Uin
+        self._chk(lib().mrfv_fused_stage(self.h, int(stage), self._p(self.dt), self._p(Uin),
+                                         self._p(Uout), self._p(self.U0)))
+
     def rhs_variants(self):
         """[(z-planes per group, threads per workgroup)] of the fused kernel's variants."""
         n = C.c_int32(0)
@@ -503,10 +511,10 @@ def collect_training_data(solver: "Solver", steps: int):
 
 
 def proposer_stats(solver: "Solver") -> dict:
-    out = (C.c_int64 * 11)()
+    out = (C.c_int64 * 13)()
     ms = C.c_double(0.0)
     solver._chk(lib().mrfv_proposer_stats(solver.h, out, C.byref(ms)))
     v = list(out)
     per = {name: dict(tp=v[2 + 3 * c], fp=v[3 + 3 * c], fn=v[4 + 3 * c])
            for c, name in enumerate(("refine", "keep", "coarsen"))}
-    return dict(steps=v[0], hits=v[1], build_ms=ms.value, **per)
+    return dict(steps=v[0], hits=v[1], staged=v[11], adopted=v[12], build_ms=ms.value, **per)
