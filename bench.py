@@ -29,9 +29,9 @@ PEAK_FP32_VECTOR = 157.3e12       # MI355X FP32 vector (FLOP/s)
 PEAK_HBM = 8.0e12                 # bytes/s
 
 
-def counted_traffic():
-    """HBM bytes per launch of the fused kernel from the committed counter summary, or
-    None when the kernel source changed since the counters were taken."""
+def counted_traffic(kernel: str):
+    """HBM bytes per launch of the given fused-kernel variant from the committed counter
+    summary, or None when the kernel source changed since the counters were taken."""
     import hashlib
     try:
         prof = json.load(open(os.path.join(ROOT, "profiles", "rhs_update_blast128_counters.json")))
@@ -40,7 +40,7 @@ def counted_traffic():
         return None
     if hashlib.sha256(src).hexdigest()[:16] != prof["source_sha256_16"]:
         return None
-    return prof["traffic_bytes_per_dispatch"]
+    return prof.get("traffic_bytes_per_dispatch", {}).get(kernel)
 
 
 def flops_per_cell_update(llf_fraction: float) -> float:
@@ -199,9 +199,11 @@ def main():
     cells_per_launch = kcells / max(launches, 1)
     fpc = flops_per_cell_update(llf)
     achieved = cells_per_launch * fpc / avg_s
+    gp, tpb = tuned["shapes"][tuned["choice"]]
+    kname = f"k_rhs_update<float, {gp}, {tpb}>"
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
-            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR, "traffic": counted_traffic(),
-            "kernel": "k_rhs_update<float>", "avg_launch_ms": avg_s * 1e3,
+            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR, "traffic": counted_traffic(kname),
+            "kernel": kname, "avg_launch_ms": avg_s * 1e3,
             "cells_per_launch": cells_per_launch, "flop_per_cell_update": fpc,
             "llf_fraction": llf}
     ms_step = 1e3 * secs / args.steps

@@ -70,24 +70,33 @@ __device__ __forceinline__ void derive_state(const Gas<T> &G, CellState<T> &s) {
     s.sr = sqrt_(s.r);
 }
 
-// WENO5-JS value at the right face of c from (a,b,c,d,e); weights 0.1/0.6/0.3,
-// eps = 1e-6, power 2.  alpha_k = d_k / e_k^2 is normalised with one reciprocal:
-// the common factor e0^2 e1^2 e2^2 cancels.
+// WENO5-JS value at the right face of c from (a,b,c,d,e); linear weights 0.1/0.6/0.3,
+// eps = 1e-6, power 2 (Jiang & Shu), written with the first differences
+// w0 = b-a, u = c-b, v = d-c, w3 = e-d:
+//   candidate k = c + r_k / 6 with r = (5u - 2 w0, u + 2v, 4v - w3),
+//   smoothness beta_k = 13/12 (t_k^2 + 3/13 s_k^2) with t = (u - w0, v - u, w3 - v),
+//   s = (t0 + 2u, u + v, t2 - 2v).
+// alpha_k = d_k / (eps + beta_k)^2 is normalised with one reciprocal: the common factor
+// prod_j (eps + beta_j)^2 (13/12)^-2 cancels, so the value is
+//   c + sum_k d_k r_k prod_{j != k} e_j^2 / (6 sum_k d_k prod_{j != k} e_j^2)
+// with e_k = 12/13 eps + t_k^2 + 3/13 s_k^2.  A constant stencil returns c exactly.
 template <typename T>
 __device__ __forceinline__ T weno5(T a, T b, T c, T d, T e) {
-    const T q0 = ((T)2 * a - (T)7 * b + (T)11 * c) * (T)(1.0 / 6.0);
-    const T q1 = (-b + (T)5 * c + (T)2 * d) * (T)(1.0 / 6.0);
-    const T q2 = ((T)2 * c + (T)5 * d - e) * (T)(1.0 / 6.0);
-    const T t0 = a - (T)2 * b + c, s0 = a - (T)4 * b + (T)3 * c;
-    const T t1 = b - (T)2 * c + d, s1 = b - d;
-    const T t2 = c - (T)2 * d + e, s2 = (T)3 * c - (T)4 * d + e;
-    const T k13 = (T)(13.0 / 12.0);
-    const T e0 = (T)1e-6 + (k13 * t0 * t0 + (T)0.25 * s0 * s0);
-    const T e1 = (T)1e-6 + (k13 * t1 * t1 + (T)0.25 * s1 * s1);
-    const T e2 = (T)1e-6 + (k13 * t2 * t2 + (T)0.25 * s2 * s2);
+    const T w0 = b - a, u = c - b, v = d - c, w3 = e - d;
+    const T t0 = u - w0, s0 = fma((T)2, u, t0);
+    const T t1 = v - u, s1 = u + v;
+    const T t2 = w3 - v, s2 = fma((T)-2, v, t2);
+    const T eps = (T)(1e-6 * 12.0 / 13.0), k = (T)(3.0 / 13.0);
+    const T e0 = fma(t0, t0, fma(s0 * k, s0, eps));
+    const T e1 = fma(t1, t1, fma(s1 * k, s1, eps));
+    const T e2 = fma(t2, t2, fma(s2 * k, s2, eps));
     const T E0 = e0 * e0, E1 = e1 * e1, E2 = e2 * e2;
-    const T a0 = (T)0.1 * (E1 * E2), a1 = (T)0.6 * (E0 * E2), a2 = (T)0.3 * (E0 * E1);
-    return (a0 * q0 + a1 * q1 + a2 * q2) * rcp_(a0 + a1 + a2);
+    const T E12 = E1 * E2, E02 = E0 * E2, E01 = E0 * E1;
+    // d_k r_k and 6 d_k scaled by 10: (1, 6, 3) r_k and (6, 36, 18)
+    const T r0 = fma((T)5, u, (T)-2 * w0), r1 = fma((T)6, u, (T)12 * v), r2 = fma((T)12, v, (T)-3 * w3);
+    const T num = fma(E12, r0, fma(E02, r1, E01 * r2));
+    const T den = fma(E12, (T)6, fma(E02, (T)36, E01 * (T)18));
+    return fma(num, rcp_(den), c);
 }
 
 // Characteristic flux of one field: upwind by the two face cells' eigenvalues, else LLF.
@@ -110,6 +119,10 @@ __device__ __forceinline__ T char_flux(const T W[6], const T G[6], T lL, T lR) {
 // upwind-right lanes and g+ = 0, g- = g for upwind-left lanes (a WENO of zeros is exactly
 // zero); otherwise one WENO with the input order picked per lane.  Bitwise equal to
 // char_flux, but mixed waves no longer execute all three branches.
+// The split is formed as g+ = cp G + ap W, g- = cm G + am W with per-lane coefficients
+// (1,0,0,0) upwind-right, (0,0,1,0) upwind-left, (1/2, a/2, 1/2, -a/2) LLF: one multiply
+// and one fused multiply-add per value instead of selects, and the same values (halving
+// is exact, so fma(a/2, W, G/2) rounds like (G + a W)/2).
 template <typename T>
 __device__ __forceinline__ T char_flux_uniform(const T W[6], const T G[6], T lL, T lR) {
     const bool up = lL > (T)0 && lR > (T)0;
@@ -121,14 +134,14 @@ __device__ __forceinline__ T char_flux_uniform(const T W[6], const T G[6], T lL,
         for (int j = 0; j < 5; ++j) a[j] = up ? G[j] : G[5 - j];
         return weno5(a[0], a[1], a[2], a[3], a[4]);
     }
-    const T al = fmax(fabs(lL), fabs(lR));
+    const T ha = (T)0.5 * fmax(fabs(lL), fabs(lR));
+    const T cp = up ? (T)1 : (dn ? (T)0 : (T)0.5), cm = dn ? (T)1 : (up ? (T)0 : (T)0.5);
+    const T ap = llf ? ha : (T)0, am = -ap;
     T gp[6], gm[6];
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
-        const T p = (T)0.5 * (G[j] + al * W[j]);
-        const T m = (T)0.5 * (G[j] - al * W[j]);
-        gp[j] = up ? G[j] : (dn ? (T)0 : p);
-        gm[j] = dn ? G[j] : (up ? (T)0 : m);
+        gp[j] = fma(ap, W[j], cp * G[j]);
+        gm[j] = fma(am, W[j], cm * G[j]);
     }
     return weno5(gp[0], gp[1], gp[2], gp[3], gp[4]) + weno5(gm[5], gm[4], gm[3], gm[2], gm[1]);
 }
@@ -149,6 +162,8 @@ __device__ __forceinline__ void face_flux(const CellState<T> w[6], const Gas<T> 
     const T ic = rcp_(c);
     const T b1 = G.gm1 * ic * ic;
     const T b2 = (T)0.5 * q2 * b1;
+    // halved coefficients (exact): tU, xU, tF, xF below hold t/2 and x/2
+    const T hb1 = (T)0.5 * b1, hb2 = (T)0.5 * b2, hic = (T)0.5 * ic;
 
     // Projection onto the left eigenvectors: with t = b2 a0 + b1 (a4 - u a1 - v a2 - w a3)
     // and x = (a1 - u a0)/c the five components are (t-x)/2, a0-t, a2-v a0, a3-w a0, (t+x)/2.
@@ -158,10 +173,10 @@ __device__ __forceinline__ void face_flux(const CellState<T> w[6], const Gas<T> 
         const CellState<T> &s = w[j];
         const T un = s.mn * s.ir;
         const T f1 = s.mn * un + s.p, f2 = s.mt1 * un, f3 = s.mt2 * un, f4 = (s.E + s.p) * un;
-        tU[j] = b2 * s.r + b1 * (s.E - u * s.mn - v * s.mt1 - ww * s.mt2);
-        xU[j] = (s.mn - u * s.r) * ic;
-        tF[j] = b2 * s.mn + b1 * (f4 - u * f1 - v * f2 - ww * f3);
-        xF[j] = (f1 - u * s.mn) * ic;
+        tU[j] = hb2 * s.r + hb1 * (s.E - u * s.mn - v * s.mt1 - ww * s.mt2);
+        xU[j] = (s.mn - u * s.r) * hic;
+        tF[j] = hb2 * s.mn + hb1 * (f4 - u * f1 - v * f2 - ww * f3);
+        xF[j] = (f1 - u * s.mn) * hic;
         a0[j] = s.r;
         f0[j] = s.mn;
         wt1[j] = s.mt1 - v * s.r;
@@ -173,19 +188,19 @@ __device__ __forceinline__ void face_flux(const CellState<T> w[6], const Gas<T> 
     T W[6], Gc[6], g[5];
     // field 1: u - c
 #pragma unroll
-    for (int j = 0; j < 6; ++j) { W[j] = (T)0.5 * (tU[j] - xU[j]); Gc[j] = (T)0.5 * (tF[j] - xF[j]); }
+    for (int j = 0; j < 6; ++j) { W[j] = tU[j] - xU[j]; Gc[j] = tF[j] - xF[j]; }
 #define MRFV_CF(W_, G_, a_, b_) (UNIFORM ? char_flux_uniform(W_, G_, a_, b_) : char_flux(W_, G_, a_, b_))
     g[0] = MRFV_CF(W, Gc, unL - L.c, unR - R.c);
     // field 2: entropy, u
 #pragma unroll
-    for (int j = 0; j < 6; ++j) { W[j] = a0[j] - tU[j]; Gc[j] = f0[j] - tF[j]; }
+    for (int j = 0; j < 6; ++j) { W[j] = fma((T)-2, tU[j], a0[j]); Gc[j] = fma((T)-2, tF[j], f0[j]); }
     g[1] = MRFV_CF(W, Gc, unL, unR);
     // fields 3, 4: shear, u
     g[2] = MRFV_CF(wt1, gt1, unL, unR);
     g[3] = MRFV_CF(wt2, gt2, unL, unR);
     // field 5: u + c
 #pragma unroll
-    for (int j = 0; j < 6; ++j) { W[j] = (T)0.5 * (tU[j] + xU[j]); Gc[j] = (T)0.5 * (tF[j] + xF[j]); }
+    for (int j = 0; j < 6; ++j) { W[j] = tU[j] + xU[j]; Gc[j] = tF[j] + xF[j]; }
     g[4] = MRFV_CF(W, Gc, unL + L.c, unR + R.c);
 #undef MRFV_CF
 
