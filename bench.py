@@ -117,6 +117,64 @@ def cpu_baseline(pb, budget_s=15.0, max_steps=10):
         sum(llf) / len(llf)
 
 
+def other_workload(args):
+    """Throughput of the FP32 batched path (stage graph, autotuned shape) on a larger
+    workload; the fused kernel's duration from HIP events on an eager run."""
+    import torch
+    from paper_2012_04385_amd import workloads as W
+    from paper_2012_04385_amd.mrfv import Solver
+    pbs = {"kh_256e_5lvl": lambda: [W.kh_mr5(steps=args.warmup + args.steps)],
+           "multi_256": lambda: W.multi_instance(steps=args.warmup + args.steps),
+           "shockblobs_512e_6lvl": lambda: [W.shock_blobs_mr6(steps=args.warmup + args.steps)]}[args.workload]()
+    res = {}
+    for batched, timing in ((2, False), (1, True)):
+        g = Solver(pbs, dtype="f32", batched=batched).init()
+        for _ in range(args.warmup):
+            g.step()
+        g.check()
+        if batched == 2:
+            choice, ms = g.autotune(reps=3)
+            res["autotune"] = {"choice": choice, "shapes": g.rhs_variants(), "ms_per_launch": ms}
+        else:
+            g.set_rhs_variant(res["autotune"]["choice"])
+            g.enable_kernel_timing(True)
+            g.kernel_time()
+        torch.cuda.synchronize()
+        cells = 0
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            cells += 3 * g.leaf_cells()
+            g.step()
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        g.check()
+        res[batched] = (cells / secs, 1e3 * secs / args.steps, g.kernel_time() if timing else None,
+                        g.stats()[1], g.step_timing())
+        log(f"[bench] {args.workload} batched={batched}: {res[batched][0]:.4e} cell-updates/s, "
+            f"{res[batched][1]:.2f} ms/step")
+        del g
+        torch.cuda.empty_cache()
+    launches, total_ms, kcells = res[1][2]
+    avg_s = total_ms / 1e3 / max(launches, 1)
+    gp, tpb = res["autotune"]["shapes"][res["autotune"]["choice"]]
+    fpc = flops_per_cell_update(0.5)
+    achieved = kcells / max(launches, 1) * fpc / avg_s
+    out = {"metric": "cell-updates/s per RK stage (FP32 batched MR RK3)", "value": res[2][0],
+           "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": res[2][1], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": args.workload, "instances": len(pbs), "leaves_final": res[2][3],
+                      "path": "batched FP32, RK stages replayed from a hipGraph"},
+           "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
+                        "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR, "traffic": None,
+                        "kernel": f"k_rhs_update<float, {gp}, {tpb}>", "avg_launch_ms": avg_s * 1e3,
+                        "flop_model_llf_fraction": 0.5},
+           "cpu_baseline": None, "value_eager_launches": res[1][0], "autotune": res["autotune"],
+           "host_adaptation_ms_per_step": {k: v / max(res[2][4]["steps"], 1) for k, v in res[2][4].items()
+                                           if k != "steps"}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -128,6 +186,9 @@ def main():
                     help="only run a device copy of 512 MiB (calibrates HBM byte counters)")
     ap.add_argument("--proposer-gain", action="store_true",
                     help="only run the learned-proposer gain test (6-level shock-blobs workload)")
+    ap.add_argument("--workload", default="blast_128e_3lvl",
+                    choices=["blast_128e_3lvl", "kh_256e_5lvl", "multi_256", "shockblobs_512e_6lvl"],
+                    help="other workloads: FP32 batched throughput only (no FP64, no CPU leg)")
     args = ap.parse_args()
     if args.proposer_gain:
         from paper_2012_04385_amd.proposer import gain_test
@@ -151,6 +212,10 @@ def main():
     import numpy as np
     import torch
     from paper_2012_04385_amd import workloads as W
+
+    if args.workload != "blast_128e_3lvl":
+        other_workload(args)
+        return
 
     pb = W.blast_mr3(steps=args.warmup + args.steps)
     log(f"[bench] workload {pb.name}: FP32 batched, warmup {args.warmup}, timed {args.steps}")
