@@ -167,7 +167,8 @@ def other_workload(args):
                       "path": "batched FP32, RK stages replayed from a hipGraph"},
            "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
                         "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR, "traffic": None,
-                        "kernel": f"k_rhs_update<float, {gp}, {tpb}>", "avg_launch_ms": avg_s * 1e3,
+                        "kernel": f"k_rhs_update<float, {gp}, {abs(tpb)}, {'true' if tpb < 0 else 'false'}>",
+                        "avg_launch_ms": avg_s * 1e3,
                         "flop_model_llf_fraction": 0.5},
            "cpu_baseline": None, "value_eager_launches": res[1][0], "autotune": res["autotune"],
            "host_adaptation_ms_per_step": {k: v / max(res[2][4]["steps"], 1) for k, v in res[2][4].items()
@@ -265,7 +266,7 @@ def main():
     fpc = flops_per_cell_update(llf)
     achieved = cells_per_launch * fpc / avg_s
     gp, tpb = tuned["shapes"][tuned["choice"]]
-    kname = f"k_rhs_update<float, {gp}, {tpb}>"
+    kname = f"k_rhs_update<float, {gp}, {abs(tpb)}, {'true' if tpb < 0 else 'false'}>"
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
             "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR, "traffic": counted_traffic(kname),
             "kernel": kname, "avg_launch_ms": avg_s * 1e3,

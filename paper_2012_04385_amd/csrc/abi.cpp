@@ -136,13 +136,16 @@ int do_project(mrfv_ctx *ctx, T *U) {
 //   same-level neighbours in place);
 //   FILL_MISSING: all regions without a same-level neighbour (before the details, which
 //   read same-level neighbours in place too).
+// with_parents = false leaves the non-leaf blocks out (a stage on a tree where no leaf face
+// reads a parent-derived value).
 template <typename T>
-int do_fill(mrfv_ctx *ctx, T *U, int max_level, FillMode mode = FILL_ALL) {
+int do_fill(mrfv_ctx *ctx, T *U, int max_level, FillMode mode = FILL_ALL, bool with_parents = true) {
     for (int l = 0; l <= std::min(max_level, levels_to_cover(ctx)); ++l) {
         if (mode == FILL_ALL) {
             HIP_OK(launch_fill_halos<T>(U, wlist(ctx, desc_lvl(l), 1024), ctx->tb, FILL_ALL, ctx->stream));
         } else {
-            HIP_OK(launch_fill_halos<T>(U, wlist(ctx, desc_par(l), 1024), ctx->tb, FILL_ALL, ctx->stream));
+            if (with_parents)
+                HIP_OK(launch_fill_halos<T>(U, wlist(ctx, desc_par(l), 1024), ctx->tb, FILL_ALL, ctx->stream));
             const int which = mode == FILL_FACES ? desc_leaf(l)
                               : mode == FILL_MISSING_FACES ? desc_jleaf(l) : desc_jleaf26(l);
             HIP_OK(launch_fill_halos<T>(U, wlist(ctx, which, 1024), ctx->tb, mode, ctx->stream));
@@ -476,11 +479,13 @@ int do_stages(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt) {
                          ctx->d_blockred, dt, ctx->stream));
     if (ctx->cfg.batched && sizeof(T) == 4) {
         // fused stages, out of place: U -> W -> U -> W, then the leaves' interiors back
+        // parents are restricted and filled only if some leaf face reads them
         float *X = (float *)U, *W = (float *)ctx->d_W;
+        const bool par = ctx->lists.parents_needed;
         for (int s = 0; s < 3; ++s) {
             float *in = (s & 1) ? W : X, *out = (s & 1) ? X : W;
-            CALL(do_project<float>(ctx, in));
-            CALL(do_fill<float>(ctx, in, 1 << 20, FILL_MISSING_FACES));
+            if (par) CALL(do_project<float>(ctx, in));
+            CALL(do_fill<float>(ctx, in, 1 << 20, FILL_MISSING_FACES, par));
             CALL(do_stage_fused(ctx, s, dt, in, out, (float *)U0));
         }
         HIP_OK(launch_copy_interiors<float>(W, X, wlist(ctx, DESC_LEAVES, 4096), ctx->stream));
@@ -503,7 +508,8 @@ int do_stages(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt) {
 // contents are read on the device, so one graph serves every tree with the same key.
 uint64_t graph_key(const mrfv_ctx *ctx) {
     const HostLists &L = ctx->lists;
-    uint64_t k = (uint64_t)L.max_level | ((uint64_t)ctx->has_jumps << 4);
+    uint64_t k = (uint64_t)L.max_level | ((uint64_t)ctx->has_jumps << 4) |
+                 ((uint64_t)L.parents_needed << 63);
     for (int l = 0; l <= L.max_level && l < MAX_LEVELS; ++l) {
         if (L.desc[2 * desc_par(l) + 1] > 0) k |= 1ull << (5 + l);
         if (L.desc[2 * desc_jleaf(l) + 1] > 0) k |= 1ull << (5 + MAX_LEVELS + l);
@@ -992,8 +998,9 @@ int mrfv_fused_stage(mrfv_ctx *ctx, int32_t stage, const double *dt_dev, void *U
     if (stage < 0 || stage > 2) return fail(ctx, MRFV_EINVAL, "fused_stage: stage must be 0..2");
     if (!dt_dev || !Uin || !Uout || !U0) return fail(ctx, MRFV_EINVAL, "fused_stage: null pointer");
     if (Uin == Uout) return fail(ctx, MRFV_EINVAL, "fused_stage: Uin and Uout must differ");
-    CALL(do_project<float>(ctx, (float *)Uin));
-    CALL(do_fill<float>(ctx, (float *)Uin, 1 << 20, FILL_MISSING_FACES));
+    const bool par = ctx->lists.parents_needed;
+    if (par) CALL(do_project<float>(ctx, (float *)Uin));
+    CALL(do_fill<float>(ctx, (float *)Uin, 1 << 20, FILL_MISSING_FACES, par));
     return do_stage_fused(ctx, stage, dt_dev, (const float *)Uin, (float *)Uout, (float *)U0);
 }
 

@@ -19,6 +19,8 @@
 // (k_ff_restrict), and a coarse leaf next to a non-leaf same-level neighbour replaces its
 // own boundary flux by that average.  With one global dt per step the correction is
 // applied at every stage.
+#include <algorithm>
+
 #include "mrfv_internal.h"
 
 namespace mrfv {
@@ -31,6 +33,8 @@ __device__ __forceinline__ float rcp_(float x) { return __builtin_amdgcn_rcpf(x)
 __device__ __forceinline__ double rcp_(double x) { return 1.0 / x; }
 __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
+__device__ __forceinline__ float rsqrt_(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsqrt_(double x) { return 1.0 / sqrt(x); }
 
 template <typename T>
 struct Gas {
@@ -129,9 +133,12 @@ __device__ __forceinline__ T char_flux_uniform(const T W[6], const T G[6], T lL,
     const bool dn = lL < (T)0 && lR < (T)0;
     const bool llf = !(up || dn);
     if (!__any(llf)) {
+        // the stencil in upwind order, blended with 0/1 weights (exact for finite values):
+        // a select here is turned into a dynamically indexed array by the compiler
+        const T su = up ? (T)1 : (T)0, sd = (T)1 - su;
         T a[5];
 #pragma unroll
-        for (int j = 0; j < 5; ++j) a[j] = up ? G[j] : G[5 - j];
+        for (int j = 0; j < 5; ++j) a[j] = fma(su, G[j], sd * G[5 - j]);
         return weno5(a[0], a[1], a[2], a[3], a[4]);
     }
     const T ha = (T)0.5 * fmax(fabs(lL), fabs(lR));
@@ -158,8 +165,8 @@ __device__ __forceinline__ void face_flux(const CellState<T> w[6], const Gas<T> 
     const T H = wl * ((L.E + L.p) * L.ir) + wr * ((R.E + R.p) * R.ir);
     const T q2 = u * u + v * v + ww * ww;
     const T c2 = G.gm1 * (H - (T)0.5 * q2);
-    const T c = sqrt_(c2);
-    const T ic = rcp_(c);
+    const T ic = rsqrt_(c2);
+    const T c = c2 * ic;
     const T b1 = G.gm1 * ic * ic;
     const T b2 = (T)0.5 * q2 * b1;
     // halved coefficients (exact): tU, xU, tF, xF below hold t/2 and x/2
@@ -499,7 +506,7 @@ __device__ __forceinline__ void face_flux_at(const T *__restrict__ ub, const T *
     Fp[t2] = F[3];
 }
 
-template <typename T, int GP, int TPB_F>
+template <typename T, int GP, int TPB_F, bool PERSIST>
 __global__ __launch_bounds__(TPB_F) void k_rhs_update(int stage, const double *__restrict__ dt,
                                                       const T *__restrict__ Uin, T *__restrict__ Uout,
                                                       T *U0, WorkList wl,
@@ -511,10 +518,10 @@ __global__ __launch_bounds__(TPB_F) void k_rhs_update(int stage, const double *_
     __shared__ T Fx[GP][NI][NI + 1][5];   // [plane][y][face x][q]
     __shared__ T Fy[GP][NI + 1][NI][5];   // [plane][face y][x][q]
     __shared__ T Fz[GP + 1][NI][NI][5];   // [face plane][y][x][q]; plane j = face k0 + j - 1/2
-    // one workgroup per leaf (no grid-stride loop: it costs registers and occupancy);
-    // graph launches size the grid by the slot capacity and surplus groups exit here
-    const int b = blockIdx.x;
-    if (b >= wl.count()) return;
+    // one workgroup per leaf (graph launches size the grid by the slot capacity and
+    // surplus groups exit here), or, persistent, a fixed grid looping over the leaves
+    const int nleaf = wl.count();
+    auto block = [&](int b) __attribute__((always_inline)) {
     const int slot = wl.at(b);
     const BlockMeta mt = meta[slot];
     const InstDev P = inst[mt.inst];
@@ -634,6 +641,12 @@ __global__ __launch_bounds__(TPB_F) void k_rhs_update(int stage, const double *_
         __syncthreads();
     }
     if (!ok) atomicOr(err, 1);
+    };
+    if constexpr (PERSIST) {
+        for (int b = blockIdx.x; b < nleaf; b += gridDim.x) block(b);   // uniform per workgroup
+    } else if (blockIdx.x < nleaf) {
+        block(blockIdx.x);   // the loop-free form keeps the register count down
+    }
 }
 
 // Batched path: the jump correction applied to the already-updated state,
@@ -717,16 +730,24 @@ hipError_t launch_update(int stage, const double *dt, T *U, T *U0, const T *L, c
 }
 
 // Launch shapes of the fused kernel: (z-planes per group, threads per workgroup).
-constexpr int N_RHS_VARIANTS = 9;
-constexpr int RHS_GP[N_RHS_VARIANTS] = {2, 1, 2, 2, 4, 4, 2, 2, 1};
-constexpr int RHS_TPB[N_RHS_VARIANTS] = {320, 256, 256, 384, 320, 512, 448, 512, 320};
+// The last two variants are persistent: a grid of as many workgroups as fit on the 256
+// CUs at once (3 waves per SIMD at their register count) loops over the leaves instead
+// of one workgroup per leaf.
+constexpr int N_RHS_VARIANTS = 11;
+constexpr int RHS_GP[N_RHS_VARIANTS] = {2, 1, 2, 2, 4, 4, 2, 2, 1, 2, 2};
+constexpr int RHS_TPB[N_RHS_VARIANTS] = {320, 256, 256, 384, 320, 512, 448, 512, 320, 512, 384};
+constexpr bool RHS_PERSIST[N_RHS_VARIANTS] = {false, false, false, false, false, false, false, false,
+                                              false, true, true};
+constexpr int persist_grid(int tpb) { return 256 * (12 / (tpb / 64) > 0 ? 12 / (tpb / 64) : 1); }
 
 template <int V>
 static void launch_variant(int stage, const double *dt, const float *Uin, float *Uout, float *U0,
                     const WorkList &wl, const DevTables &tb, const InstDev *inst, float *FF,
                     int32_t *err, hipStream_t st) {
     constexpr int G = RHS_GP[V], B = RHS_TPB[V];
-    hipLaunchKernelGGL((k_rhs_update<float, G, B>), dim3(wl.grid), dim3(B), 0, st, stage, dt, Uin,
+    constexpr bool PS = RHS_PERSIST[V];
+    const int grid = PS ? std::min(wl.grid, persist_grid(B)) : wl.grid;
+    hipLaunchKernelGGL((k_rhs_update<float, G, B, PS>), dim3(grid), dim3(B), 0, st, stage, dt, Uin,
                        Uout, U0, wl, tb.meta, tb.nbr, inst, FF, err);
 }
 
@@ -734,7 +755,7 @@ int rhs_variants() { return N_RHS_VARIANTS; }
 
 void rhs_variant_shape(int v, int *gp, int *tpb) {
     *gp = RHS_GP[v];
-    *tpb = RHS_TPB[v];
+    *tpb = RHS_PERSIST[v] ? -RHS_TPB[v] : RHS_TPB[v];   // negative: persistent grid
 }
 
 hipError_t launch_rhs_update_f32(int variant, int stage, const double *dt, const float *Uin,
@@ -752,6 +773,8 @@ hipError_t launch_rhs_update_f32(int variant, int stage, const double *dt, const
         case 6: launch_variant<6>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, st); break;
         case 7: launch_variant<7>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, st); break;
         case 8: launch_variant<8>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, st); break;
+        case 9: launch_variant<9>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, st); break;
+        case 10: launch_variant<10>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, st); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

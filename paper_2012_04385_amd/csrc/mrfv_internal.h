@@ -69,6 +69,9 @@ struct HostLists {
     std::vector<int32_t> desc;
     int32_t all_blocks_off = 0, all_blocks_cnt = 0;      // every block
     int32_t fine_off = 0, fine_cnt = 0;                  // every block with level >= 1
+    // some leaf face reads a parent-derived value inside a stage: no same-level neighbour
+    // (predicted halo) or a non-leaf same-level neighbour (restricted interior)
+    bool parents_needed = false;
 };
 
 // ---------------------------------------------------------------- host topology ------

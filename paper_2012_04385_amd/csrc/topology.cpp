@@ -279,6 +279,18 @@ void Topology::build(std::vector<BlockMeta> &meta, std::vector<int32_t> &child,
         for (int s : order)
             if (blocks_[s].level == l && blocks_[s].leaf && needs_face_fill(s)) L.data.push_back(s);
         L.jleaf_cnt[l] = (int32_t)L.data.size() - L.jleaf_off[l];
+        for (int t = L.jleaf_off[l]; t < L.jleaf_off[l] + L.jleaf_cnt[l] && !L.parents_needed; ++t) {
+            const int sl = L.data[t];
+            for (int f = 0; f < 6; ++f)
+                if (!((meta[sl].zg >> f) & 1) && nbr[(size_t)sl * 27 + face_region[f]] < 0) L.parents_needed = true;
+        }
+        for (int s : order) {
+            if (blocks_[s].level != l || !blocks_[s].leaf || L.parents_needed) continue;
+            for (int f = 0; f < 6; ++f) {
+                const int nb = nbr[(size_t)s * 27 + face_region[f]];
+                if (nb >= 0 && !blocks_[nb].leaf) L.parents_needed = true;
+            }
+        }
         L.j26_off[l] = (int32_t)L.data.size();
         for (int s : order)
             if (blocks_[s].level == l && blocks_[s].leaf && needs_region_fill(s)) L.data.push_back(s);

@@ -332,7 +332,8 @@ class Solver:
                                          self._p(Uout), self._p(self.U0)))
 
     def rhs_variants(self):
-        """[(z-planes per group, threads per workgroup)] of the fused kernel's variants."""
+        """[(z-planes per group, threads per workgroup)] of the fused kernel's variants;
+        a negative thread count marks a persistent grid looping over the leaves."""
         n = C.c_int32(0)
         lib().mrfv_rhs_variant(self.h, -1, C.byref(n), None)
         shp = (C.c_int32 * (2 * n.value))()
