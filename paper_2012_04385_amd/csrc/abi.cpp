@@ -478,17 +478,16 @@ int do_stages(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt) {
     HIP_OK(launch_cfl<T>(U, wlist(ctx, DESC_LEAVES), ctx->tb, ctx->d_inst, (int)ctx->inst.size(),
                          ctx->d_blockred, dt, ctx->stream));
     if (ctx->cfg.batched && sizeof(T) == 4) {
-        // fused stages, out of place: U -> W -> U -> W, then the leaves' interiors back
+        // fused stages, out of place through two more state buffers: U -> W -> W2 -> U;
         // parents are restricted and filled only if some leaf face reads them
-        float *X = (float *)U, *W = (float *)ctx->d_W;
+        float *buf[4] = {(float *)U, (float *)ctx->d_W, (float *)ctx->d_W2, (float *)U};
         const bool par = ctx->lists.parents_needed;
         for (int s = 0; s < 3; ++s) {
-            float *in = (s & 1) ? W : X, *out = (s & 1) ? X : W;
+            float *in = buf[s], *out = buf[s + 1];
             if (par) CALL(do_project<float>(ctx, in));
             CALL(do_fill<float>(ctx, in, 1 << 20, FILL_MISSING_FACES, par));
             CALL(do_stage_fused(ctx, s, dt, in, out, (float *)U0));
         }
-        HIP_OK(launch_copy_interiors<float>(W, X, wlist(ctx, DESC_LEAVES, 4096), ctx->stream));
         return MRFV_OK;
     }
     for (int s = 0; s < 3; ++s) {
@@ -698,7 +697,8 @@ int mrfv_create(mrfv_ctx **out, const mrfv_config *cfg, const mrfv_instance *ins
     if (!(cfg->batched && cfg->dtype == MRFV_F32)) {
         ALLOC(ctx->d_D, cap * 3 * 5 * CELLS_I * es);
     } else {
-        ALLOC(ctx->d_W, cap * 5 * CELLS_P * es);   // second state buffer of the fused stages
+        ALLOC(ctx->d_W, cap * 5 * CELLS_P * es);    // second and third state buffers of the
+        ALLOC(ctx->d_W2, cap * 5 * CELLS_P * es);   // fused stages
     }
     ALLOC(ctx->d_desc, 2 * N_DESC * sizeof(int32_t));
     if (hipHostMalloc((void **)&ctx->h_flags, cap, 0) != hipSuccess ||
@@ -750,7 +750,7 @@ int mrfv_destroy(mrfv_ctx *ctx) {
         for (void *p : pp)
             if (p) hipFree(p);
     }
-    void *ptrs[] = {ctx->d_inst, ctx->d_err, ctx->d_D, ctx->d_W, ctx->d_FF, ctx->d_blockred, ctx->d_det,
+    void *ptrs[] = {ctx->d_inst, ctx->d_err, ctx->d_D, ctx->d_W, ctx->d_W2, ctx->d_FF, ctx->d_blockred, ctx->d_det,
                     ctx->d_flags, ctx->d_slots, ctx->d_slots2, ctx->d_prim, ctx->tb.meta, ctx->tb.child,
                     ctx->tb.nbr, ctx->tb.lists, ctx->d_desc};
     for (void *p : ptrs)

@@ -285,11 +285,12 @@ __global__ __launch_bounds__(TPB) void k_predict(T *__restrict__ U,
 // Cells outside the interior are read from the same-level neighbour's interior where
 // one exists (else from the own halo, filled for such regions).
 constexpr int DZ = 4;                          // slabs per block
+constexpr int DTPB = 512;                      // threads per workgroup (LDS allows 2 per CU)
 constexpr int SZ = NP / DZ;                    // padded z-planes per slab (6)
 constexpr int PZ = SZ / 2 + 4;                 // parent planes per slab (7)
 
 template <typename T>
-__global__ __launch_bounds__(TPB) void k_details(const T *__restrict__ U, WorkList wl,
+__global__ __launch_bounds__(DTPB) void k_details(const T *__restrict__ U, WorkList wl,
                                                  const BlockMeta *__restrict__ meta,
                                                  const int32_t *__restrict__ nbr,
                                                  const InstDev *__restrict__ inst,
@@ -299,7 +300,7 @@ __global__ __launch_bounds__(TPB) void k_details(const T *__restrict__ U, WorkLi
     __shared__ double Bx[PZ * R * NP];          // x pass (21 KB)
     __shared__ double By[PZ * NP * NP];         // y pass (32 KB)
     __shared__ long long src27[27];             // element offsets of the 27 sources
-    __shared__ double red[TPB / 64];
+    __shared__ double red[DTPB / 64];
     const int nb = wl.count();
     const int part = blockIdx.y;
     const int k_lo = part * SZ;                 // first padded output plane
@@ -325,19 +326,19 @@ __global__ __launch_bounds__(TPB) void k_details(const T *__restrict__ U, WorkLi
         const int q = v == 0 ? 0 : 4;
         const double inv_s = v == 0 ? 1.0 / P.scale_rho : 1.0 / P.scale_E;
         // parent padded cells (oz*8 + kk0 + kk, oy*8 + jj, ox*8 + ii)
-        for (int t = threadIdx.x; t < PZ * R * R; t += TPB) {
+        for (int t = threadIdx.x; t < PZ * R * R; t += DTPB) {
             const int ii = t & 15, jj = (t >> 4) & 15, kk = t >> 8;
             A[t] = (double)pu[q * CELLS_P + pidx(0, oz * 8 + kk0 + kk, oy * 8 + jj, ox * 8 + ii)];
         }
         __syncthreads();
-        for (int t = threadIdx.x; t < PZ * R * NP; t += TPB) {
+        for (int t = threadIdx.x; t < PZ * R * NP; t += DTPB) {
             const int i = t % NP, r = t / NP;
             const int ci = i - HW, II = (ci >> 1) + HW;
             const double *row = A + r * R + II;
             Bx[t] = pred1<double>(row[-2], row[-1], row[0], row[1], row[2], (ci & 1) ? -1.0 : 1.0);
         }
         __syncthreads();
-        for (int t = threadIdx.x; t < PZ * NP * NP; t += TPB) {
+        for (int t = threadIdx.x; t < PZ * NP * NP; t += DTPB) {
             const int i = t % NP, j = (t / NP) % NP, kk = t / (NP * NP);
             const int cj = j - HW, JJ = (cj >> 1) + HW;
             const double *col = Bx + (kk * R + JJ) * NP + i;
@@ -345,7 +346,7 @@ __global__ __launch_bounds__(TPB) void k_details(const T *__restrict__ U, WorkLi
                                   (cj & 1) ? -1.0 : 1.0);
         }
         __syncthreads();
-        for (int cell = threadIdx.x; cell < SZ * NP * NP; cell += TPB) {
+        for (int cell = threadIdx.x; cell < SZ * NP * NP; cell += DTPB) {
             const int i = cell % NP, j = (cell / NP) % NP, k = k_lo + cell / (NP * NP);
             const int ck = k - HW, KK = (ck >> 1) + HW - kk0;
             const double *c = By + (KK * NP + j) * NP + i;
@@ -365,7 +366,7 @@ __global__ __launch_bounds__(TPB) void k_details(const T *__restrict__ U, WorkLi
     __syncthreads();
     if (threadIdx.x == 0) {
         double mx = red[0];
-        for (int w = 1; w < TPB / 64; ++w) mx = fmax(mx, red[w]);
+        for (int w = 1; w < DTPB / 64; ++w) mx = fmax(mx, red[w]);
         atomicMax((unsigned long long *)(det + slot), (unsigned long long)__double_as_longlong(mx));
     }
     __syncthreads();
@@ -580,7 +581,7 @@ template <typename T>
 hipError_t launch_details(const T *U, const WorkList &wl, const DevTables &tb,
                           const InstDev *inst, double *det, hipStream_t st) {
     if (wl.grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_details<T>, grid2(wl.grid, DZ), dim3(TPB), 0, st, U, wl, tb.meta, tb.nbr,
+    hipLaunchKernelGGL(k_details<T>, grid2(wl.grid, DZ), dim3(DTPB), 0, st, U, wl, tb.meta, tb.nbr,
                        inst, det);
     return hipGetLastError();
 }

@@ -224,7 +224,8 @@ struct mrfv_ctx {
     mrfv::DevTables tb;
     mrfv::InstDev *d_inst = nullptr;
     int32_t *d_err = nullptr;          // device error word
-    void *d_W = nullptr;               // second padded state buffer (fused FP32 stages)
+    void *d_W = nullptr, *d_W2 = nullptr;   // second and third padded state buffers
+                                            // (fused FP32 stages: U -> W -> W2 -> U)
     void *d_D = nullptr;               // flux differences [cap][3][5][16^3]
     void *d_FF = nullptr;              // boundary face fluxes [cap][6][5][16][16]
     double *d_blockred = nullptr;      // [cap][5] per-block partial reductions
