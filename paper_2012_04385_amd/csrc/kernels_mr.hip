@@ -120,6 +120,16 @@ __device__ __forceinline__ Region make_region(int mode, int ridx, int zg) {
     return g;
 }
 
+// Index decomposition without integer division: e / n for 0 <= e < 2^13 and n <= 24 as
+// the truncated product with a reciprocal rounded up by 2^-20 relative (the error stays
+// below the 1/n gap to the next integer, so the quotient is exact).
+struct Div {
+    int n;
+    float r;
+    __device__ __forceinline__ explicit Div(int n_) : n(n_), r(__frcp_rn((float)n_) * 1.000001f) {}
+    __device__ __forceinline__ int quot(int e) const { return (int)((float)e * r); }
+};
+
 // Parent padded index of child padded index c in octant half o.
 __device__ __forceinline__ int parent_of(int c, int o) { return o * (NI / 2) + ((c - HW) >> 1) + HW; }
 
@@ -148,12 +158,13 @@ __global__ __launch_bounds__(TPB) void k_fill_halos(T *__restrict__ U, WorkList 
         if ((mode & FILL_MISSING) && src >= 0 && !clamped) continue;   // read in place
         T *dst = U + (size_t)slot * 5 * CELLS_P;
         const int ncell = g.n[0] * g.n[1] * g.n[2];
+        const Div dc(ncell), d0(g.n[0]), d1(g.n[1]);
         if (src >= 0) {
             const T *sb = U + (size_t)src * 5 * CELLS_P;
             for (int t = tid; t < 5 * ncell; t += TPB) {
-                const int q = t / ncell, e = t - q * ncell;
-                const int i = g.lo[0] + e % g.n[0], j = g.lo[1] + (e / g.n[0]) % g.n[1],
-                          k = g.lo[2] + e / (g.n[0] * g.n[1]);
+                const int q = dc.quot(t), e = t - q * ncell;
+                const int e1 = d0.quot(e), e2 = d1.quot(e1);
+                const int i = g.lo[0] + e - e1 * g.n[0], j = g.lo[1] + e1 - e2 * g.n[1], k = g.lo[2] + e2;
                 const int si = g.clamp[0] >= 0 ? g.clamp[0] : i - NI * g.r[0];
                 const int sj = g.clamp[1] >= 0 ? g.clamp[1] : j - NI * g.r[1];
                 const int sk = g.clamp[2] >= 0 ? g.clamp[2] : k - NI * g.r[2];
@@ -174,16 +185,19 @@ __global__ __launch_bounds__(TPB) void k_fill_halos(T *__restrict__ U, WorkList 
             np[a] = parent_of(c0[a] + me[a] - 1, o[a]) + 2 - p0[a] + 1;
         }
         const T *pu = U + (size_t)m.parent * 5 * CELLS_P;
+        const Div dp0(np[0]), dp1(np[1]), dm0(me[0]), dm1(me[1]);
         for (int q = 0; q < 5; ++q) {
             const int na = np[0] * np[1] * np[2];
             for (int t = tid; t < na; t += TPB) {
-                const int ii = t % np[0], jj = (t / np[0]) % np[1], kk = t / (np[0] * np[1]);
+                const int t1 = dp0.quot(t), kk = dp1.quot(t1);
+                const int ii = t - t1 * np[0], jj = t1 - kk * np[1];
                 A[t] = pu[pidx(q, p0[2] + kk, p0[1] + jj, p0[0] + ii)];
             }
             __syncthreads();
             const int nx = np[2] * np[1] * me[0];
             for (int t = tid; t < nx; t += TPB) {
-                const int ex = t % me[0], jj = (t / me[0]) % np[1], kk = t / (me[0] * np[1]);
+                const int t1 = dm0.quot(t), kk = dp1.quot(t1);
+                const int ex = t - t1 * me[0], jj = t1 - kk * np[1];
                 const int c = c0[0] + ex;
                 const int I = parent_of(c, o[0]) - p0[0];
                 const T *row = A + (kk * np[1] + jj) * np[0] + I;
@@ -193,7 +207,8 @@ __global__ __launch_bounds__(TPB) void k_fill_halos(T *__restrict__ U, WorkList 
             __syncthreads();
             const int ny = np[2] * me[1] * me[0];
             for (int t = tid; t < ny; t += TPB) {
-                const int ex = t % me[0], ey = (t / me[0]) % me[1], kk = t / (me[0] * me[1]);
+                const int t1 = dm0.quot(t), kk = dm1.quot(t1);
+                const int ex = t - t1 * me[0], ey = t1 - kk * me[1];
                 const int c = c0[1] + ey;
                 const int J = parent_of(c, o[1]) - p0[1];
                 const T *col = X + (kk * np[1] + J) * me[0] + ex;
@@ -203,7 +218,8 @@ __global__ __launch_bounds__(TPB) void k_fill_halos(T *__restrict__ U, WorkList 
             }
             __syncthreads();
             for (int t = tid; t < ncell; t += TPB) {
-                const int dx = t % g.n[0], dy = (t / g.n[0]) % g.n[1], dz = t / (g.n[0] * g.n[1]);
+                const int t1 = d0.quot(t), dz = d1.quot(t1);
+                const int dx = t - t1 * g.n[0], dy = t1 - dz * g.n[1];
                 const int ex = g.clamp[0] >= 0 ? 0 : dx, ey = g.clamp[1] >= 0 ? 0 : dy,
                           ez = g.clamp[2] >= 0 ? 0 : dz;
                 const int c = c0[2] + ez;
