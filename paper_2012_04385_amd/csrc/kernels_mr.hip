@@ -301,8 +301,8 @@ __global__ __launch_bounds__(TPB) void k_predict(T *__restrict__ U,
 // Cells outside the interior are read from the same-level neighbour's interior where
 // one exists (else from the own halo, filled for such regions).
 constexpr int DZ = 4;                          // slabs per block
-constexpr int DTPB = 512;                      // threads per workgroup (LDS allows 2 per CU)
-constexpr int SZ = NP / DZ;                    // padded z-planes per slab (6)
+constexpr int DTPB = 512;                      // threads per workgroup (68 KB LDS: 2 per CU)
+constexpr int SZ = NP / DZ;                    // padded z-planes per slab (6; even)
 constexpr int PZ = SZ / 2 + 4;                 // parent planes per slab (7)
 
 template <typename T>

@@ -178,18 +178,21 @@ __device__ __forceinline__ void face_flux(const CellState<T> w[6], const Gas<T> 
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
         const CellState<T> &s = w[j];
+        // physical flux f = (mn, mn un + p, mt1 un, mt2 un, (E + p) un); with
+        // X = E - u mn - v mt1 - w mt2 its t-combination f4 - u f1 - v f2 - w f3 is
+        // un (X + p) - u p, and f1 - u mn = mn (un - u) + p
         const T un = s.mn * s.ir;
-        const T f1 = s.mn * un + s.p, f2 = s.mt1 * un, f3 = s.mt2 * un, f4 = (s.E + s.p) * un;
-        tU[j] = hb2 * s.r + hb1 * (s.E - u * s.mn - v * s.mt1 - ww * s.mt2);
+        const T X = s.E - u * s.mn - v * s.mt1 - ww * s.mt2;
+        tU[j] = hb2 * s.r + hb1 * X;
         xU[j] = (s.mn - u * s.r) * hic;
-        tF[j] = hb2 * s.mn + hb1 * (f4 - u * f1 - v * f2 - ww * f3);
-        xF[j] = (f1 - u * s.mn) * hic;
+        tF[j] = hb2 * s.mn + hb1 * (un * (X + s.p) - u * s.p);
+        xF[j] = (s.mn * (un - u) + s.p) * hic;
         a0[j] = s.r;
         f0[j] = s.mn;
         wt1[j] = s.mt1 - v * s.r;
         wt2[j] = s.mt2 - ww * s.r;
-        gt1[j] = f2 - v * s.mn;
-        gt2[j] = f3 - ww * s.mn;
+        gt1[j] = s.mt1 * un - v * s.mn;
+        gt2[j] = s.mt2 * un - ww * s.mn;
     }
     const T unL = L.mn * L.ir, unR = R.mn * R.ir;
     T W[6], Gc[6], g[5];

@@ -287,6 +287,31 @@ def test_stage_graph_matches_eager(orc, torch_mod):
         assert np.array_equal(sa[k], sb[k]), k
 
 
+def test_stage_graph_across_keys(orc, torch_mod):
+    """A multi-level tree whose jumps and per-level lists change while it adapts: the
+    graphs cached by list emptiness (re-captured when the key changes) give bitwise the
+    eager result at every step."""
+    from paper_2012_04385_amd.mrfv import Solver
+    pb = W.Problem(name="blast_jumps", kind="blast", lmax=3, n0=(1, 1, 1), dx0=1 / 16,
+                   bc=(0, 1, 0), noise=0.0, eps=1e-3, scale_rho=1.0, scale_E=25.0,
+                   seed=W.BASE_SEED + 9, params={"centre": (0.45, 0.5, 0.55), "radius": 0.12})
+    a = Solver([pb], dtype="f32", batched=1).init()
+    b = Solver([pb], dtype="f32", batched=2).init()
+    levels = set()
+    for _ in range(8):
+        a.step()
+        b.step()
+        la = {tuple(r[2:6]) for r in a.blocks() if r[6] == 1}
+        assert la == {tuple(r[2:6]) for r in b.blocks() if r[6] == 1}
+        levels |= {k[0] for k in la}
+        sa, sb = a.leaf_states(), b.leaf_states()
+        for k in sa:
+            assert np.array_equal(sa[k], sb[k]), k
+    a.check()
+    b.check()
+    assert len(levels) >= 2, "the tree should have resolution jumps"
+
+
 def _small_instances():
     """Four uneven problems: different sizes, depths, boundary conditions and ICs."""
     p0 = W.sod_single_level()
