@@ -509,8 +509,9 @@ __device__ __forceinline__ void face_flux_at(const T *__restrict__ ub, const T *
     Fp[t2] = F[3];
 }
 
-template <typename T, int GP, int TPB_F, bool PERSIST>
-__global__ __launch_bounds__(TPB_F) void k_rhs_update(int stage, const double *__restrict__ dt,
+template <typename T, int GP, int TPB_F, bool PERSIST, int WPE>
+__global__ __attribute__((amdgpu_flat_work_group_size(TPB_F, TPB_F), amdgpu_waves_per_eu(WPE)))
+void k_rhs_update(int stage, const double *__restrict__ dt,
                                                       const T *__restrict__ Uin, T *__restrict__ Uout,
                                                       T *U0, WorkList wl,
                                                       const BlockMeta *__restrict__ meta,
@@ -733,14 +734,16 @@ hipError_t launch_update(int stage, const double *dt, T *U, T *U0, const T *L, c
 }
 
 // Launch shapes of the fused kernel: (z-planes per group, threads per workgroup).
-// The last two variants are persistent: a grid of as many workgroups as fit on the 256
-// CUs at once (3 waves per SIMD at their register count) loops over the leaves instead
-// of one workgroup per leaf.
-constexpr int N_RHS_VARIANTS = 11;
-constexpr int RHS_GP[N_RHS_VARIANTS] = {2, 1, 2, 2, 4, 4, 2, 2, 1, 2, 2};
-constexpr int RHS_TPB[N_RHS_VARIANTS] = {320, 256, 256, 384, 320, 512, 448, 512, 320, 512, 384};
+// Variants 9 and 10 are persistent: a grid of as many workgroups as fit on the 256 CUs
+// at once (3 waves per SIMD at their register count) loops over the leaves instead of
+// one workgroup per leaf.  Variants 11 and 12 ask the register allocator for 5 waves per
+// SIMD (at most 96 registers, some spilled to scratch) instead of the default 4.
+constexpr int N_RHS_VARIANTS = 13;
+constexpr int RHS_GP[N_RHS_VARIANTS] = {2, 1, 2, 2, 4, 4, 2, 2, 1, 2, 2, 2, 2};
+constexpr int RHS_TPB[N_RHS_VARIANTS] = {320, 256, 256, 384, 320, 512, 448, 512, 320, 512, 384, 320, 640};
 constexpr bool RHS_PERSIST[N_RHS_VARIANTS] = {false, false, false, false, false, false, false, false,
-                                              false, true, true};
+                                              false, true, true, false, false};
+constexpr int RHS_WPE[N_RHS_VARIANTS] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 5, 5};
 constexpr int persist_grid(int tpb) { return 256 * (12 / (tpb / 64) > 0 ? 12 / (tpb / 64) : 1); }
 
 template <int V>
@@ -749,16 +752,18 @@ static void launch_variant(int stage, const double *dt, const float *Uin, float 
                     int32_t *err, hipStream_t st) {
     constexpr int G = RHS_GP[V], B = RHS_TPB[V];
     constexpr bool PS = RHS_PERSIST[V];
+    constexpr int WP = RHS_WPE[V];
     const int grid = PS ? std::min(wl.grid, persist_grid(B)) : wl.grid;
-    hipLaunchKernelGGL((k_rhs_update<float, G, B, PS>), dim3(grid), dim3(B), 0, st, stage, dt, Uin,
+    hipLaunchKernelGGL((k_rhs_update<float, G, B, PS, WP>), dim3(grid), dim3(B), 0, st, stage, dt, Uin,
                        Uout, U0, wl, tb.meta, tb.nbr, inst, FF, err);
 }
 
 int rhs_variants() { return N_RHS_VARIANTS; }
 
-void rhs_variant_shape(int v, int *gp, int *tpb) {
+void rhs_variant_shape(int v, int *gp, int *tpb, int *wpe) {
     *gp = RHS_GP[v];
     *tpb = RHS_PERSIST[v] ? -RHS_TPB[v] : RHS_TPB[v];   // negative: persistent grid
+    *wpe = RHS_WPE[v];
 }
 
 hipError_t launch_rhs_update_f32(int variant, int stage, const double *dt, const float *Uin,
@@ -778,6 +783,8 @@ hipError_t launch_rhs_update_f32(int variant, int stage, const double *dt, const
         case 8: launch_variant<8>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, st); break;
         case 9: launch_variant<9>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, st); break;
         case 10: launch_variant<10>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, st); break;
+        case 11: launch_variant<11>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, st); break;
+        case 12: launch_variant<12>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, st); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

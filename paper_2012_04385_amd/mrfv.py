@@ -332,13 +332,14 @@ class Solver:
                                          self._p(Uout), self._p(self.U0)))
 
     def rhs_variants(self):
-        """[(z-planes per group, threads per workgroup)] of the fused kernel's variants;
-        a negative thread count marks a persistent grid looping over the leaves."""
+        """[(z-planes per group, threads per workgroup, waves per SIMD aimed at)] of the
+        fused kernel's variants; a negative thread count marks a persistent grid looping
+        over the leaves, waves 1 the compiler's default register allocation."""
         n = C.c_int32(0)
         lib().mrfv_rhs_variant(self.h, -1, C.byref(n), None)
-        shp = (C.c_int32 * (2 * n.value))()
+        shp = (C.c_int32 * (3 * n.value))()
         lib().mrfv_rhs_variant(self.h, -1, None, shp)
-        return [(shp[2 * v], shp[2 * v + 1]) for v in range(n.value)]
+        return [(shp[3 * v], shp[3 * v + 1], shp[3 * v + 2]) for v in range(n.value)]
 
     def set_rhs_variant(self, v: int) -> int:
         rc = lib().mrfv_rhs_variant(self.h, int(v), None, None)
