@@ -43,6 +43,13 @@ def counted_traffic(kernel: str):
     return prof.get("traffic_bytes_per_dispatch", {}).get(kernel)
 
 
+def kernel_name(shape) -> str:
+    """Demangled name of the fused kernel's instantiation for a variant shape."""
+    gp, tpb, wpe, ring = shape
+    b = lambda v: "true" if v else "false"
+    return f"k_rhs_update<float, {gp}, {abs(tpb)}, {b(tpb < 0)}, {wpe}, {b(ring)}>"
+
+
 def flops_per_cell_update(llf_fraction: float) -> float:
     return 3.0 * (17.0 / 16.0) * (FACE_BASE + 5.0 * llf_fraction * LLF_EXTRA) + UPDATE
 
@@ -156,7 +163,7 @@ def other_workload(args):
         torch.cuda.empty_cache()
     launches, total_ms, kcells = res[1][2]
     avg_s = total_ms / 1e3 / max(launches, 1)
-    gp, tpb, wpe = res["autotune"]["shapes"][res["autotune"]["choice"]]
+    kname = kernel_name(res["autotune"]["shapes"][res["autotune"]["choice"]])
     fpc = flops_per_cell_update(0.5)
     achieved = kcells / max(launches, 1) * fpc / avg_s
     out = {"metric": "cell-updates/s per RK stage (FP32 batched MR RK3)", "value": res[2][0],
@@ -167,7 +174,7 @@ def other_workload(args):
                       "path": "batched FP32, RK stages replayed from a hipGraph"},
            "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
                         "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR, "traffic": None,
-                        "kernel": f"k_rhs_update<float, {gp}, {abs(tpb)}, {'true' if tpb < 0 else 'false'}, {wpe}>",
+                        "kernel": kname,
                         "avg_launch_ms": avg_s * 1e3,
                         "flop_model_llf_fraction": 0.5},
            "cpu_baseline": None, "value_eager_launches": res[1][0], "autotune": res["autotune"],
@@ -265,8 +272,7 @@ def main():
     cells_per_launch = kcells / max(launches, 1)
     fpc = flops_per_cell_update(llf)
     achieved = cells_per_launch * fpc / avg_s
-    gp, tpb, wpe = tuned["shapes"][tuned["choice"]]
-    kname = f"k_rhs_update<float, {gp}, {abs(tpb)}, {'true' if tpb < 0 else 'false'}, {wpe}>"
+    kname = kernel_name(tuned["shapes"][tuned["choice"]])
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
             "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR, "traffic": counted_traffic(kname),
             "kernel": kname, "avg_launch_ms": avg_s * 1e3,

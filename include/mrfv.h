@@ -193,10 +193,11 @@ int mrfv_fused_stage(mrfv_ctx *ctx, int32_t stage, const double *dt_dev, void *U
                      void *U0);
 
 /* Launch shapes of the fused rhs + update kernel (batched FP32 path): variant v groups
- * the block's z-planes by shapes_host[3v] and uses |shapes_host[3v+1]| threads per
- * workgroup, one workgroup per leaf, or, when shapes_host[3v+1] < 0, a persistent grid
- * of workgroups looping over the leaves; shapes_host[3v+2] is the number of wavefronts
- * per SIMD the register allocation aims at (1: the compiler's choice).  Every variant
+ * the block's z-planes by shapes_host[4v] and uses |shapes_host[4v+1]| threads per
+ * workgroup, one workgroup per leaf, or, when shapes_host[4v+1] < 0, a persistent grid
+ * of workgroups looping over the leaves; shapes_host[4v+2] is the number of wavefronts
+ * per SIMD the register allocation aims at (1: the compiler's choice); shapes_host[4v+3]
+ * = 1 when the z-face stencils are read from an LDS ring of z-planes.  Every variant
  * gives bitwise the same result.  rhs_variant sets the variant
  * when set >= 0 (captured stage graphs are re-captured), writes the number of variants
  * and their shapes (each may be NULL) and returns the current variant (>= 0) or an

@@ -1009,7 +1009,8 @@ int mrfv_rhs_variant(mrfv_ctx *ctx, int32_t set, int32_t *n_variants, int32_t *s
     const int n = rhs_variants();
     if (n_variants) *n_variants = n;
     if (shapes)
-        for (int v = 0; v < n; ++v) rhs_variant_shape(v, shapes + 3 * v, shapes + 3 * v + 1, shapes + 3 * v + 2);
+        for (int v = 0; v < n; ++v)
+            rhs_variant_shape(v, shapes + 4 * v, shapes + 4 * v + 1, shapes + 4 * v + 2, shapes + 4 * v + 3);
     if (set >= n) return fail(ctx, MRFV_EINVAL, "rhs_variant: index out of range");
     if (set >= 0 && set != ctx->rhs_variant) {
         ctx->rhs_variant = set;

@@ -509,7 +509,33 @@ __device__ __forceinline__ void face_flux_at(const T *__restrict__ ub, const T *
     Fp[t2] = F[3];
 }
 
-template <typename T, int GP, int TPB_F, bool PERSIST, int WPE>
+// z-face flux from the LDS ring of z-planes (ZRING variants): the six stencil cells of
+// the face below interior plane kf at column c are planes kf-3 .. kf+2, ring slot
+// (k + 3) mod ZR; same values and arithmetic as face_flux_at along z.
+template <typename T, int ZR>
+__device__ __forceinline__ void face_flux_ring(const T (*__restrict__ Zr)[5][NI * NI], int kf, int c,
+                                               const Gas<T> &G, T Fp[5]) {
+    CellState<T> w[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        const T *pl = &Zr[(kf + j) & (ZR - 1)][0][c];
+        w[j].r = pl[0];
+        w[j].mn = pl[3 * NI * NI];
+        w[j].mt1 = pl[1 * NI * NI];
+        w[j].mt2 = pl[2 * NI * NI];
+        w[j].E = pl[4 * NI * NI];
+        derive_state(G, w[j]);
+    }
+    T F[5];
+    face_flux<T, true>(w, G, F);
+    Fp[0] = F[0];
+    Fp[4] = F[4];
+    Fp[3] = F[1];
+    Fp[1] = F[2];
+    Fp[2] = F[3];
+}
+
+template <typename T, int GP, int TPB_F, bool PERSIST, int WPE, bool ZRING>
 __global__ __attribute__((amdgpu_flat_work_group_size(TPB_F, TPB_F), amdgpu_waves_per_eu(WPE)))
 void k_rhs_update(int stage, const double *__restrict__ dt,
                                                       const T *__restrict__ Uin, T *__restrict__ Uout,
@@ -522,6 +548,10 @@ void k_rhs_update(int stage, const double *__restrict__ dt,
     __shared__ T Fx[GP][NI][NI + 1][5];   // [plane][y][face x][q]
     __shared__ T Fy[GP][NI + 1][NI][5];   // [plane][face y][x][q]
     __shared__ T Fz[GP + 1][NI][NI][5];   // [face plane][y][x][q]; plane j = face k0 + j - 1/2
+    // ZRING: interior columns of the z-planes the z-faces read, planes -3 .. 18 through a
+    // ring of ZR slots (a power of two >= GP + 6), each plane loaded once per block
+    constexpr int ZR = ZRING ? (GP + 6 <= 8 ? 8 : 16) : 1;
+    __shared__ T Zr[ZR][5][ZRING ? NI * NI : 1];
     // one workgroup per leaf (graph launches size the grid by the slot capacity and
     // surplus groups exit here), or, persistent, a fixed grid looping over the leaves
     const int nleaf = wl.count();
@@ -555,6 +585,21 @@ void k_rhs_update(int stage, const double *__restrict__ dt,
     const bool owner = tid < FACE;              // column owners (x = tid & 15, y = tid >> 4)
     const int cx = tid & 15, cy = tid >> 4;
     bool ok = true;
+
+    // interior z-plane k (-3 .. 18): own plane, else the z-neighbour's (or the own halo
+    // where the face has no same-level neighbour); the source is uniform per plane
+    auto load_plane = [&](int k) {
+        const T *src = (k < 0 ? nlo[2] : (k >= NI ? nhi[2] : ub)) + (k + HW) * NP * NP;
+        T *dst = &Zr[(k + 3) & (ZR - 1)][0][0];
+        for (int e = tid; e < 5 * NFZ; e += TPB_F) {
+            const int q = e >> 8, c = e & (NFZ - 1);
+            dst[q * NFZ + c] = src[q * CELLS_P + ((c >> 4) + HW) * NP + (c & 15) + HW];
+        }
+    };
+    if constexpr (ZRING) {
+        for (int k = -3; k <= GP + 2; ++k) load_plane(k);
+        __syncthreads();
+    }
 
     auto update_group = [&](int k0, T D[GP][5]) {
 #pragma unroll
@@ -612,8 +657,12 @@ void k_rhs_update(int stage, const double *__restrict__ dt,
                 const int u = t - 2 * NFX;
                 const int x = u % NI, y = (u / NI) % NI, j = u / NFZ + first_z;
                 const int kf = k0 + j;          // face between interior planes kf-1 and kf
-                const int base = ((kf + 1) * NP + y + HW) * NP + x + HW;   // padded z = kf+1 .. kf+6
-                face_flux_at(ub, nlo[2], nhi[2], 2, base, kf + 1, G, F);
+                if constexpr (ZRING) {
+                    face_flux_ring<T, ZR>(Zr, kf, y * NI + x, G, F);
+                } else {
+                    const int base = ((kf + 1) * NP + y + HW) * NP + x + HW;   // padded z = kf+1 .. kf+6
+                    face_flux_at(ub, nlo[2], nhi[2], 2, base, kf + 1, G, F);
+                }
 #pragma unroll
                 for (int q = 0; q < 5; ++q) Fz[j][y][x][q] = F[q];
                 if (kf == 0 || kf == NI) {
@@ -635,6 +684,12 @@ void k_rhs_update(int stage, const double *__restrict__ dt,
                     D[p][q] = (dxq + dyq) + dzq;
                 }
             update_group(k0, D);
+        }
+        if constexpr (ZRING) {
+            // planes of the next group's window; the slots they take held planes this
+            // group's faces (all computed: the barrier above) no longer need
+            if (g + 1 < NI / GP)
+                for (int k = k0 + GP + 3; k <= k0 + 2 * GP + 2; ++k) load_plane(k);
         }
         __syncthreads();
         // the last face plane of this group is the first one of the next
@@ -738,12 +793,16 @@ hipError_t launch_update(int stage, const double *dt, T *U, T *U0, const T *L, c
 // at once (3 waves per SIMD at their register count) loops over the leaves instead of
 // one workgroup per leaf.  Variants 11 and 12 ask the register allocator for 5 waves per
 // SIMD (at most 96 registers, some spilled to scratch) instead of the default 4.
-constexpr int N_RHS_VARIANTS = 13;
-constexpr int RHS_GP[N_RHS_VARIANTS] = {2, 1, 2, 2, 4, 4, 2, 2, 1, 2, 2, 2, 2};
-constexpr int RHS_TPB[N_RHS_VARIANTS] = {320, 256, 256, 384, 320, 512, 448, 512, 320, 512, 384, 320, 640};
+// Variants 13-15 read the z-face stencils from an LDS ring of z-planes.
+constexpr int N_RHS_VARIANTS = 16;
+constexpr int RHS_GP[N_RHS_VARIANTS] = {2, 1, 2, 2, 4, 4, 2, 2, 1, 2, 2, 2, 2, 2, 2, 2};
+constexpr int RHS_TPB[N_RHS_VARIANTS] = {320, 256, 256, 384, 320, 512, 448, 512, 320, 512, 384, 320, 640,
+                                         512, 384, 448};
 constexpr bool RHS_PERSIST[N_RHS_VARIANTS] = {false, false, false, false, false, false, false, false,
-                                              false, true, true, false, false};
-constexpr int RHS_WPE[N_RHS_VARIANTS] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 5, 5};
+                                              false, true, true, false, false, false, false, false};
+constexpr int RHS_WPE[N_RHS_VARIANTS] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 5, 5, 1, 1, 1};
+constexpr bool RHS_RING[N_RHS_VARIANTS] = {false, false, false, false, false, false, false, false,
+                                           false, false, false, false, false, true, true, true};
 constexpr int persist_grid(int tpb) { return 256 * (12 / (tpb / 64) > 0 ? 12 / (tpb / 64) : 1); }
 
 template <int V>
@@ -753,17 +812,19 @@ static void launch_variant(int stage, const double *dt, const float *Uin, float 
     constexpr int G = RHS_GP[V], B = RHS_TPB[V];
     constexpr bool PS = RHS_PERSIST[V];
     constexpr int WP = RHS_WPE[V];
+    constexpr bool ZRG = RHS_RING[V];
     const int grid = PS ? std::min(wl.grid, persist_grid(B)) : wl.grid;
-    hipLaunchKernelGGL((k_rhs_update<float, G, B, PS, WP>), dim3(grid), dim3(B), 0, st, stage, dt, Uin,
+    hipLaunchKernelGGL((k_rhs_update<float, G, B, PS, WP, ZRG>), dim3(grid), dim3(B), 0, st, stage, dt, Uin,
                        Uout, U0, wl, tb.meta, tb.nbr, inst, FF, err);
 }
 
 int rhs_variants() { return N_RHS_VARIANTS; }
 
-void rhs_variant_shape(int v, int *gp, int *tpb, int *wpe) {
+void rhs_variant_shape(int v, int *gp, int *tpb, int *wpe, int *ring) {
     *gp = RHS_GP[v];
     *tpb = RHS_PERSIST[v] ? -RHS_TPB[v] : RHS_TPB[v];   // negative: persistent grid
     *wpe = RHS_WPE[v];
+    *ring = RHS_RING[v] ? 1 : 0;
 }
 
 hipError_t launch_rhs_update_f32(int variant, int stage, const double *dt, const float *Uin,
@@ -785,6 +846,9 @@ hipError_t launch_rhs_update_f32(int variant, int stage, const double *dt, const
         case 10: launch_variant<10>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, st); break;
         case 11: launch_variant<11>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, st); break;
         case 12: launch_variant<12>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, st); break;
+        case 13: launch_variant<13>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, st); break;
+        case 14: launch_variant<14>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, st); break;
+        case 15: launch_variant<15>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, st); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -196,7 +196,7 @@ hipError_t launch_rhs_update_f32(int variant, int stage, const double *dt, const
                                  float *Uout, float *U0, const WorkList &leaves, const DevTables &tb,
                                  const InstDev *inst, float *FF, int32_t *err, hipStream_t st);
 int rhs_variants();
-void rhs_variant_shape(int v, int *gp, int *tpb, int *wpe);
+void rhs_variant_shape(int v, int *gp, int *tpb, int *wpe, int *ring);
 template <typename T>
 hipError_t launch_reflux_update(int stage, const double *dt, T *U, const T *FF,
                                 const WorkList &leaves, const DevTables &tb,

@@ -332,14 +332,15 @@ class Solver:
                                          self._p(Uout), self._p(self.U0)))
 
     def rhs_variants(self):
-        """[(z-planes per group, threads per workgroup, waves per SIMD aimed at)] of the
-        fused kernel's variants; a negative thread count marks a persistent grid looping
-        over the leaves, waves 1 the compiler's default register allocation."""
+        """[(z-planes per group, threads per workgroup, waves per SIMD aimed at, z-plane
+        ring)] of the fused kernel's variants; a negative thread count marks a persistent
+        grid looping over the leaves, waves 1 the compiler's default register allocation,
+        ring 1 z-face stencils read from LDS."""
         n = C.c_int32(0)
         lib().mrfv_rhs_variant(self.h, -1, C.byref(n), None)
-        shp = (C.c_int32 * (3 * n.value))()
+        shp = (C.c_int32 * (4 * n.value))()
         lib().mrfv_rhs_variant(self.h, -1, None, shp)
-        return [(shp[3 * v], shp[3 * v + 1], shp[3 * v + 2]) for v in range(n.value)]
+        return [tuple(shp[4 * v + i] for i in range(4)) for v in range(n.value)]
 
     def set_rhs_variant(self, v: int) -> int:
         rc = lib().mrfv_rhs_variant(self.h, int(v), None, None)

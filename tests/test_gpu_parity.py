@@ -367,9 +367,10 @@ def test_rhs_variants_bitwise_and_autotune(torch_mod):
     for batched in (1, 2):
         g0 = Solver([pb], dtype="f32", batched=batched).init()
         shapes = g0.rhs_variants()
-        # (z-planes per group, threads per workgroup (negative: persistent grid), waves per SIMD)
-        assert len(shapes) >= 4 and all(abs(t) >= 256 and 16 % gp == 0 for gp, t, _ in shapes)
-        assert any(t < 0 for _, t, _ in shapes) and any(w > 1 for _, _, w in shapes)
+        # (z-planes, threads (negative: persistent grid), waves per SIMD, z-plane ring)
+        assert len(shapes) >= 4 and all(abs(t) >= 256 and 16 % gp == 0 for gp, t, _, _ in shapes)
+        assert any(t < 0 for _, t, _, _ in shapes) and any(w > 1 for _, _, w, _ in shapes)
+        assert any(r for _, _, _, r in shapes)
         del g0
         for v in range(len(shapes)):
             g = Solver([pb], dtype="f32", batched=batched).init()
