@@ -144,8 +144,11 @@ int do_fill(mrfv_ctx *ctx, T *U, int max_level, FillMode mode = FILL_ALL, bool w
         if (mode == FILL_ALL) {
             HIP_OK(launch_fill_halos<T>(U, wlist(ctx, desc_lvl(l), 1024), ctx->tb, FILL_ALL, ctx->stream));
         } else {
+            // a stage fills only the parents its predictions read; the fill before the
+            // details (FILL_MISSING) all non-leaf blocks, whose details are judged too
+            const int pw = mode == FILL_MISSING_FACES ? desc_pfill(l) : desc_par(l);
             if (with_parents)
-                HIP_OK(launch_fill_halos<T>(U, wlist(ctx, desc_par(l), 1024), ctx->tb, FILL_ALL, ctx->stream));
+                HIP_OK(launch_fill_halos<T>(U, wlist(ctx, pw, 1024), ctx->tb, FILL_ALL, ctx->stream));
             const int which = mode == FILL_FACES ? desc_leaf(l)
                               : mode == FILL_MISSING_FACES ? desc_jleaf(l) : desc_jleaf26(l);
             HIP_OK(launch_fill_halos<T>(U, wlist(ctx, which, 1024), ctx->tb, mode, ctx->stream));
@@ -512,6 +515,7 @@ uint64_t graph_key(const mrfv_ctx *ctx) {
     for (int l = 0; l <= L.max_level && l < MAX_LEVELS; ++l) {
         if (L.desc[2 * desc_par(l) + 1] > 0) k |= 1ull << (5 + l);
         if (L.desc[2 * desc_jleaf(l) + 1] > 0) k |= 1ull << (5 + MAX_LEVELS + l);
+        if (L.desc[2 * desc_pfill(l) + 1] > 0) k |= 1ull << (5 + 2 * MAX_LEVELS + l);
     }
     return k;
 }
@@ -672,9 +676,8 @@ int mrfv_create(mrfv_ctx **out, const mrfv_config *cfg, const mrfv_instance *ins
     }
     ctx->stream = (hipStream_t)hip_stream;
     const size_t cap = cfg->slot_capacity, es = elem_size(ctx);
-    ctx->lists_cap = 2 * cfg->n_instances + 8 * cfg->slot_capacity + 16;
+    ctx->lists_cap = 2 * cfg->n_instances + 9 * cfg->slot_capacity + 16;
     ctx->prim_batch = 128;
-    for (int i = 0; i < cfg->n_instances; ++i) ctx->lmax_all = std::max(ctx->lmax_all, (int)inst[i].lmax);
     ctx->lvl_bound.assign(MAX_LEVELS, 0);
     for (int i = 0; i < cfg->n_instances; ++i) {
         int64_t n = (int64_t)inst[i].n0[0] * inst[i].n0[1] * inst[i].n0[2];
@@ -1029,7 +1032,7 @@ int mrfv_autotune(mrfv_ctx *ctx, void *U, void *U0, double *dt_dev, int32_t reps
     float *X = (float *)U, *W = (float *)ctx->d_W;
     hipStream_t st = ctx->stream;
     // a valid first stage: CFL step, restriction, fills; each variant then runs stage 0
-    // from U into the second state buffer (U, the state, is not written)
+    // from U into the second state buffer W (U, the state, is not written)
     HIP_OK(launch_cfl<float>(X, wlist(ctx, DESC_LEAVES), ctx->tb, ctx->d_inst, (int)ctx->inst.size(),
                              ctx->d_blockred, dt_dev, st));
     CALL(do_project<float>(ctx, X));

@@ -235,22 +235,6 @@ __global__ __launch_bounds__(TPB) void k_fill_halos(T *__restrict__ U, WorkList 
     }
 }
 
-// Interiors of the listed blocks: dst <- src (the fused stages' ping-pong buffer).
-template <typename T>
-__global__ __launch_bounds__(TPB) void k_copy_interiors(const T *__restrict__ src, T *__restrict__ dst,
-                                                        WorkList wl) {
-    const int nb = wl.count();
-    for (int b = blockIdx.x; b < nb; b += gridDim.x) {
-        const size_t base = (size_t)wl.at(b) * 5 * CELLS_P;
-        const int k = blockIdx.y, j = threadIdx.x >> 4, i = threadIdx.x & 15;
-#pragma unroll
-        for (int q = 0; q < 5; ++q) {
-            const int o = pidx(q, k + HW, j + HW, i + HW);
-            dst[base + o] = src[base + o];
-        }
-    }
-}
-
 // One thread per parent interior cell.
 template <typename T>
 __global__ __launch_bounds__(TPB) void k_project(T *__restrict__ U, WorkList wl,
@@ -571,12 +555,6 @@ hipError_t launch_fill_halos(T *U, const WorkList &wl, const DevTables &tb, Fill
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_copy_interiors(const T *src, T *dst, const WorkList &wl, hipStream_t st) {
-    if (wl.grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_copy_interiors<T>, grid2(wl.grid, NI), dim3(TPB), 0, st, src, dst, wl);
-    return hipGetLastError();
-}
 
 template <typename T>
 hipError_t launch_project(T *U, const WorkList &wl, const DevTables &tb, hipStream_t st) {
@@ -645,8 +623,6 @@ hipError_t launch_totals(const T *U, const WorkList &leaves, const DevTables &tb
                                             const BlockMeta *, const InstDev *, hipStream_t); \
     template hipError_t launch_fill_halos<T>(T *, const WorkList &, const DevTables &,       \
                                              FillMode, hipStream_t);                        \
-    template hipError_t launch_copy_interiors<T>(const T *, T *, const WorkList &,         \
-                                                 hipStream_t);                              \
     template hipError_t launch_project<T>(T *, const WorkList &, const DevTables &,         \
                                           hipStream_t);                                     \
     template hipError_t launch_predict<T>(T *, const int32_t *, int, const DevTables &,    \

@@ -63,7 +63,7 @@ struct HostLists {
     int max_level = 0;
     // per level: all blocks, non-leaf blocks, leaves
     std::vector<int32_t> lvl_off, lvl_cnt, par_off, par_cnt, leaf_off, leaf_cnt, jleaf_off, jleaf_cnt,
-        j26_off, j26_cnt;
+        j26_off, j26_cnt, pfill_off, pfill_cnt;
     int32_t all_leaves_off = 0, all_leaves_cnt = 0;      // leaves of every level
     // descriptor table {offset, count} per list, mirrored on the device (graph launches)
     std::vector<int32_t> desc;
@@ -126,7 +126,7 @@ uint64_t morton_encode(int shadow, int level, int bx, int by, int bz);
 // Descriptor indices of the work lists (DevTables lists + the device descriptor table).
 constexpr int MAX_LEVELS = 13;
 constexpr int DESC_LEAVES = 0, DESC_ALL = 1, DESC_FINE = 2, DESC_SCRATCH = 3;
-constexpr int DESC_PER_LEVEL = 5;
+constexpr int DESC_PER_LEVEL = 6;
 constexpr int desc_lvl(int l) { return 4 + DESC_PER_LEVEL * l; }
 constexpr int desc_par(int l) { return 5 + DESC_PER_LEVEL * l; }
 constexpr int desc_leaf(int l) { return 6 + DESC_PER_LEVEL * l; }
@@ -136,6 +136,10 @@ constexpr int desc_jleaf(int l) { return 7 + DESC_PER_LEVEL * l; }
 // leaves of level l with at least one of the 26 halo regions lacking a same-level
 // neighbour or on a zero-gradient boundary (filled before the details)
 constexpr int desc_jleaf26(int l) { return 8 + DESC_PER_LEVEL * l; }
+// non-leaf blocks of level l whose halo a stage's predictions read: parents of leaves
+// with a face lacking a same-level neighbour, and parents of such blocks that lack a
+// same-level neighbour in some region themselves
+constexpr int desc_pfill(int l) { return 9 + DESC_PER_LEVEL * l; }
 constexpr int N_DESC = 4 + DESC_PER_LEVEL * MAX_LEVELS;
 
 // Halo fill modes, two flags: FACES restricts the fill to the 6 face regions, 3 layers
@@ -152,8 +156,6 @@ hipError_t launch_prim2cons(const double *prim, const int32_t *slots, int n, T *
 template <typename T>
 hipError_t launch_fill_halos(T *U, const WorkList &wl, const DevTables &tb, FillMode mode,
                              hipStream_t st);
-template <typename T>
-hipError_t launch_copy_interiors(const T *src, T *dst, const WorkList &wl, hipStream_t st);
 template <typename T>
 hipError_t launch_project(T *U, const WorkList &wl, const DevTables &tb, hipStream_t st);
 template <typename T>
@@ -238,7 +240,6 @@ struct mrfv_ctx {
                                                  // valid for (gU, gU0, gdt)
     void *gU = nullptr, *gU0 = nullptr;
     const double *gdt = nullptr;
-    int lmax_all = 0;                  // deepest lmax over the instances
     std::vector<int64_t> lvl_bound;    // most blocks any level can hold
     // learned refinement proposer
     mrfv_mlp *mlp = nullptr;

@@ -248,6 +248,28 @@ void Topology::build(std::vector<BlockMeta> &meta, std::vector<int32_t> &child,
     L.jleaf_cnt.assign(maxl + 1, 0);
     L.j26_off.assign(maxl + 1, 0);
     L.j26_cnt.assign(maxl + 1, 0);
+    L.pfill_off.assign(maxl + 1, 0);
+    L.pfill_cnt.assign(maxl + 1, 0);
+    // prediction sources of a stage, marked fine to coarse
+    std::vector<char> pf(cap, 0);
+    auto lacks = [&](int s, bool faces_only) {
+        const BlockMeta &m = meta[s];
+        for (int r = 0; r < 27; ++r) {
+            if (r == 13) continue;
+            const int rx = r % 3 - 1, ry = (r / 3) % 3 - 1, rz = r / 9 - 1;
+            if (faces_only && (rx != 0) + (ry != 0) + (rz != 0) != 1) continue;
+            const bool zg = (rx < 0 && (m.zg & 1)) || (rx > 0 && (m.zg & 2)) || (ry < 0 && (m.zg & 4)) ||
+                            (ry > 0 && (m.zg & 8)) || (rz < 0 && (m.zg & 16)) || (rz > 0 && (m.zg & 32));
+            if (!zg && nbr[(size_t)s * 27 + r] < 0) return true;
+        }
+        return false;
+    };
+    for (int s : order)
+        if (blocks_[s].leaf && blocks_[s].parent >= 0 && lacks(s, true)) pf[blocks_[s].parent] = 1;
+    for (int l = maxl; l >= 1; --l)
+        for (int s : order)
+            if (blocks_[s].level == l && pf[s] && lacks(s, false) && blocks_[s].parent >= 0)
+                pf[blocks_[s].parent] = 1;
     const int face_region[6] = {12, 14, 10, 16, 4, 22};
     auto needs_face_fill = [&](int s) {
         const BlockMeta &m = meta[s];
@@ -295,6 +317,10 @@ void Topology::build(std::vector<BlockMeta> &meta, std::vector<int32_t> &child,
         for (int s : order)
             if (blocks_[s].level == l && blocks_[s].leaf && needs_region_fill(s)) L.data.push_back(s);
         L.j26_cnt[l] = (int32_t)L.data.size() - L.j26_off[l];
+        L.pfill_off[l] = (int32_t)L.data.size();
+        for (int s : order)
+            if (blocks_[s].level == l && !blocks_[s].leaf && pf[s]) L.data.push_back(s);
+        L.pfill_cnt[l] = (int32_t)L.data.size() - L.pfill_off[l];
     }
     L.all_leaves_off = (int32_t)L.data.size();
     for (int i = 0; i < n_inst; ++i) {
@@ -325,6 +351,7 @@ void Topology::build(std::vector<BlockMeta> &meta, std::vector<int32_t> &child,
         set(desc_leaf(l), L.leaf_off[l], L.leaf_cnt[l]);
         set(desc_jleaf(l), L.jleaf_off[l], L.jleaf_cnt[l]);
         set(desc_jleaf26(l), L.j26_off[l], L.j26_cnt[l]);
+        set(desc_pfill(l), L.pfill_off[l], L.pfill_cnt[l]);
     }
 }
 
