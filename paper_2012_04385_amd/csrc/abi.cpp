@@ -121,10 +121,12 @@ int levels_to_cover(const mrfv_ctx *ctx) {
     return ctx->lists.max_level;
 }
 
+// stage_only: restrict only the parents a fused stage reads (desc_pproj), else all.
 template <typename T>
-int do_project(mrfv_ctx *ctx, T *U) {
+int do_project(mrfv_ctx *ctx, T *U, bool stage_only = false) {
     for (int l = levels_to_cover(ctx) - 1; l >= 0; --l)
-        HIP_OK(launch_project<T>(U, wlist(ctx, desc_par(l)), ctx->tb, ctx->stream));
+        HIP_OK(launch_project<T>(U, wlist(ctx, stage_only ? desc_pproj(l) : desc_par(l)), ctx->tb,
+                                 ctx->stream));
     return MRFV_OK;
 }
 
@@ -487,7 +489,7 @@ int do_stages(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt) {
         const bool par = ctx->lists.parents_needed;
         for (int s = 0; s < 3; ++s) {
             float *in = buf[s], *out = buf[s + 1];
-            if (par) CALL(do_project<float>(ctx, in));
+            if (par) CALL(do_project<float>(ctx, in, true));
             CALL(do_fill<float>(ctx, in, 1 << 20, FILL_MISSING_FACES, par));
             CALL(do_stage_fused(ctx, s, dt, in, out, (float *)U0));
         }
@@ -516,6 +518,7 @@ uint64_t graph_key(const mrfv_ctx *ctx) {
         if (L.desc[2 * desc_par(l) + 1] > 0) k |= 1ull << (5 + l);
         if (L.desc[2 * desc_jleaf(l) + 1] > 0) k |= 1ull << (5 + MAX_LEVELS + l);
         if (L.desc[2 * desc_pfill(l) + 1] > 0) k |= 1ull << (5 + 2 * MAX_LEVELS + l);
+        if (L.desc[2 * desc_pproj(l) + 1] > 0) k |= 1ull << (5 + 3 * MAX_LEVELS + l);
     }
     return k;
 }
@@ -676,7 +679,7 @@ int mrfv_create(mrfv_ctx **out, const mrfv_config *cfg, const mrfv_instance *ins
     }
     ctx->stream = (hipStream_t)hip_stream;
     const size_t cap = cfg->slot_capacity, es = elem_size(ctx);
-    ctx->lists_cap = 2 * cfg->n_instances + 9 * cfg->slot_capacity + 16;
+    ctx->lists_cap = 2 * cfg->n_instances + 10 * cfg->slot_capacity + 16;
     ctx->prim_batch = 128;
     ctx->lvl_bound.assign(MAX_LEVELS, 0);
     for (int i = 0; i < cfg->n_instances; ++i) {
@@ -1002,7 +1005,7 @@ int mrfv_fused_stage(mrfv_ctx *ctx, int32_t stage, const double *dt_dev, void *U
     if (!dt_dev || !Uin || !Uout || !U0) return fail(ctx, MRFV_EINVAL, "fused_stage: null pointer");
     if (Uin == Uout) return fail(ctx, MRFV_EINVAL, "fused_stage: Uin and Uout must differ");
     const bool par = ctx->lists.parents_needed;
-    if (par) CALL(do_project<float>(ctx, (float *)Uin));
+    if (par) CALL(do_project<float>(ctx, (float *)Uin, true));
     CALL(do_fill<float>(ctx, (float *)Uin, 1 << 20, FILL_MISSING_FACES, par));
     return do_stage_fused(ctx, stage, dt_dev, (const float *)Uin, (float *)Uout, (float *)U0);
 }

@@ -63,7 +63,7 @@ struct HostLists {
     int max_level = 0;
     // per level: all blocks, non-leaf blocks, leaves
     std::vector<int32_t> lvl_off, lvl_cnt, par_off, par_cnt, leaf_off, leaf_cnt, jleaf_off, jleaf_cnt,
-        j26_off, j26_cnt, pfill_off, pfill_cnt;
+        j26_off, j26_cnt, pfill_off, pfill_cnt, pproj_off, pproj_cnt;
     int32_t all_leaves_off = 0, all_leaves_cnt = 0;      // leaves of every level
     // descriptor table {offset, count} per list, mirrored on the device (graph launches)
     std::vector<int32_t> desc;
@@ -126,7 +126,7 @@ uint64_t morton_encode(int shadow, int level, int bx, int by, int bz);
 // Descriptor indices of the work lists (DevTables lists + the device descriptor table).
 constexpr int MAX_LEVELS = 13;
 constexpr int DESC_LEAVES = 0, DESC_ALL = 1, DESC_FINE = 2, DESC_SCRATCH = 3;
-constexpr int DESC_PER_LEVEL = 6;
+constexpr int DESC_PER_LEVEL = 7;
 constexpr int desc_lvl(int l) { return 4 + DESC_PER_LEVEL * l; }
 constexpr int desc_par(int l) { return 5 + DESC_PER_LEVEL * l; }
 constexpr int desc_leaf(int l) { return 6 + DESC_PER_LEVEL * l; }
@@ -140,6 +140,10 @@ constexpr int desc_jleaf26(int l) { return 8 + DESC_PER_LEVEL * l; }
 // with a face lacking a same-level neighbour, and parents of such blocks that lack a
 // same-level neighbour in some region themselves
 constexpr int desc_pfill(int l) { return 9 + DESC_PER_LEVEL * l; }
+// non-leaf blocks of level l whose interior a stage reads: the stage's prediction
+// sources, their non-leaf same-level neighbours (copied into their halos), non-leaf
+// same-level face neighbours of leaves, and the non-leaf descendants of all of these
+constexpr int desc_pproj(int l) { return 10 + DESC_PER_LEVEL * l; }
 constexpr int N_DESC = 4 + DESC_PER_LEVEL * MAX_LEVELS;
 
 // Halo fill modes, two flags: FACES restricts the fill to the 6 face regions, 3 layers

@@ -250,6 +250,8 @@ void Topology::build(std::vector<BlockMeta> &meta, std::vector<int32_t> &child,
     L.j26_cnt.assign(maxl + 1, 0);
     L.pfill_off.assign(maxl + 1, 0);
     L.pfill_cnt.assign(maxl + 1, 0);
+    L.pproj_off.assign(maxl + 1, 0);
+    L.pproj_cnt.assign(maxl + 1, 0);
     // prediction sources of a stage, marked fine to coarse
     std::vector<char> pf(cap, 0);
     auto lacks = [&](int s, bool faces_only) {
@@ -270,6 +272,25 @@ void Topology::build(std::vector<BlockMeta> &meta, std::vector<int32_t> &child,
         for (int s : order)
             if (blocks_[s].level == l && pf[s] && lacks(s, false) && blocks_[s].parent >= 0)
                 pf[blocks_[s].parent] = 1;
+    // interiors a stage reads, then their non-leaf descendants (restricted bottom-up first)
+    std::vector<char> pr(cap, 0);
+    auto mark_nonleaf = [&](int nb) {
+        if (nb >= 0 && !blocks_[nb].leaf) pr[nb] = 1;
+    };
+    for (int s : order) {
+        const HostBlock &b = blocks_[s];
+        if (pf[s]) {
+            pr[s] = 1;
+            for (int r = 0; r < 27; ++r)
+                if (r != 13) mark_nonleaf(nbr[(size_t)s * 27 + r]);
+        }
+        if (b.leaf)
+            for (int r : {12, 14, 10, 16, 4, 22}) mark_nonleaf(nbr[(size_t)s * 27 + r]);   // faces
+    }
+    for (int l = 0; l <= maxl; ++l)
+        for (int s : order)
+            if (blocks_[s].level == l && pr[s])
+                for (int o = 0; o < 8; ++o) mark_nonleaf(blocks_[s].child[o]);
     const int face_region[6] = {12, 14, 10, 16, 4, 22};
     auto needs_face_fill = [&](int s) {
         const BlockMeta &m = meta[s];
@@ -321,6 +342,10 @@ void Topology::build(std::vector<BlockMeta> &meta, std::vector<int32_t> &child,
         for (int s : order)
             if (blocks_[s].level == l && !blocks_[s].leaf && pf[s]) L.data.push_back(s);
         L.pfill_cnt[l] = (int32_t)L.data.size() - L.pfill_off[l];
+        L.pproj_off[l] = (int32_t)L.data.size();
+        for (int s : order)
+            if (blocks_[s].level == l && !blocks_[s].leaf && pr[s]) L.data.push_back(s);
+        L.pproj_cnt[l] = (int32_t)L.data.size() - L.pproj_off[l];
     }
     L.all_leaves_off = (int32_t)L.data.size();
     for (int i = 0; i < n_inst; ++i) {
@@ -352,6 +377,7 @@ void Topology::build(std::vector<BlockMeta> &meta, std::vector<int32_t> &child,
         set(desc_jleaf(l), L.jleaf_off[l], L.jleaf_cnt[l]);
         set(desc_jleaf26(l), L.j26_off[l], L.j26_cnt[l]);
         set(desc_pfill(l), L.pfill_off[l], L.pfill_cnt[l]);
+        set(desc_pproj(l), L.pproj_off[l], L.pproj_cnt[l]);
     }
 }
 
