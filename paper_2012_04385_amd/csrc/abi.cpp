@@ -140,20 +140,24 @@ int do_project(mrfv_ctx *ctx, T *U, bool stage_only = false) {
 //   read same-level neighbours in place too).
 // with_parents = false leaves the non-leaf blocks out (a stage on a tree where no leaf face
 // reads a parent-derived value).
+// FILL_RHO_E (with FILL_MISSING, before the details) applies to the parents' fill too.
 template <typename T>
-int do_fill(mrfv_ctx *ctx, T *U, int max_level, FillMode mode = FILL_ALL, bool with_parents = true) {
+int do_fill(mrfv_ctx *ctx, T *U, int max_level, int mode = FILL_ALL, bool with_parents = true) {
+    const int qsel = mode & FILL_RHO_E, m = mode & ~FILL_RHO_E;
     for (int l = 0; l <= std::min(max_level, levels_to_cover(ctx)); ++l) {
-        if (mode == FILL_ALL) {
-            HIP_OK(launch_fill_halos<T>(U, wlist(ctx, desc_lvl(l), 1024), ctx->tb, FILL_ALL, ctx->stream));
+        if (m == FILL_ALL) {
+            HIP_OK(launch_fill_halos<T>(U, wlist(ctx, desc_lvl(l), 1024), ctx->tb, (FillMode)mode,
+                                        ctx->stream));
         } else {
             // a stage fills only the parents its predictions read; the fill before the
             // details (FILL_MISSING) all non-leaf blocks, whose details are judged too
-            const int pw = mode == FILL_MISSING_FACES ? desc_pfill(l) : desc_par(l);
+            const int pw = m == FILL_MISSING_FACES ? desc_pfill(l) : desc_par(l);
             if (with_parents)
-                HIP_OK(launch_fill_halos<T>(U, wlist(ctx, pw, 1024), ctx->tb, FILL_ALL, ctx->stream));
-            const int which = mode == FILL_FACES ? desc_leaf(l)
-                              : mode == FILL_MISSING_FACES ? desc_jleaf(l) : desc_jleaf26(l);
-            HIP_OK(launch_fill_halos<T>(U, wlist(ctx, which, 1024), ctx->tb, mode, ctx->stream));
+                HIP_OK(launch_fill_halos<T>(U, wlist(ctx, pw, 1024), ctx->tb, (FillMode)(FILL_ALL | qsel),
+                                            ctx->stream));
+            const int which = m == FILL_FACES ? desc_leaf(l)
+                              : m == FILL_MISSING_FACES ? desc_jleaf(l) : desc_jleaf26(l);
+            HIP_OK(launch_fill_halos<T>(U, wlist(ctx, which, 1024), ctx->tb, (FillMode)mode, ctx->stream));
         }
     }
     return MRFV_OK;
@@ -592,7 +596,8 @@ int do_step(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt) {
     }
     if (!adapt) return MRFV_OK;
     CALL(do_project<T>(ctx, U));
-    CALL(do_fill<T>(ctx, U, 1 << 20, FILL_MISSING));
+    // the details read only rho and E; refined parents get all components in do_predict
+    CALL(do_fill<T>(ctx, U, 1 << 20, FILL_MISSING | FILL_RHO_E));
     CALL(do_details_flags<T>(ctx, U, ctx->d_flags, ctx->d_det));
     const int cap = ctx->cfg.slot_capacity;
     HIP_OK(hipMemcpyAsync(ctx->h_flags, ctx->d_flags, cap, hipMemcpyDeviceToHost, ctx->stream));

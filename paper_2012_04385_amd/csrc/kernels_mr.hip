@@ -159,10 +159,13 @@ __global__ __launch_bounds__(TPB) void k_fill_halos(T *__restrict__ U, WorkList 
         T *dst = U + (size_t)slot * 5 * CELLS_P;
         const int ncell = g.n[0] * g.n[1] * g.n[2];
         const Div dc(ncell), d0(g.n[0]), d1(g.n[1]);
+        const bool re = (mode & FILL_RHO_E) != 0;
+        const int nq = re ? 2 : 5;
         if (src >= 0) {
             const T *sb = U + (size_t)src * 5 * CELLS_P;
-            for (int t = tid; t < 5 * ncell; t += TPB) {
-                const int q = dc.quot(t), e = t - q * ncell;
+            for (int t = tid; t < nq * ncell; t += TPB) {
+                const int qi = dc.quot(t), e = t - qi * ncell;
+                const int q = re ? 4 * qi : qi;
                 const int e1 = d0.quot(e), e2 = d1.quot(e1);
                 const int i = g.lo[0] + e - e1 * g.n[0], j = g.lo[1] + e1 - e2 * g.n[1], k = g.lo[2] + e2;
                 const int si = g.clamp[0] >= 0 ? g.clamp[0] : i - NI * g.r[0];
@@ -186,7 +189,8 @@ __global__ __launch_bounds__(TPB) void k_fill_halos(T *__restrict__ U, WorkList 
         }
         const T *pu = U + (size_t)m.parent * 5 * CELLS_P;
         const Div dp0(np[0]), dp1(np[1]), dm0(me[0]), dm1(me[1]);
-        for (int q = 0; q < 5; ++q) {
+        for (int qi = 0; qi < nq; ++qi) {
+            const int q = re ? 4 * qi : qi;
             const int na = np[0] * np[1] * np[2];
             for (int t = tid; t < na; t += TPB) {
                 const int t1 = dp0.quot(t), kk = dp1.quot(t1);

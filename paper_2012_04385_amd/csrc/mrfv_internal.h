@@ -150,7 +150,9 @@ constexpr int N_DESC = 4 + DESC_PER_LEVEL * MAX_LEVELS;
 // deep (all the flux stencils read); MISSING to the regions without a same-level
 // neighbour or on a zero-gradient boundary (the other regions are read in place from
 // the neighbour's interior by the fused stage and the details).
-enum FillMode { FILL_ALL = 0, FILL_FACES = 1, FILL_MISSING = 2, FILL_MISSING_FACES = 3 };
+// FILL_RHO_E limits any mode to the density and energy components (the details read
+// nothing else).
+enum FillMode { FILL_ALL = 0, FILL_FACES = 1, FILL_MISSING = 2, FILL_MISSING_FACES = 3, FILL_RHO_E = 4 };
 
 // --------------------------------------------------------------- kernel launchers ----
 // All launchers enqueue on `st` and return hipGetLastError().
