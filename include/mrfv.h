@@ -153,7 +153,12 @@ int mrfv_commit_flags(mrfv_ctx *ctx, const int8_t *flags_host, int32_t *new_slot
  * {mr_project, fill_halos, rhs + jump correction, rk_update}; then, for adaptive
  * instances, mr_project, fill_halos, mr_flag, one device-to-host copy of the flags,
  * commit_flags and mr_predict of the new children.  U0, L: dev scratch of
- * mrfv_interior_bytes.  dt_dev: dev double[n_instances] receives this step's dt. */
+ * mrfv_interior_bytes.  dt_dev: dev double[n_instances] receives this step's dt.
+ * The batched FP32 path runs the stages out of place through two library-owned state
+ * buffers (U -> W -> W2 -> U), reading same-level neighbours' interiors directly, and
+ * restricts and fills only what the stages and the details read; on return U holds the
+ * new state in every leaf interior (call mr_project and fill_halos for restricted
+ * parents and complete halos). */
 int mrfv_step(mrfv_ctx *ctx, void *U, void *U0, void *L, double *dt_dev);
 
 /* check -- reads and clears the device error word: MRFV_ENONPHYS if a stage produced a
