@@ -472,32 +472,23 @@ struct LdsSink {
 // D in the same order, so all give bitwise the same result.
 constexpr int NFZ = NI * NI;                  // z-faces per face plane (256)
 
-template <typename T>
-__device__ __forceinline__ void load_cell_rt(const T *__restrict__ u, int idx, int n1, int t1,
-                                             int t2, CellState<T> &s) {
-    s.r = u[idx];
-    s.mn = u[idx + n1 * CELLS_P];
-    s.mt1 = u[idx + t1 * CELLS_P];
-    s.mt2 = u[idx + t2 * CELLS_P];
-    s.E = u[idx + 4 * CELLS_P];
-}
 
-// Face flux along axis d for the stencil starting at padded index base (six cells at
-// base + j*stride, padded coordinate pos0 + j along d); cells below / above the interior
-// come from lo / hi, which are the neighbour's block shifted by -+16 cells along d (or
+// Face flux along axis D for the stencil starting at padded index base (six cells at
+// base + j*stride, padded coordinate pos0 + j along D); cells below / above the interior
+// come from lo / hi, which are the neighbour's block shifted by -+16 cells along D (or
 // the own block).  The result is returned in physical component order.
-template <typename T>
+template <typename T, int D>
 __device__ __forceinline__ void face_flux_at(const T *__restrict__ ub, const T *__restrict__ lo,
-                                             const T *__restrict__ hi, int d, int base, int pos0,
+                                             const T *__restrict__ hi, int base, int pos0,
                                              const Gas<T> &G, T Fp[5]) {
-    const int stride = d == 0 ? 1 : (d == 1 ? NP : NP * NP);
-    const int n1 = d + 1, t1 = d == 0 ? 2 : (d == 1 ? 3 : 1), t2 = d == 0 ? 3 : (d == 1 ? 1 : 2);
+    constexpr int stride = Axes<D>::STRIDE;
+    constexpr int n1 = Axes<D>::N1, t1 = Axes<D>::T1, t2 = Axes<D>::T2;   // rotated components
     CellState<T> w[6];
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
         const int pos = pos0 + j;
         const T *src = pos < HW ? lo : (pos >= HW + NI ? hi : ub);
-        load_cell_rt(src, base + j * stride, n1, t1, t2, w[j]);
+        load_state<T, D>(src, base + j * stride, G, w[j]);
         derive_state(G, w[j]);
     }
     T F[5];
@@ -635,7 +626,7 @@ void k_rhs_update(int stage, const double *__restrict__ dt,
             if (t < NFX) {                      // x-faces: (plane p, row y, face f)
                 const int f = t % (NI + 1), y = (t / (NI + 1)) % NI, p = t / ((NI + 1) * NI);
                 const int base = ((k0 + p + HW) * NP + y + HW) * NP + f + 1;
-                face_flux_at(ub, nlo[0], nhi[0], 0, base, f + 1, G, F);
+                face_flux_at<T, 0>(ub, nlo[0], nhi[0], base, f + 1, G, F);
 #pragma unroll
                 for (int q = 0; q < 5; ++q) Fx[p][y][f][q] = F[q];
                 if (f == 0 || f == NI) {
@@ -646,7 +637,7 @@ void k_rhs_update(int stage, const double *__restrict__ dt,
                 const int u = t - NFX;
                 const int x = u % NI, f = (u / NI) % (NI + 1), p = u / (NI * (NI + 1));
                 const int base = ((k0 + p + HW) * NP + f + 1) * NP + x + HW;
-                face_flux_at(ub, nlo[1], nhi[1], 1, base, f + 1, G, F);
+                face_flux_at<T, 1>(ub, nlo[1], nhi[1], base, f + 1, G, F);
 #pragma unroll
                 for (int q = 0; q < 5; ++q) Fy[p][f][x][q] = F[q];
                 if (f == 0 || f == NI) {
@@ -661,7 +652,7 @@ void k_rhs_update(int stage, const double *__restrict__ dt,
                     face_flux_ring<T, ZR>(Zr, kf, y * NI + x, G, F);
                 } else {
                     const int base = ((kf + 1) * NP + y + HW) * NP + x + HW;   // padded z = kf+1 .. kf+6
-                    face_flux_at(ub, nlo[2], nhi[2], 2, base, kf + 1, G, F);
+                    face_flux_at<T, 2>(ub, nlo[2], nhi[2], base, kf + 1, G, F);
                 }
 #pragma unroll
                 for (int q = 0; q < 5; ++q) Fz[j][y][x][q] = F[q];
