@@ -155,8 +155,10 @@ def other_workload(args):
         torch.cuda.synchronize()
         secs = time.perf_counter() - t0
         g.check()
+        # MR compression: leaf cells over the cells of the uniform finest grid
+        full = sum(pb.n0[0] * pb.n0[1] * pb.n0[2] * 8 ** pb.lmax * 16 ** 3 for pb in pbs)
         res[batched] = (cells / secs, 1e3 * secs / args.steps, g.kernel_time() if timing else None,
-                        g.stats()[1], g.step_timing())
+                        g.stats()[1], g.step_timing(), g.stats()[2] / full)
         log(f"[bench] {args.workload} batched={batched}: {res[batched][0]:.4e} cell-updates/s, "
             f"{res[batched][1]:.2f} ms/step")
         del g
@@ -171,6 +173,7 @@ def other_workload(args):
            "ms_per_step": res[2][1], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f32", "data": "synthetic",
            "config": {"workload": args.workload, "instances": len(pbs), "leaves_final": res[2][3],
+                      "compression": res[2][5],
                       "path": "batched FP32, RK stages replayed from a hipGraph"},
            "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
                         "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR, "traffic": None,
