@@ -156,9 +156,10 @@ int mrfv_commit_flags(mrfv_ctx *ctx, const int8_t *flags_host, int32_t *new_slot
  * mrfv_interior_bytes.  dt_dev: dev double[n_instances] receives this step's dt.
  * The batched FP32 path runs the stages out of place through two library-owned state
  * buffers (U -> W -> W2 -> U), reading same-level neighbours' interiors directly, and
- * restricts and fills only what the stages and the details read; on return U holds the
- * new state in every leaf interior (call mr_project and fill_halos for restricted
- * parents and complete halos). */
+ * restricts and fills only what the stages read.  Before the details only rho and E are
+ * restricted and filled (all components are restricted when the flags change the tree).
+ * On return U holds the new state in every leaf interior (call mr_project and fill_halos
+ * for restricted parents and complete halos). */
 int mrfv_step(mrfv_ctx *ctx, void *U, void *U0, void *L, double *dt_dev);
 
 /* check -- reads and clears the device error word: MRFV_ENONPHYS if a stage produced a
@@ -210,8 +211,9 @@ int mrfv_fused_stage(mrfv_ctx *ctx, int32_t stage, const double *dt_dev, void *U
 int mrfv_rhs_variant(mrfv_ctx *ctx, int32_t set, int32_t *n_variants_host, int32_t *shapes_host);
 
 /* autotune -- times every variant on the current tree and state (reps launches each,
- * after one warm-up) and keeps the fastest.  The state U is not modified; U0, the second
- * state buffer and dt_dev (dev double[n_instances], receives the CFL step) are used as
+ * after one warm-up) and keeps the fastest.  Leaf interiors of U are not modified (its
+ * parents are restricted and halos filled, as before a stage); U0, the second state
+ * buffer and dt_dev (dev double[n_instances], receives the CFL step) are used as
  * scratch.  ms_host (may be NULL): host float[n_variants] receives the mean launch time
  * of each variant; *choice_host the chosen variant.  Batched FP32 contexts only.
  * Synchronises the stream. */

@@ -123,10 +123,10 @@ int levels_to_cover(const mrfv_ctx *ctx) {
 
 // stage_only: restrict only the parents a fused stage reads (desc_pproj), else all.
 template <typename T>
-int do_project(mrfv_ctx *ctx, T *U, bool stage_only = false) {
+int do_project(mrfv_ctx *ctx, T *U, bool stage_only = false, bool rho_e_only = false) {
     for (int l = levels_to_cover(ctx) - 1; l >= 0; --l)
         HIP_OK(launch_project<T>(U, wlist(ctx, stage_only ? desc_pproj(l) : desc_par(l)), ctx->tb,
-                                 ctx->stream));
+                                 ctx->stream, rho_e_only ? 0x11 : 0x1f));
     return MRFV_OK;
 }
 
@@ -268,8 +268,15 @@ int do_details_flags(mrfv_ctx *ctx, const T *U, int8_t *flags, double *det) {
 }
 
 template <typename T>
-int do_predict(mrfv_ctx *ctx, T *U, const int32_t *slots_host, int n) {
+int do_predict(mrfv_ctx *ctx, T *U, const int32_t *slots_host, int n, bool fill_parents = true) {
     if (n <= 0) return MRFV_OK;
+    if (!fill_parents) {
+        HIP_OK(hipMemcpyAsync(ctx->d_slots, slots_host, sizeof(int32_t) * n,
+                              hipMemcpyHostToDevice, ctx->stream));
+        HIP_OK(launch_predict<T>(U, ctx->d_slots, n, ctx->tb, ctx->stream));
+        HIP_OK(hipStreamSynchronize(ctx->stream));   // slots_host may be a temporary
+        return MRFV_OK;
+    }
     // the parents' halos complete first: the prediction stencils reach 2 parent cells
     // beyond the child's octant, and a parent that was a leaf may have had only the
     // regions without a same-level neighbour filled
@@ -595,8 +602,9 @@ int do_step(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt) {
         CALL(do_stages<T>(ctx, U, U0, Lb, dt));
     }
     if (!adapt) return MRFV_OK;
-    CALL(do_project<T>(ctx, U));
-    // the details read only rho and E; refined parents get all components in do_predict
+    // the details read only rho and E: parents are restricted and filled in those two;
+    // all components are restricted and filled below when the flags change the tree
+    CALL(do_project<T>(ctx, U, false, true));
     CALL(do_fill<T>(ctx, U, 1 << 20, FILL_MISSING | FILL_RHO_E));
     CALL(do_details_flags<T>(ctx, U, ctx->d_flags, ctx->d_det));
     const int cap = ctx->cfg.slot_capacity;
@@ -619,6 +627,38 @@ int do_step(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt) {
     HIP_OK(hipStreamSynchronize(ctx->stream));
     const auto w1 = clk::now();
     if (*ctx->h_err) return fail(ctx, MRFV_ENONPHYS, "non-physical state (rho<=0, p+B<=0 or NaN)");
+    {
+        // The details saw rho and E only.  When the tree changes, on the old tree and
+        // before it changes: every component is restricted (a coarsened parent becomes a
+        // leaf with its restricted values), the parents' halos are filled, and then the
+        // full halos of the leaves to be refined, whose children are predicted from them
+        // (after the commit a same-level neighbour of such a leaf can be a fresh child
+        // that holds no data yet).
+        const HostLists &L = ctx->lists;
+        bool change = false;
+        std::vector<int32_t> refined;
+        for (int i = 0; i < L.all_leaves_cnt; ++i) {
+            const int32_t sl = L.data[L.all_leaves_off + i];
+            const int8_t f = ctx->h_flags[sl];
+            change = change || f == 1 || f == -1;
+            if (f == 1) refined.push_back(sl);
+        }
+        if (change) {
+            CALL(do_project<T>(ctx, U));
+            CALL(do_fill<T>(ctx, U, 1 << 20, FILL_MISSING));
+        }
+        if (!refined.empty()) {
+            HIP_OK(hipMemcpyAsync(ctx->d_slots2, refined.data(), sizeof(int32_t) * refined.size(),
+                                  hipMemcpyHostToDevice, ctx->stream));
+            WorkList wr;
+            wr.base = ctx->d_slots2;
+            wr.n = (int32_t)refined.size();
+            wr.grid = std::min<int>(wr.n, 1024);
+            HIP_OK(launch_fill_halos<T>(U, wr, ctx->tb, FILL_ALL, ctx->stream));
+            // refined lives until the copy has been read
+            HIP_OK(hipStreamSynchronize(ctx->stream));
+        }
+    }
     std::vector<int32_t> fresh;
     if (prop) {
         bool hit = true;
@@ -646,7 +686,7 @@ int do_step(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt) {
         CALL(commit(ctx, ctx->h_flags, fresh));
     }
     const auto w2 = clk::now();
-    CALL(do_predict<T>(ctx, U, fresh.data(), (int)fresh.size()));
+    CALL(do_predict<T>(ctx, U, fresh.data(), (int)fresh.size(), false));
     const auto w3 = clk::now();
     ctx->h_wait_ms += ms(w0, w1);
     ctx->h_commit_ms += ms(w1, w2);

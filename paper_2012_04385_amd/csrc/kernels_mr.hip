@@ -239,10 +239,10 @@ __global__ __launch_bounds__(TPB) void k_fill_halos(T *__restrict__ U, WorkList 
     }
 }
 
-// One thread per parent interior cell.
+// One thread per parent interior cell; components whose bit is set in qmask.
 template <typename T>
 __global__ __launch_bounds__(TPB) void k_project(T *__restrict__ U, WorkList wl,
-                                                 const int32_t *__restrict__ child) {
+                                                 const int32_t *__restrict__ child, int qmask) {
     const int nb = wl.count();
     for (int b = blockIdx.x; b < nb; b += gridDim.x) {
     const int slot = wl.at(b);
@@ -254,6 +254,7 @@ __global__ __launch_bounds__(TPB) void k_project(T *__restrict__ U, WorkList wl,
     const int ci = HW + 2 * (I & 7), cj = HW + 2 * (J & 7), ck = HW + 2 * (K & 7);
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
+        if (!((qmask >> q) & 1)) continue;
         const T *c0 = cu + pidx(q, ck, cj, ci);
         const T *c1 = c0 + NP * NP;
         const double s = (((double)c0[0] + (double)c0[1]) + ((double)c0[NP] + (double)c0[NP + 1])) +
@@ -283,15 +284,26 @@ __global__ __launch_bounds__(TPB) void k_predict(T *__restrict__ U,
 // Details, FP64.  DZ workgroups per block (level >= 1), each for a slab of 24/DZ padded
 // z-planes, write their maxima of the rho and E details over the slab; det[slot] is the
 // maximum over the slabs (atomicMax on the bit patterns of non-negative doubles, after
-// the list's entries were zeroed).  The prediction is applied separably through LDS:
-// the parent planes the slab's stencils touch are staged once, then passes along x, y
-// and z evaluate each 1D step once per output (operation order of predict_cell).
+// the list's entries were zeroed).  The prediction is applied separably through LDS, in
+// the order z, x, y: the parent planes the slab's stencils touch are staged once, the z
+// pass makes the slab's child planes on the parent's (x, y) cells, the x pass the child
+// x-cells, and the y pass is evaluated at the output.  Both children of a parent cell
+// along the pass axis share the five stencil values and the correction (one step gives
+// z0 + corr and z0 - corr), so every stencil is read once per sibling pair.
 // Cells outside the interior are read from the same-level neighbour's interior where
 // one exists (else from the own halo, filled for such regions).
 constexpr int DZ = 4;                          // slabs per block
-constexpr int DTPB = 512;                      // threads per workgroup (68 KB LDS: 2 per CU)
+constexpr int DTPB = 384;                      // threads per workgroup (16 rows of 24 cells)
 constexpr int SZ = NP / DZ;                    // padded z-planes per slab (6; even)
 constexpr int PZ = SZ / 2 + 4;                 // parent planes per slab (7)
+
+// One 1D prediction step for both siblings: lo = z0 + corr, hi = z0 - corr.
+__device__ __forceinline__ void pred_pair(double m2, double m1, double z0, double p1, double p2,
+                                          double &lo, double &hi) {
+    const double corr = (-22.0 / 128.0) * (p1 - m1) + (3.0 / 128.0) * (p2 - m2);
+    lo = z0 + corr;
+    hi = z0 - corr;
+}
 
 template <typename T>
 __global__ __launch_bounds__(DTPB) void k_details(const T *__restrict__ U, WorkList wl,
@@ -300,75 +312,115 @@ __global__ __launch_bounds__(DTPB) void k_details(const T *__restrict__ U, WorkL
                                                  const InstDev *__restrict__ inst,
                                                  double *__restrict__ det) {
     constexpr int R = NI;                       // parent region edge in x and y (16)
-    __shared__ double A[PZ * R * R];            // parent planes (14 KB)
-    __shared__ double Bx[PZ * R * NP];          // x pass (21 KB)
-    __shared__ double By[PZ * NP * NP];         // y pass (32 KB)
-    __shared__ long long src27[27];             // element offsets of the 27 sources
+    constexpr int NPAIR = NP / 2;               // sibling pairs along a padded axis (12)
+    constexpr int NA = (PZ * R * R + DTPB - 1) / DTPB;        // parent loads per thread (5)
+    constexpr int YROWS = SZ * NPAIR;                          // y-pass rows (kc, jp): 72
+    constexpr int NY = (YROWS + DTPB / NP - 1) / (DTPB / NP);  // y-pass rows per thread (5)
+    __shared__ T A[PZ * R * R];                 // parent planes [kk][jj][ii]
+    __shared__ double Cz[SZ * R * R];           // z pass [kc][jj][ii]
+    __shared__ double Cx[SZ * R * NP];          // x pass [kc][jj][i]
     __shared__ double red[DTPB / 64];
     const int nb = wl.count();
     const int part = blockIdx.y;
     const int k_lo = part * SZ;                 // first padded output plane
     const int kk0 = ((k_lo - HW) >> 1) + HW - 2;   // first parent plane (region coordinates)
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int xi = tid % NP, xr = tid / NP;     // y pass: cell i, first row (16 rows apart)
+    const int pi = tid % NPAIR, pr = tid / NPAIR;   // x pass: pair, first row (32 rows apart)
+    const int rx = xi < HW ? 0 : (xi < HW + NI ? 1 : 2);
     for (int b = blockIdx.x; b < nb; b += gridDim.x) {
     const int slot = wl.at(b);
     const BlockMeta m = meta[slot];
     const InstDev P = inst[m.inst];
     const int ox = m.bx & 1, oy = m.by & 1, oz = m.bz & 1;
     const T *pu = U + (size_t)m.parent * 5 * CELLS_P;
-    if (threadIdx.x < 27) {
-        const int r = threadIdx.x;
-        const int rx = r % 3 - 1, ry = (r / 3) % 3 - 1, rz = r / 9 - 1;
-        const bool zg = (rx < 0 && (m.zg & 1)) || (rx > 0 && (m.zg & 2)) ||
-                        (ry < 0 && (m.zg & 4)) || (ry > 0 && (m.zg & 8)) ||
-                        (rz < 0 && (m.zg & 16)) || (rz > 0 && (m.zg & 32));
-        const int s = (r == 13 || zg) ? -1 : nbr[(size_t)slot * 27 + r];
-        src27[r] = s >= 0 ? (long long)s * 5 * CELLS_P - NI * (rx + NP * (ry + NP * rz))
-                          : (long long)slot * 5 * CELLS_P;
+    // Global loads are issued ahead of their use (barriers wait for LDS only): the parent
+    // planes of rho and E here, the slab's output cells of rho here and those of E after
+    // the rho y pass, so that they arrive during E's z and x passes.  Output cell sources:
+    // lane r < 27 of each wavefront holds the element offset of region r (the same-level
+    // neighbour shifted onto own padded indices, or the own block), read by shuffles.
+    T av[2][NA], uv[NY][2];
+#pragma unroll
+    for (int v = 0; v < 2; ++v)
+#pragma unroll
+        for (int n = 0; n < NA; ++n) {
+            const int t = tid + n * DTPB;
+            if (t < PZ * R * R) {
+                const int ii = t & 15, jj = (t >> 4) & 15, kk = t >> 8;
+                av[v][n] = pu[4 * v * CELLS_P + pidx(0, oz * 8 + kk0 + kk, oy * 8 + jj, ox * 8 + ii)];
+            }
+        }
+    long long src = (long long)slot * 5 * CELLS_P;
+    if (lane < 27) {
+        const int ex = lane % 3 - 1, ey = (lane / 3) % 3 - 1, ez = lane / 9 - 1;
+        const bool zg = (ex < 0 && (m.zg & 1)) || (ex > 0 && (m.zg & 2)) ||
+                        (ey < 0 && (m.zg & 4)) || (ey > 0 && (m.zg & 8)) ||
+                        (ez < 0 && (m.zg & 16)) || (ez > 0 && (m.zg & 32));
+        const int s = (lane == 13 || zg) ? -1 : nbr[(size_t)slot * 27 + lane];
+        if (s >= 0) src = (long long)s * 5 * CELLS_P - NI * (ex + NP * (ey + NP * ez));
     }
+    auto load_out = [&](int q) {
+#pragma unroll
+        for (int n = 0; n < NY; ++n) {
+            const int row = min(xr + n * (DTPB / NP), YROWS - 1);
+            const int kc = row / NPAIR, jp = row - kc * NPAIR, k = k_lo + kc;
+            const int rz = k < HW ? 0 : (k < HW + NI ? 1 : 2);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int j = 2 * jp + h;
+                const int ry = j < HW ? 0 : (j < HW + NI ? 1 : 2);
+                const long long so = __shfl(src, (rz * 3 + ry) * 3 + rx);
+                if (xr + n * (DTPB / NP) < YROWS) uv[n][h] = U[so + q * CELLS_P + pidx(0, k, j, xi)];
+            }
+        }
+    };
+    load_out(0);
     double d = 0.0;
+#pragma unroll
     for (int v = 0; v < 2; ++v) {
-        const int q = v == 0 ? 0 : 4;
         const double inv_s = v == 0 ? 1.0 / P.scale_rho : 1.0 / P.scale_E;
-        // parent padded cells (oz*8 + kk0 + kk, oy*8 + jj, ox*8 + ii)
-        for (int t = threadIdx.x; t < PZ * R * R; t += DTPB) {
-            const int ii = t & 15, jj = (t >> 4) & 15, kk = t >> 8;
-            A[t] = (double)pu[q * CELLS_P + pidx(0, oz * 8 + kk0 + kk, oy * 8 + jj, ox * 8 + ii)];
+        // parent padded cells (oz*8 + kk0 + kk, oy*8 + jj, ox*8 + ii); A was last read by
+        // the previous component's z pass, before its second barrier
+#pragma unroll
+        for (int n = 0; n < NA; ++n)
+            if (tid + n * DTPB < PZ * R * R) A[tid + n * DTPB] = av[v][n];
+        __syncthreads();
+        // z: child planes 2p, 2p+1 of the slab from parent planes p .. p+4
+        for (int t = tid; t < (SZ / 2) * R * R; t += DTPB) {
+            const int c = t & (R * R - 1), p = t >> 8;
+            const T *a = A + p * R * R + c;
+            pred_pair((double)a[0], (double)a[R * R], (double)a[2 * R * R], (double)a[3 * R * R],
+                      (double)a[4 * R * R], Cz[2 * p * R * R + c], Cz[(2 * p + 1) * R * R + c]);
         }
         __syncthreads();
-        for (int t = threadIdx.x; t < PZ * R * NP; t += DTPB) {
-            const int i = t % NP, r = t / NP;
-            const int ci = i - HW, II = (ci >> 1) + HW;
-            const double *row = A + r * R + II;
-            Bx[t] = pred1<double>(row[-2], row[-1], row[0], row[1], row[2], (ci & 1) ? -1.0 : 1.0);
+        // x: child cells 2ip, 2ip+1 of row (kc, jj) from parent cells ip .. ip+4
+        for (int row = pr; row < SZ * R; row += DTPB / NPAIR) {
+            const double *a = Cz + row * R + pi;
+            pred_pair(a[0], a[1], a[2], a[3], a[4], Cx[row * NP + 2 * pi], Cx[row * NP + 2 * pi + 1]);
         }
         __syncthreads();
-        for (int t = threadIdx.x; t < PZ * NP * NP; t += DTPB) {
-            const int i = t % NP, j = (t / NP) % NP, kk = t / (NP * NP);
-            const int cj = j - HW, JJ = (cj >> 1) + HW;
-            const double *col = Bx + (kk * R + JJ) * NP + i;
-            By[t] = pred1<double>(col[-2 * NP], col[-NP], col[0], col[NP], col[2 * NP],
-                                  (cj & 1) ? -1.0 : 1.0);
+        // y at the output: child rows 2jp, 2jp+1 of plane kc, cell i, from Cx rows jp .. jp+4
+#pragma unroll
+        for (int n = 0; n < NY; ++n) {
+            const int row = xr + n * (DTPB / NP);
+            if (row < YROWS) {
+                const int kc = row / NPAIR, jp = row - kc * NPAIR;
+                const double *a = Cx + (kc * R + jp) * NP + xi;
+                double pv[2];
+                pred_pair(a[0], a[NP], a[2 * NP], a[3 * NP], a[4 * NP], pv[0], pv[1]);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) d = fmax(d, fabs((double)uv[n][h] - pv[h]) * inv_s);
+            }
         }
-        __syncthreads();
-        for (int cell = threadIdx.x; cell < SZ * NP * NP; cell += DTPB) {
-            const int i = cell % NP, j = (cell / NP) % NP, k = k_lo + cell / (NP * NP);
-            const int ck = k - HW, KK = (ck >> 1) + HW - kk0;
-            const double *c = By + (KK * NP + j) * NP + i;
-            const double pv = pred1<double>(c[-2 * NP * NP], c[-NP * NP], c[0], c[NP * NP],
-                                            c[2 * NP * NP], (ck & 1) ? -1.0 : 1.0);
-            const int rx = i < HW ? 0 : (i < HW + NI ? 1 : 2), ry = j < HW ? 0 : (j < HW + NI ? 1 : 2),
-                      rz = k < HW ? 0 : (k < HW + NI ? 1 : 2);
-            const long long so = src27[(rz * 3 + ry) * 3 + rx];
-            const double u = (double)U[so + q * CELLS_P + pidx(0, k, j, i)];
-            d = fmax(d, fabs(u - pv) * inv_s);
-        }
-        __syncthreads();
+        if (v == 0) load_out(4);
+        // Cz and Cx of the next component are written after its first barrier, which
+        // every thread reaches only after this y pass
     }
     // wavefront max, then across the workgroup's waves
     for (int off = 32; off > 0; off >>= 1) d = fmax(d, __shfl_xor(d, off));
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = d;
+    if ((tid & 63) == 0) red[tid >> 6] = d;
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         double mx = red[0];
         for (int w = 1; w < DTPB / 64; ++w) mx = fmax(mx, red[w]);
         atomicMax((unsigned long long *)(det + slot), (unsigned long long)__double_as_longlong(mx));
@@ -424,13 +476,15 @@ __global__ __launch_bounds__(TPB) void k_cfl_block(const T *__restrict__ U, Work
                                                    const BlockMeta *__restrict__ meta,
                                                    const InstDev *__restrict__ inst,
                                                    double *__restrict__ bmax) {
-    __shared__ double red[3][TPB];
+    __shared__ double red[3][TPB / 64];
     const int nb = wl.count();
     for (int b = blockIdx.x; b < nb; b += gridDim.x) {
     const int slot = wl.at(b);
     const InstDev P = inst[meta[slot].inst];
     const T *u = U + (size_t)slot * 5 * CELLS_P;
     double mx[3] = {0.0, 0.0, 0.0};
+    // unrolled so that several cells' loads are in flight at once
+#pragma unroll 4
     for (int c = threadIdx.x; c < CELLS_I; c += TPB) {
         const int o = pidx(0, HW + c / FACE, HW + (c / NI) % NI, HW + c % NI);
         const double r = u[o], m0 = u[o + CELLS_P], m1 = u[o + 2 * CELLS_P],
@@ -443,15 +497,18 @@ __global__ __launch_bounds__(TPB) void k_cfl_block(const T *__restrict__ U, Work
         mx[1] = fmax(mx[1], fabs(m1 * ir) + cs);
         mx[2] = fmax(mx[2], fabs(m2 * ir) + cs);
     }
-    for (int a = 0; a < 3; ++a) red[a][threadIdx.x] = mx[a];
-    __syncthreads();
-    for (int w = TPB / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w)
-            for (int a = 0; a < 3; ++a)
-                red[a][threadIdx.x] = fmax(red[a][threadIdx.x], red[a][threadIdx.x + w]);
-        __syncthreads();
+    // maxima over the wavefront, then over the workgroup's waves
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        for (int off = 32; off > 0; off >>= 1) mx[a] = fmax(mx[a], __shfl_xor(mx[a], off));
+        if ((threadIdx.x & 63) == 0) red[a][threadIdx.x >> 6] = mx[a];
     }
-    if (threadIdx.x < 3) bmax[(size_t)slot * 5 + threadIdx.x] = red[threadIdx.x][0];
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        double v = red[threadIdx.x][0];
+        for (int w = 1; w < TPB / 64; ++w) v = fmax(v, red[threadIdx.x][w]);
+        bmax[(size_t)slot * 5 + threadIdx.x] = v;
+    }
     __syncthreads();
     }
 }
@@ -561,9 +618,10 @@ hipError_t launch_fill_halos(T *U, const WorkList &wl, const DevTables &tb, Fill
 
 
 template <typename T>
-hipError_t launch_project(T *U, const WorkList &wl, const DevTables &tb, hipStream_t st) {
+hipError_t launch_project(T *U, const WorkList &wl, const DevTables &tb, hipStream_t st,
+                          int qmask) {
     if (wl.grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_project<T>, grid2(wl.grid, NI), dim3(TPB), 0, st, U, wl, tb.child);
+    hipLaunchKernelGGL(k_project<T>, grid2(wl.grid, NI), dim3(TPB), 0, st, U, wl, tb.child, qmask);
     return hipGetLastError();
 }
 
@@ -628,7 +686,7 @@ hipError_t launch_totals(const T *U, const WorkList &leaves, const DevTables &tb
     template hipError_t launch_fill_halos<T>(T *, const WorkList &, const DevTables &,       \
                                              FillMode, hipStream_t);                        \
     template hipError_t launch_project<T>(T *, const WorkList &, const DevTables &,         \
-                                          hipStream_t);                                     \
+                                          hipStream_t, int);                                \
     template hipError_t launch_predict<T>(T *, const int32_t *, int, const DevTables &,    \
                                           hipStream_t);                                     \
     template hipError_t launch_details<T>(const T *, const WorkList &, const DevTables &,   \

@@ -121,12 +121,13 @@ __device__ __forceinline__ T char_flux(const T W[6], const T G[6], T lL, T lR) {
 // Same result with at most two WENO evaluations per wavefront: if any lane of the wave
 // needs the LLF split, every lane evaluates W-(g+) + W+(g-) with g+ = g, g- = 0 for
 // upwind-right lanes and g+ = 0, g- = g for upwind-left lanes (a WENO of zeros is exactly
-// zero); otherwise one WENO with the input order picked per lane.  Bitwise equal to
-// char_flux, but mixed waves no longer execute all three branches.
-// The split is formed as g+ = cp G + ap W, g- = cm G + am W with per-lane coefficients
-// (1,0,0,0) upwind-right, (0,0,1,0) upwind-left, (1/2, a/2, 1/2, -a/2) LLF: one multiply
-// and one fused multiply-add per value instead of selects, and the same values (halving
-// is exact, so fma(a/2, W, G/2) rounds like (G + a W)/2).
+// zero); otherwise one WENO with the input order picked per lane.  Equal to char_flux
+// on upwind lanes and up to rounding on LLF lanes, but mixed waves no longer execute all
+// three branches.
+// The split is formed as g+ = cp G + ap W and g- = G - g+ with per-lane coefficients
+// (cp, ap) = (1, 0) upwind-right, (0, 0) upwind-left, (1/2, a/2) LLF: g+ = (G + a W)/2
+// rounded once (halving is exact), g- = (G - a W)/2 up to rounding, and exactly G, 0 on
+// the upwind lanes.
 template <typename T>
 __device__ __forceinline__ T char_flux_uniform(const T W[6], const T G[6], T lL, T lR) {
     const bool up = lL > (T)0 && lR > (T)0;
@@ -142,13 +143,13 @@ __device__ __forceinline__ T char_flux_uniform(const T W[6], const T G[6], T lL,
         return weno5(a[0], a[1], a[2], a[3], a[4]);
     }
     const T ha = (T)0.5 * fmax(fabs(lL), fabs(lR));
-    const T cp = up ? (T)1 : (dn ? (T)0 : (T)0.5), cm = dn ? (T)1 : (up ? (T)0 : (T)0.5);
-    const T ap = llf ? ha : (T)0, am = -ap;
+    const T cp = up ? (T)1 : (dn ? (T)0 : (T)0.5);
+    const T ap = llf ? ha : (T)0;
     T gp[6], gm[6];
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
         gp[j] = fma(ap, W[j], cp * G[j]);
-        gm[j] = fma(am, W[j], cm * G[j]);
+        gm[j] = G[j] - gp[j];
     }
     return weno5(gp[0], gp[1], gp[2], gp[3], gp[4]) + weno5(gm[5], gm[4], gm[3], gm[2], gm[1]);
 }

@@ -163,7 +163,8 @@ template <typename T>
 hipError_t launch_fill_halos(T *U, const WorkList &wl, const DevTables &tb, FillMode mode,
                              hipStream_t st);
 template <typename T>
-hipError_t launch_project(T *U, const WorkList &wl, const DevTables &tb, hipStream_t st);
+hipError_t launch_project(T *U, const WorkList &wl, const DevTables &tb, hipStream_t st,
+                          int qmask = 31);   // bit q: restrict component q
 template <typename T>
 hipError_t launch_predict(T *U, const int32_t *list, int n, const DevTables &tb,
                           hipStream_t st);

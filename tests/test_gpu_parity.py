@@ -198,6 +198,48 @@ def test_cfl_and_totals(orc, torch_mod, dtype):
 
 # ------------------------------------------------------------------ whole runs --------
 
+def _smooth_flow_with_blob(pb, key, gamma=1.4):
+    """Uniform flow with a 1e-4 smooth modulation, plus a sharp density blob at the centre
+    of level-1 block (0, 3, 0): smooth sibling groups coarsen, the blob's leaf refines."""
+    lv, bx, by, bz = key
+    h = pb.dx(lv)
+    ar = (np.arange(N) + 0.5) * h
+    z, y, x = np.meshgrid(bz * N * h + ar, by * N * h + ar, bx * N * h + ar, indexing="ij")
+    rho = 1.0 + 1e-4 * np.sin(2 * np.pi * x) * np.cos(2 * np.pi * y)
+    c = np.array([0.5, 3.5, 0.5]) * N * pb.dx(1)
+    rho = rho + 0.3 * np.exp(-((x - c[0]) ** 2 + (y - c[1]) ** 2 + (z - c[2]) ** 2) /
+                             (2 * (1.5 * pb.dx(3)) ** 2))
+    u, v, w = 0.3, -0.2, 0.1
+    p = 1.0 + 1e-4 * np.cos(2 * np.pi * z)
+    E = p / (gamma - 1) + 0.5 * rho * (u * u + v * v + w * w)
+    return np.stack([rho, rho * u, rho * v, rho * w, E])
+
+
+@pytest.mark.parametrize("dtype,batched", [("f64", False), ("f32", 2)])
+def test_adaptive_steps_coarsen_and_refine(orc, torch_mod, dtype, batched):
+    """Steps whose flags coarsen and refine: the tree after each step equals the
+    oracle's, and so do the leaf states (a coarsened parent takes the restriction of all
+    its children's components, new children the prediction from their refined parent)."""
+    pb = jump_problem()
+    o, g = make_pair(orc, pb, REFS, dtype, batched, adapt=1)
+    set_interiors(o, g, lambda k: _smooth_flow_with_blob(pb, k))
+    _, l0, _ = same_tree(o, g)
+    tol = 1e-11 if dtype == "f64" else 2e-6
+    for s in range(2):
+        o.step()
+        g.step()
+        ok, ol, gl = same_tree(o, g)
+        assert ok, f"trees differ after step {s}: {len(ol ^ gl)} leaves"
+        if s == 0:
+            # the step both coarsened (a level-1 parent became a leaf) and refined
+            assert (1, 2, 1, 1) in ol - l0 and len(l0 - ol) > 1 and any(k[0] == 2 for k in ol - l0)
+        g.check()
+        os_, gs = o.leaf_states(), g.leaf_states()
+        worst = max(float(np.abs(gs[k] - v).max() / np.abs(v).max()) for k, v in os_.items())
+        print(f"{dtype}: step {s}, {len(ol)} leaves, worst relative difference {worst:.2e}")
+        assert worst < tol, (s, worst)
+
+
 @pytest.mark.parametrize("noise", [0.0, 1e-3])
 def test_sod_single_level_fp64_plain(orc, torch_mod, noise):
     pb = W.sod_single_level()
@@ -386,9 +428,16 @@ def test_rhs_variants_bitwise_and_autotune(torch_mod):
                 assert np.array_equal(s[k], ref[k]), (batched, v, shapes[v], k)
     g = Solver([pb], dtype="f32", batched=2).init()
     g.step()
+    leaves0 = g.leaf_states()
+    # restriction and fills of a complete state are idempotent: the autotuner's own
+    # restriction and fills then leave every byte of U as it was
+    g.mr_project()
+    g.fill_halos()
     before = g.U.clone()
     choice, ms = g.autotune(reps=2)
     assert torch_mod.equal(before, g.U)
+    leaves1 = g.leaf_states()
+    assert all(np.array_equal(leaves0[k], leaves1[k]) for k in leaves0)
     assert 0 <= choice < len(shapes) and len(ms) == len(shapes) and all(m > 0 for m in ms)
     assert ms[choice] == min(ms)
     print(f"autotune: {choice} {shapes[choice]}, ms {ms}")
