@@ -45,9 +45,9 @@ def counted_traffic(kernel: str):
 
 def kernel_name(shape) -> str:
     """Demangled name of the fused kernel's instantiation for a variant shape."""
-    gp, tpb, wpe, ring = shape
+    gp, tpb, wpe = shape
     b = lambda v: "true" if v else "false"
-    return f"k_rhs_update<float, {gp}, {abs(tpb)}, {b(tpb < 0)}, {wpe}, {b(ring)}>"
+    return f"k_rhs_update<float, {gp}, {abs(tpb)}, {b(tpb < 0)}, {wpe}>"
 
 
 def flops_per_cell_update(llf_fraction: float) -> float:

@@ -194,16 +194,19 @@ int mrfv_kernel_time(mrfv_ctx *ctx, int64_t *launches, double *total_ms, int64_t
  * then the fused rhs + update kernel reading Uin (same-level neighbours' interiors in
  * place) and writing the leaves' new interiors to Uout, with the jump correction.  Uin,
  * Uout: dev, state_bytes each, distinct; U0: dev, interior_bytes (written at stage 0, read
- * at stages 1 and 2); dt_dev: dev double[n_instances].  Batched FP32 contexts only. */
+ * at stages 1 and 2); dt_dev: dev double[n_instances].  restrict_parents != 0: leaves on
+ * level >= 1 none of whose same-level face neighbours is a non-leaf also write the
+ * restriction (eq:Projection) of their new interior into their parent's octant of Uout,
+ * as the step does for a stage whose output is restricted next.  Batched FP32 contexts
+ * only. */
 int mrfv_fused_stage(mrfv_ctx *ctx, int32_t stage, const double *dt_dev, void *Uin, void *Uout,
-                     void *U0);
+                     void *U0, int32_t restrict_parents);
 
 /* Launch shapes of the fused rhs + update kernel (batched FP32 path): variant v groups
- * the block's z-planes by shapes_host[4v] and uses |shapes_host[4v+1]| threads per
- * workgroup, one workgroup per leaf, or, when shapes_host[4v+1] < 0, a persistent grid
- * of workgroups looping over the leaves; shapes_host[4v+2] is the number of wavefronts
- * per SIMD the register allocation aims at (1: the compiler's choice); shapes_host[4v+3]
- * = 1 when the z-face stencils are read from an LDS ring of z-planes.  Every variant
+ * the block's z-planes by shapes_host[3v] and uses |shapes_host[3v+1]| threads per
+ * workgroup, one workgroup per leaf, or, when shapes_host[3v+1] < 0, a persistent grid
+ * of workgroups looping over the leaves; shapes_host[3v+2] is the number of wavefronts
+ * per SIMD the register allocation aims at (1: the compiler's choice).  Every variant
  * gives bitwise the same result.  rhs_variant sets the variant
  * when set >= 0 (captured stage graphs are re-captured), writes the number of variants
  * and their shapes (each may be NULL) and returns the current variant (>= 0) or an

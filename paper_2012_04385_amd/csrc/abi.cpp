@@ -122,11 +122,14 @@ int levels_to_cover(const mrfv_ctx *ctx) {
 }
 
 // stage_only: restrict only the parents a fused stage reads (desc_pproj), else all.
+// skip_srestr: octants of children with meta.srestr hold the restriction the last fused
+// stage wrote and are not recomputed.
 template <typename T>
-int do_project(mrfv_ctx *ctx, T *U, bool stage_only = false, bool rho_e_only = false) {
+int do_project(mrfv_ctx *ctx, T *U, bool stage_only = false, bool rho_e_only = false,
+               bool skip_srestr = false) {
     for (int l = levels_to_cover(ctx) - 1; l >= 0; --l)
         HIP_OK(launch_project<T>(U, wlist(ctx, stage_only ? desc_pproj(l) : desc_par(l)), ctx->tb,
-                                 ctx->stream, rho_e_only ? 0x11 : 0x1f));
+                                 ctx->stream, rho_e_only ? 0x11 : 0x1f, skip_srestr));
     return MRFV_OK;
 }
 
@@ -241,14 +244,14 @@ int do_update(mrfv_ctx *ctx, int stage, const double *dt, T *U, T *U0, const T *
 // One stage of the batched path: fused rhs + update over all leaves, then the jump
 // correction on the updated state.
 int do_stage_fused(mrfv_ctx *ctx, int stage, const double *dt, const float *Uin, float *Uout,
-                   float *U0) {
+                   float *U0, bool restrict_parents = false) {
     const HostLists &L = ctx->lists;
     float *FF = (float *)ctx->d_FF;
     hipEvent_t ev{};
     timing_begin(ctx, &ev);
     // the fused kernel has no grid-stride loop: its grid must cover every possible leaf
     HIP_OK(launch_rhs_update_f32(ctx->rhs_variant, stage, dt, Uin, Uout, U0, wlist(ctx, DESC_LEAVES, 1 << 30), ctx->tb,
-                                 ctx->d_inst, FF, ctx->d_err, ctx->stream));
+                                 ctx->d_inst, FF, ctx->d_err, restrict_parents ? 1 : 0, ctx->stream));
     timing_end(ctx, ev, (int64_t)L.all_leaves_cnt * CELLS_I);
     if (ctx->has_jumps) {
         for (int l = levels_to_cover(ctx) - 1; l >= 0; --l)
@@ -495,14 +498,20 @@ int do_stages(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt) {
                          ctx->d_blockred, dt, ctx->stream));
     if (ctx->cfg.batched && sizeof(T) == 4) {
         // fused stages, out of place through two more state buffers: U -> W -> W2 -> U;
-        // parents are restricted and filled only if some leaf face reads them
+        // parents are restricted and filled only if some leaf face reads them.  Stages
+        // whose output is restricted next (W and W2 when stages read parents, U before
+        // the details) write the restriction of jump-free leaves into their parents, so
+        // those restriction passes recompute only the other octants.  U comes from the
+        // caller, who may have written it: the first stage restricts in full.
         float *buf[4] = {(float *)U, (float *)ctx->d_W, (float *)ctx->d_W2, (float *)U};
         const bool par = ctx->lists.parents_needed;
+        bool adapt = false;
+        for (const auto &p : ctx->inst) adapt = adapt || (p.adapt && p.lmax > 0);
         for (int s = 0; s < 3; ++s) {
             float *in = buf[s], *out = buf[s + 1];
-            if (par) CALL(do_project<float>(ctx, in, true));
+            if (par) CALL(do_project<float>(ctx, in, true, false, s > 0));
             CALL(do_fill<float>(ctx, in, 1 << 20, FILL_MISSING_FACES, par));
-            CALL(do_stage_fused(ctx, s, dt, in, out, (float *)U0));
+            CALL(do_stage_fused(ctx, s, dt, in, out, (float *)U0, s < 2 ? par : adapt));
         }
         return MRFV_OK;
     }
@@ -602,9 +611,11 @@ int do_step(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt) {
         CALL(do_stages<T>(ctx, U, U0, Lb, dt));
     }
     if (!adapt) return MRFV_OK;
-    // the details read only rho and E: parents are restricted and filled in those two;
-    // all components are restricted and filled below when the flags change the tree
-    CALL(do_project<T>(ctx, U, false, true));
+    // the details read only rho and E: parents are restricted and filled in those two
+    // (the fused path's last stage wrote the octants of jump-free leaves); all components
+    // are restricted and filled below when the flags change the tree
+    const bool fused = ctx->cfg.batched && sizeof(T) == 4;
+    CALL(do_project<T>(ctx, U, false, true, fused));
     CALL(do_fill<T>(ctx, U, 1 << 20, FILL_MISSING | FILL_RHO_E));
     CALL(do_details_flags<T>(ctx, U, ctx->d_flags, ctx->d_det));
     const int cap = ctx->cfg.slot_capacity;
@@ -1042,7 +1053,7 @@ int mrfv_set_proposer(mrfv_ctx *ctx, mrfv_mlp *mlp, int32_t mode) {
 }
 
 int mrfv_fused_stage(mrfv_ctx *ctx, int32_t stage, const double *dt_dev, void *Uin, void *Uout,
-                     void *U0) {
+                     void *U0, int32_t restrict_parents) {
     CALL(need_init(ctx));
     if (!(ctx->cfg.batched && ctx->cfg.dtype == MRFV_F32))
         return fail(ctx, MRFV_EINVAL, "fused_stage: batched FP32 contexts only");
@@ -1052,7 +1063,8 @@ int mrfv_fused_stage(mrfv_ctx *ctx, int32_t stage, const double *dt_dev, void *U
     const bool par = ctx->lists.parents_needed;
     if (par) CALL(do_project<float>(ctx, (float *)Uin, true));
     CALL(do_fill<float>(ctx, (float *)Uin, 1 << 20, FILL_MISSING_FACES, par));
-    return do_stage_fused(ctx, stage, dt_dev, (const float *)Uin, (float *)Uout, (float *)U0);
+    return do_stage_fused(ctx, stage, dt_dev, (const float *)Uin, (float *)Uout, (float *)U0,
+                          restrict_parents != 0);
 }
 
 int mrfv_rhs_variant(mrfv_ctx *ctx, int32_t set, int32_t *n_variants, int32_t *shapes) {
@@ -1061,7 +1073,7 @@ int mrfv_rhs_variant(mrfv_ctx *ctx, int32_t set, int32_t *n_variants, int32_t *s
     if (n_variants) *n_variants = n;
     if (shapes)
         for (int v = 0; v < n; ++v)
-            rhs_variant_shape(v, shapes + 4 * v, shapes + 4 * v + 1, shapes + 4 * v + 2, shapes + 4 * v + 3);
+            rhs_variant_shape(v, shapes + 3 * v, shapes + 3 * v + 1, shapes + 3 * v + 2);
     if (set >= n) return fail(ctx, MRFV_EINVAL, "rhs_variant: index out of range");
     if (set >= 0 && set != ctx->rhs_variant) {
         ctx->rhs_variant = set;
@@ -1093,11 +1105,11 @@ int mrfv_autotune(mrfv_ctx *ctx, void *U, void *U0, double *dt_dev, int32_t reps
     float best_ms = 0.f;
     for (int v = 0; v < rhs_variants(); ++v) {
         HIP_OK(launch_rhs_update_f32(v, 0, dt_dev, X, W, (float *)U0, wl, ctx->tb, ctx->d_inst,
-                                     (float *)ctx->d_FF, ctx->d_err, st));
+                                     (float *)ctx->d_FF, ctx->d_err, 0, st));
         HIP_OK(hipEventRecord(a, st));
         for (int r = 0; r < reps; ++r)
             HIP_OK(launch_rhs_update_f32(v, 0, dt_dev, X, W, (float *)U0, wl, ctx->tb, ctx->d_inst,
-                                         (float *)ctx->d_FF, ctx->d_err, st));
+                                         (float *)ctx->d_FF, ctx->d_err, 0, st));
         HIP_OK(hipEventRecord(b, st));
         HIP_OK(hipEventSynchronize(b));
         float ms = 0.f;

@@ -239,16 +239,21 @@ __global__ __launch_bounds__(TPB) void k_fill_halos(T *__restrict__ U, WorkList 
     }
 }
 
-// One thread per parent interior cell; components whose bit is set in qmask.
+// One thread per parent interior cell; components whose bit is set in qmask.  With skip
+// set, octants whose child has meta.srestr (the fused stage kernel wrote their
+// restriction) are left as they are.
 template <typename T>
 __global__ __launch_bounds__(TPB) void k_project(T *__restrict__ U, WorkList wl,
-                                                 const int32_t *__restrict__ child, int qmask) {
+                                                 const int32_t *__restrict__ child,
+                                                 const BlockMeta *__restrict__ meta, int qmask,
+                                                 int skip) {
     const int nb = wl.count();
     for (int b = blockIdx.x; b < nb; b += gridDim.x) {
     const int slot = wl.at(b);
     const int K = blockIdx.y, J = threadIdx.x >> 4, I = threadIdx.x & 15;
     const int oct = ((K >> 3) << 2) | ((J >> 3) << 1) | (I >> 3);
     const int cs = child[(size_t)slot * 8 + oct];
+    if (skip && meta[cs].srestr) continue;
     const T *cu = U + (size_t)cs * 5 * CELLS_P;
     T *pu = U + (size_t)slot * 5 * CELLS_P;
     const int ci = HW + 2 * (I & 7), cj = HW + 2 * (J & 7), ck = HW + 2 * (K & 7);
@@ -619,9 +624,10 @@ hipError_t launch_fill_halos(T *U, const WorkList &wl, const DevTables &tb, Fill
 
 template <typename T>
 hipError_t launch_project(T *U, const WorkList &wl, const DevTables &tb, hipStream_t st,
-                          int qmask) {
+                          int qmask, bool skip_srestr) {
     if (wl.grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_project<T>, grid2(wl.grid, NI), dim3(TPB), 0, st, U, wl, tb.child, qmask);
+    hipLaunchKernelGGL(k_project<T>, grid2(wl.grid, NI), dim3(TPB), 0, st, U, wl, tb.child, tb.meta,
+                       qmask, skip_srestr ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -686,7 +692,7 @@ hipError_t launch_totals(const T *U, const WorkList &leaves, const DevTables &tb
     template hipError_t launch_fill_halos<T>(T *, const WorkList &, const DevTables &,       \
                                              FillMode, hipStream_t);                        \
     template hipError_t launch_project<T>(T *, const WorkList &, const DevTables &,         \
-                                          hipStream_t, int);                                \
+                                          hipStream_t, int, bool);                          \
     template hipError_t launch_predict<T>(T *, const int32_t *, int, const DevTables &,    \
                                           hipStream_t);                                     \
     template hipError_t launch_details<T>(const T *, const WorkList &, const DevTables &,   \

@@ -65,11 +65,15 @@ __device__ __forceinline__ void load_state(const T *__restrict__ u, int idx, con
     s.E = u[idx + 4 * CELLS_P];
 }
 
+// Every multiply-add is an explicit fma: the compiler fuses per basic block, and this
+// code is inlined after different load paths (per-lane sources, uniform base), which
+// must all give bitwise the same state.
 template <typename T>
 __device__ __forceinline__ void derive_state(const Gas<T> &G, CellState<T> &s) {
     s.ir = rcp_(s.r);
-    const T ke = (T)0.5 * (s.mn * s.mn + s.mt1 * s.mt1 + s.mt2 * s.mt2) * s.ir;
-    s.p = G.gm1 * (s.E - ke) - G.g * G.B;
+    const T m2 = fma(s.mt2, s.mt2, fma(s.mt1, s.mt1, s.mn * s.mn));
+    const T eint = fma((T)-0.5 * m2, s.ir, s.E);          // E - |m|^2 / (2 rho)
+    s.p = fma(G.gm1, eint, -(G.g * G.B));
     s.c = sqrt_(G.g * (s.p + G.B) * s.ir);
     s.sr = sqrt_(s.r);
 }
@@ -485,13 +489,33 @@ __device__ __forceinline__ void face_flux_at(const T *__restrict__ ub, const T *
     constexpr int stride = Axes<D>::STRIDE;
     constexpr int n1 = Axes<D>::N1, t1 = Axes<D>::T1, t2 = Axes<D>::T2;   // rotated components
     CellState<T> w[6];
+    if (__all(pos0 >= HW && pos0 + 5 < HW + NI)) {
+        // every stencil of the wavefront lies in the own interior: loads from the uniform
+        // component bases with 32-bit offsets (no per-lane source selection)
+        const char *__restrict__ b0 = (const char *)ub;
+        auto at = [&](int q, unsigned off) __attribute__((always_inline)) {
+            return *(const T *)(b0 + (size_t)q * CELLS_P * sizeof(T) + off);
+        };
 #pragma unroll
-    for (int j = 0; j < 6; ++j) {
-        const int pos = pos0 + j;
-        const T *src = pos < HW ? lo : (pos >= HW + NI ? hi : ub);
-        load_state<T, D>(src, base + j * stride, G, w[j]);
-        derive_state(G, w[j]);
+        for (int j = 0; j < 6; ++j) {
+            const unsigned off = (unsigned)(base + j * stride) * (unsigned)sizeof(T);
+            w[j].r = at(0, off);
+            w[j].mn = at(n1, off);
+            w[j].mt1 = at(t1, off);
+            w[j].mt2 = at(t2, off);
+            w[j].E = at(4, off);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            const int pos = pos0 + j;
+            const T *src = pos < HW ? lo : (pos >= HW + NI ? hi : ub);
+            load_state<T, D>(src, base + j * stride, G, w[j]);
+        }
     }
+    // the arithmetic follows the loads in one place for both load paths
+#pragma unroll
+    for (int j = 0; j < 6; ++j) derive_state(G, w[j]);
     T F[5];
     face_flux<T, true>(w, G, F);
     Fp[0] = F[0];
@@ -501,33 +525,7 @@ __device__ __forceinline__ void face_flux_at(const T *__restrict__ ub, const T *
     Fp[t2] = F[3];
 }
 
-// z-face flux from the LDS ring of z-planes (ZRING variants): the six stencil cells of
-// the face below interior plane kf at column c are planes kf-3 .. kf+2, ring slot
-// (k + 3) mod ZR; same values and arithmetic as face_flux_at along z.
-template <typename T, int ZR>
-__device__ __forceinline__ void face_flux_ring(const T (*__restrict__ Zr)[5][NI * NI], int kf, int c,
-                                               const Gas<T> &G, T Fp[5]) {
-    CellState<T> w[6];
-#pragma unroll
-    for (int j = 0; j < 6; ++j) {
-        const T *pl = &Zr[(kf + j) & (ZR - 1)][0][c];
-        w[j].r = pl[0];
-        w[j].mn = pl[3 * NI * NI];
-        w[j].mt1 = pl[1 * NI * NI];
-        w[j].mt2 = pl[2 * NI * NI];
-        w[j].E = pl[4 * NI * NI];
-        derive_state(G, w[j]);
-    }
-    T F[5];
-    face_flux<T, true>(w, G, F);
-    Fp[0] = F[0];
-    Fp[4] = F[4];
-    Fp[3] = F[1];
-    Fp[1] = F[2];
-    Fp[2] = F[3];
-}
-
-template <typename T, int GP, int TPB_F, bool PERSIST, int WPE, bool ZRING>
+template <typename T, int GP, int TPB_F, bool PERSIST, int WPE>
 __global__ __attribute__((amdgpu_flat_work_group_size(TPB_F, TPB_F), amdgpu_waves_per_eu(WPE)))
 void k_rhs_update(int stage, const double *__restrict__ dt,
                                                       const T *__restrict__ Uin, T *__restrict__ Uout,
@@ -535,15 +533,16 @@ void k_rhs_update(int stage, const double *__restrict__ dt,
                                                       const BlockMeta *__restrict__ meta,
                                                       const int32_t *__restrict__ nbr,
                                                       const InstDev *__restrict__ inst, T *FF,
-                                                      int32_t *err) {
-    constexpr int NFX = GP * NI * (NI + 1);   // x-faces per group
+                                                      int32_t *err, int restrict_parents) {
+    constexpr int NFX = GP * NI * (NI + 1);   // x-faces per group (y-faces alike)
+    // x- and y-faces are numbered with the faces 3 .. 13 of each row first: their
+    // six-cell stencils lie in the own interior, so whole wavefronts of them take the
+    // uniform-base loads of face_flux_at; the faces 0-2 and 14-16 follow
+    constexpr int NF_IN = NI - 5, NF_OUT = NI + 1 - NF_IN;
+    constexpr int NFX_IN = GP * NI * NF_IN;
     __shared__ T Fx[GP][NI][NI + 1][5];   // [plane][y][face x][q]
     __shared__ T Fy[GP][NI + 1][NI][5];   // [plane][face y][x][q]
     __shared__ T Fz[GP + 1][NI][NI][5];   // [face plane][y][x][q]; plane j = face k0 + j - 1/2
-    // ZRING: interior columns of the z-planes the z-faces read, planes -3 .. 18 through a
-    // ring of ZR slots (a power of two >= GP + 6), each plane loaded once per block
-    constexpr int ZR = ZRING ? (GP + 6 <= 8 ? 8 : 16) : 1;
-    __shared__ T Zr[ZR][5][ZRING ? NI * NI : 1];
     // one workgroup per leaf (graph launches size the grid by the slot capacity and
     // surplus groups exit here), or, persistent, a fixed grid looping over the leaves
     const int nleaf = wl.count();
@@ -577,23 +576,31 @@ void k_rhs_update(int stage, const double *__restrict__ dt,
     const bool owner = tid < FACE;              // column owners (x = tid & 15, y = tid >> 4)
     const int cx = tid & 15, cy = tid >> 4;
     bool ok = true;
-
-    // interior z-plane k (-3 .. 18): own plane, else the z-neighbour's (or the own halo
-    // where the face has no same-level neighbour); the source is uniform per plane
-    auto load_plane = [&](int k) {
-        const T *src = (k < 0 ? nlo[2] : (k >= NI ? nhi[2] : ub)) + (k + HW) * NP * NP;
-        T *dst = &Zr[(k + 3) & (ZR - 1)][0][0];
-        for (int e = tid; e < 5 * NFZ; e += TPB_F) {
-            const int q = e >> 8, c = e & (NFZ - 1);
-            dst[q * NFZ + c] = src[q * CELLS_P + ((c >> 4) + HW) * NP + (c & 15) + HW];
+    // Restriction of the new state into the parent's octant (eq:Projection): the sum of
+    // the 2x2x2 children is formed in FP64 as x pairs, then y pairs (lanes 1 and 16 apart
+    // in the wavefront), then z pairs, the order of the restriction kernel, so both give
+    // bitwise the same parent values.
+    const bool rp = restrict_parents && mt.srestr;   // uniform per workgroup
+    // z-plane pair (z0, z0 + 1) of the new state, one column per owner thread
+    auto restrict_pair = [&](int z0, const T (&u)[2][5]) {
+        T *pb = Uout + (size_t)mt.parent * 5 * CELLS_P +
+                (((mt.bz & 1) * 8 + (z0 >> 1) + HW) * NP + (mt.by & 1) * 8 + (cy >> 1) + HW) * NP +
+                (mt.bx & 1) * 8 + (cx >> 1) + HW;
+        const bool wr = ((cx | cy) & 1) == 0;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            double v0 = (double)u[0][q], v1 = (double)u[1][q];
+            v0 += __shfl_xor(v0, 1);
+            v1 += __shfl_xor(v1, 1);
+            v0 += __shfl_xor(v0, 16);
+            v1 += __shfl_xor(v1, 16);
+            if (wr) pb[q * CELLS_P] = (T)((v0 + v1) * 0.125);
         }
     };
-    if constexpr (ZRING) {
-        for (int k = -3; k <= GP + 2; ++k) load_plane(k);
-        __syncthreads();
-    }
 
+    T uprev[2][5];   // GP = 1: the even plane of a restriction pair
     auto update_group = [&](int k0, T D[GP][5]) {
+        T unew[GP][5];
 #pragma unroll
         for (int p = 0; p < GP; ++p) {
             const int z = k0 + p;
@@ -612,8 +619,27 @@ void k_rhs_update(int stage, const double *__restrict__ dt,
                 }
                 un[q] = u0 + a * ((us - u0) + dtt * (-D[p][q] * inv_dx));
                 ob[o + q * CELLS_P] = un[q];
+                unew[p][q] = un[q];
             }
             ok = ok && physical_state(un, G);
+        }
+        if (rp) {
+            if constexpr (GP == 1) {
+#pragma unroll
+                for (int q = 0; q < 5; ++q) uprev[k0 & 1][q] = unew[0][q];
+                if (k0 & 1) restrict_pair(k0 - 1, uprev);
+            } else {
+#pragma unroll
+                for (int p = 0; p < GP; p += 2) {
+                    T pr[2][5];
+#pragma unroll
+                    for (int q = 0; q < 5; ++q) {
+                        pr[0][q] = unew[p][q];
+                        pr[1][q] = unew[p + 1][q];
+                    }
+                    restrict_pair(k0 + p, pr);
+                }
+            }
         }
     };
 
@@ -625,7 +651,17 @@ void k_rhs_update(int stage, const double *__restrict__ dt,
         for (int t = tid; t < total; t += TPB_F) {
             T F[5];
             if (t < NFX) {                      // x-faces: (plane p, row y, face f)
-                const int f = t % (NI + 1), y = (t / (NI + 1)) % NI, p = t / ((NI + 1) * NI);
+                int f, y, p;
+                if (t < NFX_IN) {               // faces 3 .. 13 first: stencils in the interior
+                    f = 3 + t % NF_IN;
+                    y = (t / NF_IN) % NI;
+                    p = t / (NF_IN * NI);
+                } else {
+                    const int v = t - NFX_IN, fb = v % NF_OUT;
+                    f = fb < 3 ? fb : fb + NF_IN;
+                    y = (v / NF_OUT) % NI;
+                    p = v / (NF_OUT * NI);
+                }
                 const int base = ((k0 + p + HW) * NP + y + HW) * NP + f + 1;
                 face_flux_at<T, 0>(ub, nlo[0], nhi[0], base, f + 1, G, F);
 #pragma unroll
@@ -636,7 +672,17 @@ void k_rhs_update(int stage, const double *__restrict__ dt,
                 }
             } else if (t < 2 * NFX) {           // y-faces: (plane p, face f, column x)
                 const int u = t - NFX;
-                const int x = u % NI, f = (u / NI) % (NI + 1), p = u / (NI * (NI + 1));
+                int x, f, p;
+                if (u < NFX_IN) {
+                    x = u % NI;
+                    f = 3 + (u / NI) % NF_IN;
+                    p = u / (NI * NF_IN);
+                } else {
+                    const int v = u - NFX_IN, fb = (v / NI) % NF_OUT;
+                    x = v % NI;
+                    f = fb < 3 ? fb : fb + NF_IN;
+                    p = v / (NI * NF_OUT);
+                }
                 const int base = ((k0 + p + HW) * NP + f + 1) * NP + x + HW;
                 face_flux_at<T, 1>(ub, nlo[1], nhi[1], base, f + 1, G, F);
 #pragma unroll
@@ -649,12 +695,8 @@ void k_rhs_update(int stage, const double *__restrict__ dt,
                 const int u = t - 2 * NFX;
                 const int x = u % NI, y = (u / NI) % NI, j = u / NFZ + first_z;
                 const int kf = k0 + j;          // face between interior planes kf-1 and kf
-                if constexpr (ZRING) {
-                    face_flux_ring<T, ZR>(Zr, kf, y * NI + x, G, F);
-                } else {
-                    const int base = ((kf + 1) * NP + y + HW) * NP + x + HW;   // padded z = kf+1 .. kf+6
-                    face_flux_at<T, 2>(ub, nlo[2], nhi[2], base, kf + 1, G, F);
-                }
+                const int base = ((kf + 1) * NP + y + HW) * NP + x + HW;   // padded z = kf+1 .. kf+6
+                face_flux_at<T, 2>(ub, nlo[2], nhi[2], base, kf + 1, G, F);
 #pragma unroll
                 for (int q = 0; q < 5; ++q) Fz[j][y][x][q] = F[q];
                 if (kf == 0 || kf == NI) {
@@ -676,12 +718,6 @@ void k_rhs_update(int stage, const double *__restrict__ dt,
                     D[p][q] = (dxq + dyq) + dzq;
                 }
             update_group(k0, D);
-        }
-        if constexpr (ZRING) {
-            // planes of the next group's window; the slots they take held planes this
-            // group's faces (all computed: the barrier above) no longer need
-            if (g + 1 < NI / GP)
-                for (int k = k0 + GP + 3; k <= k0 + 2 * GP + 2; ++k) load_plane(k);
         }
         __syncthreads();
         // the last face plane of this group is the first one of the next
@@ -785,62 +821,54 @@ hipError_t launch_update(int stage, const double *dt, T *U, T *U0, const T *L, c
 // at once (3 waves per SIMD at their register count) loops over the leaves instead of
 // one workgroup per leaf.  Variants 11 and 12 ask the register allocator for 5 waves per
 // SIMD (at most 96 registers, some spilled to scratch) instead of the default 4.
-// Variants 13-15 read the z-face stencils from an LDS ring of z-planes.
-constexpr int N_RHS_VARIANTS = 16;
-constexpr int RHS_GP[N_RHS_VARIANTS] = {2, 1, 2, 2, 4, 4, 2, 2, 1, 2, 2, 2, 2, 2, 2, 2};
-constexpr int RHS_TPB[N_RHS_VARIANTS] = {320, 256, 256, 384, 320, 512, 448, 512, 320, 512, 384, 320, 640,
-                                         512, 384, 448};
-constexpr bool RHS_PERSIST[N_RHS_VARIANTS] = {false, false, false, false, false, false, false, false,
-                                              false, true, true, false, false, false, false, false};
-constexpr int RHS_WPE[N_RHS_VARIANTS] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 5, 5, 1, 1, 1};
-constexpr bool RHS_RING[N_RHS_VARIANTS] = {false, false, false, false, false, false, false, false,
-                                           false, false, false, false, false, true, true, true};
+constexpr int N_RHS_VARIANTS = 13;
+constexpr int RHS_GP[N_RHS_VARIANTS] = {2, 1, 2, 2, 4, 4, 2, 2, 1, 2, 2, 2, 2};
+constexpr int RHS_TPB[N_RHS_VARIANTS] = {320, 256, 256, 384, 320, 512, 448, 512, 320, 512, 384, 320, 640};
+constexpr bool RHS_PERSIST[N_RHS_VARIANTS] = {false, false, false, false, false, false, false,
+                                              false, false, true, true, false, false};
+constexpr int RHS_WPE[N_RHS_VARIANTS] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 5, 5};
 constexpr int persist_grid(int tpb) { return 256 * (12 / (tpb / 64) > 0 ? 12 / (tpb / 64) : 1); }
 
 template <int V>
 static void launch_variant(int stage, const double *dt, const float *Uin, float *Uout, float *U0,
                     const WorkList &wl, const DevTables &tb, const InstDev *inst, float *FF,
-                    int32_t *err, hipStream_t st) {
+                    int32_t *err, int restrict_parents, hipStream_t st) {
     constexpr int G = RHS_GP[V], B = RHS_TPB[V];
     constexpr bool PS = RHS_PERSIST[V];
     constexpr int WP = RHS_WPE[V];
-    constexpr bool ZRG = RHS_RING[V];
     const int grid = PS ? std::min(wl.grid, persist_grid(B)) : wl.grid;
-    hipLaunchKernelGGL((k_rhs_update<float, G, B, PS, WP, ZRG>), dim3(grid), dim3(B), 0, st, stage, dt, Uin,
-                       Uout, U0, wl, tb.meta, tb.nbr, inst, FF, err);
+    hipLaunchKernelGGL((k_rhs_update<float, G, B, PS, WP>), dim3(grid), dim3(B), 0, st, stage, dt, Uin,
+                       Uout, U0, wl, tb.meta, tb.nbr, inst, FF, err, restrict_parents);
 }
 
 int rhs_variants() { return N_RHS_VARIANTS; }
 
-void rhs_variant_shape(int v, int *gp, int *tpb, int *wpe, int *ring) {
+void rhs_variant_shape(int v, int *gp, int *tpb, int *wpe) {
     *gp = RHS_GP[v];
     *tpb = RHS_PERSIST[v] ? -RHS_TPB[v] : RHS_TPB[v];   // negative: persistent grid
     *wpe = RHS_WPE[v];
-    *ring = RHS_RING[v] ? 1 : 0;
 }
 
 hipError_t launch_rhs_update_f32(int variant, int stage, const double *dt, const float *Uin,
                                  float *Uout, float *U0, const WorkList &wl, const DevTables &tb,
-                                 const InstDev *inst, float *FF, int32_t *err, hipStream_t st) {
+                                 const InstDev *inst, float *FF, int32_t *err, int restrict_parents,
+                                 hipStream_t st) {
     if (wl.grid <= 0) return hipSuccess;
     if (Uin == Uout) return hipErrorInvalidValue;   // neighbours' interiors are read
     switch (variant) {
-        case 0: launch_variant<0>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, st); break;
-        case 1: launch_variant<1>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, st); break;
-        case 2: launch_variant<2>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, st); break;
-        case 3: launch_variant<3>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, st); break;
-        case 4: launch_variant<4>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, st); break;
-        case 5: launch_variant<5>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, st); break;
-        case 6: launch_variant<6>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, st); break;
-        case 7: launch_variant<7>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, st); break;
-        case 8: launch_variant<8>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, st); break;
-        case 9: launch_variant<9>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, st); break;
-        case 10: launch_variant<10>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, st); break;
-        case 11: launch_variant<11>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, st); break;
-        case 12: launch_variant<12>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, st); break;
-        case 13: launch_variant<13>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, st); break;
-        case 14: launch_variant<14>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, st); break;
-        case 15: launch_variant<15>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, st); break;
+        case 0: launch_variant<0>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, st); break;
+        case 1: launch_variant<1>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, st); break;
+        case 2: launch_variant<2>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, st); break;
+        case 3: launch_variant<3>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, st); break;
+        case 4: launch_variant<4>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, st); break;
+        case 5: launch_variant<5>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, st); break;
+        case 6: launch_variant<6>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, st); break;
+        case 7: launch_variant<7>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, st); break;
+        case 8: launch_variant<8>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, st); break;
+        case 9: launch_variant<9>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, st); break;
+        case 10: launch_variant<10>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, st); break;
+        case 11: launch_variant<11>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, st); break;
+        case 12: launch_variant<12>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, st); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

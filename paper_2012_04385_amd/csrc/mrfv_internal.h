@@ -25,6 +25,9 @@ struct BlockMeta {
     int32_t parent;   // parent slot, -1 on level 0
     int32_t leaf;     // 1 = leaf
     int32_t zg;       // bit (2*axis + side): block touches a zero-gradient boundary there
+    int32_t srestr;   // 1: leaf on level >= 1 without a non-leaf same-level face neighbour
+                      // (no jump correction): the fused stage writes its restriction into
+                      // the parent's octant
 };
 
 // Per-instance parameters on the device.
@@ -164,7 +167,8 @@ hipError_t launch_fill_halos(T *U, const WorkList &wl, const DevTables &tb, Fill
                              hipStream_t st);
 template <typename T>
 hipError_t launch_project(T *U, const WorkList &wl, const DevTables &tb, hipStream_t st,
-                          int qmask = 31);   // bit q: restrict component q
+                          int qmask = 31,          // bit q: restrict component q
+                          bool skip_srestr = false);   // leave octants of srestr children
 template <typename T>
 hipError_t launch_predict(T *U, const int32_t *list, int n, const DevTables &tb,
                           hipStream_t st);
@@ -201,11 +205,14 @@ hipError_t launch_update(int stage, const double *dt, T *U, T *U0, const T *L,
 // Fused stage: reads the state from Uin (same-level neighbours' interiors directly, the
 // own halo elsewhere) and writes the new interior state to Uout != Uin.
 // variant: launch shape index in [0, rhs_variants()) (all give the same result).
+// restrict_parents: leaves with meta.srestr also write the restriction of their new state
+// (all components) into their parent's octant of Uout.
 hipError_t launch_rhs_update_f32(int variant, int stage, const double *dt, const float *Uin,
                                  float *Uout, float *U0, const WorkList &leaves, const DevTables &tb,
-                                 const InstDev *inst, float *FF, int32_t *err, hipStream_t st);
+                                 const InstDev *inst, float *FF, int32_t *err, int restrict_parents,
+                                 hipStream_t st);
 int rhs_variants();
-void rhs_variant_shape(int v, int *gp, int *tpb, int *wpe, int *ring);
+void rhs_variant_shape(int v, int *gp, int *tpb, int *wpe);
 template <typename T>
 hipError_t launch_reflux_update(int stage, const double *dt, T *U, const T *FF,
                                 const WorkList &leaves, const DevTables &tb,

@@ -194,7 +194,7 @@ std::vector<int> Topology::alive_sorted() const {
 void Topology::build(std::vector<BlockMeta> &meta, std::vector<int32_t> &child,
                      std::vector<int32_t> &nbr, HostLists &L) const {
     const int cap = capacity();
-    meta.assign(cap, BlockMeta{0, 0, 0, 0, 0, -1, 0, 0});
+    meta.assign(cap, BlockMeta{0, 0, 0, 0, 0, -1, 0, 0, 0});
     child.assign((size_t)cap * 8, -1);
     nbr.assign((size_t)cap * 27, -2);
     const std::vector<int> order = alive_sorted();
@@ -203,7 +203,7 @@ void Topology::build(std::vector<BlockMeta> &meta, std::vector<int32_t> &child,
     for (int s : order) {
         const HostBlock &b = blocks_[s];
         const mrfv_instance &p = inst_[b.inst];
-        BlockMeta m{b.inst, b.level, b.bx, b.by, b.bz, b.parent, b.leaf ? 1 : 0, 0};
+        BlockMeta m{b.inst, b.level, b.bx, b.by, b.bz, b.parent, b.leaf ? 1 : 0, 0, 0};
         const int c[3] = {b.bx, b.by, b.bz};
         for (int a = 0; a < 3; ++a) {
             const int n = p.n0[a] << b.level;
@@ -233,6 +233,18 @@ void Topology::build(std::vector<BlockMeta> &meta, std::vector<int32_t> &child,
                     nbr[(size_t)s * 27 + idx] =
                         outside ? -2 : find(b.inst, b.level, q[0], q[1], q[2]);
                 }
+    }
+    // leaves whose stage result is final after the fused kernel (no jump correction of
+    // their boundary cells) restrict themselves into their parent
+    for (int s : order) {
+        const HostBlock &b = blocks_[s];
+        if (!b.leaf || b.parent < 0) continue;
+        bool coarse_side = false;
+        for (int r : {12, 14, 10, 16, 4, 22}) {
+            const int nb = nbr[(size_t)s * 27 + r];
+            if (nb >= 0 && !blocks_[nb].leaf) coarse_side = true;
+        }
+        meta[s].srestr = coarse_side ? 0 : 1;
     }
     // work lists
     const int n_inst = (int)inst_.size();

@@ -96,7 +96,7 @@ def lib():
         "mrfv_last_flags": ([vp, C.POINTER(C.c_int8)], C.c_int),
         "mrfv_step_timing": ([vp, C.POINTER(d)], C.c_int),
         "mrfv_rhs_variant": ([vp, i32, C.POINTER(i32), C.POINTER(i32)], C.c_int),
-        "mrfv_fused_stage": ([vp, i32, vp, vp, vp, vp], C.c_int),
+        "mrfv_fused_stage": ([vp, i32, vp, vp, vp, vp, i32], C.c_int),
         "mrfv_autotune": ([vp, vp, vp, vp, i32, C.POINTER(C.c_float), C.POINTER(i32)], C.c_int),
     }
     for name, (args, res) in sig.items():
@@ -325,22 +325,22 @@ class Solver:
     def leaf_cells(self) -> int:
         return self.stats()[2]
 
-    def fused_stage(self, stage: int, Uout, Uin=None):
-        """One stage of the batched FP32 path from Uin (default: the state) into Uout."""
+    def fused_stage(self, stage: int, Uout, Uin=None, restrict_parents: bool = False):
+        """One stage of the batched FP32 path from Uin (default: the state) into Uout;
+        restrict_parents: jump-free leaves also restrict their result into their parents."""
         Uin = self.U if Uin is None else Uin
         self._chk(lib().mrfv_fused_stage(self.h, int(stage), self._p(self.dt), self._p(Uin),
-                                         self._p(Uout), self._p(self.U0)))
+                                         self._p(Uout), self._p(self.U0), int(bool(restrict_parents))))
 
     def rhs_variants(self):
-        """[(z-planes per group, threads per workgroup, waves per SIMD aimed at, z-plane
-        ring)] of the fused kernel's variants; a negative thread count marks a persistent
-        grid looping over the leaves, waves 1 the compiler's default register allocation,
-        ring 1 z-face stencils read from LDS."""
+        """[(z-planes per group, threads per workgroup, waves per SIMD aimed at)] of the
+        fused kernel's variants; a negative thread count marks a persistent grid looping
+        over the leaves, waves 1 the compiler's default register allocation."""
         n = C.c_int32(0)
         lib().mrfv_rhs_variant(self.h, -1, C.byref(n), None)
-        shp = (C.c_int32 * (4 * n.value))()
+        shp = (C.c_int32 * (3 * n.value))()
         lib().mrfv_rhs_variant(self.h, -1, None, shp)
-        return [tuple(shp[4 * v + i] for i in range(4)) for v in range(n.value)]
+        return [tuple(shp[3 * v + i] for i in range(3)) for v in range(n.value)]
 
     def set_rhs_variant(self, v: int) -> int:
         rc = lib().mrfv_rhs_variant(self.h, int(v), None, None)

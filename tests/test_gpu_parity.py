@@ -196,6 +196,62 @@ def test_cfl_and_totals(orc, torch_mod, dtype):
     assert np.all(np.abs(tot_g - tot_o) <= (1e-13 if dtype == "f64" else 1e-6) * np.abs(tot_o).max())
 
 
+def test_fused_stage_restricts_parents(orc, torch_mod):
+    """A fused stage with restriction writes, into the parent octant of every leaf without
+    a non-leaf same-level face neighbour, the eq:Projection average of its new interior
+    (FP64 sums of x, then y, then z pairs: bitwise the restriction kernel's value), and
+    leaves every other parent octant untouched."""
+    torch = torch_mod
+    pb = jump_problem((0, 1, 0))
+    o, g = make_pair(orc, pb, REFS, "f32", 2)
+    rng = np.random.default_rng(11)
+    set_interiors(o, g, lambda k: random_physical(rng, (N, N, N), rough=0.01))
+    g.cfl_dt()
+    Uout = torch.zeros_like(g.U)
+    g.fused_stage(0, Uout, restrict_parents=True)
+    torch.cuda.synchronize()
+    out = Uout.double().cpu().numpy()
+    info = g.blocks()
+    gm = slot_map(g)
+    leaf = {tuple(int(v) for v in r[2:6]): bool(r[6]) for r in info}
+
+    def face_nbrs(key):
+        lv, c = key[0], list(key[1:])
+        for a in range(3):
+            for side in (-1, 1):
+                d = list(c)
+                d[a] += side
+                n = pb.n0[a] << lv
+                if d[a] < 0 or d[a] >= n:
+                    if pb.bc[a] == 1:
+                        continue
+                    d[a] %= n
+                yield (lv, *d)
+
+    written = untouched = 0
+    for key, is_leaf in leaf.items():
+        if is_leaf or key[0] >= pb.lmax:
+            continue
+        par = out[gm[key]]
+        for o_ in range(8):
+            ox, oy, oz = o_ & 1, (o_ >> 1) & 1, o_ >> 2
+            ck = (key[0] + 1, 2 * key[1] + ox, 2 * key[2] + oy, 2 * key[3] + oz)
+            octant = par[:, H + 8 * oz:H + 8 * oz + 8, H + 8 * oy:H + 8 * oy + 8, H + 8 * ox:H + 8 * ox + 8]
+            srestr = leaf[ck] and not any(nb in leaf and not leaf[nb] for nb in face_nbrs(ck))
+            if srestr:
+                c = out[gm[ck]][:, H:H + N, H:H + N, H:H + N]
+                x = c[..., 0::2] + c[..., 1::2]
+                y = x[:, :, 0::2, :] + x[:, :, 1::2, :]
+                z = y[:, 0::2] + y[:, 1::2]
+                want = (z * 0.125).astype(np.float32).astype(np.float64)
+                assert np.array_equal(octant, want), (key, o_)
+                written += 1
+            else:
+                assert not octant.any(), (key, o_)
+                untouched += 1
+    print(f"restricted octants {written}, untouched {untouched}")
+    assert written > 0 and untouched > 0
+
 # ------------------------------------------------------------------ whole runs --------
 
 def _smooth_flow_with_blob(pb, key, gamma=1.4):
@@ -409,10 +465,9 @@ def test_rhs_variants_bitwise_and_autotune(torch_mod):
     for batched in (1, 2):
         g0 = Solver([pb], dtype="f32", batched=batched).init()
         shapes = g0.rhs_variants()
-        # (z-planes, threads (negative: persistent grid), waves per SIMD, z-plane ring)
-        assert len(shapes) >= 4 and all(abs(t) >= 256 and 16 % gp == 0 for gp, t, _, _ in shapes)
-        assert any(t < 0 for _, t, _, _ in shapes) and any(w > 1 for _, _, w, _ in shapes)
-        assert any(r for _, _, _, r in shapes)
+        # (z-planes, threads (negative: persistent grid), waves per SIMD)
+        assert len(shapes) >= 4 and all(abs(t) >= 256 and 16 % gp == 0 for gp, t, _ in shapes)
+        assert any(t < 0 for _, t, _ in shapes) and any(w > 1 for _, _, w in shapes)
         del g0
         for v in range(len(shapes)):
             g = Solver([pb], dtype="f32", batched=batched).init()
