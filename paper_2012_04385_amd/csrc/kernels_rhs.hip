@@ -478,32 +478,53 @@ struct LdsSink {
 constexpr int NFZ = NI * NI;                  // z-faces per face plane (256)
 
 
+// Sources of one workgroup's stencils as 32-bit byte offsets from the lowest of them,
+// read through one buffer resource (range-checked: out-of-range reads return zero);
+// usable (near) when the own block and its six face neighbours lie within 4 GiB.
+struct NearSrc {
+    __amdgpu_buffer_rsrc_t rsrc;
+    unsigned own, lo[3], hi[3];
+    bool near;
+};
+constexpr int BUFFER_RSRC_WORD3 = 0x00020000;   // raw 32-bit loads (gfx9 family)
+
+__device__ __forceinline__ float buffer_f32(__amdgpu_buffer_rsrc_t r, unsigned voff, int soff) {
+    return __int_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, soff, 0));
+}
+
 // Face flux along axis D for the stencil starting at padded index base (six cells at
 // base + j*stride, padded coordinate pos0 + j along D); cells below / above the interior
 // come from lo / hi, which are the neighbour's block shifted by -+16 cells along D (or
 // the own block).  The result is returned in physical component order.
 template <typename T, int D>
 __device__ __forceinline__ void face_flux_at(const T *__restrict__ ub, const T *__restrict__ lo,
-                                             const T *__restrict__ hi, int base, int pos0,
-                                             const Gas<T> &G, T Fp[5]) {
+                                             const T *__restrict__ hi, const NearSrc &ns, int base,
+                                             int pos0, const Gas<T> &G, T Fp[5]) {
     constexpr int stride = Axes<D>::STRIDE;
     constexpr int n1 = Axes<D>::N1, t1 = Axes<D>::T1, t2 = Axes<D>::T2;   // rotated components
     CellState<T> w[6];
-    if (__all(pos0 >= HW && pos0 + 5 < HW + NI)) {
-        // every stencil of the wavefront lies in the own interior: loads from the uniform
-        // component bases with 32-bit offsets (no per-lane source selection)
-        const char *__restrict__ b0 = (const char *)ub;
-        auto at = [&](int q, unsigned off) __attribute__((always_inline)) {
-            return *(const T *)(b0 + (size_t)q * CELLS_P * sizeof(T) + off);
+    static_assert(sizeof(T) == 4, "the fused path is FP32");
+    constexpr int CB = CELLS_P * (int)sizeof(T);   // component stride in bytes
+    if (ns.near) {
+        // 32-bit offsets into one buffer resource: per-lane choice of the source block
+        // only where a wavefront's stencils leave the own interior
+        auto load = [&](int j, unsigned off) __attribute__((always_inline)) {
+            w[j].r = buffer_f32(ns.rsrc, off, 0);
+            w[j].mn = buffer_f32(ns.rsrc, off, n1 * CB);
+            w[j].mt1 = buffer_f32(ns.rsrc, off, t1 * CB);
+            w[j].mt2 = buffer_f32(ns.rsrc, off, t2 * CB);
+            w[j].E = buffer_f32(ns.rsrc, off, 4 * CB);
         };
+        if (__all(pos0 >= HW && pos0 + 5 < HW + NI)) {
 #pragma unroll
-        for (int j = 0; j < 6; ++j) {
-            const unsigned off = (unsigned)(base + j * stride) * (unsigned)sizeof(T);
-            w[j].r = at(0, off);
-            w[j].mn = at(n1, off);
-            w[j].mt1 = at(t1, off);
-            w[j].mt2 = at(t2, off);
-            w[j].E = at(4, off);
+            for (int j = 0; j < 6; ++j) load(j, ns.own + (unsigned)(base + j * stride) * (unsigned)sizeof(T));
+        } else {
+#pragma unroll
+            for (int j = 0; j < 6; ++j) {
+                const int pos = pos0 + j;
+                const unsigned src = pos < HW ? ns.lo[D] : (pos >= HW + NI ? ns.hi[D] : ns.own);
+                load(j, src + (unsigned)(base + j * stride) * (unsigned)sizeof(T));
+            }
         }
     } else {
 #pragma unroll
@@ -565,6 +586,27 @@ void k_rhs_update(int stage, const double *__restrict__ dt,
             const int sh = (mt.zg >> (2 * a + 1)) & 1 ? -1 : nbr[(size_t)slot * 27 + freg[2 * a + 1]];
             nlo[a] = sl >= 0 ? Uin + (size_t)sl * 5 * CELLS_P + NI * strd[a] : ub;
             nhi[a] = sh >= 0 ? Uin + (size_t)sh * 5 * CELLS_P - NI * strd[a] : ub;
+        }
+    }
+    NearSrc ns;
+    {
+        uintptr_t mn = (uintptr_t)ub, mx = (uintptr_t)ub;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            mn = min(mn, min((uintptr_t)nlo[a], (uintptr_t)nhi[a]));
+            mx = max(mx, max((uintptr_t)nlo[a], (uintptr_t)nhi[a]));
+        }
+        // every access lies below the highest source plus one block
+        const uintptr_t span = mx - mn + (uintptr_t)(5 * CELLS_P * sizeof(T));
+        ns.near = span <= (uintptr_t)0xffffffffu;
+        ns.rsrc = __builtin_amdgcn_make_buffer_rsrc((void *)(ub - ((uintptr_t)ub - mn) / sizeof(T)),
+                                                    (short)0, ns.near ? (int)(unsigned)span : 0,
+                                                    BUFFER_RSRC_WORD3);
+        ns.own = (unsigned)((uintptr_t)ub - mn);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            ns.lo[a] = (unsigned)((uintptr_t)nlo[a] - mn);
+            ns.hi[a] = (unsigned)((uintptr_t)nhi[a] - mn);
         }
     }
     T *ffs = FF + (size_t)slot * 6 * 5 * FACE;
@@ -663,7 +705,7 @@ void k_rhs_update(int stage, const double *__restrict__ dt,
                     p = v / (NF_OUT * NI);
                 }
                 const int base = ((k0 + p + HW) * NP + y + HW) * NP + f + 1;
-                face_flux_at<T, 0>(ub, nlo[0], nhi[0], base, f + 1, G, F);
+                face_flux_at<T, 0>(ub, nlo[0], nhi[0], ns, base, f + 1, G, F);
 #pragma unroll
                 for (int q = 0; q < 5; ++q) Fx[p][y][f][q] = F[q];
                 if (f == 0 || f == NI) {
@@ -684,7 +726,7 @@ void k_rhs_update(int stage, const double *__restrict__ dt,
                     p = v / (NI * NF_OUT);
                 }
                 const int base = ((k0 + p + HW) * NP + f + 1) * NP + x + HW;
-                face_flux_at<T, 1>(ub, nlo[1], nhi[1], base, f + 1, G, F);
+                face_flux_at<T, 1>(ub, nlo[1], nhi[1], ns, base, f + 1, G, F);
 #pragma unroll
                 for (int q = 0; q < 5; ++q) Fy[p][f][x][q] = F[q];
                 if (f == 0 || f == NI) {
@@ -696,7 +738,7 @@ void k_rhs_update(int stage, const double *__restrict__ dt,
                 const int x = u % NI, y = (u / NI) % NI, j = u / NFZ + first_z;
                 const int kf = k0 + j;          // face between interior planes kf-1 and kf
                 const int base = ((kf + 1) * NP + y + HW) * NP + x + HW;   // padded z = kf+1 .. kf+6
-                face_flux_at<T, 2>(ub, nlo[2], nhi[2], base, kf + 1, G, F);
+                face_flux_at<T, 2>(ub, nlo[2], nhi[2], ns, base, kf + 1, G, F);
 #pragma unroll
                 for (int q = 0; q < 5; ++q) Fz[j][y][x][q] = F[q];
                 if (kf == 0 || kf == NI) {
