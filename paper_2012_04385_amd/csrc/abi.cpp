@@ -262,11 +262,14 @@ int do_stage_fused(mrfv_ctx *ctx, int stage, const double *dt, const float *Uin,
     return MRFV_OK;
 }
 
+// flags_host / err_host (may be null): the flags and the error word are also written to
+// host memory, read after the stream synchronises (no separate copies)
 template <typename T>
-int do_details_flags(mrfv_ctx *ctx, const T *U, int8_t *flags, double *det) {
-    HIP_OK(launch_zero_f64(det, wlist(ctx, DESC_FINE), ctx->stream));
-    HIP_OK(launch_details<T>(U, wlist(ctx, DESC_FINE), ctx->tb, ctx->d_inst, det, ctx->stream));
-    HIP_OK(launch_flags(wlist(ctx, DESC_ALL), ctx->tb, ctx->d_inst, det, flags, ctx->stream));
+int do_details_flags(mrfv_ctx *ctx, const T *U, int8_t *flags, double *det,
+                     int8_t *flags_host = nullptr, int32_t *err_host = nullptr) {
+    HIP_OK(launch_details<T>(U, wlist(ctx, DESC_FINE), ctx->tb, ctx->d_inst, ctx->d_det4, ctx->stream));
+    HIP_OK(launch_flags(wlist(ctx, DESC_ALL), ctx->tb, ctx->d_inst, ctx->d_det4, det, flags, flags_host,
+                        ctx->d_err, err_host, ctx->stream));
     return MRFV_OK;
 }
 
@@ -448,7 +451,7 @@ int do_init(mrfv_ctx *ctx, mrfv_ic_fn ic, void *user, T *U) {
     }
     CALL(upload_tables(ctx));
     CALL(impose_ic<T>(ctx, ic, user, U, fresh));
-    std::vector<double> det(ctx->cfg.slot_capacity);
+    std::vector<double> det(ctx->cfg.slot_capacity), det4((size_t)ctx->cfg.slot_capacity * details_slabs());
     for (int m = 1; m <= maxl; ++m) {
         std::vector<int> parents;
         for (int s : tp.alive_sorted()) {
@@ -468,11 +471,13 @@ int do_init(mrfv_ctx *ctx, mrfv_ic_fn ic, void *user, T *U) {
             wf.base = ctx->d_slots;
             wf.n = (int32_t)fresh.size();
             wf.grid = wf.n;
-            HIP_OK(launch_zero_f64(ctx->d_det, wf, ctx->stream));
-            HIP_OK(launch_details<T>(U, wf, ctx->tb, ctx->d_inst, ctx->d_det, ctx->stream));
-            HIP_OK(hipMemcpyAsync(det.data(), ctx->d_det, sizeof(double) * det.size(),
+            HIP_OK(launch_details<T>(U, wf, ctx->tb, ctx->d_inst, ctx->d_det4, ctx->stream));
+            const int nz = details_slabs();
+            HIP_OK(hipMemcpyAsync(det4.data(), ctx->d_det4, sizeof(double) * det4.size(),
                                   hipMemcpyDeviceToHost, ctx->stream));
             HIP_OK(hipStreamSynchronize(ctx->stream));
+            for (int f : fresh)
+                det[f] = *std::max_element(det4.begin() + (size_t)f * nz, det4.begin() + (size_t)(f + 1) * nz);
             for (int p : parents) {
                 const HostBlock &b = tp.block(p);
                 const mrfv_instance &P = ctx->inst[b.inst];
@@ -617,10 +622,7 @@ int do_step(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt) {
     const bool fused = ctx->cfg.batched && sizeof(T) == 4;
     CALL(do_project<T>(ctx, U, false, true, fused));
     CALL(do_fill<T>(ctx, U, 1 << 20, FILL_MISSING | FILL_RHO_E));
-    CALL(do_details_flags<T>(ctx, U, ctx->d_flags, ctx->d_det));
-    const int cap = ctx->cfg.slot_capacity;
-    HIP_OK(hipMemcpyAsync(ctx->h_flags, ctx->d_flags, cap, hipMemcpyDeviceToHost, ctx->stream));
-    HIP_OK(hipMemcpyAsync(ctx->h_err, ctx->d_err, sizeof(int32_t), hipMemcpyDeviceToHost, ctx->stream));
+    CALL(do_details_flags<T>(ctx, U, ctx->d_flags, ctx->d_det, ctx->h_flags, ctx->h_err));
     if (prop) {
         // host-side tree work for the proposed flags, overlapped with the device
         if (ctx->prop_mode == 1 && !leaves.empty()) HIP_OK(hipEventSynchronize(ctx->ev_prop));
@@ -773,6 +775,7 @@ int mrfv_create(mrfv_ctx **out, const mrfv_config *cfg, const mrfv_instance *ins
     ALLOC(ctx->d_FF, cap * 6 * 5 * FACE * es);
     ALLOC(ctx->d_blockred, cap * 5 * sizeof(double));
     ALLOC(ctx->d_det, cap * sizeof(double));
+    ALLOC(ctx->d_det4, cap * details_slabs() * sizeof(double));
     ALLOC(ctx->d_flags, cap);
     ALLOC(ctx->d_slots, cap * sizeof(int32_t));
     ALLOC(ctx->d_slots2, cap * sizeof(int32_t));
@@ -812,7 +815,7 @@ int mrfv_destroy(mrfv_ctx *ctx) {
         for (void *p : pp)
             if (p) hipFree(p);
     }
-    void *ptrs[] = {ctx->d_inst, ctx->d_err, ctx->d_D, ctx->d_W, ctx->d_W2, ctx->d_FF, ctx->d_blockred, ctx->d_det,
+    void *ptrs[] = {ctx->d_inst, ctx->d_err, ctx->d_D, ctx->d_W, ctx->d_W2, ctx->d_FF, ctx->d_blockred, ctx->d_det, ctx->d_det4,
                     ctx->d_flags, ctx->d_slots, ctx->d_slots2, ctx->d_prim, ctx->tb.meta, ctx->tb.child,
                     ctx->tb.nbr, ctx->tb.lists, ctx->d_desc};
     for (void *p : ptrs)

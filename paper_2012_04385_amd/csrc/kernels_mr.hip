@@ -287,9 +287,8 @@ __global__ __launch_bounds__(TPB) void k_predict(T *__restrict__ U,
 }
 
 // Details, FP64.  DZ workgroups per block (level >= 1), each for a slab of 24/DZ padded
-// z-planes, write their maxima of the rho and E details over the slab; det[slot] is the
-// maximum over the slabs (atomicMax on the bit patterns of non-negative doubles, after
-// the list's entries were zeroed).  The prediction is applied separably through LDS, in
+// z-planes, write their maxima of the rho and E details over the slab to det4[slot][part];
+// the detail of the block is the maximum over its slabs (formed by k_flags).  The prediction is applied separably through LDS, in
 // the order z, x, y: the parent planes the slab's stencils touch are staged once, the z
 // pass makes the slab's child planes on the parent's (x, y) cells, the x pass the child
 // x-cells, and the y pass is evaluated at the output.  Both children of a parent cell
@@ -315,7 +314,7 @@ __global__ __launch_bounds__(DTPB) void k_details(const T *__restrict__ U, WorkL
                                                  const BlockMeta *__restrict__ meta,
                                                  const int32_t *__restrict__ nbr,
                                                  const InstDev *__restrict__ inst,
-                                                 double *__restrict__ det) {
+                                                 double *__restrict__ det4) {
     constexpr int R = NI;                       // parent region edge in x and y (16)
     constexpr int NPAIR = NP / 2;               // sibling pairs along a padded axis (12)
     constexpr int NA = (PZ * R * R + DTPB - 1) / DTPB;        // parent loads per thread (5)
@@ -428,35 +427,50 @@ __global__ __launch_bounds__(DTPB) void k_details(const T *__restrict__ U, WorkL
     if (tid == 0) {
         double mx = red[0];
         for (int w = 1; w < DTPB / 64; ++w) mx = fmax(mx, red[w]);
-        atomicMax((unsigned long long *)(det + slot), (unsigned long long)__double_as_longlong(mx));
+        det4[(size_t)slot * DZ + part] = mx;
     }
     __syncthreads();
     }
-}
-
-__global__ __launch_bounds__(TPB) void k_zero_f64(double *__restrict__ p, WorkList wl) {
-    const int nb = wl.count();
-    for (int t = blockIdx.x * TPB + threadIdx.x; t < nb; t += gridDim.x * TPB) p[wl.at(t)] = 0.0;
 }
 
 __device__ __forceinline__ double eps_level(const InstDev &P, int l) {
     return ldexp(P.eps, -3 * (P.lmax - l));
 }
 
+// Flags of all listed blocks (2 on non-leaves), from the details' slab maxima; also the
+// details themselves (det, blocks on level >= 1) and, when given, copies of the flags and
+// of the error word in host memory (read by the host after the stream synchronises).
 __global__ __launch_bounds__(TPB) void k_flags(WorkList wl,
                                                const BlockMeta *__restrict__ meta,
                                                const int32_t *__restrict__ child,
                                                const InstDev *__restrict__ inst,
-                                               const double *__restrict__ det,
-                                               int8_t *__restrict__ flags) {
+                                               const double *__restrict__ det4,
+                                               double *__restrict__ det,
+                                               int8_t *__restrict__ flags,
+                                               int8_t *__restrict__ flags_host,
+                                               const int32_t *__restrict__ err,
+                                               int32_t *__restrict__ err_host) {
+    auto detail = [&](int s) {
+        const double *p = det4 + (size_t)s * DZ;
+        double v = p[0];
+#pragma unroll
+        for (int k = 1; k < DZ; ++k) v = fmax(v, p[k]);
+        return v;
+    };
+    if (err_host && blockIdx.x == 0 && threadIdx.x == 0) *err_host = *err;
     const int nb = wl.count();
     for (int t = blockIdx.x * TPB + threadIdx.x; t < nb; t += gridDim.x * TPB) {
     const int slot = wl.at(t);
     const BlockMeta m = meta[slot];
-    if (!m.leaf) { flags[slot] = 2; continue; }
-    const InstDev P = inst[m.inst];
     const int l = m.level;
-    const double d = l >= 1 ? det[slot] : -1.0;
+    const double d = l >= 1 ? detail(slot) : -1.0;
+    if (l >= 1) det[slot] = d;
+    if (!m.leaf) {
+        flags[slot] = 2;
+        if (flags_host) flags_host[slot] = 2;
+        continue;
+    }
+    const InstDev P = inst[m.inst];
     int8_t f = 0;
     if (!P.adapt) {
         f = 0;
@@ -467,11 +481,12 @@ __global__ __launch_bounds__(TPB) void k_flags(WorkList wl,
         const double e = eps_level(P, l);
         for (int o = 0; o < 8; ++o) {
             const int s = child[(size_t)m.parent * 8 + o];
-            if (!meta[s].leaf || !(det[s] < e)) small = false;
+            if (!meta[s].leaf || !(detail(s) < e)) small = false;
         }
-        if (small && det[m.parent] < eps_level(P, l - 1)) f = -1;
+        if (small && detail(m.parent) < eps_level(P, l - 1)) f = -1;
     }
     flags[slot] = f;
+    if (flags_host) flags_host[slot] = f;
     }
 }
 
@@ -641,24 +656,21 @@ hipError_t launch_predict(T *U, const int32_t *list, int n, const DevTables &tb,
 
 template <typename T>
 hipError_t launch_details(const T *U, const WorkList &wl, const DevTables &tb,
-                          const InstDev *inst, double *det, hipStream_t st) {
+                          const InstDev *inst, double *det4, hipStream_t st) {
     if (wl.grid <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_details<T>, grid2(wl.grid, DZ), dim3(DTPB), 0, st, U, wl, tb.meta, tb.nbr,
-                       inst, det);
+                       inst, det4);
     return hipGetLastError();
 }
 
-hipError_t launch_zero_f64(double *p, const WorkList &wl, hipStream_t st) {
-    if (wl.grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_zero_f64, dim3((wl.grid + TPB - 1) / TPB), dim3(TPB), 0, st, p, wl);
-    return hipGetLastError();
-}
+int details_slabs() { return DZ; }
 
 hipError_t launch_flags(const WorkList &wl, const DevTables &tb, const InstDev *inst,
-                        const double *det, int8_t *flags, hipStream_t st) {
+                        const double *det4, double *det, int8_t *flags, int8_t *flags_host,
+                        const int32_t *err, int32_t *err_host, hipStream_t st) {
     if (wl.grid <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_flags, dim3((wl.grid + TPB - 1) / TPB), dim3(TPB), 0, st, wl, tb.meta,
-                       tb.child, inst, det, flags);
+                       tb.child, inst, det4, det, flags, flags_host, err, err_host);
     return hipGetLastError();
 }
 

@@ -174,10 +174,13 @@ hipError_t launch_predict(T *U, const int32_t *list, int n, const DevTables &tb,
                           hipStream_t st);
 template <typename T>
 hipError_t launch_details(const T *U, const WorkList &wl, const DevTables &tb,
-                          const InstDev *inst, double *det, hipStream_t st);
-hipError_t launch_zero_f64(double *p, const WorkList &wl, hipStream_t st);
+                          const InstDev *inst, double *det4, hipStream_t st);
+int details_slabs();   // slab maxima per block in det4
+// flags (and det of blocks on level >= 1) from the slab maxima; flags_host / err_host
+// (may be null): host-memory copies of the flags and of the error word err
 hipError_t launch_flags(const WorkList &wl, const DevTables &tb, const InstDev *inst,
-                        const double *det, int8_t *flags, hipStream_t st);
+                        const double *det4, double *det, int8_t *flags, int8_t *flags_host,
+                        const int32_t *err, int32_t *err_host, hipStream_t st);
 template <typename T>
 hipError_t launch_cfl(const T *U, const WorkList &leaves, const DevTables &tb,
                       const InstDev *inst, int n_inst, double *blockmax, double *dt,
@@ -246,6 +249,7 @@ struct mrfv_ctx {
     void *d_FF = nullptr;              // boundary face fluxes [cap][6][5][16][16]
     double *d_blockred = nullptr;      // [cap][5] per-block partial reductions
     double *d_det = nullptr;           // [cap]
+    double *d_det4 = nullptr;          // [cap][details_slabs()] slab maxima of the details
     int8_t *d_flags = nullptr;         // [cap]
     int32_t *d_desc = nullptr;         // [N_DESC][2] list descriptors (graph launches)
     hipStream_t gstream = nullptr;     // capture stream of the stage graph
