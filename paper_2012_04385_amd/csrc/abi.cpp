@@ -640,6 +640,7 @@ int do_step(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt) {
     HIP_OK(hipStreamSynchronize(ctx->stream));
     const auto w1 = clk::now();
     if (*ctx->h_err) return fail(ctx, MRFV_ENONPHYS, "non-physical state (rho<=0, p+B<=0 or NaN)");
+    bool change = false;
     {
         // The details saw rho and E only.  When the tree changes, on the old tree and
         // before it changes: every component is restricted (a coarsened parent becomes a
@@ -648,7 +649,6 @@ int do_step(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt) {
         // (after the commit a same-level neighbour of such a leaf can be a fresh child
         // that holds no data yet).
         const HostLists &L = ctx->lists;
-        bool change = false;
         std::vector<int32_t> refined;
         for (int i = 0; i < L.all_leaves_cnt; ++i) {
             const int32_t sl = L.data[L.all_leaves_off + i];
@@ -695,7 +695,7 @@ int do_step(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt) {
         } else {
             CALL(commit(ctx, ctx->h_flags, fresh));
         }
-    } else {
+    } else if (change) {   // flags without a refine or coarsen leave the tree as it is
         CALL(commit(ctx, ctx->h_flags, fresh));
     }
     const auto w2 = clk::now();
