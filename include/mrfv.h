@@ -162,6 +162,18 @@ int mrfv_commit_flags(mrfv_ctx *ctx, const int8_t *flags_host, int32_t *new_slot
  * for restricted parents and complete halos). */
 int mrfv_step(mrfv_ctx *ctx, void *U, void *U0, void *L, double *dt_dev);
 
+/* run -- n_steps calls of mrfv_step with the same result, bitwise, for callers that do
+ * not touch U in between.  On the batched FP32 graph path of an adaptive context without
+ * a proposer, step k+1 is queued before the host has read step k's flags; when those
+ * flags change the tree, the first kernel of step k+1 finds the change recorded on the
+ * device and zeroes that step's work lists (it does nothing), and step k+1 is queued
+ * again after the commit.  The device then runs unchanged steps back to back.  Returns
+ * after the last step with nothing left in flight; dt_dev holds the last step's dt.
+ * leaf_cells_host (may be NULL): the leaf cells of each step's tree, summed over the
+ * steps run (a step integrates each of them three times). */
+int mrfv_run(mrfv_ctx *ctx, void *U, void *U0, void *L, double *dt_dev, int32_t n_steps,
+             int64_t *leaf_cells_host);
+
 /* check -- reads and clears the device error word: MRFV_ENONPHYS if a stage produced a
  * non-physical state since the last check, else MRFV_OK.  Synchronises the stream. */
 int mrfv_check(mrfv_ctx *ctx);

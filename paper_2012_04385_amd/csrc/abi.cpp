@@ -98,7 +98,7 @@ WorkList wlist(const mrfv_ctx *ctx, int which, int grid_cap = 2048) {
     WorkList w;
     w.base = ctx->tb.lists;
     if (ctx->capturing) {
-        w.desc = ctx->d_desc + 2 * which;
+        w.desc = ctx->d_desc_g + 2 * which;   // as gated by the graph's first kernel
         const std::vector<int32_t> &d = ctx->lists.desc;
         if (2 * which + 1 >= (int)d.size() || d[2 * which + 1] == 0) return w;   // grid 0: skipped
         // bound: the most blocks the list can ever hold (per level: every instance full)
@@ -266,10 +266,26 @@ int do_stage_fused(mrfv_ctx *ctx, int stage, const double *dt, const float *Uin,
 // host memory, read after the stream synchronises (no separate copies)
 template <typename T>
 int do_details_flags(mrfv_ctx *ctx, const T *U, int8_t *flags, double *det,
-                     int8_t *flags_host = nullptr, int32_t *err_host = nullptr) {
+                     int8_t *flags_host = nullptr, int32_t *err_host = nullptr,
+                     int32_t *gate = nullptr) {
     HIP_OK(launch_details<T>(U, wlist(ctx, DESC_FINE), ctx->tb, ctx->d_inst, ctx->d_det4, ctx->stream));
     HIP_OK(launch_flags(wlist(ctx, DESC_ALL), ctx->tb, ctx->d_inst, ctx->d_det4, det, flags, flags_host,
-                        ctx->d_err, err_host, ctx->stream));
+                        ctx->d_err, err_host, gate, ctx->cfg.slot_capacity, ctx->stream));
+    return MRFV_OK;
+}
+
+// Device part of the adaptation up to the flags: the details read only rho and E, so
+// parents are restricted and filled in those two (the fused path's last stage wrote the
+// octants of jump-free leaves); all components are restricted and filled on the host's
+// side when the flags change the tree.  gated: inside a step graph (the flags kernel
+// records a tree change for the next launch's gate and writes the parity's half).
+template <typename T>
+int do_adapt_device(mrfv_ctx *ctx, T *U, bool gated) {
+    const bool fused = ctx->cfg.batched && sizeof(T) == 4;
+    CALL(do_project<T>(ctx, U, false, true, fused));
+    CALL(do_fill<T>(ctx, U, 1 << 20, FILL_MISSING | FILL_RHO_E));
+    CALL(do_details_flags<T>(ctx, U, ctx->d_flags, ctx->d_det, ctx->h_flags, ctx->h_err,
+                             gated ? ctx->d_gate : nullptr));
     return MRFV_OK;
 }
 
@@ -535,17 +551,19 @@ int do_stages(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt) {
 // Which launches a captured stage graph contains: the finest level present, whether
 // resolution jumps exist, and which per-level lists are non-empty.  Counts and list
 // contents are read on the device, so one graph serves every tree with the same key.
-uint64_t graph_key(const mrfv_ctx *ctx) {
+GraphKey graph_key(const mrfv_ctx *ctx) {
     const HostLists &L = ctx->lists;
     uint64_t k = (uint64_t)L.max_level | ((uint64_t)ctx->has_jumps << 4) |
                  ((uint64_t)L.parents_needed << 63);
+    uint64_t k2 = 0;
     for (int l = 0; l <= L.max_level && l < MAX_LEVELS; ++l) {
         if (L.desc[2 * desc_par(l) + 1] > 0) k |= 1ull << (5 + l);
         if (L.desc[2 * desc_jleaf(l) + 1] > 0) k |= 1ull << (5 + MAX_LEVELS + l);
         if (L.desc[2 * desc_pfill(l) + 1] > 0) k |= 1ull << (5 + 2 * MAX_LEVELS + l);
         if (L.desc[2 * desc_pproj(l) + 1] > 0) k |= 1ull << (5 + 3 * MAX_LEVELS + l);
+        if (L.desc[2 * desc_jleaf26(l) + 1] > 0) k2 |= 1ull << l;   // the adaptation's fill
     }
-    return k;
+    return {k, k2};
 }
 
 void drop_graphs(mrfv_ctx *ctx) {
@@ -553,9 +571,9 @@ void drop_graphs(mrfv_ctx *ctx) {
     ctx->graphs.clear();
 }
 
-int run_stage_graph(mrfv_ctx *ctx, float *U, float *U0, double *dt) {
+int run_step_graph(mrfv_ctx *ctx, float *U, float *U0, double *dt, bool adapt) {
     if (ctx->gU != U || ctx->gU0 != U0 || ctx->gdt != dt) drop_graphs(ctx);
-    const uint64_t key = graph_key(ctx);
+    const GraphKey key = graph_key(ctx);
     auto it = ctx->graphs.find(key);
     if (it == ctx->graphs.end()) {
         if (ctx->graphs.size() >= 32) drop_graphs(ctx);   // bound the cache
@@ -566,13 +584,19 @@ int run_stage_graph(mrfv_ctx *ctx, float *U, float *U0, double *dt) {
         ctx->stream = ctx->gstream;
         ctx->capturing = true;
         hipError_t e = hipStreamBeginCapture(ctx->gstream, hipStreamCaptureModeThreadLocal);
-        int rc = e == hipSuccess ? do_stages<float>(ctx, U, U0, nullptr, dt) : MRFV_EHIP;
+        int rc = MRFV_EHIP;
+        if (e == hipSuccess) {
+            rc = launch_gate(ctx->d_gate, ctx->d_desc, ctx->d_desc_g, N_DESC, ctx->stream) == hipSuccess
+                     ? MRFV_OK : MRFV_EHIP;
+            if (rc == MRFV_OK) rc = do_stages<float>(ctx, U, U0, nullptr, dt);
+            if (rc == MRFV_OK && adapt) rc = do_adapt_device<float>(ctx, U, true);
+        }
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(ctx->gstream, &g);
         ctx->capturing = false;
         ctx->stream = user;
         if (e != hipSuccess || e2 != hipSuccess || rc != MRFV_OK || !g)
-            return fail(ctx, MRFV_EHIP, "stage graph capture failed");
+            return fail(ctx, MRFV_EHIP, "step graph capture failed");
         hipError_t e3 = hipGraphInstantiate(&ctx->graph, g, nullptr, nullptr, 0);
         hipGraphDestroy(g);
         if (e3 != hipSuccess) {
@@ -586,60 +610,42 @@ int run_stage_graph(mrfv_ctx *ctx, float *U, float *U0, double *dt) {
         ctx->graph = nullptr;
     }
     HIP_OK(hipGraphLaunch(it->second, ctx->stream));
+    ctx->graph_launches++;
     return MRFV_OK;
 }
 
+// Device part of a step: stages and, for adaptive contexts, the restriction, fills,
+// details and flags.  The batched FP32 path replays all of it as one graph whose first
+// kernel gates the work lists (see k_gate); *half receives the half of the host flag
+// buffers the flags go to.
 template <typename T>
-int do_step(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt) {
-    bool adapt = false;
-    for (const auto &p : ctx->inst) adapt = adapt || (p.adapt && p.lmax > 0);
-    const bool prop = adapt && ctx->prop_mode != 0;
-    std::vector<int32_t> leaves;
-    if (prop) {
-        const HostLists &L = ctx->lists;
-        leaves.assign(L.data.begin() + L.all_leaves_off,
-                      L.data.begin() + L.all_leaves_off + L.all_leaves_cnt);
-    }
-    if (prop && ctx->prop_mode == 1 && !leaves.empty()) {
-        // proposal for this step's judge from the state at its start; it is queued
-        // ahead of the stages, so the host can read it while the device continues
-        HIP_OK(launch_features<T>(U, wlist(ctx, DESC_LEAVES), ctx->tb, ctx->d_inst, ctx->d_X,
-                                  ctx->stream));
-        CALL(mlp_forward_on(ctx->mlp, ctx->stream, ctx->d_X, (int)leaves.size(), ctx->d_logits));
-        HIP_OK(hipMemcpyAsync(ctx->h_logits, ctx->d_logits, leaves.size() * 3 * sizeof(float),
-                              hipMemcpyDeviceToHost, ctx->stream));
-        HIP_OK(hipEventRecord(ctx->ev_prop, ctx->stream));
-    }
+int launch_step(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt, bool adapt, int *half) {
     if (ctx->cfg.batched == 2 && sizeof(T) == 4 && !ctx->timing) {
-        CALL(run_stage_graph(ctx, (float *)U, (float *)U0, dt));
-    } else {
-        CALL(do_stages<T>(ctx, U, U0, Lb, dt));
+        CALL(run_step_graph(ctx, (float *)U, (float *)U0, dt, adapt));
+        *half = (int)(ctx->graph_launches & 1);
+        return MRFV_OK;
     }
-    if (!adapt) return MRFV_OK;
-    // the details read only rho and E: parents are restricted and filled in those two
-    // (the fused path's last stage wrote the octants of jump-free leaves); all components
-    // are restricted and filled below when the flags change the tree
-    const bool fused = ctx->cfg.batched && sizeof(T) == 4;
-    CALL(do_project<T>(ctx, U, false, true, fused));
-    CALL(do_fill<T>(ctx, U, 1 << 20, FILL_MISSING | FILL_RHO_E));
-    CALL(do_details_flags<T>(ctx, U, ctx->d_flags, ctx->d_det, ctx->h_flags, ctx->h_err));
-    if (prop) {
-        // host-side tree work for the proposed flags, overlapped with the device
-        if (ctx->prop_mode == 1 && !leaves.empty()) HIP_OK(hipEventSynchronize(ctx->ev_prop));
-        const auto t0 = std::chrono::steady_clock::now();
-        decode_proposal(ctx, leaves);
-        CALL(stage_proposal(ctx));
-        ctx->p_build_ms +=
-            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    }
+    CALL(do_stages<T>(ctx, U, U0, Lb, dt));
+    if (adapt) CALL(do_adapt_device<T>(ctx, U, false));
+    *half = 0;
+    return MRFV_OK;
+}
+
+// Host part of an adaptive step once its flags are in host memory (half `half`): the
+// error word, then, when the flags change the tree, the full restriction and fills on
+// the old tree, the commit and the prediction of the new children.  *changed: whether
+// the tree changed.
+template <typename T>
+int finish_step(mrfv_ctx *ctx, T *U, int half, bool prop, const std::vector<int32_t> &leaves,
+                bool *changed) {
     using clk = std::chrono::steady_clock;
     auto ms = [](clk::time_point a, clk::time_point b) {
         return std::chrono::duration<double, std::milli>(b - a).count();
     };
-    const auto w0 = clk::now();
-    HIP_OK(hipStreamSynchronize(ctx->stream));
     const auto w1 = clk::now();
-    if (*ctx->h_err) return fail(ctx, MRFV_ENONPHYS, "non-physical state (rho<=0, p+B<=0 or NaN)");
+    const int8_t *hf = ctx->h_flags + (size_t)half * ctx->cfg.slot_capacity;
+    ctx->last_half = half;
+    if (ctx->h_err[half]) return fail(ctx, MRFV_ENONPHYS, "non-physical state (rho<=0, p+B<=0 or NaN)");
     bool change = false;
     {
         // The details saw rho and E only.  When the tree changes, on the old tree and
@@ -652,7 +658,7 @@ int do_step(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt) {
         std::vector<int32_t> refined;
         for (int i = 0; i < L.all_leaves_cnt; ++i) {
             const int32_t sl = L.data[L.all_leaves_off + i];
-            const int8_t f = ctx->h_flags[sl];
+            const int8_t f = hf[sl];
             change = change || f == 1 || f == -1;
             if (f == 1) refined.push_back(sl);
         }
@@ -673,39 +679,154 @@ int do_step(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt) {
         }
     }
     std::vector<int32_t> fresh;
+    bool tree_changed = change;
     if (prop) {
         bool hit = true;
         for (int32_t s : leaves) {
-            const int j = ctx->h_flags[s], q = ctx->proposal[s];
+            const int j = hf[s], q = ctx->proposal[s];
             const int cj = j == 1 ? 0 : (j == -1 ? 2 : 1), cq = q == 1 ? 0 : (q == -1 ? 2 : 1);
             if (j != q) hit = false;
             if (cj == cq) ctx->p_tp[cj]++;
             else { ctx->p_fn[cj]++; ctx->p_fp[cq]++; }
         }
         ctx->p_steps++;
-        bool change = false;
-        for (int32_t sl : leaves) change = change || ctx->proposal[sl] != 0;
+        bool pchange = false;
+        for (int32_t sl : leaves) pchange = pchange || ctx->proposal[sl] != 0;
         if (hit) ctx->p_hits++;
         if (ctx->staged) ctx->p_staged++;
-        if (hit && !change) {
+        if (hit && !pchange) {
             // nothing to commit
         } else if (hit && ctx->staged) {
             ctx->p_adopted++;
             CALL(adopt_staged(ctx, fresh));
         } else {
-            CALL(commit(ctx, ctx->h_flags, fresh));
+            CALL(commit(ctx, hf, fresh));
         }
     } else if (change) {   // flags without a refine or coarsen leave the tree as it is
-        CALL(commit(ctx, ctx->h_flags, fresh));
+        CALL(commit(ctx, hf, fresh));
     }
     const auto w2 = clk::now();
     CALL(do_predict<T>(ctx, U, fresh.data(), (int)fresh.size(), false));
     const auto w3 = clk::now();
-    ctx->h_wait_ms += ms(w0, w1);
     ctx->h_commit_ms += ms(w1, w2);
     ctx->h_predict_ms += ms(w2, w3);
     ctx->h_steps++;
+    *changed = tree_changed;
     return MRFV_OK;
+}
+
+bool adaptive(const mrfv_ctx *ctx) {
+    bool adapt = false;
+    for (const auto &p : ctx->inst) adapt = adapt || (p.adapt && p.lmax > 0);
+    return adapt;
+}
+
+template <typename T>
+int do_step(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt) {
+    const bool adapt = adaptive(ctx);
+    const bool prop = adapt && ctx->prop_mode != 0;
+    std::vector<int32_t> leaves;
+    if (prop) {
+        const HostLists &L = ctx->lists;
+        leaves.assign(L.data.begin() + L.all_leaves_off,
+                      L.data.begin() + L.all_leaves_off + L.all_leaves_cnt);
+    }
+    if (prop && ctx->prop_mode == 1 && !leaves.empty()) {
+        // proposal for this step's judge from the state at its start; it is queued
+        // ahead of the stages, so the host can read it while the device continues
+        HIP_OK(launch_features<T>(U, wlist(ctx, DESC_LEAVES), ctx->tb, ctx->d_inst, ctx->d_X,
+                                  ctx->stream));
+        CALL(mlp_forward_on(ctx->mlp, ctx->stream, ctx->d_X, (int)leaves.size(), ctx->d_logits));
+        HIP_OK(hipMemcpyAsync(ctx->h_logits, ctx->d_logits, leaves.size() * 3 * sizeof(float),
+                              hipMemcpyDeviceToHost, ctx->stream));
+        HIP_OK(hipEventRecord(ctx->ev_prop, ctx->stream));
+    }
+    // this step is not speculative: no earlier change may gate it
+    HIP_OK(hipMemsetAsync(ctx->d_gate, 0, sizeof(int32_t), ctx->stream));
+    int half = 0;
+    CALL(launch_step<T>(ctx, U, U0, Lb, dt, adapt, &half));
+    if (!adapt) return MRFV_OK;
+    if (prop) {
+        // host-side tree work for the proposed flags, overlapped with the device
+        if (ctx->prop_mode == 1 && !leaves.empty()) HIP_OK(hipEventSynchronize(ctx->ev_prop));
+        const auto t0 = std::chrono::steady_clock::now();
+        decode_proposal(ctx, leaves);
+        CALL(stage_proposal(ctx));
+        ctx->p_build_ms +=
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    const auto w0 = std::chrono::steady_clock::now();
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    ctx->h_wait_ms +=
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - w0).count();
+    bool changed = false;
+    return finish_step<T>(ctx, U, half, prop, leaves, &changed);
+}
+
+// n steps.  On the graph path of an adaptive context without a proposer, step k+1 is
+// launched before the host has read step k's flags; if those flags change the tree, the
+// gate at the start of step k+1 zeroes its work lists (it does nothing), and step k+1 is
+// launched again after the commit.  Otherwise the device runs the steps back to back.
+template <typename T>
+int do_run(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt, int n, int64_t *cells) {
+    const bool adapt = adaptive(ctx);
+    const bool spec = adapt && ctx->prop_mode == 0 && ctx->cfg.batched == 2 && sizeof(T) == 4 &&
+                      !ctx->timing;
+    auto leaf_cells = [&]() { return (int64_t)ctx->lists.all_leaves_cnt * CELLS_I; };
+    *cells = 0;
+    if (!spec) {
+        for (int k = 0; k < n; ++k) {
+            *cells += leaf_cells();
+            CALL(do_step<T>(ctx, U, U0, Lb, dt));
+        }
+        return MRFV_OK;
+    }
+    if (n <= 0) return MRFV_OK;
+    const std::vector<int32_t> none;
+    hipEvent_t ev[2];
+    HIP_OK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+    if (hipEventCreateWithFlags(&ev[1], hipEventDisableTiming) != hipSuccess) {
+        hipEventDestroy(ev[0]);
+        return fail(ctx, MRFV_EHIP, "hipEventCreate failed");
+    }
+    int rc = MRFV_OK;
+    int half[2] = {0, 0};
+    int64_t step_cells[2] = {0, 0};
+    auto launch = [&](int k) {
+        step_cells[k & 1] = leaf_cells();   // the tree this launch integrates
+        int r = launch_step<T>(ctx, U, U0, Lb, dt, true, &half[k & 1]);
+        if (r == MRFV_OK && hipEventRecord(ev[k & 1], ctx->stream) != hipSuccess)
+            r = fail(ctx, MRFV_EHIP, "hipEventRecord failed");
+        return r;
+    };
+    if (hipMemsetAsync(ctx->d_gate, 0, sizeof(int32_t), ctx->stream) != hipSuccess)
+        rc = fail(ctx, MRFV_EHIP, "hipMemsetAsync failed");
+    if (rc == MRFV_OK) rc = launch(0);
+    for (int k = 0; k < n && rc == MRFV_OK; ++k) {
+        if (k + 1 < n && (rc = launch(k + 1)) != MRFV_OK) break;   // speculative
+        const auto w0 = std::chrono::steady_clock::now();
+        if (hipEventSynchronize(ev[k & 1]) != hipSuccess) {
+            rc = fail(ctx, MRFV_EHIP, "hipEventSynchronize failed");
+            break;
+        }
+        ctx->h_wait_ms +=
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - w0).count();
+        bool changed = false;
+        *cells += step_cells[k & 1];
+        if ((rc = finish_step<T>(ctx, U, half[k & 1], false, none, &changed)) != MRFV_OK) break;
+        if (changed && k + 1 < n) {
+            // the speculative step k+1 was gated (it changed nothing): run it on the new tree
+            if (hipMemsetAsync(ctx->d_gate, 0, sizeof(int32_t), ctx->stream) != hipSuccess) {
+                rc = fail(ctx, MRFV_EHIP, "hipMemsetAsync failed");
+                break;
+            }
+            rc = launch(k + 1);
+        }
+    }
+    hipStreamSynchronize(ctx->stream);   // nothing of this call stays in flight
+    hipEventDestroy(ev[0]);
+    hipEventDestroy(ev[1]);
+    return rc;
 }
 
 int need_init(mrfv_ctx *ctx) {
@@ -765,13 +886,15 @@ int mrfv_create(mrfv_ctx **out, const mrfv_config *cfg, const mrfv_instance *ins
         ALLOC(ctx->d_W2, cap * 5 * CELLS_P * es);   // fused stages
     }
     ALLOC(ctx->d_desc, 2 * N_DESC * sizeof(int32_t));
-    if (hipHostMalloc((void **)&ctx->h_flags, cap, 0) != hipSuccess ||
-        hipHostMalloc((void **)&ctx->h_err, sizeof(int32_t), 0) != hipSuccess) {
+    ALLOC(ctx->d_desc_g, 2 * N_DESC * sizeof(int32_t));
+    ALLOC(ctx->d_gate, 2 * sizeof(int32_t));
+    if (hipHostMalloc((void **)&ctx->h_flags, 2 * cap, 0) != hipSuccess ||
+        hipHostMalloc((void **)&ctx->h_err, 2 * sizeof(int32_t), 0) != hipSuccess) {
         ctx->err = "hipHostMalloc failed";
         return bail(MRFV_ENOMEM);
     }
-    std::fill(ctx->h_flags, ctx->h_flags + cap, (int8_t)0);
-    *ctx->h_err = 0;
+    std::fill(ctx->h_flags, ctx->h_flags + 2 * cap, (int8_t)0);
+    ctx->h_err[0] = ctx->h_err[1] = 0;
     ALLOC(ctx->d_FF, cap * 6 * 5 * FACE * es);
     ALLOC(ctx->d_blockred, cap * 5 * sizeof(double));
     ALLOC(ctx->d_det, cap * sizeof(double));
@@ -788,7 +911,8 @@ int mrfv_create(mrfv_ctx **out, const mrfv_config *cfg, const mrfv_instance *ins
     if (hipMemcpy(ctx->d_inst, id.data(), sizeof(InstDev) * id.size(), hipMemcpyHostToDevice) !=
             hipSuccess ||
         hipMemset(ctx->d_err, 0, sizeof(int32_t)) != hipSuccess ||
-        hipMemset(ctx->d_det, 0, cap * sizeof(double)) != hipSuccess)
+        hipMemset(ctx->d_det, 0, cap * sizeof(double)) != hipSuccess ||
+        hipMemset(ctx->d_gate, 0, 2 * sizeof(int32_t)) != hipSuccess)
         return bail(MRFV_EHIP);
     ctx->topo.reset(cfg->slot_capacity, ctx->inst);
     *out = ctx;
@@ -817,7 +941,7 @@ int mrfv_destroy(mrfv_ctx *ctx) {
     }
     void *ptrs[] = {ctx->d_inst, ctx->d_err, ctx->d_D, ctx->d_W, ctx->d_W2, ctx->d_FF, ctx->d_blockred, ctx->d_det, ctx->d_det4,
                     ctx->d_flags, ctx->d_slots, ctx->d_slots2, ctx->d_prim, ctx->tb.meta, ctx->tb.child,
-                    ctx->tb.nbr, ctx->tb.lists, ctx->d_desc};
+                    ctx->tb.nbr, ctx->tb.lists, ctx->d_desc, ctx->d_desc_g, ctx->d_gate};
     for (void *p : ptrs)
         if (p) hipFree(p);
     for (hipEvent_t e : ctx->ev_free) hipEventDestroy(e);
@@ -937,6 +1061,19 @@ int mrfv_step(mrfv_ctx *ctx, void *U, void *U0, void *L, double *dt_dev) {
     return ctx->cfg.dtype == MRFV_F64
                ? do_step<double>(ctx, (double *)U, (double *)U0, (double *)L, dt_dev)
                : do_step<float>(ctx, (float *)U, (float *)U0, (float *)L, dt_dev);
+}
+
+int mrfv_run(mrfv_ctx *ctx, void *U, void *U0, void *L, double *dt_dev, int32_t n_steps,
+             int64_t *leaf_cells_host) {
+    CALL(need_init(ctx));
+    if (!U || !U0 || !L || !dt_dev) return fail(ctx, MRFV_EINVAL, "run: null pointer");
+    if (n_steps < 0) return fail(ctx, MRFV_EINVAL, "run: n_steps must be >= 0");
+    int64_t cells = 0;
+    const int rc = ctx->cfg.dtype == MRFV_F64
+                       ? do_run<double>(ctx, (double *)U, (double *)U0, (double *)L, dt_dev, n_steps, &cells)
+                       : do_run<float>(ctx, (float *)U, (float *)U0, (float *)L, dt_dev, n_steps, &cells);
+    if (leaf_cells_host) *leaf_cells_host = cells;
+    return rc;
 }
 
 int mrfv_check(mrfv_ctx *ctx) {
@@ -1146,7 +1283,8 @@ int mrfv_step_timing(mrfv_ctx *ctx, double *out) {
 int mrfv_last_flags(mrfv_ctx *ctx, int8_t *flags_host) {
     if (!ctx || !flags_host) return MRFV_EINVAL;
     HIP_OK(hipStreamSynchronize(ctx->stream));
-    std::copy(ctx->h_flags, ctx->h_flags + ctx->cfg.slot_capacity, flags_host);
+    const int8_t *hf = ctx->h_flags + (size_t)ctx->last_half * ctx->cfg.slot_capacity;
+    std::copy(hf, hf + ctx->cfg.slot_capacity, flags_host);
     return MRFV_OK;
 }
 

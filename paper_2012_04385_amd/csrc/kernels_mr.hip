@@ -449,7 +449,8 @@ __global__ __launch_bounds__(TPB) void k_flags(WorkList wl,
                                                int8_t *__restrict__ flags,
                                                int8_t *__restrict__ flags_host,
                                                const int32_t *__restrict__ err,
-                                               int32_t *__restrict__ err_host) {
+                                               int32_t *__restrict__ err_host,
+                                               int32_t *__restrict__ gate, int cap) {
     auto detail = [&](int s) {
         const double *p = det4 + (size_t)s * DZ;
         double v = p[0];
@@ -457,6 +458,11 @@ __global__ __launch_bounds__(TPB) void k_flags(WorkList wl,
         for (int k = 1; k < DZ; ++k) v = fmax(v, p[k]);
         return v;
     };
+    // with a gate word pair (graph launches): the host buffers' half given by the launch
+    // parity, and any refine or coarsen recorded in gate[0] for the next launch's gate
+    const int half = gate ? gate[1] : 0;
+    if (flags_host) flags_host += (size_t)half * cap;
+    if (err_host) err_host += half;
     if (err_host && blockIdx.x == 0 && threadIdx.x == 0) *err_host = *err;
     const int nb = wl.count();
     for (int t = blockIdx.x * TPB + threadIdx.x; t < nb; t += gridDim.x * TPB) {
@@ -487,6 +493,27 @@ __global__ __launch_bounds__(TPB) void k_flags(WorkList wl,
     }
     flags[slot] = f;
     if (flags_host) flags_host[slot] = f;
+    if (gate && f != 0) gate[0] = 1;
+    }
+}
+
+// First kernel of a step graph: the work-list descriptors the step's kernels read,
+// copied from desc, with every count zero when the previous step's flags changed the
+// tree (gate[0]): a step launched before the host has seen those flags then does
+// nothing.  Clears gate[0] and flips the launch parity gate[1].
+__global__ __launch_bounds__(TPB) void k_gate(int32_t *__restrict__ gate,
+                                              const int32_t *__restrict__ desc,
+                                              int32_t *__restrict__ desc_g, int n_desc) {
+    __shared__ int32_t changed;
+    if (threadIdx.x == 0) changed = gate[0];
+    __syncthreads();
+    for (int i = threadIdx.x; i < n_desc; i += TPB) {
+        desc_g[2 * i] = desc[2 * i];
+        desc_g[2 * i + 1] = changed ? 0 : desc[2 * i + 1];
+    }
+    if (threadIdx.x == 0) {
+        gate[0] = 0;
+        gate[1] ^= 1;
     }
 }
 
@@ -667,10 +694,17 @@ int details_slabs() { return DZ; }
 
 hipError_t launch_flags(const WorkList &wl, const DevTables &tb, const InstDev *inst,
                         const double *det4, double *det, int8_t *flags, int8_t *flags_host,
-                        const int32_t *err, int32_t *err_host, hipStream_t st) {
+                        const int32_t *err, int32_t *err_host, int32_t *gate, int cap,
+                        hipStream_t st) {
     if (wl.grid <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_flags, dim3((wl.grid + TPB - 1) / TPB), dim3(TPB), 0, st, wl, tb.meta,
-                       tb.child, inst, det4, det, flags, flags_host, err, err_host);
+                       tb.child, inst, det4, det, flags, flags_host, err, err_host, gate, cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_gate(int32_t *gate, const int32_t *desc, int32_t *desc_g, int n_desc,
+                       hipStream_t st) {
+    hipLaunchKernelGGL(k_gate, dim3(1), dim3(TPB), 0, st, gate, desc, desc_g, n_desc);
     return hipGetLastError();
 }
 

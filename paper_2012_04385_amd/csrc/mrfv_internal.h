@@ -177,10 +177,16 @@ hipError_t launch_details(const T *U, const WorkList &wl, const DevTables &tb,
                           const InstDev *inst, double *det4, hipStream_t st);
 int details_slabs();   // slab maxima per block in det4
 // flags (and det of blocks on level >= 1) from the slab maxima; flags_host / err_host
-// (may be null): host-memory copies of the flags and of the error word err
+// (may be null): host-memory copies of the flags and of the error word err; gate (may be
+// null; graph launches): {tree changed, launch parity}: the host copies go to the half
+// given by the parity ([2][cap] flags, [2] error words) and a refine or coarsen sets gate[0]
 hipError_t launch_flags(const WorkList &wl, const DevTables &tb, const InstDev *inst,
                         const double *det4, double *det, int8_t *flags, int8_t *flags_host,
-                        const int32_t *err, int32_t *err_host, hipStream_t st);
+                        const int32_t *err, int32_t *err_host, int32_t *gate, int cap,
+                        hipStream_t st);
+// first launch of a step graph: desc_g = desc, counts zeroed when gate[0] is set
+hipError_t launch_gate(int32_t *gate, const int32_t *desc, int32_t *desc_g, int n_desc,
+                       hipStream_t st);
 template <typename T>
 hipError_t launch_cfl(const T *U, const WorkList &leaves, const DevTables &tb,
                       const InstDev *inst, int n_inst, double *blockmax, double *dt,
@@ -232,6 +238,9 @@ namespace mrfv {
 // The proposer network's forward pass queued on a given stream; logits [N][3] FP32.
 int mlp_forward_on(mrfv_mlp *mm, hipStream_t st, const float *X, int N, float *logits);
 }  // namespace mrfv
+// Which launches a captured step graph holds: two words of per-level list emptiness.
+using GraphKey = std::pair<uint64_t, uint64_t>;
+
 struct mrfv_ctx {
     mrfv_config cfg{};
     std::vector<mrfv_instance> inst;
@@ -254,7 +263,8 @@ struct mrfv_ctx {
     int32_t *d_desc = nullptr;         // [N_DESC][2] list descriptors (graph launches)
     hipStream_t gstream = nullptr;     // capture stream of the stage graph
     hipGraphExec_t graph = nullptr;    // graph being instantiated
-    std::map<uint64_t, hipGraphExec_t> graphs;   // CFL + three RK stages by graph key,
+    std::map<GraphKey, hipGraphExec_t> graphs;   // step graphs (gate, CFL, three RK stages,
+                                                 // adaptation up to the flags) by graph key,
                                                  // valid for (gU, gU0, gdt)
     void *gU = nullptr, *gU0 = nullptr;
     const double *gdt = nullptr;
@@ -264,8 +274,12 @@ struct mrfv_ctx {
     int prop_mode = 0;                 // 0 off, 1 network, 2 persistence (no change)
     float *d_X = nullptr, *d_logits = nullptr;
     float *h_logits = nullptr;         // pinned
-    int8_t *h_flags = nullptr;         // pinned, judge flags
-    int32_t *h_err = nullptr;          // pinned
+    int8_t *h_flags = nullptr;         // pinned [2][cap], judge flags (halves: launch parity)
+    int32_t *h_err = nullptr;          // pinned [2]
+    int32_t *d_gate = nullptr;         // {tree changed by the last flags, launch parity}
+    int32_t *d_desc_g = nullptr;       // descriptors as gated for the current step graph
+    int64_t graph_launches = 0;        // step graphs launched (parity of the next: +1)
+    int last_half = 0;                 // half of h_flags / h_err the last step wrote
     std::vector<int8_t> proposal;      // per slot
     mrfv::DevTables tb2;               // staging tables built from the proposal
     int32_t *d_desc2 = nullptr;

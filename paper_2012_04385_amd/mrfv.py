@@ -71,6 +71,7 @@ def lib():
         "mrfv_totals": ([vp, vp, vp], C.c_int),
         "mrfv_commit_flags": ([vp, C.POINTER(C.c_int8), C.POINTER(i32), C.POINTER(i32)], C.c_int),
         "mrfv_step": ([vp, vp, vp, vp, vp], C.c_int),
+        "mrfv_run": ([vp, vp, vp, vp, vp, i32, C.POINTER(i64)], C.c_int),
         "mrfv_check": ([vp], C.c_int),
         "mrfv_get_blocks": ([vp, C.POINTER(i64), C.POINTER(i32)], C.c_int),
         "mrfv_stats": ([vp, C.POINTER(i64)], C.c_int),
@@ -119,7 +120,7 @@ def exported_symbols():
             "mrfv_mlp_get_params", "mrfv_mlp_forward", "mrfv_mlp_loss_grad",
             "mrfv_mlp_adam_step", "mrfv_features", "mrfv_set_proposer", "mrfv_proposer_stats",
             "mrfv_last_flags", "mrfv_step_timing", "mrfv_rhs_variant", "mrfv_autotune",
-            "mrfv_fused_stage"]
+            "mrfv_fused_stage", "mrfv_run"]
 
 
 def morton_encode(shadow, level, bx, by, bz) -> int:
@@ -275,6 +276,15 @@ class Solver:
                                   self._p(self.dt)))
         return self.dt
 
+    def run(self, n: int) -> int:
+        """n steps natively (mrfv_run: the same result as n calls of step, with the next
+        step queued before the host reads the current step's flags).  Returns the leaf
+        cells of the steps' trees, summed over the steps."""
+        cells = C.c_int64(0)
+        self._chk(lib().mrfv_run(self.h, self._p(self.U), self._p(self.U0), self._p(self.L),
+                                 self._p(self.dt), int(n), C.byref(cells)))
+        return int(cells.value)
+
     def check(self):
         self._chk(lib().mrfv_check(self.h))
 
@@ -301,7 +311,8 @@ class Solver:
         return n.value, ms.value, cells.value
 
     # ------------------------------------------------------------- conveniences
-    def run(self, steps: int):
+    def advance(self, steps: int):
+        """steps calls of step, accumulating the simulated time; checks the error word."""
         for _ in range(steps):
             self.step()
             self.time += self.dt.cpu().numpy()

@@ -252,6 +252,56 @@ def test_fused_stage_restricts_parents(orc, torch_mod):
     print(f"restricted octants {written}, untouched {untouched}")
     assert written > 0 and untouched > 0
 
+def _solver_pair(kind, torch):
+    """Two identical FP32 graph-path solvers for the run-vs-steps comparison."""
+    from paper_2012_04385_amd.mrfv import Solver
+    if kind == "blast":
+        pb = W.blast_mr3(steps=6)
+        return pb, [Solver([pb], dtype="f32", batched=2).init() for _ in range(2)]
+    if kind == "sod":
+        pb = W.sod_single_level()
+        return pb, [Solver([pb], dtype="f32", batched=2).init() for _ in range(2)]
+    pb = jump_problem()
+    gs = []
+    for _ in range(2):
+        g = Solver([pb], dtype="f32", batched=2, adapt=1).init()
+        for r in REFS:
+            g.refine(0, *r)
+        for key, slot in slot_map(g).items():
+            g.U[slot, :, H:H + N, H:H + N, H:H + N] = torch.as_tensor(
+                _smooth_flow_with_blob(pb, key), dtype=g.tdtype, device=g.device)
+        torch.cuda.synchronize()
+        gs.append(g)
+    return pb, gs
+
+
+@pytest.mark.parametrize("kind,steps", [("blast", 6), ("adaptive", 3), ("sod", 4)])
+def test_run_equals_steps(torch_mod, kind, steps):
+    """mrfv_run queues step k+1 before it reads step k's flags (and gates it on the device
+    when they change the tree): trees, leaf states and the counted leaf cells are those of
+    the same number of mrfv_step calls, bitwise, also when the first step coarsens and
+    refines."""
+    torch = torch_mod
+    pb, (a, b) = _solver_pair(kind, torch)
+    leaves0 = {tuple(int(v) for v in r[2:6]) for r in a.blocks() if r[6] == 1}
+    cells = a.run(steps)
+    want = 0
+    for _ in range(steps):
+        want += b.leaf_cells()
+        b.step()
+    a.check()
+    b.check()
+    la = {tuple(int(v) for v in r[2:6]) for r in a.blocks() if r[6] == 1}
+    lb = {tuple(int(v) for v in r[2:6]) for r in b.blocks() if r[6] == 1}
+    assert la == lb
+    if kind == "adaptive":
+        assert la != leaves0, "the tree should change during the run"
+    assert cells == want, (cells, want)
+    sa, sb = a.leaf_states(), b.leaf_states()
+    for k in sa:
+        assert np.array_equal(sa[k], sb[k]), k
+    assert torch.equal(a.dt, b.dt)
+
 # ------------------------------------------------------------------ whole runs --------
 
 def _smooth_flow_with_blob(pb, key, gamma=1.4):
@@ -305,7 +355,7 @@ def test_sod_single_level_fp64_plain(orc, torch_mod, noise):
     g = Solver([pb], dtype="f64", batched=False).init()
     for _ in range(pb.steps):
         o.step()
-    g.run(pb.steps)
+    g.advance(pb.steps)
     ol, gl = o.leaf_states(), g.leaf_states()
     worst = max(np.abs(gl[k] - v).max() / np.abs(v).max() for k, v in ol.items())
     e_rho = l1_diff(o, g, 0)
@@ -332,7 +382,7 @@ def test_sod_single_level_fp32_batched(orc, torch_mod):
     g = Solver([pb], dtype="f32", batched=True).init()
     for _ in range(pb.steps):
         o.step()
-    g.run(pb.steps)
+    g.advance(pb.steps)
     e0, e4 = l1_diff(o, g, 0), l1_diff(o, g, 4)
     print(f"sod fp32: L1 rho {e0:.3e}, L1 E {e4:.3e}")
     assert e0 <= 1e-6
