@@ -122,7 +122,7 @@ def cpu_baseline(pb, budget_s=15.0, max_steps=10):
 
 
 def other_workload(args):
-    """Throughput of the FP32 batched path (stage graph, autotuned shape) on a larger
+    """Throughput of the FP32 batched path (step graph, autotuned shape) on a larger
     workload; the fused kernel's duration from HIP events on an eager run."""
     import torch
     from paper_2012_04385_amd import workloads as W

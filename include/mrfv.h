@@ -220,7 +220,7 @@ int mrfv_fused_stage(mrfv_ctx *ctx, int32_t stage, const double *dt_dev, void *U
  * of workgroups looping over the leaves; shapes_host[3v+2] is the number of wavefronts
  * per SIMD the register allocation aims at (1: the compiler's choice).  Every variant
  * gives bitwise the same result.  rhs_variant sets the variant
- * when set >= 0 (captured stage graphs are re-captured), writes the number of variants
+ * when set >= 0 (captured step graphs are re-captured), writes the number of variants
  * and their shapes (each may be NULL) and returns the current variant (>= 0) or an
  * error.  Host only. */
 int mrfv_rhs_variant(mrfv_ctx *ctx, int32_t set, int32_t *n_variants_host, int32_t *shapes_host);

@@ -545,10 +545,11 @@ int do_stages(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt) {
     return MRFV_OK;
 }
 
-// hipGraph of the CFL step and the three RK stages (batched FP32 path, batched == 2): the
-// kernels read their work lists through the device descriptors, so one capture serves
-// every later tree.  Captured on the library's own stream, launched on the caller's.
-// Which launches a captured stage graph contains: the finest level present, whether
+// hipGraph of a step (batched FP32 path, batched == 2): the gate, the CFL step, the three
+// RK stages and, for adaptive contexts, the adaptation up to the flags.  The kernels read
+// their work lists through the gated device descriptors, so one capture serves every
+// later tree.  Captured on the library's own stream, launched on the caller's.
+// Which launches a captured step graph contains: the finest level present, whether
 // resolution jumps exist, and which per-level lists are non-empty.  Counts and list
 // contents are read on the device, so one graph serves every tree with the same key.
 GraphKey graph_key(const mrfv_ctx *ctx) {

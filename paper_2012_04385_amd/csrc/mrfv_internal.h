@@ -261,7 +261,7 @@ struct mrfv_ctx {
     double *d_det4 = nullptr;          // [cap][details_slabs()] slab maxima of the details
     int8_t *d_flags = nullptr;         // [cap]
     int32_t *d_desc = nullptr;         // [N_DESC][2] list descriptors (graph launches)
-    hipStream_t gstream = nullptr;     // capture stream of the stage graph
+    hipStream_t gstream = nullptr;     // capture stream of the step graphs
     hipGraphExec_t graph = nullptr;    // graph being instantiated
     std::map<GraphKey, hipGraphExec_t> graphs;   // step graphs (gate, CFL, three RK stages,
                                                  // adaptation up to the flags) by graph key,
@@ -304,7 +304,7 @@ struct mrfv_ctx {
     int lists_cap = 0;
     // kernel timing
     bool has_jumps = false;            // some leaf has a non-leaf same-level face neighbour
-    bool capturing = false;            // recording the stage graph
+    bool capturing = false;            // recording a step graph
     bool timing = false;
     std::vector<hipEvent_t> ev_free;   // event pool
     std::vector<hipEvent_t> ev_pairs;  // recorded (start, stop) pairs not yet read

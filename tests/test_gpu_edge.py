@@ -2,7 +2,7 @@
 
 * Free stream: a uniform state on a tree with 1- and 2-level resolution jumps, periodic
   and zero-gradient, with and without adaptation, stays bitwise uniform on the FP32
-  batched (stage graph) and FP64 plain paths: every face sees a constant stencil (the
+  batched (step graph) and FP64 plain paths: every face sees a constant stencil (the
   WENO5 form returns its centre exactly), restriction and prediction reproduce constants
   exactly, and the increment-form update adds an exact zero.
 * A single level-0 block on a periodic box is its own neighbour across every face
