@@ -561,9 +561,16 @@ void k_rhs_update(int stage, const double *__restrict__ dt,
     // uniform-base loads of face_flux_at; the faces 0-2 and 14-16 follow
     constexpr int NF_IN = NI - 5, NF_OUT = NI + 1 - NF_IN;
     constexpr int NFX_IN = GP * NI * NF_IN;
-    __shared__ T Fx[GP][NI][NI + 1][5];   // [plane][y][face x][q]
-    __shared__ T Fy[GP][NI + 1][NI][5];   // [plane][face y][x][q]
-    __shared__ T Fz[GP + 1][NI][NI][5];   // [face plane][y][x][q]; plane j = face k0 + j - 1/2
+    // Groups are pipelined: while the column owners update group g from one buffer, all
+    // wavefronts compute the faces of group g + 1 into the other, taking 64-face chunks
+    // from an LDS counter (owners join after their update); one barrier per group.
+    // z-face planes live in a ring of 2 GP + 1 slots (face plane kf in slot kf mod NZR):
+    // the planes of group g (k0 .. k0 + GP) and those group g + 1 adds never share a slot.
+    constexpr int NZR = 2 * GP + 1;
+    __shared__ T Fx[2][GP][NI][NI + 1][5];   // [buffer][plane][y][face x][q]
+    __shared__ T Fy[2][GP][NI + 1][NI][5];   // [buffer][plane][face y][x][q]
+    __shared__ T Fz[NZR][NI][NI][5];         // [face plane mod NZR][y][x][q]
+    __shared__ int next_chunk[2];            // per buffer: first face not yet handed out
     // one workgroup per leaf (graph launches size the grid by the slot capacity and
     // surplus groups exit here), or, persistent, a fixed grid looping over the leaves
     const int nleaf = wl.count();
@@ -685,14 +692,23 @@ void k_rhs_update(int stage, const double *__restrict__ dt,
         }
     };
 
-    for (int g = 0; g < NI / GP; ++g) {
+    // faces of group g: x-faces (plane p, row y, face f), y-faces (plane p, face f,
+    // column x), then the z-face planes the group adds (all GP + 1 for the first group)
+    auto group_faces = [&](int g) {
         const int k0 = g * GP;
-        const int first_z = g == 0 ? 0 : 1;     // face planes already known from the last group
-        const int nz = (GP + 1 - first_z) * NFZ;
-        const int total = 2 * NFX + nz;
-        for (int t = tid; t < total; t += TPB_F) {
+        const int first_z = g == 0 ? 0 : 1;
+        const int total = 2 * NFX + (GP + 1 - first_z) * NFZ;
+        const int buf = g & 1;
+        const int lane = tid & 63;
+        for (;;) {
+            int c0 = 0;
+            if (lane == 0) c0 = atomicAdd(&next_chunk[buf], 64);
+            c0 = __shfl(c0, 0);
+            if (c0 >= total) break;
+            const int t = c0 + lane;
+            if (t >= total) continue;
             T F[5];
-            if (t < NFX) {                      // x-faces: (plane p, row y, face f)
+            if (t < NFX) {
                 int f, y, p;
                 if (t < NFX_IN) {               // faces 3 .. 13 first: stencils in the interior
                     f = 3 + t % NF_IN;
@@ -707,12 +723,12 @@ void k_rhs_update(int stage, const double *__restrict__ dt,
                 const int base = ((k0 + p + HW) * NP + y + HW) * NP + f + 1;
                 face_flux_at<T, 0>(ub, nlo[0], nhi[0], ns, base, f + 1, G, F);
 #pragma unroll
-                for (int q = 0; q < 5; ++q) Fx[p][y][f][q] = F[q];
+                for (int q = 0; q < 5; ++q) Fx[buf][p][y][f][q] = F[q];
                 if (f == 0 || f == NI) {
 #pragma unroll
                     for (int q = 0; q < 5; ++q) ffs[((f ? 1 : 0) * 5 + q) * FACE + (k0 + p) * NI + y] = F[q];
                 }
-            } else if (t < 2 * NFX) {           // y-faces: (plane p, face f, column x)
+            } else if (t < 2 * NFX) {
                 const int u = t - NFX;
                 int x, f, p;
                 if (u < NFX_IN) {
@@ -728,45 +744,51 @@ void k_rhs_update(int stage, const double *__restrict__ dt,
                 const int base = ((k0 + p + HW) * NP + f + 1) * NP + x + HW;
                 face_flux_at<T, 1>(ub, nlo[1], nhi[1], ns, base, f + 1, G, F);
 #pragma unroll
-                for (int q = 0; q < 5; ++q) Fy[p][f][x][q] = F[q];
+                for (int q = 0; q < 5; ++q) Fy[buf][p][f][x][q] = F[q];
                 if (f == 0 || f == NI) {
 #pragma unroll
                     for (int q = 0; q < 5; ++q) ffs[((2 + (f ? 1 : 0)) * 5 + q) * FACE + (k0 + p) * NI + x] = F[q];
                 }
-            } else {                            // z-faces: (face plane j, y, x)
+            } else {
                 const int u = t - 2 * NFX;
                 const int x = u % NI, y = (u / NI) % NI, j = u / NFZ + first_z;
                 const int kf = k0 + j;          // face between interior planes kf-1 and kf
                 const int base = ((kf + 1) * NP + y + HW) * NP + x + HW;   // padded z = kf+1 .. kf+6
                 face_flux_at<T, 2>(ub, nlo[2], nhi[2], ns, base, kf + 1, G, F);
 #pragma unroll
-                for (int q = 0; q < 5; ++q) Fz[j][y][x][q] = F[q];
+                for (int q = 0; q < 5; ++q) Fz[kf % NZR][y][x][q] = F[q];
                 if (kf == 0 || kf == NI) {
 #pragma unroll
                     for (int q = 0; q < 5; ++q) ffs[((4 + (kf ? 1 : 0)) * 5 + q) * FACE + y * NI + x] = F[q];
                 }
             }
         }
-        __syncthreads();
-        if (owner) {
-            T D[GP][5];
+    };
+    auto group_update = [&](int g) {
+        const int k0 = g * GP, buf = g & 1;
+        T D[GP][5];
 #pragma unroll
-            for (int p = 0; p < GP; ++p)
+        for (int p = 0; p < GP; ++p)
 #pragma unroll
-                for (int q = 0; q < 5; ++q) {
-                    const T dxq = Fx[p][cy][cx + 1][q] - Fx[p][cy][cx][q];
-                    const T dyq = Fy[p][cy + 1][cx][q] - Fy[p][cy][cx][q];
-                    const T dzq = Fz[p + 1][cy][cx][q] - Fz[p][cy][cx][q];
-                    D[p][q] = (dxq + dyq) + dzq;
-                }
-            update_group(k0, D);
-        }
-        __syncthreads();
-        // the last face plane of this group is the first one of the next
-        for (int t = tid; t < NFZ * 5; t += TPB_F) {
-            const int q = t % 5, x = (t / 5) % NI, y = t / (5 * NI);
-            Fz[0][y][x][q] = Fz[GP][y][x][q];
-        }
+            for (int q = 0; q < 5; ++q) {
+                const T dxq = Fx[buf][p][cy][cx + 1][q] - Fx[buf][p][cy][cx][q];
+                const T dyq = Fy[buf][p][cy + 1][cx][q] - Fy[buf][p][cy][cx][q];
+                const T dzq = Fz[(k0 + p + 1) % NZR][cy][cx][q] - Fz[(k0 + p) % NZR][cy][cx][q];
+                D[p][q] = (dxq + dyq) + dzq;
+            }
+        update_group(k0, D);
+    };
+
+    if (tid < 2) next_chunk[tid] = 0;
+    __syncthreads();
+    // iteration g: update group g (g >= 0) and compute the faces of group g + 1
+#pragma unroll 1
+    for (int g = -1; g < NI / GP; ++g) {
+        if (g >= 0 && owner) group_update(g);
+        if (g + 1 < NI / GP) group_faces(g + 1);
+        // group g's counter is free again (its faces were done before the last barrier);
+        // group g + 2 takes it after the next one
+        if (g >= 0 && tid == 0) next_chunk[g & 1] = 0;
         __syncthreads();
     }
     if (!ok) atomicOr(err, 1);
