@@ -136,6 +136,16 @@ def run_mode(pb, steps: int, mode: int, mlp=None, variant=None):
     return out
 
 
+def tuned_variant(pb, warm: int = 3) -> int:
+    """Launch shape of the fused kernel the autotuner picks on this workload."""
+    g = Solver([pb], dtype="f32", batched=2).init()
+    for _ in range(warm):
+        g.step()
+    choice, _ = g.autotune(reps=2)
+    del g
+    return choice
+
+
 def gain_test(steps: int = 100, epochs: int = 30, variant=None, log=print):
     import torch
     t0 = time.perf_counter()
@@ -156,6 +166,9 @@ def gain_test(steps: int = 100, epochs: int = 30, variant=None, log=print):
     del X
     torch.cuda.empty_cache()
     pb = W.shock_blobs_mr6(steps=steps)
+    if variant is None:
+        variant = tuned_variant(pb)
+    log(f"[proposer] fused-kernel launch shape {variant} (autotuned) for all modes")
     res = {}
     for name, mode, net in (("off", 0, None), ("persistence", 2, None), ("network", 1, mlp)):
         log(f"[proposer] {pb.name}, {steps} steps, proposer {name}")
@@ -165,7 +178,8 @@ def gain_test(steps: int = 100, epochs: int = 30, variant=None, log=print):
     same = len({r["digest"] for r in res.values()}) == 1
     gain = (res["network"]["ms_per_step"] < res["off"]["ms_per_step"] and
             res["network"]["ms_per_step"] < res["persistence"]["ms_per_step"])
-    return {"workload": pb.name, "steps": steps, "training": {"sources": info, "loss_before": l0,
+    return {"workload": pb.name, "steps": steps, "variant": variant,
+            "training": {"sources": info, "loss_before": l0,
             "loss_after": l1, "train_accuracy": train_acc, "epochs": epochs,
             "keep_bias_shift": shift, "train_change_classes": tr_prec},
             "runs": res, "bitwise_identical": same, "network_gain": gain}
