@@ -94,11 +94,12 @@ int upload_tables(mrfv_ctx *ctx) {
 // table, grid bounded by the capacity, so the graph stays valid when the tree changes
 // as long as the same lists are empty (the graph's key, graph_key); lists empty at
 // capture are left out of the graph.
-WorkList wlist(const mrfv_ctx *ctx, int which, int grid_cap = 2048) {
+WorkList wlist(const mrfv_ctx *ctx, int which, int grid_cap = 2048, bool gated = true) {
     WorkList w;
     w.base = ctx->tb.lists;
     if (ctx->capturing) {
-        w.desc = ctx->d_desc_g + 2 * which;   // as gated by the graph's first kernel
+        // as gated by the graph's CFL reduction (see do_stages), or as uploaded
+        w.desc = (gated ? ctx->d_desc_g : ctx->d_desc) + 2 * which;
         const std::vector<int32_t> &d = ctx->lists.desc;
         if (2 * which + 1 >= (int)d.size() || d[2 * which + 1] == 0) return w;   // grid 0: skipped
         // bound: the most blocks the list can ever hold (per level: every instance full)
@@ -467,7 +468,7 @@ int do_init(mrfv_ctx *ctx, mrfv_ic_fn ic, void *user, T *U) {
     }
     CALL(upload_tables(ctx));
     CALL(impose_ic<T>(ctx, ic, user, U, fresh));
-    std::vector<double> det(ctx->cfg.slot_capacity), det4((size_t)ctx->cfg.slot_capacity * details_slabs());
+    std::vector<double> det(ctx->cfg.slot_capacity), det4((size_t)ctx->cfg.slot_capacity * details_parts());
     for (int m = 1; m <= maxl; ++m) {
         std::vector<int> parents;
         for (int s : tp.alive_sorted()) {
@@ -488,7 +489,7 @@ int do_init(mrfv_ctx *ctx, mrfv_ic_fn ic, void *user, T *U) {
             wf.n = (int32_t)fresh.size();
             wf.grid = wf.n;
             HIP_OK(launch_details<T>(U, wf, ctx->tb, ctx->d_inst, ctx->d_det4, ctx->stream));
-            const int nz = details_slabs();
+            const int nz = details_parts();
             HIP_OK(hipMemcpyAsync(det4.data(), ctx->d_det4, sizeof(double) * det4.size(),
                                   hipMemcpyDeviceToHost, ctx->stream));
             HIP_OK(hipStreamSynchronize(ctx->stream));
@@ -515,8 +516,17 @@ int do_init(mrfv_ctx *ctx, mrfv_ic_fn ic, void *user, T *U) {
 // CFL step and the three RK stages.
 template <typename T>
 int do_stages(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt) {
-    HIP_OK(launch_cfl<T>(U, wlist(ctx, DESC_LEAVES), ctx->tb, ctx->d_inst, (int)ctx->inst.size(),
-                         ctx->d_blockred, dt, ctx->stream));
+    if (ctx->capturing) {
+        // a step graph: the CFL step reads the ungated leaf list, and its per-instance
+        // reduction gates the lists of every later kernel (a speculative step whose tree
+        // was changed meanwhile computes a time step that the relaunched step replaces)
+        HIP_OK(launch_cfl<T>(U, wlist(ctx, DESC_LEAVES, 2048, false), ctx->tb, ctx->d_inst,
+                             (int)ctx->inst.size(), ctx->d_blockred, dt, ctx->stream, ctx->d_gate,
+                             ctx->d_desc, ctx->d_desc_g, N_DESC));
+    } else {
+        HIP_OK(launch_cfl<T>(U, wlist(ctx, DESC_LEAVES), ctx->tb, ctx->d_inst, (int)ctx->inst.size(),
+                             ctx->d_blockred, dt, ctx->stream));
+    }
     if (ctx->cfg.batched && sizeof(T) == 4) {
         // fused stages, out of place through two more state buffers: U -> W -> W2 -> U;
         // parents are restricted and filled only if some leaf face reads them.  Stages
@@ -545,9 +555,9 @@ int do_stages(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt) {
     return MRFV_OK;
 }
 
-// hipGraph of a step (batched FP32 path, batched == 2): the gate, the CFL step, the three
-// RK stages and, for adaptive contexts, the adaptation up to the flags.  The kernels read
-// their work lists through the gated device descriptors, so one capture serves every
+// hipGraph of a step (batched FP32 path, batched == 2): the CFL step with the gate, the
+// three RK stages and, for adaptive contexts, the adaptation up to the flags.  The kernels
+// read their work lists through the gated device descriptors, so one capture serves every
 // later tree.  Captured on the library's own stream, launched on the caller's.
 // Which launches a captured step graph contains: the finest level present, whether
 // resolution jumps exist, and which per-level lists are non-empty.  Counts and list
@@ -587,9 +597,7 @@ int run_step_graph(mrfv_ctx *ctx, float *U, float *U0, double *dt, bool adapt) {
         hipError_t e = hipStreamBeginCapture(ctx->gstream, hipStreamCaptureModeThreadLocal);
         int rc = MRFV_EHIP;
         if (e == hipSuccess) {
-            rc = launch_gate(ctx->d_gate, ctx->d_desc, ctx->d_desc_g, N_DESC, ctx->stream) == hipSuccess
-                     ? MRFV_OK : MRFV_EHIP;
-            if (rc == MRFV_OK) rc = do_stages<float>(ctx, U, U0, nullptr, dt);
+            rc = do_stages<float>(ctx, U, U0, nullptr, dt);
             if (rc == MRFV_OK && adapt) rc = do_adapt_device<float>(ctx, U, true);
         }
         hipGraph_t g = nullptr;
@@ -616,8 +624,8 @@ int run_step_graph(mrfv_ctx *ctx, float *U, float *U0, double *dt, bool adapt) {
 }
 
 // Device part of a step: stages and, for adaptive contexts, the restriction, fills,
-// details and flags.  The batched FP32 path replays all of it as one graph whose first
-// kernel gates the work lists (see k_gate); *half receives the half of the host flag
+// details and flags.  The batched FP32 path replays all of it as one graph whose CFL
+// reduction gates the work lists (see k_cfl_inst); *half receives the half of the host flag
 // buffers the flags go to.
 template <typename T>
 int launch_step(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt, bool adapt, int *half) {
@@ -897,9 +905,9 @@ int mrfv_create(mrfv_ctx **out, const mrfv_config *cfg, const mrfv_instance *ins
     std::fill(ctx->h_flags, ctx->h_flags + 2 * cap, (int8_t)0);
     ctx->h_err[0] = ctx->h_err[1] = 0;
     ALLOC(ctx->d_FF, cap * 6 * 5 * FACE * es);
-    ALLOC(ctx->d_blockred, cap * 5 * sizeof(double));
+    ALLOC(ctx->d_blockred, cap * std::max(5, 3 * cfl_slabs()) * sizeof(double));
     ALLOC(ctx->d_det, cap * sizeof(double));
-    ALLOC(ctx->d_det4, cap * details_slabs() * sizeof(double));
+    ALLOC(ctx->d_det4, cap * details_parts() * sizeof(double));
     ALLOC(ctx->d_flags, cap);
     ALLOC(ctx->d_slots, cap * sizeof(int32_t));
     ALLOC(ctx->d_slots2, cap * sizeof(int32_t));

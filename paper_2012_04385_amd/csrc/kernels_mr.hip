@@ -148,8 +148,12 @@ __global__ __launch_bounds__(TPB) void k_fill_halos(T *__restrict__ U, WorkList 
     __shared__ T Y[PR_Y];
     const int nb = wl.count();
     const int tid = threadIdx.x;
-    for (int b = blockIdx.x; b < nb; b += gridDim.x) {
-        const int slot = wl.at(b);
+    // blocks in XCD-aware order, as in k_details
+    for (int base = 0; base < nb; base += gridDim.x) {
+        const int m_round = min(nb - base, (int)gridDim.x);
+        const int bi = xcd_item(blockIdx.x, gridDim.x, m_round);
+        if (bi >= m_round) continue;   // uniform per workgroup
+        const int slot = wl.at(base + bi);
         const BlockMeta m = meta[slot];
         const Region g = make_region(mode, blockIdx.y, m.zg);
         const bool clamped = g.clamp[0] >= 0 || g.clamp[1] >= 0 || g.clamp[2] >= 0;
@@ -332,7 +336,13 @@ __global__ __launch_bounds__(DTPB) void k_details(const T *__restrict__ U, WorkL
     const int xi = tid % NP, xr = tid / NP;     // y pass: cell i, first row (16 rows apart)
     const int pi = tid % NPAIR, pr = tid / NPAIR;   // x pass: pair, first row (32 rows apart)
     const int rx = xi < HW ? 0 : (xi < HW + NI ? 1 : 2);
-    for (int b = blockIdx.x; b < nb; b += gridDim.x) {
+    // blocks in XCD-aware order (gridDim.x is a multiple of 8, so the XCD of a workgroup
+    // depends on blockIdx.x alone): list neighbours and siblings share an L2
+    for (int base = 0; base < nb; base += gridDim.x) {
+    const int m_round = min(nb - base, (int)gridDim.x);
+    const int bi = xcd_item(blockIdx.x, gridDim.x, m_round);
+    if (bi >= m_round) continue;   // uniform per workgroup
+    const int b = base + bi;
     const int slot = wl.at(b);
     const BlockMeta m = meta[slot];
     const InstDev P = inst[m.inst];
@@ -497,45 +507,34 @@ __global__ __launch_bounds__(TPB) void k_flags(WorkList wl,
     }
 }
 
-// First kernel of a step graph: the work-list descriptors the step's kernels read,
-// copied from desc, with every count zero when the previous step's flags changed the
-// tree (gate[0]): a step launched before the host has seen those flags then does
-// nothing.  Clears gate[0] and flips the launch parity gate[1].
-__global__ __launch_bounds__(TPB) void k_gate(int32_t *__restrict__ gate,
-                                              const int32_t *__restrict__ desc,
-                                              int32_t *__restrict__ desc_g, int n_desc) {
-    __shared__ int32_t changed;
-    if (threadIdx.x == 0) changed = gate[0];
-    __syncthreads();
-    for (int i = threadIdx.x; i < n_desc; i += TPB) {
-        desc_g[2 * i] = desc[2 * i];
-        desc_g[2 * i + 1] = changed ? 0 : desc[2 * i + 1];
-    }
-    if (threadIdx.x == 0) {
-        gate[0] = 0;
-        gate[1] ^= 1;
-    }
-}
-
-// Per-block maxima of |v_d| + c over the interior, FP64.
+// Per-block maxima of |v_d| + c over the interior, FP64, per z-slab of CZ (workgroup y):
+// bmax[slot][slab][d].
+constexpr int CZ = 4;
 template <typename T>
 __global__ __launch_bounds__(TPB) void k_cfl_block(const T *__restrict__ U, WorkList wl,
                                                    const BlockMeta *__restrict__ meta,
                                                    const InstDev *__restrict__ inst,
                                                    double *__restrict__ bmax) {
+    constexpr int NC = CELLS_I / CZ / TPB;   // cells per thread (4)
     __shared__ double red[3][TPB / 64];
     const int nb = wl.count();
+    const int part = blockIdx.y;
     for (int b = blockIdx.x; b < nb; b += gridDim.x) {
     const int slot = wl.at(b);
     const InstDev P = inst[meta[slot].inst];
     const T *u = U + (size_t)slot * 5 * CELLS_P;
     double mx[3] = {0.0, 0.0, 0.0};
-    // unrolled so that several cells' loads are in flight at once
-#pragma unroll 4
-    for (int c = threadIdx.x; c < CELLS_I; c += TPB) {
+    T v[NC][5];
+#pragma unroll
+    for (int n = 0; n < NC; ++n) {
+        const int c = part * (CELLS_I / CZ) + n * TPB + threadIdx.x;
         const int o = pidx(0, HW + c / FACE, HW + (c / NI) % NI, HW + c % NI);
-        const double r = u[o], m0 = u[o + CELLS_P], m1 = u[o + 2 * CELLS_P],
-                     m2 = u[o + 3 * CELLS_P], E = u[o + 4 * CELLS_P];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) v[n][q] = u[o + q * CELLS_P];
+    }
+#pragma unroll
+    for (int n = 0; n < NC; ++n) {
+        const double r = v[n][0], m0 = v[n][1], m1 = v[n][2], m2 = v[n][3], E = v[n][4];
         const double ir = 1.0 / r;
         const double p = (P.gamma - 1.0) * (E - 0.5 * (m0 * m0 + m1 * m1 + m2 * m2) * ir) -
                          P.gamma * P.B;
@@ -552,40 +551,69 @@ __global__ __launch_bounds__(TPB) void k_cfl_block(const T *__restrict__ U, Work
     }
     __syncthreads();
     if (threadIdx.x < 3) {
-        double v = red[threadIdx.x][0];
-        for (int w = 1; w < TPB / 64; ++w) v = fmax(v, red[threadIdx.x][w]);
-        bmax[(size_t)slot * 5 + threadIdx.x] = v;
+        double m = red[threadIdx.x][0];
+        for (int w = 1; w < TPB / 64; ++w) m = fmax(m, red[threadIdx.x][w]);
+        bmax[((size_t)slot * CZ + part) * 3 + threadIdx.x] = m;
     }
     __syncthreads();
     }
 }
 
 // One workgroup per instance over that instance's contiguous range of the leaf list.
+// With gate words (step graphs), workgroup 0 also gates the work-list descriptors that
+// the step's later kernels read: desc_g = desc, with every count zero when the previous
+// step's flags changed the tree (gate[0]), so that a step launched before the host has
+// seen those flags does nothing; it clears gate[0] and flips the launch parity gate[1].
+// The CFL launches themselves read the ungated leaf list.
 __global__ __launch_bounds__(TPB) void k_cfl_inst(const int32_t *__restrict__ list,
                                                   const int32_t *__restrict__ off,
                                                   const int32_t *__restrict__ cnt,
                                                   const InstDev *__restrict__ inst,
                                                   const double *__restrict__ bmax,
-                                                  double *__restrict__ dt) {
-    __shared__ double red[3][TPB];
+                                                  double *__restrict__ dt,
+                                                  int32_t *__restrict__ gate,
+                                                  const int32_t *__restrict__ desc,
+                                                  int32_t *__restrict__ desc_g, int n_desc) {
+    __shared__ double red[3][TPB / 64];
+    __shared__ int32_t changed;
     const int ins = blockIdx.x;
-    double mx[3] = {0.0, 0.0, 0.0};
-    for (int t = threadIdx.x; t < cnt[ins]; t += TPB) {
-        const int slot = list[off[ins] + t];
-        for (int a = 0; a < 3; ++a) mx[a] = fmax(mx[a], bmax[(size_t)slot * 5 + a]);
-    }
-    for (int a = 0; a < 3; ++a) red[a][threadIdx.x] = mx[a];
-    __syncthreads();
-    for (int w = TPB / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w)
-            for (int a = 0; a < 3; ++a)
-                red[a][threadIdx.x] = fmax(red[a][threadIdx.x], red[a][threadIdx.x + w]);
+    if (gate && ins == 0) {
+        if (threadIdx.x == 0) changed = gate[0];
         __syncthreads();
+        for (int i = threadIdx.x; i < n_desc; i += TPB) {
+            desc_g[2 * i] = desc[2 * i];
+            desc_g[2 * i + 1] = changed ? 0 : desc[2 * i + 1];
+        }
+        if (threadIdx.x == 0) {
+            gate[0] = 0;
+            gate[1] ^= 1;
+        }
     }
+    double mx[3] = {0.0, 0.0, 0.0};
+    const int n = cnt[ins] * CZ;
+    const int32_t *l = list + off[ins];
+    for (int t = threadIdx.x; t < n; t += TPB) {
+        const double *m = bmax + ((size_t)l[t / CZ] * CZ + t % CZ) * 3;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) mx[a] = fmax(mx[a], m[a]);
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        for (int o = 32; o > 0; o >>= 1) mx[a] = fmax(mx[a], __shfl_xor(mx[a], o));
+        if ((threadIdx.x & 63) == 0) red[a][threadIdx.x >> 6] = mx[a];
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
+        double s = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            double m = red[a][0];
+            for (int w = 1; w < TPB / 64; ++w) m = fmax(m, red[a][w]);
+            s += m;
+        }
         const InstDev P = inst[ins];
         const double dx = ldexp(P.dx0, -P.lmax);
-        dt[ins] = P.cfl * dx / (red[0][0] + red[1][0] + red[2][0]);
+        if (n > 0) dt[ins] = P.cfl * dx / s;
     }
 }
 
@@ -658,7 +686,7 @@ template <typename T>
 hipError_t launch_fill_halos(T *U, const WorkList &wl, const DevTables &tb, FillMode mode,
                              hipStream_t st) {
     if (wl.grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fill_halos<T>, grid2(wl.grid, (mode & FILL_FACES) ? 6 : 26), dim3(TPB), 0,
+    hipLaunchKernelGGL(k_fill_halos<T>, grid2(round_xcd(wl.grid), (mode & FILL_FACES) ? 6 : 26), dim3(TPB), 0,
                        st, U, wl, tb.meta, tb.nbr, (int)mode);
     return hipGetLastError();
 }
@@ -685,12 +713,12 @@ template <typename T>
 hipError_t launch_details(const T *U, const WorkList &wl, const DevTables &tb,
                           const InstDev *inst, double *det4, hipStream_t st) {
     if (wl.grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_details<T>, grid2(wl.grid, DZ), dim3(DTPB), 0, st, U, wl, tb.meta, tb.nbr,
-                       inst, det4);
+    hipLaunchKernelGGL(k_details<T>, grid2(round_xcd(wl.grid), DZ), dim3(DTPB), 0, st, U, wl,
+                       tb.meta, tb.nbr, inst, det4);
     return hipGetLastError();
 }
 
-int details_slabs() { return DZ; }
+int details_parts() { return DZ; }
 
 hipError_t launch_flags(const WorkList &wl, const DevTables &tb, const InstDev *inst,
                         const double *det4, double *det, int8_t *flags, int8_t *flags_host,
@@ -702,24 +730,23 @@ hipError_t launch_flags(const WorkList &wl, const DevTables &tb, const InstDev *
     return hipGetLastError();
 }
 
-hipError_t launch_gate(int32_t *gate, const int32_t *desc, int32_t *desc_g, int n_desc,
-                       hipStream_t st) {
-    hipLaunchKernelGGL(k_gate, dim3(1), dim3(TPB), 0, st, gate, desc, desc_g, n_desc);
-    return hipGetLastError();
-}
 
 template <typename T>
 hipError_t launch_cfl(const T *U, const WorkList &leaves, const DevTables &tb,
                       const InstDev *inst, int n_inst, double *blockmax, double *dt,
-                      hipStream_t st) {
-    if (leaves.grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_cfl_block<T>, dim3(leaves.grid), dim3(TPB), 0, st, U, leaves, tb.meta,
-                       inst, blockmax);
+                      hipStream_t st, int32_t *gate, const int32_t *desc, int32_t *desc_g,
+                      int n_desc) {
+    if (leaves.grid <= 0 && !gate) return hipSuccess;
+    if (leaves.grid > 0)
+        hipLaunchKernelGGL(k_cfl_block<T>, grid2(leaves.grid, CZ), dim3(TPB), 0, st, U, leaves,
+                           tb.meta, inst, blockmax);
     // per-instance leaf ranges: the lists array starts with [offsets, counts]
     hipLaunchKernelGGL(k_cfl_inst, dim3(n_inst), dim3(TPB), 0, st, tb.lists, tb.lists,
-                       tb.lists + n_inst, inst, blockmax, dt);
+                       tb.lists + n_inst, inst, blockmax, dt, gate, desc, desc_g, n_desc);
     return hipGetLastError();
 }
+
+int cfl_slabs() { return CZ; }
 
 template <typename T>
 hipError_t launch_totals(const T *U, const WorkList &leaves, const DevTables &tb,
@@ -744,7 +771,8 @@ hipError_t launch_totals(const T *U, const WorkList &leaves, const DevTables &tb
     template hipError_t launch_details<T>(const T *, const WorkList &, const DevTables &,   \
                                           const InstDev *, double *, hipStream_t);          \
     template hipError_t launch_cfl<T>(const T *, const WorkList &, const DevTables &,       \
-                                      const InstDev *, int, double *, double *, hipStream_t); \
+                                      const InstDev *, int, double *, double *, hipStream_t, \
+                                      int32_t *, const int32_t *, int32_t *, int);          \
     template hipError_t launch_totals<T>(const T *, const WorkList &, const DevTables &,    \
                                          const InstDev *, int, double *, double *, hipStream_t);
 MRFV_INST(float)

@@ -87,7 +87,9 @@ __device__ __forceinline__ void derive_state(const Gas<T> &G, CellState<T> &s) {
 // alpha_k = d_k / (eps + beta_k)^2 is normalised with one reciprocal: the common factor
 // prod_j (eps + beta_j)^2 (13/12)^-2 cancels, so the value is
 //   c + sum_k d_k r_k prod_{j != k} e_j^2 / (6 sum_k d_k prod_{j != k} e_j^2)
-// with e_k = 12/13 eps + t_k^2 + 3/13 s_k^2.  A constant stencil returns c exactly.
+// with e_k = 12/13 eps + t_k^2 + 3/13 s_k^2; with 10 d = (1, 6, 3) and the 6 taken into the
+// numerator, the terms are (r0 / 6, r1, r2 / 2) over (1, 6, 3).  A constant stencil
+// returns c exactly.
 template <typename T>
 __device__ __forceinline__ T weno5(T a, T b, T c, T d, T e) {
     const T w0 = b - a, u = c - b, v = d - c, w3 = e - d;
@@ -100,10 +102,11 @@ __device__ __forceinline__ T weno5(T a, T b, T c, T d, T e) {
     const T e2 = fma(t2, t2, fma(s2 * k, s2, eps));
     const T E0 = e0 * e0, E1 = e1 * e1, E2 = e2 * e2;
     const T E12 = E1 * E2, E02 = E0 * E2, E01 = E0 * E1;
-    // d_k r_k and 6 d_k scaled by 10: (1, 6, 3) r_k and (6, 36, 18)
-    const T r0 = fma((T)5, u, (T)-2 * w0), r1 = fma((T)6, u, (T)12 * v), r2 = fma((T)12, v, (T)-3 * w3);
-    const T num = fma(E12, r0, fma(E02, r1, E01 * r2));
-    const T den = fma(E12, (T)6, fma(E02, (T)36, E01 * (T)18));
+    const T h0 = fma((T)(5.0 / 6.0), u, (T)(-1.0 / 3.0) * w0);   // r0 / 6
+    const T h1 = fma((T)2, v, u);                                  // r1
+    const T h2 = fma((T)2, v, (T)-0.5 * w3);                       // r2 / 2
+    const T num = fma(E12, h0, fma(E02, h1, E01 * h2));
+    const T den = fma((T)6, E02, fma((T)3, E01, E12));
     return fma(num, rcp_(den), c);
 }
 
@@ -138,13 +141,10 @@ __device__ __forceinline__ T char_flux_uniform(const T W[6], const T G[6], T lL,
     const bool dn = lL < (T)0 && lR < (T)0;
     const bool llf = !(up || dn);
     if (!__any(llf)) {
-        // the stencil in upwind order, blended with 0/1 weights (exact for finite values):
-        // a select here is turned into a dynamically indexed array by the compiler
-        const T su = up ? (T)1 : (T)0, sd = (T)1 - su;
-        T a[5];
-#pragma unroll
-        for (int j = 0; j < 5; ++j) a[j] = fma(su, G[j], sd * G[5 - j]);
-        return weno5(a[0], a[1], a[2], a[3], a[4]);
+        // the stencil in upwind order, selected per lane from scalar copies (a select
+        // between elements of G itself becomes a dynamically indexed array)
+        const T g0 = G[0], g1 = G[1], g2 = G[2], g3 = G[3], g4 = G[4], g5 = G[5];
+        return weno5(up ? g0 : g5, up ? g1 : g4, up ? g2 : g3, up ? g3 : g2, up ? g4 : g1);
     }
     const T ha = (T)0.5 * fmax(fabs(lL), fabs(lR));
     const T cp = up ? (T)1 : (dn ? (T)0 : (T)0.5);
@@ -519,10 +519,12 @@ __device__ __forceinline__ void face_flux_at(const T *__restrict__ ub, const T *
 #pragma unroll
             for (int j = 0; j < 6; ++j) load(j, ns.own + (unsigned)(base + j * stride) * (unsigned)sizeof(T));
         } else {
+            // selects of values, not of members (a member select keeps ns in scratch)
+            const unsigned olo = ns.lo[D], ohi = ns.hi[D], oown = ns.own;
 #pragma unroll
             for (int j = 0; j < 6; ++j) {
                 const int pos = pos0 + j;
-                const unsigned src = pos < HW ? ns.lo[D] : (pos >= HW + NI ? ns.hi[D] : ns.own);
+                const unsigned src = pos < HW ? olo : (pos >= HW + NI ? ohi : oown);
                 load(j, src + (unsigned)(base + j * stride) * (unsigned)sizeof(T));
             }
         }
@@ -571,8 +573,8 @@ void k_rhs_update(int stage, const double *__restrict__ dt,
     __shared__ T Fy[2][GP][NI + 1][NI][5];   // [buffer][plane][face y][x][q]
     __shared__ T Fz[NZR][NI][NI][5];         // [face plane mod NZR][y][x][q]
     __shared__ int next_chunk[2];            // per buffer: first face not yet handed out
-    // one workgroup per leaf (graph launches size the grid by the slot capacity and
-    // surplus groups exit here), or, persistent, a fixed grid looping over the leaves
+    // one workgroup per leaf in XCD-aware order (graph launches size the grid by the slot
+    // capacity and surplus groups exit), or, persistent, a fixed grid looping over the leaves
     const int nleaf = wl.count();
     auto block = [&](int b) __attribute__((always_inline)) {
     const int slot = wl.at(b);
@@ -795,8 +797,10 @@ void k_rhs_update(int stage, const double *__restrict__ dt,
     };
     if constexpr (PERSIST) {
         for (int b = blockIdx.x; b < nleaf; b += gridDim.x) block(b);   // uniform per workgroup
-    } else if (blockIdx.x < nleaf) {
-        block(blockIdx.x);   // the loop-free form keeps the register count down
+    } else {
+        // the grid covers every leaf; the loop-free form keeps the register count down
+        const int b = xcd_item(blockIdx.x, gridDim.x, nleaf);
+        if (b < nleaf) block(b);
     }
 }
 
@@ -900,7 +904,7 @@ static void launch_variant(int stage, const double *dt, const float *Uin, float 
     constexpr int G = RHS_GP[V], B = RHS_TPB[V];
     constexpr bool PS = RHS_PERSIST[V];
     constexpr int WP = RHS_WPE[V];
-    const int grid = PS ? std::min(wl.grid, persist_grid(B)) : wl.grid;
+    const int grid = PS ? std::min(wl.grid, persist_grid(B)) : round_xcd(wl.grid);
     hipLaunchKernelGGL((k_rhs_update<float, G, B, PS, WP>), dim3(grid), dim3(B), 0, st, stage, dt, Uin,
                        Uout, U0, wl, tb.meta, tb.nbr, inst, FF, err, restrict_parents);
 }

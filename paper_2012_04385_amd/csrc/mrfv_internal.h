@@ -57,6 +57,20 @@ struct WorkList {
     __device__ __forceinline__ int32_t at(int i) const { return base[(desc ? desc[0] : off) + i]; }
 };
 
+// XCD-aware item order for a one-dimensional grid of `total` workgroups handling `m` <= total
+// items: the chip hands workgroup w to XCD w mod 8, so item order x * ceil(m / 8) + w / 8 gives
+// each XCD one contiguous range of the list (Morton-ordered blocks: spatial neighbours and
+// siblings share an L2).  Returns m for workgroups without an item.  A total that is not a
+// multiple of 8 keeps the identity order (the covering argument needs total >= 8 ceil(m / 8)).
+constexpr int N_XCD = 8;
+__device__ __forceinline__ int xcd_item(int w, int total, int m) {
+    if (total % N_XCD) return w < m ? w : m;
+    const int per = (m + N_XCD - 1) / N_XCD, l = w / N_XCD;
+    const int i = (w % N_XCD) * per + l;
+    return l < per && i < m ? i : m;
+}
+inline int round_xcd(int grid) { return (grid + N_XCD - 1) / N_XCD * N_XCD; }
+
 // Work lists, concatenated in DevTables::lists (host copy).  The array starts with the
 // per-instance leaf ranges: data[i] = offset (into data) of instance i's leaves,
 // data[n_inst + i] = their count; the instance ranges are contiguous parts of the
@@ -175,7 +189,7 @@ hipError_t launch_predict(T *U, const int32_t *list, int n, const DevTables &tb,
 template <typename T>
 hipError_t launch_details(const T *U, const WorkList &wl, const DevTables &tb,
                           const InstDev *inst, double *det4, hipStream_t st);
-int details_slabs();   // slab maxima per block in det4
+int details_parts();   // detail maxima per block in det4 (one per slab)
 // flags (and det of blocks on level >= 1) from the slab maxima; flags_host / err_host
 // (may be null): host-memory copies of the flags and of the error word err; gate (may be
 // null; graph launches): {tree changed, launch parity}: the host copies go to the half
@@ -184,13 +198,14 @@ hipError_t launch_flags(const WorkList &wl, const DevTables &tb, const InstDev *
                         const double *det4, double *det, int8_t *flags, int8_t *flags_host,
                         const int32_t *err, int32_t *err_host, int32_t *gate, int cap,
                         hipStream_t st);
-// first launch of a step graph: desc_g = desc, counts zeroed when gate[0] is set
-hipError_t launch_gate(int32_t *gate, const int32_t *desc, int32_t *desc_g, int n_desc,
-                       hipStream_t st);
+// per-block maxima, then dt per instance; with gate words (step graphs) the second launch
+// also writes desc_g = desc, counts zeroed when gate[0] is set
 template <typename T>
 hipError_t launch_cfl(const T *U, const WorkList &leaves, const DevTables &tb,
                       const InstDev *inst, int n_inst, double *blockmax, double *dt,
-                      hipStream_t st);
+                      hipStream_t st, int32_t *gate = nullptr, const int32_t *desc = nullptr,
+                      int32_t *desc_g = nullptr, int n_desc = 0);
+int cfl_slabs();      // z-slab maxima per block in the CFL reduction
 template <typename T>
 hipError_t launch_totals(const T *U, const WorkList &leaves, const DevTables &tb,
                          const InstDev *inst, int n_inst, double *blocksum, double *tot,
@@ -258,7 +273,7 @@ struct mrfv_ctx {
     void *d_FF = nullptr;              // boundary face fluxes [cap][6][5][16][16]
     double *d_blockred = nullptr;      // [cap][5] per-block partial reductions
     double *d_det = nullptr;           // [cap]
-    double *d_det4 = nullptr;          // [cap][details_slabs()] slab maxima of the details
+    double *d_det4 = nullptr;          // [cap][details_parts()] slab maxima of the details
     int8_t *d_flags = nullptr;         // [cap]
     int32_t *d_desc = nullptr;         // [N_DESC][2] list descriptors (graph launches)
     hipStream_t gstream = nullptr;     // capture stream of the step graphs
