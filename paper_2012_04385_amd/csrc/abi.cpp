@@ -245,14 +245,14 @@ int do_update(mrfv_ctx *ctx, int stage, const double *dt, T *U, T *U0, const T *
 // One stage of the batched path: fused rhs + update over all leaves, then the jump
 // correction on the updated state.
 int do_stage_fused(mrfv_ctx *ctx, int stage, const double *dt, const float *Uin, float *Uout,
-                   float *U0, bool restrict_parents = false) {
+                   float *U0, bool restrict_parents = false, double *cflmax = nullptr) {
     const HostLists &L = ctx->lists;
     float *FF = (float *)ctx->d_FF;
     hipEvent_t ev{};
     timing_begin(ctx, &ev);
     // the fused kernel has no grid-stride loop: its grid must cover every possible leaf
     HIP_OK(launch_rhs_update_f32(ctx->rhs_variant, stage, dt, Uin, Uout, U0, wlist(ctx, DESC_LEAVES, 1 << 30), ctx->tb,
-                                 ctx->d_inst, FF, ctx->d_err, restrict_parents ? 1 : 0, ctx->stream));
+                                 ctx->d_inst, FF, ctx->d_err, restrict_parents ? 1 : 0, cflmax, ctx->stream));
     timing_end(ctx, ev, (int64_t)L.all_leaves_cnt * CELLS_I);
     if (ctx->has_jumps) {
         for (int l = levels_to_cover(ctx) - 1; l >= 0; --l)
@@ -519,10 +519,14 @@ int do_stages(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt) {
     if (ctx->capturing) {
         // a step graph: the CFL step reads the ungated leaf list, and its per-instance
         // reduction gates the lists of every later kernel (a speculative step whose tree
-        // was changed meanwhile computes a time step that the relaunched step replaces)
-        HIP_OK(launch_cfl<T>(U, wlist(ctx, DESC_LEAVES, 2048, false), ctx->tb, ctx->d_inst,
-                             (int)ctx->inst.size(), ctx->d_blockred, dt, ctx->stream, ctx->d_gate,
-                             ctx->d_desc, ctx->d_desc_g, N_DESC));
+        // was changed meanwhile computes a time step that the relaunched step replaces).
+        // After a step on the same jump-free tree the block maxima are already there: that
+        // step's last stage wrote them from its new state (leaf interiors do not change
+        // after it).
+        WorkList lv = wlist(ctx, DESC_LEAVES, 2048, false);
+        if (ctx->cfl_from_stage) lv.grid = 0;
+        HIP_OK(launch_cfl<T>(U, lv, ctx->tb, ctx->d_inst, (int)ctx->inst.size(), ctx->d_blockred,
+                             dt, ctx->stream, ctx->d_gate, ctx->d_desc, ctx->d_desc_g, N_DESC));
     } else {
         HIP_OK(launch_cfl<T>(U, wlist(ctx, DESC_LEAVES), ctx->tb, ctx->d_inst, (int)ctx->inst.size(),
                              ctx->d_blockred, dt, ctx->stream));
@@ -542,7 +546,11 @@ int do_stages(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt) {
             float *in = buf[s], *out = buf[s + 1];
             if (par) CALL(do_project<float>(ctx, in, true, false, s > 0));
             CALL(do_fill<float>(ctx, in, 1 << 20, FILL_MISSING_FACES, par));
-            CALL(do_stage_fused(ctx, s, dt, in, out, (float *)U0, s < 2 ? par : adapt));
+            // a step graph's last stage on a jump-free tree writes the block maxima of the
+            // signal speeds for the next step's CFL pass (with jumps the correction changes
+            // leaf cells after the stage)
+            double *cflmax = ctx->capturing && s == 2 && !ctx->has_jumps ? ctx->d_blockred : nullptr;
+            CALL(do_stage_fused(ctx, s, dt, in, out, (float *)U0, s < 2 ? par : adapt, cflmax));
         }
         return MRFV_OK;
     }
@@ -565,7 +573,7 @@ int do_stages(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt) {
 GraphKey graph_key(const mrfv_ctx *ctx) {
     const HostLists &L = ctx->lists;
     uint64_t k = (uint64_t)L.max_level | ((uint64_t)ctx->has_jumps << 4) |
-                 ((uint64_t)L.parents_needed << 63);
+                 ((uint64_t)L.parents_needed << 63) | ((uint64_t)ctx->cfl_from_stage << 62);
     uint64_t k2 = 0;
     for (int l = 0; l <= L.max_level && l < MAX_LEVELS; ++l) {
         if (L.desc[2 * desc_par(l) + 1] > 0) k |= 1ull << (5 + l);
@@ -801,9 +809,15 @@ int do_run(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt, int n, int64_t *cells)
     int rc = MRFV_OK;
     int half[2] = {0, 0};
     int64_t step_cells[2] = {0, 0};
+    // whether the last launch's final stage wrote the CFL block maxima of its new state on
+    // the current tree (the first launch of a call never uses them: the caller owns U)
+    bool stage_maxima = false;
     auto launch = [&](int k) {
         step_cells[k & 1] = leaf_cells();   // the tree this launch integrates
+        ctx->cfl_from_stage = stage_maxima;
         int r = launch_step<T>(ctx, U, U0, Lb, dt, true, &half[k & 1]);
+        ctx->cfl_from_stage = false;
+        stage_maxima = r == MRFV_OK && !ctx->has_jumps;
         if (r == MRFV_OK && hipEventRecord(ev[k & 1], ctx->stream) != hipSuccess)
             r = fail(ctx, MRFV_EHIP, "hipEventRecord failed");
         return r;
@@ -823,6 +837,7 @@ int do_run(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt, int n, int64_t *cells)
         bool changed = false;
         *cells += step_cells[k & 1];
         if ((rc = finish_step<T>(ctx, U, half[k & 1], false, none, &changed)) != MRFV_OK) break;
+        if (changed) stage_maxima = false;   // new leaves, and step k+1 (if queued) was void
         if (changed && k + 1 < n) {
             // the speculative step k+1 was gated (it changed nothing): run it on the new tree
             if (hipMemsetAsync(ctx->d_gate, 0, sizeof(int32_t), ctx->stream) != hipSuccess) {
@@ -1254,11 +1269,11 @@ int mrfv_autotune(mrfv_ctx *ctx, void *U, void *U0, double *dt_dev, int32_t reps
     float best_ms = 0.f;
     for (int v = 0; v < rhs_variants(); ++v) {
         HIP_OK(launch_rhs_update_f32(v, 0, dt_dev, X, W, (float *)U0, wl, ctx->tb, ctx->d_inst,
-                                     (float *)ctx->d_FF, ctx->d_err, 0, st));
+                                     (float *)ctx->d_FF, ctx->d_err, 0, nullptr, st));
         HIP_OK(hipEventRecord(a, st));
         for (int r = 0; r < reps; ++r)
             HIP_OK(launch_rhs_update_f32(v, 0, dt_dev, X, W, (float *)U0, wl, ctx->tb, ctx->d_inst,
-                                         (float *)ctx->d_FF, ctx->d_err, 0, st));
+                                         (float *)ctx->d_FF, ctx->d_err, 0, nullptr, st));
         HIP_OK(hipEventRecord(b, st));
         HIP_OK(hipEventSynchronize(b));
         float ms = 0.f;

@@ -509,7 +509,7 @@ __global__ __launch_bounds__(TPB) void k_flags(WorkList wl,
 
 // Per-block maxima of |v_d| + c over the interior, FP64, per z-slab of CZ (workgroup y):
 // bmax[slot][slab][d].
-constexpr int CZ = 4;
+constexpr int CZ = CFL_SLABS;
 template <typename T>
 __global__ __launch_bounds__(TPB) void k_cfl_block(const T *__restrict__ U, WorkList wl,
                                                    const BlockMeta *__restrict__ meta,
@@ -534,14 +534,10 @@ __global__ __launch_bounds__(TPB) void k_cfl_block(const T *__restrict__ U, Work
     }
 #pragma unroll
     for (int n = 0; n < NC; ++n) {
-        const double r = v[n][0], m0 = v[n][1], m1 = v[n][2], m2 = v[n][3], E = v[n][4];
-        const double ir = 1.0 / r;
-        const double p = (P.gamma - 1.0) * (E - 0.5 * (m0 * m0 + m1 * m1 + m2 * m2) * ir) -
-                         P.gamma * P.B;
-        const double cs = sqrt(P.gamma * (p + P.B) * ir);
-        mx[0] = fmax(mx[0], fabs(m0 * ir) + cs);
-        mx[1] = fmax(mx[1], fabs(m1 * ir) + cs);
-        mx[2] = fmax(mx[2], fabs(m2 * ir) + cs);
+        double sp[3];
+        cfl_speeds(v[n][0], v[n][1], v[n][2], v[n][3], v[n][4], P.gamma, P.B, sp);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) mx[a] = fmax(mx[a], sp[a]);
     }
     // maxima over the wavefront, then over the workgroup's waves
 #pragma unroll
@@ -592,7 +588,8 @@ __global__ __launch_bounds__(TPB) void k_cfl_inst(const int32_t *__restrict__ li
     double mx[3] = {0.0, 0.0, 0.0};
     const int n = cnt[ins] * CZ;
     const int32_t *l = list + off[ins];
-    for (int t = threadIdx.x; t < n; t += TPB) {
+#pragma unroll 4
+    for (int t = threadIdx.x; t < n; t += TPB) {   // unrolled: several load chains in flight
         const double *m = bmax + ((size_t)l[t / CZ] * CZ + t % CZ) * 3;
 #pragma unroll
         for (int a = 0; a < 3; ++a) mx[a] = fmax(mx[a], m[a]);

@@ -556,7 +556,8 @@ void k_rhs_update(int stage, const double *__restrict__ dt,
                                                       const BlockMeta *__restrict__ meta,
                                                       const int32_t *__restrict__ nbr,
                                                       const InstDev *__restrict__ inst, T *FF,
-                                                      int32_t *err, int restrict_parents) {
+                                                      int32_t *err, int restrict_parents,
+                                                      double *__restrict__ cflmax) {
     constexpr int NFX = GP * NI * (NI + 1);   // x-faces per group (y-faces alike)
     // x- and y-faces are numbered with the faces 3 .. 13 of each row first: their
     // six-cell stencils lie in the own interior, so whole wavefronts of them take the
@@ -573,6 +574,7 @@ void k_rhs_update(int stage, const double *__restrict__ dt,
     __shared__ T Fy[2][GP][NI + 1][NI][5];   // [buffer][plane][face y][x][q]
     __shared__ T Fz[NZR][NI][NI][5];         // [face plane mod NZR][y][x][q]
     __shared__ int next_chunk[2];            // per buffer: first face not yet handed out
+    __shared__ double cfl_acc[3][FACE];      // with cflmax: per owner column, the speed maxima
     // one workgroup per leaf in XCD-aware order (graph launches size the grid by the slot
     // capacity and surplus groups exit), or, persistent, a fixed grid looping over the leaves
     const int nleaf = wl.count();
@@ -673,6 +675,12 @@ void k_rhs_update(int stage, const double *__restrict__ dt,
                 unew[p][q] = un[q];
             }
             ok = ok && physical_state(un, G);
+            if (cflmax) {   // uniform: the last stage of a step, for the next step's CFL
+                double sp[3];
+                cfl_speeds(un[0], un[1], un[2], un[3], un[4], P.gamma, P.B, sp);
+#pragma unroll
+                for (int d = 0; d < 3; ++d) cfl_acc[d][tid] = fmax(cfl_acc[d][tid], sp[d]);
+            }
         }
         if (rp) {
             if constexpr (GP == 1) {
@@ -782,6 +790,9 @@ void k_rhs_update(int stage, const double *__restrict__ dt,
     };
 
     if (tid < 2) next_chunk[tid] = 0;
+    if (cflmax && owner)
+#pragma unroll
+        for (int d = 0; d < 3; ++d) cfl_acc[d][tid] = 0.0;
     __syncthreads();
     // iteration g: update group g (g >= 0) and compute the faces of group g + 1
 #pragma unroll 1
@@ -794,6 +805,31 @@ void k_rhs_update(int stage, const double *__restrict__ dt,
         __syncthreads();
     }
     if (!ok) atomicOr(err, 1);
+    if (cflmax) {
+        // block maxima of the signal speeds (the CFL pass's values, stored as the first slab's
+        // maxima, the other slabs zero): over each owner wavefront, then over the four
+        double m[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            m[d] = owner ? cfl_acc[d][tid] : 0.0;
+            for (int off = 32; off > 0; off >>= 1) m[d] = fmax(m[d], __shfl_xor(m[d], off));
+        }
+        __syncthreads();
+        if (owner && (tid & 63) == 0)
+#pragma unroll
+            for (int d = 0; d < 3; ++d) cfl_acc[d][tid >> 6] = m[d];
+        __syncthreads();
+        if (tid < 3) {
+            double v = cfl_acc[tid][0];
+#pragma unroll
+            for (int w = 1; w < FACE / 64; ++w) v = fmax(v, cfl_acc[tid][w]);
+            double *bm = cflmax + (size_t)slot * CFL_SLABS * 3;
+            bm[tid] = v;
+#pragma unroll
+            for (int k = 1; k < CFL_SLABS; ++k) bm[k * 3 + tid] = 0.0;
+        }
+        __syncthreads();   // cfl_acc is cleared again for a persistent grid's next block
+    }
     };
     if constexpr (PERSIST) {
         for (int b = blockIdx.x; b < nleaf; b += gridDim.x) block(b);   // uniform per workgroup
@@ -900,13 +936,13 @@ constexpr int persist_grid(int tpb) { return 256 * (12 / (tpb / 64) > 0 ? 12 / (
 template <int V>
 static void launch_variant(int stage, const double *dt, const float *Uin, float *Uout, float *U0,
                     const WorkList &wl, const DevTables &tb, const InstDev *inst, float *FF,
-                    int32_t *err, int restrict_parents, hipStream_t st) {
+                    int32_t *err, int restrict_parents, double *cflmax, hipStream_t st) {
     constexpr int G = RHS_GP[V], B = RHS_TPB[V];
     constexpr bool PS = RHS_PERSIST[V];
     constexpr int WP = RHS_WPE[V];
     const int grid = PS ? std::min(wl.grid, persist_grid(B)) : round_xcd(wl.grid);
     hipLaunchKernelGGL((k_rhs_update<float, G, B, PS, WP>), dim3(grid), dim3(B), 0, st, stage, dt, Uin,
-                       Uout, U0, wl, tb.meta, tb.nbr, inst, FF, err, restrict_parents);
+                       Uout, U0, wl, tb.meta, tb.nbr, inst, FF, err, restrict_parents, cflmax);
 }
 
 int rhs_variants() { return N_RHS_VARIANTS; }
@@ -920,23 +956,23 @@ void rhs_variant_shape(int v, int *gp, int *tpb, int *wpe) {
 hipError_t launch_rhs_update_f32(int variant, int stage, const double *dt, const float *Uin,
                                  float *Uout, float *U0, const WorkList &wl, const DevTables &tb,
                                  const InstDev *inst, float *FF, int32_t *err, int restrict_parents,
-                                 hipStream_t st) {
+                                 double *cflmax, hipStream_t st) {
     if (wl.grid <= 0) return hipSuccess;
     if (Uin == Uout) return hipErrorInvalidValue;   // neighbours' interiors are read
     switch (variant) {
-        case 0: launch_variant<0>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, st); break;
-        case 1: launch_variant<1>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, st); break;
-        case 2: launch_variant<2>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, st); break;
-        case 3: launch_variant<3>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, st); break;
-        case 4: launch_variant<4>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, st); break;
-        case 5: launch_variant<5>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, st); break;
-        case 6: launch_variant<6>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, st); break;
-        case 7: launch_variant<7>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, st); break;
-        case 8: launch_variant<8>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, st); break;
-        case 9: launch_variant<9>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, st); break;
-        case 10: launch_variant<10>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, st); break;
-        case 11: launch_variant<11>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, st); break;
-        case 12: launch_variant<12>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, st); break;
+        case 0: launch_variant<0>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, cflmax, st); break;
+        case 1: launch_variant<1>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, cflmax, st); break;
+        case 2: launch_variant<2>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, cflmax, st); break;
+        case 3: launch_variant<3>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, cflmax, st); break;
+        case 4: launch_variant<4>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, cflmax, st); break;
+        case 5: launch_variant<5>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, cflmax, st); break;
+        case 6: launch_variant<6>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, cflmax, st); break;
+        case 7: launch_variant<7>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, cflmax, st); break;
+        case 8: launch_variant<8>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, cflmax, st); break;
+        case 9: launch_variant<9>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, cflmax, st); break;
+        case 10: launch_variant<10>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, cflmax, st); break;
+        case 11: launch_variant<11>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, cflmax, st); break;
+        case 12: launch_variant<12>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, cflmax, st); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -71,6 +71,21 @@ __device__ __forceinline__ int xcd_item(int w, int total, int m) {
 }
 inline int round_xcd(int grid) { return (grid + N_XCD - 1) / N_XCD * N_XCD; }
 
+// Signal speeds |v_d| + c, d = 0, 1, 2, of one cell for the CFL condition, FP64 with explicit
+// fused multiply-adds, so that every kernel evaluating it (the CFL pass, the last stage of
+// a step) rounds alike and their block maxima agree bitwise.
+__device__ __forceinline__ void cfl_speeds(double r, double m0, double m1, double m2, double E,
+                                           double gamma, double B, double s[3]) {
+    const double ir = 1.0 / r;
+    const double k2 = fma(m2, m2, fma(m1, m1, m0 * m0));
+    const double p = fma(gamma - 1.0, fma(-0.5 * k2, ir, E), -gamma * B);
+    const double cs = sqrt(gamma * (p + B) * ir);
+    s[0] = fma(fabs(m0), ir, cs);
+    s[1] = fma(fabs(m1), ir, cs);
+    s[2] = fma(fabs(m2), ir, cs);
+}
+constexpr int CFL_SLABS = 4;   // per-block CFL maxima: [slot][CFL_SLABS][3]
+
 // Work lists, concatenated in DevTables::lists (host copy).  The array starts with the
 // per-instance leaf ranges: data[i] = offset (into data) of instance i's leaves,
 // data[n_inst + i] = their count; the instance ranges are contiguous parts of the
@@ -234,7 +249,7 @@ hipError_t launch_update(int stage, const double *dt, T *U, T *U0, const T *L,
 hipError_t launch_rhs_update_f32(int variant, int stage, const double *dt, const float *Uin,
                                  float *Uout, float *U0, const WorkList &leaves, const DevTables &tb,
                                  const InstDev *inst, float *FF, int32_t *err, int restrict_parents,
-                                 hipStream_t st);
+                                 double *cflmax, hipStream_t st);   // cflmax: null, or CFL block maxima out
 int rhs_variants();
 void rhs_variant_shape(int v, int *gp, int *tpb, int *wpe);
 template <typename T>
@@ -320,6 +335,9 @@ struct mrfv_ctx {
     // kernel timing
     bool has_jumps = false;            // some leaf has a non-leaf same-level face neighbour
     bool capturing = false;            // recording a step graph
+    // step graphs: the CFL pass takes the block maxima the previous step's last stage wrote
+    // (set by mrfv_run for a step that follows a step on the same jump-free tree)
+    bool cfl_from_stage = false;
     bool timing = false;
     std::vector<hipEvent_t> ev_free;   // event pool
     std::vector<hipEvent_t> ev_pairs;  // recorded (start, stop) pairs not yet read
