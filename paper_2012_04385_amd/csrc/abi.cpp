@@ -537,14 +537,17 @@ int do_stages(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt) {
         // whose output is restricted next (W and W2 when stages read parents, U before
         // the details) write the restriction of jump-free leaves into their parents, so
         // those restriction passes recompute only the other octants.  U comes from the
-        // caller, who may have written it: the first stage restricts in full.
+        // caller, who may have written it: the first stage restricts in full, except in a
+        // step graph after a step on the same tree (the last stage of an adaptive step
+        // restricts, and nothing changes leaf interiors after it).
         float *buf[4] = {(float *)U, (float *)ctx->d_W, (float *)ctx->d_W2, (float *)U};
         const bool par = ctx->lists.parents_needed;
         bool adapt = false;
         for (const auto &p : ctx->inst) adapt = adapt || (p.adapt && p.lmax > 0);
         for (int s = 0; s < 3; ++s) {
             float *in = buf[s], *out = buf[s + 1];
-            if (par) CALL(do_project<float>(ctx, in, true, false, s > 0));
+            const bool skip = s > 0 || (ctx->capturing && ctx->restrict_from_stage);
+            if (par) CALL(do_project<float>(ctx, in, true, false, skip));
             CALL(do_fill<float>(ctx, in, 1 << 20, FILL_MISSING_FACES, par));
             // a step graph's last stage on a jump-free tree writes the block maxima of the
             // signal speeds for the next step's CFL pass (with jumps the correction changes
@@ -573,7 +576,8 @@ int do_stages(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt) {
 GraphKey graph_key(const mrfv_ctx *ctx) {
     const HostLists &L = ctx->lists;
     uint64_t k = (uint64_t)L.max_level | ((uint64_t)ctx->has_jumps << 4) |
-                 ((uint64_t)L.parents_needed << 63) | ((uint64_t)ctx->cfl_from_stage << 62);
+                 ((uint64_t)L.parents_needed << 63) | ((uint64_t)ctx->cfl_from_stage << 62) |
+                 ((uint64_t)ctx->restrict_from_stage << 61);
     uint64_t k2 = 0;
     for (int l = 0; l <= L.max_level && l < MAX_LEVELS; ++l) {
         if (L.desc[2 * desc_par(l) + 1] > 0) k |= 1ull << (5 + l);
@@ -811,13 +815,16 @@ int do_run(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt, int n, int64_t *cells)
     int64_t step_cells[2] = {0, 0};
     // whether the last launch's final stage wrote the CFL block maxima of its new state on
     // the current tree (the first launch of a call never uses them: the caller owns U)
-    bool stage_maxima = false;
+    // and whether it restricted its leaves into their parents (every launch here adapts)
+    bool stage_maxima = false, stage_restricted = false;
     auto launch = [&](int k) {
         step_cells[k & 1] = leaf_cells();   // the tree this launch integrates
         ctx->cfl_from_stage = stage_maxima;
+        ctx->restrict_from_stage = stage_restricted;
         int r = launch_step<T>(ctx, U, U0, Lb, dt, true, &half[k & 1]);
-        ctx->cfl_from_stage = false;
+        ctx->cfl_from_stage = ctx->restrict_from_stage = false;
         stage_maxima = r == MRFV_OK && !ctx->has_jumps;
+        stage_restricted = r == MRFV_OK;
         if (r == MRFV_OK && hipEventRecord(ev[k & 1], ctx->stream) != hipSuccess)
             r = fail(ctx, MRFV_EHIP, "hipEventRecord failed");
         return r;
@@ -837,7 +844,7 @@ int do_run(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt, int n, int64_t *cells)
         bool changed = false;
         *cells += step_cells[k & 1];
         if ((rc = finish_step<T>(ctx, U, half[k & 1], false, none, &changed)) != MRFV_OK) break;
-        if (changed) stage_maxima = false;   // new leaves, and step k+1 (if queued) was void
+        if (changed) stage_maxima = stage_restricted = false;   // new leaves; step k+1 (if queued) was void
         if (changed && k + 1 < n) {
             // the speculative step k+1 was gated (it changed nothing): run it on the new tree
             if (hipMemsetAsync(ctx->d_gate, 0, sizeof(int32_t), ctx->stream) != hipSuccess) {

@@ -193,14 +193,31 @@ __global__ __launch_bounds__(TPB) void k_fill_halos(T *__restrict__ U, WorkList 
         }
         const T *pu = U + (size_t)m.parent * 5 * CELLS_P;
         const Div dp0(np[0]), dp1(np[1]), dm0(me[0]), dm1(me[1]);
+        // the parent region of component qi is loaded into registers while component
+        // qi - 1 runs its passes (at most PR_A / TPB values per thread)
+        constexpr int NAT = (PR_A + TPB - 1) / TPB;
+        const int na = np[0] * np[1] * np[2];
+        int aoff[NAT];
+#pragma unroll
+        for (int n = 0; n < NAT; ++n) {
+            const int t = tid + n * TPB;
+            const int t1 = dp0.quot(t), kk = dp1.quot(t1);
+            const int ii = t - t1 * np[0], jj = t1 - kk * np[1];
+            aoff[n] = pidx(0, p0[2] + kk, p0[1] + jj, p0[0] + ii);
+        }
+        T av[NAT];
+        auto load_a = [&](int q) {
+#pragma unroll
+            for (int n = 0; n < NAT; ++n)
+                if (tid + n * TPB < na) av[n] = pu[q * CELLS_P + aoff[n]];
+        };
+        load_a(0);
         for (int qi = 0; qi < nq; ++qi) {
             const int q = re ? 4 * qi : qi;
-            const int na = np[0] * np[1] * np[2];
-            for (int t = tid; t < na; t += TPB) {
-                const int t1 = dp0.quot(t), kk = dp1.quot(t1);
-                const int ii = t - t1 * np[0], jj = t1 - kk * np[1];
-                A[t] = pu[pidx(q, p0[2] + kk, p0[1] + jj, p0[0] + ii)];
-            }
+#pragma unroll
+            for (int n = 0; n < NAT; ++n)
+                if (tid + n * TPB < na) A[tid + n * TPB] = av[n];
+            if (qi + 1 < nq) load_a(re ? 4 * (qi + 1) : qi + 1);
             __syncthreads();
             const int nx = np[2] * np[1] * me[0];
             for (int t = tid; t < nx; t += TPB) {
@@ -508,7 +525,7 @@ __global__ __launch_bounds__(TPB) void k_flags(WorkList wl,
 }
 
 // Per-block maxima of |v_d| + c over the interior, FP64, per z-slab of CZ (workgroup y):
-// bmax[slot][slab][d].
+// bmax[b][slab][d] by position b in the leaf list (instance ranges are contiguous there).
 constexpr int CZ = CFL_SLABS;
 template <typename T>
 __global__ __launch_bounds__(TPB) void k_cfl_block(const T *__restrict__ U, WorkList wl,
@@ -549,34 +566,36 @@ __global__ __launch_bounds__(TPB) void k_cfl_block(const T *__restrict__ U, Work
     if (threadIdx.x < 3) {
         double m = red[threadIdx.x][0];
         for (int w = 1; w < TPB / 64; ++w) m = fmax(m, red[threadIdx.x][w]);
-        bmax[((size_t)slot * CZ + part) * 3 + threadIdx.x] = m;
+        bmax[((size_t)b * CZ + part) * 3 + threadIdx.x] = m;
     }
     __syncthreads();
     }
 }
 
-// One workgroup per instance over that instance's contiguous range of the leaf list.
+// One workgroup per instance over that instance's contiguous range of the leaf list (and so
+// of the block maxima, stored by list position: leaves_off is the list's start in `list`).
 // With gate words (step graphs), workgroup 0 also gates the work-list descriptors that
 // the step's later kernels read: desc_g = desc, with every count zero when the previous
 // step's flags changed the tree (gate[0]), so that a step launched before the host has
 // seen those flags does nothing; it clears gate[0] and flips the launch parity gate[1].
 // The CFL launches themselves read the ungated leaf list.
-__global__ __launch_bounds__(TPB) void k_cfl_inst(const int32_t *__restrict__ list,
-                                                  const int32_t *__restrict__ off,
-                                                  const int32_t *__restrict__ cnt,
-                                                  const InstDev *__restrict__ inst,
-                                                  const double *__restrict__ bmax,
-                                                  double *__restrict__ dt,
-                                                  int32_t *__restrict__ gate,
-                                                  const int32_t *__restrict__ desc,
-                                                  int32_t *__restrict__ desc_g, int n_desc) {
-    __shared__ double red[3][TPB / 64];
+constexpr int CTPB = 1024;   // threads of the per-instance reduction
+__global__ __launch_bounds__(CTPB) void k_cfl_inst(WorkList leaves,
+                                                   const int32_t *__restrict__ off,
+                                                   const int32_t *__restrict__ cnt,
+                                                   const InstDev *__restrict__ inst,
+                                                   const double *__restrict__ bmax,
+                                                   double *__restrict__ dt,
+                                                   int32_t *__restrict__ gate,
+                                                   const int32_t *__restrict__ desc,
+                                                   int32_t *__restrict__ desc_g, int n_desc) {
+    __shared__ double red[3][CTPB / 64];
     __shared__ int32_t changed;
     const int ins = blockIdx.x;
     if (gate && ins == 0) {
         if (threadIdx.x == 0) changed = gate[0];
         __syncthreads();
-        for (int i = threadIdx.x; i < n_desc; i += TPB) {
+        for (int i = threadIdx.x; i < n_desc; i += CTPB) {
             desc_g[2 * i] = desc[2 * i];
             desc_g[2 * i + 1] = changed ? 0 : desc[2 * i + 1];
         }
@@ -587,13 +606,11 @@ __global__ __launch_bounds__(TPB) void k_cfl_inst(const int32_t *__restrict__ li
     }
     double mx[3] = {0.0, 0.0, 0.0};
     const int n = cnt[ins] * CZ;
-    const int32_t *l = list + off[ins];
+    const double *bm = bmax + (size_t)(off[ins] - (leaves.desc ? leaves.desc[0] : leaves.off)) * CZ * 3;
 #pragma unroll 4
-    for (int t = threadIdx.x; t < n; t += TPB) {   // unrolled: several load chains in flight
-        const double *m = bmax + ((size_t)l[t / CZ] * CZ + t % CZ) * 3;
+    for (int t = threadIdx.x; t < n; t += CTPB)
 #pragma unroll
-        for (int a = 0; a < 3; ++a) mx[a] = fmax(mx[a], m[a]);
-    }
+        for (int a = 0; a < 3; ++a) mx[a] = fmax(mx[a], bm[(size_t)t * 3 + a]);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         for (int o = 32; o > 0; o >>= 1) mx[a] = fmax(mx[a], __shfl_xor(mx[a], o));
@@ -605,7 +622,7 @@ __global__ __launch_bounds__(TPB) void k_cfl_inst(const int32_t *__restrict__ li
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             double m = red[a][0];
-            for (int w = 1; w < TPB / 64; ++w) m = fmax(m, red[a][w]);
+            for (int w = 1; w < CTPB / 64; ++w) m = fmax(m, red[a][w]);
             s += m;
         }
         const InstDev P = inst[ins];
@@ -738,7 +755,7 @@ hipError_t launch_cfl(const T *U, const WorkList &leaves, const DevTables &tb,
         hipLaunchKernelGGL(k_cfl_block<T>, grid2(leaves.grid, CZ), dim3(TPB), 0, st, U, leaves,
                            tb.meta, inst, blockmax);
     // per-instance leaf ranges: the lists array starts with [offsets, counts]
-    hipLaunchKernelGGL(k_cfl_inst, dim3(n_inst), dim3(TPB), 0, st, tb.lists, tb.lists,
+    hipLaunchKernelGGL(k_cfl_inst, dim3(n_inst), dim3(CTPB), 0, st, leaves, tb.lists,
                        tb.lists + n_inst, inst, blockmax, dt, gate, desc, desc_g, n_desc);
     return hipGetLastError();
 }

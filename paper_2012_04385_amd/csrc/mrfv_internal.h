@@ -338,6 +338,9 @@ struct mrfv_ctx {
     // step graphs: the CFL pass takes the block maxima the previous step's last stage wrote
     // (set by mrfv_run for a step that follows a step on the same jump-free tree)
     bool cfl_from_stage = false;
+    // step graphs: the first stage's restriction skips the octants the previous step's last
+    // stage restricted (set by mrfv_run for a step that follows a step on the same tree)
+    bool restrict_from_stage = false;
     bool timing = false;
     std::vector<hipEvent_t> ev_free;   // event pool
     std::vector<hipEvent_t> ev_pairs;  // recorded (start, stop) pairs not yet read
