@@ -165,9 +165,13 @@ int mrfv_step(mrfv_ctx *ctx, void *U, void *U0, void *L, double *dt_dev);
 /* run -- n_steps calls of mrfv_step with the same result, bitwise, for callers that do
  * not touch U in between.  On the batched FP32 graph path of an adaptive context without
  * a proposer, step k+1 is queued before the host has read step k's flags; when those
- * flags change the tree, the first kernel of step k+1 finds the change recorded on the
+ * flags change the tree, the CFL reduction of step k+1 finds the change recorded on the
  * device and zeroes that step's work lists (it does nothing), and step k+1 is queued
- * again after the commit.  The device then runs unchanged steps back to back.  Returns
+ * again after the commit.  The device then runs unchanged steps back to back.  A step
+ * that follows a step on the same tree inside the call reuses that step's last stage:
+ * its restriction into the parents (the first stage then restricts only the other
+ * octants) and, on trees without resolution jumps, its per-block CFL maxima (the CFL
+ * pass over the leaves is skipped; the maxima are bitwise those of the pass).  Returns
  * after the last step with nothing left in flight; dt_dev holds the last step's dt.
  * leaf_cells_host (may be NULL): the leaf cells of each step's tree, summed over the
  * steps run (a step integrates each of them three times). */
