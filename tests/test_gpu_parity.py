@@ -275,12 +275,13 @@ def _solver_pair(kind, torch):
     return pb, gs
 
 
-@pytest.mark.parametrize("kind,steps", [("blast", 6), ("adaptive", 3), ("sod", 4)])
+@pytest.mark.parametrize("kind,steps", [("blast", 6), ("adaptive", 3), ("adaptive", 6), ("sod", 4)])
 def test_run_equals_steps(torch_mod, kind, steps):
     """mrfv_run queues step k+1 before it reads step k's flags (and gates it on the device
     when they change the tree): trees, leaf states and the counted leaf cells are those of
     the same number of mrfv_step calls, bitwise, also when the first step coarsens and
-    refines."""
+    refines.  Inside the run, steps on an unchanged tree take the previous step's last-stage
+    restriction (the adaptive tree has jumps) and, without jumps, its CFL maxima (blast)."""
     torch = torch_mod
     pb, (a, b) = _solver_pair(kind, torch)
     leaves0 = {tuple(int(v) for v in r[2:6]) for r in a.blocks() if r[6] == 1}
