@@ -128,9 +128,13 @@ int levels_to_cover(const mrfv_ctx *ctx) {
 template <typename T>
 int do_project(mrfv_ctx *ctx, T *U, bool stage_only = false, bool rho_e_only = false,
                bool skip_srestr = false) {
-    for (int l = levels_to_cover(ctx) - 1; l >= 0; --l)
+    const HostLists &L = ctx->lists;
+    for (int l = levels_to_cover(ctx) - 1; l >= 0; --l) {
+        // a pass that skips the srestr octants has nothing to do when every child is one
+        if (skip_srestr && (stage_only ? L.pproj_srestr[l] : L.par_srestr[l])) continue;
         HIP_OK(launch_project<T>(U, wlist(ctx, stage_only ? desc_pproj(l) : desc_par(l)), ctx->tb,
                                  ctx->stream, rho_e_only ? 0x11 : 0x1f, skip_srestr));
+    }
     return MRFV_OK;
 }
 
@@ -585,6 +589,8 @@ GraphKey graph_key(const mrfv_ctx *ctx) {
         if (L.desc[2 * desc_pfill(l) + 1] > 0) k |= 1ull << (5 + 2 * MAX_LEVELS + l);
         if (L.desc[2 * desc_pproj(l) + 1] > 0) k |= 1ull << (5 + 3 * MAX_LEVELS + l);
         if (L.desc[2 * desc_jleaf26(l) + 1] > 0) k2 |= 1ull << l;   // the adaptation's fill
+        if (L.par_srestr[l]) k2 |= 1ull << (MAX_LEVELS + l);            // restriction passes
+        if (L.pproj_srestr[l]) k2 |= 1ull << (2 * MAX_LEVELS + l);      // left out
     }
     return {k, k2};
 }

@@ -19,7 +19,7 @@ constexpr int CELLS_P = NP * NP * NP;    // 13824
 constexpr int CELLS_I = NI * NI * NI;    // 4096
 constexpr int FACE = NI * NI;            // 256
 
-// Per-slot block description on the device (32 bytes).
+// Per-slot block description on the device (36 bytes).
 struct BlockMeta {
     int32_t inst, level, bx, by, bz;
     int32_t parent;   // parent slot, -1 on level 0
@@ -104,6 +104,9 @@ struct HostLists {
     // some leaf face reads a parent-derived value inside a stage: no same-level neighbour
     // (predicted halo) or a non-leaf same-level neighbour (restricted interior)
     bool parents_needed = false;
+    // per level: every child of every block in the par / pproj list has meta.srestr (a
+    // restriction pass that skips those octants has nothing to do)
+    std::vector<uint8_t> par_srestr, pproj_srestr;
 };
 
 // ---------------------------------------------------------------- host topology ------

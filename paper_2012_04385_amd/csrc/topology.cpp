@@ -264,6 +264,16 @@ void Topology::build(std::vector<BlockMeta> &meta, std::vector<int32_t> &child,
     L.pfill_cnt.assign(maxl + 1, 0);
     L.pproj_off.assign(maxl + 1, 0);
     L.pproj_cnt.assign(maxl + 1, 0);
+    L.par_srestr.assign(maxl + 1, 0);
+    L.pproj_srestr.assign(maxl + 1, 0);
+    auto all_srestr = [&](int off, int cnt) {
+        for (int t = off; t < off + cnt; ++t)
+            for (int o = 0; o < 8; ++o) {
+                const int c = blocks_[L.data[t]].child[o];
+                if (c < 0 || !meta[c].srestr) return false;
+            }
+        return true;
+    };
     // prediction sources of a stage, marked fine to coarse
     std::vector<char> pf(cap, 0);
     auto lacks = [&](int s, bool faces_only) {
@@ -358,6 +368,8 @@ void Topology::build(std::vector<BlockMeta> &meta, std::vector<int32_t> &child,
         for (int s : order)
             if (blocks_[s].level == l && !blocks_[s].leaf && pr[s]) L.data.push_back(s);
         L.pproj_cnt[l] = (int32_t)L.data.size() - L.pproj_off[l];
+        L.par_srestr[l] = all_srestr(L.par_off[l], L.par_cnt[l]);
+        L.pproj_srestr[l] = all_srestr(L.pproj_off[l], L.pproj_cnt[l]);
     }
     L.all_leaves_off = (int32_t)L.data.size();
     for (int i = 0; i < n_inst; ++i) {
