@@ -170,8 +170,8 @@ int mrfv_step(mrfv_ctx *ctx, void *U, void *U0, void *L, double *dt_dev);
  * again after the commit.  The device then runs unchanged steps back to back.  A step
  * that follows a step on the same tree inside the call reuses that step's last stage:
  * its restriction into the parents (the first stage then restricts only the other
- * octants) and, on trees without resolution jumps, its per-block CFL maxima (the CFL
- * pass over the leaves is skipped; the maxima are bitwise those of the pass).  Returns
+ * octants) and its per-block CFL maxima (the CFL pass over the leaves is skipped, except
+ * for the leaves the jump correction changed; the maxima are bitwise those of the pass).  Returns
  * after the last step with nothing left in flight; dt_dev holds the last step's dt.
  * leaf_cells_host (may be NULL): the leaf cells of each step's tree, summed over the
  * steps run (a step integrates each of them three times). */

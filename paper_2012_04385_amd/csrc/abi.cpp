@@ -524,9 +524,9 @@ int do_stages(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt) {
         // a step graph: the CFL step reads the ungated leaf list, and its per-instance
         // reduction gates the lists of every later kernel (a speculative step whose tree
         // was changed meanwhile computes a time step that the relaunched step replaces).
-        // After a step on the same jump-free tree the block maxima are already there: that
-        // step's last stage wrote them from its new state (leaf interiors do not change
-        // after it).
+        // After a step on the same tree the block maxima are already there: that step's last
+        // stage (and, at jumps, a pass after the correction) wrote them from its new state
+        // (leaf interiors do not change after that).
         WorkList lv = wlist(ctx, DESC_LEAVES, 2048, false);
         if (ctx->cfl_from_stage) lv.grid = 0;
         HIP_OK(launch_cfl<T>(U, lv, ctx->tb, ctx->d_inst, (int)ctx->inst.size(), ctx->d_blockred,
@@ -553,11 +553,14 @@ int do_stages(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt) {
             const bool skip = s > 0 || (ctx->capturing && ctx->restrict_from_stage);
             if (par) CALL(do_project<float>(ctx, in, true, false, skip));
             CALL(do_fill<float>(ctx, in, 1 << 20, FILL_MISSING_FACES, par));
-            // a step graph's last stage on a jump-free tree writes the block maxima of the
-            // signal speeds for the next step's CFL pass (with jumps the correction changes
-            // leaf cells after the stage)
-            double *cflmax = ctx->capturing && s == 2 && !ctx->has_jumps ? ctx->d_blockred : nullptr;
+            // a step graph's last stage writes the block maxima of the signal speeds for the
+            // next step's CFL pass; the leaves whose boundary cells the jump correction then
+            // changes get theirs again from the corrected state
+            double *cflmax = ctx->capturing && s == 2 ? ctx->d_blockred : nullptr;
             CALL(do_stage_fused(ctx, s, dt, in, out, (float *)U0, s < 2 ? par : adapt, cflmax));
+            if (cflmax && ctx->has_jumps)
+                HIP_OK(launch_cfl_blocks<float>(out, wlist(ctx, DESC_JCORR), ctx->tb, ctx->d_inst,
+                                                ctx->d_blockred, ctx->stream));
         }
         return MRFV_OK;
     }
@@ -819,8 +822,8 @@ int do_run(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt, int n, int64_t *cells)
     int rc = MRFV_OK;
     int half[2] = {0, 0};
     int64_t step_cells[2] = {0, 0};
-    // whether the last launch's final stage wrote the CFL block maxima of its new state on
-    // the current tree (the first launch of a call never uses them: the caller owns U)
+    // whether the last launch wrote the CFL block maxima of its new state on the current
+    // tree (the first launch of a call never uses them: the caller owns U)
     // and whether it restricted its leaves into their parents (every launch here adapts)
     bool stage_maxima = false, stage_restricted = false;
     auto launch = [&](int k) {
@@ -829,7 +832,7 @@ int do_run(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt, int n, int64_t *cells)
         ctx->restrict_from_stage = stage_restricted;
         int r = launch_step<T>(ctx, U, U0, Lb, dt, true, &half[k & 1]);
         ctx->cfl_from_stage = ctx->restrict_from_stage = false;
-        stage_maxima = r == MRFV_OK && !ctx->has_jumps;
+        stage_maxima = r == MRFV_OK;
         stage_restricted = r == MRFV_OK;
         if (r == MRFV_OK && hipEventRecord(ev[k & 1], ctx->stream) != hipSuccess)
             r = fail(ctx, MRFV_EHIP, "hipEventRecord failed");

@@ -525,7 +525,8 @@ __global__ __launch_bounds__(TPB) void k_flags(WorkList wl,
 }
 
 // Per-block maxima of |v_d| + c over the interior, FP64, per z-slab of CZ (workgroup y):
-// bmax[b][slab][d] by position b in the leaf list (instance ranges are contiguous there).
+// bmax[lpos][slab][d] by the block's position in the all-leaves list (instance ranges are
+// contiguous there); wl may be any list of leaves.
 constexpr int CZ = CFL_SLABS;
 template <typename T>
 __global__ __launch_bounds__(TPB) void k_cfl_block(const T *__restrict__ U, WorkList wl,
@@ -566,7 +567,7 @@ __global__ __launch_bounds__(TPB) void k_cfl_block(const T *__restrict__ U, Work
     if (threadIdx.x < 3) {
         double m = red[threadIdx.x][0];
         for (int w = 1; w < TPB / 64; ++w) m = fmax(m, red[threadIdx.x][w]);
-        bmax[((size_t)b * CZ + part) * 3 + threadIdx.x] = m;
+        bmax[((size_t)meta[slot].lpos * CZ + part) * 3 + threadIdx.x] = m;
     }
     __syncthreads();
     }
@@ -763,6 +764,15 @@ hipError_t launch_cfl(const T *U, const WorkList &leaves, const DevTables &tb,
 int cfl_slabs() { return CZ; }
 
 template <typename T>
+hipError_t launch_cfl_blocks(const T *U, const WorkList &wl, const DevTables &tb,
+                             const InstDev *inst, double *blockmax, hipStream_t st) {
+    if (wl.grid <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cfl_block<T>, grid2(wl.grid, CZ), dim3(TPB), 0, st, U, wl, tb.meta, inst,
+                       blockmax);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_totals(const T *U, const WorkList &leaves, const DevTables &tb,
                          const InstDev *inst, int n_inst, double *blocksum, double *tot,
                          hipStream_t st) {
@@ -787,6 +797,8 @@ hipError_t launch_totals(const T *U, const WorkList &leaves, const DevTables &tb
     template hipError_t launch_cfl<T>(const T *, const WorkList &, const DevTables &,       \
                                       const InstDev *, int, double *, double *, hipStream_t, \
                                       int32_t *, const int32_t *, int32_t *, int);          \
+    template hipError_t launch_cfl_blocks<T>(const T *, const WorkList &, const DevTables &, \
+                                             const InstDev *, double *, hipStream_t);      \
     template hipError_t launch_totals<T>(const T *, const WorkList &, const DevTables &,    \
                                          const InstDev *, int, double *, double *, hipStream_t);
 MRFV_INST(float)

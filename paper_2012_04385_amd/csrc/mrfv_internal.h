@@ -19,7 +19,7 @@ constexpr int CELLS_P = NP * NP * NP;    // 13824
 constexpr int CELLS_I = NI * NI * NI;    // 4096
 constexpr int FACE = NI * NI;            // 256
 
-// Per-slot block description on the device (36 bytes).
+// Per-slot block description on the device (40 bytes).
 struct BlockMeta {
     int32_t inst, level, bx, by, bz;
     int32_t parent;   // parent slot, -1 on level 0
@@ -28,6 +28,7 @@ struct BlockMeta {
     int32_t srestr;   // 1: leaf on level >= 1 without a non-leaf same-level face neighbour
                       // (no jump correction): the fused stage writes its restriction into
                       // the parent's octant
+    int32_t lpos;     // position in the all-leaves list (-1: not a leaf)
 };
 
 // Per-instance parameters on the device.
@@ -101,6 +102,7 @@ struct HostLists {
     std::vector<int32_t> desc;
     int32_t all_blocks_off = 0, all_blocks_cnt = 0;      // every block
     int32_t fine_off = 0, fine_cnt = 0;                  // every block with level >= 1
+    int32_t jcorr_off = 0, jcorr_cnt = 0;                // leaves the jump correction changes
     // some leaf face reads a parent-derived value inside a stage: no same-level neighbour
     // (predicted halo) or a non-leaf same-level neighbour (restricted interior)
     bool parents_needed = false;
@@ -160,7 +162,9 @@ uint64_t morton_encode(int shadow, int level, int bx, int by, int bz);
 
 // Descriptor indices of the work lists (DevTables lists + the device descriptor table).
 constexpr int MAX_LEVELS = 13;
-constexpr int DESC_LEAVES = 0, DESC_ALL = 1, DESC_FINE = 2, DESC_SCRATCH = 3;
+// DESC_JCORR: leaves with a non-leaf same-level face neighbour (the jump correction
+// changes their boundary cells after the fused stage)
+constexpr int DESC_LEAVES = 0, DESC_ALL = 1, DESC_FINE = 2, DESC_JCORR = 3;
 constexpr int DESC_PER_LEVEL = 7;
 constexpr int desc_lvl(int l) { return 4 + DESC_PER_LEVEL * l; }
 constexpr int desc_par(int l) { return 5 + DESC_PER_LEVEL * l; }
@@ -224,6 +228,10 @@ hipError_t launch_cfl(const T *U, const WorkList &leaves, const DevTables &tb,
                       hipStream_t st, int32_t *gate = nullptr, const int32_t *desc = nullptr,
                       int32_t *desc_g = nullptr, int n_desc = 0);
 int cfl_slabs();      // z-slab maxima per block in the CFL reduction
+// the per-block pass of the CFL step alone, over any list of leaves
+template <typename T>
+hipError_t launch_cfl_blocks(const T *U, const WorkList &wl, const DevTables &tb,
+                             const InstDev *inst, double *blockmax, hipStream_t st);
 template <typename T>
 hipError_t launch_totals(const T *U, const WorkList &leaves, const DevTables &tb,
                          const InstDev *inst, int n_inst, double *blocksum, double *tot,
@@ -338,8 +346,8 @@ struct mrfv_ctx {
     // kernel timing
     bool has_jumps = false;            // some leaf has a non-leaf same-level face neighbour
     bool capturing = false;            // recording a step graph
-    // step graphs: the CFL pass takes the block maxima the previous step's last stage wrote
-    // (set by mrfv_run for a step that follows a step on the same jump-free tree)
+    // step graphs: the CFL pass takes the block maxima the previous step wrote after its
+    // last stage (set by mrfv_run for a step that follows a step on the same tree)
     bool cfl_from_stage = false;
     // step graphs: the first stage's restriction skips the octants the previous step's last
     // stage restricted (set by mrfv_run for a step that follows a step on the same tree)

@@ -194,7 +194,7 @@ std::vector<int> Topology::alive_sorted() const {
 void Topology::build(std::vector<BlockMeta> &meta, std::vector<int32_t> &child,
                      std::vector<int32_t> &nbr, HostLists &L) const {
     const int cap = capacity();
-    meta.assign(cap, BlockMeta{0, 0, 0, 0, 0, -1, 0, 0, 0});
+    meta.assign(cap, BlockMeta{0, 0, 0, 0, 0, -1, 0, 0, 0, -1});
     child.assign((size_t)cap * 8, -1);
     nbr.assign((size_t)cap * 27, -2);
     const std::vector<int> order = alive_sorted();
@@ -203,7 +203,7 @@ void Topology::build(std::vector<BlockMeta> &meta, std::vector<int32_t> &child,
     for (int s : order) {
         const HostBlock &b = blocks_[s];
         const mrfv_instance &p = inst_[b.inst];
-        BlockMeta m{b.inst, b.level, b.bx, b.by, b.bz, b.parent, b.leaf ? 1 : 0, 0, 0};
+        BlockMeta m{b.inst, b.level, b.bx, b.by, b.bz, b.parent, b.leaf ? 1 : 0, 0, 0, -1};
         const int c[3] = {b.bx, b.by, b.bz};
         for (int a = 0; a < 3; ++a) {
             const int n = p.n0[a] << b.level;
@@ -379,6 +379,7 @@ void Topology::build(std::vector<BlockMeta> &meta, std::vector<int32_t> &child,
         L.data[n_inst + i] = (int32_t)L.data.size() - L.data[i];
     }
     L.all_leaves_cnt = (int32_t)L.data.size() - L.all_leaves_off;
+    for (int t = 0; t < L.all_leaves_cnt; ++t) meta[L.data[L.all_leaves_off + t]].lpos = t;
     L.all_blocks_off = (int32_t)L.data.size();
     for (int s : order) L.data.push_back(s);
     L.all_blocks_cnt = (int32_t)L.data.size() - L.all_blocks_off;
@@ -386,6 +387,17 @@ void Topology::build(std::vector<BlockMeta> &meta, std::vector<int32_t> &child,
     for (int s : order)
         if (blocks_[s].level >= 1) L.data.push_back(s);
     L.fine_cnt = (int32_t)L.data.size() - L.fine_off;
+    L.jcorr_off = (int32_t)L.data.size();
+    for (int s : order) {
+        if (!blocks_[s].leaf) continue;
+        bool coarse_side = false;
+        for (int r : {12, 14, 10, 16, 4, 22}) {
+            const int nb = nbr[(size_t)s * 27 + r];
+            if (nb >= 0 && !blocks_[nb].leaf) coarse_side = true;
+        }
+        if (coarse_side) L.data.push_back(s);
+    }
+    L.jcorr_cnt = (int32_t)L.data.size() - L.jcorr_off;
     L.desc.assign(2 * N_DESC, 0);
     auto set = [&](int which, int32_t off, int32_t cnt) {
         L.desc[2 * which] = off;
@@ -394,6 +406,7 @@ void Topology::build(std::vector<BlockMeta> &meta, std::vector<int32_t> &child,
     set(DESC_LEAVES, L.all_leaves_off, L.all_leaves_cnt);
     set(DESC_ALL, L.all_blocks_off, L.all_blocks_cnt);
     set(DESC_FINE, L.fine_off, L.fine_cnt);
+    set(DESC_JCORR, L.jcorr_off, L.jcorr_cnt);
     for (int l = 0; l <= maxl && l < MAX_LEVELS; ++l) {
         set(desc_lvl(l), L.lvl_off[l], L.lvl_cnt[l]);
         set(desc_par(l), L.par_off[l], L.par_cnt[l]);
