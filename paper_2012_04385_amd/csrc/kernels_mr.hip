@@ -167,7 +167,8 @@ __global__ __launch_bounds__(TPB) void k_fill_halos(T *__restrict__ U, WorkList 
         const int nq = re ? 2 : 5;
         if (src >= 0) {
             const T *sb = U + (size_t)src * 5 * CELLS_P;
-            for (int t = tid; t < nq * ncell; t += TPB) {
+#pragma unroll 4
+            for (int t = tid; t < nq * ncell; t += TPB) {   // unrolled: several loads in flight
                 const int qi = dc.quot(t), e = t - qi * ncell;
                 const int q = re ? 4 * qi : qi;
                 const int e1 = d0.quot(e), e2 = d1.quot(e1);
