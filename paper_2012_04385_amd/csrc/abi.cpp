@@ -152,6 +152,13 @@ int do_project(mrfv_ctx *ctx, T *U, bool stage_only = false, bool rho_e_only = f
 template <typename T>
 int do_fill(mrfv_ctx *ctx, T *U, int max_level, int mode = FILL_ALL, bool with_parents = true) {
     const int qsel = mode & FILL_RHO_E, m = mode & ~FILL_RHO_E;
+    // before the details every non-leaf block gets its full halo; when that is copies only
+    // (no prediction reads a coarser level's fill) one launch covers all levels
+    const bool merged = m == FILL_MISSING && with_parents && ctx->lists.pars_copy_only &&
+                        max_level >= levels_to_cover(ctx);
+    if (merged)
+        HIP_OK(launch_fill_halos<T>(U, wlist(ctx, DESC_PARS, 1024), ctx->tb, (FillMode)(FILL_ALL | qsel),
+                                    ctx->stream));
     for (int l = 0; l <= std::min(max_level, levels_to_cover(ctx)); ++l) {
         if (m == FILL_ALL) {
             HIP_OK(launch_fill_halos<T>(U, wlist(ctx, desc_lvl(l), 1024), ctx->tb, (FillMode)mode,
@@ -160,7 +167,7 @@ int do_fill(mrfv_ctx *ctx, T *U, int max_level, int mode = FILL_ALL, bool with_p
             // a stage fills only the parents its predictions read; the fill before the
             // details (FILL_MISSING) all non-leaf blocks, whose details are judged too
             const int pw = m == FILL_MISSING_FACES ? desc_pfill(l) : desc_par(l);
-            if (with_parents)
+            if (with_parents && !merged)
                 HIP_OK(launch_fill_halos<T>(U, wlist(ctx, pw, 1024), ctx->tb, (FillMode)(FILL_ALL | qsel),
                                             ctx->stream));
             const int which = m == FILL_FACES ? desc_leaf(l)
@@ -584,7 +591,7 @@ GraphKey graph_key(const mrfv_ctx *ctx) {
     const HostLists &L = ctx->lists;
     uint64_t k = (uint64_t)L.max_level | ((uint64_t)ctx->has_jumps << 4) |
                  ((uint64_t)L.parents_needed << 63) | ((uint64_t)ctx->cfl_from_stage << 62) |
-                 ((uint64_t)ctx->restrict_from_stage << 61);
+                 ((uint64_t)ctx->restrict_from_stage << 61) | ((uint64_t)L.pars_copy_only << 60);
     uint64_t k2 = 0;
     for (int l = 0; l <= L.max_level && l < MAX_LEVELS; ++l) {
         if (L.desc[2 * desc_par(l) + 1] > 0) k |= 1ull << (5 + l);

@@ -103,6 +103,10 @@ struct HostLists {
     int32_t all_blocks_off = 0, all_blocks_cnt = 0;      // every block
     int32_t fine_off = 0, fine_cnt = 0;                  // every block with level >= 1
     int32_t jcorr_off = 0, jcorr_cnt = 0;                // leaves the jump correction changes
+    int32_t pars_off = 0, pars_cnt = 0;                  // every non-leaf block
+    // no non-leaf block on level >= 1 has a halo region without a same-level neighbour or
+    // on a zero-gradient side: filling the parents' halos is copies only, in any order
+    bool pars_copy_only = false;
     // some leaf face reads a parent-derived value inside a stage: no same-level neighbour
     // (predicted halo) or a non-leaf same-level neighbour (restricted interior)
     bool parents_needed = false;
@@ -164,26 +168,27 @@ uint64_t morton_encode(int shadow, int level, int bx, int by, int bz);
 constexpr int MAX_LEVELS = 13;
 // DESC_JCORR: leaves with a non-leaf same-level face neighbour (the jump correction
 // changes their boundary cells after the fused stage)
-constexpr int DESC_LEAVES = 0, DESC_ALL = 1, DESC_FINE = 2, DESC_JCORR = 3;
+// DESC_PARS: every non-leaf block, all levels
+constexpr int DESC_LEAVES = 0, DESC_ALL = 1, DESC_FINE = 2, DESC_JCORR = 3, DESC_PARS = 4;
 constexpr int DESC_PER_LEVEL = 7;
-constexpr int desc_lvl(int l) { return 4 + DESC_PER_LEVEL * l; }
-constexpr int desc_par(int l) { return 5 + DESC_PER_LEVEL * l; }
-constexpr int desc_leaf(int l) { return 6 + DESC_PER_LEVEL * l; }
+constexpr int desc_lvl(int l) { return 5 + DESC_PER_LEVEL * l; }
+constexpr int desc_par(int l) { return 6 + DESC_PER_LEVEL * l; }
+constexpr int desc_leaf(int l) { return 7 + DESC_PER_LEVEL * l; }
 // leaves of level l with at least one face that has no same-level neighbour or lies on a
 // zero-gradient boundary: the only leaves whose halos a fused stage must fill
-constexpr int desc_jleaf(int l) { return 7 + DESC_PER_LEVEL * l; }
+constexpr int desc_jleaf(int l) { return 8 + DESC_PER_LEVEL * l; }
 // leaves of level l with at least one of the 26 halo regions lacking a same-level
 // neighbour or on a zero-gradient boundary (filled before the details)
-constexpr int desc_jleaf26(int l) { return 8 + DESC_PER_LEVEL * l; }
+constexpr int desc_jleaf26(int l) { return 9 + DESC_PER_LEVEL * l; }
 // non-leaf blocks of level l whose halo a stage's predictions read: parents of leaves
 // with a face lacking a same-level neighbour, and parents of such blocks that lack a
 // same-level neighbour in some region themselves
-constexpr int desc_pfill(int l) { return 9 + DESC_PER_LEVEL * l; }
+constexpr int desc_pfill(int l) { return 10 + DESC_PER_LEVEL * l; }
 // non-leaf blocks of level l whose interior a stage reads: the stage's prediction
 // sources, their non-leaf same-level neighbours (copied into their halos), non-leaf
 // same-level face neighbours of leaves, and the non-leaf descendants of all of these
-constexpr int desc_pproj(int l) { return 10 + DESC_PER_LEVEL * l; }
-constexpr int N_DESC = 4 + DESC_PER_LEVEL * MAX_LEVELS;
+constexpr int desc_pproj(int l) { return 11 + DESC_PER_LEVEL * l; }
+constexpr int N_DESC = 5 + DESC_PER_LEVEL * MAX_LEVELS;
 
 // Halo fill modes, two flags: FACES restricts the fill to the 6 face regions, 3 layers
 // deep (all the flux stencils read); MISSING to the regions without a same-level

@@ -398,6 +398,14 @@ void Topology::build(std::vector<BlockMeta> &meta, std::vector<int32_t> &child,
         if (coarse_side) L.data.push_back(s);
     }
     L.jcorr_cnt = (int32_t)L.data.size() - L.jcorr_off;
+    L.pars_off = (int32_t)L.data.size();
+    L.pars_copy_only = true;
+    for (int s : order)
+        if (!blocks_[s].leaf) {
+            L.data.push_back(s);
+            if (blocks_[s].level >= 1 && needs_region_fill(s)) L.pars_copy_only = false;
+        }
+    L.pars_cnt = (int32_t)L.data.size() - L.pars_off;
     L.desc.assign(2 * N_DESC, 0);
     auto set = [&](int which, int32_t off, int32_t cnt) {
         L.desc[2 * which] = off;
@@ -407,6 +415,7 @@ void Topology::build(std::vector<BlockMeta> &meta, std::vector<int32_t> &child,
     set(DESC_ALL, L.all_blocks_off, L.all_blocks_cnt);
     set(DESC_FINE, L.fine_off, L.fine_cnt);
     set(DESC_JCORR, L.jcorr_off, L.jcorr_cnt);
+    set(DESC_PARS, L.pars_off, L.pars_cnt);
     for (int l = 0; l <= maxl && l < MAX_LEVELS; ++l) {
         set(desc_lvl(l), L.lvl_off[l], L.lvl_cnt[l]);
         set(desc_par(l), L.par_off[l], L.par_cnt[l]);
