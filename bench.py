@@ -21,9 +21,12 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic FLOPs of the fused right-hand side + update per cell-update (see the design doc,
-# "FLOP model"): per face 734 FLOPs with every characteristic field upwind, plus 110 per
-# field that takes the LLF split; 17/16 faces per cell per axis; 40 per cell for the update.
+# Algorithmic FLOPs of the fused right-hand side + update per cell-update, counted from the
+# textbook formulation: per face 734 FLOPs with every characteristic field upwind (17 for the
+# new cell's primitives, 40 for the Roe average and eigen-quantities, 234 for projecting six
+# cells' states and fluxes, 66 to assemble the fields, 22 for the back-projection, 5 for the
+# difference, 70 per WENO5), plus 110 per field that takes the LLF split; 17/16 faces per
+# cell per axis; 40 per cell for the update.
 FACE_BASE, LLF_EXTRA, UPDATE = 734.0, 110.0, 40.0
 PEAK_FP32_VECTOR = 157.3e12       # MI355X FP32 vector (FLOP/s)
 PEAK_HBM = 8.0e12                 # bytes/s

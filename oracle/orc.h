@@ -18,9 +18,8 @@
  *   per conserved quantity, stored [q][z][y][x] with x fastest; interior index 4..19.
  *   q = (rho, rho*u, rho*v, rho*w, E).
  *
- * Parity status per function is stated in the oracle section of the design doc; every
- * function here is pinned by a CPU test (tests/test_oracle_*.py) against closed forms,
- * invariants, exact rational arithmetic or brute force.
+ * Every function here is pinned by a CPU test (tests/test_oracle_*.py) against closed
+ * forms, invariants, exact rational arithmetic or brute force; none is parity unpinned.
  */
 #ifndef ORACLE_ORC_API_H
 #define ORACLE_ORC_API_H
