@@ -318,10 +318,10 @@ __global__ __launch_bounds__(TPB) void k_predict(T *__restrict__ U,
 // z0 + corr and z0 - corr), so every stencil is read once per sibling pair.
 // Cells outside the interior are read from the same-level neighbour's interior where
 // one exists (else from the own halo, filled for such regions).
-constexpr int DZ = 4;                          // slabs per block
+constexpr int DZ = 6;                          // slabs per block
 constexpr int DTPB = 384;                      // threads per workgroup (16 rows of 24 cells)
-constexpr int SZ = NP / DZ;                    // padded z-planes per slab (6; even)
-constexpr int PZ = SZ / 2 + 4;                 // parent planes per slab (7)
+constexpr int SZ = NP / DZ;                    // padded z-planes per slab (4; even)
+constexpr int PZ = SZ / 2 + 4;                 // parent planes per slab (6)
 
 // One 1D prediction step for both siblings: lo = z0 + corr, hi = z0 - corr.
 __device__ __forceinline__ void pred_pair(double m2, double m1, double z0, double p1, double p2,
@@ -339,9 +339,9 @@ __global__ __launch_bounds__(DTPB) void k_details(const T *__restrict__ U, WorkL
                                                  double *__restrict__ det4) {
     constexpr int R = NI;                       // parent region edge in x and y (16)
     constexpr int NPAIR = NP / 2;               // sibling pairs along a padded axis (12)
-    constexpr int NA = (PZ * R * R + DTPB - 1) / DTPB;        // parent loads per thread (5)
-    constexpr int YROWS = SZ * NPAIR;                          // y-pass rows (kc, jp): 72
-    constexpr int NY = (YROWS + DTPB / NP - 1) / (DTPB / NP);  // y-pass rows per thread (5)
+    constexpr int NA = (PZ * R * R + DTPB - 1) / DTPB;        // parent loads per thread (4)
+    constexpr int YROWS = SZ * NPAIR;                          // y-pass rows (kc, jp): 48
+    constexpr int NY = (YROWS + DTPB / NP - 1) / (DTPB / NP);  // y-pass rows per thread (3)
     __shared__ T A[PZ * R * R];                 // parent planes [kk][jj][ii]
     __shared__ double Cz[SZ * R * R];           // z pass [kc][jj][ii]
     __shared__ double Cx[SZ * R * NP];          // x pass [kc][jj][i]
