@@ -19,7 +19,13 @@
  *   q = (rho, rho*u, rho*v, rho*w, E).
  *
  * Every function here is pinned by a CPU test (tests/test_oracle_*.py) against closed
- * forms, invariants, exact rational arithmetic or brute force; none is parity unpinned.
+ * forms, invariants, exact rational arithmetic, published values or brute force: the
+ * x-direction flux by consistency, the Roe property, a smooth entropy wave and Sod's
+ * exact solution; the y and z directions by bitwise axis permutations (Sod, single level
+ * and adaptive; the isentropic vortex) and by fifth-order convergence of the vortex in
+ * the x-y plane; the exact Riemann solver by the published star state of Sod's data.
+ * What stays unpinned is the solution of the flows without a closed form (shear layer,
+ * shock and blobs): there the GPU is compared with this oracle, not with a truth.
  */
 #ifndef ORACLE_ORC_API_H
 #define ORACLE_ORC_API_H

@@ -578,7 +578,10 @@ double orc_sim_dt(const orc_sim *s) {
                         mx[a] = std::max(mx[a], std::fabs(U[1 + a] / U[0]) + c);
                 }
     }
-    return s->p.cfl * dx_level(s->p, s->p.lmax) / (mx[0] + mx[1] + mx[2]);
+    // eq:Cfl sums the three directional maxima; they are added in ascending order so that
+    // dt does not depend on which axis is called x (a rotated problem gets the same dt)
+    std::sort(mx, mx + 3);
+    return s->p.cfl * dx_level(s->p, s->p.lmax) / ((mx[0] + mx[1]) + mx[2]);
 }
 
 double orc_ssprk3_stage(int stage, double u0, double us, double L, double dt) {

@@ -4,7 +4,9 @@
 * conservation to round-off on a periodic domain with jumps and with adaptation (checks
   the jump flux correction of algo:ComputeLoop and the conservative MR operators);
 * the exact Riemann solution of the Sod shock tube (the paper's verification case);
-* fifth-order convergence on a smooth entropy wave (point values, dt ~ dx^(5/3));
+* fifth-order convergence on a smooth entropy wave along x (point values,
+  dt ~ dx^(5/3)); the transverse directions and the acoustic and shear fields are
+  pinned by the isentropic vortex and the axis permutations in test_oracle_symmetry.py;
 * CFL time step (eq:Cfl) and totals in closed form;
 * halo fill exact for polynomial data away from the domain boundary;
 * details/flags (eq:DetailFunction, eq:Thresholding, eq:LevelWiseEpsilon): zero details
