@@ -6,7 +6,8 @@ import os
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["orc_euler.cpp", "orc_mr.cpp", "orc_riemann.cpp", "orc_tree.cpp", "orc_mlp.cpp"]
+SOURCES = ["orc_euler.cpp", "orc_mr.cpp", "orc_riemann.cpp", "orc_tree.cpp", "orc_mlp.cpp",
+           "orc_schemes.cpp"]
 LIB = os.path.join(HERE, "liborc.so")
 
 

@@ -20,7 +20,7 @@ class _Params(C.Structure):
     _fields_ = [("gamma", C.c_double), ("B", C.c_double), ("cfl", C.c_double),
                 ("eps", C.c_double), ("scale_rho", C.c_double), ("scale_E", C.c_double),
                 ("dx0", C.c_double), ("lmax", C.c_int32), ("n0", C.c_int32 * 3),
-                ("bc", C.c_int32 * 3), ("adapt", C.c_int32)]
+                ("bc", C.c_int32 * 3), ("adapt", C.c_int32), ("scheme", C.c_int32)]
 
 
 IC_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
@@ -85,6 +85,17 @@ def lib():
         L.orc_sim_time.restype = d
         L.orc_sim_llf_fraction.argtypes = [vp]
         L.orc_sim_llf_fraction.restype = d
+        L.orc_num_threads.restype = C.c_int
+        L.orc_teno5_minus.argtypes = [d] * 5
+        L.orc_teno5_minus.restype = d
+        L.orc_wao53_minus.argtypes = [d] * 5
+        L.orc_wao53_minus.restype = d
+        L.orc_beta_quartic.argtypes = [d] * 5
+        L.orc_beta_quartic.restype = d
+        L.orc_hllc_flux_x.argtypes = [pd, pd, d, d, pd]
+        L.orc_face_flux_scheme.argtypes = [C.c_int, C.c_int, pd, d, d, pd]
+        L.orc_face_flux_scheme.restype = C.c_int
+        L.orc_block_rhs_scheme.argtypes = [C.c_int, pd, d, d, d, pd]
         L.orc_morton_encode.argtypes = [i32] * 5
         L.orc_morton_encode.restype = C.c_uint64
         L.orc_morton_neighbor.argtypes = [C.c_uint64, i32, i32, C.POINTER(i32)]
@@ -144,6 +155,44 @@ def face_flux(d: int, st, gamma=1.4, B=0.0):
     return F, n
 
 
+SCHEMES = {"roe_weno5": 0, "roe_teno5": 1, "llf_weno5": 2, "hllc_wao53": 3}
+
+
+def teno5_minus(a, b, c, d, e) -> float:
+    return lib().orc_teno5_minus(float(a), float(b), float(c), float(d), float(e))
+
+
+def wao53_minus(a, b, c, d, e) -> float:
+    return lib().orc_wao53_minus(float(a), float(b), float(c), float(d), float(e))
+
+
+def beta_quartic(a, b, c, d, e) -> float:
+    return lib().orc_beta_quartic(float(a), float(b), float(c), float(d), float(e))
+
+
+def hllc_flux_x(UL, UR, gamma=1.4, B=0.0) -> np.ndarray:
+    UL = np.ascontiguousarray(UL, dtype=np.float64)
+    UR = np.ascontiguousarray(UR, dtype=np.float64)
+    F = np.zeros(5)
+    lib().orc_hllc_flux_x(_dp(UL), _dp(UR), gamma, B, _dp(F))
+    return F
+
+
+def face_flux_scheme(scheme: int, d: int, st, gamma=1.4, B=0.0):
+    st = np.ascontiguousarray(st, dtype=np.float64).reshape(30)
+    F = np.zeros(5)
+    n = lib().orc_face_flux_scheme(scheme, d, _dp(st), gamma, B, _dp(F))
+    return F, n
+
+
+def block_rhs_scheme(scheme, u_padded, gamma, B, dx) -> np.ndarray:
+    u = np.ascontiguousarray(u_padded, dtype=np.float64)
+    assert u.shape == (5, P, P, P)
+    out = np.zeros((5, 16, 16, 16))
+    lib().orc_block_rhs_scheme(scheme, _dp(u), gamma, B, dx, _dp(out))
+    return out
+
+
 def predict_cell(parent_padded: np.ndarray, octant, i, j, k) -> float:
     a = np.ascontiguousarray(parent_padded, dtype=np.float64)
     assert a.shape == (P, P, P)
@@ -166,6 +215,10 @@ def exact_riemann(left, right, gamma, s) -> np.ndarray:
     if rc != 0:
         raise RuntimeError("exact Riemann solver did not converge")
     return out
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
 
 
 def morton_encode(shadow, level, bx, by, bz) -> int:
@@ -252,6 +305,7 @@ class Sim:
             p.n0[a] = problem.n0[a]
             p.bc[a] = problem.bc[a]
         p.adapt = problem.adapt if adapt is None else int(adapt)
+        p.scheme = SCHEMES[getattr(problem, "scheme", "roe_weno5")]
         self._p = p
         self.h = lib().orc_sim_create(C.byref(p))
         self._cb = None

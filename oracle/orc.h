@@ -63,6 +63,22 @@ int orc_face_flux_x(const double st[30], double gamma, double B, double F[5]);
 /* Same along axis d (0,1,2) for a stencil given in the physical component order. */
 int orc_face_flux(int d, const double st[30], double gamma, double B, double F[5]);
 
+/* ---------------- the other flux kernels of Sec. "Numerical Scheme" ---------------- */
+
+/* TENO5 (Fu, Hu & Adams) value at the right face of the middle point, left-biased. */
+double orc_teno5_minus(double a, double b, double c, double d, double e);
+/* WENO-AO(5,3) (Balsara, Garain & Shu) value at the right face of the middle point. */
+double orc_wao53_minus(double a, double b, double c, double d, double e);
+/* Smoothness indicator of the quartic with cell averages a..e (unit cells -2..2). */
+double orc_beta_quartic(double a, double b, double c, double d, double e);
+/* HLLC flux along x between two conservative states. */
+void orc_hllc_flux_x(const double UL[5], const double UR[5], double gamma, double B, double F[5]);
+/* Face flux of the six-cell stencil with one of the paper's flux kernels:
+ * 0 Roe + WENO5-JS (orc_face_flux), 1 Roe + TENO5, 2 LLF + WENO5-JS (every field split),
+ * 3 HLLC + WENO-AO(5,3) (characteristic-wise face states).  Returns the LLF fields. */
+int orc_face_flux_x_scheme(int scheme, const double st[30], double gamma, double B, double F[5]);
+int orc_face_flux_scheme(int scheme, int d, const double st[30], double gamma, double B, double F[5]);
+
 /* ---------------- MR operators (eq:Averaging, eq:Prediction + appendix Q-terms) ------ */
 
 /* Fifth-order conservative prediction of one fine cell from a padded 24^3 parent array
@@ -97,6 +113,7 @@ typedef struct {
     int32_t n0[3];         /* level-0 blocks per axis                          */
     int32_t bc[3];         /* per axis: 0 periodic, 1 zero-gradient            */
     int32_t adapt;         /* 1: refine/coarsen after each step                */
+    int32_t scheme;        /* flux kernel, see orc_face_flux_scheme            */
 } orc_params;
 
 typedef struct orc_sim orc_sim;
@@ -127,6 +144,8 @@ void orc_sim_set_block(orc_sim *s, int32_t idx, const double *in);
  * L[5][16][16][16], with cell size dx; and the detail of eq:DetailFunction of a padded
  * child block against its padded parent (octant ox, oy, oz). */
 void orc_block_rhs(const double *u_padded, double gamma, double B, double dx, double *L);
+void orc_block_rhs_scheme(int scheme, const double *u_padded, double gamma, double B, double dx,
+                          double *L);
 double orc_block_detail(const double *u_padded, const double *parent_padded, int ox, int oy,
                         int oz, double s_rho, double s_E);
 
@@ -154,6 +173,8 @@ void orc_sim_totals(const orc_sim *s, double *tot);
 double orc_sim_time(const orc_sim *s);
 /* Fraction of face-fields that took the LLF branch during the last rhs evaluation. */
 double orc_sim_llf_fraction(const orc_sim *s);
+/* Threads the oracle's parallel loops use (OpenMP). */
+int orc_num_threads(void);
 
 /* ---------------- learned refinement proposer (not in the paper) -------------------- */
 

@@ -16,6 +16,7 @@
 #include "orc.h"
 
 #include <algorithm>
+#include <omp.h>
 #include <cmath>
 #include <cstring>
 #include <unordered_map>
@@ -299,7 +300,7 @@ long block_rhs(const orc_sim *s, Block *b) {
                         c[o_hi] = H + m;
                         for (int q = 0; q < 5; ++q) st[5 * j + q] = b->u[at(q, c[2], c[1], c[0])];
                     }
-                    n_llf += orc_face_flux(d, st, g, B, Fh);
+                    n_llf += orc_face_flux_scheme(s->p.scheme, d, st, g, B, Fh);
                     for (int q = 0; q < 5; ++q) F[fidx(d, q, m, r, f)] = Fh[q];
                 }
     b->rhs.assign(5 * ICELLS, 0.0);
@@ -660,7 +661,13 @@ void orc_sim_set_block(orc_sim *s, int32_t idx, const double *in) {
 double orc_sim_detail(const orc_sim *s, int32_t idx) { return s->order[idx]->detail; }
 
 void orc_block_rhs(const double *u_padded, double gamma, double B, double dx, double *L) {
+    orc_block_rhs_scheme(0, u_padded, gamma, B, dx, L);
+}
+
+void orc_block_rhs_scheme(int scheme, const double *u_padded, double gamma, double B, double dx,
+                          double *L) {
     orc_sim tmp;
+    tmp.p.scheme = scheme;
     tmp.p.gamma = gamma;
     tmp.p.B = B;
     tmp.p.dx0 = dx;
@@ -736,5 +743,7 @@ void orc_sim_totals(const orc_sim *s, double *tot) {
 
 double orc_sim_time(const orc_sim *s) { return s->time; }
 double orc_sim_llf_fraction(const orc_sim *s) { return s->llf_fraction; }
+
+int orc_num_threads(void) { return omp_get_max_threads(); }
 
 }  // extern "C"

@@ -72,6 +72,9 @@ class Problem:
     noise: float = 1e-3
     params: dict = dataclasses.field(default_factory=dict)
     custom: Optional[Callable] = None      # custom(x, y, z) -> (rho, u, v, w, p)
+    # flux kernel (Sec. "Numerical Scheme"): roe_weno5 (the standard configuration),
+    # roe_teno5, llf_weno5, hllc_wao53
+    scheme: str = "roe_weno5"
 
     @property
     def adapt(self) -> int:
