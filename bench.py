@@ -1,15 +1,24 @@
-"""Benchmark: cell-updates per second per SSP-RK3 stage of the MR blast workload
-(3 levels, 128^3 effective, 16^3 blocks + 4 halo layers), FP32 batched path, one MI355X.
+"""Benchmark: cell-updates per second per SSP-RK3 stage of the FP32 batched MR path on one
+MI355X.  Default workload: the 6-level shock-blobs problem (512^3 effective, 16^3 blocks +
+4 halo layers, resolution jumps in every step), the largest single-GPU configuration.
 
 One "step" is one global time step of the whole hot path: CFL reduction, three stages of
 {restriction, halo fill, fused right-hand side + stage update, jump correction}, then the
-MR adaptation (restriction, 26-region halo fill, details/flags, flag read-back, tree
-update, prediction of new children).  value = (leaf cells x 3 stages) summed over the timed
-steps / wall time, with the state resident in HBM.
+MR adaptation (restriction, halo fill, details/flags, flag read-back, tree update,
+prediction of new children).  value = (leaf cells x 3 stages) summed over the timed steps
+/ wall time, with the state resident in HBM, steps run by the library's own step loop
+(step graph replays, the next step queued before the flags are read).
 
-Also measured on the same workload: the FP64 plain path (speed-up), the L1 density
-difference and flag agreement between the two GPU paths, the dominant kernel's average
-duration from HIP events (roofline), and the FP64 CPU oracle on a bounded sample.
+Also measured on the same workload:
+  * parity: the FP64 CPU oracle and the GPU run the first steps from the same seeded
+    initial condition; identical leaf sets after algo:Init and every step, L1 density and
+    energy differences at the end (volume-weighted, over the whole domain);
+  * cpu_baseline: the oracle's rate on those steps (threads, physical cores, CPU model);
+  * roofline: the fused kernel's average duration from HIP events around each launch on
+    the library's stream (eager run with the autotuned shape), against the FP32 vector
+    peak, plus its algorithmic HBM bandwidth and the counter-measured traffic;
+  * the FP64 plain path on the same workload (speed-up), and config 2 (the 3-level blast)
+    as extra keys.
 Prints one JSON line on stdout; progress goes to stderr.
 """
 import argparse
@@ -28,16 +37,44 @@ sys.path.insert(0, ROOT)
 # difference, 70 per WENO5), plus 110 per field that takes the LLF split; 17/16 faces per
 # cell per axis; 40 per cell for the update.
 FACE_BASE, LLF_EXTRA, UPDATE = 734.0, 110.0, 40.0
-PEAK_FP32_VECTOR = 157.3e12       # MI355X FP32 vector (FLOP/s)
+PEAK_FP32_VECTOR = 157.3e12       # MI355X FP32 vector with packed FP32 (FLOP/s)
+PEAK_FP32_UNPACKED = 78.6e12      # without packed FP32 instructions (this build)
 PEAK_HBM = 8.0e12                 # bytes/s
+# algorithmic bytes per FP32 cell-update of the fused kernel, every stage: read the interior
+# and the 3-wide face layers (5 components x 4 B x 8704 / 4096 cells = 42.5 B), write the new
+# state (20 B), and write U0 (stage 1) or read it (stages 2, 3) (20 B)
+BYTES_PER_CELL_UPDATE = 82.5
+
+WORKLOADS = ["shockblobs_512e_6lvl", "blast_128e_3lvl", "kh_256e_5lvl", "multi_256"]
 
 
-def counted_traffic(kernel: str):
-    """HBM bytes per launch of the given fused-kernel variant from the committed counter
-    summary, or None when the kernel source changed since the counters were taken."""
+def problems(name, steps):
+    from paper_2012_04385_amd import workloads as W
+    return {"shockblobs_512e_6lvl": lambda: [W.shock_blobs_mr6(steps=steps)],
+            "blast_128e_3lvl": lambda: [W.blast_mr3(steps=steps)],
+            "kh_256e_5lvl": lambda: [W.kh_mr5(steps=steps)],
+            "multi_256": lambda: W.multi_instance(steps=steps)}[name]()
+
+
+def describe(name, pbs):
+    pb = pbs[0]
+    ics = {"shockblobs_512e_6lvl": "Mach-2 shock at x=0.1 into 32 seeded Gaussian density blobs "
+                                   "(amplitude 0.5, width 0.02)",
+           "blast_128e_3lvl": "spherical blast r=0.1, (1,10)|(0.125,0.1), +-1e-3 rho noise",
+           "kh_256e_5lvl": "shear layer rho 2|1, u +-0.5, p 2.5, seeded v modes 1-8",
+           "multi_256": "256 seeded blast/Sod instances, 32-128^3, 2-4 levels"}
+    eff = max(pb.n0) * 16 << pb.lmax
+    return {"workload": name, "instances": len(pbs), "levels": pb.lmax + 1, "effective_grid": eff,
+            "block": "16^3 + 4 halo", "ic": ics[name], "eps": pb.eps, "cfl": pb.cfl,
+            "path": "batched FP32, steps replayed from a hipGraph, next step queued ahead"}
+
+
+def counted_traffic(name: str, kernel: str):
+    """HBM bytes per launch of the given fused-kernel variant on a workload from the
+    committed counter summary, or None when the kernel source changed since."""
     import hashlib
     try:
-        prof = json.load(open(os.path.join(ROOT, "profiles", "rhs_update_blast128_counters.json")))
+        prof = json.load(open(os.path.join(ROOT, "profiles", f"rhs_update_{name}_counters.json")))
         src = open(os.path.join(ROOT, prof["source"]), "rb").read()
     except (OSError, KeyError, ValueError):
         return None
@@ -48,9 +85,9 @@ def counted_traffic(kernel: str):
 
 def kernel_name(shape) -> str:
     """Demangled name of the fused kernel's instantiation for a variant shape."""
-    gp, tpb, wpe = shape
+    gp, tpb, wpe, ptr = shape
     b = lambda v: "true" if v else "false"
-    return f"k_rhs_update<float, {gp}, {abs(tpb)}, {b(tpb < 0)}, {wpe}>"
+    return f"k_rhs_update<float, {gp}, {abs(tpb)}, {b(tpb < 0)}, {wpe}, 0, {b(ptr)}>"
 
 
 def flops_per_cell_update(llf_fraction: float) -> float:
@@ -61,14 +98,97 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_gpu(pb, dtype, batched, warmup, steps, timing=False, variant=None):
-    """Timed run of `steps` steps through the library's own step loop (mrfv_run).  The
-    batched FP32 path autotunes the fused kernel's launch shape after the warm-up (or
-    takes `variant`)."""
+def host_cpu():
+    """CPU model, physical cores and logical CPUs this process may run on."""
+    model, cores = "unknown", set()
+    try:
+        phys = core = None
+        for line in open("/proc/cpuinfo"):
+            k, _, v = line.partition(":")
+            k, v = k.strip(), v.strip()
+            if k == "model name":
+                model = v
+            elif k == "physical id":
+                phys = v
+            elif k == "core id":
+                core = v
+            elif not k and phys is not None:
+                cores.add((phys, core))
+                phys = core = None
+    except OSError:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except AttributeError:
+        allowed = os.cpu_count() or 1
+    return model, len(cores) or None, allowed
+
+
+def leafset(g, inst=0):
+    return frozenset(tuple(int(v) for v in r[2:6]) for r in g.blocks() if r[6] == 1 and r[1] == inst)
+
+
+def oracle_leafset(o):
+    return frozenset(tuple(int(v) for v in r[:4]) for r in o.blocks() if r[4] == 1)
+
+
+def l1(o, g, q):
+    """Volume-weighted L1 difference of component q over the leaves both trees share."""
+    import numpy as np
+    so, sg = o.leaf_states(), g.leaf_states()
+    return sum(np.abs(sg[k][q] - v[q]).sum() * o.problem.dx(k[0]) ** 3 for k, v in so.items() if k in sg)
+
+
+def parity_leg(name, pbs, g, steps, want_cpu):
+    """The oracle and the GPU solver g (freshly initialised) run `steps` steps from the same
+    initial condition.  Returns the parity summary, the oracle's rate and LLF fraction."""
+    from oracle import oracle
+    pb = pbs[0]
+    t0 = time.perf_counter()
+    o = oracle.Sim(pb).init()
+    log(f"[bench] oracle algo:Init of {name}: {time.perf_counter() - t0:.1f} s, "
+        f"{len(o.blocks())} blocks")
+    same = [oracle_leafset(o) == leafset(g)]
+    cells, secs, llf = 0, 0.0, []
+    for s in range(steps):
+        leaves = int((o.blocks()[:, 4] == 1).sum())
+        t0 = time.perf_counter()
+        o.step()
+        secs += time.perf_counter() - t0
+        cells += 3 * leaves * 16 ** 3
+        llf.append(o.llf_fraction)
+        g.step()
+        same.append(oracle_leafset(o) == leafset(g))
+        log(f"[bench] parity step {s}: oracle {secs:.1f} s so far, trees identical {same[-1]}")
+    g.check()
+    e_rho, e_E = l1(o, g, 0), l1(o, g, 4)
+    vol = float(pb.n0[0] * pb.n0[1] * pb.n0[2]) * (16 * pb.dx0) ** 3
+    par = {"steps": steps, "trees_identical": f"{sum(same)}/{len(same)} (init + steps)",
+           "l1_rho": e_rho, "l1_E": e_E, "domain_volume": vol,
+           "l1_over_common_leaves_only": not all(same)}
+    cpu = None
+    if want_cpu:
+        model, phys, allowed = host_cpu()
+        cpu = {"value": cells / secs, "unit": "cell-updates/s", "cores": oracle.num_threads(),
+               "kind": "oracle",
+               "sample": f"steps 1-{steps} of {name} after the oracle's own algo:Init "
+                         f"({cells / 3 / steps / 4096:.0f} leaves; FP64, OpenMP over blocks)",
+               "physical_cores": phys, "logical_cpus_allowed": allowed, "cpu_model": model}
+    return par, cpu, sum(llf) / len(llf)
+
+
+def run_gpu(pbs, dtype, batched, warmup, steps, timing=False, variant=None, prepare=None):
+    """Init, `warmup` steps (the first ones through `prepare(g)` if given), autotune the
+    fused kernel's launch shape (batched FP32; or take `variant`), then `steps` timed
+    steps through the library's step loop (mrfv_run)."""
     import torch
     from paper_2012_04385_amd.mrfv import Solver
-    g = Solver([pb], dtype=dtype, batched=batched).init()
-    for _ in range(warmup):
+    t0 = time.perf_counter()
+    g = Solver(pbs, dtype=dtype, batched=batched).init()
+    log(f"[bench] {dtype} batched={batched}: algo:Init {time.perf_counter() - t0:.1f} s, "
+        f"{g.stats()[1]} leaves")
+    done = prepare(g) if prepare else 0
+    for _ in range(max(warmup - done, 0)):
         g.step()
     g.check()
     g.tuned = None
@@ -85,118 +205,36 @@ def run_gpu(pb, dtype, batched, warmup, steps, timing=False, variant=None):
         g.kernel_time()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    cells = 3 * g.run(steps)     # the library's step loop; leaf cells of every step's tree
+    cells = 3 * g.run(steps)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    secs = time.perf_counter() - t0
     g.check()
     kt = g.kernel_time() if timing else None
-    return g, cells, t1 - t0, kt
+    return g, cells, secs, kt
 
 
-def run_trees(pb, dtype, batched, steps):
-    """Untimed run recording the leaf set after every step (flag agreement)."""
-    from paper_2012_04385_amd.mrfv import Solver
-    g = Solver([pb], dtype=dtype, batched=batched).init()
-    trees = []
-    for _ in range(steps):
-        g.step()
-        info = g.blocks()
-        trees.append(frozenset(tuple(int(v) for v in r[2:6]) for r in info if r[6] == 1))
-    g.check()
-    return g, trees
-
-
-def cpu_baseline(pb, budget_s=15.0, max_steps=10):
-    from oracle import oracle
-    o = oracle.Sim(pb).init()
-    cells, n, llf = 0, 0, []
-    t0 = time.perf_counter()
-    while n < max_steps and (time.perf_counter() - t0) < budget_s:
-        leaves = int((o.blocks()[:, 4] == 1).sum())
-        o.step()
-        llf.append(o.llf_fraction)
-        cells += leaves * 16 ** 3 * 3
-        n += 1
-    dt = time.perf_counter() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": cells / dt, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {n} of {pb.steps} steps of {pb.name} (FP64, OpenMP over blocks)"}, \
-        sum(llf) / len(llf)
-
-
-def other_workload(args):
-    """Throughput of the FP32 batched path (step graph, autotuned shape) on a larger
-    workload; the fused kernel's duration from HIP events on an eager run."""
+def free(g):
     import torch
-    from paper_2012_04385_amd import workloads as W
-    from paper_2012_04385_amd.mrfv import Solver
-    pbs = {"kh_256e_5lvl": lambda: [W.kh_mr5(steps=args.warmup + args.steps)],
-           "multi_256": lambda: W.multi_instance(steps=args.warmup + args.steps),
-           "shockblobs_512e_6lvl": lambda: [W.shock_blobs_mr6(steps=args.warmup + args.steps)]}[args.workload]()
-    res = {}
-    for batched, timing in ((2, False), (1, True)):
-        g = Solver(pbs, dtype="f32", batched=batched).init()
-        for _ in range(args.warmup):
-            g.step()
-        g.check()
-        if batched == 2:
-            choice, ms = g.autotune(reps=3)
-            res["autotune"] = {"choice": choice, "shapes": g.rhs_variants(), "ms_per_launch": ms}
-        else:
-            g.set_rhs_variant(res["autotune"]["choice"])
-            g.enable_kernel_timing(True)
-            g.kernel_time()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        cells = 3 * g.run(args.steps)
-        torch.cuda.synchronize()
-        secs = time.perf_counter() - t0
-        g.check()
-        # MR compression: leaf cells over the cells of the uniform finest grid
-        full = sum(pb.n0[0] * pb.n0[1] * pb.n0[2] * 8 ** pb.lmax * 16 ** 3 for pb in pbs)
-        res[batched] = (cells / secs, 1e3 * secs / args.steps, g.kernel_time() if timing else None,
-                        g.stats()[1], g.step_timing(), g.stats()[2] / full)
-        log(f"[bench] {args.workload} batched={batched}: {res[batched][0]:.4e} cell-updates/s, "
-            f"{res[batched][1]:.2f} ms/step")
-        del g
-        torch.cuda.empty_cache()
-    launches, total_ms, kcells = res[1][2]
-    avg_s = total_ms / 1e3 / max(launches, 1)
-    kname = kernel_name(res["autotune"]["shapes"][res["autotune"]["choice"]])
-    fpc = flops_per_cell_update(0.5)
-    achieved = kcells / max(launches, 1) * fpc / avg_s
-    out = {"metric": "cell-updates/s per RK stage (FP32 batched MR RK3)", "value": res[2][0],
-           "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-           "ms_per_step": res[2][1], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f32", "data": "synthetic",
-           "config": {"workload": args.workload, "instances": len(pbs), "leaves_final": res[2][3],
-                      "compression": res[2][5],
-                      "path": "batched FP32, steps replayed from a hipGraph, next step queued ahead"},
-           "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
-                        "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR, "traffic": None,
-                        "kernel": kname,
-                        "avg_launch_ms": avg_s * 1e3,
-                        "flop_model_llf_fraction": 0.5},
-           "cpu_baseline": None, "value_eager_launches": res[1][0], "autotune": res["autotune"],
-           "host_adaptation_ms_per_step": {k: v / max(res[2][4]["steps"], 1) for k, v in res[2][4].items()
-                                           if k != "steps"}}
-    print(json.dumps(out), flush=True)
+    g.close()
+    del g
+    torch.cuda.empty_cache()
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=45)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 plain comparison")
+    ap.add_argument("--workload", default="shockblobs_512e_6lvl", choices=WORKLOADS)
+    ap.add_argument("--parity-steps", type=int, default=2,
+                    help="first steps also run by the oracle (parity and CPU baseline)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle (parity, CPU baseline)")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 plain path")
+    ap.add_argument("--no-extra", action="store_true", help="skip the config-2 extra keys")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device copy of 512 MiB (calibrates HBM byte counters)")
     ap.add_argument("--proposer-gain", action="store_true",
                     help="only run the learned-proposer gain test (6-level shock-blobs workload)")
-    ap.add_argument("--workload", default="blast_128e_3lvl",
-                    choices=["blast_128e_3lvl", "kh_256e_5lvl", "multi_256", "shockblobs_512e_6lvl"],
-                    help="other workloads: FP32 batched throughput only (no FP64, no CPU leg)")
     args = ap.parse_args()
     if args.proposer_gain:
         from paper_2012_04385_amd.proposer import gain_test
@@ -217,79 +255,86 @@ def main():
               "(the multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
-    import torch
-    from paper_2012_04385_amd import workloads as W
+    name = args.workload
+    nsteps = args.warmup + args.steps
+    pbs = problems(name, nsteps)
+    log(f"[bench] workload {name}: FP32 batched, warmup {args.warmup}, timed {args.steps}")
+    oracle_leg = not args.no_cpu and len(pbs) == 1
+    res = {}
 
-    if args.workload != "blast_128e_3lvl":
-        other_workload(args)
-        return
+    def prepare(g):
+        if not oracle_leg:
+            return 0
+        res["parity"], res["cpu"], res["llf"] = parity_leg(name, pbs, g, args.parity_steps, True)
+        return args.parity_steps
 
-    pb = W.blast_mr3(steps=args.warmup + args.steps)
-    log(f"[bench] workload {pb.name}: FP32 batched, warmup {args.warmup}, timed {args.steps}")
-    g32, cells, secs, _ = run_gpu(pb, "f32", 2, args.warmup, args.steps)
+    g32, cells, secs, _ = run_gpu(pbs, "f32", 2, args.warmup, args.steps, prepare=prepare)
     value = cells / secs
     tuned = g32.tuned
-    log(f"[bench] FP32 batched, stage hipGraph: {value:.4e} cell-updates/s, "
+    full = sum(pb.n0[0] * pb.n0[1] * pb.n0[2] * 8 ** pb.lmax * 16 ** 3 for pb in pbs)
+    stats = {"leaves_final": g32.stats()[1], "compression": g32.stats()[2] / full,
+             "host_adaptation_ms_per_step": {k: v / max(g32.step_timing()["steps"], 1)
+                                             for k, v in g32.step_timing().items() if k != "steps"}}
+    log(f"[bench] FP32 batched, step graph: {value:.4e} cell-updates/s, "
         f"{1e3 * secs / args.steps:.3f} ms/step")
-    del g32
+    free(g32)
     # same steps with eager launches and HIP events around every fused-kernel launch
-    ge, cells_e, secs_e, kt = run_gpu(pb, "f32", 1, args.warmup, args.steps, timing=True,
+    ge, cells_e, secs_e, kt = run_gpu(pbs, "f32", 1, args.warmup, args.steps, timing=True,
                                       variant=tuned["choice"])
     value_eager = cells_e / secs_e
     log(f"[bench] FP32 batched, eager + kernel events: {value_eager:.4e} cell-updates/s")
-    del ge
+    free(ge)
 
     extra = {}
     if not args.no_fp64:
-        log("[bench] FP64 plain path on the same workload")
-        g64, cells64, secs64, _ = run_gpu(pb, "f64", False, args.warmup, args.steps)
-        del g64
+        g64, cells64, secs64, _ = run_gpu(pbs, "f64", 0, args.warmup, args.steps)
+        free(g64)
         v64 = cells64 / secs64
         log(f"[bench] FP64 plain: {v64:.4e} cell-updates/s")
-        nsteps = args.warmup + args.steps
-        a32, trees32 = run_trees(pb, "f32", True, nsteps)
-        a64, trees64 = run_trees(pb, "f64", False, nsteps)
-        s32, s64 = a32.leaf_states(), a64.leaf_states()
-        common = set(s32) & set(s64)
-        l1 = sum(np.abs(s32[k][0] - s64[k][0]).sum() * pb.dx(k[0]) ** 3 for k in common)
-        same = sum(1 for a, b in zip(trees32, trees64) if a == b)
-        extra = {"fp64_plain_value": v64, "speedup_vs_fp64_plain": value / v64,
-                 "l1_rho_fp32_vs_fp64": l1, "steps_with_identical_flags": f"{same}/{nsteps}"}
-        log(f"[bench] L1(rho) FP32 vs FP64 after {nsteps} steps = {l1:.3e}; identical trees "
-            f"after {same}/{nsteps} steps")
-        del a32, a64
+        extra.update({"fp64_plain_value": v64, "speedup_vs_fp64_plain": value / v64})
 
-    cpu, llf = None, 0.5
-    if not args.no_cpu:
-        log("[bench] CPU oracle sample")
-        cpu, llf = cpu_baseline(W.blast_mr3(steps=args.warmup + args.steps))
-        log(f"[bench] oracle: {cpu['value']:.4e} cell-updates/s on {cpu['cores']} threads; "
-            f"LLF fraction {llf:.3f}")
+    if not args.no_extra and name != "blast_128e_3lvl":
+        pb2 = problems("blast_128e_3lvl", 50)
+        gb, cb, sb, _ = run_gpu(pb2, "f32", 2, 5, 45)
+        free(gb)
+        c2 = {"value": cb / sb, "ms_per_step": 1e3 * sb / 45, "steps": 45, "warmup": 5}
+        if not args.no_fp64:
+            gb, cb64, sb64, _ = run_gpu(pb2, "f64", 0, 5, 45)
+            free(gb)
+            c2["fp64_plain_value"] = cb64 / sb64
+            c2["speedup_vs_fp64_plain"] = c2["value"] / c2["fp64_plain_value"]
+        extra["blast_128e_3lvl"] = c2
+        log(f"[bench] config 2 (blast_128e_3lvl): {c2['value']:.4e} cell-updates/s")
 
     launches, total_ms, kcells = kt
     avg_s = total_ms / 1e3 / max(launches, 1)
     cells_per_launch = kcells / max(launches, 1)
+    llf = res.get("llf", 0.5)
     fpc = flops_per_cell_update(llf)
     achieved = cells_per_launch * fpc / avg_s
     kname = kernel_name(tuned["shapes"][tuned["choice"]])
+    hbm = cells_per_launch * BYTES_PER_CELL_UPDATE / avg_s
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32_VECTOR / 1e12,
-            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR, "traffic": counted_traffic(kname),
-            "kernel": kname, "avg_launch_ms": avg_s * 1e3,
+            "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR,
+            "traffic": counted_traffic(name, kname),
+            "kernel": kname, "avg_launch_ms": avg_s * 1e3, "launches": launches,
             "cells_per_launch": cells_per_launch, "flop_per_cell_update": fpc,
-            "llf_fraction": llf}
-    ms_step = 1e3 * secs / args.steps
+            "llf_fraction": llf, "llf_source": "oracle, parity steps" if "llf" in res else "assumed",
+            "peak_unpacked_fp32": PEAK_FP32_UNPACKED / 1e12,
+            "frac_of_unpacked": achieved / PEAK_FP32_UNPACKED,
+            "algorithmic_hbm_gbs": hbm / 1e9, "algorithmic_hbm_frac": hbm / PEAK_HBM,
+            "bytes_per_cell_update": BYTES_PER_CELL_UPDATE}
     out = {"metric": "cell-updates/s per RK stage (FP32 batched MR RK3)", "value": value,
            "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-           "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+           "ms_per_step": 1e3 * secs / args.steps, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": pb.name, "levels": pb.lmax + 1, "effective_grid": 128,
-                      "block": "16^3 + 4 halo", "ic": "spherical blast r=0.1, (1,10)|(0.125,0.1), "
-                      "+-1e-3 rho noise", "eps": pb.eps, "cfl": pb.cfl,
-                      "path": "batched FP32, steps replayed from a hipGraph, next step queued ahead"},
-           "roofline": roof, "cpu_baseline": cpu}
+           "config": dict(describe(name, pbs), **{k: stats[k] for k in ("leaves_final", "compression")}),
+           "roofline": roof, "cpu_baseline": res.get("cpu")}
+    if "parity" in res:
+        out["parity_vs_oracle"] = res["parity"]
     out["value_eager_launches"] = value_eager
     out["autotune"] = tuned
+    out["host_adaptation_ms_per_step"] = stats["host_adaptation_ms_per_step"]
     out.update(extra)
     print(json.dumps(out), flush=True)
 

@@ -41,6 +41,14 @@ typedef enum {
 } mrfv_status;
 
 typedef enum { MRFV_F32 = 0, MRFV_F64 = 1 } mrfv_dtype;
+
+/* Flux kernels of Sec. "Numerical Scheme" (the combinations of the weak-scaling runs):
+ * Roe with WENO5-JS (the standard configuration: per characteristic field, upwind when the
+ * two face cells' eigenvalues agree in sign, else a local Lax-Friedrichs split), Roe with
+ * TENO5, local Lax-Friedrichs (Rusanov; every field split, speeds from the two face cells)
+ * with WENO5-JS, and HLLC with WENO-AO(5,3) face states (characteristic-wise). */
+typedef enum { MRFV_ROE_WENO5 = 0, MRFV_ROE_TENO5 = 1, MRFV_LLF_WENO5 = 2,
+               MRFV_HLLC_WAO53 = 3 } mrfv_scheme;
 typedef enum { MRFV_BC_PERIODIC = 0, MRFV_BC_ZEROGRAD = 1 } mrfv_bc;
 
 /* One independent MR problem (one forest of octrees on a box). */
@@ -68,6 +76,7 @@ typedef struct {
                                2: batched path with the CFL step and the three RK stages
                                replayed from one hipGraph (captured on first use, valid
                                across tree changes; FP32)                              */
+    int32_t scheme;         /* mrfv_scheme: the flux kernel of every leaf               */
 } mrfv_config;
 
 typedef struct mrfv_ctx mrfv_ctx;
@@ -130,8 +139,20 @@ int mrfv_mr_predict(mrfv_ctx *ctx, void *U, const int32_t *slots_host, int32_t n
  * thresholds of eq:LevelWiseEpsilon): REFINE (1) if l < lmax and d >= eps_l; COARSEN (-1)
  * if l >= 2, all 8 siblings are leaves with d < eps_l and the parent's d < eps_{l-1};
  * else KEEP (0); non-leaves get 2.  All 26 halo regions must be filled.
+ * The prediction is evaluated in its separable form; a slab of a block whose detail lies
+ * within a narrow band of its threshold (see mrfv_set_detail_band) is evaluated again with
+ * the prediction summed term by term as the appendix writes it (Q_x ... Q_xyz, left to
+ * right, no fused multiply-add) and |u - P| divided by the scale, so that every flag is
+ * the one that evaluation order gives.
  * flags_dev: dev int8[capacity], det_dev: dev double[capacity] (indexed by slot). */
 int mrfv_mr_flag(mrfv_ctx *ctx, const void *U, int8_t *flags_dev, double *det_dev);
+
+/* set_detail_band -- half-width of the band around eps_l inside which mr_flag (and the
+ * adaptation of mrfv_step / mrfv_run) re-evaluates a detail in the appendix's term order
+ * (default 1e-9, in units of the normalised detail).  0 re-evaluates only exact ties; a
+ * large value re-evaluates every block (slow; for checks).  band >= 0, else MRFV_EINVAL.
+ * Synchronises the stream. */
+int mrfv_set_detail_band(mrfv_ctx *ctx, double band);
 
 /* cfl_dt -- eq:Cfl per instance: dt = cfl dx_lmax / sum_d max(|v_d| + c) over leaf
  * interior cells, reduced in double precision.  dt_dev: dev double[n_instances]. */
@@ -212,18 +233,21 @@ int mrfv_kernel_time(mrfv_ctx *ctx, int64_t *launches, double *total_ms, int64_t
  * Uout: dev, state_bytes each, distinct; U0: dev, interior_bytes (written at stage 0, read
  * at stages 1 and 2); dt_dev: dev double[n_instances].  restrict_parents != 0: leaves on
  * level >= 1 none of whose same-level face neighbours is a non-leaf also write the
- * restriction (eq:Projection) of their new interior into their parent's octant of Uout,
+ * restriction (eq:Averaging) of their new interior into their parent's octant of Uout,
  * as the step does for a stage whose output is restricted next.  Batched FP32 contexts
  * only. */
 int mrfv_fused_stage(mrfv_ctx *ctx, int32_t stage, const double *dt_dev, void *Uin, void *Uout,
                      void *U0, int32_t restrict_parents);
 
-/* Launch shapes of the fused rhs + update kernel (batched FP32 path): variant v groups
- * the block's z-planes by shapes_host[3v] and uses |shapes_host[3v+1]| threads per
- * workgroup, one workgroup per leaf, or, when shapes_host[3v+1] < 0, a persistent grid
- * of workgroups looping over the leaves; shapes_host[3v+2] is the number of wavefronts
- * per SIMD the register allocation aims at (1: the compiler's choice).  Every variant
- * gives bitwise the same result.  rhs_variant sets the variant
+/* Launch shapes of the fused rhs + update kernel (batched FP32 path; 14 for the standard
+ * Roe-WENO5 kernel, 3 for the other flux kernels): variant v groups
+ * the block's z-planes by shapes_host[4v] and uses |shapes_host[4v+1]| threads per
+ * workgroup, one workgroup per leaf, or, when shapes_host[4v+1] < 0, a persistent grid
+ * of workgroups looping over the leaves; shapes_host[4v+2] is the number of wavefronts
+ * per SIMD the register allocation aims at (1: the compiler's choice); shapes_host[4v+3]
+ * is 1 when the stencils are always loaded through per-lane pointers (otherwise through
+ * one buffer resource whenever a workgroup's source blocks lie within 4 GiB).  Every
+ * variant gives bitwise the same result.  rhs_variant sets the variant
  * when set >= 0 (captured step graphs are re-captured), writes the number of variants
  * and their shapes (each may be NULL) and returns the current variant (>= 0) or an
  * error.  Host only. */

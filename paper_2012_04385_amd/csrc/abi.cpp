@@ -221,10 +221,10 @@ int do_flux(mrfv_ctx *ctx, const T *U) {
     hipEvent_t ev{};
     timing_begin(ctx, &ev);
     if (ctx->cfg.batched) {
-        HIP_OK(launch_flux<T>(U, wlist(ctx, DESC_LEAVES), ctx->tb, ctx->d_inst, D, FF, ctx->stream));
+        HIP_OK(launch_flux<T>(ctx->cfg.scheme, U, wlist(ctx, DESC_LEAVES), ctx->tb, ctx->d_inst, D, FF, ctx->stream));
     } else {
         for (int l = 0; l <= L.max_level; ++l)
-            HIP_OK(launch_flux<T>(U, wlist(ctx, desc_leaf(l)), ctx->tb, ctx->d_inst, D, FF,
+            HIP_OK(launch_flux<T>(ctx->cfg.scheme, U, wlist(ctx, desc_leaf(l)), ctx->tb, ctx->d_inst, D, FF,
                                   ctx->stream));
     }
     timing_end(ctx, ev, (int64_t)L.all_leaves_cnt * CELLS_I);
@@ -262,7 +262,7 @@ int do_stage_fused(mrfv_ctx *ctx, int stage, const double *dt, const float *Uin,
     hipEvent_t ev{};
     timing_begin(ctx, &ev);
     // the fused kernel has no grid-stride loop: its grid must cover every possible leaf
-    HIP_OK(launch_rhs_update_f32(ctx->rhs_variant, stage, dt, Uin, Uout, U0, wlist(ctx, DESC_LEAVES, 1 << 30), ctx->tb,
+    HIP_OK(launch_rhs_update_f32(ctx->cfg.scheme, ctx->rhs_variant, stage, dt, Uin, Uout, U0, wlist(ctx, DESC_LEAVES, 1 << 30), ctx->tb,
                                  ctx->d_inst, FF, ctx->d_err, restrict_parents ? 1 : 0, cflmax, ctx->stream));
     timing_end(ctx, ev, (int64_t)L.all_leaves_cnt * CELLS_I);
     if (ctx->has_jumps) {
@@ -280,7 +280,7 @@ template <typename T>
 int do_details_flags(mrfv_ctx *ctx, const T *U, int8_t *flags, double *det,
                      int8_t *flags_host = nullptr, int32_t *err_host = nullptr,
                      int32_t *gate = nullptr) {
-    HIP_OK(launch_details<T>(U, wlist(ctx, DESC_FINE), ctx->tb, ctx->d_inst, ctx->d_det4, ctx->stream));
+    HIP_OK(launch_details<T>(U, wlist(ctx, DESC_FINE), ctx->tb, ctx->d_inst, ctx->d_det4, ctx->d_recheck, ctx->stream));
     HIP_OK(launch_flags(wlist(ctx, DESC_ALL), ctx->tb, ctx->d_inst, ctx->d_det4, det, flags, flags_host,
                         ctx->d_err, err_host, gate, ctx->cfg.slot_capacity, ctx->stream));
     return MRFV_OK;
@@ -499,7 +499,7 @@ int do_init(mrfv_ctx *ctx, mrfv_ic_fn ic, void *user, T *U) {
             wf.base = ctx->d_slots;
             wf.n = (int32_t)fresh.size();
             wf.grid = wf.n;
-            HIP_OK(launch_details<T>(U, wf, ctx->tb, ctx->d_inst, ctx->d_det4, ctx->stream));
+            HIP_OK(launch_details<T>(U, wf, ctx->tb, ctx->d_inst, ctx->d_det4, ctx->d_recheck, ctx->stream));
             const int nz = details_parts();
             HIP_OK(hipMemcpyAsync(det4.data(), ctx->d_det4, sizeof(double) * det4.size(),
                                   hipMemcpyDeviceToHost, ctx->stream));
@@ -899,6 +899,7 @@ int mrfv_create(mrfv_ctx **out, const mrfv_config *cfg, const mrfv_instance *ins
     if (cfg->dtype != MRFV_F32 && cfg->dtype != MRFV_F64) return bail(MRFV_EINVAL);
     if (cfg->n_instances < 1 || cfg->n_instances > 4095) return bail(MRFV_EINVAL);
     if (cfg->slot_capacity < 1 || cfg->slot_capacity > (1 << 22)) return bail(MRFV_EINVAL);
+    if (cfg->scheme < MRFV_ROE_WENO5 || cfg->scheme > MRFV_HLLC_WAO53) return bail(MRFV_EINVAL);
     for (int i = 0; i < cfg->n_instances; ++i) {
         if (check_instance(ctx, inst[i], i) != MRFV_OK) return bail(MRFV_EINVAL);
         ctx->inst.push_back(inst[i]);
@@ -917,7 +918,8 @@ int mrfv_create(mrfv_ctx **out, const mrfv_config *cfg, const mrfv_instance *ins
     for (int i = 0; i < cfg->n_instances; ++i) {
         const mrfv_instance &p = inst[i];
         id[i] = InstDev{p.gamma, p.B, p.cfl, p.eps, p.scale_rho, p.scale_E, p.dx0, p.lmax,
-                        {p.n0[0], p.n0[1], p.n0[2]}, {p.bc[0], p.bc[1], p.bc[2]}, p.adapt};
+                        {p.n0[0], p.n0[1], p.n0[2]}, {p.bc[0], p.bc[1], p.bc[2]}, p.adapt,
+                        DETAIL_BAND_DEFAULT};
     }
 #define ALLOC(ptr, bytes)                                                                  \
     if (hipMalloc((void **)&(ptr), (bytes)) != hipSuccess) {                                \
@@ -946,6 +948,7 @@ int mrfv_create(mrfv_ctx **out, const mrfv_config *cfg, const mrfv_instance *ins
     ALLOC(ctx->d_blockred, cap * std::max(5, 3 * cfl_slabs()) * sizeof(double));
     ALLOC(ctx->d_det, cap * sizeof(double));
     ALLOC(ctx->d_det4, cap * details_parts() * sizeof(double));
+    ALLOC(ctx->d_recheck, (2 + cap * details_parts()) * sizeof(int32_t));
     ALLOC(ctx->d_flags, cap);
     ALLOC(ctx->d_slots, cap * sizeof(int32_t));
     ALLOC(ctx->d_slots2, cap * sizeof(int32_t));
@@ -959,7 +962,8 @@ int mrfv_create(mrfv_ctx **out, const mrfv_config *cfg, const mrfv_instance *ins
             hipSuccess ||
         hipMemset(ctx->d_err, 0, sizeof(int32_t)) != hipSuccess ||
         hipMemset(ctx->d_det, 0, cap * sizeof(double)) != hipSuccess ||
-        hipMemset(ctx->d_gate, 0, 2 * sizeof(int32_t)) != hipSuccess)
+        hipMemset(ctx->d_gate, 0, 2 * sizeof(int32_t)) != hipSuccess ||
+        hipMemset(ctx->d_recheck, 0, 2 * sizeof(int32_t)) != hipSuccess)
         return bail(MRFV_EHIP);
     ctx->topo.reset(cfg->slot_capacity, ctx->inst);
     *out = ctx;
@@ -987,7 +991,7 @@ int mrfv_destroy(mrfv_ctx *ctx) {
             if (p) hipFree(p);
     }
     void *ptrs[] = {ctx->d_inst, ctx->d_err, ctx->d_D, ctx->d_W, ctx->d_W2, ctx->d_FF, ctx->d_blockred, ctx->d_det, ctx->d_det4,
-                    ctx->d_flags, ctx->d_slots, ctx->d_slots2, ctx->d_prim, ctx->tb.meta, ctx->tb.child,
+                    ctx->d_recheck, ctx->d_flags, ctx->d_slots, ctx->d_slots2, ctx->d_prim, ctx->tb.meta, ctx->tb.child,
                     ctx->tb.nbr, ctx->tb.lists, ctx->d_desc, ctx->d_desc_g, ctx->d_gate};
     for (void *p : ptrs)
         if (p) hipFree(p);
@@ -1065,6 +1069,17 @@ int mrfv_mr_flag(mrfv_ctx *ctx, const void *U, int8_t *flags_dev, double *det_de
     return ctx->cfg.dtype == MRFV_F64
                ? do_details_flags<double>(ctx, (const double *)U, flags_dev, det_dev)
                : do_details_flags<float>(ctx, (const float *)U, flags_dev, det_dev);
+}
+
+int mrfv_set_detail_band(mrfv_ctx *ctx, double band) {
+    if (!ctx) return MRFV_EINVAL;
+    if (!(band >= 0.0)) return fail(ctx, MRFV_EINVAL, "set_detail_band: band must be >= 0");
+    std::vector<InstDev> id(ctx->inst.size());
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    HIP_OK(hipMemcpy(id.data(), ctx->d_inst, sizeof(InstDev) * id.size(), hipMemcpyDeviceToHost));
+    for (InstDev &d : id) d.detail_band = band;
+    HIP_OK(hipMemcpy(ctx->d_inst, id.data(), sizeof(InstDev) * id.size(), hipMemcpyHostToDevice));
+    return MRFV_OK;
 }
 
 int mrfv_cfl_dt(mrfv_ctx *ctx, const void *U, double *dt_dev) {
@@ -1256,11 +1271,12 @@ int mrfv_fused_stage(mrfv_ctx *ctx, int32_t stage, const double *dt_dev, void *U
 
 int mrfv_rhs_variant(mrfv_ctx *ctx, int32_t set, int32_t *n_variants, int32_t *shapes) {
     if (!ctx) return MRFV_EINVAL;
-    const int n = rhs_variants();
+    const int n = rhs_variants(ctx->cfg.scheme);
     if (n_variants) *n_variants = n;
     if (shapes)
         for (int v = 0; v < n; ++v)
-            rhs_variant_shape(v, shapes + 3 * v, shapes + 3 * v + 1, shapes + 3 * v + 2);
+            rhs_variant_shape(ctx->cfg.scheme, v, shapes + 4 * v, shapes + 4 * v + 1, shapes + 4 * v + 2,
+                              shapes + 4 * v + 3);
     if (set >= n) return fail(ctx, MRFV_EINVAL, "rhs_variant: index out of range");
     if (set >= 0 && set != ctx->rhs_variant) {
         ctx->rhs_variant = set;
@@ -1290,12 +1306,12 @@ int mrfv_autotune(mrfv_ctx *ctx, void *U, void *U0, double *dt_dev, int32_t reps
     HIP_OK(hipEventCreate(&b));
     int best = -1;
     float best_ms = 0.f;
-    for (int v = 0; v < rhs_variants(); ++v) {
-        HIP_OK(launch_rhs_update_f32(v, 0, dt_dev, X, W, (float *)U0, wl, ctx->tb, ctx->d_inst,
+    for (int v = 0; v < rhs_variants(ctx->cfg.scheme); ++v) {
+        HIP_OK(launch_rhs_update_f32(ctx->cfg.scheme, v, 0, dt_dev, X, W, (float *)U0, wl, ctx->tb, ctx->d_inst,
                                      (float *)ctx->d_FF, ctx->d_err, 0, nullptr, st));
         HIP_OK(hipEventRecord(a, st));
         for (int r = 0; r < reps; ++r)
-            HIP_OK(launch_rhs_update_f32(v, 0, dt_dev, X, W, (float *)U0, wl, ctx->tb, ctx->d_inst,
+            HIP_OK(launch_rhs_update_f32(ctx->cfg.scheme, v, 0, dt_dev, X, W, (float *)U0, wl, ctx->tb, ctx->d_inst,
                                          (float *)ctx->d_FF, ctx->d_err, 0, nullptr, st));
         HIP_OK(hipEventRecord(b, st));
         HIP_OK(hipEventSynchronize(b));

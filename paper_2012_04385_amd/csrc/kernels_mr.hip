@@ -308,6 +308,85 @@ __global__ __launch_bounds__(TPB) void k_predict(T *__restrict__ U,
             predict_cell<T, T>(pu + q * CELLS_P, m.bx & 1, m.by & 1, m.bz & 1, i, j, k);
 }
 
+__device__ __forceinline__ double eps_level(const InstDev &P, int l) {
+    return ldexp(P.eps, -3 * (P.lmax - l));
+}
+
+// Prediction of child padded cell (i, j, k) in the form the appendix writes it: the
+// parent value plus the signed Q-terms in the order Q_x, Q_y, Q_z, Q_xy, Q_xz, Q_yz,
+// Q_xyz, each a weighted sum of sign-alternating differences of the parent's 5^3
+// neighbourhood in the appendix's term order, every sum taken left to right and no
+// multiply fused with an add.  The terms are walked by loops that are not unrolled, so
+// the loads stay few at a time.  Slower than the separable form (125 loads per cell), it
+// is used only where a detail lies within a narrow band around its threshold: there the flag is
+// decided on this value.
+template <typename T>
+__device__ double predict_qterms(const T *__restrict__ pu, int ox, int oy, int oz, int i, int j,
+                                 int k) {
+#pragma clang fp contract(off)
+    const int ci = i - HW, cj = j - HW, ck = k - HW;
+    const int I = ox * (NI / 2) + (ci >> 1) + HW;
+    const int J = oy * (NI / 2) + (cj >> 1) + HW;
+    const int K = oz * (NI / 2) + (ck >> 1) + HW;
+    const T *pc = pu + (K * NP + J) * NP + I;
+    auto u = [&](int off) -> double { return (double)pc[off]; };
+    const double c0 = -22.0 / 128.0, c1 = 3.0 / 128.0;
+    const int st[3] = {1, NP, NP * NP};
+    const double sg[3] = {(ci & 1) ? -1.0 : 1.0, (cj & 1) ? -1.0 : 1.0, (ck & 1) ? -1.0 : 1.0};
+    // two-axis groups: offsets (a along the first axis, b along the second) and weights
+    const int A2[4] = {1, 2, 1, 2}, B2[4] = {1, 2, 2, 1};
+    const double W2[4] = {c0 * c0, c1 * c1, c0 * c1, c1 * c0};
+    // three-axis groups (x, y, z offsets) and weights
+    const int A3[8] = {1, 2, 1, 2, 1, 2, 1, 2}, B3[8] = {1, 2, 1, 2, 2, 1, 2, 1};
+    const int C3[8] = {1, 2, 2, 1, 2, 1, 1, 2};
+    const double W3[8] = {c0 * c0 * c0, c1 * c1 * c1, c0 * c0 * c1, c1 * c1 * c0,
+                          c0 * c1 * c1, c1 * c0 * c0, c0 * c1 * c0, c1 * c0 * c1};
+    const int masks[7] = {1, 2, 4, 3, 5, 6, 7};   // x, y, z, xy, xz, yz, xyz
+    double pred = u(0);
+#pragma unroll 1
+    for (int t = 0; t < 7; ++t) {
+        const int mk = masks[t];
+        double sign = 1.0;
+        int ax[3], na = 0;
+        for (int a = 0; a < 3; ++a)
+            if (mk & (1 << a)) {
+                sign = sign * sg[a];
+                ax[na++] = a;
+            }
+        double q = 0.0;
+        if (na == 1) {
+            const int o = st[ax[0]];
+            q = c0 * (u(o) - u(-o));
+            q = q + c1 * (u(2 * o) - u(-2 * o));
+        } else if (na == 2) {
+#pragma unroll 1
+            for (int g = 0; g < 4; ++g) {
+                const int a = A2[g] * st[ax[0]], b = B2[g] * st[ax[1]];
+                const double cr = (u(a + b) + u(-a - b)) - (u(-a + b) + u(a - b));
+                q = g == 0 ? W2[0] * cr : q + W2[g] * cr;
+            }
+        } else {
+#pragma unroll 1
+            for (int g = 0; g < 8; ++g) {
+                const int a = A3[g], b = B3[g] * NP, c = C3[g] * NP * NP;
+                const double gr = (u(a + b + c) - u(-a - b - c)) + (u(-a - b + c) - u(a + b - c)) +
+                                  (u(a - b - c) - u(-a + b + c)) + (u(-a + b - c) - u(a - b + c));
+                q = g == 0 ? W3[0] * gr : q + W3[g] * gr;
+            }
+        }
+        pred = pred + sign * q;
+    }
+    return pred;
+}
+
+// The band around a level's threshold inside which a slab's detail is recomputed with
+// predict_qterms (InstDev::detail_band, 1e-9 unless set otherwise).  The separable and the
+// Q-term forms of the prediction differ by a few units in the last place of the
+// normalised field values (below 1e-12 for values up to 1e3 times their scale), so
+// outside the band both forms fall on the same side of the threshold and the flags equal
+// those of the Q-term form everywhere.
+constexpr int DETAIL_EXACT_GRID = 64;   // workgroups of k_details_exact (loop over the list)
+
 // Details, FP64.  DZ workgroups per block (level >= 1), each for a slab of 24/DZ padded
 // z-planes, write their maxima of the rho and E details over the slab to det4[slot][part];
 // the detail of the block is the maximum over its slabs (formed by k_flags).  The prediction is applied separably through LDS, in
@@ -336,7 +415,7 @@ __global__ __launch_bounds__(DTPB) void k_details(const T *__restrict__ U, WorkL
                                                  const BlockMeta *__restrict__ meta,
                                                  const int32_t *__restrict__ nbr,
                                                  const InstDev *__restrict__ inst,
-                                                 double *__restrict__ det4) {
+                                                 double *__restrict__ det4, int32_t *recheck) {
     constexpr int R = NI;                       // parent region edge in x and y (16)
     constexpr int NPAIR = NP / 2;               // sibling pairs along a padded axis (12)
     constexpr int NA = (PZ * R * R + DTPB - 1) / DTPB;        // parent loads per thread (4)
@@ -346,6 +425,7 @@ __global__ __launch_bounds__(DTPB) void k_details(const T *__restrict__ U, WorkL
     __shared__ double Cz[SZ * R * R];           // z pass [kc][jj][ii]
     __shared__ double Cx[SZ * R * NP];          // x pass [kc][jj][i]
     __shared__ double red[DTPB / 64];
+    __shared__ double slab_max;
     const int nb = wl.count();
     const int part = blockIdx.y;
     const int k_lo = part * SZ;                 // first padded output plane
@@ -455,14 +535,87 @@ __global__ __launch_bounds__(DTPB) void k_details(const T *__restrict__ U, WorkL
     if (tid == 0) {
         double mx = red[0];
         for (int w = 1; w < DTPB / 64; ++w) mx = fmax(mx, red[w]);
+        slab_max = mx;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        const double mx = slab_max;
         det4[(size_t)slot * DZ + part] = mx;
+        // near the threshold: the slab is evaluated again by k_details_exact
+        if (fabs(mx - eps_level(P, m.level)) <= P.detail_band) {
+            const int at = atomicAdd(recheck, 1);
+            recheck[2 + at] = slot * DZ + part;   // the list holds every slab of every slot
+        }
     }
     __syncthreads();
     }
 }
 
-__device__ __forceinline__ double eps_level(const InstDev &P, int l) {
-    return ldexp(P.eps, -3 * (P.lmax - l));
+// Slabs listed by k_details (their maximum lies within the band around the threshold):
+// the maximum again with the Q-term prediction and |u - P| / scale divided, not
+// multiplied by the reciprocal, which is how the flags are decided there.  A fixed grid
+// loops over the list; the last workgroup to finish clears the list for the next launch.
+constexpr int XTPB = 256;
+template <typename T>
+__global__ __launch_bounds__(XTPB) void k_details_exact(const T *__restrict__ U,
+                                                       const BlockMeta *__restrict__ meta,
+                                                       const int32_t *__restrict__ nbr,
+                                                       const InstDev *__restrict__ inst,
+                                                       double *__restrict__ det4,
+                                                       int32_t *recheck) {
+    __shared__ double red[XTPB / 64];
+    __shared__ long long srcs[27];
+    const int tid = threadIdx.x;
+    const int n = __atomic_load_n(recheck, __ATOMIC_RELAXED);
+    for (int it = blockIdx.x; it < n; it += gridDim.x) {
+        const int item = recheck[2 + it];
+        const int slot = item / DZ, part = item % DZ;
+        const BlockMeta m = meta[slot];
+        const InstDev P = inst[m.inst];
+        const int ox = m.bx & 1, oy = m.by & 1, oz = m.bz & 1;
+        const T *pu = U + (size_t)m.parent * 5 * CELLS_P;
+        if (tid < 27) {
+            // the source of each halo region, as k_details reads it
+            const int ex = tid % 3 - 1, ey = (tid / 3) % 3 - 1, ez = tid / 9 - 1;
+            const bool zg = (ex < 0 && (m.zg & 1)) || (ex > 0 && (m.zg & 2)) ||
+                            (ey < 0 && (m.zg & 4)) || (ey > 0 && (m.zg & 8)) ||
+                            (ez < 0 && (m.zg & 16)) || (ez > 0 && (m.zg & 32));
+            const int s = (tid == 13 || zg) ? -1 : nbr[(size_t)slot * 27 + tid];
+            srcs[tid] = s >= 0 ? (long long)s * 5 * CELLS_P - NI * (ex + NP * (ey + NP * ez))
+                               : (long long)slot * 5 * CELLS_P;
+        }
+        __syncthreads();
+        double e = 0.0;
+        for (int t = tid; t < SZ * NP * NP; t += XTPB) {
+            const int i = t % NP, j = (t / NP) % NP, k = part * SZ + t / (NP * NP);
+            const int r = ((k < HW ? 0 : (k < HW + NI ? 1 : 2)) * 3 +
+                           (j < HW ? 0 : (j < HW + NI ? 1 : 2))) * 3 +
+                          (i < HW ? 0 : (i < HW + NI ? 1 : 2));
+            const long long so = srcs[r];
+            for (int v = 0; v < 2; ++v) {
+                const double uq = (double)U[so + 4 * v * CELLS_P + pidx(0, k, j, i)];
+                const double pv = predict_qterms(pu + 4 * v * CELLS_P, ox, oy, oz, i, j, k);
+                e = fmax(e, fabs(uq - pv) / (v == 0 ? P.scale_rho : P.scale_E));
+            }
+        }
+        for (int off = 32; off > 0; off >>= 1) e = fmax(e, __shfl_xor(e, off));
+        if ((tid & 63) == 0) red[tid >> 6] = e;
+        __syncthreads();
+        if (tid == 0) {
+            double mx = red[0];
+            for (int w = 1; w < XTPB / 64; ++w) mx = fmax(mx, red[w]);
+            det4[(size_t)slot * DZ + part] = mx;
+        }
+        __syncthreads();
+    }
+    // the last workgroup out resets the list (every workgroup has read its count)
+    if (tid == 0) {
+        __threadfence();
+        if (atomicAdd(recheck + 1, 1) == (int)gridDim.x - 1) {
+            recheck[0] = 0;
+            recheck[1] = 0;
+        }
+    }
 }
 
 // Flags of all listed blocks (2 on non-leaves), from the details' slab maxima; also the
@@ -620,13 +773,17 @@ __global__ __launch_bounds__(CTPB) void k_cfl_inst(WorkList leaves,
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double s = 0.0;
+        double m[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            double m = red[a][0];
-            for (int w = 1; w < CTPB / 64; ++w) m = fmax(m, red[a][w]);
-            s += m;
+            m[a] = red[a][0];
+            for (int w = 1; w < CTPB / 64; ++w) m[a] = fmax(m[a], red[a][w]);
         }
+        // the three directional maxima are added in ascending order: dt does not depend
+        // on the labelling of the axes
+        const double lo = fmin(fmin(m[0], m[1]), m[2]), hi = fmax(fmax(m[0], m[1]), m[2]);
+        const double mid = fmax(fmin(m[0], m[1]), fmin(fmax(m[0], m[1]), m[2]));   // median
+        const double s = (lo + mid) + hi;
         const InstDev P = inst[ins];
         const double dx = ldexp(P.dx0, -P.lmax);
         if (n > 0) dt[ins] = P.cfl * dx / s;
@@ -727,10 +884,12 @@ hipError_t launch_predict(T *U, const int32_t *list, int n, const DevTables &tb,
 
 template <typename T>
 hipError_t launch_details(const T *U, const WorkList &wl, const DevTables &tb,
-                          const InstDev *inst, double *det4, hipStream_t st) {
+                          const InstDev *inst, double *det4, int32_t *recheck, hipStream_t st) {
     if (wl.grid <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_details<T>, grid2(round_xcd(wl.grid), DZ), dim3(DTPB), 0, st, U, wl,
-                       tb.meta, tb.nbr, inst, det4);
+                       tb.meta, tb.nbr, inst, det4, recheck);
+    hipLaunchKernelGGL(k_details_exact<T>, dim3(DETAIL_EXACT_GRID), dim3(XTPB), 0, st, U, tb.meta,
+                       tb.nbr, inst, det4, recheck);
     return hipGetLastError();
 }
 
@@ -794,7 +953,7 @@ hipError_t launch_totals(const T *U, const WorkList &leaves, const DevTables &tb
     template hipError_t launch_predict<T>(T *, const int32_t *, int, const DevTables &,    \
                                           hipStream_t);                                     \
     template hipError_t launch_details<T>(const T *, const WorkList &, const DevTables &,   \
-                                          const InstDev *, double *, hipStream_t);          \
+                                          const InstDev *, double *, int32_t *, hipStream_t); \
     template hipError_t launch_cfl<T>(const T *, const WorkList &, const DevTables &,       \
                                       const InstDev *, int, double *, double *, hipStream_t, \
                                       int32_t *, const int32_t *, int32_t *, int);          \

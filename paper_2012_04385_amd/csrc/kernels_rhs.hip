@@ -110,11 +110,102 @@ __device__ __forceinline__ T weno5(T a, T b, T c, T d, T e) {
     return fma(num, rcp_(den), c);
 }
 
-// Characteristic flux of one field: upwind by the two face cells' eigenvalues, else LLF.
+// TENO5 (Fu, Hu & Adams 2016) at the right face of c: the three 3-cell candidates of
+// WENO5 with the optimal weights (0.1, 0.6, 0.3), each kept (weight as is) or dropped
+// (weight 0) by the cut-off test chi_k >= C_T with chi_k = gamma_k / sum_j gamma_j,
+// gamma_k = (1 + tau5 / (beta_k + eps))^6, tau5 = |beta_0 - beta_2|, C_T = 1e-5.  The test
+// is evaluated as (R_k / R_m)^6 >= C_T sum_j (R_j / R_m)^6 with R = 1 + tau5 / (beta + eps)
+// and m the candidate with the smallest beta (largest R), which cannot overflow; eps is
+// 1e-40 in FP64 and 1e-30 in FP32 (above the smallest normal float).
 template <typename T>
+__device__ __forceinline__ T teno5(T a, T b, T c, T d, T e) {
+    const T w0 = b - a, u = c - b, v = d - c, w3 = e - d;
+    const T t0 = u - w0, s0 = fma((T)2, u, t0);
+    const T t1 = v - u, s1 = u + v;
+    const T t2 = w3 - v, s2 = fma((T)-2, v, t2);
+    const T k13 = (T)(13.0 / 12.0), eps = sizeof(T) == 8 ? (T)1e-40 : (T)1e-30;
+    const T e0 = fma(k13 * t0, t0, fma((T)0.25 * s0, s0, eps));
+    const T e1 = fma(k13 * t1, t1, fma((T)0.25 * s1, s1, eps));
+    const T e2 = fma(k13 * t2, t2, fma((T)0.25 * s2, s2, eps));
+    const T tau = fabs(e0 - e2);
+    const T em = fmin(e0, fmin(e1, e2));
+    const T fm = em * rcp_(em + tau);                 // 1 / R_m
+    auto ratio6 = [&](T ek) {
+        const T r = (ek + tau) * rcp_(ek) * fm;       // R_k / R_m in (0, 1]
+        const T r2 = r * r;
+        return r2 * r2 * r2;
+    };
+    const T g0 = ratio6(e0), g1 = ratio6(e1), g2 = ratio6(e2);
+    const T cut = (T)1e-5 * ((g0 + g1) + g2);
+    const T d0 = g0 >= cut ? (T)1 : (T)0, d1 = g1 >= cut ? (T)1 : (T)0, d2 = g2 >= cut ? (T)1 : (T)0;
+    // sum_k d_k delta_k (q_k - c) / sum_k d_k delta_k with q_k - c = (r0, r1, r2) / 6
+    const T h0 = fma((T)(5.0 / 6.0), u, (T)(-1.0 / 3.0) * w0);   // r0 / 6
+    const T h1 = fma((T)2, v, u);                                  // r1
+    const T h2 = fma((T)2, v, (T)-0.5 * w3);                       // r2 / 2
+    const T num = fma(d0, h0, fma(d1, h1, d2 * h2));
+    const T den = fma((T)6, d1, fma((T)3, d2, d0));
+    return fma(num, rcp_(den), c);
+}
+
+// WENO-AO(5,3) (Balsara, Garain & Shu 2016) at the right face of c: the fifth-order value
+// q5 and the three third-order candidates q_l, q_c, q_r combined as
+//   (w4 / g4)(q5 - g1 q_l - g2 q_c - g3 q_r) + w1 q_l + w2 q_c + w3 q_r,
+// linear weights g = ((1-gH)(1-gL)/2, (1-gH) gL, (1-gH)(1-gL)/2, gH), gH = gL = 0.85,
+// normalised weights w_k ~ g_k / (eps + beta_k)^2 (eps = 1e-6), beta_1..3 the Jiang-Shu
+// indicators and beta_4 that of the quartic through all five cells, in Legendre form:
+//   beta_4 = (U1 + U3/10)^2 + 13/3 (U2 + 123/455 U4)^2 + 781/20 U3^2 + 1421461/2275 U4^2.
+// Evaluated relative to c (every candidate minus c), so a constant stencil returns c.
+template <typename T>
+__device__ __forceinline__ T wao53(T a, T b, T c, T d, T e) {
+    const T w0 = b - a, u = c - b, v = d - c, w3 = e - d;
+    const T t0 = u - w0, s0 = fma((T)2, u, t0);
+    const T t1 = v - u, s1 = u + v;
+    const T t2 = w3 - v, s2 = fma((T)-2, v, t2);
+    const T k13 = (T)(13.0 / 12.0), eps = (T)1e-6;
+    const T b1 = fma(k13 * t0, t0, (T)0.25 * s0 * s0);
+    const T b2 = fma(k13 * t1, t1, (T)0.25 * s1 * s1);
+    const T b3 = fma(k13 * t2, t2, (T)0.25 * s2 * s2);
+    const T U1 = ((T)11 * (a - e) + (T)82 * (d - b)) * (T)(1.0 / 120.0);
+    const T U2 = ((T)-3 * (a + e) + (T)40 * (b + d) - (T)74 * c) * (T)(1.0 / 56.0);
+    const T U3 = ((e - a) + (T)2 * (b - d)) * (T)(1.0 / 12.0);
+    const T U4 = ((a + e) - (T)4 * (b + d) + (T)6 * c) * (T)(1.0 / 24.0);
+    const T p1 = fma((T)0.1, U3, U1), p2 = fma((T)(123.0 / 455.0), U4, U2);
+    const T b4 = fma(p1, p1, fma((T)(13.0 / 3.0) * p2, p2,
+                                 fma((T)(781.0 / 20.0) * U3, U3, (T)(1421461.0 / 2275.0) * U4 * U4)));
+    const T g1 = (T)(0.15 * 0.15 / 2.0), g2 = (T)(0.15 * 0.85), g3 = g1, g4 = (T)0.85;
+    auto wt = [&](T g, T beta) {
+        const T x = eps + beta;
+        return g * rcp_(x * x);
+    };
+    const T wl = wt(g1, b1), wc = wt(g2, b2), wr = wt(g3, b3), wh = wt(g4, b4);
+    const T ql = fma((T)(5.0 / 6.0), u, (T)(-1.0 / 3.0) * w0);            // q_l - c
+    const T qc = fma((T)(1.0 / 3.0), v, (T)(1.0 / 6.0) * u);              // q_c - c
+    const T qr = fma((T)(2.0 / 3.0), v, (T)(-1.0 / 6.0) * w3);            // q_r - c
+    const T q5 = fma((T)0.1, ql, fma((T)0.6, qc, (T)0.3 * qr));           // q5 - c
+    const T hi = q5 - fma(g1, ql, fma(g2, qc, g3 * qr));
+    const T num = fma(wh * (T)(1.0 / 0.85), hi, fma(wl, ql, fma(wc, qc, wr * qr)));
+    const T den = (wl + wc) + (wr + wh);
+    return fma(num, rcp_(den), c);
+}
+
+// Flux kernels of Sec. "Numerical Scheme" (the weak-scaling combinations).
+enum { SCH_ROE_WENO5 = 0, SCH_ROE_TENO5 = 1, SCH_LLF_WENO5 = 2, SCH_HLLC_WAO53 = 3 };
+
+// Reconstruction of the flux-splitting kernels at the right face of c.
+template <int SCH, typename T>
+__device__ __forceinline__ T recon(T a, T b, T c, T d, T e) {
+    if constexpr (SCH == SCH_ROE_TENO5) return teno5(a, b, c, d, e);
+    else return weno5(a, b, c, d, e);
+}
+
+// Characteristic flux of one field: upwind by the two face cells' eigenvalues, else LLF
+// (always LLF for the LLF kernel).
+template <int SCH, typename T>
 __device__ __forceinline__ T char_flux(const T W[6], const T G[6], T lL, T lR) {
-    if (lL > (T)0 && lR > (T)0) return weno5(G[0], G[1], G[2], G[3], G[4]);
-    if (lL < (T)0 && lR < (T)0) return weno5(G[5], G[4], G[3], G[2], G[1]);
+    if (SCH != SCH_LLF_WENO5) {
+        if (lL > (T)0 && lR > (T)0) return recon<SCH>(G[0], G[1], G[2], G[3], G[4]);
+        if (lL < (T)0 && lR < (T)0) return recon<SCH>(G[5], G[4], G[3], G[2], G[1]);
+    }
     const T al = fmax(fabs(lL), fabs(lR));
     T gp[6], gm[6];
 #pragma unroll
@@ -122,7 +213,7 @@ __device__ __forceinline__ T char_flux(const T W[6], const T G[6], T lL, T lR) {
         gp[j] = (T)0.5 * (G[j] + al * W[j]);
         gm[j] = (T)0.5 * (G[j] - al * W[j]);
     }
-    return weno5(gp[0], gp[1], gp[2], gp[3], gp[4]) + weno5(gm[5], gm[4], gm[3], gm[2], gm[1]);
+    return recon<SCH>(gp[0], gp[1], gp[2], gp[3], gp[4]) + recon<SCH>(gm[5], gm[4], gm[3], gm[2], gm[1]);
 }
 
 // Same result with at most two WENO evaluations per wavefront: if any lane of the wave
@@ -135,16 +226,16 @@ __device__ __forceinline__ T char_flux(const T W[6], const T G[6], T lL, T lR) {
 // (cp, ap) = (1, 0) upwind-right, (0, 0) upwind-left, (1/2, a/2) LLF: g+ = (G + a W)/2
 // rounded once (halving is exact), g- = (G - a W)/2 up to rounding, and exactly G, 0 on
 // the upwind lanes.
-template <typename T>
+template <int SCH, typename T>
 __device__ __forceinline__ T char_flux_uniform(const T W[6], const T G[6], T lL, T lR) {
-    const bool up = lL > (T)0 && lR > (T)0;
-    const bool dn = lL < (T)0 && lR < (T)0;
+    const bool up = SCH != SCH_LLF_WENO5 && lL > (T)0 && lR > (T)0;
+    const bool dn = SCH != SCH_LLF_WENO5 && lL < (T)0 && lR < (T)0;
     const bool llf = !(up || dn);
-    if (!__any(llf)) {
+    if (SCH != SCH_LLF_WENO5 && !__any(llf)) {
         // the stencil in upwind order, selected per lane from scalar copies (a select
         // between elements of G itself becomes a dynamically indexed array)
         const T g0 = G[0], g1 = G[1], g2 = G[2], g3 = G[3], g4 = G[4], g5 = G[5];
-        return weno5(up ? g0 : g5, up ? g1 : g4, up ? g2 : g3, up ? g3 : g2, up ? g4 : g1);
+        return recon<SCH>(up ? g0 : g5, up ? g1 : g4, up ? g2 : g3, up ? g3 : g2, up ? g4 : g1);
     }
     const T ha = (T)0.5 * fmax(fabs(lL), fabs(lR));
     const T cp = up ? (T)1 : (dn ? (T)0 : (T)0.5);
@@ -155,11 +246,45 @@ __device__ __forceinline__ T char_flux_uniform(const T W[6], const T G[6], T lL,
         gp[j] = fma(ap, W[j], cp * G[j]);
         gm[j] = G[j] - gp[j];
     }
-    return weno5(gp[0], gp[1], gp[2], gp[3], gp[4]) + weno5(gm[5], gm[4], gm[3], gm[2], gm[1]);
+    return recon<SCH>(gp[0], gp[1], gp[2], gp[3], gp[4]) + recon<SCH>(gm[5], gm[4], gm[3], gm[2], gm[1]);
+}
+
+// HLLC flux (Toro, Spruce & Speares 1994) between two rotated conservative states
+// (rho, m_n, m_t1, m_t2, E); wave speeds S_L = min(u_L - c_L, u~ - c~), S_R = max(u_R + c_R,
+// u~ + c~) from the Roe average of the two states.
+template <typename T>
+__device__ __forceinline__ void hllc(const T UL[5], const T UR[5], const Gas<T> &G, T F[5]) {
+    const T irl = rcp_(UL[0]), irr = rcp_(UR[0]);
+    const T ul = UL[1] * irl, ur = UR[1] * irr;
+    const T pl = fma(G.gm1, fma((T)-0.5 * fma(UL[3], UL[3], fma(UL[2], UL[2], UL[1] * UL[1])), irl, UL[4]), -(G.g * G.B));
+    const T pr = fma(G.gm1, fma((T)-0.5 * fma(UR[3], UR[3], fma(UR[2], UR[2], UR[1] * UR[1])), irr, UR[4]), -(G.g * G.B));
+    const T cl = sqrt_(G.g * (pl + G.B) * irl), cr = sqrt_(G.g * (pr + G.B) * irr);
+    const T sl = sqrt_(UL[0]), sr = sqrt_(UR[0]);
+    const T iw = rcp_(sl + sr);
+    const T ut = (sl * ul + sr * ur) * iw;
+    const T vt = (sl * (UL[2] * irl) + sr * (UR[2] * irr)) * iw;
+    const T wt = (sl * (UL[3] * irl) + sr * (UR[3] * irr)) * iw;
+    const T Ht = (sl * ((UL[4] + pl) * irl) + sr * ((UR[4] + pr) * irr)) * iw;
+    const T ct = sqrt_(G.gm1 * (Ht - (T)0.5 * (ut * ut + vt * vt + wt * wt)));
+    const T SL = fmin(ul - cl, ut - ct), SR = fmax(ur + cr, ut + ct);
+    const T ml = UL[0] * (SL - ul), mr = UR[0] * (SR - ur);
+    const T Ss = (pr - pl + ul * ml - ur * mr) * rcp_(ml - mr);
+    // side K: the physical flux, plus S_K (U*_K - U_K) when the face lies in the star region
+    const bool left = SL >= (T)0 || Ss >= (T)0;
+    const T *U = left ? UL : UR;
+    const T ir = left ? irl : irr, un = left ? ul : ur, p = left ? pl : pr;
+    const T S = left ? SL : SR, m = left ? ml : mr;
+    const T Fk[5] = {U[1], fma(U[1], un, p), U[2] * un, U[3] * un, (U[4] + p) * un};
+    const bool star = left ? SL < (T)0 : SR > (T)0;
+    const T f = m * rcp_(S - Ss);
+    const T Us[5] = {f, f * Ss, f * (U[2] * ir), f * (U[3] * ir),
+                     f * fma(Ss - un, Ss + p * rcp_(m), U[4] * ir)};
+#pragma unroll
+    for (int k = 0; k < 5; ++k) F[k] = star ? fma(S, Us[k] - U[k], Fk[k]) : Fk[k];
 }
 
 // Numerical flux through the face between window cells 2 and 3 (rotated components).
-template <typename T, bool UNIFORM = false>
+template <typename T, bool UNIFORM = false, int SCH = SCH_ROE_WENO5>
 __device__ __forceinline__ void face_flux(const CellState<T> w[6], const Gas<T> &G, T F[5]) {
     const CellState<T> &L = w[2], &R = w[3];
     const T inv = rcp_(L.sr + R.sr);
@@ -199,12 +324,53 @@ __device__ __forceinline__ void face_flux(const CellState<T> w[6], const Gas<T> 
         gt1[j] = s.mt1 * un - v * s.mn;
         gt2[j] = s.mt2 * un - ww * s.mn;
     }
+    if constexpr (SCH == SCH_HLLC_WAO53) {
+        // face states: WENO-AO(5,3) of the characteristic variables (left-biased from cells
+        // 0..4, right-biased from cells 5..1), back to conservative components; a state
+        // that is not physical falls back to the face cell's own state
+        T wlf[5], wrf[5];
+        {
+            T Wm[6];
+#pragma unroll
+            for (int m = 0; m < 5; ++m) {
+#pragma unroll
+                for (int j = 0; j < 6; ++j)
+                    Wm[j] = m == 0 ? tU[j] - xU[j]
+                          : m == 1 ? fma((T)-2, tU[j], a0[j])
+                          : m == 2 ? wt1[j]
+                          : m == 3 ? wt2[j]
+                                   : tU[j] + xU[j];
+                wlf[m] = wao53(Wm[0], Wm[1], Wm[2], Wm[3], Wm[4]);
+                wrf[m] = wao53(Wm[5], Wm[4], Wm[3], Wm[2], Wm[1]);
+            }
+        }
+        T UL[5], UR[5];
+        auto back = [&](const T g_[5], T out[5]) {
+            const T s15_ = g_[0] + g_[4];
+            out[0] = s15_ + g_[1];
+            out[1] = u * out[0] + c * (g_[4] - g_[0]);
+            out[2] = v * out[0] + g_[2];
+            out[3] = ww * out[0] + g_[3];
+            out[4] = H * s15_ + u * c * (g_[4] - g_[0]) + (T)0.5 * q2 * g_[1] + v * g_[2] + ww * g_[3];
+        };
+        back(wlf, UL);
+        back(wrf, UR);
+        auto physical = [&](const T U_[5]) {
+            const T pk = fma(G.gm1, fma((T)-0.5 * fma(U_[3], U_[3], fma(U_[2], U_[2], U_[1] * U_[1])),
+                                        rcp_(U_[0]), U_[4]), -(G.g * G.B));
+            return U_[0] > (T)0 && pk + G.B > (T)0;
+        };
+        if (!physical(UL)) { UL[0] = L.r; UL[1] = L.mn; UL[2] = L.mt1; UL[3] = L.mt2; UL[4] = L.E; }
+        if (!physical(UR)) { UR[0] = R.r; UR[1] = R.mn; UR[2] = R.mt1; UR[3] = R.mt2; UR[4] = R.E; }
+        hllc(UL, UR, G, F);
+        return;
+    }
     const T unL = L.mn * L.ir, unR = R.mn * R.ir;
     T W[6], Gc[6], g[5];
     // field 1: u - c
 #pragma unroll
     for (int j = 0; j < 6; ++j) { W[j] = tU[j] - xU[j]; Gc[j] = tF[j] - xF[j]; }
-#define MRFV_CF(W_, G_, a_, b_) (UNIFORM ? char_flux_uniform(W_, G_, a_, b_) : char_flux(W_, G_, a_, b_))
+#define MRFV_CF(W_, G_, a_, b_) (UNIFORM ? char_flux_uniform<SCH>(W_, G_, a_, b_) : char_flux<SCH>(W_, G_, a_, b_))
     g[0] = MRFV_CF(W, Gc, unL - L.c, unR - R.c);
     // field 2: entropy, u
 #pragma unroll
@@ -245,7 +411,7 @@ __device__ __forceinline__ int pencil_base(int r, int m) {
 
 // Walks the pencil (r, m) along DIR: 17 faces, flux differences for 16 cells.
 // sink.cell(q_phys, cell, dF) and sink.face(side, q_phys, F) receive the results.
-template <typename T, int DIR, class Sink>
+template <typename T, int DIR, int SCH, class Sink>
 __device__ __forceinline__ void pencil(const T *__restrict__ ub, int r, int m, const Gas<T> &G,
                                        Sink &sink) {
     constexpr int S = Axes<DIR>::STRIDE;
@@ -263,7 +429,7 @@ __device__ __forceinline__ void pencil(const T *__restrict__ ub, int r, int m, c
         load_state<T, DIR>(ub, base + (f + 6) * S, G, w[5]);
         derive_state(G, w[5]);
         T F[5];
-        face_flux(w, G, F);
+        face_flux<T, false, SCH>(w, G, F);
         if (f == 0) {
 #pragma unroll
             for (int k = 0; k < 5; ++k) sink.face(2 * DIR, qmap[k], F[k]);
@@ -299,7 +465,7 @@ struct GlobalSink {
     __device__ void face(int side, int q, T v) { FF[(side * 5 + q) * FACE + rm] = v; }
 };
 
-template <typename T>
+template <typename T, int SCH>
 __global__ __launch_bounds__(TPB) void k_flux(const T *__restrict__ U, WorkList wl,
                                               const BlockMeta *__restrict__ meta,
                                               const InstDev *__restrict__ inst, T *D, T *FF) {
@@ -311,9 +477,9 @@ __global__ __launch_bounds__(TPB) void k_flux(const T *__restrict__ U, WorkList 
     const T *ub = U + (size_t)slot * 5 * CELLS_P;
     GlobalSink<T> sink{D + (size_t)slot * 3 * 5 * CELLS_I, FF + (size_t)slot * 6 * 5 * FACE,
                        (int)blockIdx.y, m * NI + r};
-    if (blockIdx.y == 0) pencil<T, 0>(ub, r, m, G, sink);
-    else if (blockIdx.y == 1) pencil<T, 1>(ub, r, m, G, sink);
-    else pencil<T, 2>(ub, r, m, G, sink);
+    if (blockIdx.y == 0) pencil<T, 0, SCH>(ub, r, m, G, sink);
+    else if (blockIdx.y == 1) pencil<T, 1, SCH>(ub, r, m, G, sink);
+    else pencil<T, 2, SCH>(ub, r, m, G, sink);
     }
 }
 
@@ -496,7 +662,7 @@ __device__ __forceinline__ float buffer_f32(__amdgpu_buffer_rsrc_t r, unsigned v
 // base + j*stride, padded coordinate pos0 + j along D); cells below / above the interior
 // come from lo / hi, which are the neighbour's block shifted by -+16 cells along D (or
 // the own block).  The result is returned in physical component order.
-template <typename T, int D>
+template <typename T, int D, int SCH>
 __device__ __forceinline__ void face_flux_at(const T *__restrict__ ub, const T *__restrict__ lo,
                                              const T *__restrict__ hi, const NearSrc &ns, int base,
                                              int pos0, const Gas<T> &G, T Fp[5]) {
@@ -540,7 +706,7 @@ __device__ __forceinline__ void face_flux_at(const T *__restrict__ ub, const T *
 #pragma unroll
     for (int j = 0; j < 6; ++j) derive_state(G, w[j]);
     T F[5];
-    face_flux<T, true>(w, G, F);
+    face_flux<T, true, SCH>(w, G, F);
     Fp[0] = F[0];
     Fp[4] = F[4];
     Fp[n1] = F[1];
@@ -548,7 +714,7 @@ __device__ __forceinline__ void face_flux_at(const T *__restrict__ ub, const T *
     Fp[t2] = F[3];
 }
 
-template <typename T, int GP, int TPB_F, bool PERSIST, int WPE>
+template <typename T, int GP, int TPB_F, bool PERSIST, int WPE, int SCH, bool PTR>
 __global__ __attribute__((amdgpu_flat_work_group_size(TPB_F, TPB_F), amdgpu_waves_per_eu(WPE)))
 void k_rhs_update(int stage, const double *__restrict__ dt,
                                                       const T *__restrict__ Uin, T *__restrict__ Uout,
@@ -609,7 +775,7 @@ void k_rhs_update(int stage, const double *__restrict__ dt,
         }
         // every access lies below the highest source plus one block
         const uintptr_t span = mx - mn + (uintptr_t)(5 * CELLS_P * sizeof(T));
-        ns.near = span <= (uintptr_t)0xffffffffu;
+        ns.near = !PTR && span <= (uintptr_t)0xffffffffu;   // PTR: always the pointer loads
         ns.rsrc = __builtin_amdgcn_make_buffer_rsrc((void *)(ub - ((uintptr_t)ub - mn) / sizeof(T)),
                                                     (short)0, ns.near ? (int)(unsigned)span : 0,
                                                     BUFFER_RSRC_WORD3);
@@ -629,7 +795,7 @@ void k_rhs_update(int stage, const double *__restrict__ dt,
     const bool owner = tid < FACE;              // column owners (x = tid & 15, y = tid >> 4)
     const int cx = tid & 15, cy = tid >> 4;
     bool ok = true;
-    // Restriction of the new state into the parent's octant (eq:Projection): the sum of
+    // Restriction of the new state into the parent's octant (eq:Averaging): the sum of
     // the 2x2x2 children is formed in FP64 as x pairs, then y pairs (lanes 1 and 16 apart
     // in the wavefront), then z pairs, the order of the restriction kernel, so both give
     // bitwise the same parent values.
@@ -731,7 +897,7 @@ void k_rhs_update(int stage, const double *__restrict__ dt,
                     p = v / (NF_OUT * NI);
                 }
                 const int base = ((k0 + p + HW) * NP + y + HW) * NP + f + 1;
-                face_flux_at<T, 0>(ub, nlo[0], nhi[0], ns, base, f + 1, G, F);
+                face_flux_at<T, 0, SCH>(ub, nlo[0], nhi[0], ns, base, f + 1, G, F);
 #pragma unroll
                 for (int q = 0; q < 5; ++q) Fx[buf][p][y][f][q] = F[q];
                 if (f == 0 || f == NI) {
@@ -752,7 +918,7 @@ void k_rhs_update(int stage, const double *__restrict__ dt,
                     p = v / (NI * NF_OUT);
                 }
                 const int base = ((k0 + p + HW) * NP + f + 1) * NP + x + HW;
-                face_flux_at<T, 1>(ub, nlo[1], nhi[1], ns, base, f + 1, G, F);
+                face_flux_at<T, 1, SCH>(ub, nlo[1], nhi[1], ns, base, f + 1, G, F);
 #pragma unroll
                 for (int q = 0; q < 5; ++q) Fy[buf][p][f][x][q] = F[q];
                 if (f == 0 || f == NI) {
@@ -764,7 +930,7 @@ void k_rhs_update(int stage, const double *__restrict__ dt,
                 const int x = u % NI, y = (u / NI) % NI, j = u / NFZ + first_z;
                 const int kf = k0 + j;          // face between interior planes kf-1 and kf
                 const int base = ((kf + 1) * NP + y + HW) * NP + x + HW;   // padded z = kf+1 .. kf+6
-                face_flux_at<T, 2>(ub, nlo[2], nhi[2], ns, base, kf + 1, G, F);
+                face_flux_at<T, 2, SCH>(ub, nlo[2], nhi[2], ns, base, kf + 1, G, F);
 #pragma unroll
                 for (int q = 0; q < 5; ++q) Fz[kf % NZR][y][x][q] = F[q];
                 if (kf == 0 || kf == NI) {
@@ -880,10 +1046,17 @@ __global__ __launch_bounds__(TPB) void k_reflux_update(int stage, const double *
 }  // namespace
 
 template <typename T>
-hipError_t launch_flux(const T *U, const WorkList &wl, const DevTables &tb, const InstDev *inst,
-                       T *D, T *FF, hipStream_t st) {
+hipError_t launch_flux(int scheme, const T *U, const WorkList &wl, const DevTables &tb,
+                       const InstDev *inst, T *D, T *FF, hipStream_t st) {
     if (wl.grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_flux<T>, dim3(wl.grid, 3), dim3(TPB), 0, st, U, wl, tb.meta, inst, D, FF);
+    const dim3 grid(wl.grid, 3), block(TPB);
+    switch (scheme) {
+        case SCH_ROE_WENO5: hipLaunchKernelGGL((k_flux<T, SCH_ROE_WENO5>), grid, block, 0, st, U, wl, tb.meta, inst, D, FF); break;
+        case SCH_ROE_TENO5: hipLaunchKernelGGL((k_flux<T, SCH_ROE_TENO5>), grid, block, 0, st, U, wl, tb.meta, inst, D, FF); break;
+        case SCH_LLF_WENO5: hipLaunchKernelGGL((k_flux<T, SCH_LLF_WENO5>), grid, block, 0, st, U, wl, tb.meta, inst, D, FF); break;
+        case SCH_HLLC_WAO53: hipLaunchKernelGGL((k_flux<T, SCH_HLLC_WAO53>), grid, block, 0, st, U, wl, tb.meta, inst, D, FF); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -925,56 +1098,90 @@ hipError_t launch_update(int stage, const double *dt, T *U, T *U0, const T *L, c
 // at once (3 waves per SIMD at their register count) loops over the leaves instead of
 // one workgroup per leaf.  Variants 11 and 12 ask the register allocator for 5 waves per
 // SIMD (at most 96 registers, some spilled to scratch) instead of the default 4.
-constexpr int N_RHS_VARIANTS = 13;
-constexpr int RHS_GP[N_RHS_VARIANTS] = {2, 1, 2, 2, 4, 4, 2, 2, 1, 2, 2, 2, 2};
-constexpr int RHS_TPB[N_RHS_VARIANTS] = {320, 256, 256, 384, 320, 512, 448, 512, 320, 512, 384, 320, 640};
+// Variant 13 is variant 7 with the stencils always loaded through per-lane pointers (the
+// path taken when a workgroup's source blocks span more than 4 GiB).
+constexpr int N_RHS_VARIANTS = 14;
+constexpr int RHS_GP[N_RHS_VARIANTS] = {2, 1, 2, 2, 4, 4, 2, 2, 1, 2, 2, 2, 2, 2};
+constexpr int RHS_TPB[N_RHS_VARIANTS] = {320, 256, 256, 384, 320, 512, 448, 512, 320, 512, 384, 320, 640, 512};
 constexpr bool RHS_PERSIST[N_RHS_VARIANTS] = {false, false, false, false, false, false, false,
-                                              false, false, true, true, false, false};
-constexpr int RHS_WPE[N_RHS_VARIANTS] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 5, 5};
+                                              false, false, true, true, false, false, false};
+constexpr int RHS_WPE[N_RHS_VARIANTS] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 5, 5, 1};
+constexpr bool RHS_PTR[N_RHS_VARIANTS] = {false, false, false, false, false, false, false,
+                                          false, false, false, false, false, false, true};
 constexpr int persist_grid(int tpb) { return 256 * (12 / (tpb / 64) > 0 ? 12 / (tpb / 64) : 1); }
 
-template <int V>
+// The other flux kernels are instantiated in three launch shapes (variants 7, 2, 3 of the
+// standard kernel), which the autotuner chooses among.
+constexpr int N_ALT_VARIANTS = 3;
+constexpr int ALT_VARIANT[N_ALT_VARIANTS] = {7, 2, 3};
+
+template <int V, int SCH>
 static void launch_variant(int stage, const double *dt, const float *Uin, float *Uout, float *U0,
                     const WorkList &wl, const DevTables &tb, const InstDev *inst, float *FF,
                     int32_t *err, int restrict_parents, double *cflmax, hipStream_t st) {
     constexpr int G = RHS_GP[V], B = RHS_TPB[V];
     constexpr bool PS = RHS_PERSIST[V];
     constexpr int WP = RHS_WPE[V];
+    constexpr bool PT = RHS_PTR[V];
     const int grid = PS ? std::min(wl.grid, persist_grid(B)) : round_xcd(wl.grid);
-    hipLaunchKernelGGL((k_rhs_update<float, G, B, PS, WP>), dim3(grid), dim3(B), 0, st, stage, dt, Uin,
+    hipLaunchKernelGGL((k_rhs_update<float, G, B, PS, WP, SCH, PT>), dim3(grid), dim3(B), 0, st, stage, dt, Uin,
                        Uout, U0, wl, tb.meta, tb.nbr, inst, FF, err, restrict_parents, cflmax);
 }
 
-int rhs_variants() { return N_RHS_VARIANTS; }
+int rhs_variants(int scheme) { return scheme == SCH_ROE_WENO5 ? N_RHS_VARIANTS : N_ALT_VARIANTS; }
 
-void rhs_variant_shape(int v, int *gp, int *tpb, int *wpe) {
+void rhs_variant_shape(int scheme, int v, int *gp, int *tpb, int *wpe, int *ptr) {
+    if (scheme != SCH_ROE_WENO5) v = ALT_VARIANT[v];
     *gp = RHS_GP[v];
     *tpb = RHS_PERSIST[v] ? -RHS_TPB[v] : RHS_TPB[v];   // negative: persistent grid
     *wpe = RHS_WPE[v];
+    *ptr = RHS_PTR[v] ? 1 : 0;
 }
 
-hipError_t launch_rhs_update_f32(int variant, int stage, const double *dt, const float *Uin,
+template <int SCH>
+static void launch_alt(int variant, int stage, const double *dt, const float *Uin, float *Uout,
+                       float *U0, const WorkList &wl, const DevTables &tb, const InstDev *inst,
+                       float *FF, int32_t *err, int restrict_parents, double *cflmax, hipStream_t st) {
+    switch (ALT_VARIANT[variant]) {
+        case 7: launch_variant<7, SCH>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, cflmax, st); break;
+        case 2: launch_variant<2, SCH>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, cflmax, st); break;
+        default: launch_variant<3, SCH>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, cflmax, st); break;
+    }
+}
+
+hipError_t launch_rhs_update_f32(int scheme, int variant, int stage, const double *dt, const float *Uin,
                                  float *Uout, float *U0, const WorkList &wl, const DevTables &tb,
                                  const InstDev *inst, float *FF, int32_t *err, int restrict_parents,
                                  double *cflmax, hipStream_t st) {
     if (wl.grid <= 0) return hipSuccess;
     if (Uin == Uout) return hipErrorInvalidValue;   // neighbours' interiors are read
-    switch (variant) {
-        case 0: launch_variant<0>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, cflmax, st); break;
-        case 1: launch_variant<1>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, cflmax, st); break;
-        case 2: launch_variant<2>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, cflmax, st); break;
-        case 3: launch_variant<3>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, cflmax, st); break;
-        case 4: launch_variant<4>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, cflmax, st); break;
-        case 5: launch_variant<5>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, cflmax, st); break;
-        case 6: launch_variant<6>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, cflmax, st); break;
-        case 7: launch_variant<7>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, cflmax, st); break;
-        case 8: launch_variant<8>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, cflmax, st); break;
-        case 9: launch_variant<9>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, cflmax, st); break;
-        case 10: launch_variant<10>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, cflmax, st); break;
-        case 11: launch_variant<11>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, cflmax, st); break;
-        case 12: launch_variant<12>(stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, cflmax, st); break;
+    if (variant < 0 || variant >= rhs_variants(scheme)) return hipErrorInvalidValue;
+#define MRFV_ARGS stage, dt, Uin, Uout, U0, wl, tb, inst, FF, err, restrict_parents, cflmax, st
+    switch (scheme) {
+        case SCH_ROE_WENO5:
+            switch (variant) {
+                case 0: launch_variant<0, SCH_ROE_WENO5>(MRFV_ARGS); break;
+                case 1: launch_variant<1, SCH_ROE_WENO5>(MRFV_ARGS); break;
+                case 2: launch_variant<2, SCH_ROE_WENO5>(MRFV_ARGS); break;
+                case 3: launch_variant<3, SCH_ROE_WENO5>(MRFV_ARGS); break;
+                case 4: launch_variant<4, SCH_ROE_WENO5>(MRFV_ARGS); break;
+                case 5: launch_variant<5, SCH_ROE_WENO5>(MRFV_ARGS); break;
+                case 6: launch_variant<6, SCH_ROE_WENO5>(MRFV_ARGS); break;
+                case 7: launch_variant<7, SCH_ROE_WENO5>(MRFV_ARGS); break;
+                case 8: launch_variant<8, SCH_ROE_WENO5>(MRFV_ARGS); break;
+                case 9: launch_variant<9, SCH_ROE_WENO5>(MRFV_ARGS); break;
+                case 10: launch_variant<10, SCH_ROE_WENO5>(MRFV_ARGS); break;
+                case 11: launch_variant<11, SCH_ROE_WENO5>(MRFV_ARGS); break;
+                case 12: launch_variant<12, SCH_ROE_WENO5>(MRFV_ARGS); break;
+                default: launch_variant<13, SCH_ROE_WENO5>(MRFV_ARGS); break;
+            }
+            break;
+        case SCH_ROE_TENO5: launch_alt<SCH_ROE_TENO5>(variant, MRFV_ARGS); break;
+        case SCH_LLF_WENO5: launch_alt<SCH_LLF_WENO5>(variant, MRFV_ARGS); break;
+        case SCH_HLLC_WAO53: launch_alt<SCH_HLLC_WAO53>(variant, MRFV_ARGS); break;
         default: return hipErrorInvalidValue;
     }
+#undef MRFV_ARGS
     return hipGetLastError();
 }
 
@@ -989,7 +1196,7 @@ hipError_t launch_reflux_update(int stage, const double *dt, T *U, const T *FF,
 }
 
 #define MRFV_INST_RHS(T)                                                                    \
-    template hipError_t launch_flux<T>(const T *, const WorkList &, const DevTables &,      \
+    template hipError_t launch_flux<T>(int, const T *, const WorkList &, const DevTables &, \
                                        const InstDev *, T *, T *, hipStream_t);             \
     template hipError_t launch_ff_restrict<T>(T *, const WorkList &, const DevTables &,     \
                                               hipStream_t);                                 \

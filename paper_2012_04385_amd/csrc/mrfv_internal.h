@@ -35,7 +35,9 @@ struct BlockMeta {
 struct InstDev {
     double gamma, B, cfl, eps, scale_rho, scale_E, dx0;
     int32_t lmax, n0[3], bc[3], adapt;
+    double detail_band;   // slabs with |detail - eps_l| <= band are evaluated again exactly
 };
+constexpr double DETAIL_BAND_DEFAULT = 1e-9;
 
 // Device-resident topology tables, rebuilt after every change of the tree.
 struct DevTables {
@@ -215,7 +217,7 @@ hipError_t launch_predict(T *U, const int32_t *list, int n, const DevTables &tb,
                           hipStream_t st);
 template <typename T>
 hipError_t launch_details(const T *U, const WorkList &wl, const DevTables &tb,
-                          const InstDev *inst, double *det4, hipStream_t st);
+                          const InstDev *inst, double *det4, int32_t *recheck, hipStream_t st);
 int details_parts();   // detail maxima per block in det4 (one per slab)
 // flags (and det of blocks on level >= 1) from the slab maxima; flags_host / err_host
 // (may be null): host-memory copies of the flags and of the error word err; gate (may be
@@ -242,7 +244,7 @@ hipError_t launch_totals(const T *U, const WorkList &leaves, const DevTables &tb
                          const InstDev *inst, int n_inst, double *blocksum, double *tot,
                          hipStream_t st);
 template <typename T>
-hipError_t launch_flux(const T *U, const WorkList &leaves, const DevTables &tb,
+hipError_t launch_flux(int scheme, const T *U, const WorkList &leaves, const DevTables &tb,
                        const InstDev *inst, T *D, T *FF, hipStream_t st);
 template <typename T>
 hipError_t launch_ff_restrict(T *FF, const WorkList &parents, const DevTables &tb,
@@ -259,15 +261,16 @@ hipError_t launch_update(int stage, const double *dt, T *U, T *U0, const T *L,
                          int32_t *err, hipStream_t st);
 // Fused stage: reads the state from Uin (same-level neighbours' interiors directly, the
 // own halo elsewhere) and writes the new interior state to Uout != Uin.
-// variant: launch shape index in [0, rhs_variants()) (all give the same result).
+// scheme: flux kernel (mrfv_scheme); variant: launch shape index in [0, rhs_variants(scheme))
+// (all give the same result).
 // restrict_parents: leaves with meta.srestr also write the restriction of their new state
 // (all components) into their parent's octant of Uout.
-hipError_t launch_rhs_update_f32(int variant, int stage, const double *dt, const float *Uin,
+hipError_t launch_rhs_update_f32(int scheme, int variant, int stage, const double *dt, const float *Uin,
                                  float *Uout, float *U0, const WorkList &leaves, const DevTables &tb,
                                  const InstDev *inst, float *FF, int32_t *err, int restrict_parents,
                                  double *cflmax, hipStream_t st);   // cflmax: null, or CFL block maxima out
-int rhs_variants();
-void rhs_variant_shape(int v, int *gp, int *tpb, int *wpe);
+int rhs_variants(int scheme);
+void rhs_variant_shape(int scheme, int v, int *gp, int *tpb, int *wpe, int *ptr);
 template <typename T>
 hipError_t launch_reflux_update(int stage, const double *dt, T *U, const T *FF,
                                 const WorkList &leaves, const DevTables &tb,
@@ -305,6 +308,8 @@ struct mrfv_ctx {
     double *d_blockred = nullptr;      // [cap][5] per-block partial reductions
     double *d_det = nullptr;           // [cap]
     double *d_det4 = nullptr;          // [cap][details_parts()] slab maxima of the details
+    int32_t *d_recheck = nullptr;      // [2 + cap * details_parts()]: count, done count, list of
+                                       // slabs whose detail lies near the threshold (zero between launches)
     int8_t *d_flags = nullptr;         // [cap]
     int32_t *d_desc = nullptr;         // [N_DESC][2] list descriptors (graph launches)
     hipStream_t gstream = nullptr;     // capture stream of the step graphs

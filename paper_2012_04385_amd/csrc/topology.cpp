@@ -125,6 +125,10 @@ bool Topology::commit(const int8_t *flags, std::vector<TreeOp> *ops, std::vector
         if (flags[s] == -1 && (b.bx & 1) == 0 && (b.by & 1) == 0 && (b.bz & 1) == 0)
             coarsen_p.push_back(b.parent);
     }
+    // all or nothing: every refinement needs 8 free slots, counting the slots the
+    // coarsenings free first, so a commit that cannot complete leaves the tree unchanged
+    if ((int64_t)free_.size() + 8 * (int64_t)coarsen_p.size() < 8 * (int64_t)refine_s.size())
+        return false;
     for (int p : coarsen_p) {
         TreeOp op{-1, p, {}};
         for (int o = 0; o < 8; ++o) op.child[o] = blocks_[p].child[o];

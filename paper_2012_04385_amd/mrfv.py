@@ -35,7 +35,11 @@ class Instance(C.Structure):
 
 class Config(C.Structure):
     _fields_ = [("dtype", C.c_int32), ("n_instances", C.c_int32),
-                ("slot_capacity", C.c_int32), ("batched", C.c_int32)]
+                ("slot_capacity", C.c_int32), ("batched", C.c_int32), ("scheme", C.c_int32)]
+
+
+# flux kernels (mrfv_scheme)
+SCHEMES = {"roe_weno5": 0, "roe_teno5": 1, "llf_weno5": 2, "hllc_wao53": 3}
 
 
 IC_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
@@ -67,6 +71,7 @@ def lib():
         "mrfv_mr_project": ([vp, vp], C.c_int),
         "mrfv_mr_predict": ([vp, vp, C.POINTER(i32), i32], C.c_int),
         "mrfv_mr_flag": ([vp, vp, vp, vp], C.c_int),
+        "mrfv_set_detail_band": ([vp, d], C.c_int),
         "mrfv_cfl_dt": ([vp, vp, vp], C.c_int),
         "mrfv_totals": ([vp, vp, vp], C.c_int),
         "mrfv_commit_flags": ([vp, C.POINTER(C.c_int8), C.POINTER(i32), C.POINTER(i32)], C.c_int),
@@ -120,7 +125,7 @@ def exported_symbols():
             "mrfv_mlp_get_params", "mrfv_mlp_forward", "mrfv_mlp_loss_grad",
             "mrfv_mlp_adam_step", "mrfv_features", "mrfv_set_proposer", "mrfv_proposer_stats",
             "mrfv_last_flags", "mrfv_step_timing", "mrfv_rhs_variant", "mrfv_autotune",
-            "mrfv_fused_stage", "mrfv_run"]
+            "mrfv_fused_stage", "mrfv_run", "mrfv_set_detail_band"]
 
 
 def morton_encode(shadow, level, bx, by, bz) -> int:
@@ -174,7 +179,11 @@ class Solver:
             arr[i] = _instance(pb)
             if adapt is not None:
                 arr[i].adapt = int(adapt)
-        cfg = Config(self.dtype, n, cap, int(batched))
+        schemes = {getattr(pb, "scheme", "roe_weno5") for pb in self.problems}
+        if len(schemes) != 1:
+            raise ValueError("all problems of one context use the same flux kernel")
+        self.scheme = schemes.pop()
+        cfg = Config(self.dtype, n, cap, int(batched), SCHEMES[self.scheme])
         self.stream = torch.cuda.current_stream(self.device)
         h = C.c_void_p()
         rc = lib().mrfv_create(C.byref(h), C.byref(cfg), arr, C.c_void_p(self.stream.cuda_stream))
@@ -254,6 +263,9 @@ class Solver:
     def mr_flag(self):
         self._chk(lib().mrfv_mr_flag(self.h, self._p(self.U), self._p(self.flags), self._p(self.det)))
         return self.flags, self.det
+
+    def set_detail_band(self, band: float):
+        self._chk(lib().mrfv_set_detail_band(self.h, float(band)))
 
     def cfl_dt(self):
         self._chk(lib().mrfv_cfl_dt(self.h, self._p(self.U), self._p(self.dt)))
@@ -344,14 +356,15 @@ class Solver:
                                          self._p(Uout), self._p(self.U0), int(bool(restrict_parents))))
 
     def rhs_variants(self):
-        """[(z-planes per group, threads per workgroup, waves per SIMD aimed at)] of the
-        fused kernel's variants; a negative thread count marks a persistent grid looping
-        over the leaves, waves 1 the compiler's default register allocation."""
+        """[(z-planes per group, threads per workgroup, waves per SIMD aimed at, pointer
+        loads)] of the fused kernel's variants; a negative thread count marks a persistent
+        grid looping over the leaves, waves 1 the compiler's default register allocation,
+        pointer loads 1 the per-lane pointer path for the stencils."""
         n = C.c_int32(0)
         lib().mrfv_rhs_variant(self.h, -1, C.byref(n), None)
-        shp = (C.c_int32 * (3 * n.value))()
+        shp = (C.c_int32 * (4 * n.value))()
         lib().mrfv_rhs_variant(self.h, -1, None, shp)
-        return [tuple(shp[3 * v + i] for i in range(3)) for v in range(n.value)]
+        return [tuple(shp[4 * v + i] for i in range(4)) for v in range(n.value)]
 
     def set_rhs_variant(self, v: int) -> int:
         rc = lib().mrfv_rhs_variant(self.h, int(v), None, None)

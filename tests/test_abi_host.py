@@ -38,7 +38,8 @@ def test_create_rejects_bad_config_without_device():
     for a in range(3):
         inst[0].n0[a] = 1
     h = C.c_void_p()
-    bad = [mrfv.Config(7, 1, 10, 0), mrfv.Config(0, 0, 10, 0), mrfv.Config(0, 1, 0, 0)]
+    bad = [mrfv.Config(7, 1, 10, 0), mrfv.Config(0, 0, 10, 0), mrfv.Config(0, 1, 0, 0),
+           mrfv.Config(0, 1, 10, 0, 4)]
     for cfg in bad:
         assert mrfv.lib().mrfv_create(C.byref(h), C.byref(cfg), inst, None) == mrfv.EINVAL
     inst[0].gamma = 1.0

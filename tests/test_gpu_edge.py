@@ -93,3 +93,28 @@ def test_capacity_exhausted_reported(torch_mod):
     with pytest.raises(MrfvError) as e:
         g.init()
     assert e.value.code == -3
+
+
+def test_commit_capacity_leaves_tree_unchanged(torch_mod):
+    """A commit that would need more slots than are free fails with ENOMEM before it
+    changes anything: the tree, and the device tables built from it, stay as they were,
+    and the context keeps stepping."""
+    from paper_2012_04385_amd.mrfv import MrfvError, Solver
+    pb = W.uniform_flow(lmax=3, n0=(2, 1, 1))
+    # algo:Init needs 2 + 16 + 128 slots at its peak; 18 blocks remain
+    g = Solver([pb], dtype="f32", batched=2, capacity=146).init()
+    g.refine(0, 1, 0, 0, 0)                      # 26 blocks, 120 free slots
+    before = g.blocks().copy()
+    flags = np.zeros(g.capacity, dtype=np.int8)
+    for r in before:
+        if r[6] == 1 and r[2] == 1:
+            flags[r[0]] = 1                      # 15 level-1 leaves: 120 slots
+    lvl2 = [r for r in before if r[6] == 1 and r[2] == 2]
+    flags[lvl2[0][0]] = 1                        # and one more: 128 > 120
+    with pytest.raises(MrfvError) as e:
+        g.commit_flags(flags)
+    assert e.value.code == -3
+    after = g.blocks()
+    assert np.array_equal(np.sort(before, axis=0), np.sort(after, axis=0))
+    g.step()                                     # the uniform field coarsens the group again
+    g.check()

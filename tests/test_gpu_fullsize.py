@@ -1,35 +1,29 @@
-"""Full-size checks of the batched FP32 path on the three larger workloads (5-level
+"""Full-size parity of the batched FP32 path on the three larger workloads (5-level
 Kelvin-Helmholtz, 256-instance uneven batch, 6-level shock-blobs), in the launch
-configuration the benchmark times (stage hipGraph, autotuned fused-kernel shape).
+configuration the benchmark times (step graph, autotuned fused-kernel shape).
 
-The oracle cannot run these trees in seconds, so it checks sampled outputs one block at
-a time:
-  * one fused stage (mrfv_fused_stage, stage 0): for sampled leaves, the GPU result
-    u + dt L is compared with the oracle's -div F of the block as the kernel sees it
-    (own interior, same-level neighbours' interiors across faces, the fill's predicted
-    or clamped halo elsewhere).  Leaves on the coarse side of a resolution jump are not
-    sampled (their boundary fluxes are corrected from the finer neighbour).  Samples
-    cover interior leaves, leaves on the fine side of a jump and zero-gradient leaves.
-  * details: for sampled blocks the GPU's FP64 detail equals the oracle's
-    eq:DetailFunction on the same FP32 data to 1e-12; the flags of every leaf follow
-    the threshold rule applied to the GPU details (bit-exact);
+The oracle runs the same workloads from the same seeded initial conditions (its own
+algo:Init and one global step; for the 256-instance batch a sample of 12 instances,
+each an independent problem), and is compared with the GPU on every leaf:
+  * identical leaf sets after algo:Init and after the step (the flags of every leaf,
+    decided by the FP64 judge on each side's own state);
+  * every leaf's state after the step, including the leaves on the coarse side of a
+    resolution jump, whose boundary fluxes the jump correction replaces: L1 density
+    <= 1e-6 and energy <= 1e-5 per unit volume, and max |gpu - oracle| <= 5e-3 of the
+    component's magnitude over the instance (the momenta share the largest momentum).
+    Measured worst: 1.5e-7 (shear layer), 3.7e-5 (shock-blobs), 1.8e-3 (a blast of
+    pressure ratio up to 100 in the batch, where FP32 and FP64 can take different
+    branches of the Roe/LLF sign test at cells whose velocity is zero up to rounding);
   * conservation on the periodic workload: mass and energy totals (FP64 sums) change by
     less than 1e-6 relative over a step.
-
-Tolerance of the stage check: FP32 flux arithmetic (~700 operations per face, errors
-~1e-6 relative to the flux magnitude F ~ (|U| + p)(|v| + c)) divided by dx, plus four
-units in the last place of the FP32 state: |gpu - (u + dt L)| <= dt (3e-5 |L|max +
-3e-6 F / dx) + 4 ulp(u).
 """
 import numpy as np
 import pytest
 
+from gpu_helpers import l1_diff
 from paper_2012_04385_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
-
-H, N, P = 4, 16, 24
-FACE = [(0, -1), (0, 1), (1, -1), (1, 1), (2, -1), (2, 1)]
 
 
 @pytest.fixture(scope="module")
@@ -44,160 +38,79 @@ def _configs():
             "shockblobs_512e_6lvl": [W.shock_blobs_mr6()]}
 
 
-def _index(info):
-    return {(int(r[1]), int(r[2]), int(r[3]), int(r[4]), int(r[5])): int(r[0]) for r in info}
+def _gpu_leaves(g, inst):
+    return {tuple(int(v) for v in r[2:6]) for r in g.blocks() if r[6] == 1 and r[1] == inst}
 
 
-def _face_neighbour(pb, key, a, side):
-    """Same-level neighbour key across face (a, side), 'zg' at a zero-gradient edge."""
-    inst, lv, c = key[0], key[1], list(key[2:])
-    n = pb.n0[a] << lv
-    c[a] += side
-    if c[a] < 0 or c[a] >= n:
-        if pb.bc[a] == 1:
-            return "zg"
-        c[a] %= n
-    return (inst, lv, c[0], c[1], c[2])
+def _oracle_leaves(o):
+    return {tuple(int(v) for v in r[:4]) for r in o.blocks() if r[4] == 1}
 
 
-def _sample_leaves(pbs, info, idx, rng, per_kind=10):
-    kinds = {"interior": [], "fine_side": [], "zero_gradient": []}
-    for r in info:
-        if r[6] != 1:
-            continue
-        key = (int(r[1]), int(r[2]), int(r[3]), int(r[4]), int(r[5]))
-        pb = pbs[key[0]]
-        nbs = [_face_neighbour(pb, key, a, s) for a, s in FACE]
-        coarse_side = any(nb != "zg" and nb in idx and info_leaf(info, idx[nb]) == 0 for nb in nbs)
-        if coarse_side:
-            continue
-        if any(nb == "zg" for nb in nbs):
-            kinds["zero_gradient"].append(key)
-        elif any(nb not in idx for nb in nbs):
-            kinds["fine_side"].append(key)
-        else:
-            kinds["interior"].append(key)
-    out = []
-    for k, v in kinds.items():
-        if v:
-            pick = rng.choice(len(v), size=min(per_kind, len(v)), replace=False)
-            out += [(k, v[i]) for i in pick]
-    return out, {k: len(v) for k, v in kinds.items()}
-
-
-_LEAF = {}
-
-
-def info_leaf(info, slot):
-    return _LEAF[slot]
-
-
-def _block(t, slot):
-    return t[slot].double().cpu().numpy()
+def _jump_coarse_side(pb, leaves):
+    """Leaves whose same-level face neighbour is a refined block (coarse side of a jump)."""
+    inner = set()
+    for (lv, bx, by, bz) in leaves:
+        for d in range(1, lv + 1):
+            inner.add((lv - d, bx >> d, by >> d, bz >> d))
+    out = set()
+    for (lv, bx, by, bz) in leaves:
+        for a in range(3):
+            for s in (-1, 1):
+                c = [bx, by, bz]
+                c[a] += s
+                n = pb.n0[a] << lv
+                if not 0 <= c[a] < n:
+                    if pb.bc[a] != 0:
+                        continue
+                    c[a] %= n
+                if (lv, c[0], c[1], c[2]) in inner:
+                    out.add((lv, bx, by, bz))
+    return out
 
 
 @pytest.mark.parametrize("name", ["kh_256e_5lvl", "multi_256", "shockblobs_512e_6lvl"])
-def test_fullsize_sampled(orc, torch_mod, name):
-    torch = torch_mod
+def test_fullsize_against_oracle(orc, torch_mod, name):
     from paper_2012_04385_amd.mrfv import Solver
     pbs = _configs()[name]
     g = Solver(pbs, dtype="f32", batched=2).init()
-    g.step()
     choice, _ = g.autotune(reps=2)
-    g.step()
-    g.check()
+    sample = list(range(len(pbs))) if len(pbs) == 1 else \
+        sorted(np.random.default_rng(7).choice(len(pbs), size=12, replace=False).tolist())
+    sims = {i: orc.Sim(pbs[i]).init() for i in sample}
+    for i in sample:
+        assert _gpu_leaves(g, i) == _oracle_leaves(sims[i]), f"instance {i}: trees differ after algo:Init"
     periodic = all(all(b == 0 for b in pb.bc) for pb in pbs)
     tot0 = g.totals().cpu().numpy().copy() if periodic else None
     g.step()
     g.check()
+    for o in sims.values():
+        o.step()
     if periodic:
         tot1 = g.totals().cpu().numpy()
         for q in (0, 4):
             rel = np.abs(tot1[:, q] - tot0[:, q]) / np.abs(tot0[:, q])
             print(f"{name}: relative change of total {q} over a step {rel.max():.2e}")
             assert rel.max() <= 1e-6
-
-    # ---- one fused stage, sampled leaves vs the oracle's block right-hand side
-    info = g.blocks()
-    idx = _index(info)
-    _LEAF.clear()
-    _LEAF.update({int(r[0]): int(r[6]) for r in info})
-    rng = np.random.default_rng(7)
-    sample, counts = _sample_leaves(pbs, info, idx, rng)
-    print(f"{name}: variant {choice}, {g.stats()[1]} leaves, candidates {counts}, {len(sample)} sampled")
-    assert counts["interior"] > 0 and len(sample) >= 10
-    g.cfl_dt()
-    dt = g.dt.cpu().numpy().copy()
-    Uout = torch.zeros_like(g.U)
-    g.fused_stage(0, Uout)
-    torch.cuda.synchronize()
-    worst = 0.0
-    for kind, key in sample:
-        pb = pbs[key[0]]
-        s = idx[key]
-        u = _block(g.U, s)                       # own block incl. the fill's halos
-        for a, side in FACE:
-            nb = _face_neighbour(pb, key, a, side)
-            if nb == "zg" or nb not in idx:
-                continue                         # predicted / clamped halo, as filled
-            v = _block(g.U, idx[nb])
-            dst = [slice(None)] * 4
-            src = [slice(None)] * 4
-            dst[3 - a] = slice(1, 4) if side < 0 else slice(20, 23)
-            src[3 - a] = slice(17, 20) if side < 0 else slice(4, 7)
-            u[tuple(dst)] = v[tuple(src)]
-        L = orc.block_rhs(u, pb.gamma, pb.B, pb.dx(key[1]))
-        us = u[:, H:H + N, H:H + N, H:H + N]
-        got = _block(Uout, s)[:, H:H + N, H:H + N, H:H + N]
-        want = us + dt[key[0]] * L
-        rho, m = us[0], us[1:4]
-        pr = (pb.gamma - 1) * (us[4] - 0.5 * (m * m).sum(0) / rho) - pb.gamma * pb.B
-        vel = np.sqrt((m * m).sum(0)) / rho + np.sqrt(pb.gamma * (pr + pb.B) / rho)
-        F = (np.abs(us).max() + np.abs(pr).max()) * vel.max()
-        for q in range(5):
-            tol = dt[key[0]] * (3e-5 * np.abs(L[q]).max() + 3e-6 * F / pb.dx(key[1])) + \
-                4 * np.spacing(np.abs(us[q]).astype(np.float32)).astype(np.float64)
-            err = np.abs(got[q] - want[q])
-            worst = max(worst, float((err / tol).max()))
-            assert np.all(err <= tol), (name, kind, key, q, float(err.max()))
-    print(f"{name}: stage check worst err/tol {worst:.3f}")
-
-    # ---- details and flags after a full adaptation state
-    g.mr_project()
-    g.fill_halos()
-    flags, det = g.mr_flag()
-    torch.cuda.synchronize()
-    flags = flags.cpu().numpy()
-    det = det.cpu().numpy()
-    fine = [k for _, k in sample if k[1] >= 1]
-    checked = 0
-    for key in fine[:16]:
-        pb = pbs[key[0]]
-        par = idx[(key[0], key[1] - 1, key[2] // 2, key[3] // 2, key[4] // 2)]
-        want = orc.block_detail(_block(g.U, idx[key]), _block(g.U, par),
-                                (key[2] & 1, key[3] & 1, key[4] & 1), pb.scale_rho, pb.scale_E)
-        assert abs(det[idx[key]] - want) <= 1e-12 * max(1.0, want), (key, det[idx[key]], want)
-        checked += 1
-    assert checked > 0
-    # flags of every leaf from the threshold rule on the GPU details
-    by_key = {k: s for k, s in idx.items()}
-    bad = 0
-    for key, s in by_key.items():
-        if _LEAF[s] != 1:
-            continue
-        pb = pbs[key[0]]
-        lv = key[1]
-        eps = lambda l: pb.eps * 2.0 ** (-3 * (pb.lmax - l))
-        f = 0
-        if pb.adapt:
-            if lv < pb.lmax and lv >= 1 and det[s] >= eps(lv):
-                f = 1
-            elif lv >= 2:
-                pk = (key[0], lv - 1, key[2] // 2, key[3] // 2, key[4] // 2)
-                sib = [(key[0], lv, 2 * pk[2] + (o & 1), 2 * pk[3] + ((o >> 1) & 1), 2 * pk[4] + (o >> 2))
-                       for o in range(8)]
-                if all(_LEAF[idx[c]] == 1 and det[idx[c]] < eps(lv) for c in sib) and det[idx[pk]] < eps(lv - 1):
-                    f = -1
-        bad += int(flags[s] != f)
-    assert bad == 0, f"{bad} leaves flagged differently from the rule"
-    print(f"{name}: details of {checked} blocks and flags of all leaves agree")
+    n_leaves, n_coarse, worst = 0, 0, 0.0
+    for i in sample:
+        o = sims[i]
+        ol, gl = _oracle_leaves(o), _gpu_leaves(g, i)
+        assert ol == gl, f"instance {i}: refinement flags differ after the step ({len(ol ^ gl)} leaves)"
+        coarse = _jump_coarse_side(pbs[i], ol)
+        n_leaves += len(ol)
+        n_coarse += len(coarse)
+        so, sg = o.leaf_states(), g.leaf_states(i)
+        # per component, the instance's magnitude (momenta share the largest momentum)
+        mag = np.max([np.abs(v).reshape(5, -1).max(axis=1) for v in so.values()], axis=0)
+        mag[1:4] = mag[1:4].max()
+        for k, v in so.items():
+            err = np.abs(sg[k] - v).reshape(5, -1).max(axis=1) / mag
+            worst = max(worst, float(err.max()))
+            assert np.all(err <= 5e-3), (name, i, k, k in coarse, err)
+        e_rho, e_E = l1_diff(o, g, 0, i), l1_diff(o, g, 4, i)
+        vol = float(np.prod([pbs[i].n0[a] * 16 * pbs[i].dx0 for a in range(3)]))
+        assert e_rho / vol <= 1e-6 and e_E / vol <= 1e-5, (i, e_rho, e_E)
+    print(f"{name}: variant {choice}, {n_leaves} leaves compared ({n_coarse} on the coarse side "
+          f"of a jump), worst relative error {worst:.2e}")
+    if name == "shockblobs_512e_6lvl":
+        assert n_coarse > 0

@@ -1,0 +1,149 @@
+"""The other flux kernels of Sec. "Numerical Scheme" on the GPU (Roe-TENO5, LLF-WENO5,
+HLLC-WENO-AO(5,3)) against the oracle, through the C ABI.
+
+* right-hand side with the jump correction on a tree with resolution jumps and random
+  physical states, identical halos on both sides (FP64 plain path <= 1e-10 relative,
+  FP32 <= 5e-5 relative; the FP64 tolerance also covers the reconstructions' different
+  evaluation order: TENO5's cut-off evaluated as a ratio, WENO-AO relative to c);
+* the Sod tube (single level, no noise) for 12 steps: FP64 plain path <= 1e-12 relative
+  to the oracle, FP32 batched path (step graph) L1(rho) <= 1e-6;
+* the 3-level blast (config 2's problem) for 6 steps on the FP32 batched path:
+  identical leaf sets after every step and L1(rho) <= 1e-5;
+* a stationary contact stays put on the GPU as on the oracle;
+* the launch variants of the fused kernel give bitwise the same run.
+"""
+import numpy as np
+import pytest
+
+from gpu_helpers import (H, N, l1_diff, make_pair, oracle_padded_to_gpu, random_physical,
+                         same_tree, set_interiors, slot_map)
+from paper_2012_04385_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+SCHEMES = ["roe_teno5", "llf_weno5", "hllc_wao53"]
+REFS = [(1, 1, 1, 1), (1, 2, 1, 1), (2, 3, 2, 2), (1, 0, 3, 0)]
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def _jump_problem(scheme):
+    pb = W.uniform_flow(lmax=3, n0=(2, 2, 2))
+    pb.bc = (0, 1, 0)
+    pb.scheme = scheme
+    return pb
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("dtype,batched", [("f64", False), ("f32", False)])
+def test_rhs_with_jumps(orc, torch_mod, scheme, dtype, batched):
+    o, g = make_pair(orc, _jump_problem(scheme), REFS, dtype, batched)
+    rng = np.random.default_rng(4)
+    set_interiors(o, g, lambda k: random_physical(rng, (N, N, N)))
+    o.project()
+    o.fill_halos()
+    oracle_padded_to_gpu(o, g)
+    Lo = o.rhs()
+    g.rhs_stage()
+    torch_mod.cuda.synchronize()
+    Lg = g.L.double().cpu().numpy()
+    gm = slot_map(g)
+    leaves = [tuple(int(v) for v in r[:4]) for r in o.blocks() if r[4] == 1]
+    worst = max(np.abs(Lg[gm[k]] - Lo[i]).max() / np.abs(Lo[i]).max() for i, k in enumerate(leaves))
+    print(f"{scheme} {dtype}: rhs worst relative difference {worst:.3e}")
+    assert worst < (1e-10 if dtype == "f64" else 5e-5), worst
+
+
+def _sod(scheme):
+    return W.Problem(name="sod", kind="sod", lmax=0, n0=(4, 1, 1), dx0=1.0 / 64, bc=(1, 0, 0),
+                     noise=0.0, cfl=0.5, scheme=scheme,
+                     params={"axis": 0, "pos": 0.5, "left": (1.0, 1.0), "right": (0.125, 0.1)})
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("dtype,batched", [("f64", 0), ("f32", 2)])
+def test_sod_run(orc, torch_mod, scheme, dtype, batched):
+    from paper_2012_04385_amd.mrfv import Solver
+    pb = _sod(scheme)
+    o = orc.Sim(pb).init()
+    g = Solver([pb], dtype=dtype, batched=batched).init()
+    for _ in range(12):
+        o.step()
+        g.step()
+    g.check()
+    ol, gl = o.leaf_states(), g.leaf_states()
+    worst = max(np.abs(gl[k] - v).max() / np.abs(v).max() for k, v in ol.items())
+    e = l1_diff(o, g, 0)
+    print(f"{scheme} {dtype}: Sod max rel {worst:.3e}, L1 rho {e:.3e}")
+    if dtype == "f64":
+        assert worst <= 1e-12
+    else:
+        assert e <= 1e-6
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_blast_mr_fp32(orc, torch_mod, scheme):
+    from paper_2012_04385_amd.mrfv import Solver
+    pb = W.blast_mr3(steps=6)
+    pb.scheme = scheme
+    o = orc.Sim(pb).init()
+    g = Solver([pb], dtype="f32", batched=2).init()
+    assert same_tree(o, g)[0]
+    for s in range(pb.steps):
+        o.step()
+        g.step()
+        ok, ol, gl = same_tree(o, g)
+        assert ok, f"{scheme}: trees differ at step {s} ({len(ol ^ gl)} leaves)"
+    g.check()
+    e = l1_diff(o, g, 0)
+    print(f"{scheme}: blast L1 rho after {pb.steps} steps {e:.3e}")
+    assert e <= 1e-5
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_stationary_contact(torch_mod, scheme):
+    from paper_2012_04385_amd.mrfv import Solver
+
+    def prim(x, y, z):
+        return (np.where(x < 0.5, 1.0, 0.25), 0 * x, 0 * x, 0 * x, 0.7 + 0 * x)
+
+    pb = W.Problem(name="contact", kind="custom", custom=prim, lmax=0, n0=(2, 1, 1), dx0=1.0 / 32,
+                   bc=(1, 0, 0), noise=0.0, cfl=0.5, scheme=scheme)
+    for dtype, batched, tol in (("f64", 0, 1e-12), ("f32", 2, 1e-6)):
+        g = Solver([pb], dtype=dtype, batched=batched).init()
+        before = g.leaf_states()
+        for _ in range(20):
+            g.step()
+        g.check()
+        after = g.leaf_states()
+        change = max(np.abs(after[k] - before[k]).max() for k in before)
+        print(f"{scheme} {dtype}: stationary contact max change {change:.3e}")
+        assert change <= tol
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_variants_bitwise(torch_mod, scheme):
+    from paper_2012_04385_amd.mrfv import Solver
+    pb = W.blast_mr3(steps=2)
+    pb.scheme = scheme
+    ref = None
+    g0 = Solver([pb], dtype="f32", batched=1).init()
+    n = len(g0.rhs_variants())
+    assert n == 3
+    del g0
+    for v in range(n):
+        g = Solver([pb], dtype="f32", batched=1).init()
+        g.set_rhs_variant(v)
+        g.step()
+        g.step()
+        g.check()
+        s = g.leaf_states()
+        if ref is None:
+            ref = s
+        for k in s:
+            assert np.array_equal(s[k], ref[k]), (scheme, v, k)
