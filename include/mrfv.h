@@ -162,6 +162,17 @@ int mrfv_cfl_dt(mrfv_ctx *ctx, const void *U, double *dt_dev);
  * precision with a fixed reduction order.  tot_dev: dev double[n_instances][5]. */
 int mrfv_totals(mrfv_ctx *ctx, const void *U, double *tot_dev);
 
+/* totals_noalloc -- mrfv_totals for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same kernels and the same result, bitwise, with the per-slot partial sums kept in a
+ * static device array of the library (65536 slots x 5 doubles = 2.6 MB per device, held
+ * until the process ends) instead of the context's scratch.  Calls no allocating
+ * routine.  Every call on one device shares that array and overwrites what it needs
+ * before reading it; calls that overlap on one device (several streams or contexts at
+ * once) race.  MRFV_EINVAL when the context's slot capacity exceeds 65536, MRFV_ESTATE
+ * when the context's device is not current.  tot_dev: dev double[n_instances][5]. */
+int mrfv_totals_noalloc(mrfv_ctx *ctx, const void *U, double *tot_dev);
+
 /* commit_flags -- apply flags (host int8[capacity] by slot, as written by mr_flag) to
  * the tree: refine creates 8 children (their interiors are NOT yet predicted), coarsen
  * removes 8 leaf siblings; then rebuilds and uploads the device tables.  The new child

@@ -905,6 +905,11 @@ int mrfv_create(mrfv_ctx **out, const mrfv_config *cfg, const mrfv_instance *ins
         ctx->inst.push_back(inst[i]);
     }
     ctx->stream = (hipStream_t)hip_stream;
+    if (hipGetDevice(&ctx->device) != hipSuccess ||
+        static_totals_scratch(ctx->device, &ctx->d_static_totals) != hipSuccess) {
+        ctx->err = "cannot resolve the static totals scratch";
+        return bail(MRFV_EHIP);
+    }
     const size_t cap = cfg->slot_capacity, es = elem_size(ctx);
     ctx->lists_cap = 2 * cfg->n_instances + 10 * cfg->slot_capacity + 16;
     ctx->prim_batch = 128;
@@ -1103,6 +1108,28 @@ int mrfv_totals(mrfv_ctx *ctx, const void *U, double *tot_dev) {
     else
         HIP_OK(launch_totals<float>((const float *)U, wlist(ctx, DESC_LEAVES), ctx->tb, ctx->d_inst,
                                     (int)ctx->inst.size(), ctx->d_blockred, tot_dev, ctx->stream));
+    return MRFV_OK;
+}
+
+int mrfv_totals_noalloc(mrfv_ctx *ctx, const void *U, double *tot_dev) {
+    CALL(need_init(ctx));
+    if (!U || !tot_dev) return fail(ctx, MRFV_EINVAL, "totals_noalloc: null pointer");
+    if (ctx->cfg.slot_capacity > static_totals_slots())
+        return fail(ctx, MRFV_EINVAL,
+                    "totals_noalloc: slot capacity " + std::to_string(ctx->cfg.slot_capacity) +
+                        " exceeds the static scratch (" + std::to_string(static_totals_slots()) +
+                        " slots); use mrfv_totals");
+    int cur = -1;
+    HIP_OK(hipGetDevice(&cur));
+    if (cur != ctx->device)
+        return fail(ctx, MRFV_ESTATE, "totals_noalloc: the context's device is not current");
+    // every listed slot's partials are written before they are read: nothing to clear
+    if (ctx->cfg.dtype == MRFV_F64)
+        HIP_OK(launch_totals<double>((const double *)U, wlist(ctx, DESC_LEAVES), ctx->tb, ctx->d_inst,
+                                     (int)ctx->inst.size(), ctx->d_static_totals, tot_dev, ctx->stream));
+    else
+        HIP_OK(launch_totals<float>((const float *)U, wlist(ctx, DESC_LEAVES), ctx->tb, ctx->d_inst,
+                                    (int)ctx->inst.size(), ctx->d_static_totals, tot_dev, ctx->stream));
     return MRFV_OK;
 }
 

@@ -14,6 +14,8 @@
 // c0 = -22/128, c1 = 3/128 (Q_x = D_x u, Q_xy = D_x D_y u, Q_xyz = D_x D_y D_z u), so the
 // child value is (1 + s_z D_z)(1 + s_y D_y)(1 + s_x D_x) u, s = +1 for the lower child.
 // Written in difference form it reproduces a uniform field exactly.
+#include <mutex>
+
 #include "mrfv_internal.h"
 
 namespace mrfv {
@@ -941,6 +943,36 @@ hipError_t launch_totals(const T *U, const WorkList &leaves, const DevTables &tb
     hipLaunchKernelGGL(k_sum_inst, dim3(n_inst), dim3(TPB), 0, st, tb.lists, tb.lists,
                        tb.lists + n_inst, tb.meta, inst, blocksum, tot);
     return hipGetLastError();
+}
+
+// Per-slot FP64 partial sums of mrfv_totals_noalloc, for callers that cannot allocate:
+// a file-scope device array of STATIC_TOTALS_SLOTS * 5 doubles (2.6 MB, held by every
+// device the library runs on until the process ends).  Host code never passes the
+// array's name to a kernel: it is a host-side stand-in, not a device address.  The
+// device address is looked up once per device (static_totals_scratch) and kept.
+constexpr int STATIC_TOTALS_SLOTS = 65536;
+static __device__ __align__(256) double scratch[(size_t)STATIC_TOTALS_SLOTS * 5];
+
+int static_totals_slots() { return STATIC_TOTALS_SLOTS; }
+
+hipError_t static_totals_scratch(int device, double **ptr) {
+    constexpr int MAX_DEV = 64;
+    static std::mutex mu;
+    static double *addr[MAX_DEV] = {};
+    if (device < 0 || device >= MAX_DEV) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device) return hipErrorInvalidDevice;   // resolved with the device current
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[device] = (double *)p;
+    }
+    *ptr = addr[device];
+    return hipSuccess;
 }
 
 #define MRFV_INST(T)                                                                        \

@@ -235,6 +235,10 @@ hipError_t launch_cfl(const T *U, const WorkList &leaves, const DevTables &tb,
                       hipStream_t st, int32_t *gate = nullptr, const int32_t *desc = nullptr,
                       int32_t *desc_g = nullptr, int n_desc = 0);
 int cfl_slabs();      // z-slab maxima per block in the CFL reduction
+// Static device scratch of the allocation-free totals: its capacity in slots, and its
+// device address on `device` (looked up once, with that device current).
+int static_totals_slots();
+hipError_t static_totals_scratch(int device, double **ptr);
 // the per-block pass of the CFL step alone, over any list of leaves
 template <typename T>
 hipError_t launch_cfl_blocks(const T *U, const WorkList &wl, const DevTables &tb,
@@ -300,6 +304,8 @@ struct mrfv_ctx {
     mrfv::HostLists lists;
     mrfv::DevTables tb;
     mrfv::InstDev *d_inst = nullptr;
+    int device = -1;                   // the HIP device current at mrfv_create
+    double *d_static_totals = nullptr; // that device's static totals scratch (not owned)
     int32_t *d_err = nullptr;          // device error word
     void *d_W = nullptr, *d_W2 = nullptr;   // second and third padded state buffers
                                             // (fused FP32 stages: U -> W -> W2 -> U)

@@ -74,6 +74,7 @@ def lib():
         "mrfv_set_detail_band": ([vp, d], C.c_int),
         "mrfv_cfl_dt": ([vp, vp, vp], C.c_int),
         "mrfv_totals": ([vp, vp, vp], C.c_int),
+        "mrfv_totals_noalloc": ([vp, vp, vp], C.c_int),
         "mrfv_commit_flags": ([vp, C.POINTER(C.c_int8), C.POINTER(i32), C.POINTER(i32)], C.c_int),
         "mrfv_step": ([vp, vp, vp, vp, vp], C.c_int),
         "mrfv_run": ([vp, vp, vp, vp, vp, i32, C.POINTER(i64)], C.c_int),
@@ -125,7 +126,7 @@ def exported_symbols():
             "mrfv_mlp_get_params", "mrfv_mlp_forward", "mrfv_mlp_loss_grad",
             "mrfv_mlp_adam_step", "mrfv_features", "mrfv_set_proposer", "mrfv_proposer_stats",
             "mrfv_last_flags", "mrfv_step_timing", "mrfv_rhs_variant", "mrfv_autotune",
-            "mrfv_fused_stage", "mrfv_run", "mrfv_set_detail_band"]
+            "mrfv_fused_stage", "mrfv_run", "mrfv_set_detail_band", "mrfv_totals_noalloc"]
 
 
 def morton_encode(shadow, level, bx, by, bz) -> int:
