@@ -87,7 +87,7 @@ def kernel_name(shape) -> str:
     """Demangled name of the fused kernel's instantiation for a variant shape."""
     gp, tpb, wpe, ptr = shape
     b = lambda v: "true" if v else "false"
-    return f"k_rhs_update<float, {gp}, {abs(tpb)}, {b(tpb < 0)}, {wpe}, 0, {b(ptr)}>"
+    return f"k_rhs_update<float, {gp}, {abs(tpb)}, {b(tpb < 0)}, {wpe}, 0>"
 
 
 def flops_per_cell_update(llf_fraction: float) -> float:

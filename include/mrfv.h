@@ -64,6 +64,8 @@ typedef struct {
     int32_t n0[3];        /* level-0 blocks per axis                                    */
     int32_t bc[3];        /* mrfv_bc per axis                                           */
     int32_t adapt;        /* 1: refine/coarsen after each step                          */
+    double gravity[3];    /* source term of eq:Euler: S(U) = (0, rho g, rho v . g); zero
+                             vector: no source                                          */
 } mrfv_instance;
 
 typedef struct {

@@ -20,7 +20,8 @@ class _Params(C.Structure):
     _fields_ = [("gamma", C.c_double), ("B", C.c_double), ("cfl", C.c_double),
                 ("eps", C.c_double), ("scale_rho", C.c_double), ("scale_E", C.c_double),
                 ("dx0", C.c_double), ("lmax", C.c_int32), ("n0", C.c_int32 * 3),
-                ("bc", C.c_int32 * 3), ("adapt", C.c_int32), ("scheme", C.c_int32)]
+                ("bc", C.c_int32 * 3), ("adapt", C.c_int32), ("scheme", C.c_int32),
+                ("gravity", C.c_double * 3)]
 
 
 IC_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
@@ -306,6 +307,8 @@ class Sim:
             p.bc[a] = problem.bc[a]
         p.adapt = problem.adapt if adapt is None else int(adapt)
         p.scheme = SCHEMES[getattr(problem, "scheme", "roe_weno5")]
+        for a, gv in enumerate(getattr(problem, "gravity", (0.0, 0.0, 0.0))):
+            p.gravity[a] = gv
         self._p = p
         self.h = lib().orc_sim_create(C.byref(p))
         self._cb = None

@@ -114,6 +114,7 @@ typedef struct {
     int32_t bc[3];         /* per axis: 0 periodic, 1 zero-gradient            */
     int32_t adapt;         /* 1: refine/coarsen after each step                */
     int32_t scheme;        /* flux kernel, see orc_face_flux_scheme            */
+    double gravity[3];     /* source term of eq:Euler: S = (0, rho g, rho v.g) */
 } orc_params;
 
 typedef struct orc_sim orc_sim;

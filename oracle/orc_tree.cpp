@@ -313,6 +313,20 @@ long block_rhs(const orc_sim *s, Block *b) {
                     const double ddz = F[fidx(2, q, j, i, k + 1)] - F[fidx(2, q, j, i, k)];
                     b->rhs[ati(q, k, j, i)] = -(ddx + ddy + ddz) / dx;
                 }
+    // Source term of eq:Euler: gravity, S(u) = (0, rho g, rho v . g), from the stage state.
+    const double *gv = s->p.gravity;
+    if (gv[0] != 0.0 || gv[1] != 0.0 || gv[2] != 0.0)
+        for (int k = 0; k < N; ++k)
+            for (int j = 0; j < N; ++j)
+                for (int i = 0; i < N; ++i) {
+                    const double rho = b->u[at(0, H + k, H + j, H + i)];
+                    double work = 0.0;
+                    for (int a = 0; a < 3; ++a) {
+                        b->rhs[ati(1 + a, k, j, i)] += rho * gv[a];
+                        work += b->u[at(1 + a, H + k, H + j, H + i)] * gv[a];
+                    }
+                    b->rhs[ati(4, k, j, i)] += work;
+                }
     // Boundary face planes for the jump correction, stored [q][m][r].
     for (int side = 0; side < 6; ++side) {
         const int d = side / 2, f = (side % 2) ? N : 0;

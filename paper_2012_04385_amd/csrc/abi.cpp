@@ -43,6 +43,8 @@ int check_instance(mrfv_ctx *ctx, const mrfv_instance &p, int i) {
     if (!(p.eps >= 0.0)) return fail(ctx, MRFV_EINVAL, w + "eps must be >= 0");
     if (!(p.scale_rho > 0.0) || !(p.scale_E > 0.0))
         return fail(ctx, MRFV_EINVAL, w + "detail scales must be > 0");
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(p.gravity[a])) return fail(ctx, MRFV_EINVAL, w + "gravity must be finite");
     if (p.lmax < 0 || p.lmax > 12) return fail(ctx, MRFV_EINVAL, w + "lmax must be in [0,12]");
     for (int a = 0; a < 3; ++a) {
         if (p.n0[a] < 1 || ((int64_t)p.n0[a] << p.lmax) > 65535)
@@ -242,7 +244,7 @@ int do_rhs(mrfv_ctx *ctx, const T *U, T *Lout) {
     const HostLists &L = ctx->lists;
     (void)L;
     HIP_OK(launch_combine<T>((const T *)ctx->d_D, Lout, wlist(ctx, DESC_LEAVES), ctx->tb,
-                             ctx->d_inst, ctx->stream));
+                             ctx->d_inst, U, ctx->stream));
     return MRFV_OK;
 }
 
@@ -924,7 +926,8 @@ int mrfv_create(mrfv_ctx **out, const mrfv_config *cfg, const mrfv_instance *ins
         const mrfv_instance &p = inst[i];
         id[i] = InstDev{p.gamma, p.B, p.cfl, p.eps, p.scale_rho, p.scale_E, p.dx0, p.lmax,
                         {p.n0[0], p.n0[1], p.n0[2]}, {p.bc[0], p.bc[1], p.bc[2]}, p.adapt,
-                        DETAIL_BAND_DEFAULT};
+                        DETAIL_BAND_DEFAULT, {p.gravity[0], p.gravity[1], p.gravity[2]},
+                        (p.gravity[0] != 0.0 || p.gravity[1] != 0.0 || p.gravity[2] != 0.0) ? 1 : 0};
     }
 #define ALLOC(ptr, bytes)                                                                  \
     if (hipMalloc((void **)&(ptr), (bytes)) != hipSuccess) {                                \

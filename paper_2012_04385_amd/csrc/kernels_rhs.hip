@@ -548,23 +548,47 @@ __global__ __launch_bounds__(TPB) void k_reflux(T *D, const T *__restrict__ FF, 
     }
 }
 
+// Gravity source of eq:Euler at one cell, added to the right-hand side L:
+// S(u) = (0, rho g, rho v . g) with the momenta m = rho v of the stage state.
+template <typename T>
+__device__ __forceinline__ void add_source(const InstDev &P, const T u[5], T L[5]) {
+    const T gx = (T)P.gravity[0], gy = (T)P.gravity[1], gz = (T)P.gravity[2];
+    L[1] = fma(u[0], gx, L[1]);
+    L[2] = fma(u[0], gy, L[2]);
+    L[3] = fma(u[0], gz, L[3]);
+    L[4] += fma(u[3], gz, fma(u[2], gy, u[1] * gx));
+}
+
 template <typename T>
 __global__ __launch_bounds__(TPB) void k_combine(const T *__restrict__ D, T *L, WorkList wl,
                                                  const BlockMeta *__restrict__ meta,
-                                                 const InstDev *__restrict__ inst) {
+                                                 const InstDev *__restrict__ inst,
+                                                 const T *__restrict__ U) {
     const int nb = wl.count();
     for (int b = blockIdx.x; b < nb; b += gridDim.x) {
     const int slot = wl.at(b);
     const BlockMeta mt = meta[slot];
-    const T inv_dx = (T)(1.0 / ldexp(inst[mt.inst].dx0, -mt.level));
+    const InstDev &P = inst[mt.inst];
+    const T inv_dx = (T)(1.0 / ldexp(P.dx0, -mt.level));
     const T *Ds = D + (size_t)slot * 3 * 5 * CELLS_I;
     T *Ls = L + (size_t)slot * 5 * CELLS_I;
     const int c = blockIdx.y * TPB + threadIdx.x;
+    T l[5];
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
         const T s = (Ds[q * CELLS_I + c] + Ds[(5 + q) * CELLS_I + c]) + Ds[(10 + q) * CELLS_I + c];
-        Ls[q * CELLS_I + c] = -s * inv_dx;
+        l[q] = -s * inv_dx;
     }
+    if (P.has_source) {   // uniform per workgroup
+        const T *ub = U + (size_t)slot * 5 * CELLS_P;
+        const int o = ((c / FACE + HW) * NP + (c / NI) % NI + HW) * NP + c % NI + HW;
+        T u[5];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) u[q] = ub[o + q * CELLS_P];
+        add_source(P, u, l);
+    }
+#pragma unroll
+    for (int q = 0; q < 5; ++q) Ls[q * CELLS_I + c] = l[q];
     }
 }
 
@@ -714,7 +738,7 @@ __device__ __forceinline__ void face_flux_at(const T *__restrict__ ub, const T *
     Fp[t2] = F[3];
 }
 
-template <typename T, int GP, int TPB_F, bool PERSIST, int WPE, int SCH, bool PTR>
+template <typename T, int GP, int TPB_F, bool PERSIST, int WPE, int SCH>
 __global__ __attribute__((amdgpu_flat_work_group_size(TPB_F, TPB_F), amdgpu_waves_per_eu(WPE)))
 void k_rhs_update(int stage, const double *__restrict__ dt,
                                                       const T *__restrict__ Uin, T *__restrict__ Uout,
@@ -723,7 +747,7 @@ void k_rhs_update(int stage, const double *__restrict__ dt,
                                                       const int32_t *__restrict__ nbr,
                                                       const InstDev *__restrict__ inst, T *FF,
                                                       int32_t *err, int restrict_parents,
-                                                      double *__restrict__ cflmax) {
+                                                      double *__restrict__ cflmax, int force_ptr) {
     constexpr int NFX = GP * NI * (NI + 1);   // x-faces per group (y-faces alike)
     // x- and y-faces are numbered with the faces 3 .. 13 of each row first: their
     // six-cell stencils lie in the own interior, so whole wavefronts of them take the
@@ -775,7 +799,9 @@ void k_rhs_update(int stage, const double *__restrict__ dt,
         }
         // every access lies below the highest source plus one block
         const uintptr_t span = mx - mn + (uintptr_t)(5 * CELLS_P * sizeof(T));
-        ns.near = !PTR && span <= (uintptr_t)0xffffffffu;   // PTR: always the pointer loads
+        // force_ptr (a launch argument, so the code is the production code): always the
+        // per-lane pointer loads
+        ns.near = !force_ptr && span <= (uintptr_t)0xffffffffu;
         ns.rsrc = __builtin_amdgcn_make_buffer_rsrc((void *)(ub - ((uintptr_t)ub - mn) / sizeof(T)),
                                                     (short)0, ns.near ? (int)(unsigned)span : 0,
                                                     BUFFER_RSRC_WORD3);
@@ -825,18 +851,23 @@ void k_rhs_update(int stage, const double *__restrict__ dt,
             const int z = k0 + p;
             const int c = (z * NI + cy) * NI + cx;
             const int o = ((z + HW) * NP + cy + HW) * NP + cx + HW;
-            T un[5];
+            T un[5], us[5], lq[5];
 #pragma unroll
             for (int q = 0; q < 5; ++q) {
-                const T us = ub[o + q * CELLS_P];
+                us[q] = ub[o + q * CELLS_P];
+                lq[q] = -D[p][q] * inv_dx;
+            }
+            if (P.has_source) add_source(P, us, lq);   // uniform per workgroup
+#pragma unroll
+            for (int q = 0; q < 5; ++q) {
                 T u0;
                 if (stage == 0) {
-                    u0 = us;
-                    u0b[q * CELLS_I + c] = us;
+                    u0 = us[q];
+                    u0b[q * CELLS_I + c] = us[q];
                 } else {
                     u0 = u0b[q * CELLS_I + c];
                 }
-                un[q] = u0 + a * ((us - u0) + dtt * (-D[p][q] * inv_dx));
+                un[q] = u0 + a * ((us[q] - u0) + dtt * lq[q]);
                 ob[o + q * CELLS_P] = un[q];
                 unew[p][q] = un[q];
             }
@@ -1077,10 +1108,10 @@ hipError_t launch_reflux(T *D, const T *FF, const WorkList &wl, const DevTables 
 
 template <typename T>
 hipError_t launch_combine(const T *D, T *L, const WorkList &wl, const DevTables &tb,
-                          const InstDev *inst, hipStream_t st) {
+                          const InstDev *inst, const T *U, hipStream_t st) {
     if (wl.grid <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_combine<T>, dim3(wl.grid, CELLS_I / TPB), dim3(TPB), 0, st, D, L, wl,
-                       tb.meta, inst);
+                       tb.meta, inst, U);
     return hipGetLastError();
 }
 
@@ -1098,8 +1129,9 @@ hipError_t launch_update(int stage, const double *dt, T *U, T *U0, const T *L, c
 // at once (3 waves per SIMD at their register count) loops over the leaves instead of
 // one workgroup per leaf.  Variants 11 and 12 ask the register allocator for 5 waves per
 // SIMD (at most 96 registers, some spilled to scratch) instead of the default 4.
-// Variant 13 is variant 7 with the stencils always loaded through per-lane pointers (the
-// path taken when a workgroup's source blocks span more than 4 GiB).
+// Variant 13 is variant 7 (the same code) told at launch to load the stencils through
+// per-lane pointers always (the path taken when a workgroup's source blocks span more
+// than 4 GiB).
 constexpr int N_RHS_VARIANTS = 14;
 constexpr int RHS_GP[N_RHS_VARIANTS] = {2, 1, 2, 2, 4, 4, 2, 2, 1, 2, 2, 2, 2, 2};
 constexpr int RHS_TPB[N_RHS_VARIANTS] = {320, 256, 256, 384, 320, 512, 448, 512, 320, 512, 384, 320, 640, 512};
@@ -1122,10 +1154,10 @@ static void launch_variant(int stage, const double *dt, const float *Uin, float 
     constexpr int G = RHS_GP[V], B = RHS_TPB[V];
     constexpr bool PS = RHS_PERSIST[V];
     constexpr int WP = RHS_WPE[V];
-    constexpr bool PT = RHS_PTR[V];
     const int grid = PS ? std::min(wl.grid, persist_grid(B)) : round_xcd(wl.grid);
-    hipLaunchKernelGGL((k_rhs_update<float, G, B, PS, WP, SCH, PT>), dim3(grid), dim3(B), 0, st, stage, dt, Uin,
-                       Uout, U0, wl, tb.meta, tb.nbr, inst, FF, err, restrict_parents, cflmax);
+    hipLaunchKernelGGL((k_rhs_update<float, G, B, PS, WP, SCH>), dim3(grid), dim3(B), 0, st, stage, dt, Uin,
+                       Uout, U0, wl, tb.meta, tb.nbr, inst, FF, err, restrict_parents, cflmax,
+                       RHS_PTR[V] ? 1 : 0);
 }
 
 int rhs_variants(int scheme) { return scheme == SCH_ROE_WENO5 ? N_RHS_VARIANTS : N_ALT_VARIANTS; }
@@ -1203,7 +1235,7 @@ hipError_t launch_reflux_update(int stage, const double *dt, T *U, const T *FF,
     template hipError_t launch_reflux<T>(T *, const T *, const WorkList &, const DevTables &, \
                                          hipStream_t);                                      \
     template hipError_t launch_combine<T>(const T *, T *, const WorkList &, const DevTables &, \
-                                          const InstDev *, hipStream_t);                    \
+                                          const InstDev *, const T *, hipStream_t);         \
     template hipError_t launch_update<T>(int, const double *, T *, T *, const T *,          \
                                          const WorkList &, const DevTables &, const InstDev *, \
                                          int32_t *, hipStream_t);                           \

@@ -36,6 +36,8 @@ struct InstDev {
     double gamma, B, cfl, eps, scale_rho, scale_E, dx0;
     int32_t lmax, n0[3], bc[3], adapt;
     double detail_band;   // slabs with |detail - eps_l| <= band are evaluated again exactly
+    double gravity[3];    // source term S(U) = (0, rho g, rho v . g)
+    int32_t has_source;   // gravity is not the zero vector
 };
 constexpr double DETAIL_BAND_DEFAULT = 1e-9;
 
@@ -258,7 +260,7 @@ hipError_t launch_reflux(T *D, const T *FF, const WorkList &leaves, const DevTab
                          hipStream_t st);
 template <typename T>
 hipError_t launch_combine(const T *D, T *L, const WorkList &leaves, const DevTables &tb,
-                          const InstDev *inst, hipStream_t st);
+                          const InstDev *inst, const T *U, hipStream_t st);
 template <typename T>
 hipError_t launch_update(int stage, const double *dt, T *U, T *U0, const T *L,
                          const WorkList &leaves, const DevTables &tb, const InstDev *inst,

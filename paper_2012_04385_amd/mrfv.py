@@ -30,7 +30,7 @@ class Instance(C.Structure):
     _fields_ = [("gamma", C.c_double), ("B", C.c_double), ("cfl", C.c_double),
                 ("eps", C.c_double), ("scale_rho", C.c_double), ("scale_E", C.c_double),
                 ("dx0", C.c_double), ("lmax", C.c_int32), ("n0", C.c_int32 * 3),
-                ("bc", C.c_int32 * 3), ("adapt", C.c_int32)]
+                ("bc", C.c_int32 * 3), ("adapt", C.c_int32), ("gravity", C.c_double * 3)]
 
 
 class Config(C.Structure):
@@ -148,6 +148,8 @@ def _instance(pb) -> Instance:
         inst.n0[a] = pb.n0[a]
         inst.bc[a] = pb.bc[a]
     inst.adapt = pb.adapt
+    for a, gv in enumerate(getattr(pb, "gravity", (0.0, 0.0, 0.0))):
+        inst.gravity[a] = gv
     return inst
 
 

