@@ -106,7 +106,8 @@ WorkList wlist(const mrfv_ctx *ctx, int which, int grid_cap = 2048, bool gated =
         if (2 * which + 1 >= (int)d.size() || d[2 * which + 1] == 0) return w;   // grid 0: skipped
         // bound: the most blocks the list can ever hold (per level: every instance full)
         int64_t bound = ctx->cfg.slot_capacity;
-        if (which >= desc_lvl(0)) bound = std::min<int64_t>(bound, ctx->lvl_bound[(which - desc_lvl(0)) / DESC_PER_LEVEL]);
+        if (which >= desc_lvl(0) && which < desc_lvl(0) + DESC_PER_LEVEL * MAX_LEVELS)   // per-level lists
+            bound = std::min<int64_t>(bound, ctx->lvl_bound[(which - desc_lvl(0)) / DESC_PER_LEVEL]);
         w.grid = (int)std::min<int64_t>(bound, grid_cap);
     } else {
         const std::vector<int32_t> &d = ctx->lists.desc;

@@ -1020,7 +1020,7 @@ void k_rhs_update(int stage, const double *__restrict__ dt,
             double v = cfl_acc[tid][0];
 #pragma unroll
             for (int w = 1; w < FACE / 64; ++w) v = fmax(v, cfl_acc[tid][w]);
-            double *bm = cflmax + (size_t)b * CFL_SLABS * 3;   // by leaf-list position
+            double *bm = cflmax + (size_t)mt.lpos * CFL_SLABS * 3;   // by all-leaves position
             bm[tid] = v;
 #pragma unroll
             for (int k = 1; k < CFL_SLABS; ++k) bm[k * 3 + tid] = 0.0;
