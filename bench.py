@@ -39,6 +39,7 @@ sys.path.insert(0, ROOT)
 FACE_BASE, LLF_EXTRA, UPDATE = 734.0, 110.0, 40.0
 PEAK_FP32_VECTOR = 157.3e12       # MI355X FP32 vector with packed FP32 (FLOP/s)
 PEAK_FP32_UNPACKED = 78.6e12      # without packed FP32 instructions (this build)
+PEAK_FP64_VECTOR = 78.6e12        # MI355X FP64 vector (FLOP/s)
 PEAK_HBM = 8.0e12                 # bytes/s
 # algorithmic bytes per FP32 cell-update of the fused kernel, every stage: read the interior
 # and the 3-wide face layers (5 components x 4 B x 8704 / 4096 cells = 42.5 B), write the new
@@ -292,6 +293,13 @@ def main():
         v64 = cells64 / secs64
         log(f"[bench] FP64 plain: {v64:.4e} cell-updates/s")
         extra.update({"fp64_plain_value": v64, "speedup_vs_fp64_plain": value / v64})
+        # the baseline's own roofline: the same FLOP model per cell-update over the whole
+        # step's rate (an upper bound on the plain path's flux kernel rate) against FP64 peak
+        fpc64 = flops_per_cell_update(res.get("llf", 0.5))
+        extra["fp64_plain_roofline"] = {"bound": "alu", "achieved": v64 * fpc64 / 1e12,
+                                        "peak": PEAK_FP64_VECTOR / 1e12, "unit": "TFLOP/s",
+                                        "frac": v64 * fpc64 / PEAK_FP64_VECTOR,
+                                        "basis": "whole-step rate x FLOP model"}
 
     if not args.no_extra and name != "blast_128e_3lvl":
         pb2 = problems("blast_128e_3lvl", 50)
