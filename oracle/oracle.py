@@ -14,6 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
 
 P, H, N = 24, 4, 16
+MAX_LEVELS = 16
 
 
 class _Params(C.Structure):
@@ -63,6 +64,15 @@ def lib():
         L.orc_sim_init.restype = C.c_int
         L.orc_sim_step.argtypes = [vp, pd]
         L.orc_sim_step.restype = C.c_int
+        L.orc_sim_step_dt.argtypes = [vp, d]
+        L.orc_sim_step_dt.restype = C.c_int
+        L.orc_sim_step_lts_dt.argtypes = [vp, d]
+        L.orc_sim_step_lts_dt.restype = C.c_int
+        L.orc_sim_step_lts.argtypes = [vp, pd]
+        L.orc_sim_step_lts.restype = C.c_int
+        L.orc_sim_lts_steps.argtypes = [vp, C.POINTER(C.c_int64)]
+        L.orc_lts_lowest_ending.argtypes = [i32, i32]
+        L.orc_lts_lowest_ending.restype = i32
         L.orc_sim_nblocks.argtypes = [vp]
         L.orc_sim_nblocks.restype = i32
         L.orc_sim_blocks.argtypes = [vp, C.POINTER(C.c_int64)]
@@ -218,6 +228,11 @@ def exact_riemann(left, right, gamma, s) -> np.ndarray:
     return out
 
 
+def lts_lowest_ending(lmax: int, r: int) -> int:
+    """Lowest level that completes a step of its own at micro step r (algo:ComputeLoop)."""
+    return lib().orc_lts_lowest_ending(lmax, r)
+
+
 def num_threads() -> int:
     return int(lib().orc_num_threads())
 
@@ -344,6 +359,31 @@ class Sim:
         if rc != 0:
             raise RuntimeError(f"oracle step failed ({rc}): non-physical state")
         return dt.value
+
+    def step_dt(self, dt: float):
+        """One global step with a given dt."""
+        if lib().orc_sim_step_dt(self.h, dt) != 0:
+            raise RuntimeError("oracle step failed: non-physical state")
+
+    def step_lts_dt(self, dt: float):
+        """One LTS macro step with a given level-lmax step dt."""
+        if lib().orc_sim_step_lts_dt(self.h, dt) != 0:
+            raise RuntimeError("oracle LTS step failed: non-physical state")
+
+    def step_lts(self) -> float:
+        """One macro step of local time stepping (eq:LtsTimestep): 2^lmax micro steps of
+        the returned dt (the eq:Cfl step of level lmax), level l stepping 2^(lmax-l) dt."""
+        dt = C.c_double(0.0)
+        rc = lib().orc_sim_step_lts(self.h, C.byref(dt))
+        if rc != 0:
+            raise RuntimeError(f"oracle LTS step failed ({rc}): non-physical state")
+        return dt.value
+
+    def lts_steps(self) -> np.ndarray:
+        """Own steps completed per level under local time stepping."""
+        out = np.zeros(MAX_LEVELS, dtype=np.int64)
+        lib().orc_sim_lts_steps(self.h, out.ctypes.data_as(C.POINTER(C.c_int64)))
+        return out
 
     def blocks(self) -> np.ndarray:
         n = lib().orc_sim_nblocks(self.h)

@@ -38,6 +38,7 @@ extern "C" {
 #define ORC_IC 16   /* interior cells per block edge            */
 #define ORC_H 4     /* halo layers per side                     */
 #define ORC_P 24    /* padded edge = ORC_IC + 2*ORC_H           */
+#define ORC_MAX_LEVELS 16
 
 /* ---------------- pointwise numerics (Sec. "Numerical Scheme", eq:StiffenedGas) ---- */
 
@@ -133,6 +134,18 @@ int orc_sim_init(orc_sim *s, orc_ic_fn ic, void *user);
 /* One global time step: CFL dt, three SSP-RK3 stages, then MR adaptation.
  * Returns 0, or -5 when a non-physical state (rho<=0, p+B<=0, NaN) appeared. */
 int orc_sim_step(orc_sim *s, double *dt_out);
+/* the same step with a given dt (time-step convergence studies) */
+int orc_sim_step_dt(orc_sim *s, double dt);
+/* One macro step of local time stepping (eq:LtsTimestep, algo:ComputeLoop,
+ * algo:Integration): 2^lmax micro steps of dt = the eq:Cfl step of level lmax, level l
+ * advancing with 2^(lmax-l) dt; adaptation (if enabled) once, at the end, when every
+ * level has reached the same time.  *dt_out = dt; time advances by 2^lmax dt. */
+int orc_sim_step_lts(orc_sim *s, double *dt_out);
+int orc_sim_step_lts_dt(orc_sim *s, double dt);
+/* own steps completed per level since creation (ORC_MAX_LEVELS entries) */
+void orc_sim_lts_steps(const orc_sim *s, int64_t *out);
+/* lowest level that completes a step of its own at micro step r */
+int32_t orc_lts_lowest_ending(int32_t lmax, int32_t r);
 
 /* Block table: n blocks; info[n][8] = (level, bx, by, bz, is_leaf, flag, morton, 0). */
 int32_t orc_sim_nblocks(const orc_sim *s);

@@ -42,6 +42,10 @@ struct Block {
     std::vector<double> u0;    // 5 * 16^3 state at t^n
     std::vector<double> rhs;   // 5 * 16^3
     std::vector<double> face[6];  // boundary face fluxes, 5 * 16 * 16 each
+    // local time stepping only
+    std::vector<double> F;        // 5 * 24^3 flux divergence (interior and halo)
+    std::vector<double> u0p;      // 5 * 24^3 state at the start of the block's own step
+    std::vector<double> acc[6];   // time-integrated boundary face fluxes, 5 * 16 * 16 each
     Block() : u(5 * CELLS, 0.0) {}
 };
 
@@ -52,6 +56,7 @@ struct orc_sim {
     int shadow = 0;
     double time = 0.0;
     double llf_fraction = 0.0;
+    int64_t lts_steps[ORC_MAX_LEVELS] = {};  // own steps completed per level (local time stepping)
     std::unordered_map<uint64_t, Block *> map;
     std::vector<Block *> order;  // blocks sorted by (level, id); rebuilt after edits
     ~orc_sim() {
@@ -184,7 +189,9 @@ void predict_interior(const Block *parent, Block *child) {
     }
 }
 
-void average_into_parent(orc_sim *s, Block *parent) {
+using Field = std::vector<double> Block::*;
+
+void average_into_parent(orc_sim *s, Block *parent, Field fld = &Block::u) {
     for (int oz = 0; oz < 2; ++oz)
         for (int oy = 0; oy < 2; ++oy)
             for (int ox = 0; ox < 2; ++ox) {
@@ -198,10 +205,10 @@ void average_into_parent(orc_sim *s, Block *parent) {
                                     for (int cy = 0; cy < 2; ++cy)
                                         for (int cx = 0; cx < 2; ++cx)
                                             v[cz * 4 + cy * 2 + cx] =
-                                                c->u[at(q, H + 2 * K + cz, H + 2 * J + cy,
-                                                        H + 2 * I + cx)];
-                                parent->u[at(q, H + oz * N / 2 + K, H + oy * N / 2 + J,
-                                             H + ox * N / 2 + I)] = orc_average8(v);
+                                                (c->*fld)[at(q, H + 2 * K + cz, H + 2 * J + cy,
+                                                             H + 2 * I + cx)];
+                                (parent->*fld)[at(q, H + oz * N / 2 + K, H + oy * N / 2 + J,
+                                                  H + ox * N / 2 + I)] = orc_average8(v);
                             }
             }
 }
@@ -215,7 +222,8 @@ void project(orc_sim *s) {
     }
 }
 
-void fill_block_halos(orc_sim *s, Block *b) {
+void fill_block_halos(orc_sim *s, Block *b, Field fld = &Block::u) {
+    std::vector<double> &u = b->*fld;
     const int lo[3] = {0, H, H + N}, hi[3] = {H, H + N, P};
     Block *parent = parent_of(s, b);
     for (int dz = -1; dz <= 1; ++dz)
@@ -231,11 +239,11 @@ void fill_block_halos(orc_sim *s, Block *b) {
                             for (int i = lo[dx + 1]; i < hi[dx + 1]; ++i) {
                                 double v;
                                 if (nb)
-                                    v = nb->u[at(q, k - N * dz, j - N * dy, i - N * dx)];
+                                    v = (nb->*fld)[at(q, k - N * dz, j - N * dy, i - N * dx)];
                                 else
-                                    v = orc_predict_cell(parent->u.data() + q * CELLS, b->bx & 1,
-                                                         b->by & 1, b->bz & 1, i, j, k);
-                                b->u[at(q, k, j, i)] = v;
+                                    v = orc_predict_cell((parent->*fld).data() + q * CELLS,
+                                                         b->bx & 1, b->by & 1, b->bz & 1, i, j, k);
+                                u[at(q, k, j, i)] = v;
                             }
             }
     // Zero-gradient boundaries, axis by axis over the full padded extent.
@@ -258,18 +266,18 @@ void fill_block_halos(orc_sim *s, Block *b) {
                             const int o1 = (a + 1) % 3, o2 = (a + 2) % 3;
                             is[o1] = id[o1] = r;
                             is[o2] = id[o2] = m;
-                            b->u[at(q, id[2], id[1], id[0])] = b->u[at(q, is[2], is[1], is[0])];
+                            u[at(q, id[2], id[1], id[0])] = u[at(q, is[2], is[1], is[0])];
                         }
                 }
         }
     }
 }
 
-void fill_halos(orc_sim *s) {
+void fill_halos(orc_sim *s, Field fld = &Block::u) {
     for (int l = 0; l <= s->p.lmax; ++l) {
         std::vector<Block *> lv = blocks_on_level(s, l);
 #pragma omp parallel for schedule(static)
-        for (long n = 0; n < (long)lv.size(); ++n) fill_block_halos(s, lv[n]);
+        for (long n = 0; n < (long)lv.size(); ++n) fill_block_halos(s, lv[n], fld);
     }
 }
 
@@ -340,8 +348,10 @@ long block_rhs(const orc_sim *s, Block *b) {
 
 // Face plane of block b on side `side`: its own flux if a leaf, else the area average of
 // its children's planes on that side (recursively).
-std::vector<double> face_plane(orc_sim *s, Block *b, int side) {
-    if (b->leaf) return b->face[side];
+using Planes = std::vector<double>[6];
+
+std::vector<double> face_plane(orc_sim *s, Block *b, int side, Planes Block::*pl = &Block::face) {
+    if (b->leaf) return (b->*pl)[side];
     const int d = side / 2, hi = side % 2;
     const int o_lo = d == 0 ? 1 : 0, o_hi = d == 2 ? 1 : 2;
     std::vector<double> out(5 * PLANE, 0.0);
@@ -352,7 +362,7 @@ std::vector<double> face_plane(orc_sim *s, Block *b, int side) {
             o[o_lo] = cr;
             o[o_hi] = cm;
             Block *c = child_of(s, b, o[0], o[1], o[2]);
-            const std::vector<double> cp = face_plane(s, c, side);
+            const std::vector<double> cp = face_plane(s, c, side, pl);
             for (int q = 0; q < 5; ++q)
                 for (int M = 0; M < N / 2; ++M)
                     for (int R = 0; R < N / 2; ++R) {
@@ -506,6 +516,219 @@ void commit_flags(orc_sim *s) {
     rebuild_order(s);
 }
 
+// ------------------------------------------------------------ local time stepping ----
+//
+// eq:LtsTimestep: level l advances with its own step dt_l = 2^(lmax - l) dt, dt being the
+// eq:Cfl step of level lmax; a macro step is 2^lmax micro steps r (algo:ComputeLoop).
+// Level l completes one step of its own at micro step r when r + 1 is a multiple of
+// 2^(lmax - l); the levels doing so form the active set {lmax, ..., lmax + 1 -
+// popcount((r + 1) xor r)} of algo:ComputeLoop.  A level's first stage is evaluated at the
+// micro step its step starts in, its integration (all stages) happens at the micro step it
+// ends in.  Halo cells at a resolution jump carry their own state, integrated with the
+// flux divergence predicted from the coarser level (algo:Integration); the flux divergence
+// is averaged into parents and predicted into halos like the conserved variables.
+// Conservation: every leaf sums its boundary face fluxes over its stages and steps,
+// weighted as the RK scheme weights them; at the last stage of its step a coarse leaf
+// next to a refined same-level neighbour replaces its own sum on that face by the area
+// average of the fine sums (the coarse cell adjustment of algo:ComputeLoop).
+
+// Lowest level that ends a step at micro step r.
+int lts_lowest_ending(int lmax, int r) {
+    return lmax + 1 - __builtin_popcount((unsigned)((r + 1) ^ r));
+}
+
+// Lowest level that starts a step at micro step r (every level at r = 0).
+int lts_lowest_starting(int lmax, int r) { return r == 0 ? 0 : lts_lowest_ending(lmax, r - 1); }
+
+enum FaceKind { FACE_PRESENT, FACE_BOUNDARY, FACE_JUMP };
+
+FaceKind face_kind(orc_sim *s, const Block *b, int side, Block **nb_out = nullptr) {
+    int off[3] = {0, 0, 0};
+    off[side >> 1] = (side & 1) ? 1 : -1;
+    int np[3];
+    if (!neighbor_pos(s, b, off[0], off[1], off[2], np)) return FACE_BOUNDARY;
+    Block *nb = find(s, b->level, np[0], np[1], np[2]);
+    if (nb_out) *nb_out = nb;
+    return nb ? FACE_PRESENT : FACE_JUMP;
+}
+
+// Level of the leaf on the other side of a face: the block's own level unless the face is
+// a resolution jump, then the level of the coarser leaf that covers the position.
+int across_level(orc_sim *s, const Block *b, int side) {
+    if (face_kind(s, b, side) != FACE_JUMP) return b->level;
+    int off[3] = {0, 0, 0};
+    off[side >> 1] = (side & 1) ? 1 : -1;
+    int np[3];
+    neighbor_pos(s, b, off[0], off[1], off[2], np);
+    for (int m = b->level - 1; m >= 0; --m) {
+        const int sh = b->level - m;
+        if (find(s, m, np[0] >> sh, np[1] >> sh, np[2] >> sh)) return m;
+    }
+    return 0;
+}
+
+// The three halo layers of a face that the flux stencils read, interior extent across.
+template <class Fn>
+void for_face_slab(int side, Fn fn) {
+    const int d = side >> 1, hi = side & 1;
+    const int o_lo = d == 0 ? 1 : 0, o_hi = d == 2 ? 1 : 2;
+    for (int h = 0; h < 3; ++h)
+        for (int m = H; m < H + N; ++m)
+            for (int r = H; r < H + N; ++r) {
+                int c[3];
+                c[d] = hi ? H + N + h : H - 3 + h;
+                c[o_lo] = r;
+                c[o_hi] = m;
+                fn(c[2], c[1], c[0]);
+            }
+}
+
+// State halos of a leaf that are copies (same-level neighbour) or a zero-gradient
+// boundary; faces at resolution jumps keep their integrated values.
+void fill_present_faces(orc_sim *s, Block *b) {
+    for (int side = 0; side < 6; ++side) {
+        Block *nb = nullptr;
+        const FaceKind kind = face_kind(s, b, side, &nb);
+        if (kind == FACE_JUMP) continue;
+        const int d = side >> 1;
+        int off[3] = {0, 0, 0};
+        off[d] = (side & 1) ? 1 : -1;
+        const int src = (side & 1) ? H + N - 1 : H;
+        for (int q = 0; q < 5; ++q)
+            for_face_slab(side, [&](int k, int j, int i) {
+                if (kind == FACE_PRESENT) {
+                    b->u[at(q, k, j, i)] = nb->u[at(q, k - N * off[2], j - N * off[1], i - N * off[0])];
+                } else {
+                    int c[3] = {i, j, k};
+                    c[d] = src;
+                    b->u[at(q, k, j, i)] = b->u[at(q, c[2], c[1], c[0])];
+                }
+            });
+    }
+}
+
+// One RK stage of a leaf's own step (algo:Integration): interior cells and the halo cells
+// of its resolution-jump faces, from the stored flux divergence; the boundary face fluxes
+// of the stage are added to the leaf's sums with the stage's weight in the RK scheme
+// (SSP-RK3: 1/6, 1/6, 2/3).
+void lts_integrate(orc_sim *s, Block *b, int st, double dtl) {
+    static const double bw[3] = {1.0 / 6.0, 1.0 / 6.0, 2.0 / 3.0};
+    if (st == 0) b->u0p = b->u;
+    auto upd = [&](int q, int k, int j, int i) {
+        const int n = at(q, k, j, i);
+        b->u[n] = orc_ssprk3_stage(st, b->u0p[n], b->u[n], b->F[n], dtl);
+    };
+    for (int q = 0; q < 5; ++q)
+        for (int k = H; k < H + N; ++k)
+            for (int j = H; j < H + N; ++j)
+                for (int i = H; i < H + N; ++i) upd(q, k, j, i);
+    for (int side = 0; side < 6; ++side) {
+        if (face_kind(s, b, side) == FACE_JUMP)
+            for (int q = 0; q < 5; ++q)
+                for_face_slab(side, [&](int k, int j, int i) { upd(q, k, j, i); });
+        for (int n = 0; n < 5 * PLANE; ++n) b->acc[side][n] += bw[st] * dtl * b->face[side][n];
+    }
+}
+
+// Coarse cell adjustment at the end of a coarse leaf's step: on faces whose same-level
+// neighbour is refined, the own time-integrated flux is replaced by the average of the
+// fine ones.
+void lts_adjust(orc_sim *s, Block *b) {
+    const double dx = dx_level(s->p, b->level);
+    for (int side = 0; side < 6; ++side) {
+        Block *nb = nullptr;
+        if (face_kind(s, b, side, &nb) != FACE_PRESENT || nb->leaf) continue;
+        const std::vector<double> fine = face_plane(s, nb, side ^ 1, &Block::acc);
+        const int d = side >> 1, hi = side & 1;
+        const int o_lo = d == 0 ? 1 : 0, o_hi = d == 2 ? 1 : 2;
+        for (int q = 0; q < 5; ++q)
+            for (int m = 0; m < N; ++m)
+                for (int r = 0; r < N; ++r) {
+                    int c[3];
+                    c[d] = hi ? H + N - 1 : H;
+                    c[o_lo] = H + r;
+                    c[o_hi] = H + m;
+                    const double own = b->acc[side][(q * N + m) * N + r];
+                    const double fn = fine[(q * N + m) * N + r];
+                    b->u[at(q, c[2], c[1], c[0])] += hi ? (own - fn) / dx : (fn - own) / dx;
+                }
+    }
+}
+
+// Parents of the blocks on levels >= lo (descending), from their children.
+void average_levels(orc_sim *s, int lo, Field fld) {
+    for (int l = s->p.lmax; l >= std::max(lo, 1); --l) {
+        std::vector<Block *> pv = blocks_on_level(s, l - 1);
+#pragma omp parallel for schedule(static)
+        for (long n = 0; n < (long)pv.size(); ++n)
+            if (!pv[n]->leaf) average_into_parent(s, pv[n], fld);
+    }
+}
+
+void adapt_tree(orc_sim *s) {
+    project(s);
+    fill_halos(s);
+    compute_details(s);
+    compute_flags(s);
+    commit_flags(s);
+}
+
+int lts_macro_step(orc_sim *s, double dt) {
+    const int lmax = s->p.lmax;
+    project(s);
+    fill_halos(s);
+    for (Block *b : s->order) {
+        b->F.assign(5 * CELLS, 0.0);
+        for (int side = 0; side < 6; ++side) b->acc[side].assign(5 * PLANE, 0.0);
+    }
+    const std::vector<Block *> lv = leaves(s);
+    for (int r = 0; r < (1 << lmax); ++r) {
+        const int lo_end = lts_lowest_ending(lmax, r);
+        std::vector<Block *> ending;
+        for (Block *b : lv)
+            if (b->level >= lo_end) ending.push_back(b);
+        for (int st = 0; st < 3; ++st) {
+            const int lo_rhs = st == 0 ? lts_lowest_starting(lmax, r) : lo_end;
+            std::vector<Block *> eval;
+            for (Block *b : lv)
+                if (b->level >= lo_rhs) eval.push_back(b);
+#pragma omp parallel for schedule(static)
+            for (long n = 0; n < (long)eval.size(); ++n) fill_present_faces(s, eval[n]);
+#pragma omp parallel for schedule(static)
+            for (long n = 0; n < (long)eval.size(); ++n) {
+                Block *b = eval[n];
+                block_rhs(s, b);
+                for (int q = 0; q < 5; ++q)
+                    for (int k = 0; k < N; ++k)
+                        for (int j = 0; j < N; ++j)
+                            for (int i = 0; i < N; ++i)
+                                b->F[at(q, H + k, H + j, H + i)] = b->rhs[ati(q, k, j, i)];
+            }
+            average_levels(s, lo_rhs, &Block::F);
+            fill_halos(s, &Block::F);
+            int bad = 0;
+#pragma omp parallel for schedule(static) reduction(+ : bad)
+            for (long n = 0; n < (long)ending.size(); ++n) {
+                Block *b = ending[n];
+                lts_integrate(s, b, st, std::ldexp(dt, lmax - b->level));
+                if (!physical(s, b)) bad += 1;
+            }
+            if (bad) return -5;
+            if (st == 2) {
+#pragma omp parallel for schedule(static)
+                for (long n = 0; n < (long)ending.size(); ++n) lts_adjust(s, ending[n]);
+                // the sums a coarse leaf has just used start again
+                for (Block *b : lv)
+                    for (int side = 0; side < 6; ++side)
+                        if (across_level(s, b, side) >= lo_end) std::fill(b->acc[side].begin(), b->acc[side].end(), 0.0);
+                for (int l = lo_end; l <= lmax; ++l) s->lts_steps[l] += 1;
+            }
+            average_levels(s, lo_end, &Block::u);
+        }
+    }
+    return 0;
+}
+
 void impose_ic(orc_sim *s, Block *b, orc_ic_fn ic, void *user) {
     std::vector<double> prim(5 * ICELLS);
     ic(user, b->level, b->bx, b->by, b->bz, prim.data());
@@ -607,6 +830,10 @@ double orc_ssprk3_stage(int stage, double u0, double us, double L, double dt) {
 int orc_sim_step(orc_sim *s, double *dt_out) {
     const double dt = orc_sim_dt(s);
     if (dt_out) *dt_out = dt;
+    return orc_sim_step_dt(s, dt);
+}
+
+int orc_sim_step_dt(orc_sim *s, double dt) {
     std::vector<Block *> lv = leaves(s);
     for (Block *b : lv) {
         b->u0.assign(5 * ICELLS, 0.0);
@@ -646,6 +873,26 @@ int orc_sim_step(orc_sim *s, double *dt_out) {
     }
     return 0;
 }
+
+int orc_sim_step_lts(orc_sim *s, double *dt_out) {
+    const double dt = orc_sim_dt(s);
+    if (dt_out) *dt_out = dt;
+    return orc_sim_step_lts_dt(s, dt);
+}
+
+int orc_sim_step_lts_dt(orc_sim *s, double dt) {
+    const int rc = lts_macro_step(s, dt);
+    if (rc) return rc;
+    s->time += std::ldexp(dt, s->p.lmax);
+    if (s->p.adapt) adapt_tree(s);
+    return 0;
+}
+
+void orc_sim_lts_steps(const orc_sim *s, int64_t *out) {
+    for (int l = 0; l < ORC_MAX_LEVELS; ++l) out[l] = s->lts_steps[l];
+}
+
+int32_t orc_lts_lowest_ending(int32_t lmax, int32_t r) { return lts_lowest_ending(lmax, r); }
 
 int32_t orc_sim_nblocks(const orc_sim *s) { return (int32_t)s->order.size(); }
 
