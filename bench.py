@@ -214,6 +214,53 @@ def run_gpu(pbs, dtype, batched, warmup, steps, timing=False, variant=None, prep
     return g, cells, secs, kt
 
 
+def lts_leg(pbs, dtype, warmup, macro_steps):
+    """Local time stepping (mrfv_step_lts, plain kernels in `dtype`) against global steps
+    of the same kernels from the same start: simulated time advanced per second of wall
+    clock (time to solution), and cell-updates per second per RK stage (leaf cells times
+    their own steps)."""
+    import torch
+    from paper_2012_04385_amd.mrfv import Solver
+    lmax = pbs[0].lmax
+    out = {"dtype": dtype, "path": "plain per-block kernels", "macro_steps": macro_steps,
+           "micro_steps_per_macro_step": 1 << lmax}
+    g = Solver(pbs, dtype=dtype, batched=0).init()
+    for _ in range(warmup):
+        g.step_lts()
+    g.check()
+    torch.cuda.synchronize()
+    sim, cells = 0.0, 0
+    t0 = time.perf_counter()
+    for _ in range(macro_steps):
+        cells += 3 * g.step_lts()
+        sim += float(g.dt.cpu()[0]) * (1 << lmax)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    g.check()
+    out.update({"ms_per_macro_step": 1e3 * secs / macro_steps, "sim_time_per_s": sim / secs,
+                "cell_updates_per_s": cells / secs, "leaves_final": g.stats()[1]})
+    free(g)
+    g = Solver(pbs, dtype=dtype, batched=0).init()
+    for _ in range(warmup * (1 << lmax)):
+        g.step()
+    g.check()
+    torch.cuda.synchronize()
+    sim_g, steps = 0.0, 0
+    t0 = time.perf_counter()
+    while sim_g < sim:
+        g.step()
+        sim_g += float(g.dt.cpu()[0])
+        steps += 1
+    torch.cuda.synchronize()
+    secs_g = time.perf_counter() - t0
+    g.check()
+    free(g)
+    out.update({"global_steps": steps, "global_ms_per_step": 1e3 * secs_g / steps,
+                "global_sim_time_per_s": sim_g / secs_g,
+                "time_to_solution_speedup": (sim / secs) / (sim_g / secs_g)})
+    return out
+
+
 def free(g):
     import torch
     g.close()
@@ -234,12 +281,22 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the config-2 extra keys")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device copy of 512 MiB (calibrates HBM byte counters)")
+    ap.add_argument("--lts", action="store_true",
+                    help="only run local time stepping against global steps (plain kernels)")
+    ap.add_argument("--lts-macro-steps", type=int, default=2)
     ap.add_argument("--proposer-gain", action="store_true",
                     help="only run the learned-proposer gain test (6-level shock-blobs workload)")
     args = ap.parse_args()
     if args.proposer_gain:
         from paper_2012_04385_amd.proposer import gain_test
         print(json.dumps(gain_test(log=log)), flush=True)
+        return
+    if args.lts:
+        for dtype in ("f32", "f64"):
+            r = lts_leg(problems(args.workload, 10 ** 6), dtype, 1, args.lts_macro_steps)
+            log(f"[bench] LTS {dtype}: {r['ms_per_macro_step']:.1f} ms per macro step, "
+                f"time-to-solution speed-up {r['time_to_solution_speedup']:.2f}")
+            print(json.dumps(dict(r, workload=args.workload)), flush=True)
         return
     if args.copy_calibration:
         import torch

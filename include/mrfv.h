@@ -212,6 +212,28 @@ int mrfv_step(mrfv_ctx *ctx, void *U, void *U0, void *L, double *dt_dev);
 int mrfv_run(mrfv_ctx *ctx, void *U, void *U0, void *L, double *dt_dev, int32_t n_steps,
              int64_t *leaf_cells_host);
 
+/* step_lts -- one macro step of local time stepping (eq:LtsTimestep; algo:ComputeLoop with
+ * algo:Integration): dt = the eq:Cfl step of level lmax (written to dt_dev, one double per
+ * instance), 2^lmax micro steps of dt, level l advancing with dt_l = 2^(lmax - l) dt; the
+ * clock advances 2^lmax dt.  Level l completes a step of its own at micro step r when
+ * r + 1 is a multiple of 2^(lmax - l) (the active set of algo:ComputeLoop); its first RK
+ * stage is evaluated at the micro step its step starts in, all its stages are integrated
+ * at the micro step it ends in.  Halo cells of faces without a same-level neighbour are
+ * predicted from the state at the macro step's start and then integrated with the flux
+ * divergence, which is averaged into parents and predicted into those halos like the
+ * state (eq:Averaging, eq:Prediction).  Conservative: leaves sum their boundary face
+ * fluxes with the RK weights, and a coarse leaf next to a refined same-level neighbour
+ * replaces its own sum by the fine average at the end of its step (coarse cell
+ * adjustment).  Adaptive instances run mr_flag, commit_flags and mr_predict once, after
+ * the last micro step.  Runs on the plain per-block kernels in the context's dtype (any
+ * batched mode).  U0, L: dev scratch of mrfv_interior_bytes, as for mrfv_step; the
+ * library allocates its padded flux-divergence field, the jump-halo stage state and the
+ * face-flux sums on first use (MRFV_ENOMEM if it cannot).  cell_updates_host (may be
+ * NULL): leaf cells times their own steps in this macro step.  Every instance must have
+ * the same lmax (else MRFV_EINVAL). */
+int mrfv_step_lts(mrfv_ctx *ctx, void *U, void *U0, void *L, double *dt_dev,
+                  int64_t *cell_updates_host);
+
 /* check -- reads and clears the device error word: MRFV_ENONPHYS if a stage produced a
  * non-physical state since the last check, else MRFV_OK.  Synchronises the stream. */
 int mrfv_check(mrfv_ctx *ctx);
@@ -335,7 +357,9 @@ int mrfv_mlp_adam_step(mrfv_mlp *mlp, float lr, float beta1, float beta2, float 
 int mrfv_features(mrfv_ctx *ctx, const void *U, float *X_dev, int32_t *slots_host, int32_t *n);
 
 /* set_proposer -- mode 0: off (the default); 1: the network mlp (borrowed, must outlive
- * its use) proposes each step's flags; 2: persistence, i.e. the proposal is "no change".
+ * its use) proposes a step's flags when the step before changed the tree (and on the
+ * first step after this call), otherwise the proposal is "no change"; 2: persistence,
+ * i.e. the proposal is always "no change".
  * With a proposal, mrfv_step commits it on the host tree, builds and uploads its tables to
  * a second device copy while the device integrates, undoes the commit, and adopts the copy
  * when the judged flags equal the proposal; otherwise it commits the judged flags as
@@ -347,10 +371,10 @@ int mrfv_set_proposer(mrfv_ctx *ctx, mrfv_mlp *mlp, int32_t mode);
  * labels of the proposer.  Zero before the first adaptive step.  Synchronises the stream. */
 int mrfv_last_flags(mrfv_ctx *ctx, int8_t *flags_host);
 
-/* proposer_stats -- out_host int64[13] = (steps, hits, then for refine, keep, coarsen:
+/* proposer_stats -- out_host int64[14] = (steps, hits, then for refine, keep, coarsen:
  * true positives, false positives, false negatives, then steps whose proposal changed the
- * tree and was staged, staged proposals adopted); build_ms_host (may be NULL): host
- * milliseconds spent decoding and staging proposals. */
+ * tree and was staged, staged proposals adopted, steps on which the network ran);
+ * build_ms_host (may be NULL): host milliseconds spent decoding and staging proposals. */
 int mrfv_proposer_stats(mrfv_ctx *ctx, int64_t *out_host, double *build_ms_host);
 
 #ifdef __cplusplus

@@ -12,7 +12,9 @@
 //     (eq:Averaging) before every stage;
 //   * after each step: details (eq:DetailFunction as u_l - P(u_{l-1})), level-wise
 //     thresholds (eq:Thresholding, eq:LevelWiseEpsilon with D = 3), refine/coarsen;
-//   * bottom-up initialisation of algo:Init (including level l_max).
+//   * bottom-up initialisation of algo:Init (including level l_max);
+//   * local time stepping (eq:LtsTimestep, algo:ComputeLoop, algo:Integration) as a
+//     second step function, described where it is defined.
 #include "orc.h"
 
 #include <algorithm>

@@ -351,10 +351,11 @@ int commit(mrfv_ctx *ctx, const int8_t *flags, std::vector<int32_t> &fresh) {
 // Turn per-leaf class scores into a committable proposal: refine only below l_max,
 // coarsen only whole sibling groups of leaves on levels >= 2, nothing for non-adaptive
 // instances.  mode 2 (persistence) proposes no change at all.
-void decode_proposal(mrfv_ctx *ctx, const std::vector<int32_t> &leaves) {
+// net: the network's logits for this step are in h_logits (else the proposal is no change)
+void decode_proposal(mrfv_ctx *ctx, const std::vector<int32_t> &leaves, bool net) {
     std::vector<int8_t> &P = ctx->proposal;
     P.assign(ctx->cfg.slot_capacity, 0);
-    if (ctx->prop_mode != 1) return;
+    if (ctx->prop_mode != 1 || !net) return;
     const Topology &tp = ctx->topo;
     for (size_t r = 0; r < leaves.size(); ++r) {
         const float *z = ctx->h_logits + 3 * r;
@@ -771,7 +772,12 @@ int do_step(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt) {
         leaves.assign(L.data.begin() + L.all_leaves_off,
                       L.data.begin() + L.all_leaves_off + L.all_leaves_cnt);
     }
-    if (prop && ctx->prop_mode == 1 && !leaves.empty()) {
+    // the network runs only after a step that changed the tree (and on the first step): after
+    // a step without change the proposal is "no change", which is right whenever the tree
+    // stays as it is, at no cost
+    const bool net = prop && ctx->prop_mode == 1 && !leaves.empty() && ctx->p_net_due;
+    if (net) {
+        ctx->p_net_runs++;
         // proposal for this step's judge from the state at its start; it is queued
         // ahead of the stages, so the host can read it while the device continues
         HIP_OK(launch_features<T>(U, wlist(ctx, DESC_LEAVES), ctx->tb, ctx->d_inst, ctx->d_X,
@@ -788,9 +794,9 @@ int do_step(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt) {
     if (!adapt) return MRFV_OK;
     if (prop) {
         // host-side tree work for the proposed flags, overlapped with the device
-        if (ctx->prop_mode == 1 && !leaves.empty()) HIP_OK(hipEventSynchronize(ctx->ev_prop));
+        if (net) HIP_OK(hipEventSynchronize(ctx->ev_prop));
         const auto t0 = std::chrono::steady_clock::now();
-        decode_proposal(ctx, leaves);
+        decode_proposal(ctx, leaves, net);
         CALL(stage_proposal(ctx));
         ctx->p_build_ms +=
             std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -800,7 +806,9 @@ int do_step(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt) {
     ctx->h_wait_ms +=
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - w0).count();
     bool changed = false;
-    return finish_step<T>(ctx, U, half, prop, leaves, &changed);
+    CALL(finish_step<T>(ctx, U, half, prop, leaves, &changed));
+    ctx->p_net_due = changed;
+    return MRFV_OK;
 }
 
 // n steps.  On the graph path of an adaptive context without a proposer, step k+1 is
@@ -877,6 +885,106 @@ int do_run(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt, int n, int64_t *cells)
     hipEventDestroy(ev[0]);
     hipEventDestroy(ev[1]);
     return rc;
+}
+
+// ---------------------------------------------------------- local time stepping ----
+// eq:LtsTimestep, algo:ComputeLoop, algo:Integration on the plain kernels.  A macro step
+// is 2^lmax micro steps r of dt (the eq:Cfl step of level lmax); level l completes a step
+// of its own dt_l = 2^(lmax - l) dt at micro step r when r + 1 is a multiple of
+// 2^(lmax - l).  A level's first stage is evaluated at the micro step its step starts in;
+// its stages are integrated at the micro step it ends in.  Halo cells of faces without a
+// same-level neighbour hold their own state, set by prediction when every level is at
+// the same time (the macro step's start) and integrated in between with the flux
+// divergence predicted from the coarser level.  Every leaf sums its boundary face fluxes
+// with the RK weights; at the end of its step a coarse leaf next to a refined same-level
+// neighbour replaces its own sum by the fine average (the coarse cell adjustment).
+
+int lts_lowest_ending(int lmax, int r) { return lmax + 1 - __builtin_popcount((unsigned)((r + 1) ^ r)); }
+
+template <typename T>
+int lts_buffers(mrfv_ctx *ctx) {
+    if (ctx->d_Fp && ctx->d_D) return MRFV_OK;
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    const size_t cap = ctx->cfg.slot_capacity, es = sizeof(T);
+    struct Want { void **p; size_t bytes; } want[] = {
+        {&ctx->d_D, cap * 3 * 5 * CELLS_I * es},
+        {&ctx->d_Fp, cap * 5 * CELLS_P * es},
+        {&ctx->d_H0, cap * 6 * 5 * (size_t)lts_halo_slab() * es},
+        {&ctx->d_ACC, cap * 6 * 5 * FACE * es}};
+    for (auto &w : want) {
+        if (*w.p) continue;
+        if (hipMalloc(w.p, w.bytes) != hipSuccess) {
+            *w.p = nullptr;
+            return fail(ctx, MRFV_ENOMEM, "hipMalloc of the local time stepping buffers failed");
+        }
+    }
+    // halo regions of F that no kernel writes are never read; cleared once for tidiness
+    HIP_OK(hipMemsetAsync(ctx->d_Fp, 0, cap * 5 * CELLS_P * es, ctx->stream));
+    return MRFV_OK;
+}
+
+template <typename T>
+int do_lts_macro(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt, int64_t *cell_updates) {
+    CALL(lts_buffers<T>(ctx));
+    const HostLists &L = ctx->lists;
+    const int lmax = ctx->inst[0].lmax, top = levels_to_cover(ctx);
+    T *D = (T *)ctx->d_D, *FF = (T *)ctx->d_FF, *F = (T *)ctx->d_Fp, *H0 = (T *)ctx->d_H0,
+      *ACC = (T *)ctx->d_ACC;
+    const size_t cap = ctx->cfg.slot_capacity;
+    int64_t cells = 0;
+    for (int l = 0; l <= top; ++l) cells += (int64_t)L.leaf_cnt[l] * ((int64_t)1 << l) * CELLS_I;
+    if (cell_updates) *cell_updates = cells;
+    HIP_OK(launch_cfl<T>(U, wlist(ctx, DESC_LEAVES), ctx->tb, ctx->d_inst, (int)ctx->inst.size(),
+                         ctx->d_blockred, dt, ctx->stream));
+    // every level at the same time: parents and all face halos from the state
+    CALL(do_project<T>(ctx, U));
+    CALL(do_fill<T>(ctx, U, 1 << 20, FILL_FACES));
+    HIP_OK(hipMemsetAsync(ACC, 0, cap * 6 * 5 * FACE * sizeof(T), ctx->stream));
+    for (int r = 0; r < (1 << lmax); ++r) {
+        const int lo_end = lts_lowest_ending(lmax, r);
+        const int lo_start = r == 0 ? 0 : lts_lowest_ending(lmax, r - 1);
+        for (int st = 0; st < 3; ++st) {
+            const int lo_rhs = st == 0 ? lo_start : lo_end;
+            // flux divergence of the leaves being evaluated, after their copied halos
+            for (int l = lo_rhs; l <= top; ++l) {
+                const WorkList w = wlist(ctx, desc_leaf(l));
+                HIP_OK(launch_fill_halos<T>(U, w, ctx->tb, (FillMode)(FILL_FACES | FILL_PRESENT), ctx->stream));
+                HIP_OK(launch_flux<T>(ctx->cfg.scheme, U, w, ctx->tb, ctx->d_inst, D, FF, ctx->stream));
+                HIP_OK(launch_combine<T>(D, Lb, w, ctx->tb, ctx->d_inst, U, ctx->stream));
+                HIP_OK(launch_lts_scatter<T>(Lb, F, w, ctx->stream));
+            }
+            // averaged into the parents, predicted into the jump halos
+            for (int p = top - 1; p >= std::max(lo_rhs, 1) - 1; --p)
+                HIP_OK(launch_project<T>(F, wlist(ctx, desc_par(p)), ctx->tb, ctx->stream));
+            CALL(do_fill<T>(ctx, F, 1 << 20, FILL_MISSING_FACES, true));
+            // algo:Integration of the levels that end a step at r
+            for (int l = lo_end; l <= top; ++l)
+                HIP_OK(launch_lts_update<T>(st, dt, U, U0, H0, F, FF, ACC, wlist(ctx, desc_leaf(l)), ctx->tb,
+                                            ctx->d_inst, ctx->d_err, ctx->stream));
+            if (st == 2 && ctx->has_jumps) {
+                for (int p = top - 1; p >= lo_end; --p)
+                    HIP_OK(launch_ff_restrict<T>(ACC, wlist(ctx, desc_par(p)), ctx->tb, ctx->stream));
+                for (int l = lo_end; l <= top; ++l)
+                    HIP_OK(launch_lts_adjust<T>(U, ACC, wlist(ctx, desc_leaf(l)), ctx->tb, ctx->d_inst,
+                                                ctx->stream));
+            }
+            if (st == 2)
+                HIP_OK(launch_lts_zero<T>(ACC, wlist(ctx, DESC_LEAVES), ctx->tb, lo_end, ctx->stream));
+            for (int p = top - 1; p >= std::max(lo_end, 1) - 1; --p)
+                HIP_OK(launch_project<T>(U, wlist(ctx, desc_par(p)), ctx->tb, ctx->stream));
+        }
+    }
+    return MRFV_OK;
+}
+
+template <typename T>
+int do_step_lts(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt, int64_t *cell_updates) {
+    CALL(do_lts_macro<T>(ctx, U, U0, Lb, dt, cell_updates));
+    if (!adaptive(ctx)) return MRFV_OK;
+    CALL(do_adapt_device<T>(ctx, U, false));
+    HIP_OK(hipStreamSynchronize(ctx->stream));
+    bool changed = false;
+    return finish_step<T>(ctx, U, 0, false, {}, &changed);
 }
 
 int need_init(mrfv_ctx *ctx) {
@@ -999,7 +1107,8 @@ int mrfv_destroy(mrfv_ctx *ctx) {
         for (void *p : pp)
             if (p) hipFree(p);
     }
-    void *ptrs[] = {ctx->d_inst, ctx->d_err, ctx->d_D, ctx->d_W, ctx->d_W2, ctx->d_FF, ctx->d_blockred, ctx->d_det, ctx->d_det4,
+    void *ptrs[] = {ctx->d_inst, ctx->d_err, ctx->d_D, ctx->d_W, ctx->d_W2, ctx->d_FF, ctx->d_Fp, ctx->d_H0, ctx->d_ACC,
+                    ctx->d_blockred, ctx->d_det, ctx->d_det4,
                     ctx->d_recheck, ctx->d_flags, ctx->d_slots, ctx->d_slots2, ctx->d_prim, ctx->tb.meta, ctx->tb.child,
                     ctx->tb.nbr, ctx->tb.lists, ctx->d_desc, ctx->d_desc_g, ctx->d_gate};
     for (void *p : ptrs)
@@ -1156,6 +1265,18 @@ int mrfv_step(mrfv_ctx *ctx, void *U, void *U0, void *L, double *dt_dev) {
                : do_step<float>(ctx, (float *)U, (float *)U0, (float *)L, dt_dev);
 }
 
+int mrfv_step_lts(mrfv_ctx *ctx, void *U, void *U0, void *L, double *dt_dev,
+                  int64_t *cell_updates_host) {
+    CALL(need_init(ctx));
+    if (!U || !U0 || !L || !dt_dev) return fail(ctx, MRFV_EINVAL, "step_lts: null pointer");
+    for (const auto &p : ctx->inst)
+        if (p.lmax != ctx->inst[0].lmax)
+            return fail(ctx, MRFV_EINVAL, "step_lts: every instance needs the same lmax");
+    return ctx->cfg.dtype == MRFV_F64
+               ? do_step_lts<double>(ctx, (double *)U, (double *)U0, (double *)L, dt_dev, cell_updates_host)
+               : do_step_lts<float>(ctx, (float *)U, (float *)U0, (float *)L, dt_dev, cell_updates_host);
+}
+
 int mrfv_run(mrfv_ctx *ctx, void *U, void *U0, void *L, double *dt_dev, int32_t n_steps,
              int64_t *leaf_cells_host) {
     CALL(need_init(ctx));
@@ -1282,6 +1403,7 @@ int mrfv_set_proposer(mrfv_ctx *ctx, mrfv_mlp *mlp, int32_t mode) {
     }
     ctx->mlp = mlp;
     ctx->prop_mode = mode;
+    ctx->p_net_due = true;
     return MRFV_OK;
 }
 
@@ -1393,6 +1515,7 @@ int mrfv_proposer_stats(mrfv_ctx *ctx, int64_t *out, double *build_ms) {
     }
     out[11] = ctx->p_staged;
     out[12] = ctx->p_adopted;
+    out[13] = ctx->p_net_runs;
     if (build_ms) *build_ms = ctx->p_build_ms;
     return MRFV_OK;
 }

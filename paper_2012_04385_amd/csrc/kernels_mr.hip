@@ -162,6 +162,7 @@ __global__ __launch_bounds__(TPB) void k_fill_halos(T *__restrict__ U, WorkList 
         const bool own = g.r[0] == 0 && g.r[1] == 0 && g.r[2] == 0;
         const int src = own ? slot : nbr[(size_t)slot * 27 + (g.r[2] + 1) * 9 + (g.r[1] + 1) * 3 + (g.r[0] + 1)];
         if ((mode & FILL_MISSING) && src >= 0 && !clamped) continue;   // read in place
+        if ((mode & FILL_PRESENT) && src < 0) continue;                // keeps its values
         T *dst = U + (size_t)slot * 5 * CELLS_P;
         const int ncell = g.n[0] * g.n[1] * g.n[2];
         const Div dc(ncell), d0(g.n[0]), d1(g.n[1]);

@@ -199,8 +199,10 @@ constexpr int N_DESC = 5 + DESC_PER_LEVEL * MAX_LEVELS;
 // neighbour or on a zero-gradient boundary (the other regions are read in place from
 // the neighbour's interior by the fused stage and the details).
 // FILL_RHO_E limits any mode to the density and energy components (the details read
-// nothing else).
-enum FillMode { FILL_ALL = 0, FILL_FACES = 1, FILL_MISSING = 2, FILL_MISSING_FACES = 3, FILL_RHO_E = 4 };
+// nothing else).  FILL_PRESENT (with FILL_FACES) copies only: faces without a same-level
+// neighbour keep their values (the integrated jump halos of local time stepping).
+enum FillMode { FILL_ALL = 0, FILL_FACES = 1, FILL_MISSING = 2, FILL_MISSING_FACES = 3, FILL_RHO_E = 4,
+                FILL_PRESENT = 8 };
 
 // --------------------------------------------------------------- kernel launchers ----
 // All launchers enqueue on `st` and return hipGetLastError().
@@ -281,6 +283,22 @@ template <typename T>
 hipError_t launch_reflux_update(int stage, const double *dt, T *U, const T *FF,
                                 const WorkList &leaves, const DevTables &tb,
                                 const InstDev *inst, hipStream_t st);
+// Local time stepping (kernels_lts.hip).  F: padded flux divergence [cap][5][24^3];
+// H0: stage-start state of the halo cells of jump faces [cap][6][5][lts_halo_slab()];
+// ACC: time-integrated boundary face fluxes [cap][6][5][16][16] (the layout of FF).
+template <typename T>
+hipError_t launch_lts_scatter(const T *L, T *F, const WorkList &leaves, hipStream_t st);
+template <typename T>
+hipError_t launch_lts_update(int stage, const double *dt, T *U, T *U0, T *H0, const T *F,
+                             const T *FF, T *ACC, const WorkList &leaves, const DevTables &tb,
+                             const InstDev *inst, int32_t *err, hipStream_t st);
+template <typename T>
+hipError_t launch_lts_adjust(T *U, const T *ACC, const WorkList &leaves, const DevTables &tb,
+                             const InstDev *inst, hipStream_t st);
+template <typename T>
+hipError_t launch_lts_zero(T *ACC, const WorkList &leaves, const DevTables &tb, int lo_end,
+                           hipStream_t st);
+int lts_halo_slab();
 template <typename T>
 hipError_t launch_features(const T *U, const WorkList &wl, const DevTables &tb, const InstDev *inst,
                            float *X, hipStream_t st);
@@ -313,6 +331,7 @@ struct mrfv_ctx {
                                             // (fused FP32 stages: U -> W -> W2 -> U)
     void *d_D = nullptr;               // flux differences [cap][3][5][16^3]
     void *d_FF = nullptr;              // boundary face fluxes [cap][6][5][16][16]
+    void *d_Fp = nullptr, *d_H0 = nullptr, *d_ACC = nullptr;   // local time stepping, on first use
     double *d_blockred = nullptr;      // [cap][5] per-block partial reductions
     double *d_det = nullptr;           // [cap]
     double *d_det4 = nullptr;          // [cap][details_parts()] slab maxima of the details
@@ -350,6 +369,8 @@ struct mrfv_ctx {
     hipEvent_t ev_prop = nullptr;      // proposal copied to the host
     int64_t p_steps = 0, p_hits = 0, p_tp[3] = {0, 0, 0}, p_fp[3] = {0, 0, 0}, p_fn[3] = {0, 0, 0};
     int64_t p_staged = 0, p_adopted = 0;
+    bool p_net_due = true;             // the network runs on the next step (the last one changed the tree)
+    int64_t p_net_runs = 0;            // steps on which the network ran
     double p_build_ms = 0.0;
     // host time of the adaptation phase of mrfv_step: waiting for the judged flags, tree
     // commit + table build + upload (or adoption of staged tables), prediction; steps

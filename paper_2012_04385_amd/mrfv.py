@@ -78,6 +78,7 @@ def lib():
         "mrfv_commit_flags": ([vp, C.POINTER(C.c_int8), C.POINTER(i32), C.POINTER(i32)], C.c_int),
         "mrfv_step": ([vp, vp, vp, vp, vp], C.c_int),
         "mrfv_run": ([vp, vp, vp, vp, vp, i32, C.POINTER(i64)], C.c_int),
+        "mrfv_step_lts": ([vp, vp, vp, vp, vp, C.POINTER(i64)], C.c_int),
         "mrfv_check": ([vp], C.c_int),
         "mrfv_get_blocks": ([vp, C.POINTER(i64), C.POINTER(i32)], C.c_int),
         "mrfv_stats": ([vp, C.POINTER(i64)], C.c_int),
@@ -126,7 +127,8 @@ def exported_symbols():
             "mrfv_mlp_get_params", "mrfv_mlp_forward", "mrfv_mlp_loss_grad",
             "mrfv_mlp_adam_step", "mrfv_features", "mrfv_set_proposer", "mrfv_proposer_stats",
             "mrfv_last_flags", "mrfv_step_timing", "mrfv_rhs_variant", "mrfv_autotune",
-            "mrfv_fused_stage", "mrfv_run", "mrfv_set_detail_band", "mrfv_totals_noalloc"]
+            "mrfv_fused_stage", "mrfv_run", "mrfv_set_detail_band", "mrfv_totals_noalloc",
+            "mrfv_step_lts"]
 
 
 def morton_encode(shadow, level, bx, by, bz) -> int:
@@ -298,6 +300,15 @@ class Solver:
         cells = C.c_int64(0)
         self._chk(lib().mrfv_run(self.h, self._p(self.U), self._p(self.U0), self._p(self.L),
                                  self._p(self.dt), int(n), C.byref(cells)))
+        return int(cells.value)
+
+    def step_lts(self) -> int:
+        """One macro step of local time stepping (mrfv_step_lts): 2^lmax micro steps of
+        dt (left in self.dt), level l advancing with 2^(lmax-l) dt.  Returns the cell
+        updates of the macro step (leaf cells times their own steps)."""
+        cells = C.c_int64(0)
+        self._chk(lib().mrfv_step_lts(self.h, self._p(self.U), self._p(self.U0), self._p(self.L),
+                                      self._p(self.dt), C.byref(cells)))
         return int(cells.value)
 
     def check(self):
@@ -526,25 +537,30 @@ def last_flags(solver: "Solver") -> np.ndarray:
     return f
 
 
-def collect_training_data(solver: "Solver", steps: int):
+def collect_training_data(solver: "Solver", steps: int, with_steps: bool = False):
     """Run steps and record, for every step, the features of the leaves at its start and
-    the judge's class for each of them at its end: (device X [n, 192], int32 labels)."""
+    the judge's class for each of them at its end: (device X [n, 192], int32 labels), and
+    with_steps the step index of every row."""
     torch = solver.torch
-    Xs, ys = [], []
-    for _ in range(steps):
+    Xs, ys, ks = [], [], []
+    for k in range(steps):
         X, slots = solver_features(solver)
         X = X.clone()
         solver.step()
         ys.append(flags_to_classes(last_flags(solver)[slots]))
         Xs.append(X)
+        ks.append(np.full(len(slots), k, dtype=np.int64))
+    if with_steps:
+        return torch.cat(Xs), np.concatenate(ys), np.concatenate(ks)
     return torch.cat(Xs), np.concatenate(ys)
 
 
 def proposer_stats(solver: "Solver") -> dict:
-    out = (C.c_int64 * 13)()
+    out = (C.c_int64 * 14)()
     ms = C.c_double(0.0)
     solver._chk(lib().mrfv_proposer_stats(solver.h, out, C.byref(ms)))
     v = list(out)
     per = {name: dict(tp=v[2 + 3 * c], fp=v[3 + 3 * c], fn=v[4 + 3 * c])
            for c, name in enumerate(("refine", "keep", "coarsen"))}
-    return dict(steps=v[0], hits=v[1], staged=v[11], adopted=v[12], build_ms=ms.value, **per)
+    return dict(steps=v[0], hits=v[1], staged=v[11], adopted=v[12], net_runs=v[13], build_ms=ms.value,
+                **per)
