@@ -40,17 +40,29 @@ def training_sources(blast_steps: int = 50, kh_steps: int = 20, blob_steps: int 
 
 
 def collect(sources):
-    """Features and judged classes of every leaf of every step of the sources."""
+    """Features and judged classes of every leaf of every step of the sources, and a step
+    id per row (unique over the sources; the first step of each source has the lowest id
+    of that source)."""
     import torch
-    Xs, ys, info = [], [], {}
+    Xs, ys, ks, info = [], [], [], {}
+    base = 0
     for name, pb, steps in sources:
         g = Solver([pb], dtype="f32", batched=2).init()
-        X, y = collect_training_data(g, steps)
+        X, y, k = collect_training_data(g, steps, with_steps=True)
         Xs.append(X)
         ys.append(y)
+        ks.append(k + base)
+        base += steps
         info[name] = np.bincount(y, minlength=3).tolist()
         del g
-    return torch.cat(Xs), np.concatenate(ys), info
+    return torch.cat(Xs), np.concatenate(ys), np.concatenate(ks), info
+
+
+def gated_steps(y, k, first_ids):
+    """Step ids on which the solver runs the network: the first step of a run and every step
+    that follows a step whose judge changed the tree."""
+    changed = set(np.unique(k[y != 1]).tolist())
+    return sorted(set(first_ids) | {s + 1 for s in changed if s + 1 in set(k.tolist()) and s + 1 not in first_ids})
 
 
 def train(X, y, epochs: int = 30, lr: float = 3e-3, batch: int = 4096, seed: int = 0,
@@ -68,20 +80,36 @@ def train(X, y, epochs: int = 30, lr: float = 3e-3, batch: int = 4096, seed: int
     return mlp, float(l0), float(l1)
 
 
-def calibrate_keep_bias(mlp, X, y):
-    """Raise the keep logit's bias until the network proposes no more refines and
-    coarsens on the training data than the judge made (class weighting biases the
-    argmax towards the rare classes; a wrong change proposal wastes a staged tree).
-    Returns the bias shift."""
+def step_hits(z, y, k, steps, shift):
+    """Steps (of `steps`) on which the argmax proposal with the keep logit raised by
+    `shift` equals the judge's classes on every leaf."""
+    zz = z.copy()
+    zz[:, 1] += shift
+    wrong = zz.argmax(axis=1) != y
+    bad = set(np.unique(k[wrong]).tolist())
+    return sum(1 for s in steps if s not in bad)
+
+
+def calibrate_keep_bias(mlp, X, y, k, steps):
+    """Raise the keep logit's bias to the value at which the network's proposal is exact
+    on the most of the given training steps (those the solver runs it on): class
+    weighting biases the argmax towards the rare classes, and one wrong leaf makes a whole
+    step's staged tree useless.  Among equally good values the largest (fewest change
+    proposals) is taken.  Returns the bias shift."""
     import torch
-    z = torch.cat([mlp.forward(X[a:a + 32768]) for a in range(0, X.shape[0], 32768)]).cpu().numpy()
-    n_change = int((y != 1).sum())
-    # margin of the best non-keep class over keep, per sample
-    m = np.maximum(z[:, 0], z[:, 2]) - z[:, 1]
-    shift = 0.0
-    if (m > 0).sum() > n_change:
-        shift = float(np.sort(m)[::-1][n_change]) if n_change < len(m) else float(m.max())
-        shift = max(shift, 0.0) + 1e-3
+    b = min(32768, mlp.max_rows)
+    z = torch.cat([mlp.forward(X[a:a + b]) for a in range(0, X.shape[0], b)]).cpu().numpy()
+    sel = np.isin(k, steps)
+    m = np.maximum(z[sel, 0], z[sel, 2]) - z[sel, 1]   # margin of a change over keep
+    cand = np.unique(np.concatenate([[0.0], np.maximum(m, 0.0) + 1e-3]))
+    if len(cand) > 512:   # a coarse grid of the margins' quantiles is enough
+        cand = np.unique(np.quantile(cand, np.linspace(0.0, 1.0, 512)))
+        cand = np.append(cand, m.max() + 1e-3 if len(m) else 0.0)
+    best, shift = -1, 0.0
+    for c in cand:
+        h = step_hits(z, y, k, steps, float(c))
+        if h >= best:
+            best, shift = h, float(c)
     p = mlp.get_params()
     p[-3 + 1] += shift
     mlp.set_params(p)
@@ -129,7 +157,8 @@ def run_mode(pb, steps: int, mode: int, mlp=None, variant=None):
             tp, fp, fn = st[c]["tp"], st[c]["fp"], st[c]["fn"]
             prf[c] = {"precision": tp / (tp + fp) if tp + fp else None,
                       "recall": tp / (tp + fn) if tp + fn else None, "support": tp + fn}
-        out["proposer"] = {"steps": st["steps"], "hits": st["hits"], "staged": st["staged"],
+        out["proposer"] = {"steps": st["steps"], "hits": st["hits"], "network_runs": st["net_runs"],
+                           "staged": st["staged"],
                            "adopted": st["adopted"], "wasted_staged": st["staged"] - st["adopted"],
                            "build_ms_per_step": st["build_ms"] / max(st["steps"], 1), "classes": prf}
     out["digest"] = leaf_digest(g)
@@ -149,12 +178,16 @@ def tuned_variant(pb, warm: int = 3) -> int:
 def gain_test(steps: int = 100, epochs: int = 30, variant=None, log=print):
     import torch
     t0 = time.perf_counter()
-    X, y, info = collect(training_sources())
-    log(f"[proposer] {X.shape[0]} labelled leaves, classes (refine, keep, coarsen) by source: {info}")
+    src = training_sources()
+    X, y, k, info = collect(src)
+    firsts = list(np.cumsum([0] + [s for _, _, s in src[:-1]]))
+    gsteps = gated_steps(y, k, firsts)
+    log(f"[proposer] {X.shape[0]} labelled leaves, classes (refine, keep, coarsen) by source: {info}; "
+        f"{len(gsteps)} steps follow a tree change or start a run")
     mlp, l0, l1 = train(X, y, epochs=epochs)
     log(f"[proposer] trained {epochs} epochs: loss {l0:.4f} -> {l1:.4f} "
         f"({time.perf_counter() - t0:.1f} s with data collection)")
-    shift = calibrate_keep_bias(mlp, X, y)
+    shift = calibrate_keep_bias(mlp, X, y, k, gsteps)
     pred = np.concatenate([mlp.forward(X[a:a + 32768]).argmax(dim=1).cpu().numpy()
                            for a in range(0, X.shape[0], 32768)])
     train_acc = float((pred == y).mean())
@@ -178,8 +211,11 @@ def gain_test(steps: int = 100, epochs: int = 30, variant=None, log=print):
     same = len({r["digest"] for r in res.values()}) == 1
     gain = (res["network"]["ms_per_step"] < res["off"]["ms_per_step"] and
             res["network"]["ms_per_step"] < res["persistence"]["ms_per_step"])
+    no_loss = (res["network"]["proposer"]["hits"] >= res["persistence"]["proposer"]["hits"])
     return {"workload": pb.name, "steps": steps, "variant": variant,
             "training": {"sources": info, "loss_before": l0,
             "loss_after": l1, "train_accuracy": train_acc, "epochs": epochs,
-            "keep_bias_shift": shift, "train_change_classes": tr_prec},
-            "runs": res, "bitwise_identical": same, "network_gain": gain}
+            "keep_bias_shift": shift, "train_change_classes": tr_prec,
+            "calibration_steps": len(gsteps)},
+            "runs": res, "bitwise_identical": same, "network_gain": gain,
+            "network_hits_at_least_persistence": no_loss}

@@ -160,6 +160,10 @@ def test_proposer_modes_bitwise_identical(torch_mod):
         assert st["steps"] == steps
         print(f"mode {mode}: {st}")
         assert 0 <= st["hits"] <= steps
+        if mode == 1:
+            # the network runs on the first step and after every step that changed the tree
+            changes = sum(1 for a, b in zip(t0[:-1], t0[1:]) if a != b)
+            assert 1 <= st["net_runs"] <= 2 + changes
 
 
 def test_proposer_trained_hits(torch_mod):
@@ -169,8 +173,8 @@ def test_proposer_trained_hits(torch_mod):
     torch = torch_mod
     pb = W.blast_mr3(steps=10)
     g = Solver([pb], dtype="f32", batched=2).init()
-    X, y = collect_training_data(g, 10)
-    assert X.shape[0] == len(y) > 100
+    X, y, ks = collect_training_data(g, 10, with_steps=True)
+    assert X.shape[0] == len(y) == len(ks) > 100
     m = MLP(max_rows=4096)
     m.init_params(seed=6)
     cnt = np.bincount(y, minlength=3).astype(np.float64)
@@ -187,3 +191,16 @@ def test_proposer_trained_hits(torch_mod):
     for k in s:
         assert np.array_equal(s[k], ref[k]), k
     print(f"trained proposer on its training run: {st}")
+    # calibrated on its training steps, then run on a held-out seed: the solution is the
+    # judge's, and where the tree does not change only the steps the network runs on (the
+    # first, and those after a change) can miss
+    from paper_2012_04385_amd.proposer import calibrate_keep_bias
+    calibrate_keep_bias(m, X, y, ks, list(range(10)))
+    pb2 = W.blast_mr3(seed_k=9, steps=10)
+    base2, tb, _ = _run(pb2, 0, 10)
+    g2, t2, st2 = _run(pb2, 1, 10, m)
+    assert t2 == tb
+    print(f"calibrated proposer on a held-out seed: {st2}")
+    changes = sum(1 for a, b in zip(tb[:-1], tb[1:]) if a != b)
+    if changes == 0:
+        assert st2["net_runs"] <= 2 and st2["hits"] >= 10 - st2["net_runs"], st2
