@@ -22,7 +22,8 @@ class _Params(C.Structure):
                 ("eps", C.c_double), ("scale_rho", C.c_double), ("scale_E", C.c_double),
                 ("dx0", C.c_double), ("lmax", C.c_int32), ("n0", C.c_int32 * 3),
                 ("bc", C.c_int32 * 3), ("adapt", C.c_int32), ("scheme", C.c_int32),
-                ("gravity", C.c_double * 3)]
+                ("gravity", C.c_double * 3), ("eos", C.c_int32), ("tait_A", C.c_double),
+                ("tait_rho0", C.c_double)]
 
 
 IC_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
@@ -121,6 +122,16 @@ def lib():
         L.orc_mlp_loss_grad.restype = d
         L.orc_features.argtypes = [pd, d, d, d, d, d, pd]
         L.orc_block_rhs.argtypes = [pd, d, d, d, pd]
+        L.orc_tait_pressure.argtypes = [d, d, d, d, d]
+        L.orc_tait_pressure.restype = d
+        L.orc_tait_sound_speed.argtypes = [d, d, d, d]
+        L.orc_tait_sound_speed.restype = d
+        L.orc_tait_flux_x.argtypes = [pd, d, d, d, d, pd]
+        L.orc_tait_roe_matrices.argtypes = [pd, pd, d, d, d, d, pd, pd]
+        L.orc_tait_face_flux.argtypes = [C.c_int, pd, d, d, d, d, pd]
+        L.orc_tait_face_flux.restype = C.c_int
+        L.orc_tait_exact_riemann.argtypes = [d, d, d, d, d, d, d, d, pd, C.c_int, pd]
+        L.orc_tait_exact_riemann.restype = C.c_int
         L.orc_block_rhs.restype = None
         L.orc_block_detail.argtypes = [pd, pd, C.c_int, C.c_int, C.c_int, d, d]
         L.orc_block_detail.restype = d
@@ -228,6 +239,49 @@ def exact_riemann(left, right, gamma, s) -> np.ndarray:
     return out
 
 
+EOS = {"stiffened": 0, "tait": 1}
+
+
+def tait_pressure(rho, gamma, B, A, rho0) -> float:
+    return lib().orc_tait_pressure(rho, gamma, B, A, rho0)
+
+
+def tait_sound_speed(rho, gamma, B, rho0) -> float:
+    return lib().orc_tait_sound_speed(rho, gamma, B, rho0)
+
+
+def tait_flux_x(U, gamma, B, A, rho0) -> np.ndarray:
+    u = np.ascontiguousarray(U, dtype=np.float64)
+    F = np.zeros(5)
+    lib().orc_tait_flux_x(_dp(u), gamma, B, A, rho0, _dp(F))
+    return F
+
+
+def tait_roe_matrices(UL, UR, gamma, B, A, rho0):
+    a, b = np.ascontiguousarray(UL, dtype=np.float64), np.ascontiguousarray(UR, dtype=np.float64)
+    R, L = np.zeros(16), np.zeros(16)
+    lib().orc_tait_roe_matrices(_dp(a), _dp(b), gamma, B, A, rho0, _dp(R), _dp(L))
+    return R.reshape(4, 4), L.reshape(4, 4)
+
+
+def tait_face_flux(d: int, st, gamma, B, A, rho0):
+    s = np.ascontiguousarray(st, dtype=np.float64).reshape(30)
+    F = np.zeros(5)
+    n = lib().orc_tait_face_flux(d, _dp(s), gamma, B, A, rho0, _dp(F))
+    return F, n
+
+
+def tait_exact_riemann(left, right, gamma, B, A, rho0, s) -> np.ndarray:
+    """(rho, u) of the exact barotropic Riemann solution at x/t = s; left/right = (rho, u)."""
+    s = np.ascontiguousarray(s, dtype=np.float64)
+    out = np.zeros((len(s), 2))
+    rc = lib().orc_tait_exact_riemann(left[0], left[1], right[0], right[1], gamma, B, A, rho0,
+                                      _dp(s), len(s), _dp(out))
+    if rc != 0:
+        raise ValueError("vacuum")
+    return out
+
+
 def lts_lowest_ending(lmax: int, r: int) -> int:
     """Lowest level that completes a step of its own at micro step r (algo:ComputeLoop)."""
     return lib().orc_lts_lowest_ending(lmax, r)
@@ -324,6 +378,9 @@ class Sim:
         p.scheme = SCHEMES[getattr(problem, "scheme", "roe_weno5")]
         for a, gv in enumerate(getattr(problem, "gravity", (0.0, 0.0, 0.0))):
             p.gravity[a] = gv
+        p.eos = EOS[getattr(problem, "eos", "stiffened")]
+        p.tait_A = getattr(problem, "tait_A", 1.0)
+        p.tait_rho0 = getattr(problem, "tait_rho0", 1.0)
         self._p = p
         self.h = lib().orc_sim_create(C.byref(p))
         self._cb = None

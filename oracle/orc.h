@@ -80,6 +80,25 @@ void orc_hllc_flux_x(const double UL[5], const double UR[5], double gamma, doubl
 int orc_face_flux_x_scheme(int scheme, const double st[30], double gamma, double B, double F[5]);
 int orc_face_flux_scheme(int scheme, int d, const double st[30], double gamma, double B, double F[5]);
 
+/* ---------------- Tait's equation of state (Sec. "Influence of Equation of State") ---- */
+
+/* p = B ((rho/rho0)^gamma - 1) + A and c = sqrt(dp/drho). */
+double orc_tait_pressure(double rho, double gamma, double B, double A, double rho0);
+double orc_tait_sound_speed(double rho, double gamma, double B, double rho0);
+/* Flux along x of the barotropic system (rho, rho v); the energy component is zero. */
+void orc_tait_flux_x(const double U[5], double gamma, double B, double A, double rho0, double F[5]);
+/* Roe matrices (4x4, row-major; fields u-c, u, u, u+c on rho, m1, m2, m3). */
+void orc_tait_roe_matrices(const double UL[5], const double UR[5], double gamma, double B, double A,
+                           double rho0, double R[16], double L[16]);
+/* Characteristic WENO5-JS Roe flux with per-field LLF fallback, x and axis d. */
+int orc_tait_face_flux_x(const double st[30], double gamma, double B, double A, double rho0,
+                         double F[5]);
+int orc_tait_face_flux(int d, const double st[30], double gamma, double B, double A, double rho0,
+                       double F[5]);
+/* Exact 1D Riemann solution (rho, u) at x/t = s[i] (out[2 i..]); -1 if vacuum forms. */
+int orc_tait_exact_riemann(double rl, double ul, double rr, double ur, double gamma, double B,
+                           double A, double rho0, const double *s, int n, double *out);
+
 /* ---------------- MR operators (eq:Averaging, eq:Prediction + appendix Q-terms) ------ */
 
 /* Fifth-order conservative prediction of one fine cell from a padded 24^3 parent array
@@ -116,6 +135,8 @@ typedef struct {
     int32_t adapt;         /* 1: refine/coarsen after each step                */
     int32_t scheme;        /* flux kernel, see orc_face_flux_scheme            */
     double gravity[3];     /* source term of eq:Euler: S = (0, rho g, rho v.g) */
+    int32_t eos;           /* 0 stiffened gas (eq:StiffenedGas), 1 Tait        */
+    double tait_A, tait_rho0;   /* Tait: p = B ((rho/rho0)^gamma - 1) + A       */
 } orc_params;
 
 typedef struct orc_sim orc_sim;

@@ -310,7 +310,9 @@ long block_rhs(const orc_sim *s, Block *b) {
                         c[o_hi] = H + m;
                         for (int q = 0; q < 5; ++q) st[5 * j + q] = b->u[at(q, c[2], c[1], c[0])];
                     }
-                    n_llf += orc_face_flux_scheme(s->p.scheme, d, st, g, B, Fh);
+                    n_llf += s->p.eos == 1
+                                 ? orc_tait_face_flux(d, st, g, B, s->p.tait_A, s->p.tait_rho0, Fh)
+                                 : orc_face_flux_scheme(s->p.scheme, d, st, g, B, Fh);
                     for (int q = 0; q < 5; ++q) F[fidx(d, q, m, r, f)] = Fh[q];
                 }
     b->rhs.assign(5 * ICELLS, 0.0);
@@ -335,7 +337,7 @@ long block_rhs(const orc_sim *s, Block *b) {
                         b->rhs[ati(1 + a, k, j, i)] += rho * gv[a];
                         work += b->u[at(1 + a, H + k, H + j, H + i)] * gv[a];
                     }
-                    b->rhs[ati(4, k, j, i)] += work;
+                    if (s->p.eos == 0) b->rhs[ati(4, k, j, i)] += work;   // Tait: energy not evolved
                 }
     // Boundary face planes for the jump correction, stored [q][m][r].
     for (int side = 0; side < 6; ++side) {
@@ -430,6 +432,10 @@ bool physical(const orc_sim *s, const Block *b) {
             for (int i = H; i < H + N; ++i) {
                 double U[5];
                 for (int q = 0; q < 5; ++q) U[q] = b->u[at(q, k, j, i)];
+                if (s->p.eos == 1) {   // Tait: any positive density
+                    if (!(U[0] > 0.0) || !std::isfinite(U[1] + U[2] + U[3])) return false;
+                    continue;
+                }
                 const double p = orc_pressure(U, s->p.gamma, s->p.B);
                 if (!(U[0] > 0.0) || !(p + s->p.B > 0.0) || !std::isfinite(U[4])) return false;
             }
@@ -745,8 +751,9 @@ void impose_ic(orc_sim *s, Block *b, orc_ic_fn ic, void *user) {
                 b->u[at(1, H + k, H + j, H + i)] = rho * u;
                 b->u[at(2, H + k, H + j, H + i)] = rho * v;
                 b->u[at(3, H + k, H + j, H + i)] = rho * w;
+                // Tait: the pressure follows from the density; the energy is not evolved
                 b->u[at(4, H + k, H + j, H + i)] =
-                    (p + g * B) / (g - 1.0) + 0.5 * rho * (u * u + v * v + w * w);
+                    s->p.eos == 1 ? 0.0 : (p + g * B) / (g - 1.0) + 0.5 * rho * (u * u + v * v + w * w);
             }
 }
 
@@ -812,8 +819,9 @@ double orc_sim_dt(const orc_sim *s) {
                 for (int i = H; i < H + N; ++i) {
                     double U[5];
                     for (int q = 0; q < 5; ++q) U[q] = b->u[at(q, k, j, i)];
-                    const double p = orc_pressure(U, s->p.gamma, s->p.B);
-                    const double c = std::sqrt(s->p.gamma * (p + s->p.B) / U[0]);
+                    const double c =
+                        s->p.eos == 1 ? orc_tait_sound_speed(U[0], s->p.gamma, s->p.B, s->p.tait_rho0)
+                                      : std::sqrt(s->p.gamma * (orc_pressure(U, s->p.gamma, s->p.B) + s->p.B) / U[0]);
                     for (int a = 0; a < 3; ++a)
                         mx[a] = std::max(mx[a], std::fabs(U[1 + a] / U[0]) + c);
                 }

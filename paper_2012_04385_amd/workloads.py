@@ -77,6 +77,11 @@ class Problem:
     scheme: str = "roe_weno5"
     # gravity vector of the source term of eq:Euler (zero: no source)
     gravity: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    # equation of state: "stiffened" (eq:StiffenedGas with gamma, B) or "tait"
+    # (p = B ((rho/rho0)^gamma - 1) + A; the energy is not evolved and the IC pressure unused)
+    eos: str = "stiffened"
+    tait_A: float = 1.0
+    tait_rho0: float = 1.0
 
     @property
     def adapt(self) -> int:
@@ -202,6 +207,18 @@ def sod_single_level(seed_k: int = 1) -> Problem:
     return Problem(name="sod_32c_1lvl", kind="sod", lmax=0, n0=(2, 2, 2), dx0=1.0 / 32,
                    bc=(1, 0, 0), steps=10, seed=BASE_SEED + seed_k, noise=1e-3,
                    scale_rho=1.0, scale_E=2.5, eps=1e-3,
+                   params={"axis": 0, "pos": 0.5, "left": (1.0, 1.0), "right": (0.125, 0.1)})
+
+
+def sod_tait_mr3(seed_k: int = 6, steps: int = 40, eos: str = "tait") -> Problem:
+    """Sec. "Influence of Equation of State": Sod tube along x with l_max = 3 (2 level-0
+    blocks in x, 256 cells effective), Tait's equation with gamma 1.4, A = 1, B = 0.937315,
+    rho0 = 1 (eos = "stiffened": the same tube with the ideal gas), densities 1 | 0.125 at
+    rest, pressures 1 | 0.1 for the ideal gas, zero-gradient in x, periodic in y and z."""
+    return Problem(name=f"sod_{eos}_256e_4lvl", kind="sod", lmax=3, n0=(2, 1, 1), dx0=1.0 / 32,
+                   bc=(1, 0, 0), steps=steps, seed=BASE_SEED + seed_k, noise=0.0,
+                   scale_rho=1.0, scale_E=2.5, eps=1e-3, cfl=0.5, B=0.937315 if eos == "tait" else 0.0,
+                   eos=eos, tait_A=1.0, tait_rho0=1.0,
                    params={"axis": 0, "pos": 0.5, "left": (1.0, 1.0), "right": (0.125, 0.1)})
 
 
