@@ -261,6 +261,26 @@ def lts_leg(pbs, dtype, warmup, macro_steps):
     return out
 
 
+def eos_leg(warmup, steps):
+    """The Sod tube of Sec. "Influence of Equation of State" (l_max 3) with Tait's equation
+    and with the stiffened gas, plain kernels, FP32 and FP64: cell-updates per second and
+    their ratio (Tait evolves four of the five components)."""
+    from paper_2012_04385_amd import workloads as W
+    out = {"workload": "sod tube, 256 cells effective along x, l_max 3", "path": "plain per-block kernels",
+           "steps": steps, "warmup": warmup}
+    for dtype in ("f32", "f64"):
+        for eos in ("stiffened", "tait"):
+            pbs = [W.sod_tait_mr3(eos=eos, steps=warmup + steps)]
+            g, cells, secs, _ = run_gpu(pbs, dtype, 0, warmup, steps)
+            out[f"{eos}_{dtype}"] = {"cell_updates_per_s": cells / secs, "ms_per_step": 1e3 * secs / steps,
+                                     "leaves_final": g.stats()[1]}
+            free(g)
+            log(f"[bench] {eos} {dtype}: {cells / secs:.4e} cell-updates/s")
+        out[f"tait_time_per_cell_update_vs_stiffened_{dtype}"] = (
+            out[f"stiffened_{dtype}"]["cell_updates_per_s"] / out[f"tait_{dtype}"]["cell_updates_per_s"])
+    return out
+
+
 def free(g):
     import torch
     g.close()
@@ -278,12 +298,16 @@ def main():
                     help="first steps also run by the oracle (parity and CPU baseline)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle (parity, CPU baseline)")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 plain path")
-    ap.add_argument("--no-extra", action="store_true", help="skip the config-2 extra keys")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the extra keys (config 2, local time stepping, Tait's equation)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device copy of 512 MiB (calibrates HBM byte counters)")
     ap.add_argument("--lts", action="store_true",
                     help="only run local time stepping against global steps (plain kernels)")
     ap.add_argument("--lts-macro-steps", type=int, default=2)
+    ap.add_argument("--eos-compare", action="store_true",
+                    help="only run the Sod tube with Tait's equation against the stiffened gas "
+                         "(plain kernels)")
     ap.add_argument("--proposer-gain", action="store_true",
                     help="only run the learned-proposer gain test (6-level shock-blobs workload)")
     args = ap.parse_args()
@@ -297,6 +321,9 @@ def main():
             log(f"[bench] LTS {dtype}: {r['ms_per_macro_step']:.1f} ms per macro step, "
                 f"time-to-solution speed-up {r['time_to_solution_speedup']:.2f}")
             print(json.dumps(dict(r, workload=args.workload)), flush=True)
+        return
+    if args.eos_compare:
+        print(json.dumps(eos_leg(args.warmup, args.steps)), flush=True)
         return
     if args.copy_calibration:
         import torch
@@ -370,6 +397,15 @@ def main():
             c2["speedup_vs_fp64_plain"] = c2["value"] / c2["fp64_plain_value"]
         extra["blast_128e_3lvl"] = c2
         log(f"[bench] config 2 (blast_128e_3lvl): {c2['value']:.4e} cell-updates/s")
+
+    if not args.no_extra:
+        try:
+            lt = lts_leg(pbs, "f32", 1, 2)
+            extra["local_time_stepping"] = lt
+            log(f"[bench] LTS f32: time-to-solution speed-up {lt['time_to_solution_speedup']:.2f}")
+        except Exception as e:   # reported, not fatal: the headline stands on its own
+            extra["local_time_stepping"] = {"error": str(e)}
+        extra["tait_vs_stiffened"] = eos_leg(5, 30)
 
     launches, total_ms, kcells = kt
     avg_s = total_ms / 1e3 / max(launches, 1)

@@ -49,6 +49,16 @@ typedef enum { MRFV_F32 = 0, MRFV_F64 = 1 } mrfv_dtype;
  * with WENO5-JS, and HLLC with WENO-AO(5,3) face states (characteristic-wise). */
 typedef enum { MRFV_ROE_WENO5 = 0, MRFV_ROE_TENO5 = 1, MRFV_LLF_WENO5 = 2,
                MRFV_HLLC_WAO53 = 3 } mrfv_scheme;
+
+/* Equation of state (Sec. "Governing Equations"; Sec. "Influence of Equation of State").
+ * MRFV_TAIT: p = B ((rho/rho0)^gamma - 1) + A depends on the density alone; the energy is
+ * a dependent variable, is not evolved and stays zero (the initial pressure is unused).
+ * The flux is the standard configuration's characteristic WENO5-JS Roe solver with
+ * per-field LLF fallback on the four fields (u-c, u, u, u+c), Roe c~^2 = (p_R - p_L) /
+ * (rho_R - rho_L).  Tait runs on the plain kernels: contexts with it must use scheme
+ * MRFV_ROE_WENO5, no gravity, no proposer, and not the fused FP32 path (batched with
+ * MRFV_F32); mrfv_create returns MRFV_EINVAL otherwise. */
+typedef enum { MRFV_STIFFENED_GAS = 0, MRFV_TAIT = 1 } mrfv_eos;
 typedef enum { MRFV_BC_PERIODIC = 0, MRFV_BC_ZEROGRAD = 1 } mrfv_bc;
 
 /* One independent MR problem (one forest of octrees on a box). */
@@ -66,6 +76,8 @@ typedef struct {
     int32_t adapt;        /* 1: refine/coarsen after each step                          */
     double gravity[3];    /* source term of eq:Euler: S(U) = (0, rho g, rho v . g); zero
                              vector: no source                                          */
+    int32_t eos;          /* mrfv_eos; the same for every instance of a context          */
+    double tait_A, tait_rho0;   /* Tait: p = B ((rho/rho0)^gamma - 1) + A (gamma, B above) */
 } mrfv_instance;
 
 typedef struct {

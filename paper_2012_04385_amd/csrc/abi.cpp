@@ -46,6 +46,14 @@ int check_instance(mrfv_ctx *ctx, const mrfv_instance &p, int i) {
     for (int a = 0; a < 3; ++a)
         if (!std::isfinite(p.gravity[a])) return fail(ctx, MRFV_EINVAL, w + "gravity must be finite");
     if (p.lmax < 0 || p.lmax > 12) return fail(ctx, MRFV_EINVAL, w + "lmax must be in [0,12]");
+    if (p.eos != MRFV_STIFFENED_GAS && p.eos != MRFV_TAIT)
+        return fail(ctx, MRFV_EINVAL, w + "eos must be 0 (stiffened gas) or 1 (Tait)");
+    if (p.eos == MRFV_TAIT) {
+        if (!(p.B > 0.0) || !(p.tait_rho0 > 0.0) || !std::isfinite(p.tait_A))
+            return fail(ctx, MRFV_EINVAL, w + "Tait needs B > 0, rho0 > 0 and a finite A");
+        if (p.gravity[0] != 0.0 || p.gravity[1] != 0.0 || p.gravity[2] != 0.0)
+            return fail(ctx, MRFV_EINVAL, w + "Tait has no energy equation for the gravity source");
+    }
     for (int a = 0; a < 3; ++a) {
         if (p.n0[a] < 1 || ((int64_t)p.n0[a] << p.lmax) > 65535)
             return fail(ctx, MRFV_EINVAL, w + "n0 out of range");
@@ -54,6 +62,9 @@ int check_instance(mrfv_ctx *ctx, const mrfv_instance &p, int i) {
     }
     return MRFV_OK;
 }
+
+// Flux kernel of the context's leaves: the configured scheme, or the Tait system's kernel.
+int flux_kernel(const mrfv_ctx *ctx) { return ctx->inst[0].eos == MRFV_TAIT ? 4 : ctx->cfg.scheme; }
 
 // A jump face exists when some leaf has a non-leaf same-level face neighbour.
 bool any_jump(const Topology &tp, const HostLists &L, const std::vector<int32_t> &nbr) {
@@ -224,10 +235,10 @@ int do_flux(mrfv_ctx *ctx, const T *U) {
     hipEvent_t ev{};
     timing_begin(ctx, &ev);
     if (ctx->cfg.batched) {
-        HIP_OK(launch_flux<T>(ctx->cfg.scheme, U, wlist(ctx, DESC_LEAVES), ctx->tb, ctx->d_inst, D, FF, ctx->stream));
+        HIP_OK(launch_flux<T>(flux_kernel(ctx), U, wlist(ctx, DESC_LEAVES), ctx->tb, ctx->d_inst, D, FF, ctx->stream));
     } else {
         for (int l = 0; l <= L.max_level; ++l)
-            HIP_OK(launch_flux<T>(ctx->cfg.scheme, U, wlist(ctx, desc_leaf(l)), ctx->tb, ctx->d_inst, D, FF,
+            HIP_OK(launch_flux<T>(flux_kernel(ctx), U, wlist(ctx, desc_leaf(l)), ctx->tb, ctx->d_inst, D, FF,
                                   ctx->stream));
     }
     timing_end(ctx, ev, (int64_t)L.all_leaves_cnt * CELLS_I);
@@ -949,7 +960,7 @@ int do_lts_macro(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt, int64_t *cell_up
             for (int l = lo_rhs; l <= top; ++l) {
                 const WorkList w = wlist(ctx, desc_leaf(l));
                 HIP_OK(launch_fill_halos<T>(U, w, ctx->tb, (FillMode)(FILL_FACES | FILL_PRESENT), ctx->stream));
-                HIP_OK(launch_flux<T>(ctx->cfg.scheme, U, w, ctx->tb, ctx->d_inst, D, FF, ctx->stream));
+                HIP_OK(launch_flux<T>(flux_kernel(ctx), U, w, ctx->tb, ctx->d_inst, D, FF, ctx->stream));
                 HIP_OK(launch_combine<T>(D, Lb, w, ctx->tb, ctx->d_inst, U, ctx->stream));
                 HIP_OK(launch_lts_scatter<T>(Lb, F, w, ctx->stream));
             }
@@ -1013,7 +1024,16 @@ int mrfv_create(mrfv_ctx **out, const mrfv_config *cfg, const mrfv_instance *ins
     if (cfg->scheme < MRFV_ROE_WENO5 || cfg->scheme > MRFV_HLLC_WAO53) return bail(MRFV_EINVAL);
     for (int i = 0; i < cfg->n_instances; ++i) {
         if (check_instance(ctx, inst[i], i) != MRFV_OK) return bail(MRFV_EINVAL);
+        if (inst[i].eos != inst[0].eos) {
+            ctx->err = "every instance of a context needs the same equation of state";
+            return bail(MRFV_EINVAL);
+        }
         ctx->inst.push_back(inst[i]);
+    }
+    if (inst[0].eos == MRFV_TAIT &&
+        (cfg->scheme != MRFV_ROE_WENO5 || (cfg->batched && cfg->dtype == MRFV_F32))) {
+        ctx->err = "Tait's equation runs on the plain kernels with the Roe-WENO5 flux";
+        return bail(MRFV_EINVAL);
     }
     ctx->stream = (hipStream_t)hip_stream;
     if (hipGetDevice(&ctx->device) != hipSuccess ||
@@ -1036,7 +1056,8 @@ int mrfv_create(mrfv_ctx **out, const mrfv_config *cfg, const mrfv_instance *ins
         id[i] = InstDev{p.gamma, p.B, p.cfl, p.eps, p.scale_rho, p.scale_E, p.dx0, p.lmax,
                         {p.n0[0], p.n0[1], p.n0[2]}, {p.bc[0], p.bc[1], p.bc[2]}, p.adapt,
                         DETAIL_BAND_DEFAULT, {p.gravity[0], p.gravity[1], p.gravity[2]},
-                        (p.gravity[0] != 0.0 || p.gravity[1] != 0.0 || p.gravity[2] != 0.0) ? 1 : 0};
+                        (p.gravity[0] != 0.0 || p.gravity[1] != 0.0 || p.gravity[2] != 0.0) ? 1 : 0,
+                        p.eos, p.tait_A, p.tait_rho0};
     }
 #define ALLOC(ptr, bytes)                                                                  \
     if (hipMalloc((void **)&(ptr), (bytes)) != hipSuccess) {                                \
@@ -1385,6 +1406,8 @@ int mrfv_set_proposer(mrfv_ctx *ctx, mrfv_mlp *mlp, int32_t mode) {
     if (!ctx) return MRFV_EINVAL;
     if (mode < 0 || mode > 2 || (mode == 1 && !mlp))
         return fail(ctx, MRFV_EINVAL, "set_proposer: mode 0 (off), 1 (network) or 2 (persistence)");
+    if (mode != 0 && ctx->inst[0].eos == MRFV_TAIT)
+        return fail(ctx, MRFV_EINVAL, "set_proposer: the features assume the stiffened gas");
     const size_t cap = ctx->cfg.slot_capacity;
     if (mode != 0 && !ctx->tb2.meta) {
         auto al = [&](void **p, size_t bytes) { return hipMalloc(p, bytes) == hipSuccess; };

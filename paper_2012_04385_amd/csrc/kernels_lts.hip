@@ -56,6 +56,7 @@ __device__ __forceinline__ T lts_stage_coef(int stage) {
 
 template <typename T>
 __device__ __forceinline__ bool lts_physical(const T u[5], const InstDev &P) {
+    if (P.eos == 1) return u[0] > (T)0 && isfinite(u[1] + u[2] + u[3]);   // Tait
     const T g = (T)P.gamma, B = (T)P.B;
     const T ke = (T)0.5 * (u[1] * u[1] + u[2] * u[2] + u[3] * u[3]) / u[0];
     const T p = (g - (T)1) * (u[4] - ke) - g * B;

@@ -82,8 +82,10 @@ __global__ __launch_bounds__(TPB) void k_prim2cons(const double *__restrict__ pr
     ub[o + CELLS_P] = (T)(rho * u);
     ub[o + 2 * CELLS_P] = (T)(rho * v);
     ub[o + 3 * CELLS_P] = (T)(rho * w);
-    ub[o + 4 * CELLS_P] = (T)((p + P.gamma * P.B) / (P.gamma - 1.0) +
-                              0.5 * rho * (u * u + v * v + w * w));
+    // Tait: the pressure follows from the density and the energy is not evolved
+    ub[o + 4 * CELLS_P] = P.eos == 1 ? (T)0
+                                     : (T)((p + P.gamma * P.B) / (P.gamma - 1.0) +
+                                           0.5 * rho * (u * u + v * v + w * w));
 }
 
 // Halo regions.  Region (rx, ry, rz) in {-1, 0, 1}^3 \ {0} covers padded indices
@@ -710,7 +712,10 @@ __global__ __launch_bounds__(TPB) void k_cfl_block(const T *__restrict__ U, Work
 #pragma unroll
     for (int n = 0; n < NC; ++n) {
         double sp[3];
-        cfl_speeds(v[n][0], v[n][1], v[n][2], v[n][3], v[n][4], P.gamma, P.B, sp);
+        if (P.eos == 1)
+            cfl_speeds_tait(v[n][0], v[n][1], v[n][2], v[n][3], P.gamma, P.B, P.tait_rho0, sp);
+        else
+            cfl_speeds(v[n][0], v[n][1], v[n][2], v[n][3], v[n][4], P.gamma, P.B, sp);
 #pragma unroll
         for (int a = 0; a < 3; ++a) mx[a] = fmax(mx[a], sp[a]);
     }

@@ -190,6 +190,8 @@ __device__ __forceinline__ T wao53(T a, T b, T c, T d, T e) {
 
 // Flux kernels of Sec. "Numerical Scheme" (the weak-scaling combinations).
 enum { SCH_ROE_WENO5 = 0, SCH_ROE_TENO5 = 1, SCH_LLF_WENO5 = 2, SCH_HLLC_WAO53 = 3 };
+// Roe-WENO5 of the barotropic system of Tait's equation (plain path only)
+constexpr int SCH_TAIT_ROE_WENO5 = 4;
 
 // Reconstruction of the flux-splitting kernels at the right face of c.
 template <int SCH, typename T>
@@ -449,6 +451,120 @@ __device__ __forceinline__ void pencil(const T *__restrict__ ub, int r, int m, c
     }
 }
 
+// ------------------------------------------------- Tait's equation of state --------
+// Sec. "Influence of Equation of State": p = B (pg - 1) + A with pg = (rho/rho0)^gamma, so
+// c^2 = dp/drho = gamma B pg / rho; the energy is not evolved (its flux is zero).  The four
+// fields (u - c, u, u, u + c) of the barotropic system are projected with the closed-form
+// left eigenvectors at the Roe state (sqrt(rho)-weighted velocity and
+// c~^2 = (p_R - p_L)/(rho_R - rho_L)) and reconstructed by char_flux as for the stiffened
+// gas.  The secant c~^2 is evaluated without cancellation as
+//   B pg_L / rho_L * ((1 + d)^gamma - 1) / d,  d = (rho_R - rho_L) / rho_L,
+// with (1 + d)^gamma - 1 = expm1(gamma log1p(d)), and gamma B pg_L / rho_L = c_L^2 at d = 0;
+// the plain difference quotient loses all digits when the densities differ by a few
+// rounding units, which in FP32 is common in smooth regions.
+template <typename T>
+struct TaitGas {
+    T g, B, A, ir0;   // gamma, B, A, 1 / rho0
+};
+
+template <typename T>
+struct TaitState {
+    T r, mn, mt1, mt2, ir, un, pg, p, c;
+};
+
+__device__ __forceinline__ float pow_(float x, float y) { return powf(x, y); }
+__device__ __forceinline__ double pow_(double x, double y) { return pow(x, y); }
+__device__ __forceinline__ float expm1_(float x) { return expm1f(x); }
+__device__ __forceinline__ double expm1_(double x) { return expm1(x); }
+__device__ __forceinline__ float log1p_(float x) { return log1pf(x); }
+__device__ __forceinline__ double log1p_(double x) { return log1p(x); }
+
+template <typename T, int DIR>
+__device__ __forceinline__ void load_tait(const T *__restrict__ u, int idx, const TaitGas<T> &G,
+                                          TaitState<T> &s) {
+    s.r = u[idx];
+    s.mn = u[idx + Axes<DIR>::N1 * CELLS_P];
+    s.mt1 = u[idx + Axes<DIR>::T1 * CELLS_P];
+    s.mt2 = u[idx + Axes<DIR>::T2 * CELLS_P];
+    s.ir = rcp_(s.r);
+    s.un = s.mn * s.ir;
+    s.pg = pow_(s.r * G.ir0, G.g);
+    s.p = fma(G.B, s.pg - (T)1, G.A);
+    s.c = sqrt_(G.g * G.B * s.pg * s.ir);
+}
+
+template <typename T>
+__device__ __forceinline__ void face_flux_tait(const TaitState<T> w[6], const TaitGas<T> &G, T F[5]) {
+    const TaitState<T> &L = w[2], &R = w[3];
+    const T sl = sqrt_(L.r), sr = sqrt_(R.r);
+    const T inv = rcp_(sl + sr);
+    const T u = (sl * L.un + sr * R.un) * inv;
+    const T v = (sl * (L.mt1 * L.ir) + sr * (R.mt1 * R.ir)) * inv;
+    const T ww = (sl * (L.mt2 * L.ir) + sr * (R.mt2 * R.ir)) * inv;
+    const T d = (R.r - L.r) * L.ir;
+    const T ratio = d == (T)0 ? G.g : expm1_(G.g * log1p_(d)) / d;
+    const T c = sqrt_(G.B * L.pg * L.ir * ratio), h = (T)0.5 * rcp_(c);
+    const T upc = u + c, umc = u - c;
+    T W1[6], W2[6], W3[6], W4[6], G1[6], G2[6], G3[6], G4[6];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        const TaitState<T> &q = w[j];
+        const T f1 = fma(q.mn, q.un, q.p);
+        W1[j] = (upc * q.r - q.mn) * h;
+        W4[j] = (q.mn - umc * q.r) * h;
+        W2[j] = q.mt1 - v * q.r;
+        W3[j] = q.mt2 - ww * q.r;
+        G1[j] = (upc * q.mn - f1) * h;
+        G4[j] = (f1 - umc * q.mn) * h;
+        G2[j] = q.mt1 * q.un - v * q.mn;
+        G3[j] = q.mt2 * q.un - ww * q.mn;
+    }
+    const T g1 = char_flux<SCH_ROE_WENO5>(W1, G1, L.un - L.c, R.un - R.c);
+    const T g2 = char_flux<SCH_ROE_WENO5>(W2, G2, L.un, R.un);
+    const T g3 = char_flux<SCH_ROE_WENO5>(W3, G3, L.un, R.un);
+    const T g4 = char_flux<SCH_ROE_WENO5>(W4, G4, L.un + L.c, R.un + R.c);
+    F[0] = g1 + g4;
+    F[1] = umc * g1 + upc * g4;
+    F[2] = v * F[0] + g2;
+    F[3] = ww * F[0] + g3;
+    F[4] = (T)0;
+}
+
+// The pencil walk of `pencil` for Tait's system.
+template <typename T, int DIR, class Sink>
+__device__ __forceinline__ void pencil_tait(const T *__restrict__ ub, int r, int m, const TaitGas<T> &G,
+                                            Sink &sink) {
+    constexpr int S = Axes<DIR>::STRIDE;
+    const int qmap[5] = {0, Axes<DIR>::N1, Axes<DIR>::T1, Axes<DIR>::T2, 4};
+    const int base = pencil_base<DIR>(r, m);
+    TaitState<T> w[6];
+#pragma unroll
+    for (int j = 0; j < 5; ++j) load_tait<T, DIR>(ub, base + (j + 1) * S, G, w[j]);
+    T Fp[5];
+#pragma unroll 1
+    for (int f = 0; f <= NI; ++f) {
+        load_tait<T, DIR>(ub, base + (f + 6) * S, G, w[5]);
+        T F[5];
+        face_flux_tait<T>(w, G, F);
+        if (f == 0) {
+#pragma unroll
+            for (int k = 0; k < 5; ++k) sink.face(2 * DIR, qmap[k], F[k]);
+        } else {
+            const int cell = cell_of<DIR>(r, m, f - 1);
+#pragma unroll
+            for (int k = 0; k < 5; ++k) sink.cell(qmap[k], cell, F[k] - Fp[k]);
+        }
+        if (f == NI) {
+#pragma unroll
+            for (int k = 0; k < 5; ++k) sink.face(2 * DIR + 1, qmap[k], F[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < 5; ++k) Fp[k] = F[k];
+#pragma unroll
+        for (int j = 0; j < 5; ++j) w[j] = w[j + 1];
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ Gas<T> gas_of(const InstDev &P) {
     return Gas<T>{(T)P.gamma, (T)P.B, (T)(P.gamma - 1.0)};
@@ -472,14 +588,22 @@ __global__ __launch_bounds__(TPB) void k_flux(const T *__restrict__ U, WorkList 
     const int nb = wl.count();
     for (int b = blockIdx.x; b < nb; b += gridDim.x) {
     const int slot = wl.at(b);
-    const Gas<T> G = gas_of<T>(inst[meta[slot].inst]);
     const int r = threadIdx.x & 15, m = threadIdx.x >> 4;
     const T *ub = U + (size_t)slot * 5 * CELLS_P;
     GlobalSink<T> sink{D + (size_t)slot * 3 * 5 * CELLS_I, FF + (size_t)slot * 6 * 5 * FACE,
                        (int)blockIdx.y, m * NI + r};
-    if (blockIdx.y == 0) pencil<T, 0, SCH>(ub, r, m, G, sink);
-    else if (blockIdx.y == 1) pencil<T, 1, SCH>(ub, r, m, G, sink);
-    else pencil<T, 2, SCH>(ub, r, m, G, sink);
+    if constexpr (SCH == SCH_TAIT_ROE_WENO5) {
+        const InstDev &P = inst[meta[slot].inst];
+        const TaitGas<T> G{(T)P.gamma, (T)P.B, (T)P.tait_A, (T)(1.0 / P.tait_rho0)};
+        if (blockIdx.y == 0) pencil_tait<T, 0>(ub, r, m, G, sink);
+        else if (blockIdx.y == 1) pencil_tait<T, 1>(ub, r, m, G, sink);
+        else pencil_tait<T, 2>(ub, r, m, G, sink);
+    } else {
+        const Gas<T> G = gas_of<T>(inst[meta[slot].inst]);
+        if (blockIdx.y == 0) pencil<T, 0, SCH>(ub, r, m, G, sink);
+        else if (blockIdx.y == 1) pencil<T, 1, SCH>(ub, r, m, G, sink);
+        else pencil<T, 2, SCH>(ub, r, m, G, sink);
+    }
     }
 }
 
@@ -635,7 +759,10 @@ __global__ __launch_bounds__(TPB) void k_update(int stage, const double *__restr
         un[q] = u0 + a * ((us - u0) + dtt * lb[q * CELLS_I + c]);
         ub[o + q * CELLS_P] = un[q];
     }
-    if (!physical_state(un, G)) atomicOr(err, 1);
+    // Tait: any positive density (the energy is not evolved)
+    const bool ok = inst[mt.inst].eos == 1 ? un[0] > (T)0 && isfinite(un[1] + un[2] + un[3])
+                                           : physical_state(un, G);
+    if (!ok) atomicOr(err, 1);
     }
 }
 
@@ -1086,6 +1213,7 @@ hipError_t launch_flux(int scheme, const T *U, const WorkList &wl, const DevTabl
         case SCH_ROE_TENO5: hipLaunchKernelGGL((k_flux<T, SCH_ROE_TENO5>), grid, block, 0, st, U, wl, tb.meta, inst, D, FF); break;
         case SCH_LLF_WENO5: hipLaunchKernelGGL((k_flux<T, SCH_LLF_WENO5>), grid, block, 0, st, U, wl, tb.meta, inst, D, FF); break;
         case SCH_HLLC_WAO53: hipLaunchKernelGGL((k_flux<T, SCH_HLLC_WAO53>), grid, block, 0, st, U, wl, tb.meta, inst, D, FF); break;
+        case SCH_TAIT_ROE_WENO5: hipLaunchKernelGGL((k_flux<T, SCH_TAIT_ROE_WENO5>), grid, block, 0, st, U, wl, tb.meta, inst, D, FF); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

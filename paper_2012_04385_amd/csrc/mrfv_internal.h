@@ -38,6 +38,8 @@ struct InstDev {
     double detail_band;   // slabs with |detail - eps_l| <= band are evaluated again exactly
     double gravity[3];    // source term S(U) = (0, rho g, rho v . g)
     int32_t has_source;   // gravity is not the zero vector
+    int32_t eos;          // 0 stiffened gas, 1 Tait (p = B ((rho/rho0)^gamma - 1) + A)
+    double tait_A, tait_rho0;
 };
 constexpr double DETAIL_BAND_DEFAULT = 1e-9;
 
@@ -85,6 +87,15 @@ __device__ __forceinline__ void cfl_speeds(double r, double m0, double m1, doubl
     const double k2 = fma(m2, m2, fma(m1, m1, m0 * m0));
     const double p = fma(gamma - 1.0, fma(-0.5 * k2, ir, E), -gamma * B);
     const double cs = sqrt(gamma * (p + B) * ir);
+    s[0] = fma(fabs(m0), ir, cs);
+    s[1] = fma(fabs(m1), ir, cs);
+    s[2] = fma(fabs(m2), ir, cs);
+}
+// The same for Tait's equation, c^2 = gamma B / rho0 (rho / rho0)^(gamma - 1).
+__device__ __forceinline__ void cfl_speeds_tait(double r, double m0, double m1, double m2,
+                                                double gamma, double B, double rho0, double s[3]) {
+    const double ir = 1.0 / r;
+    const double cs = sqrt(gamma * B / rho0 * pow(r / rho0, gamma - 1.0));
     s[0] = fma(fabs(m0), ir, cs);
     s[1] = fma(fabs(m1), ir, cs);
     s[2] = fma(fabs(m2), ir, cs);

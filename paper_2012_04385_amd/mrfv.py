@@ -30,7 +30,8 @@ class Instance(C.Structure):
     _fields_ = [("gamma", C.c_double), ("B", C.c_double), ("cfl", C.c_double),
                 ("eps", C.c_double), ("scale_rho", C.c_double), ("scale_E", C.c_double),
                 ("dx0", C.c_double), ("lmax", C.c_int32), ("n0", C.c_int32 * 3),
-                ("bc", C.c_int32 * 3), ("adapt", C.c_int32), ("gravity", C.c_double * 3)]
+                ("bc", C.c_int32 * 3), ("adapt", C.c_int32), ("gravity", C.c_double * 3),
+                ("eos", C.c_int32), ("tait_A", C.c_double), ("tait_rho0", C.c_double)]
 
 
 class Config(C.Structure):
@@ -40,6 +41,7 @@ class Config(C.Structure):
 
 # flux kernels (mrfv_scheme)
 SCHEMES = {"roe_weno5": 0, "roe_teno5": 1, "llf_weno5": 2, "hllc_wao53": 3}
+EOS = {"stiffened": 0, "tait": 1}
 
 
 IC_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
@@ -152,6 +154,9 @@ def _instance(pb) -> Instance:
     inst.adapt = pb.adapt
     for a, gv in enumerate(getattr(pb, "gravity", (0.0, 0.0, 0.0))):
         inst.gravity[a] = gv
+    inst.eos = EOS[getattr(pb, "eos", "stiffened")]
+    inst.tait_A = getattr(pb, "tait_A", 1.0)
+    inst.tait_rho0 = getattr(pb, "tait_rho0", 1.0)
     return inst
 
 
