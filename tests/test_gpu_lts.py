@@ -138,3 +138,43 @@ def test_lts_rejects_mixed_lmax(torch_mod):
     g = Solver(pbs, dtype="f64", batched=False, adapt=0).init()
     with pytest.raises(MrfvError):
         g.step_lts()
+
+
+def test_lts_levels_without_leaves(orc, torch_mod):
+    """l_max = 3 but leaves on levels 0 and 1 only: the micro steps of the empty finer levels
+    integrate nothing, level 1 steps with 4 dt and level 0 with 8 dt."""
+    pb = W.uniform_flow(lmax=3, n0=(2, 2, 2))
+    o, g = make_pair(orc, pb, [], "f64")
+    o.coarsen(0, 1, 0, 1)
+    g.coarsen(0, 0, 1, 0, 1)
+    set_interiors(o, g, lambda k: _pulse(pb, k))
+    o.project()
+    g.mr_project()
+    assert {k[0] for k in o.leaf_states()} == {0, 1}
+    o.step_lts()
+    g.step_lts()
+    torch_mod.cuda.synchronize()
+    g.check()
+    worst = _worst(o, g)
+    print(f"[lts] empty finer levels: worst relative difference {worst:.3e}", flush=True)
+    assert worst < 1e-12, worst
+
+
+def test_lts_between_graph_steps(orc, torch_mod):
+    """A macro step between step-graph runs of the fused FP32 path gives the oracle's
+    global, local, global sequence (the graph steps' reuse of the previous stage's
+    restriction and CFL maxima must not carry across the macro step)."""
+    o, g = _pair(orc, "f32", batched=2)
+    for _ in range(2):
+        o.step()
+    g.run(2)
+    o.step_lts()
+    g.step_lts()
+    for _ in range(2):
+        o.step()
+    g.run(2)
+    torch_mod.cuda.synchronize()
+    g.check()
+    worst = _worst(o, g)
+    print(f"[lts] between graph steps: worst relative difference {worst:.3e}", flush=True)
+    assert worst < 5e-6, worst
