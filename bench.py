@@ -258,7 +258,48 @@ def lts_leg(pbs, dtype, warmup, macro_steps):
     out.update({"global_steps": steps, "global_ms_per_step": 1e3 * secs_g / steps,
                 "global_sim_time_per_s": sim_g / secs_g,
                 "time_to_solution_speedup": (sim / secs) / (sim_g / secs_g)})
+    # the path's own roofline: the stiffened-gas FLOP model per cell-update over the whole
+    # macro step's rate (a lower bound of its flux kernel's rate)
+    peak = PEAK_FP32_VECTOR if dtype == "f32" else PEAK_FP64_VECTOR
+    fpc = flops_per_cell_update(0.5)
+    out["roofline"] = {"bound": "alu", "achieved": out["cell_updates_per_s"] * fpc / 1e12,
+                       "peak": peak / 1e12, "unit": "TFLOP/s", "frac": out["cell_updates_per_s"] * fpc / peak,
+                       "basis": "whole-macro-step rate x FLOP model (LLF fraction 0.5 assumed)"}
+    out["cpu_baseline"] = lts_oracle_sample()
     return out
+
+
+def lts_oracle_sample():
+    """The oracle's local time stepping timed on a bounded sample: one macro step of a
+    four-level periodic tree (levels 0-3, one- and two-level jumps, a Gaussian pulse)."""
+    import numpy as np
+    from oracle import oracle
+    from paper_2012_04385_amd import workloads as W
+    pb = W.uniform_flow(lmax=3, n0=(2, 2, 2))
+    sim = oracle.Sim(pb, adapt=0).init()
+    for args in [(1, 1, 1, 1), (1, 2, 1, 1), (2, 3, 2, 2), (1, 0, 3, 0)]:
+        sim.refine(*args)
+    sim.coarsen(0, 1, 0, 1)
+    for n, r in enumerate(sim.blocks()):
+        lvl, bx, by, bz = (int(v) for v in r[:4])
+        h = pb.dx(lvl)
+        ar = np.arange(16) + 0.5
+        z, y, x = np.meshgrid((bz * 16 + ar) * h, (by * 16 + ar) * h, (bx * 16 + ar) * h, indexing="ij")
+        g = np.exp(-((x - 0.45) ** 2 + (y - 0.5) ** 2 + (z - 0.55) ** 2) / 0.01)
+        rho, p = 1.0 + 0.5 * g, 1.0 + 2.0 * g
+        blk = sim.get_block(n)
+        blk[:, 4:20, 4:20, 4:20] = np.stack([rho, 0.4 * rho, -0.2 * rho, 0.3 * rho,
+                                            p / 0.4 + 0.5 * rho * 0.29])
+        sim.set_block(n, blk)
+    sim.project()
+    cells = 3 * sum((1 << int(r[0])) * 16 ** 3 for r in sim.blocks() if r[4] == 1)
+    t0 = time.perf_counter()
+    sim.step_lts()
+    secs = time.perf_counter() - t0
+    model, phys, allowed = host_cpu()
+    return {"value": cells / secs, "unit": "cell-updates/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": "one LTS macro step of a 4-level periodic test tree (FP64, OpenMP over blocks)",
+            "physical_cores": phys, "logical_cpus_allowed": allowed, "cpu_model": model}
 
 
 def eos_leg(warmup, steps):
@@ -278,6 +319,20 @@ def eos_leg(warmup, steps):
             log(f"[bench] {eos} {dtype}: {cells / secs:.4e} cell-updates/s")
         out[f"tait_time_per_cell_update_vs_stiffened_{dtype}"] = (
             out[f"stiffened_{dtype}"]["cell_updates_per_s"] / out[f"tait_{dtype}"]["cell_updates_per_s"])
+    # the oracle on the same tube with Tait's equation: five steps after its algo:Init
+    from oracle import oracle
+    pb = W.sod_tait_mr3(eos="tait", steps=5)
+    sim = oracle.Sim(pb).init()
+    cells = 0
+    t0 = time.perf_counter()
+    for _ in range(5):
+        cells += 3 * 16 ** 3 * int((sim.blocks()[:, 4] == 1).sum())
+        sim.step()
+    secs = time.perf_counter() - t0
+    model, phys, allowed = host_cpu()
+    out["cpu_baseline_tait"] = {"value": cells / secs, "unit": "cell-updates/s", "cores": oracle.num_threads(),
+                                "kind": "oracle", "sample": "steps 1-5 of the tube with Tait's equation (FP64)",
+                                "physical_cores": phys, "logical_cpus_allowed": allowed, "cpu_model": model}
     return out
 
 

@@ -238,9 +238,9 @@ int mrfv_run(mrfv_ctx *ctx, void *U, void *U0, void *L, double *dt_dev, int32_t 
  * replaces its own sum by the fine average at the end of its step (coarse cell
  * adjustment).  Adaptive instances run mr_flag, commit_flags and mr_predict once, after
  * the last micro step.  Runs on the plain per-block kernels in the context's dtype (any
- * batched mode).  U0, L: dev scratch of mrfv_interior_bytes, as for mrfv_step; the
- * library allocates its padded flux-divergence field, the jump-halo stage state and the
- * face-flux sums on first use (MRFV_ENOMEM if it cannot).  cell_updates_host (may be
+ * batched mode).  U0: dev scratch of mrfv_interior_bytes, as for mrfv_step; L is not used
+ * (may be NULL); the library allocates its padded flux-divergence field, the jump-halo
+ * stage state and the face-flux sums on first use (MRFV_ENOMEM if it cannot).  cell_updates_host (may be
  * NULL): leaf cells times their own steps in this macro step.  Every instance must have
  * the same lmax (else MRFV_EINVAL). */
 int mrfv_step_lts(mrfv_ctx *ctx, void *U, void *U0, void *L, double *dt_dev,

@@ -961,8 +961,7 @@ int do_lts_macro(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt, int64_t *cell_up
                 const WorkList w = wlist(ctx, desc_leaf(l));
                 HIP_OK(launch_fill_halos<T>(U, w, ctx->tb, (FillMode)(FILL_FACES | FILL_PRESENT), ctx->stream));
                 HIP_OK(launch_flux<T>(flux_kernel(ctx), U, w, ctx->tb, ctx->d_inst, D, FF, ctx->stream));
-                HIP_OK(launch_combine<T>(D, Lb, w, ctx->tb, ctx->d_inst, U, ctx->stream));
-                HIP_OK(launch_lts_scatter<T>(Lb, F, w, ctx->stream));
+                HIP_OK(launch_lts_combine<T>(D, F, w, ctx->tb, ctx->d_inst, U, ctx->stream));
             }
             // averaged into the parents, predicted into the jump halos
             for (int p = top - 1; p >= std::max(lo_rhs, 1) - 1; --p)
@@ -1289,7 +1288,7 @@ int mrfv_step(mrfv_ctx *ctx, void *U, void *U0, void *L, double *dt_dev) {
 int mrfv_step_lts(mrfv_ctx *ctx, void *U, void *U0, void *L, double *dt_dev,
                   int64_t *cell_updates_host) {
     CALL(need_init(ctx));
-    if (!U || !U0 || !L || !dt_dev) return fail(ctx, MRFV_EINVAL, "step_lts: null pointer");
+    if (!U || !U0 || !dt_dev) return fail(ctx, MRFV_EINVAL, "step_lts: null pointer");
     for (const auto &p : ctx->inst)
         if (p.lmax != ctx->inst[0].lmax)
             return fail(ctx, MRFV_EINVAL, "step_lts: every instance needs the same lmax");

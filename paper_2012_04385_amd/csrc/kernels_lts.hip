@@ -4,13 +4,15 @@
 // Level l advances with its own step dt_l = 2^(lmax - l) dt, dt being the eq:Cfl step of
 // level lmax.  Per RK stage of a level's step the host runs the plain flux kernels on the
 // leaves being evaluated, then
-//   lts_scatter  the flux divergence of those leaves into the padded field F, whose
-//                parents (eq:Averaging) and halos at resolution jumps (eq:Prediction) are
-//                built by the state's own kernels (project, fill_halos) applied to F;
+//   lts_combine  the flux divergence of those leaves (from the flux kernel's differences)
+//                into the padded field F, whose parents (eq:Averaging) and halos at
+//                resolution jumps (eq:Prediction) are built by the state's own kernels
+//                (project, fill_halos) applied to F;
 //   lts_update   the SSP-RK3 stage of the interior cells and of the halo cells of faces
 //                without a same-level neighbour (integrated with the predicted flux
 //                divergence, algo:Integration), and the stage's boundary face fluxes added
-//                to per-face sums with the stage's weight in the RK scheme;
+//                to per-face sums with the stage's weight in the RK scheme (only on the
+//                faces a coarse cell adjustment reads);
 //   lts_adjust   the coarse cell adjustment at the end of a coarse leaf's step: on faces
 //                whose same-level neighbour is refined, the own time-integrated flux is
 //                replaced by the area average of the fine sums (built by k_ff_restrict);
@@ -63,18 +65,43 @@ __device__ __forceinline__ bool lts_physical(const T u[5], const InstDev &P) {
     return u[0] > (T)0 && p + B > (T)0 && isfinite(u[4]) && isfinite(u[1] + u[2] + u[3]);
 }
 
+// The flux divergence of a leaf, L = -(D_x + D_y + D_z) / dx plus the gravity source of
+// eq:Euler (the plain path's combine, in the same operation order), written into the
+// padded field F.
 template <typename T>
-__global__ __launch_bounds__(TPB) void k_lts_scatter(const T *__restrict__ L, T *__restrict__ F,
-                                                     WorkList wl) {
+__global__ __launch_bounds__(TPB) void k_lts_combine(const T *__restrict__ D, T *__restrict__ F, WorkList wl,
+                                                     const BlockMeta *__restrict__ meta,
+                                                     const InstDev *__restrict__ inst,
+                                                     const T *__restrict__ U) {
     const int nb = wl.count();
     for (int b = blockIdx.x; b < nb; b += gridDim.x) {
         const int slot = wl.at(b);
+        const BlockMeta mt = meta[slot];
+        const InstDev &P = inst[mt.inst];
+        const T inv_dx = (T)(1.0 / ldexp(P.dx0, -mt.level));
+        const T *Ds = D + (size_t)slot * 3 * 5 * CELLS_I;
         const int c = blockIdx.y * TPB + threadIdx.x;
         const int o = ((c / FACE + HW) * NP + (c / NI) % NI + HW) * NP + c % NI + HW;
-        const T *ls = L + (size_t)slot * 5 * CELLS_I;
+        T l[5];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            const T s = (Ds[q * CELLS_I + c] + Ds[(5 + q) * CELLS_I + c]) + Ds[(10 + q) * CELLS_I + c];
+            l[q] = -s * inv_dx;
+        }
+        if (P.has_source) {   // uniform per workgroup
+            const T *ub = U + (size_t)slot * 5 * CELLS_P;
+            T u[5];
+#pragma unroll
+            for (int q = 0; q < 5; ++q) u[q] = ub[o + q * CELLS_P];
+            const T gx = (T)P.gravity[0], gy = (T)P.gravity[1], gz = (T)P.gravity[2];
+            l[1] = fma(u[0], gx, l[1]);
+            l[2] = fma(u[0], gy, l[2]);
+            l[3] = fma(u[0], gz, l[3]);
+            l[4] += fma(u[3], gz, fma(u[2], gy, u[1] * gx));
+        }
         T *fs = F + (size_t)slot * 5 * CELLS_P;
 #pragma unroll
-        for (int q = 0; q < 5; ++q) fs[q * CELLS_P + o] = ls[q * CELLS_I + c];
+        for (int q = 0; q < 5; ++q) fs[q * CELLS_P + o] = l[q];
     }
 }
 
@@ -137,7 +164,11 @@ __global__ __launch_bounds__(TPB) void k_lts_update(int stage, const double *__r
                 ub[n] = u0 + a * ((us - u0) + (T)dtl * fb[n]);
             }
         } else {
+            // only faces that a coarse cell adjustment reads: jump faces (the fine side) and
+            // faces whose same-level neighbour is refined (the coarse side)
             const int side = part - UPD_INTERIOR - 18;
+            const int nbs = nbr[(size_t)slot * 27 + face_region(side)];
+            if (!(nbs == -1 || (nbs >= 0 && !meta[nbs].leaf))) continue;
             const double bw = stage == 2 ? 2.0 / 3.0 : 1.0 / 6.0;
             const T w = (T)(bw * dtl);
             const size_t base = ((size_t)slot * 6 + side) * 5 * FACE + tid;
@@ -204,9 +235,11 @@ __global__ __launch_bounds__(TPB) void k_lts_zero(T *ACC, WorkList wl, const Blo
 }  // namespace
 
 template <typename T>
-hipError_t launch_lts_scatter(const T *L, T *F, const WorkList &wl, hipStream_t st) {
+hipError_t launch_lts_combine(const T *D, T *F, const WorkList &wl, const DevTables &tb,
+                              const InstDev *inst, const T *U, hipStream_t st) {
     if (wl.grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_lts_scatter<T>, dim3(wl.grid, CELLS_I / TPB), dim3(TPB), 0, st, L, F, wl);
+    hipLaunchKernelGGL(k_lts_combine<T>, dim3(wl.grid, CELLS_I / TPB), dim3(TPB), 0, st, D, F, wl, tb.meta,
+                       inst, U);
     return hipGetLastError();
 }
 
@@ -241,7 +274,8 @@ hipError_t launch_lts_zero(T *ACC, const WorkList &wl, const DevTables &tb, int 
 int lts_halo_slab() { return SLAB; }
 
 #define MRFV_LTS_INST(T)                                                                          \
-    template hipError_t launch_lts_scatter<T>(const T *, T *, const WorkList &, hipStream_t);     \
+    template hipError_t launch_lts_combine<T>(const T *, T *, const WorkList &, const DevTables &, \
+                                              const InstDev *, const T *, hipStream_t);             \
     template hipError_t launch_lts_update<T>(int, const double *, T *, T *, T *, const T *,      \
                                              const T *, T *, const WorkList &, const DevTables &, \
                                              const InstDev *, int32_t *, hipStream_t);            \

@@ -298,7 +298,8 @@ hipError_t launch_reflux_update(int stage, const double *dt, T *U, const T *FF,
 // H0: stage-start state of the halo cells of jump faces [cap][6][5][lts_halo_slab()];
 // ACC: time-integrated boundary face fluxes [cap][6][5][16][16] (the layout of FF).
 template <typename T>
-hipError_t launch_lts_scatter(const T *L, T *F, const WorkList &leaves, hipStream_t st);
+hipError_t launch_lts_combine(const T *D, T *F, const WorkList &leaves, const DevTables &tb,
+                              const InstDev *inst, const T *U, hipStream_t st);
 template <typename T>
 hipError_t launch_lts_update(int stage, const double *dt, T *U, T *U0, T *H0, const T *F,
                              const T *FF, T *ACC, const WorkList &leaves, const DevTables &tb,
