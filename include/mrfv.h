@@ -1,7 +1,8 @@
 /*
  * mrfv.h -- C ABI of the MI355X (gfx950) hot path of the block-based multiresolution
  * finite-volume solver of Hoppe, Adami & Adams (arXiv 2012.04385) for the 3D
- * compressible Euler equations (eq:Euler with the stiffened-gas EOS eq:StiffenedGas).
+ * compressible Euler equations (eq:Euler with the stiffened-gas EOS eq:StiffenedGas), with
+ * optional gravity and viscous terms and Tait's equation of state.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -59,7 +60,16 @@ typedef enum { MRFV_ROE_WENO5 = 0, MRFV_ROE_TENO5 = 1, MRFV_LLF_WENO5 = 2,
  * MRFV_ROE_WENO5, no gravity, no proposer, and not the fused FP32 path (batched with
  * MRFV_F32); mrfv_create returns MRFV_EINVAL otherwise. */
 typedef enum { MRFV_STIFFENED_GAS = 0, MRFV_TAIT = 1 } mrfv_eos;
-typedef enum { MRFV_BC_PERIODIC = 0, MRFV_BC_ZEROGRAD = 1 } mrfv_bc;
+/* External boundaries per axis: periodic; zero gradient (every halo layer a copy of the
+ * boundary cell); symmetry (the halo is the mirror image of the interior with the
+ * momentum normal to the boundary reversed: a slip wall, the symmetry planes of the
+ * paper's Rayleigh-Taylor and implosion cases); fixed values (each halo layer holds a
+ * given state, uniform over the boundary plane: mrfv_instance.bc_fixed; the top and
+ * bottom of the Rayleigh-Taylor case).  Where halo layers of several boundary axes meet
+ * (edges, corners), the axes apply in the order x, y, z, each over the whole padded
+ * extent of the others. */
+typedef enum { MRFV_BC_PERIODIC = 0, MRFV_BC_ZEROGRAD = 1, MRFV_BC_SYMMETRY = 2,
+               MRFV_BC_FIXED = 3 } mrfv_bc;
 
 /* One independent MR problem (one forest of octrees on a box). */
 typedef struct {
@@ -78,6 +88,26 @@ typedef struct {
                              vector: no source                                          */
     int32_t eos;          /* mrfv_eos; the same for every instance of a context          */
     double tait_A, tait_rho0;   /* Tait: p = B ((rho/rho0)^gamma - 1) + A (gamma, B above) */
+    double mu;            /* dynamic viscosity (>= 0; 0: Euler equations).  With mu > 0
+                             the flux carries the viscous terms of the Navier-Stokes
+                             equations: Newtonian stress with Stokes' hypothesis, tau =
+                             mu (grad v + grad v^T) - 2/3 mu (div v) I, flux (0, tau_d.,
+                             tau_d. . v) subtracted from the convective one, no heat
+                             conduction; second-order central differences at the faces
+                             (normal: the two cells sharing the face; tangential: the mean
+                             of their central differences).  dt is then also bounded by
+                             cfl * 3/16 * dx_lmax^2 * min(rho) / mu.  Viscous contexts
+                             (any instance with mu > 0) run on the plain kernels and fill
+                             all 26 halo regions of the leaves every stage (the
+                             tangential derivatives read the edge halos); mrfv_create
+                             returns MRFV_EINVAL for one on the fused FP32 path (batched
+                             with MRFV_F32), mrfv_step_lts returns MRFV_EINVAL for one. */
+    const double *bc_fixed;   /* host, read by mrfv_create only; required when some axis
+                             has MRFV_BC_FIXED, else ignored (may be NULL): primitive states
+                             (rho, u, v, w, p) of the halo cells beyond the sides of those
+                             axes, [6 sides: x-, x+, y-, y+, z-, z+][lmax + 1 levels]
+                             [4 layers, the one at the face first][5], converted with the
+                             instance's EOS like the initial condition               */
 } mrfv_instance;
 
 typedef struct {
@@ -242,7 +272,7 @@ int mrfv_run(mrfv_ctx *ctx, void *U, void *U0, void *L, double *dt_dev, int32_t 
  * (may be NULL); the library allocates its padded flux-divergence field, the jump-halo
  * stage state and the face-flux sums on first use (MRFV_ENOMEM if it cannot).  cell_updates_host (may be
  * NULL): leaf cells times their own steps in this macro step.  Every instance must have
- * the same lmax (else MRFV_EINVAL). */
+ * the same lmax (else MRFV_EINVAL), and none may be viscous (MRFV_EINVAL). */
 int mrfv_step_lts(mrfv_ctx *ctx, void *U, void *U0, void *L, double *dt_dev,
                   int64_t *cell_updates_host);
 

@@ -7,7 +7,7 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCES = ["orc_euler.cpp", "orc_mr.cpp", "orc_riemann.cpp", "orc_tree.cpp", "orc_mlp.cpp",
-           "orc_schemes.cpp", "orc_tait.cpp"]
+           "orc_schemes.cpp", "orc_tait.cpp", "orc_viscous.cpp"]
 LIB = os.path.join(HERE, "liborc.so")
 
 

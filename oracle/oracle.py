@@ -23,7 +23,7 @@ class _Params(C.Structure):
                 ("dx0", C.c_double), ("lmax", C.c_int32), ("n0", C.c_int32 * 3),
                 ("bc", C.c_int32 * 3), ("adapt", C.c_int32), ("scheme", C.c_int32),
                 ("gravity", C.c_double * 3), ("eos", C.c_int32), ("tait_A", C.c_double),
-                ("tait_rho0", C.c_double)]
+                ("tait_rho0", C.c_double), ("mu", C.c_double), ("bc_fixed", C.POINTER(C.c_double))]
 
 
 IC_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
@@ -132,6 +132,11 @@ def lib():
         L.orc_tait_face_flux.restype = C.c_int
         L.orc_tait_exact_riemann.argtypes = [d, d, d, d, d, d, d, d, pd, C.c_int, pd]
         L.orc_tait_exact_riemann.restype = C.c_int
+        L.orc_visc_face_flux.argtypes = [C.c_int, pd, d, C.c_int, d, pd]
+        L.orc_visc_dt.argtypes = [d, d, d, d]
+        L.orc_visc_dt.restype = d
+        L.orc_rti_growth_rate.argtypes = [d, d, d, d, d]
+        L.orc_rti_growth_rate.restype = d
         L.orc_block_rhs.restype = None
         L.orc_block_detail.argtypes = [pd, pd, C.c_int, C.c_int, C.c_int, d, d]
         L.orc_block_detail.restype = d
@@ -282,6 +287,28 @@ def tait_exact_riemann(left, right, gamma, B, A, rho0, s) -> np.ndarray:
     return out
 
 
+def visc_face_flux(d: int, st, mu: float, dx: float, energy: bool = True) -> np.ndarray:
+    """Viscous flux through a face normal to axis d; st[2][5][5] = (side, cell, q) with
+    cell 0 the one sharing the face and 1..4 its tangential neighbours (-1/+1 along the
+    lower other axis, then along the higher one)."""
+    s = np.ascontiguousarray(st, dtype=np.float64).reshape(50)
+    F = np.zeros(5)
+    lib().orc_visc_face_flux(d, _dp(s), mu, 1 if energy else 0, dx, _dp(F))
+    return F
+
+
+def visc_dt(cfl: float, dx: float, mu: float, rinv_max: float) -> float:
+    return lib().orc_visc_dt(cfl, dx, mu, rinv_max)
+
+
+def rti_growth_rate(k: float, rho_h: float, rho_l: float, mu: float, g: float) -> float:
+    """Root n of eq:SinglePhaseGrowth (equal dynamic viscosities, no surface tension)."""
+    n = lib().orc_rti_growth_rate(k, rho_h, rho_l, mu, g)
+    if n < 0:
+        raise ValueError("no growing mode")
+    return n
+
+
 def lts_lowest_ending(lmax: int, r: int) -> int:
     """Lowest level that completes a step of its own at micro step r (algo:ComputeLoop)."""
     return lib().orc_lts_lowest_ending(lmax, r)
@@ -381,6 +408,11 @@ class Sim:
         p.eos = EOS[getattr(problem, "eos", "stiffened")]
         p.tait_A = getattr(problem, "tait_A", 1.0)
         p.tait_rho0 = getattr(problem, "tait_rho0", 1.0)
+        p.mu = getattr(problem, "mu", 0.0)
+        fixed = problem.bc_fixed_states() if hasattr(problem, "bc_fixed_states") else None
+        if fixed is not None:
+            self._fixed = np.ascontiguousarray(fixed, dtype=np.float64)   # copied by create
+            p.bc_fixed = _dp(self._fixed)
         self._p = p
         self.h = lib().orc_sim_create(C.byref(p))
         self._cb = None
@@ -424,7 +456,10 @@ class Sim:
 
     def step_lts_dt(self, dt: float):
         """One LTS macro step with a given level-lmax step dt."""
-        if lib().orc_sim_step_lts_dt(self.h, dt) != 0:
+        rc = lib().orc_sim_step_lts_dt(self.h, dt)
+        if rc == -1:
+            raise ValueError("local time stepping with viscosity is not supported")
+        if rc != 0:
             raise RuntimeError("oracle LTS step failed: non-physical state")
 
     def step_lts(self) -> float:
@@ -432,6 +467,8 @@ class Sim:
         the returned dt (the eq:Cfl step of level lmax), level l stepping 2^(lmax-l) dt."""
         dt = C.c_double(0.0)
         rc = lib().orc_sim_step_lts(self.h, C.byref(dt))
+        if rc == -1:
+            raise ValueError("local time stepping with viscosity is not supported")
         if rc != 0:
             raise RuntimeError(f"oracle LTS step failed ({rc}): non-physical state")
         return dt.value

@@ -113,6 +113,29 @@ double orc_average8(const double c[8]);
  * u^(s+1) = u0 + a_s ((u^(s) - u0) + dt L(u^(s))), a = (1, 1/4, 2/3). */
 double orc_ssprk3_stage(int stage, double u0, double us, double L, double dt);
 
+/* ---------------- viscous terms (Navier-Stokes form of eq:Euler) ------------------- */
+
+/* Viscous flux through the face between two cells along axis d, from the velocities of
+ * the two cells and of their four tangential neighbours: st[s][n][q], s = 0 the cell on
+ * the low side, 1 the cell on the high side; n = 0 the cell itself, 1 / 2 its neighbours
+ * at -1 / +1 along the lower of the two other axes, 3 / 4 along the higher one; q the
+ * conservative state in physical component order.  F = (0, tau_d., tau_d. . v_face) with
+ * the Newtonian stress of Stokes' hypothesis, tau = mu (grad v + grad v^T) - 2/3 mu div v I:
+ * normal derivatives from the two cells, tangential derivatives as the mean of the two
+ * cells' central differences, v_face the mean of the two velocities.  energy = 0 leaves
+ * F[4] zero (Tait's barotropic system).  The face's total flux is the convective flux
+ * minus this one. */
+void orc_visc_face_flux(int d, const double st[50], double mu, int energy, double dx, double F[5]);
+
+/* Explicit time-step bound of the viscous terms: cfl * 3/16 * dx^2 / (mu * max(1/rho)). */
+double orc_visc_dt(double cfl, double dx, double mu, double rinv_max);
+
+/* Linear growth rate n > 0 of the Rayleigh-Taylor instability of two viscous fluids with
+ * equal dynamic viscosity mu (eq:SinglePhaseGrowth): heavy density rho_h on top of rho_l,
+ * gravity g, wavenumber k.  Bisection on n in (0, sqrt(At g k)].  Returns -1 if the
+ * relation has no root there. */
+double orc_rti_growth_rate(double k, double rho_h, double rho_l, double mu, double g);
+
 /* ---------------- exact Riemann solver (textbook, Toro ch. 4) for the Sod pin ------- */
 
 /* Samples the exact solution of the 1D Riemann problem (ideal gas, B = 0) at x/t = s
@@ -131,12 +154,19 @@ typedef struct {
     double dx0;            /* cell size on level 0                             */
     int32_t lmax;          /* finest level                                     */
     int32_t n0[3];         /* level-0 blocks per axis                          */
-    int32_t bc[3];         /* per axis: 0 periodic, 1 zero-gradient            */
+    int32_t bc[3];         /* per axis: 0 periodic, 1 zero-gradient, 2 symmetry,
+                              3 fixed values (bc_fixed)                        */
     int32_t adapt;         /* 1: refine/coarsen after each step                */
     int32_t scheme;        /* flux kernel, see orc_face_flux_scheme            */
     double gravity[3];     /* source term of eq:Euler: S = (0, rho g, rho v.g) */
     int32_t eos;           /* 0 stiffened gas (eq:StiffenedGas), 1 Tait        */
     double tait_A, tait_rho0;   /* Tait: p = B ((rho/rho0)^gamma - 1) + A       */
+    double mu;             /* dynamic viscosity (0: Euler equations)           */
+    /* fixed-value boundaries: primitive states (rho, u, v, w, p) of the halo cells beyond
+     * the sides of the axes with bc 3, [6 sides x-, x+, y-, y+, z-, z+][lmax + 1 levels]
+     * [4 layers, the one at the face first][5], uniform over the boundary plane; copied by
+     * orc_sim_create; NULL when no axis has bc 3 */
+    const double *bc_fixed;
 } orc_params;
 
 typedef struct orc_sim orc_sim;
@@ -161,7 +191,7 @@ int orc_sim_step_dt(orc_sim *s, double dt);
  * algo:Integration): 2^lmax micro steps of dt = the eq:Cfl step of level lmax, level l
  * advancing with 2^(lmax-l) dt; adaptation (if enabled) once, at the end, when every
  * level has reached the same time.  *dt_out = dt; time advances by 2^lmax dt. */
-int orc_sim_step_lts(orc_sim *s, double *dt_out);
+int orc_sim_step_lts(orc_sim *s, double *dt_out);   /* -1: viscous (not supported) */
 int orc_sim_step_lts_dt(orc_sim *s, double dt);
 /* own steps completed per level since creation (ORC_MAX_LEVELS entries) */
 void orc_sim_lts_steps(const orc_sim *s, int64_t *out);

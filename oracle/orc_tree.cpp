@@ -59,6 +59,7 @@ struct orc_sim {
     double time = 0.0;
     double llf_fraction = 0.0;
     int64_t lts_steps[ORC_MAX_LEVELS] = {};  // own steps completed per level (local time stepping)
+    std::vector<double> fixed;   // conservative fixed-value halo states [6][lmax+1][4][5]
     std::unordered_map<uint64_t, Block *> map;
     std::vector<Block *> order;  // blocks sorted by (level, id); rebuilt after edits
     ~orc_sim() {
@@ -248,18 +249,26 @@ void fill_block_halos(orc_sim *s, Block *b, Field fld = &Block::u) {
                                 u[at(q, k, j, i)] = v;
                             }
             }
-    // Zero-gradient boundaries, axis by axis over the full padded extent.
+    // External boundaries, axis by axis over the full padded extent: zero gradient (every
+    // halo layer a copy of the boundary cell), symmetry (the halo the mirror image of the
+    // interior, the momentum normal to the boundary reversed) or fixed values (each halo
+    // layer the given state; the state field only: a flux-divergence field keeps its halo).
     const int c[3] = {b->bx, b->by, b->bz};
     for (int a = 0; a < 3; ++a) {
         if (s->p.bc[a] == 0) continue;
+        const bool mirror = s->p.bc[a] == 2, fixed = s->p.bc[a] == 3;
+        if (fixed && fld != &Block::u) continue;
         const int n = level_extent(s->p, a, b->level);
         for (int side = 0; side < 2; ++side) {
             if (side == 0 && c[a] != 0) continue;
             if (side == 1 && c[a] != n - 1) continue;
-            const int src = side == 0 ? H : H + N - 1;
             for (int q = 0; q < 5; ++q)
                 for (int h = 0; h < H; ++h) {
                     const int dst = side == 0 ? h : H + N + h;
+                    const int src = mirror ? 2 * (side == 0 ? H : H + N) - 1 - dst : (side == 0 ? H : H + N - 1);
+                    const double sign = mirror && q == 1 + a ? -1.0 : 1.0;
+                    const int layer = side == 0 ? H - 1 - h : h;   // 0 at the face
+                    const double fv = fixed ? s->fixed[(((2 * a + side) * (s->p.lmax + 1) + b->level) * 4 + layer) * 5 + q] : 0.0;
                     for (int m = 0; m < P; ++m)
                         for (int r = 0; r < P; ++r) {
                             int is[3], id[3];
@@ -268,7 +277,7 @@ void fill_block_halos(orc_sim *s, Block *b, Field fld = &Block::u) {
                             const int o1 = (a + 1) % 3, o2 = (a + 2) % 3;
                             is[o1] = id[o1] = r;
                             is[o2] = id[o2] = m;
-                            u[at(q, id[2], id[1], id[0])] = u[at(q, is[2], is[1], is[0])];
+                            u[at(q, id[2], id[1], id[0])] = fixed ? fv : sign * u[at(q, is[2], is[1], is[0])];
                         }
                 }
         }
@@ -313,6 +322,22 @@ long block_rhs(const orc_sim *s, Block *b) {
                     n_llf += s->p.eos == 1
                                  ? orc_tait_face_flux(d, st, g, B, s->p.tait_A, s->p.tait_rho0, Fh)
                                  : orc_face_flux_scheme(s->p.scheme, d, st, g, B, Fh);
+                    if (s->p.mu > 0.0) {
+                        // the two cells sharing the face and their tangential neighbours
+                        const int o_lo = d == 0 ? 1 : 0, o_hi = d == 2 ? 1 : 2;
+                        const int dn[5][2] = {{0, 0}, {-1, 0}, {1, 0}, {0, -1}, {0, 1}};
+                        double vs[50], Fv[5];
+                        for (int sd = 0; sd < 2; ++sd)
+                            for (int n = 0; n < 5; ++n) {
+                                int c[3];
+                                c[d] = H + f - 1 + sd;
+                                c[o_lo] = H + r + dn[n][0];
+                                c[o_hi] = H + m + dn[n][1];
+                                for (int q = 0; q < 5; ++q) vs[(sd * 5 + n) * 5 + q] = b->u[at(q, c[2], c[1], c[0])];
+                            }
+                        orc_visc_face_flux(d, vs, s->p.mu, s->p.eos == 0, dx, Fv);
+                        for (int q = 0; q < 5; ++q) Fh[q] -= Fv[q];
+                    }
                     for (int q = 0; q < 5; ++q) F[fidx(d, q, m, r, f)] = Fh[q];
                 }
     b->rhs.assign(5 * ICELLS, 0.0);
@@ -591,26 +616,33 @@ void for_face_slab(int side, Fn fn) {
             }
 }
 
-// State halos of a leaf that are copies (same-level neighbour) or a zero-gradient
-// boundary; faces at resolution jumps keep their integrated values.
+// State halos of a leaf that are copies (same-level neighbour) or an external boundary
+// (zero gradient, symmetry, fixed values, as in fill_block_halos); faces at resolution
+// jumps keep their integrated values.
 void fill_present_faces(orc_sim *s, Block *b) {
     for (int side = 0; side < 6; ++side) {
         Block *nb = nullptr;
         const FaceKind kind = face_kind(s, b, side, &nb);
         if (kind == FACE_JUMP) continue;
-        const int d = side >> 1;
+        const int d = side >> 1, hi = side & 1, bc = s->p.bc[d];
         int off[3] = {0, 0, 0};
-        off[d] = (side & 1) ? 1 : -1;
-        const int src = (side & 1) ? H + N - 1 : H;
+        off[d] = hi ? 1 : -1;
         for (int q = 0; q < 5; ++q)
             for_face_slab(side, [&](int k, int j, int i) {
                 if (kind == FACE_PRESENT) {
                     b->u[at(q, k, j, i)] = nb->u[at(q, k - N * off[2], j - N * off[1], i - N * off[0])];
-                } else {
-                    int c[3] = {i, j, k};
-                    c[d] = src;
-                    b->u[at(q, k, j, i)] = b->u[at(q, c[2], c[1], c[0])];
+                    return;
                 }
+                int c[3] = {i, j, k};
+                const int dst = c[d];
+                if (bc == 3) {
+                    const int layer = hi ? dst - (H + N) : H - 1 - dst;
+                    b->u[at(q, k, j, i)] = s->fixed[((side * (s->p.lmax + 1) + b->level) * 4 + layer) * 5 + q];
+                    return;
+                }
+                c[d] = bc == 2 ? 2 * (hi ? H + N : H) - 1 - dst : (hi ? H + N - 1 : H);
+                const double sign = bc == 2 && q == 1 + d ? -1.0 : 1.0;
+                b->u[at(q, k, j, i)] = sign * b->u[at(q, c[2], c[1], c[0])];
             });
     }
 }
@@ -764,6 +796,21 @@ extern "C" {
 orc_sim *orc_sim_create(const orc_params *p) {
     orc_sim *s = new orc_sim();
     s->p = *p;
+    s->p.bc_fixed = nullptr;
+    if (p->bc_fixed) {
+        // stored conservative, converted with the EOS like the initial condition
+        const int nl = p->lmax + 1;
+        s->fixed.assign((size_t)6 * nl * 4 * 5, 0.0);
+        const double g = p->gamma, B = p->B;
+        for (int n = 0; n < 6 * nl * 4; ++n) {
+            const double *w = p->bc_fixed + 5 * n;
+            double *u = s->fixed.data() + 5 * n;
+            u[0] = w[0];
+            for (int a = 0; a < 3; ++a) u[1 + a] = w[0] * w[1 + a];
+            u[4] = p->eos == 1 ? 0.0
+                               : (w[4] + g * B) / (g - 1.0) + 0.5 * w[0] * (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]);
+        }
+    }
     int mx = std::max(p->n0[0], std::max(p->n0[1], p->n0[2]));
     while ((1 << s->shadow) < mx) ++s->shadow;
     return s;
@@ -829,7 +876,18 @@ double orc_sim_dt(const orc_sim *s) {
     // eq:Cfl sums the three directional maxima; they are added in ascending order so that
     // dt does not depend on which axis is called x (a rotated problem gets the same dt)
     std::sort(mx, mx + 3);
-    return s->p.cfl * dx_level(s->p, s->p.lmax) / ((mx[0] + mx[1]) + mx[2]);
+    const double dx = dx_level(s->p, s->p.lmax);
+    const double dt = s->p.cfl * dx / ((mx[0] + mx[1]) + mx[2]);
+    if (!(s->p.mu > 0.0)) return dt;
+    // with viscosity, also the explicit bound of the viscous terms at the smallest density
+    double rinv = 0.0;
+    for (const Block *b : s->order) {
+        if (!b->leaf) continue;
+        for (int k = H; k < H + N; ++k)
+            for (int j = H; j < H + N; ++j)
+                for (int i = H; i < H + N; ++i) rinv = std::max(rinv, 1.0 / b->u[at(0, k, j, i)]);
+    }
+    return std::min(dt, orc_visc_dt(s->p.cfl, dx, s->p.mu, rinv));
 }
 
 double orc_ssprk3_stage(int stage, double u0, double us, double L, double dt) {
@@ -891,6 +949,8 @@ int orc_sim_step_lts(orc_sim *s, double *dt_out) {
 }
 
 int orc_sim_step_lts_dt(orc_sim *s, double dt) {
+    // the viscous fluxes read edge halos, which the local time stepping here does not keep
+    if (s->p.mu > 0.0) return -1;
     const int rc = lts_macro_step(s, dt);
     if (rc) return rc;
     s->time += std::ldexp(dt, s->p.lmax);

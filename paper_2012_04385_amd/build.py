@@ -8,7 +8,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmrfv.so")
 SOURCES = ["abi.cpp", "topology.cpp", "mlp.cpp", "kernels_mr.hip", "kernels_rhs.hip", "kernels_mlp.hip",
-           "kernels_lts.hip"]
+           "kernels_lts.hip", "kernels_visc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 instructions are switched off: hipcc emits them from plain float code.
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

@@ -46,6 +46,7 @@ int check_instance(mrfv_ctx *ctx, const mrfv_instance &p, int i) {
     for (int a = 0; a < 3; ++a)
         if (!std::isfinite(p.gravity[a])) return fail(ctx, MRFV_EINVAL, w + "gravity must be finite");
     if (p.lmax < 0 || p.lmax > 12) return fail(ctx, MRFV_EINVAL, w + "lmax must be in [0,12]");
+    if (!(p.mu >= 0.0) || !std::isfinite(p.mu)) return fail(ctx, MRFV_EINVAL, w + "mu must be finite and >= 0");
     if (p.eos != MRFV_STIFFENED_GAS && p.eos != MRFV_TAIT)
         return fail(ctx, MRFV_EINVAL, w + "eos must be 0 (stiffened gas) or 1 (Tait)");
     if (p.eos == MRFV_TAIT) {
@@ -57,8 +58,18 @@ int check_instance(mrfv_ctx *ctx, const mrfv_instance &p, int i) {
     for (int a = 0; a < 3; ++a) {
         if (p.n0[a] < 1 || ((int64_t)p.n0[a] << p.lmax) > 65535)
             return fail(ctx, MRFV_EINVAL, w + "n0 out of range");
-        if (p.bc[a] != MRFV_BC_PERIODIC && p.bc[a] != MRFV_BC_ZEROGRAD)
-            return fail(ctx, MRFV_EINVAL, w + "bc must be 0 or 1");
+        if (p.bc[a] < MRFV_BC_PERIODIC || p.bc[a] > MRFV_BC_FIXED)
+            return fail(ctx, MRFV_EINVAL, w + "bc must be 0, 1, 2 or 3");
+        if (p.bc[a] == MRFV_BC_FIXED) {
+            if (!p.bc_fixed) return fail(ctx, MRFV_EINVAL, w + "fixed-value boundary without bc_fixed");
+            for (int sd = 0; sd < 2; ++sd)
+                for (int n = 0; n < (p.lmax + 1) * 4; ++n) {
+                    const double *v = p.bc_fixed + ((size_t)(2 * a + sd) * (p.lmax + 1) * 4 + n) * 5;
+                    bool ok = v[0] > 0.0;
+                    for (int q = 0; q < 5; ++q) ok = ok && std::isfinite(v[q]);
+                    if (!ok) return fail(ctx, MRFV_EINVAL, w + "bc_fixed: needs finite states with rho > 0");
+                }
+        }
     }
     return MRFV_OK;
 }
@@ -242,11 +253,27 @@ int do_flux(mrfv_ctx *ctx, const T *U) {
                                   ctx->stream));
     }
     timing_end(ctx, ev, (int64_t)L.all_leaves_cnt * CELLS_I);
+    // viscous terms: subtracted from the differences and face planes before the jump
+    // correction averages the (total) fine fluxes
+    if (ctx->viscous)
+        HIP_OK(launch_visc<T>(U, wlist(ctx, DESC_LEAVES), ctx->tb, ctx->d_inst, D, FF, ctx->stream));
     if (ctx->has_jumps) {
         for (int l = L.max_level - 1; l >= 0; --l)
             HIP_OK(launch_ff_restrict<T>(FF, wlist(ctx, desc_par(l)), ctx->tb, ctx->stream));
         HIP_OK(launch_reflux<T>(D, FF, wlist(ctx, DESC_LEAVES), ctx->tb, ctx->stream));
     }
+    return MRFV_OK;
+}
+
+// CFL time step of eq:Cfl per instance and, for viscous instances, the viscous bound.
+template <typename T>
+int do_cfl(mrfv_ctx *ctx, const T *U, double *dt) {
+    const WorkList lv = wlist(ctx, DESC_LEAVES);
+    HIP_OK(launch_cfl<T>(U, lv, ctx->tb, ctx->d_inst, (int)ctx->inst.size(), ctx->d_blockred, dt,
+                         ctx->stream));
+    if (ctx->viscous)
+        HIP_OK(launch_visc_dt<T>(U, lv, ctx->tb, ctx->d_inst, (int)ctx->inst.size(), ctx->d_viscred, dt,
+                                 ctx->stream));
     return MRFV_OK;
 }
 
@@ -554,8 +581,7 @@ int do_stages(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt) {
         HIP_OK(launch_cfl<T>(U, lv, ctx->tb, ctx->d_inst, (int)ctx->inst.size(), ctx->d_blockred,
                              dt, ctx->stream, ctx->d_gate, ctx->d_desc, ctx->d_desc_g, N_DESC));
     } else {
-        HIP_OK(launch_cfl<T>(U, wlist(ctx, DESC_LEAVES), ctx->tb, ctx->d_inst, (int)ctx->inst.size(),
-                             ctx->d_blockred, dt, ctx->stream));
+        CALL(do_cfl<T>(ctx, U, dt));
     }
     if (ctx->cfg.batched && sizeof(T) == 4) {
         // fused stages, out of place through two more state buffers: U -> W -> W2 -> U;
@@ -586,9 +612,11 @@ int do_stages(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt) {
         }
         return MRFV_OK;
     }
+    // the viscous fluxes read the edge halos too
+    const int fill = ctx->viscous ? FILL_ALL : FILL_FACES;
     for (int s = 0; s < 3; ++s) {
         CALL(do_project<T>(ctx, U));
-        CALL(do_fill<T>(ctx, U, 1 << 20, FILL_FACES));
+        CALL(do_fill<T>(ctx, U, 1 << 20, fill));
         CALL(do_rhs<T>(ctx, U, Lb));
         CALL(do_update<T>(ctx, s, dt, U, U0, Lb));
     }
@@ -1034,6 +1062,11 @@ int mrfv_create(mrfv_ctx **out, const mrfv_config *cfg, const mrfv_instance *ins
         ctx->err = "Tait's equation runs on the plain kernels with the Roe-WENO5 flux";
         return bail(MRFV_EINVAL);
     }
+    for (int i = 0; i < cfg->n_instances; ++i) ctx->viscous = ctx->viscous || inst[i].mu > 0.0;
+    if (ctx->viscous && cfg->batched && cfg->dtype == MRFV_F32) {
+        ctx->err = "the viscous terms run on the plain kernels, not on the fused FP32 path";
+        return bail(MRFV_EINVAL);
+    }
     ctx->stream = (hipStream_t)hip_stream;
     if (hipGetDevice(&ctx->device) != hipSuccess ||
         static_totals_scratch(ctx->device, &ctx->d_static_totals) != hipSuccess) {
@@ -1056,7 +1089,7 @@ int mrfv_create(mrfv_ctx **out, const mrfv_config *cfg, const mrfv_instance *ins
                         {p.n0[0], p.n0[1], p.n0[2]}, {p.bc[0], p.bc[1], p.bc[2]}, p.adapt,
                         DETAIL_BAND_DEFAULT, {p.gravity[0], p.gravity[1], p.gravity[2]},
                         (p.gravity[0] != 0.0 || p.gravity[1] != 0.0 || p.gravity[2] != 0.0) ? 1 : 0,
-                        p.eos, p.tait_A, p.tait_rho0};
+                        p.eos, p.tait_A, p.tait_rho0, p.mu};
     }
 #define ALLOC(ptr, bytes)                                                                  \
     if (hipMalloc((void **)&(ptr), (bytes)) != hipSuccess) {                                \
@@ -1064,6 +1097,41 @@ int mrfv_create(mrfv_ctx **out, const mrfv_config *cfg, const mrfv_instance *ins
         return bail(MRFV_ENOMEM);                                                          \
     }
     ALLOC(ctx->d_inst, sizeof(InstDev) * id.size());
+    {
+        // fixed-value halo states, conservative in the context dtype
+        bool any = false;
+        for (int i = 0; i < cfg->n_instances; ++i)
+            for (int a = 0; a < 3; ++a) any = any || inst[i].bc[a] == MRFV_BC_FIXED;
+        if (any) {
+            const size_t per = (size_t)6 * MAX_LEVELS * 4 * 5;
+            std::vector<double> h(per * cfg->n_instances, 0.0);
+            for (int i = 0; i < cfg->n_instances; ++i) {
+                const mrfv_instance &p = inst[i];
+                for (int a = 0; a < 3; ++a) {
+                    if (p.bc[a] != MRFV_BC_FIXED) continue;
+                    for (int sd = 0; sd < 2; ++sd)
+                        for (int l = 0; l <= p.lmax; ++l)
+                            for (int ly = 0; ly < 4; ++ly) {
+                                const double *w = p.bc_fixed + (((size_t)(2 * a + sd) * (p.lmax + 1) + l) * 4 + ly) * 5;
+                                double *u = h.data() + per * i + (((size_t)(2 * a + sd) * MAX_LEVELS + l) * 4 + ly) * 5;
+                                u[0] = w[0];
+                                for (int c = 0; c < 3; ++c) u[1 + c] = w[0] * w[1 + c];
+                                u[4] = p.eos == MRFV_TAIT ? 0.0
+                                                          : (w[4] + p.gamma * p.B) / (p.gamma - 1.0) +
+                                                                0.5 * w[0] * (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]);
+                            }
+                }
+            }
+            ALLOC(ctx->d_bcfix, h.size() * es);
+            std::vector<float> f(h.begin(), h.end());
+            const void *src = es == sizeof(double) ? (const void *)h.data() : (const void *)f.data();
+            if (hipMemcpy(ctx->d_bcfix, src, h.size() * es, hipMemcpyHostToDevice) != hipSuccess) {
+                ctx->err = "hipMemcpy of the fixed-value boundary states failed";
+                return bail(MRFV_EHIP);
+            }
+            ctx->tb.bcfix = ctx->tb2.bcfix = ctx->d_bcfix;
+        }
+    }
     ALLOC(ctx->d_err, sizeof(int32_t));
     if (!(cfg->batched && cfg->dtype == MRFV_F32)) {
         ALLOC(ctx->d_D, cap * 3 * 5 * CELLS_I * es);
@@ -1083,6 +1151,7 @@ int mrfv_create(mrfv_ctx **out, const mrfv_config *cfg, const mrfv_instance *ins
     ctx->h_err[0] = ctx->h_err[1] = 0;
     ALLOC(ctx->d_FF, cap * 6 * 5 * FACE * es);
     ALLOC(ctx->d_blockred, cap * std::max(5, 3 * cfl_slabs()) * sizeof(double));
+    if (ctx->viscous) ALLOC(ctx->d_viscred, cap * sizeof(double));
     ALLOC(ctx->d_det, cap * sizeof(double));
     ALLOC(ctx->d_det4, cap * details_parts() * sizeof(double));
     ALLOC(ctx->d_recheck, (2 + cap * details_parts()) * sizeof(int32_t));
@@ -1128,7 +1197,7 @@ int mrfv_destroy(mrfv_ctx *ctx) {
             if (p) hipFree(p);
     }
     void *ptrs[] = {ctx->d_inst, ctx->d_err, ctx->d_D, ctx->d_W, ctx->d_W2, ctx->d_FF, ctx->d_Fp, ctx->d_H0, ctx->d_ACC,
-                    ctx->d_blockred, ctx->d_det, ctx->d_det4,
+                    ctx->d_blockred, ctx->d_viscred, ctx->d_bcfix, ctx->d_det, ctx->d_det4,
                     ctx->d_recheck, ctx->d_flags, ctx->d_slots, ctx->d_slots2, ctx->d_prim, ctx->tb.meta, ctx->tb.child,
                     ctx->tb.nbr, ctx->tb.lists, ctx->d_desc, ctx->d_desc_g, ctx->d_gate};
     for (void *p : ptrs)
@@ -1224,12 +1293,8 @@ int mrfv_cfl_dt(mrfv_ctx *ctx, const void *U, double *dt_dev) {
     CALL(need_init(ctx));
     if (!U || !dt_dev) return fail(ctx, MRFV_EINVAL, "cfl_dt: null pointer");
     if (ctx->cfg.dtype == MRFV_F64)
-        HIP_OK(launch_cfl<double>((const double *)U, wlist(ctx, DESC_LEAVES), ctx->tb, ctx->d_inst,
-                                  (int)ctx->inst.size(), ctx->d_blockred, dt_dev, ctx->stream));
-    else
-        HIP_OK(launch_cfl<float>((const float *)U, wlist(ctx, DESC_LEAVES), ctx->tb, ctx->d_inst,
-                                 (int)ctx->inst.size(), ctx->d_blockred, dt_dev, ctx->stream));
-    return MRFV_OK;
+        return do_cfl<double>(ctx, (const double *)U, dt_dev);
+    return do_cfl<float>(ctx, (const float *)U, dt_dev);
 }
 
 int mrfv_totals(mrfv_ctx *ctx, const void *U, double *tot_dev) {
@@ -1289,6 +1354,7 @@ int mrfv_step_lts(mrfv_ctx *ctx, void *U, void *U0, void *L, double *dt_dev,
                   int64_t *cell_updates_host) {
     CALL(need_init(ctx));
     if (!U || !U0 || !dt_dev) return fail(ctx, MRFV_EINVAL, "step_lts: null pointer");
+    if (ctx->viscous) return fail(ctx, MRFV_EINVAL, "step_lts: the viscous terms run with the global step only");
     for (const auto &p : ctx->inst)
         if (p.lmax != ctx->inst[0].lmax)
             return fail(ctx, MRFV_EINVAL, "step_lts: every instance needs the same lmax");

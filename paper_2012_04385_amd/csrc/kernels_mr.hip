@@ -91,12 +91,18 @@ __global__ __launch_bounds__(TPB) void k_prim2cons(const double *__restrict__ pr
 // Halo regions.  Region (rx, ry, rz) in {-1, 0, 1}^3 \ {0} covers padded indices
 // [0, 4) / [4, 20) / [20, 24) along each axis; in the face modes only the 3 layers the
 // flux stencils read ([1, 4) and [20, 23)).  One workgroup per (block, region): a region
-// is either copied from the same-level neighbour's interior, clamped (zero-gradient
-// boundary) or predicted from the parent, never a mix.
+// is either copied from the same-level neighbour's interior, clamped at an external
+// boundary or predicted from the parent, never a mix.  On a clamped axis the region's
+// cells take their values from the block's own cells along that axis: all from the
+// boundary cell (zero gradient), or each from its mirror image across the boundary face
+// (symmetry, padded index mir - i, with the momentum normal to the boundary reversed).
 struct Region {
-    int r[3];       // region direction after zero-gradient clamping (0 on clamped axes)
+    int r[3];       // region direction after clamping (0 on clamped axes)
     int lo[3], n[3];
     int clamp[3];   // -1, or the padded index every cell of the axis copies/predicts from
+    int mir[3];     // 0, or (symmetry boundary) cell i of the axis takes index mir - i
+    int fix;        // -1, or 4 * side + axis of the last axis (x, y, z order) whose
+                    // boundary has fixed values: the region then holds those values
 };
 
 __device__ __forceinline__ Region make_region(int mode, int ridx, int zg) {
@@ -117,9 +123,24 @@ __device__ __forceinline__ Region make_region(int mode, int ridx, int zg) {
         g.lo[a] = r[a] < 0 ? (faces ? 1 : 0) : (r[a] == 0 ? HW : HW + NI);
         g.n[a] = r[a] == 0 ? NI : (faces ? 3 : HW);
         g.clamp[a] = -1;
+        g.mir[a] = 0;
         g.r[a] = r[a];
-        if (r[a] < 0 && (zg & (1 << (2 * a)))) { g.clamp[a] = HW; g.r[a] = 0; }
-        if (r[a] > 0 && (zg & (1 << (2 * a + 1)))) { g.clamp[a] = HW + NI - 1; g.r[a] = 0; }
+        if (r[a] < 0 && (zg & (1 << (2 * a)))) {
+            g.clamp[a] = HW;
+            g.r[a] = 0;
+            if (zg & (64 << (2 * a))) g.mir[a] = 2 * HW - 1;
+        }
+        if (r[a] > 0 && (zg & (1 << (2 * a + 1)))) {
+            g.clamp[a] = HW + NI - 1;
+            g.r[a] = 0;
+            if (zg & (64 << (2 * a + 1))) g.mir[a] = 2 * (HW + NI) - 1;
+        }
+    }
+    g.fix = -1;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (r[a] < 0 && (zg & (4096 << (2 * a)))) g.fix = a;
+        if (r[a] > 0 && (zg & (4096 << (2 * a + 1)))) g.fix = 4 + a;
     }
     return g;
 }
@@ -146,7 +167,8 @@ constexpr int PR_A = 6 * 12 * 12, PR_X = 16 * 12 * 6, PR_Y = 16 * 16 * 6;
 template <typename T>
 __global__ __launch_bounds__(TPB) void k_fill_halos(T *__restrict__ U, WorkList wl,
                                                     const BlockMeta *__restrict__ meta,
-                                                    const int32_t *__restrict__ nbr, int mode) {
+                                                    const int32_t *__restrict__ nbr, int mode,
+                                                    const T *__restrict__ bcfix) {
     __shared__ T A[PR_A];
     __shared__ T X[PR_X];
     __shared__ T Y[PR_Y];
@@ -160,6 +182,30 @@ __global__ __launch_bounds__(TPB) void k_fill_halos(T *__restrict__ U, WorkList 
         const int slot = wl.at(base + bi);
         const BlockMeta m = meta[slot];
         const Region g = make_region(mode, blockIdx.y, m.zg);
+        if (g.fix >= 0) {
+            // fixed values: the state of the layer (distance from the face) along the last
+            // fixed axis, with the normal momentum of later symmetry axes reversed
+            if (!bcfix) continue;
+            const int fa = g.fix & 3, fhi = g.fix >> 2;
+            const T *fv = bcfix + ((size_t)(m.inst * 6 + 2 * fa + fhi) * MAX_LEVELS + m.level) * 4 * 5;
+            T *dst = U + (size_t)slot * 5 * CELLS_P;
+            const int ncell = g.n[0] * g.n[1] * g.n[2];
+            const Div d0(g.n[0]), d1(g.n[1]);
+            const bool re = (mode & FILL_RHO_E) != 0;
+            for (int e = tid; e < ncell; e += TPB) {
+                const int e1 = d0.quot(e), e2 = d1.quot(e1);
+                int c[3] = {g.lo[0] + e - e1 * g.n[0], g.lo[1] + e1 - e2 * g.n[1], g.lo[2] + e2};
+                const int layer = fhi ? c[fa] - (HW + NI) : HW - 1 - c[fa];
+#pragma unroll
+                for (int q = 0; q < 5; ++q) {
+                    if (re && q != 0 && q != 4) continue;
+                    const bool flip = q >= 1 && q <= 3 && q - 1 > fa && g.mir[q - 1];
+                    const T v = fv[layer * 5 + q];
+                    dst[pidx(q, c[2], c[1], c[0])] = flip ? -v : v;
+                }
+            }
+            continue;
+        }
         const bool clamped = g.clamp[0] >= 0 || g.clamp[1] >= 0 || g.clamp[2] >= 0;
         const bool own = g.r[0] == 0 && g.r[1] == 0 && g.r[2] == 0;
         const int src = own ? slot : nbr[(size_t)slot * 27 + (g.r[2] + 1) * 9 + (g.r[1] + 1) * 3 + (g.r[0] + 1)];
@@ -170,6 +216,11 @@ __global__ __launch_bounds__(TPB) void k_fill_halos(T *__restrict__ U, WorkList 
         const Div dc(ncell), d0(g.n[0]), d1(g.n[1]);
         const bool re = (mode & FILL_RHO_E) != 0;
         const int nq = re ? 2 : 5;
+        // symmetry: the momentum component normal to a mirrored boundary changes sign
+        // (mirrored on two axes: both components)
+        auto msign = [&](int q) {
+            return (q >= 1 && q <= 3 && g.mir[q - 1]) ? (T)-1 : (T)1;
+        };
         if (src >= 0) {
             const T *sb = U + (size_t)src * 5 * CELLS_P;
 #pragma unroll 4
@@ -178,10 +229,10 @@ __global__ __launch_bounds__(TPB) void k_fill_halos(T *__restrict__ U, WorkList 
                 const int q = re ? 4 * qi : qi;
                 const int e1 = d0.quot(e), e2 = d1.quot(e1);
                 const int i = g.lo[0] + e - e1 * g.n[0], j = g.lo[1] + e1 - e2 * g.n[1], k = g.lo[2] + e2;
-                const int si = g.clamp[0] >= 0 ? g.clamp[0] : i - NI * g.r[0];
-                const int sj = g.clamp[1] >= 0 ? g.clamp[1] : j - NI * g.r[1];
-                const int sk = g.clamp[2] >= 0 ? g.clamp[2] : k - NI * g.r[2];
-                dst[pidx(q, k, j, i)] = sb[pidx(q, sk, sj, si)];
+                const int si = g.mir[0] ? g.mir[0] - i : (g.clamp[0] >= 0 ? g.clamp[0] : i - NI * g.r[0]);
+                const int sj = g.mir[1] ? g.mir[1] - j : (g.clamp[1] >= 0 ? g.clamp[1] : j - NI * g.r[1]);
+                const int sk = g.mir[2] ? g.mir[2] - k : (g.clamp[2] >= 0 ? g.clamp[2] : k - NI * g.r[2]);
+                dst[pidx(q, k, j, i)] = msign(q) * sb[pidx(q, sk, sj, si)];
             }
             continue;
         }
@@ -192,8 +243,10 @@ __global__ __launch_bounds__(TPB) void k_fill_halos(T *__restrict__ U, WorkList 
         int me[3], c0[3], p0[3], np[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            me[a] = g.clamp[a] >= 0 ? 1 : g.n[a];                  // evaluation points
-            c0[a] = g.clamp[a] >= 0 ? g.clamp[a] : g.lo[a];        // first child index
+            // evaluation points and the first child index: the boundary cell (zero
+            // gradient), the mirror images of the region's cells (symmetry), or the region
+            me[a] = g.mir[a] ? g.n[a] : (g.clamp[a] >= 0 ? 1 : g.n[a]);
+            c0[a] = g.mir[a] ? g.mir[a] - (g.lo[a] + g.n[a] - 1) : (g.clamp[a] >= 0 ? g.clamp[a] : g.lo[a]);
             p0[a] = parent_of(c0[a], o[a]) - 2;
             np[a] = parent_of(c0[a] + me[a] - 1, o[a]) + 2 - p0[a] + 1;
         }
@@ -251,15 +304,17 @@ __global__ __launch_bounds__(TPB) void k_fill_halos(T *__restrict__ U, WorkList 
             for (int t = tid; t < ncell; t += TPB) {
                 const int t1 = d0.quot(t), dz = d1.quot(t1);
                 const int dx = t - t1 * g.n[0], dy = t1 - dz * g.n[1];
-                const int ex = g.clamp[0] >= 0 ? 0 : dx, ey = g.clamp[1] >= 0 ? 0 : dy,
-                          ez = g.clamp[2] >= 0 ? 0 : dz;
+                // evaluation point of the cell: its mirror image runs backwards
+                const int ex = g.mir[0] ? g.n[0] - 1 - dx : (g.clamp[0] >= 0 ? 0 : dx);
+                const int ey = g.mir[1] ? g.n[1] - 1 - dy : (g.clamp[1] >= 0 ? 0 : dy);
+                const int ez = g.mir[2] ? g.n[2] - 1 - dz : (g.clamp[2] >= 0 ? 0 : dz);
                 const int c = c0[2] + ez;
                 const int K = parent_of(c, o[2]) - p0[2];
                 const int st = me[0] * me[1];
                 const T *col = Y + (K * me[1] + ey) * me[0] + ex;
                 const T sz = ((c - HW) & 1) ? (T)-1 : (T)1;
                 dst[pidx(q, g.lo[2] + dz, g.lo[1] + dy, g.lo[0] + dx)] =
-                    pred1<T>(col[-2 * st], col[-st], col[0], col[st], col[2 * st], sz);
+                    msign(q) * pred1<T>(col[-2 * st], col[-st], col[0], col[st], col[2 * st], sz);
             }
             __syncthreads();
         }
@@ -868,7 +923,7 @@ hipError_t launch_fill_halos(T *U, const WorkList &wl, const DevTables &tb, Fill
                              hipStream_t st) {
     if (wl.grid <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_halos<T>, grid2(round_xcd(wl.grid), (mode & FILL_FACES) ? 6 : 26), dim3(TPB), 0,
-                       st, U, wl, tb.meta, tb.nbr, (int)mode);
+                       st, U, wl, tb.meta, tb.nbr, (int)mode, (const T *)tb.bcfix);
     return hipGetLastError();
 }
 

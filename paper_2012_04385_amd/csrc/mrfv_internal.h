@@ -24,7 +24,9 @@ struct BlockMeta {
     int32_t inst, level, bx, by, bz;
     int32_t parent;   // parent slot, -1 on level 0
     int32_t leaf;     // 1 = leaf
-    int32_t zg;       // bit (2*axis + side): block touches a zero-gradient boundary there
+    int32_t zg;       // bit (2*axis + side): block touches a non-periodic boundary there;
+                      // bit (6 + 2*axis + side): that boundary is a symmetry plane;
+                      // bit (12 + 2*axis + side): it has fixed values
     int32_t srestr;   // 1: leaf on level >= 1 without a non-leaf same-level face neighbour
                       // (no jump correction): the fused stage writes its restriction into
                       // the parent's octant
@@ -40,6 +42,7 @@ struct InstDev {
     int32_t has_source;   // gravity is not the zero vector
     int32_t eos;          // 0 stiffened gas, 1 Tait (p = B ((rho/rho0)^gamma - 1) + A)
     double tait_A, tait_rho0;
+    double mu;            // dynamic viscosity (0: no viscous terms)
 };
 constexpr double DETAIL_BAND_DEFAULT = 1e-9;
 
@@ -49,6 +52,8 @@ struct DevTables {
     int32_t *child = nullptr;    // [cap][8], -1 when absent
     int32_t *nbr = nullptr;      // [cap][27] same-level neighbour slot; -1 absent, -2 outside
     int32_t *lists = nullptr;    // concatenated work lists (see HostLists)
+    const void *bcfix = nullptr; // fixed-value halo states (context dtype, conservative):
+                                 // [inst][6 sides][MAX_LEVELS][4 layers][5]; null if none
 };
 
 // A work list of block slots.  Eager launches pass the offset and count from the host;
@@ -258,6 +263,17 @@ hipError_t static_totals_scratch(int device, double **ptr);
 template <typename T>
 hipError_t launch_cfl_blocks(const T *U, const WorkList &wl, const DevTables &tb,
                              const InstDev *inst, double *blockmax, hipStream_t st);
+// Viscous terms (kernels_visc.hip): the viscous flux subtracted from the plain flux
+// kernel's differences D and face planes FF of the listed leaves, and the viscous bound on
+// the time step (dt[inst] = min(dt[inst], cfl 3/16 dx_lmax^2 / (mu max 1/rho))) for the
+// instances with mu > 0; blockmax: one double per leaf.
+template <typename T>
+hipError_t launch_visc(const T *U, const WorkList &wl, const DevTables &tb, const InstDev *inst,
+                       T *D, T *FF, hipStream_t st);
+template <typename T>
+hipError_t launch_visc_dt(const T *U, const WorkList &leaves, const DevTables &tb,
+                          const InstDev *inst, int n_inst, double *blockmax, double *dt,
+                          hipStream_t st);
 template <typename T>
 hipError_t launch_totals(const T *U, const WorkList &leaves, const DevTables &tb,
                          const InstDev *inst, int n_inst, double *blocksum, double *tot,
@@ -345,6 +361,8 @@ struct mrfv_ctx {
     void *d_FF = nullptr;              // boundary face fluxes [cap][6][5][16][16]
     void *d_Fp = nullptr, *d_H0 = nullptr, *d_ACC = nullptr;   // local time stepping, on first use
     double *d_blockred = nullptr;      // [cap][5] per-block partial reductions
+    double *d_viscred = nullptr;       // [cap] per-leaf max 1/rho (viscous contexts)
+    void *d_bcfix = nullptr;           // fixed-value halo states (see DevTables::bcfix)
     double *d_det = nullptr;           // [cap]
     double *d_det4 = nullptr;          // [cap][details_parts()] slab maxima of the details
     int32_t *d_recheck = nullptr;      // [2 + cap * details_parts()]: count, done count, list of
@@ -396,6 +414,7 @@ struct mrfv_ctx {
     int lists_cap = 0;
     // kernel timing
     bool has_jumps = false;            // some leaf has a non-leaf same-level face neighbour
+    bool viscous = false;              // some instance has mu > 0 (plain path only)
     bool capturing = false;            // recording a step graph
     // step graphs: the CFL pass takes the block maxima the previous step wrote after its
     // last stage (set by mrfv_run for a step that follows a step on the same tree)

@@ -211,9 +211,11 @@ void Topology::build(std::vector<BlockMeta> &meta, std::vector<int32_t> &child,
         const int c[3] = {b.bx, b.by, b.bz};
         for (int a = 0; a < 3; ++a) {
             const int n = p.n0[a] << b.level;
-            if (p.bc[a] == MRFV_BC_ZEROGRAD) {
-                if (c[a] == 0) m.zg |= 1 << (2 * a);
-                if (c[a] == n - 1) m.zg |= 1 << (2 * a + 1);
+            if (p.bc[a] != MRFV_BC_PERIODIC) {
+                // boundary bit, plus bit 6 + side (mirror) or 12 + side (fixed values)
+                const int mir = p.bc[a] == MRFV_BC_SYMMETRY ? 65 : (p.bc[a] == MRFV_BC_FIXED ? 4097 : 1);
+                if (c[a] == 0) m.zg |= mir << (2 * a);
+                if (c[a] == n - 1) m.zg |= mir << (2 * a + 1);
             }
         }
         meta[s] = m;
@@ -228,7 +230,7 @@ void Topology::build(std::vector<BlockMeta> &meta, std::vector<int32_t> &child,
                         const int n = p.n0[a] << b.level;
                         int v = c[a] + d[a];
                         if (v < 0 || v >= n) {
-                            if (p.bc[a] == MRFV_BC_ZEROGRAD) outside = true;
+                            if (p.bc[a] != MRFV_BC_PERIODIC) outside = true;
                             v = (v + n) % n;
                         }
                         q[a] = v;

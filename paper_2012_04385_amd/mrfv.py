@@ -31,7 +31,8 @@ class Instance(C.Structure):
                 ("eps", C.c_double), ("scale_rho", C.c_double), ("scale_E", C.c_double),
                 ("dx0", C.c_double), ("lmax", C.c_int32), ("n0", C.c_int32 * 3),
                 ("bc", C.c_int32 * 3), ("adapt", C.c_int32), ("gravity", C.c_double * 3),
-                ("eos", C.c_int32), ("tait_A", C.c_double), ("tait_rho0", C.c_double)]
+                ("eos", C.c_int32), ("tait_A", C.c_double), ("tait_rho0", C.c_double),
+                ("mu", C.c_double), ("bc_fixed", C.POINTER(C.c_double))]
 
 
 class Config(C.Structure):
@@ -143,7 +144,9 @@ def morton_neighbor(mid: int, shadow: int, d: int, direction: int):
     return int(n), bool(w.value)
 
 
-def _instance(pb) -> Instance:
+def _instance(pb, keep: list) -> Instance:
+    """The ABI struct of a problem; arrays it points to are appended to `keep` (they must
+    outlive mrfv_create)."""
     inst = Instance()
     inst.gamma, inst.B, inst.cfl, inst.eps = pb.gamma, pb.B, pb.cfl, pb.eps
     inst.scale_rho, inst.scale_E, inst.dx0 = pb.scale_rho, pb.scale_E, pb.dx0
@@ -157,6 +160,12 @@ def _instance(pb) -> Instance:
     inst.eos = EOS[getattr(pb, "eos", "stiffened")]
     inst.tait_A = getattr(pb, "tait_A", 1.0)
     inst.tait_rho0 = getattr(pb, "tait_rho0", 1.0)
+    inst.mu = getattr(pb, "mu", 0.0)
+    fixed = pb.bc_fixed_states() if hasattr(pb, "bc_fixed_states") else None
+    if fixed is not None:
+        fixed = np.ascontiguousarray(fixed, dtype=np.float64)
+        keep.append(fixed)
+        inst.bc_fixed = fixed.ctypes.data_as(C.POINTER(C.c_double))
     return inst
 
 
@@ -185,8 +194,9 @@ class Solver:
         cap = capacity or slot_capacity_for(self.problems)
         n = len(self.problems)
         arr = (Instance * n)()
+        keep = []
         for i, pb in enumerate(self.problems):
-            arr[i] = _instance(pb)
+            arr[i] = _instance(pb, keep)
             if adapt is not None:
                 arr[i].adapt = int(adapt)
         schemes = {getattr(pb, "scheme", "roe_weno5") for pb in self.problems}

@@ -65,7 +65,9 @@ class Problem:
     lmax: int = 0
     n0: Tuple[int, int, int] = (1, 1, 1)
     dx0: float = 1.0 / 16.0
-    bc: Tuple[int, int, int] = (0, 0, 0)   # 0 periodic, 1 zero-gradient
+    # per axis: 0 periodic, 1 zero-gradient, 2 symmetry, 3 fixed values (the initial
+    # condition continued into the halo, see bc_fixed_states)
+    bc: Tuple[int, int, int] = (0, 0, 0)
     steps: int = 10
     seed: int = BASE_SEED
     instance: int = 0
@@ -82,6 +84,8 @@ class Problem:
     eos: str = "stiffened"
     tait_A: float = 1.0
     tait_rho0: float = 1.0
+    # dynamic viscosity of the Navier-Stokes form (0: Euler equations)
+    mu: float = 0.0
 
     @property
     def adapt(self) -> int:
@@ -97,6 +101,30 @@ class Problem:
         gz, gy, gx = np.meshgrid(bz * IC + ar, by * IC + ar, bx * IC + ar, indexing="ij")
         h = self.dx(level)
         return (gx, gy, gz), ((gx + 0.5) * h, (gy + 0.5) * h, (gz + 0.5) * h)
+
+    def bc_fixed_states(self) -> Optional[np.ndarray]:
+        """Halo states of the fixed-value boundaries: the initial condition (without noise)
+        at the halo cell centres beyond each side of the axes with bc 3, taken on the
+        line through the middle of the boundary plane (such problems are uniform along
+        their fixed boundaries).  [6 sides x-, x+, y-, y+, z-, z+][lmax + 1][4 layers, the
+        one at the face first][5 primitives]; None if no axis has bc 3."""
+        if 3 not in tuple(self.bc):
+            return None
+        out = np.zeros((6, self.lmax + 1, 4, 5))
+        ext = [self.n0[a] * IC * self.dx0 for a in range(3)]
+        for a in range(3):
+            if self.bc[a] != 3:
+                continue
+            for side in range(2):
+                for lvl in range(self.lmax + 1):
+                    h = self.dx(lvl)
+                    c = [np.full(4, 0.5 * ext[b]) for b in range(3)]
+                    lay = np.arange(4) + 0.5
+                    c[a] = ext[a] + lay * h if side else -lay * h
+                    st = _STATES[self.kind](self, *c)
+                    for q in range(5):
+                        out[2 * a + side, lvl, :, q] = np.broadcast_to(st[q], (4,))
+        return out
 
     def primitives(self, level: int, bx: int, by: int, bz: int) -> np.ndarray:
         """Initial primitive state (rho, u, v, w, p) of one block interior, [5][16][16][16]."""
@@ -184,6 +212,23 @@ def _shock_blobs(pb: Problem, x, y, z):
     return rho, u, _full(x, 0.0), _full(x, 0.0), p
 
 
+def _rti(pb: Problem, x, y, z):
+    """Heavy fluid (rho_h) above a light one (rho_l) under gravity -g along y, interface
+    y_i(x) = y0 + a cos(k x) smoothed as a tanh of thickness delta, at rest; pressure in
+    hydrostatic balance with the unperturbed (flat) profile, p0 at y0:
+    p(y) = p0 - g (rho_m (y - y0) + (rho_h - rho_l)/2 delta ln cosh((y - y0)/delta))."""
+    prm = pb.params
+    rh, rl, g = prm["rho_h"], prm["rho_l"], prm["g"]
+    k, a, y0, dl, p0 = prm["k"], prm["amp"], prm["y0"], prm["delta"], prm["p0"]
+    yi = y0 + a * np.cos(k * x)
+    rho = rl + (rh - rl) * 0.5 * (1.0 + np.tanh((y - yi) / dl))
+    s = (y - y0) / dl
+    lncosh = np.abs(s) + np.log1p(np.exp(-2.0 * np.abs(s))) - math.log(2.0)
+    p = p0 - g * (0.5 * (rh + rl) * (y - y0) + 0.5 * (rh - rl) * dl * lncosh)
+    zero = _full(x, 0.0)
+    return rho, zero, zero.copy(), zero.copy(), p
+
+
 def _uniform(pb: Problem, x, y, z):
     r, u, v, w, p = pb.params.get("state", (1.3, 0.3, -0.2, 0.1, 0.9))
     return _full(x, r), _full(x, u), _full(x, v), _full(x, w), _full(x, p)
@@ -195,7 +240,7 @@ def _custom(pb: Problem, x, y, z):
 
 
 _STATES = {"sod": _sod, "blast": _blast, "kh": _kh, "shock_blobs": _shock_blobs,
-           "uniform": _uniform, "custom": _custom}
+           "uniform": _uniform, "custom": _custom, "rti": _rti}
 
 
 # ---------------------------------------------------------------- named workloads -----
@@ -283,6 +328,37 @@ def shock_blobs_mr6(seed_k: int = 5, steps: int = 30) -> Problem:
                    dx0=1.0 / 16, bc=(1, 0, 0), steps=steps, seed=BASE_SEED + seed_k, noise=0.0,
                    eps=1e-3, scale_rho=8.0 / 3.0, scale_E=12.0,
                    params={"x_shock": 0.1, "blobs": 32, "amp": 0.5, "width": 0.02})
+
+
+# fluid properties of the Rayleigh-Taylor growth-rate study per Atwood number:
+# (rho_h, rho_l, mu); g = 1 for both
+RTI_FLUIDS = {0.5: (1.5, 0.5, 0.1), 0.998: (99.9, 0.1, 0.5)}
+
+
+def rti(k: float = 1.0, atwood: float = 0.5, lmax: int = 3, steps: int = 0, p0: Optional[float] = None,
+        delta_cells: float = 1.0, amp: Optional[float] = None, eps: float = 1e-3,
+        long_blocks: int = 10) -> Problem:
+    """Sec. "Rayleigh-Taylor instability" with the fluids of its table of inputs: the short
+    sides span one wavelength 2 pi / k, the long (vertical, y) side ten (1:10, one level-0
+    block across, ten along y, 16 * 2^lmax cells per wavelength: 1280 cells along y at
+    lmax = 3); interface at mid-height deflected by amp cos(k x), amp = 0.05 / k; gravity
+    -g along y; symmetry planes on the sides, fixed values (the hydrostatic initial state
+    continued) at top and bottom; one ideal gas (gamma 1.4) whose density
+    jumps at the interface, both fluids with the same dynamic viscosity.  p0 (interface
+    pressure) defaults to 15 wavelengths of heavy-fluid weight, which keeps the top at 10
+    and the flow nearly incompressible (g / (k c^2) < 0.01 at k = 1)."""
+    rh, rl, mu = RTI_FLUIDS[atwood]
+    g = 1.0
+    lam = 2.0 * math.pi / k
+    dx0 = lam / 16.0
+    return Problem(name=f"rti_at{atwood}_k{k:g}_{lmax + 1}lvl", kind="rti", lmax=lmax,
+                   n0=(1, long_blocks, 1), dx0=dx0, bc=(2, 3, 2), steps=steps, noise=0.0, eps=eps,
+                   scale_rho=rh, scale_E=(p0 or 15.0 * lam * rh * g) / 0.4, cfl=0.5,
+                   gravity=(0.0, -g, 0.0), mu=mu,
+                   params={"rho_h": rh, "rho_l": rl, "g": g, "k": k,
+                           "amp": 0.05 / k if amp is None else amp,
+                           "y0": 0.5 * long_blocks * lam, "delta": delta_cells * dx0 / (1 << lmax),
+                           "p0": p0 or 15.0 * lam * rh * g})
 
 
 def uniform_flow(lmax: int = 2, n0=(1, 1, 1), state=(1.3, 0.3, -0.2, 0.1, 0.9)) -> Problem:

@@ -1,0 +1,202 @@
+"""Viscous terms and symmetry boundaries on the GPU (through the C ABI) against the oracle.
+
+* right-hand side with viscosity and the jump correction on a tree with one- and
+  two-level jumps, random states (identical halos on both sides, all 26 regions), FP64
+  and FP32, stiffened gas and Tait;
+* whole adaptive runs of a small Rayleigh-Taylor layer (viscosity, gravity, symmetry
+  planes on every side; identical trees and time steps after every step), FP64 and FP32
+  on the plain path; the time step where the viscous bound sets it;
+* symmetry boundaries without viscosity on the fused FP32 path (step graphs) and the
+  plain FP64 path: a blast in a corner of the box, adaptive;
+* conservation of mass, momentum and energy with viscosity and jumps;
+* fixed-value top and bottom: a resting hydrostatic column stays at rest (global and local
+  time stepping, with a resolution jump);
+* the combinations the library refuses (fused FP32 path, local time stepping).
+
+Tolerances: FP64 1e-10 relative on the right-hand side and 1e-10 on whole runs (another
+operation order in the viscous differences), dt to 1e-13 (bitwise where the viscous bound
+sets it); FP32 5e-5 on the right-hand side, 3e-5 on the smooth runs, 2e-4 relative and
+L1(rho) <= 1e-5 on the blast (shocks).
+"""
+import numpy as np
+import pytest
+
+from gpu_helpers import (N, l1_diff, make_pair, oracle_padded_to_gpu, random_physical, same_tree,
+                         set_interiors, slot_map)
+from paper_2012_04385_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+REFS = [(1, 1, 1, 1), (1, 2, 1, 1), (2, 3, 2, 2), (1, 0, 3, 0)]
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def _jump_problem(eos="stiffened"):
+    pb = W.uniform_flow(lmax=3, n0=(2, 2, 2))
+    pb.bc = (0, 2, 1)   # periodic, symmetry, zero-gradient: every boundary kind at once
+    pb.mu = 0.05
+    if eos == "tait":
+        pb.eos, pb.B, pb.tait_A, pb.tait_rho0 = "tait", 0.937315, 1.0, 1.0
+    return pb
+
+
+@pytest.mark.parametrize("dtype,eos", [("f64", "stiffened"), ("f32", "stiffened"), ("f64", "tait")])
+def test_rhs_with_jump_correction(orc, torch_mod, dtype, eos):
+    o, g = make_pair(orc, _jump_problem(eos), REFS, dtype)
+    print(f"[visc] rhs {dtype} {eos}", flush=True)
+    rng = np.random.default_rng(41)
+
+    def state(k):
+        u = random_physical(rng, (N, N, N))
+        if eos == "tait":
+            u[4] = 0.0
+        return u
+
+    set_interiors(o, g, state)
+    o.project()
+    o.fill_halos()
+    oracle_padded_to_gpu(o, g)
+    Lo = o.rhs()
+    g.rhs_stage()
+    torch_mod.cuda.synchronize()
+    Lg = g.L.double().cpu().numpy()
+    gm = slot_map(g)
+    leaves = [tuple(int(v) for v in r[:4]) for r in o.blocks() if r[4] == 1]
+    tol = 1e-10 if dtype == "f64" else 5e-5
+    worst = 0.0
+    for i, k in enumerate(leaves):
+        ref = Lo[i]
+        worst = max(worst, np.abs(Lg[gm[k]] - ref).max() / np.abs(ref).max())
+    print(f"[visc] worst {worst:.2e}", flush=True)
+    assert worst < tol, worst
+
+
+def _rti_small(seed_k=0):
+    # two wavelengths tall, 64 cells per wavelength on level 2; the interface deflection
+    # of the paper's setup
+    return W.rti(k=2.0, lmax=2, long_blocks=2)
+
+
+def _compare(o, g):
+    ol, gl = o.leaf_states(), g.leaf_states()
+    assert ol.keys() == gl.keys()
+    return max(np.abs(gl[k] - v).max() / np.abs(v).max() for k, v in ol.items())
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-10), ("f32", 3e-5)])
+def test_rti_runs_adaptive(orc, torch_mod, dtype, tol):
+    pb = _rti_small()
+    o, g = make_pair(orc, pb, (), dtype, adapt=1)
+    print(f"[visc] rti {dtype}", flush=True)
+    for m in range(6):
+        dto = o.step()
+        g.step()
+        torch_mod.cuda.synchronize()
+        dtg = float(g.dt.cpu()[0])
+        assert abs(dtg - dto) <= (1e-13 if dtype == "f64" else 1e-5) * dto, (m, dtg, dto)
+        ok, ol, gl = same_tree(o, g)
+        assert ok, (m, ol ^ gl)
+    g.check()
+    levels = {k[0] for k in o.leaf_states()}
+    assert 2 in levels and len(levels) >= 2, levels
+    worst = _compare(o, g)
+    print(f"[visc] worst {worst:.2e}", flush=True)
+    assert worst < tol, worst
+
+
+def test_viscous_dt(orc, torch_mod):
+    # a viscosity large enough that the viscous bound sets the step
+    pb = _rti_small()
+    pb.mu = 2.0
+    for dtype in ("f64", "f32"):
+        o, g = make_pair(orc, pb, (), dtype)
+        print(f"[visc] dt {dtype}", flush=True)
+        g.cfl_dt()
+        torch_mod.cuda.synchronize()
+        dto, dtg = o.dt(), float(g.dt.cpu()[0])
+        rinv = max(float((1.0 / v[0]).max()) for v in o.leaf_states().values())
+        assert dto == orc.visc_dt(pb.cfl, pb.dx(pb.lmax), pb.mu, rinv)
+        assert abs(dtg - dto) <= (0.0 if dtype == "f64" else 1e-6) * dto, (dtg, dto)
+
+
+def _corner_blast():
+    return W.Problem(name="corner_blast", kind="blast", lmax=2, n0=(1, 1, 1), dx0=1.0 / 16, bc=(2, 2, 2),
+                     noise=1e-3, eps=1e-3, scale_rho=1.0, scale_E=25.0, seed=W.BASE_SEED + 9,
+                     params={"centre": (0.0, 0.0, 0.0), "radius": 0.15, "inner": (1.0, 10.0),
+                             "outer": (0.125, 0.1)})
+
+
+@pytest.mark.parametrize("dtype,batched,tol", [("f64", False, 1e-11), ("f32", 2, 2e-4)])
+def test_symmetry_corner_blast(orc, torch_mod, dtype, batched, tol):
+    pb = _corner_blast()
+    o, g = make_pair(orc, pb, (), dtype, batched=batched, adapt=1)
+    print(f"[visc] symmetric corner blast {dtype} batched={batched}", flush=True)
+    for m in range(8):
+        o.step()
+        g.step()
+        torch_mod.cuda.synchronize()
+        ok, ol, gl = same_tree(o, g)
+        assert ok, (m, ol ^ gl)
+    g.check()
+    worst = _compare(o, g)
+    print(f"[visc] worst {worst:.2e} L1(rho) {l1_diff(o, g, 0):.2e}", flush=True)
+    assert worst < tol, worst
+    if dtype == "f32":
+        assert l1_diff(o, g, 0) <= 1e-5
+
+
+def test_conservation_with_jumps(torch_mod, orc):
+    rng = np.random.default_rng(43)
+    pb = W.uniform_flow(lmax=3, n0=(2, 2, 2))   # periodic: the totals are conserved
+    pb.mu = 0.05
+    o, g = make_pair(orc, pb, REFS, "f64")
+    set_interiors(o, g, lambda k: random_physical(rng, (N, N, N)))
+    g.mr_project()
+    g.totals()
+    t0 = g.tot.cpu().numpy()[0].copy()
+    for _ in range(2):
+        g.step()
+    g.totals()
+    torch_mod.cuda.synchronize()
+    t1 = g.tot.cpu().numpy()[0]
+    assert np.all(np.abs(t1 - t0) <= 1e-13 * np.abs(t0).max()), t1 - t0
+
+
+def test_refused_combinations(torch_mod):
+    from paper_2012_04385_amd.mrfv import MrfvError, Solver
+    pb = _rti_small()
+    with pytest.raises(MrfvError):
+        Solver([pb], dtype="f32", batched=2)
+    g = Solver([pb], dtype="f64", batched=False).init()
+    with pytest.raises(MrfvError):
+        g.step_lts()
+
+
+@pytest.mark.parametrize("dtype,tol", [("f64", 1e-11), ("f32", 2e-4)])
+def test_resting_column_fixed_values(orc, torch_mod, dtype, tol):
+    # a hydrostatic column with fixed-value top and bottom stays at rest (the flux
+    # divergence of the linear pressure balances gravity in every cell), global and local
+    # time stepping, on a tree with a resolution jump
+    from test_oracle_viscous import _column
+    pb = _column(lmax=1)
+    o, g = make_pair(orc, pb, (), dtype)
+    print(f"[visc] resting column {dtype}", flush=True)
+    o.coarsen(0, 0, 1, 0)
+    g.coarsen(0, 0, 0, 1, 0)
+    for _ in range(2):
+        o.step()
+        g.step()
+    o.step_lts()
+    g.step_lts()
+    torch_mod.cuda.synchronize()
+    ok, ol, gl = same_tree(o, g)
+    assert ok, ol ^ gl
+    vmax = max(np.abs(u[1:4] / u[0]).max() for u in g.leaf_states().values())
+    print(f"[visc] vmax {vmax:.2e}", flush=True)
+    assert vmax < tol, vmax
