@@ -336,6 +336,54 @@ def eos_leg(warmup, steps):
     return out
 
 
+def rti_leg(ks, t_end, dtype="f64"):
+    """The Rayleigh-Taylor growth-rate study (Sec. "Rayleigh-Taylor instability") at the
+    settings of its table of inputs for Atwood number 0.5 (l_max 3, 128 cells per
+    wavelength, 1:10 domain, amplitude 0.05 / k), viscous plain kernels: per wavenumber the
+    growth rate n = d/dt ln(d / d0), fitted over 3 / sqrt(k) <= t <= t_end / sqrt(k) (past the
+    start-up transient, before the amplitude leaves the linear regime), against the root of
+    eq:SinglePhaseGrowth, and the solver's rate in cell-updates per second."""
+    import math
+    from oracle import oracle
+    from paper_2012_04385_amd import rti
+    from paper_2012_04385_amd import workloads as W
+    from paper_2012_04385_amd.mrfv import Solver
+    rh, rl, mu = W.RTI_FLUIDS[0.5]
+    out = {"workload": "Rayleigh-Taylor, At 0.5, rho 1.5 | 0.5, mu 0.1, g 1, l_max 3, 128 cells per "
+                       "wavelength, 1280 along y", "dtype": dtype, "path": "plain per-block kernels + viscous",
+           "fit": "least-squares slope of ln d(t) over 3/sqrt(k) <= t <= t_end/sqrt(k)", "runs": []}
+    for k in ks:
+        pb = W.rti(k=k, atwood=0.5, lmax=3)
+        n_th = oracle.rti_growth_rate(k, rh, rl, mu, 1.0)
+        scale = 1.0 / math.sqrt(k)   # time scale of the instability ~ 1 / sqrt(At g k)
+        g = Solver([pb], dtype=dtype, batched=False).init()
+        ts, ds = [0.0], [rti.displacement(g, pb)]
+        cells, steps = 0, 0
+        t0 = time.perf_counter()
+        while g.time[0] < t_end * scale:
+            for _ in range(25):
+                cells += 3 * g.leaf_cells()
+                g.advance(1)
+            steps += 25
+            ts.append(float(g.time[0]))
+            ds.append(rti.displacement(g, pb))
+            if steps % 2500 == 0:
+                log(f"[bench] rti k={k}: step {steps}, t {ts[-1]:.3f}, d/d0 {ds[-1] / ds[0]:.3f}")
+        secs = time.perf_counter() - t0
+        try:
+            n = rti.growth_rate(ts, ds, 3.0 * scale, t_end * scale)
+        except ValueError:   # a run shorter than the fit window (profiling): no rate
+            n = float("nan")
+        run = {"k": k, "n": n, "n_eq_single_phase_growth": n_th, "ratio": n / n_th,
+               "n_inviscid": math.sqrt(0.5 * k), "steps": steps, "t_end": ts[-1],
+               "amplitude_growth": ds[-1] / ds[0], "leaves_final": g.stats()[1],
+               "cell_updates_per_s": cells / secs, "wall_s": secs}
+        out["runs"].append(run)
+        log(f"[bench] rti k={k}: n {n:.4f} vs {n_th:.4f} ({n / n_th:.3f}), {cells / secs:.3e} cell-updates/s")
+        free(g)
+    return out
+
+
 def free(g):
     import torch
     g.close()
@@ -363,6 +411,11 @@ def main():
     ap.add_argument("--eos-compare", action="store_true",
                     help="only run the Sod tube with Tait's equation against the stiffened gas "
                          "(plain kernels)")
+    ap.add_argument("--rti", action="store_true",
+                    help="only run the Rayleigh-Taylor growth-rate study (viscous plain kernels)")
+    ap.add_argument("--rti-k", default="1", help="comma-separated wavenumbers of --rti")
+    ap.add_argument("--rti-t-end", type=float, default=4.5,
+                    help="end of the run and of the fit window, in units of 1/sqrt(k)")
     ap.add_argument("--proposer-gain", action="store_true",
                     help="only run the learned-proposer gain test (6-level shock-blobs workload)")
     args = ap.parse_args()
@@ -376,6 +429,10 @@ def main():
             log(f"[bench] LTS {dtype}: {r['ms_per_macro_step']:.1f} ms per macro step, "
                 f"time-to-solution speed-up {r['time_to_solution_speedup']:.2f}")
             print(json.dumps(dict(r, workload=args.workload)), flush=True)
+        return
+    if args.rti:
+        ks = [float(v) for v in args.rti_k.split(",")]
+        print(json.dumps(rti_leg(ks, args.rti_t_end)), flush=True)
         return
     if args.eos_compare:
         print(json.dumps(eos_leg(args.warmup, args.steps)), flush=True)
