@@ -11,12 +11,11 @@
 //
 // k_visc runs after the convective flux kernel of the plain path and subtracts the viscous
 // flux differences from its per-direction differences D and the boundary face fluxes from
-// its face planes FF, so that the jump correction averages total fluxes.  Layout and
-// thread mapping are the flux kernel's: one workgroup per (leaf, direction), one thread per
-// pencil (r, m) along the direction, walking its 17 faces; each cell's velocity and the
-// four tangential differences the faces need are computed once and carried from face to
-// face.  The tangential neighbours of the halo cells ahead of and behind the pencil lie in
-// the edge halo regions, which the plain path fills for viscous contexts.
+// its face planes FF, so that the jump correction averages total fluxes.  It walks the
+// z-planes of a leaf with the velocities of three planes in LDS (coalesced row loads, one
+// division per cell and plane pass) and evaluates all three face directions there.  The
+// tangential neighbours of the halo cells beside the faces lie in the edge halo regions,
+// which the plain path fills for viscous contexts.
 //
 // k_rinv_block / k_visc_dt: the explicit bound of the viscous terms.  Fourier analysis of
 // the central operator gives -(40/3) nu / dx^2 for the most negative eigenvalue of the
@@ -36,37 +35,21 @@ __device__ __forceinline__ int pidx(int q, int k, int j, int i) {
     return ((q * NP + k) * NP + j) * NP + i;
 }
 
-// Axis roles of direction DIR: the lower and the higher of the two other axes, and the
-// padded-index strides of all three.
+// Axis roles of direction DIR: the lower and the higher of the two other axes.
 template <int DIR>
 struct VAxes {
     static constexpr int TLO = DIR == 0 ? 1 : 0;
     static constexpr int THI = DIR == 2 ? 1 : 2;
-    static constexpr int S_N = DIR == 0 ? 1 : (DIR == 1 ? NP : NP * NP);
-    static constexpr int S_LO = TLO == 0 ? 1 : NP;
-    static constexpr int S_HI = THI == 1 ? NP : NP * NP;
 };
 
-// Per cell along the pencil: velocity and the undivided central differences of the
-// components the stress on a DIR face needs (normal and t_lo components along t_lo,
-// normal and t_hi components along t_hi).
+// Per cell beside a DIR face: velocity and the undivided central differences of the
+// components the stress on the face needs (normal and t_lo components along t_lo, normal
+// and t_hi components along t_hi).
 template <typename T>
 struct VCell {
     T v[3];
     T n_lo, lo_lo, n_hi, hi_hi;
 };
-
-template <typename T, int DIR>
-__device__ __forceinline__ void load_vcell(const T *__restrict__ u, int o, VCell<T> &c) {
-    using A = VAxes<DIR>;
-    auto vel = [&](int oo, int comp) { return u[oo + (1 + comp) * CELLS_P] / u[oo]; };
-#pragma unroll
-    for (int k = 0; k < 3; ++k) c.v[k] = vel(o, k);
-    c.n_lo = vel(o + A::S_LO, DIR) - vel(o - A::S_LO, DIR);
-    c.lo_lo = vel(o + A::S_LO, A::TLO) - vel(o - A::S_LO, A::TLO);
-    c.n_hi = vel(o + A::S_HI, DIR) - vel(o - A::S_HI, DIR);
-    c.hi_hi = vel(o + A::S_HI, A::THI) - vel(o - A::S_HI, A::THI);
-}
 
 // Viscous flux through the face between cells a (low side) and b (high side).
 template <typename T, int DIR>
@@ -101,39 +84,60 @@ __device__ __forceinline__ void visc_flux(const VCell<T> &a, const VCell<T> &b, 
     F[4] = energy ? work : (T)0;
 }
 
+// One workgroup per (leaf, z-slab of 4 planes), 16 x 16 threads on the (x, y) cells of a
+// z-plane, walking the slab's planes.  The velocities of three consecutive planes (z - 1, z, z + 1, each 18 x 18 with
+// the one-cell halo ring) sit in LDS, loaded once per plane with coalesced rows; every
+// derivative is then two LDS reads.  Per plane a thread evaluates the x-face on the left of
+// its cell, the y-face below it and the z-face below the plane (the last column / row /
+// plane also the far faces), the x- and y-face fluxes go through LDS to form the
+// differences, the z-face flux is carried from plane to plane in registers (the face
+// between two slabs is evaluated by both).
+constexpr int VR = NI + 2;            // 18: a plane with its halo ring
+constexpr int VPL = VR * VR;          // 324 cells
+constexpr int VSLABS = 4;             // z-slabs per leaf (workgroups): enough workgroups
+constexpr int VSZ = NI / VSLABS;      // to fill the chip on a few hundred leaves
+
+template <typename T>
+struct VisLds {
+    T v[3][3][VPL];                   // [ring slot][component][(y + 1) * 18 + x + 1]
+    T fx[4][NI][NI + 1];              // x-face fluxes (components 1..4) [y][face]
+    T fy[4][NI + 1][NI];              // y-face fluxes [face][x]
+};
+
+template <typename T>
+__device__ __forceinline__ T vat(const VisLds<T> &L, int slot, int comp, int x, int y) {
+    return L.v[slot][comp][(y + 1) * VR + x + 1];
+}
+
+// The per-cell record of a DIR face: velocity and the undivided central differences along
+// the two tangential axes, from the ring (slots of planes z - 1, z, z + 1 for the cell's z).
 template <typename T, int DIR>
-__device__ __forceinline__ void visc_pencil(const T *__restrict__ ub, int r, int m, T mu, T inv_dx,
-                                            bool energy, T *__restrict__ D, T *__restrict__ FF) {
+__device__ __forceinline__ void cell_rec(const VisLds<T> &L, int zm, int z0, int zp, int x, int y,
+                                         VCell<T> &c) {
     using A = VAxes<DIR>;
-    int c[3];
-    c[DIR] = HW - 1;
-    c[A::TLO] = HW + r;
-    c[A::THI] = HW + m;
-    const int o0 = pidx(0, c[2], c[1], c[0]);
-    const int rm = m * NI + r;
-    VCell<T> prev, cur;
-    load_vcell<T, DIR>(ub, o0, prev);
-    T Fp[5];
-#pragma unroll 1
-    for (int f = 0; f <= NI; ++f) {
-        load_vcell<T, DIR>(ub, o0 + (f + 1) * A::S_N, cur);
-        T F[5];
-        visc_flux<T, DIR>(prev, cur, mu, inv_dx, energy, F);
-        if (f == 0 || f == NI) {
-            T *ff = FF + (2 * DIR + (f == NI)) * 5 * FACE + rm;
 #pragma unroll
-            for (int k = 1; k < 5; ++k) ff[k * FACE] -= F[k];
-        }
-        if (f > 0) {
-            const int p = f - 1;
-            const int cell = DIR == 0 ? (m * NI + r) * NI + p : (DIR == 1 ? (m * NI + p) * NI + r : (p * NI + m) * NI + r);
-            T *d = D + DIR * 5 * CELLS_I + cell;
+    for (int k = 0; k < 3; ++k) c.v[k] = vat(L, z0, k, x, y);
+    // difference of component `comp` along axis `ax` (0 x, 1 y, 2 z)
+    auto dif = [&](int comp, int ax) {
+        if (ax == 0) return vat(L, z0, comp, x + 1, y) - vat(L, z0, comp, x - 1, y);
+        if (ax == 1) return vat(L, z0, comp, x, y + 1) - vat(L, z0, comp, x, y - 1);
+        return vat(L, zp, comp, x, y) - vat(L, zm, comp, x, y);
+    };
+    c.n_lo = dif(DIR, A::TLO);
+    c.lo_lo = dif(A::TLO, A::TLO);
+    c.n_hi = dif(DIR, A::THI);
+    c.hi_hi = dif(A::THI, A::THI);
+}
+
+template <typename T>
+__device__ __forceinline__ void load_plane(const T *__restrict__ ub, VisLds<T> &L, int zz, int tid) {
+    const int sl = (zz + 3) % 3;
+    for (int c = tid; c < VPL; c += TPB) {
+        const int x = c % VR - 1, y = c / VR - 1;
+        const int o = pidx(0, HW + zz, HW + y, HW + x);
+        const T r = ub[o];
 #pragma unroll
-            for (int k = 1; k < 5; ++k) d[k * CELLS_I] -= F[k] - Fp[k];
-        }
-#pragma unroll
-        for (int k = 0; k < 5; ++k) Fp[k] = F[k];
-        prev = cur;
+        for (int k = 0; k < 3; ++k) L.v[sl][k][c] = ub[o + (1 + k) * CELLS_P] / r;
     }
 }
 
@@ -141,7 +145,10 @@ template <typename T>
 __global__ __launch_bounds__(TPB) void k_visc(const T *__restrict__ U, WorkList wl,
                                               const BlockMeta *__restrict__ meta,
                                               const InstDev *__restrict__ inst, T *D, T *FF) {
+    __shared__ VisLds<T> L;
     const int nb = wl.count();
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    const int z0s = blockIdx.y * VSZ, z1s = z0s + VSZ;   // this workgroup's planes [z0s, z1s)
     for (int b = blockIdx.x; b < nb; b += gridDim.x) {
         const int slot = wl.at(b);
         const BlockMeta mt = meta[slot];
@@ -149,13 +156,118 @@ __global__ __launch_bounds__(TPB) void k_visc(const T *__restrict__ U, WorkList 
         if (!(P.mu > 0.0)) continue;   // uniform per workgroup
         const T mu = (T)P.mu, inv_dx = (T)(1.0 / ldexp(P.dx0, -mt.level));
         const bool energy = P.eos == 0;
-        const int r = threadIdx.x & 15, m = threadIdx.x >> 4;
         const T *ub = U + (size_t)slot * 5 * CELLS_P;
         T *Ds = D + (size_t)slot * 3 * 5 * CELLS_I;
         T *Fs = FF + (size_t)slot * 6 * 5 * FACE;
-        if (blockIdx.y == 0) visc_pencil<T, 0>(ub, r, m, mu, inv_dx, energy, Ds, Fs);
-        else if (blockIdx.y == 1) visc_pencil<T, 1>(ub, r, m, mu, inv_dx, energy, Ds, Fs);
-        else visc_pencil<T, 2>(ub, r, m, mu, inv_dx, energy, Ds, Fs);
+        load_plane(ub, L, z0s - 1, tid);
+        load_plane(ub, L, z0s, tid);
+        T Fz[5];   // the z-face below the current plane
+#pragma unroll 1
+        for (int z = z0s; z < z1s; ++z) {
+            load_plane(ub, L, z + 1, tid);
+            __syncthreads();
+            const int zm = (z + 2) % 3, z0 = z % 3, zp = (z + 1) % 3;   // slots of z - 1, z, z + 1
+            VCell<T> a, c;
+            T F[5];
+            // x-faces: left of the cell, and the far face for the last column
+            cell_rec<T, 0>(L, zm, z0, zp, tx - 1, ty, a);
+            cell_rec<T, 0>(L, zm, z0, zp, tx, ty, c);
+            visc_flux<T, 0>(a, c, mu, inv_dx, energy, F);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) L.fx[k][ty][tx] = F[k + 1];
+            if (tx == NI - 1) {
+                cell_rec<T, 0>(L, zm, z0, zp, NI, ty, a);
+                visc_flux<T, 0>(c, a, mu, inv_dx, energy, F);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) L.fx[k][ty][NI] = F[k + 1];
+            }
+            // y-faces: below the cell, and the far face for the last row
+            cell_rec<T, 1>(L, zm, z0, zp, tx, ty - 1, a);
+            cell_rec<T, 1>(L, zm, z0, zp, tx, ty, c);
+            visc_flux<T, 1>(a, c, mu, inv_dx, energy, F);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) L.fy[k][ty][tx] = F[k + 1];
+            if (ty == NI - 1) {
+                cell_rec<T, 1>(L, zm, z0, zp, tx, NI, a);
+                visc_flux<T, 1>(c, a, mu, inv_dx, energy, F);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) L.fy[k][NI][tx] = F[k + 1];
+            }
+            // z-face below the plane, between cells (x, y, z - 1) and (x, y, z): a z-face
+            // needs differences along x and y only
+            {
+                VCell<T> lo, hi;
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    lo.v[k] = vat(L, zm, k, tx, ty);
+                    hi.v[k] = vat(L, z0, k, tx, ty);
+                }
+                // tangential axes of a z-face: x (t_lo) and y (t_hi)
+                lo.n_lo = vat(L, zm, 2, tx + 1, ty) - vat(L, zm, 2, tx - 1, ty);
+                lo.lo_lo = vat(L, zm, 0, tx + 1, ty) - vat(L, zm, 0, tx - 1, ty);
+                lo.n_hi = vat(L, zm, 2, tx, ty + 1) - vat(L, zm, 2, tx, ty - 1);
+                lo.hi_hi = vat(L, zm, 1, tx, ty + 1) - vat(L, zm, 1, tx, ty - 1);
+                hi.n_lo = vat(L, z0, 2, tx + 1, ty) - vat(L, z0, 2, tx - 1, ty);
+                hi.lo_lo = vat(L, z0, 0, tx + 1, ty) - vat(L, z0, 0, tx - 1, ty);
+                hi.n_hi = vat(L, z0, 2, tx, ty + 1) - vat(L, z0, 2, tx, ty - 1);
+                hi.hi_hi = vat(L, z0, 1, tx, ty + 1) - vat(L, z0, 1, tx, ty - 1);
+                T Fn[5];
+                visc_flux<T, 2>(lo, hi, mu, inv_dx, energy, Fn);
+                const int rm = ty * NI + tx;   // z-face planes: r = x, m = y
+                if (z == 0) {
+#pragma unroll
+                    for (int k = 1; k < 5; ++k) Fs[(4 * 5 + k) * FACE + rm] -= Fn[k];
+                } else if (z > z0s) {   // the slab's first face only starts the carry
+                    const int cell = ((z - 1) * NI + ty) * NI + tx;
+#pragma unroll
+                    for (int k = 1; k < 5; ++k) Ds[(2 * 5 + k) * CELLS_I + cell] -= Fn[k] - Fz[k];
+                }
+#pragma unroll
+                for (int k = 0; k < 5; ++k) Fz[k] = Fn[k];
+                if (z == z1s - 1) {
+                    // the slab's far z-face, between planes z and z + 1 (slot zp)
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        lo.v[k] = hi.v[k];
+                        hi.v[k] = vat(L, zp, k, tx, ty);
+                    }
+                    lo.n_lo = hi.n_lo;
+                    lo.lo_lo = hi.lo_lo;
+                    lo.n_hi = hi.n_hi;
+                    lo.hi_hi = hi.hi_hi;
+                    hi.n_lo = vat(L, zp, 2, tx + 1, ty) - vat(L, zp, 2, tx - 1, ty);
+                    hi.lo_lo = vat(L, zp, 0, tx + 1, ty) - vat(L, zp, 0, tx - 1, ty);
+                    hi.n_hi = vat(L, zp, 2, tx, ty + 1) - vat(L, zp, 2, tx, ty - 1);
+                    hi.hi_hi = vat(L, zp, 1, tx, ty + 1) - vat(L, zp, 1, tx, ty - 1);
+                    visc_flux<T, 2>(lo, hi, mu, inv_dx, energy, Fn);
+                    const int cell = (z * NI + ty) * NI + tx;
+#pragma unroll
+                    for (int k = 1; k < 5; ++k) {
+                        Ds[(2 * 5 + k) * CELLS_I + cell] -= Fn[k] - Fz[k];
+                        if (z == NI - 1) Fs[(5 * 5 + k) * FACE + rm] -= Fn[k];
+                    }
+                }
+            }
+            __syncthreads();
+            // x and y differences of the cell, boundary face planes of the x and y sides
+            const int cell = (z * NI + ty) * NI + tx;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                Ds[(0 * 5 + 1 + k) * CELLS_I + cell] -= L.fx[k][ty][tx + 1] - L.fx[k][ty][tx];
+                Ds[(1 * 5 + 1 + k) * CELLS_I + cell] -= L.fy[k][ty + 1][tx] - L.fy[k][ty][tx];
+            }
+            if (tx == 0 || tx == NI - 1) {   // x-face planes: r = y, m = z
+                const int side = tx == 0 ? 0 : 1, f = tx == 0 ? 0 : NI;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) Fs[(side * 5 + 1 + k) * FACE + z * NI + ty] -= L.fx[k][ty][f];
+            }
+            if (ty == 0 || ty == NI - 1) {   // y-face planes: r = x, m = z
+                const int side = ty == 0 ? 2 : 3, f = ty == 0 ? 0 : NI;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) Fs[(side * 5 + 1 + k) * FACE + z * NI + tx] -= L.fy[k][f][tx];
+            }
+            __syncthreads();   // the ring slot of z - 1 and the face arrays are reused
+        }
     }
 }
 
@@ -215,7 +327,7 @@ template <typename T>
 hipError_t launch_visc(const T *U, const WorkList &wl, const DevTables &tb, const InstDev *inst,
                        T *D, T *FF, hipStream_t st) {
     if (wl.grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_visc<T>, dim3(wl.grid, 3), dim3(TPB), 0, st, U, wl, tb.meta, inst, D, FF);
+    hipLaunchKernelGGL(k_visc<T>, dim3(wl.grid, VSLABS), dim3(TPB), 0, st, U, wl, tb.meta, inst, D, FF);
     return hipGetLastError();
 }
 
