@@ -1097,6 +1097,10 @@ int mrfv_create(mrfv_ctx **out, const mrfv_config *cfg, const mrfv_instance *ins
         return bail(MRFV_ENOMEM);                                                          \
     }
     ALLOC(ctx->d_inst, sizeof(InstDev) * id.size());
+    for (int i = 0; i < cfg->n_instances; ++i)
+        for (int a = 0; a < 3; ++a)
+            if (inst[i].bc[a] == MRFV_BC_SYMMETRY || inst[i].bc[a] == MRFV_BC_FIXED)
+                ctx->tb.ext_bc = ctx->tb2.ext_bc = true;
     {
         // fixed-value halo states, conservative in the context dtype
         bool any = false;

@@ -100,13 +100,15 @@ struct Region {
     int r[3];       // region direction after clamping (0 on clamped axes)
     int lo[3], n[3];
     int clamp[3];   // -1, or the padded index every cell of the axis copies/predicts from
-    int mir[3];     // 0, or (symmetry boundary) cell i of the axis takes index mir - i
+    int mirbits;    // bit a: axis a is clamped at a symmetry boundary, where cell i takes
+                    // index mir_index(g, a) - i
     int fix;        // -1, or 4 * side + axis of the last axis (x, y, z order) whose
                     // boundary has fixed values: the region then holds those values
 };
 
 __device__ __forceinline__ Region make_region(int mode, int ridx, int zg) {
     Region g;
+    g.mirbits = 0;
     int r[3];
     const bool faces = (mode & FILL_FACES) != 0;
     if (!faces) {
@@ -123,17 +125,16 @@ __device__ __forceinline__ Region make_region(int mode, int ridx, int zg) {
         g.lo[a] = r[a] < 0 ? (faces ? 1 : 0) : (r[a] == 0 ? HW : HW + NI);
         g.n[a] = r[a] == 0 ? NI : (faces ? 3 : HW);
         g.clamp[a] = -1;
-        g.mir[a] = 0;
         g.r[a] = r[a];
         if (r[a] < 0 && (zg & (1 << (2 * a)))) {
             g.clamp[a] = HW;
             g.r[a] = 0;
-            if (zg & (64 << (2 * a))) g.mir[a] = 2 * HW - 1;
+            if (zg & (64 << (2 * a))) g.mirbits |= 1 << a;
         }
         if (r[a] > 0 && (zg & (1 << (2 * a + 1)))) {
             g.clamp[a] = HW + NI - 1;
             g.r[a] = 0;
-            if (zg & (64 << (2 * a + 1))) g.mir[a] = 2 * (HW + NI) - 1;
+            if (zg & (64 << (2 * a + 1))) g.mirbits |= 1 << a;
         }
     }
     g.fix = -1;
@@ -143,6 +144,12 @@ __device__ __forceinline__ Region make_region(int mode, int ridx, int zg) {
         if (r[a] > 0 && (zg & (4096 << (2 * a + 1)))) g.fix = 4 + a;
     }
     return g;
+}
+
+// Mirror constant of a symmetry-clamped axis: halo cell i of the low side takes padded
+// index 2 HW - 1 - i, of the high side 2 (HW + NI) - 1 - i.
+__device__ __forceinline__ int mir_index(const Region &g, int a) {
+    return g.clamp[a] == HW ? 2 * HW - 1 : 2 * (HW + NI) - 1;
 }
 
 // Index decomposition without integer division: e / n for 0 <= e < 2^13 and n <= 24 as
@@ -164,7 +171,9 @@ __device__ __forceinline__ int parent_of(int c, int o) { return o * (NI / 2) + (
 // regions), y pass (16 x 16 x 6 for z-normal regions, else 16 x 4 x 12).
 constexpr int PR_A = 6 * 12 * 12, PR_X = 16 * 12 * 6, PR_Y = 16 * 16 * 6;
 
-template <typename T>
+// EXT: the context has symmetry or fixed-value sides; without them the mirror and
+// fixed-value code is compiled out (the periodic / zero-gradient fill pays nothing for it).
+template <typename T, bool EXT>
 __global__ __launch_bounds__(TPB) void k_fill_halos(T *__restrict__ U, WorkList wl,
                                                     const BlockMeta *__restrict__ meta,
                                                     const int32_t *__restrict__ nbr, int mode,
@@ -181,8 +190,11 @@ __global__ __launch_bounds__(TPB) void k_fill_halos(T *__restrict__ U, WorkList 
         if (bi >= m_round) continue;   // uniform per workgroup
         const int slot = wl.at(base + bi);
         const BlockMeta m = meta[slot];
-        const Region g = make_region(mode, blockIdx.y, m.zg);
-        if (g.fix >= 0) {
+        const Region g = make_region(mode, blockIdx.y, EXT ? m.zg : (m.zg & 63));
+        // mirrored axes as bits (no run-time indexing into the region's arrays, which would
+        // put them in scratch memory)
+        const int mirbits = EXT ? g.mirbits : 0;
+        if (EXT && g.fix >= 0) {
             // fixed values: the state of the layer (distance from the face) along the last
             // fixed axis, with the normal momentum of later symmetry axes reversed
             if (!bcfix) continue;
@@ -192,16 +204,18 @@ __global__ __launch_bounds__(TPB) void k_fill_halos(T *__restrict__ U, WorkList 
             const int ncell = g.n[0] * g.n[1] * g.n[2];
             const Div d0(g.n[0]), d1(g.n[1]);
             const bool re = (mode & FILL_RHO_E) != 0;
+            const int flipbits = mirbits & ~((2 << fa) - 1);   // mirrored axes after fa
             for (int e = tid; e < ncell; e += TPB) {
                 const int e1 = d0.quot(e), e2 = d1.quot(e1);
-                int c[3] = {g.lo[0] + e - e1 * g.n[0], g.lo[1] + e1 - e2 * g.n[1], g.lo[2] + e2};
-                const int layer = fhi ? c[fa] - (HW + NI) : HW - 1 - c[fa];
+                const int ci = g.lo[0] + e - e1 * g.n[0], cj = g.lo[1] + e1 - e2 * g.n[1], ck = g.lo[2] + e2;
+                const int cf = fa == 0 ? ci : (fa == 1 ? cj : ck);
+                const int layer = fhi ? cf - (HW + NI) : HW - 1 - cf;
 #pragma unroll
                 for (int q = 0; q < 5; ++q) {
                     if (re && q != 0 && q != 4) continue;
-                    const bool flip = q >= 1 && q <= 3 && q - 1 > fa && g.mir[q - 1];
+                    const bool flip = q >= 1 && q <= 3 && ((flipbits >> (q - 1)) & 1);
                     const T v = fv[layer * 5 + q];
-                    dst[pidx(q, c[2], c[1], c[0])] = flip ? -v : v;
+                    dst[pidx(q, ck, cj, ci)] = flip ? -v : v;
                 }
             }
             continue;
@@ -219,20 +233,34 @@ __global__ __launch_bounds__(TPB) void k_fill_halos(T *__restrict__ U, WorkList 
         // symmetry: the momentum component normal to a mirrored boundary changes sign
         // (mirrored on two axes: both components)
         auto msign = [&](int q) {
-            return (q >= 1 && q <= 3 && g.mir[q - 1]) ? (T)-1 : (T)1;
+            return (q >= 1 && q <= 3 && ((mirbits >> (q - 1)) & 1)) ? (T)-1 : (T)1;
         };
         if (src >= 0) {
             const T *sb = U + (size_t)src * 5 * CELLS_P;
+            if (mirbits == 0) {   // copies and zero-gradient clamps (uniform per workgroup)
 #pragma unroll 4
-            for (int t = tid; t < nq * ncell; t += TPB) {   // unrolled: several loads in flight
-                const int qi = dc.quot(t), e = t - qi * ncell;
-                const int q = re ? 4 * qi : qi;
-                const int e1 = d0.quot(e), e2 = d1.quot(e1);
-                const int i = g.lo[0] + e - e1 * g.n[0], j = g.lo[1] + e1 - e2 * g.n[1], k = g.lo[2] + e2;
-                const int si = g.mir[0] ? g.mir[0] - i : (g.clamp[0] >= 0 ? g.clamp[0] : i - NI * g.r[0]);
-                const int sj = g.mir[1] ? g.mir[1] - j : (g.clamp[1] >= 0 ? g.clamp[1] : j - NI * g.r[1]);
-                const int sk = g.mir[2] ? g.mir[2] - k : (g.clamp[2] >= 0 ? g.clamp[2] : k - NI * g.r[2]);
-                dst[pidx(q, k, j, i)] = msign(q) * sb[pidx(q, sk, sj, si)];
+                for (int t = tid; t < nq * ncell; t += TPB) {   // unrolled: several loads in flight
+                    const int qi = dc.quot(t), e = t - qi * ncell;
+                    const int q = re ? 4 * qi : qi;
+                    const int e1 = d0.quot(e), e2 = d1.quot(e1);
+                    const int i = g.lo[0] + e - e1 * g.n[0], j = g.lo[1] + e1 - e2 * g.n[1], k = g.lo[2] + e2;
+                    const int si = g.clamp[0] >= 0 ? g.clamp[0] : i - NI * g.r[0];
+                    const int sj = g.clamp[1] >= 0 ? g.clamp[1] : j - NI * g.r[1];
+                    const int sk = g.clamp[2] >= 0 ? g.clamp[2] : k - NI * g.r[2];
+                    dst[pidx(q, k, j, i)] = sb[pidx(q, sk, sj, si)];
+                }
+            } else {              // some axis mirrored
+#pragma unroll 4
+                for (int t = tid; t < nq * ncell; t += TPB) {
+                    const int qi = dc.quot(t), e = t - qi * ncell;
+                    const int q = re ? 4 * qi : qi;
+                    const int e1 = d0.quot(e), e2 = d1.quot(e1);
+                    const int i = g.lo[0] + e - e1 * g.n[0], j = g.lo[1] + e1 - e2 * g.n[1], k = g.lo[2] + e2;
+                    const int si = (mirbits & 1) ? mir_index(g, 0) - i : (g.clamp[0] >= 0 ? g.clamp[0] : i - NI * g.r[0]);
+                    const int sj = (mirbits & 2) ? mir_index(g, 1) - j : (g.clamp[1] >= 0 ? g.clamp[1] : j - NI * g.r[1]);
+                    const int sk = (mirbits & 4) ? mir_index(g, 2) - k : (g.clamp[2] >= 0 ? g.clamp[2] : k - NI * g.r[2]);
+                    dst[pidx(q, k, j, i)] = msign(q) * sb[pidx(q, sk, sj, si)];
+                }
             }
             continue;
         }
@@ -245,8 +273,9 @@ __global__ __launch_bounds__(TPB) void k_fill_halos(T *__restrict__ U, WorkList 
         for (int a = 0; a < 3; ++a) {
             // evaluation points and the first child index: the boundary cell (zero
             // gradient), the mirror images of the region's cells (symmetry), or the region
-            me[a] = g.mir[a] ? g.n[a] : (g.clamp[a] >= 0 ? 1 : g.n[a]);
-            c0[a] = g.mir[a] ? g.mir[a] - (g.lo[a] + g.n[a] - 1) : (g.clamp[a] >= 0 ? g.clamp[a] : g.lo[a]);
+            const bool ma = (mirbits >> a) & 1;
+            me[a] = ma ? g.n[a] : (g.clamp[a] >= 0 ? 1 : g.n[a]);
+            c0[a] = ma ? mir_index(g, a) - (g.lo[a] + g.n[a] - 1) : (g.clamp[a] >= 0 ? g.clamp[a] : g.lo[a]);
             p0[a] = parent_of(c0[a], o[a]) - 2;
             np[a] = parent_of(c0[a] + me[a] - 1, o[a]) + 2 - p0[a] + 1;
         }
@@ -305,9 +334,9 @@ __global__ __launch_bounds__(TPB) void k_fill_halos(T *__restrict__ U, WorkList 
                 const int t1 = d0.quot(t), dz = d1.quot(t1);
                 const int dx = t - t1 * g.n[0], dy = t1 - dz * g.n[1];
                 // evaluation point of the cell: its mirror image runs backwards
-                const int ex = g.mir[0] ? g.n[0] - 1 - dx : (g.clamp[0] >= 0 ? 0 : dx);
-                const int ey = g.mir[1] ? g.n[1] - 1 - dy : (g.clamp[1] >= 0 ? 0 : dy);
-                const int ez = g.mir[2] ? g.n[2] - 1 - dz : (g.clamp[2] >= 0 ? 0 : dz);
+                const int ex = (mirbits & 1) ? g.n[0] - 1 - dx : (g.clamp[0] >= 0 ? 0 : dx);
+                const int ey = (mirbits & 2) ? g.n[1] - 1 - dy : (g.clamp[1] >= 0 ? 0 : dy);
+                const int ez = (mirbits & 4) ? g.n[2] - 1 - dz : (g.clamp[2] >= 0 ? 0 : dz);
                 const int c = c0[2] + ez;
                 const int K = parent_of(c, o[2]) - p0[2];
                 const int st = me[0] * me[1];
@@ -922,8 +951,13 @@ template <typename T>
 hipError_t launch_fill_halos(T *U, const WorkList &wl, const DevTables &tb, FillMode mode,
                              hipStream_t st) {
     if (wl.grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fill_halos<T>, grid2(round_xcd(wl.grid), (mode & FILL_FACES) ? 6 : 26), dim3(TPB), 0,
-                       st, U, wl, tb.meta, tb.nbr, (int)mode, (const T *)tb.bcfix);
+    const dim3 grid = grid2(round_xcd(wl.grid), (mode & FILL_FACES) ? 6 : 26);
+    if (tb.ext_bc)
+        hipLaunchKernelGGL((k_fill_halos<T, true>), grid, dim3(TPB), 0, st, U, wl, tb.meta, tb.nbr, (int)mode,
+                           (const T *)tb.bcfix);
+    else
+        hipLaunchKernelGGL((k_fill_halos<T, false>), grid, dim3(TPB), 0, st, U, wl, tb.meta, tb.nbr, (int)mode,
+                           (const T *)nullptr);
     return hipGetLastError();
 }
 

@@ -54,6 +54,7 @@ struct DevTables {
     int32_t *lists = nullptr;    // concatenated work lists (see HostLists)
     const void *bcfix = nullptr; // fixed-value halo states (context dtype, conservative):
                                  // [inst][6 sides][MAX_LEVELS][4 layers][5]; null if none
+    bool ext_bc = false;         // some instance has a symmetry or fixed-value side
 };
 
 // A work list of block slots.  Eager launches pass the offset and count from the host;
