@@ -65,9 +65,9 @@ int check_instance(mrfv_ctx *ctx, const mrfv_instance &p, int i) {
             for (int sd = 0; sd < 2; ++sd)
                 for (int n = 0; n < (p.lmax + 1) * 4; ++n) {
                     const double *v = p.bc_fixed + ((size_t)(2 * a + sd) * (p.lmax + 1) * 4 + n) * 5;
-                    bool ok = v[0] > 0.0;
+                    bool ok = v[0] > 0.0 && (p.eos == MRFV_TAIT || v[4] + p.B > 0.0);
                     for (int q = 0; q < 5; ++q) ok = ok && std::isfinite(v[q]);
-                    if (!ok) return fail(ctx, MRFV_EINVAL, w + "bc_fixed: needs finite states with rho > 0");
+                    if (!ok) return fail(ctx, MRFV_EINVAL, w + "bc_fixed: needs finite states with rho > 0, p + B > 0");
                 }
         }
     }

@@ -44,6 +44,26 @@ def test_create_rejects_bad_config_without_device():
         assert mrfv.lib().mrfv_create(C.byref(h), C.byref(cfg), inst, None) == mrfv.EINVAL
     inst[0].gamma = 1.0
     assert mrfv.lib().mrfv_create(C.byref(h), C.byref(mrfv.Config(0, 1, 10, 0)), inst, None) == mrfv.EINVAL
+    inst[0].gamma = 1.4
+    ok_cfg = mrfv.Config(1, 1, 10, 0)
+    # viscosity, boundary kinds and fixed-value states are validated before any device call
+    inst[0].mu = -1.0
+    assert mrfv.lib().mrfv_create(C.byref(h), C.byref(ok_cfg), inst, None) == mrfv.EINVAL
+    inst[0].mu = 0.0
+    inst[0].bc[1] = 4
+    assert mrfv.lib().mrfv_create(C.byref(h), C.byref(ok_cfg), inst, None) == mrfv.EINVAL
+    inst[0].bc[1] = 3   # fixed values without states
+    assert mrfv.lib().mrfv_create(C.byref(h), C.byref(ok_cfg), inst, None) == mrfv.EINVAL
+    import numpy as np
+    states = np.ones((6, 1, 4, 5))
+    states[3, 0, 2, 0] = 0.0   # rho = 0 in one layer of the y+ side
+    inst[0].bc_fixed = states.ctypes.data_as(C.POINTER(C.c_double))
+    assert mrfv.lib().mrfv_create(C.byref(h), C.byref(ok_cfg), inst, None) == mrfv.EINVAL
+    states[3, 0, 2, 0] = 1.0
+    states[2, 0, 0, 4] = -2.0  # negative pressure on the y- side
+    assert mrfv.lib().mrfv_create(C.byref(h), C.byref(ok_cfg), inst, None) == mrfv.EINVAL
+    states[2, 0, 0, 4] = 1.0   # all valid now: only the missing device stops the context
+    assert mrfv.lib().mrfv_create(C.byref(h), C.byref(ok_cfg), inst, None) not in (mrfv.OK, mrfv.EINVAL)
     assert mrfv.lib().mrfv_destroy(None) == mrfv.EINVAL
     assert mrfv.lib().mrfv_step(None, None, None, None, None) == mrfv.EINVAL
 
