@@ -384,6 +384,60 @@ def rti_leg(ks, t_end, dtype="f64"):
     return out
 
 
+def schemes_leg(warmup, steps, parity_steps=2):
+    """The four flux kernels of Sec. "Numerical Scheme" on the weak-scaling case of Sec. "Weak
+    Scaling" in its one-core size (Woodward-Colella blast along y, l_max 3, 128 x 512 x 128,
+    CFL 0.9): per kernel the FP32 batched path's rate (step graph, autotuned shape) after
+    `parity_steps` steps run next to the oracle (identical trees, L1 differences), and the
+    FP64 plain path's rate; times relative to the standard configuration (Roe-WENO5)."""
+    from paper_2012_04385_amd import workloads as W
+    out = {"workload": "Woodward-Colella blast along y, 128 x 512 x 128 effective, l_max 3, CFL 0.9",
+           "steps": steps, "warmup": warmup, "kernels": {}}
+    for scheme in ("roe_weno5", "roe_teno5", "llf_weno5", "hllc_wao53"):
+        pbs = [W.wc_blast_mr4(scheme, steps=warmup + steps)]
+        res = {}
+
+        def prepare(g):
+            res["parity"], _, res["llf"] = parity_leg(pbs[0].name, pbs, g, parity_steps, False)
+            return parity_steps
+
+        from paper_2012_04385_amd.mrfv import MrfvError
+        r = {}
+        for cfl in (0.9, 0.5):
+            # LLF-WENO5 in FP32 loses positivity in the first stage at the 1e5 pressure jump
+            # with CFL 0.9 (both FP32 paths; FP64 runs): reported, and measured at CFL 0.5
+            pbs = [W.wc_blast_mr4(scheme, steps=warmup + steps)]
+            pbs[0].cfl = cfl
+            try:
+                g, cells, secs, _ = run_gpu(pbs, "f32", 2, warmup, steps, prepare=prepare)
+            except MrfvError as e:
+                r[f"fp32_error_cfl_{cfl}"] = str(e)
+                import torch
+                torch.cuda.empty_cache()
+                continue
+            r.update({"cell_updates_per_s": cells / secs, "ms_per_step": 1e3 * secs / steps, "fp32_cfl": cfl,
+                      "leaves_final": g.stats()[1], "parity_vs_oracle": res["parity"],
+                      "autotuned_shape": g.rhs_variants()[g.tuned["choice"]]})
+            free(g)
+            break
+        pbs = [W.wc_blast_mr4(scheme, steps=warmup + steps)]
+        g, c64, s64, _ = run_gpu(pbs, "f64", 0, warmup, steps)
+        free(g)
+        r["fp64_plain_cell_updates_per_s"] = c64 / s64
+        out["kernels"][scheme] = r
+        log(f"[bench] {scheme}: {r.get('cell_updates_per_s', float('nan')):.3e} cell-updates/s FP32 batched "
+            f"(CFL {r.get('fp32_cfl')}), {r['fp64_plain_cell_updates_per_s']:.3e} FP64 plain, "
+            f"parity {r.get('parity_vs_oracle', {}).get('trees_identical')} "
+            f"L1(rho) {r.get('parity_vs_oracle', {}).get('l1_rho', float('nan')):.1e}")
+    ref = out["kernels"]["roe_weno5"]
+    for k, r in out["kernels"].items():
+        # time per cell-update relative to the standard configuration
+        if "cell_updates_per_s" in r and "cell_updates_per_s" in ref:
+            r["time_vs_standard_fp32"] = ref["cell_updates_per_s"] / r["cell_updates_per_s"]
+        r["time_vs_standard_fp64"] = ref["fp64_plain_cell_updates_per_s"] / r["fp64_plain_cell_updates_per_s"]
+    return out
+
+
 def free(g):
     import torch
     g.close()
@@ -411,6 +465,8 @@ def main():
     ap.add_argument("--eos-compare", action="store_true",
                     help="only run the Sod tube with Tait's equation against the stiffened gas "
                          "(plain kernels)")
+    ap.add_argument("--schemes", action="store_true",
+                    help="only run the four flux kernels on the weak-scaling blast (Sec. \"Weak Scaling\")")
     ap.add_argument("--rti", action="store_true",
                     help="only run the Rayleigh-Taylor growth-rate study (viscous plain kernels)")
     ap.add_argument("--rti-k", default="1", help="comma-separated wavenumbers of --rti")
@@ -429,6 +485,9 @@ def main():
             log(f"[bench] LTS {dtype}: {r['ms_per_macro_step']:.1f} ms per macro step, "
                 f"time-to-solution speed-up {r['time_to_solution_speedup']:.2f}")
             print(json.dumps(dict(r, workload=args.workload)), flush=True)
+        return
+    if args.schemes:
+        print(json.dumps(schemes_leg(3, 22)), flush=True)
         return
     if args.rti:
         ks = [float(v) for v in args.rti_k.split(",")]

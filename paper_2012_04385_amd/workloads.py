@@ -229,6 +229,17 @@ def _rti(pb: Problem, x, y, z):
     return rho, zero, zero.copy(), zero.copy(), p
 
 
+def _wc_blast(pb: Problem, x, y, z):
+    """Woodward and Colella's interacting blast waves along y: gas at rest, rho = 1,
+    p = 1000 below y = 0.1, 0.01 in between, 100 above y = 0.9."""
+    prm = pb.params
+    lo, hi = prm.get("lo", 0.1), prm.get("hi", 0.9)
+    p = np.where(y < lo, prm.get("p_left", 1000.0), np.where(y > hi, prm.get("p_right", 100.0),
+                                                              prm.get("p_mid", 0.01)))
+    zero = _full(x, 0.0)
+    return _full(x, 1.0), zero, zero.copy(), zero.copy(), p
+
+
 def _uniform(pb: Problem, x, y, z):
     r, u, v, w, p = pb.params.get("state", (1.3, 0.3, -0.2, 0.1, 0.9))
     return _full(x, r), _full(x, u), _full(x, v), _full(x, w), _full(x, p)
@@ -240,7 +251,7 @@ def _custom(pb: Problem, x, y, z):
 
 
 _STATES = {"sod": _sod, "blast": _blast, "kh": _kh, "shock_blobs": _shock_blobs,
-           "uniform": _uniform, "custom": _custom, "rti": _rti}
+           "uniform": _uniform, "custom": _custom, "rti": _rti, "wc_blast": _wc_blast}
 
 
 # ---------------------------------------------------------------- named workloads -----
@@ -328,6 +339,16 @@ def shock_blobs_mr6(seed_k: int = 5, steps: int = 30) -> Problem:
                    dx0=1.0 / 16, bc=(1, 0, 0), steps=steps, seed=BASE_SEED + seed_k, noise=0.0,
                    eps=1e-3, scale_rho=8.0 / 3.0, scale_E=12.0,
                    params={"x_shock": 0.1, "blobs": 32, "amp": 0.5, "width": 0.02})
+
+
+def wc_blast_mr4(scheme: str = "roe_weno5", steps: int = 25, seed_k: int = 8) -> Problem:
+    """The weak-scaling case of Sec. "Weak Scaling" in its one-core size: Woodward and
+    Colella's interacting blast waves along y, l_max = 3, 128 x 512 x 128 cells effective
+    (level 0: one block across x and z, four along y, dx0 = 1/64), reflecting (symmetry)
+    walls at y = 0 and 1, periodic in x and z, CFL 0.9, 25 steps; flux kernel `scheme`."""
+    return Problem(name=f"wcblast_128x512x128_4lvl_{scheme}", kind="wc_blast", lmax=3, n0=(1, 4, 1),
+                   dx0=1.0 / 64, bc=(0, 2, 0), steps=steps, seed=BASE_SEED + seed_k, noise=0.0, eps=1e-3,
+                   scale_rho=1.0, scale_E=2500.0, cfl=0.9, scheme=scheme, params={})
 
 
 # fluid properties of the Rayleigh-Taylor growth-rate study per Atwood number:
