@@ -404,8 +404,8 @@ def schemes_leg(warmup, steps, parity_steps=2):
         from paper_2012_04385_amd.mrfv import MrfvError
         r = {}
         for cfl in (0.9, 0.5):
-            # LLF-WENO5 in FP32 loses positivity in the first stage at the 1e5 pressure jump
-            # with CFL 0.9 (both FP32 paths; FP64 runs): reported, and measured at CFL 0.5
+            # a kernel that stops with a non-physical state at the paper's CFL 0.9 is reported
+            # and measured at CFL 0.5
             pbs = [W.wc_blast_mr4(scheme, steps=warmup + steps)]
             pbs[0].cfl = cfl
             try:

@@ -91,6 +91,15 @@ __device__ __forceinline__ void derive_state(const Gas<T> &G, CellState<T> &s) {
 // numerator, the terms are (r0 / 6, r1, r2 / 2) over (1, 6, 3).  A constant stencil
 // returns c exactly.
 template <typename T>
+__device__ __forceinline__ T weno5_combine(T e0, T e1, T e2, T h0, T h1, T h2, T c) {
+    const T E0 = e0 * e0, E1 = e1 * e1, E2 = e2 * e2;
+    const T E12 = E1 * E2, E02 = E0 * E2, E01 = E0 * E1;
+    const T num = fma(E12, h0, fma(E02, h1, E01 * h2));
+    const T den = fma((T)6, E02, fma((T)3, E01, E12));
+    return fma(num, rcp_(den), c);
+}
+
+template <typename T>
 __device__ __forceinline__ T weno5(T a, T b, T c, T d, T e) {
     const T w0 = b - a, u = c - b, v = d - c, w3 = e - d;
     const T t0 = u - w0, s0 = fma((T)2, u, t0);
@@ -100,14 +109,21 @@ __device__ __forceinline__ T weno5(T a, T b, T c, T d, T e) {
     const T e0 = fma(t0, t0, fma(s0 * k, s0, eps));
     const T e1 = fma(t1, t1, fma(s1 * k, s1, eps));
     const T e2 = fma(t2, t2, fma(s2 * k, s2, eps));
-    const T E0 = e0 * e0, E1 = e1 * e1, E2 = e2 * e2;
-    const T E12 = E1 * E2, E02 = E0 * E2, E01 = E0 * E1;
     const T h0 = fma((T)(5.0 / 6.0), u, (T)(-1.0 / 3.0) * w0);   // r0 / 6
     const T h1 = fma((T)2, v, u);                                  // r1
     const T h2 = fma((T)2, v, (T)-0.5 * w3);                       // r2 / 2
-    const T num = fma(E12, h0, fma(E02, h1, E01 * h2));
-    const T den = fma((T)6, E02, fma((T)3, E01, E12));
-    return fma(num, rcp_(den), c);
+    T r = weno5_combine(e0, e1, e2, h0, h1, h2, c);
+    if constexpr (sizeof(T) == 4) {
+        // The fourth powers of the indicators leave the FP32 range once they pass ~1e9
+        // (steep characteristic fluxes behind strong shocks, LLF splits): the weights are
+        // homogeneous of degree zero in (e0, e1, e2), so such lanes evaluate them again
+        // with the indicators scaled by their maximum.  Other lanes are unchanged.
+        if (!isfinite(r)) {
+            const T sc = rcp_(fmax(e0, fmax(e1, e2)));
+            r = weno5_combine(e0 * sc, e1 * sc, e2 * sc, h0, h1, h2, c);
+        }
+    }
+    return r;
 }
 
 // TENO5 (Fu, Hu & Adams 2016) at the right face of c: the three 3-cell candidates of
