@@ -46,7 +46,7 @@ PEAK_HBM = 8.0e12                 # bytes/s
 # state (20 B), and write U0 (stage 1) or read it (stages 2, 3) (20 B)
 BYTES_PER_CELL_UPDATE = 82.5
 
-WORKLOADS = ["shockblobs_512e_6lvl", "blast_128e_3lvl", "kh_256e_5lvl", "multi_256"]
+WORKLOADS = ["shockblobs_512e_6lvl", "blast_128e_3lvl", "kh_256e_5lvl", "multi_256", "localblast_256e_5lvl"]
 
 
 def problems(name, steps):
@@ -54,7 +54,8 @@ def problems(name, steps):
     return {"shockblobs_512e_6lvl": lambda: [W.shock_blobs_mr6(steps=steps)],
             "blast_128e_3lvl": lambda: [W.blast_mr3(steps=steps)],
             "kh_256e_5lvl": lambda: [W.kh_mr5(steps=steps)],
-            "multi_256": lambda: W.multi_instance(steps=steps)}[name]()
+            "multi_256": lambda: W.multi_instance(steps=steps),
+            "localblast_256e_5lvl": lambda: [W.local_blast_mr5(steps=steps)]}[name]()
 
 
 def describe(name, pbs):
@@ -185,7 +186,7 @@ def run_gpu(pbs, dtype, batched, warmup, steps, timing=False, variant=None, prep
     import torch
     from paper_2012_04385_amd.mrfv import Solver
     t0 = time.perf_counter()
-    g = Solver(pbs, dtype=dtype, batched=batched).init()
+    g = Solver(pbs, dtype=dtype, batched=batched, capacity=capacity_for(pbs)).init()
     log(f"[bench] {dtype} batched={batched}: algo:Init {time.perf_counter() - t0:.1f} s, "
         f"{g.stats()[1]} leaves")
     done = prepare(g) if prepare else 0
@@ -214,6 +215,13 @@ def run_gpu(pbs, dtype, batched, warmup, steps, timing=False, variant=None, prep
     return g, cells, secs, kt
 
 
+def capacity_for(pbs):
+    """Slots for the benchmark contexts: every instance fully refined, at most 60,000 (a
+    localised feature on a deep tree never comes near its full refinement)."""
+    from paper_2012_04385_amd.mrfv import slot_capacity_for
+    return min(slot_capacity_for(pbs), 60000)
+
+
 def lts_leg(pbs, dtype, warmup, macro_steps):
     """Local time stepping (mrfv_step_lts, plain kernels in `dtype`) against global steps
     of the same kernels from the same start: simulated time advanced per second of wall
@@ -224,7 +232,7 @@ def lts_leg(pbs, dtype, warmup, macro_steps):
     lmax = pbs[0].lmax
     out = {"dtype": dtype, "path": "plain per-block kernels", "macro_steps": macro_steps,
            "micro_steps_per_macro_step": 1 << lmax}
-    g = Solver(pbs, dtype=dtype, batched=0).init()
+    g = Solver(pbs, dtype=dtype, batched=0, capacity=capacity_for(pbs)).init()
     for _ in range(warmup):
         g.step_lts()
     g.check()
@@ -240,7 +248,7 @@ def lts_leg(pbs, dtype, warmup, macro_steps):
     out.update({"ms_per_macro_step": 1e3 * secs / macro_steps, "sim_time_per_s": sim / secs,
                 "cell_updates_per_s": cells / secs, "leaves_final": g.stats()[1]})
     free(g)
-    g = Solver(pbs, dtype=dtype, batched=0).init()
+    g = Solver(pbs, dtype=dtype, batched=0, capacity=capacity_for(pbs)).init()
     for _ in range(warmup * (1 << lmax)):
         g.step()
     g.check()
@@ -258,6 +266,25 @@ def lts_leg(pbs, dtype, warmup, macro_steps):
     out.update({"global_steps": steps, "global_ms_per_step": 1e3 * secs_g / steps,
                 "global_sim_time_per_s": sim_g / secs_g,
                 "time_to_solution_speedup": (sim / secs) / (sim_g / secs_g)})
+    if dtype == "f32":
+        # context: global steps on the fused batched path (step graphs) over the same time
+        g = Solver(pbs, dtype=dtype, batched=2, capacity=capacity_for(pbs)).init()
+        for _ in range(warmup * (1 << lmax)):
+            g.step()
+        g.check()
+        torch.cuda.synchronize()
+        sim_f, steps_f = 0.0, 0
+        t0 = time.perf_counter()
+        while sim_f < sim:
+            g.step()
+            sim_f += float(g.dt.cpu()[0])
+            steps_f += 1
+        torch.cuda.synchronize()
+        secs_f = time.perf_counter() - t0
+        g.check()
+        free(g)
+        out.update({"fused_global_ms_per_step": 1e3 * secs_f / steps_f,
+                    "speedup_vs_fused_global": (sim / secs) / (sim_f / secs_f)})
     # the path's own roofline: the stiffened-gas FLOP model per cell-update over the whole
     # macro step's rate (a lower bound of its flux kernel's rate)
     peak = PEAK_FP32_VECTOR if dtype == "f32" else PEAK_FP64_VECTOR

@@ -289,6 +289,18 @@ def blast_mr3(seed_k: int = 2, steps: int = 50) -> Problem:
                            "outer": (0.125, 0.1)})
 
 
+def local_blast_mr5(seed_k: int = 10, steps: int = 20) -> Problem:
+    """A localised 3D feature on a 5-level tree, the kind of tree local time stepping is for:
+    a blast of radius 0.05 at the centre of a periodic unit box, (rho, p) = (1, 10) inside
+    and (0.125, 0.1) outside, at rest, no noise; l_max = 4, 4^3 level-0 blocks (256^3
+    effective).  After algo:Init 1240 leaves, 512 of them on level 4."""
+    return Problem(name="localblast_256e_5lvl", kind="blast", lmax=4, n0=(4, 4, 4), dx0=1.0 / 64,
+                   bc=(0, 0, 0), steps=steps, seed=BASE_SEED + seed_k, noise=0.0, eps=1e-3,
+                   scale_rho=1.0, scale_E=25.0,
+                   params={"centre": (0.5, 0.5, 0.5), "radius": 0.05, "inner": (1.0, 10.0),
+                           "outer": (0.125, 0.1)})
+
+
 def kh_mr5(seed_k: int = 3, steps: int = 20) -> Problem:
     """5-level MR, 256^3 effective: Kelvin-Helmholtz shear layer (rho = 2|1, u = +-0.5,
     p = 2.5) with seeded sinusoidal v-perturbations of amplitude 0.01 over modes 1-8."""
