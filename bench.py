@@ -223,16 +223,22 @@ def capacity_for(pbs):
 
 
 def lts_leg(pbs, dtype, warmup, macro_steps):
-    """Local time stepping (mrfv_step_lts, plain kernels in `dtype`) against global steps
-    of the same kernels from the same start: simulated time advanced per second of wall
-    clock (time to solution), and cell-updates per second per RK stage (leaf cells times
-    their own steps)."""
+    """Local time stepping (mrfv_step_lts on a per-block context in `dtype`: FP32 takes the
+    flux divergence from the fused stage kernel in its default launch shape, FP64 from the
+    plain flux kernel) against global steps of the same context from the same start, and
+    in FP32 against global steps of the batched path in the same shape: simulated time
+    advanced per second of wall clock (time to solution), and cell-updates per second per
+    RK stage (leaf cells times their own steps)."""
     import torch
     from paper_2012_04385_amd.mrfv import Solver
     lmax = pbs[0].lmax
-    out = {"dtype": dtype, "path": "plain per-block kernels", "macro_steps": macro_steps,
+    path = ("fused stage kernel (flux divergence) + local time stepping kernels" if dtype == "f32"
+            else "plain per-block kernels")
+    out = {"dtype": dtype, "path": path, "macro_steps": macro_steps,
            "micro_steps_per_macro_step": 1 << lmax}
     g = Solver(pbs, dtype=dtype, batched=0, capacity=capacity_for(pbs)).init()
+    if dtype == "f32":
+        out["launch_shape"] = g.rhs_variants()[g.set_rhs_variant(-1)]
     for _ in range(warmup):
         g.step_lts()
     g.check()
@@ -267,7 +273,8 @@ def lts_leg(pbs, dtype, warmup, macro_steps):
                 "global_sim_time_per_s": sim_g / secs_g,
                 "time_to_solution_speedup": (sim / secs) / (sim_g / secs_g)})
     if dtype == "f32":
-        # context: global steps on the fused batched path (step graphs) over the same time
+        # global steps on the fused batched path (step graphs) over the same time, in the
+        # launch shape the local time stepping context used
         g = Solver(pbs, dtype=dtype, batched=2, capacity=capacity_for(pbs)).init()
         for _ in range(warmup * (1 << lmax)):
             g.step()

@@ -324,7 +324,8 @@ int mrfv_fused_stage(mrfv_ctx *ctx, int32_t stage, const double *dt_dev, void *U
  * per SIMD the register allocation aims at (1: the compiler's choice); shapes_host[4v+3]
  * is 1 when the stencils are always loaded through per-lane pointers (otherwise through
  * one buffer resource whenever a workgroup's source blocks lie within 4 GiB).  Every
- * variant gives bitwise the same result.  rhs_variant sets the variant
+ * variant gives bitwise the same result.  A new context takes the shape GP 2 x 512
+ * threads (the first variant of the other kernels).  rhs_variant sets the variant
  * when set >= 0 (captured step graphs are re-captured), writes the number of variants
  * and their shapes (each may be NULL) and returns the current variant (>= 0) or an
  * error.  Host only. */

@@ -970,6 +970,9 @@ int do_lts_macro(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt, int64_t *cell_up
     T *D = (T *)ctx->d_D, *FF = (T *)ctx->d_FF, *F = (T *)ctx->d_Fp, *H0 = (T *)ctx->d_H0,
       *ACC = (T *)ctx->d_ACC;
     const size_t cap = ctx->cfg.slot_capacity;
+    // FP32 flux divergence from the fused stage kernel (not Tait's system, which it lacks),
+    // in the context's launch shape
+    const bool fused = sizeof(T) == 4 && flux_kernel(ctx) != 4;
     int64_t cells = 0;
     for (int l = 0; l <= top; ++l) cells += (int64_t)L.leaf_cnt[l] * ((int64_t)1 << l) * CELLS_I;
     if (cell_updates) *cell_updates = cells;
@@ -984,9 +987,19 @@ int do_lts_macro(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt, int64_t *cell_up
         const int lo_start = r == 0 ? 0 : lts_lowest_ending(lmax, r - 1);
         for (int st = 0; st < 3; ++st) {
             const int lo_rhs = st == 0 ? lo_start : lo_end;
-            // flux divergence of the leaves being evaluated, after their copied halos
+            // flux divergence of the leaves being evaluated, after their copied halos; in
+            // FP32 the fused stage kernel evaluates it (reading same-level neighbours in
+            // place, so only boundary halos are filled) straight into F
             for (int l = lo_rhs; l <= top; ++l) {
                 const WorkList w = wlist(ctx, desc_leaf(l));
+                if (fused) {
+                    HIP_OK(launch_fill_halos<T>(U, w, ctx->tb, (FillMode)(FILL_MISSING_FACES | FILL_PRESENT),
+                                                ctx->stream));
+                    HIP_OK(launch_rhs_update_f32(ctx->cfg.scheme, ctx->rhs_variant, -1, dt, (const float *)U, (float *)F,
+                                                 (float *)U0, wlist(ctx, desc_leaf(l), 1 << 30), ctx->tb,
+                                                 ctx->d_inst, (float *)FF, ctx->d_err, 0, nullptr, ctx->stream));
+                    continue;
+                }
                 HIP_OK(launch_fill_halos<T>(U, w, ctx->tb, (FillMode)(FILL_FACES | FILL_PRESENT), ctx->stream));
                 HIP_OK(launch_flux<T>(flux_kernel(ctx), U, w, ctx->tb, ctx->d_inst, D, FF, ctx->stream));
                 HIP_OK(launch_lts_combine<T>(D, F, w, ctx->tb, ctx->d_inst, U, ctx->stream));
@@ -1045,6 +1058,7 @@ int mrfv_create(mrfv_ctx **out, const mrfv_config *cfg, const mrfv_instance *ins
         return code;
     };
     ctx->cfg = *cfg;
+    ctx->rhs_variant = rhs_default_variant(cfg->scheme);
     if (cfg->dtype != MRFV_F32 && cfg->dtype != MRFV_F64) return bail(MRFV_EINVAL);
     if (cfg->n_instances < 1 || cfg->n_instances > 4095) return bail(MRFV_EINVAL);
     if (cfg->slot_capacity < 1 || cfg->slot_capacity > (1 << 22)) return bail(MRFV_EINVAL);

@@ -25,10 +25,18 @@ namespace mrfv {
 
 namespace {
 
-constexpr int TPB = 256;
+constexpr int TPB = 256;                  // one thread per cell of a z-plane
 constexpr int SLAB = 3 * FACE;            // halo cells of one face that the flux reads
-constexpr int UPD_INTERIOR = CELLS_I / TPB;   // 16 workgroup rows for the interior
-constexpr int UPD_PARTS = UPD_INTERIOR + 6 * 3 + 6;
+// The stage update runs four workgroups per leaf, each over four interior z-planes (its
+// loads issued together) and six of the leaf's 24 face pieces (18 halo layers, 6 face-flux
+// sums), most of which are skipped: one workgroup per plane and piece took 41 % longer in
+// FP32 (27 % in FP64), most of it in starting workgroups that had little or nothing to do.
+// The combine keeps one workgroup per z-plane (with four planes each it took 7 % longer,
+// at three waves per SIMD instead of eight).
+constexpr int PLANES = 4;
+constexpr int PARTS = NI / PLANES;
+constexpr int PIECES = (6 * 3 + 6) / PARTS;
+static_assert(NI % PLANES == 0 && (6 * 3 + 6) % PARTS == 0, "parts must tile the leaf");
 
 __device__ __forceinline__ int pidx(int q, int k, int j, int i) {
     return ((q * NP + k) * NP + j) * NP + i;
@@ -105,8 +113,9 @@ __global__ __launch_bounds__(TPB) void k_lts_combine(const T *__restrict__ D, T 
     }
 }
 
-// blockIdx.y: [0, 16) interior rows of 256 cells; [16, 34) face side * 3 + halo layer;
-// [34, 40) the face-flux sums of one side.
+// blockIdx.y = part: interior z-planes [PLANES * part, PLANES * (part + 1)) and face pieces
+// [PIECES * part, PIECES * (part + 1)) of 24: side * 3 + halo layer for pieces below 18,
+// then the face-flux sums of one side.
 template <typename T>
 __global__ __launch_bounds__(TPB) void k_lts_update(int stage, const double *__restrict__ dt,
                                                     T *U, T *U0, T *H0, const T *__restrict__ F,
@@ -125,55 +134,69 @@ __global__ __launch_bounds__(TPB) void k_lts_update(int stage, const double *__r
         const T a = lts_stage_coef<T>(stage);
         T *ub = U + (size_t)slot * 5 * CELLS_P;
         const T *fb = F + (size_t)slot * 5 * CELLS_P;
-        if (part < UPD_INTERIOR) {
-            const int c = part * TPB + tid;
-            const int o = ((c / FACE + HW) * NP + (c / NI) % NI + HW) * NP + c % NI + HW;
+        {
+            // interior: every load of the four planes before the first store (U is read
+            // and written through the same pointer, so the compiler keeps program order)
             T *u0b = U0 + (size_t)slot * 5 * CELLS_I;
-            T un[5];
+            int c[PLANES], o[PLANES];
+            T us[PLANES][5], u0[PLANES][5], fl[PLANES][5];
 #pragma unroll
-            for (int q = 0; q < 5; ++q) {
-                const T us = ub[o + q * CELLS_P];
-                T u0;
-                if (stage == 0) {
-                    u0 = us;
-                    u0b[q * CELLS_I + c] = us;
-                } else {
-                    u0 = u0b[q * CELLS_I + c];
+            for (int k = 0; k < PLANES; ++k) {
+                c[k] = (part * PLANES + k) * FACE + tid;
+                o[k] = ((c[k] / FACE + HW) * NP + (c[k] / NI) % NI + HW) * NP + c[k] % NI + HW;
+#pragma unroll
+                for (int q = 0; q < 5; ++q) {
+                    us[k][q] = ub[o[k] + q * CELLS_P];
+                    fl[k][q] = fb[o[k] + q * CELLS_P];
+                    u0[k][q] = stage == 0 ? us[k][q] : u0b[q * CELLS_I + c[k]];
                 }
-                un[q] = u0 + a * ((us - u0) + (T)dtl * fb[o + q * CELLS_P]);
-                ub[o + q * CELLS_P] = un[q];
             }
-            if (!lts_physical(un, P)) atomicOr(err, 1);
-        } else if (part < UPD_INTERIOR + 18) {
-            const int f = part - UPD_INTERIOR, side = f / 3, h = f % 3;
-            if (nbr[(size_t)slot * 27 + face_region(side)] != -1) continue;   // not a jump face
-            const int d = side >> 1, hi = side & 1;
-            const int p = hi ? HW + NI + h : HW - 3 + h;
-            T *h0 = H0 + ((size_t)slot * 6 + side) * 5 * SLAB + h * FACE + tid;
+            bool ok = true;
 #pragma unroll
-            for (int q = 0; q < 5; ++q) {
-                const int n = plane_cell(q, d, p, tid >> 4, tid & 15);
-                const T us = ub[n];
-                T u0;
-                if (stage == 0) {
-                    u0 = us;
-                    h0[q * SLAB] = us;
-                } else {
-                    u0 = h0[q * SLAB];
+            for (int k = 0; k < PLANES; ++k) {
+                T un[5];
+#pragma unroll
+                for (int q = 0; q < 5; ++q) {
+                    if (stage == 0) u0b[q * CELLS_I + c[k]] = us[k][q];
+                    un[q] = u0[k][q] + a * ((us[k][q] - u0[k][q]) + (T)dtl * fl[k][q]);
+                    ub[o[k] + q * CELLS_P] = un[q];
                 }
-                ub[n] = u0 + a * ((us - u0) + (T)dtl * fb[n]);
+                ok = ok && lts_physical(un, P);
             }
-        } else {
-            // only faces that a coarse cell adjustment reads: jump faces (the fine side) and
-            // faces whose same-level neighbour is refined (the coarse side)
-            const int side = part - UPD_INTERIOR - 18;
-            const int nbs = nbr[(size_t)slot * 27 + face_region(side)];
-            if (!(nbs == -1 || (nbs >= 0 && !meta[nbs].leaf))) continue;
-            const double bw = stage == 2 ? 2.0 / 3.0 : 1.0 / 6.0;
-            const T w = (T)(bw * dtl);
-            const size_t base = ((size_t)slot * 6 + side) * 5 * FACE + tid;
+            if (!ok) atomicOr(err, 1);
+        }
+        for (int f = part * PIECES; f < (part + 1) * PIECES; ++f) {
+            if (f < 18) {
+                const int side = f / 3, h = f % 3;
+                if (nbr[(size_t)slot * 27 + face_region(side)] != -1) continue;   // not a jump face
+                const int d = side >> 1, hi = side & 1;
+                const int p = hi ? HW + NI + h : HW - 3 + h;
+                T *h0 = H0 + ((size_t)slot * 6 + side) * 5 * SLAB + h * FACE + tid;
 #pragma unroll
-            for (int q = 0; q < 5; ++q) ACC[base + q * FACE] += w * FF[base + q * FACE];
+                for (int q = 0; q < 5; ++q) {
+                    const int n = plane_cell(q, d, p, tid >> 4, tid & 15);
+                    const T us = ub[n];
+                    T u0;
+                    if (stage == 0) {
+                        u0 = us;
+                        h0[q * SLAB] = us;
+                    } else {
+                        u0 = h0[q * SLAB];
+                    }
+                    ub[n] = u0 + a * ((us - u0) + (T)dtl * fb[n]);
+                }
+            } else {
+                // only faces that a coarse cell adjustment reads: jump faces (the fine side)
+                // and faces whose same-level neighbour is refined (the coarse side)
+                const int side = f - 18;
+                const int nbs = nbr[(size_t)slot * 27 + face_region(side)];
+                if (!(nbs == -1 || (nbs >= 0 && !meta[nbs].leaf))) continue;
+                const double bw = stage == 2 ? 2.0 / 3.0 : 1.0 / 6.0;
+                const T w = (T)(bw * dtl);
+                const size_t base = ((size_t)slot * 6 + side) * 5 * FACE + tid;
+#pragma unroll
+                for (int q = 0; q < 5; ++q) ACC[base + q * FACE] += w * FF[base + q * FACE];
+            }
         }
     }
 }
@@ -238,7 +261,7 @@ template <typename T>
 hipError_t launch_lts_combine(const T *D, T *F, const WorkList &wl, const DevTables &tb,
                               const InstDev *inst, const T *U, hipStream_t st) {
     if (wl.grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_lts_combine<T>, dim3(wl.grid, CELLS_I / TPB), dim3(TPB), 0, st, D, F, wl, tb.meta,
+    hipLaunchKernelGGL(k_lts_combine<T>, dim3(wl.grid, NI), dim3(TPB), 0, st, D, F, wl, tb.meta,
                        inst, U);
     return hipGetLastError();
 }
@@ -248,7 +271,7 @@ hipError_t launch_lts_update(int stage, const double *dt, T *U, T *U0, T *H0, co
                              const T *FF, T *ACC, const WorkList &wl, const DevTables &tb,
                              const InstDev *inst, int32_t *err, hipStream_t st) {
     if (wl.grid <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_lts_update<T>, dim3(wl.grid, UPD_PARTS), dim3(TPB), 0, st, stage, dt, U,
+    hipLaunchKernelGGL(k_lts_update<T>, dim3(wl.grid, PARTS), dim3(TPB), 0, st, stage, dt, U,
                        U0, H0, F, FF, ACC, wl, tb.meta, tb.nbr, inst, err);
     return hipGetLastError();
 }

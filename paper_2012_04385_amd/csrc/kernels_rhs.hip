@@ -1001,6 +1001,11 @@ void k_rhs_update(int stage, const double *__restrict__ dt,
                 lq[q] = -D[p][q] * inv_dx;
             }
             if (P.has_source) add_source(P, us, lq);   // uniform per workgroup
+            if (stage < 0) {   // flux divergence only (local time stepping): L into Uout
+#pragma unroll
+                for (int q = 0; q < 5; ++q) ob[o + q * CELLS_P] = lq[q];
+                continue;
+            }
 #pragma unroll
             for (int q = 0; q < 5; ++q) {
                 T u0;
@@ -1305,6 +1310,10 @@ static void launch_variant(int stage, const double *dt, const float *Uin, float 
 }
 
 int rhs_variants(int scheme) { return scheme == SCH_ROE_WENO5 ? N_RHS_VARIANTS : N_ALT_VARIANTS; }
+
+// Until a context is tuned it takes variant 7 (two z-planes per group, 512 threads), the
+// shape the autotuner chose on the benchmark trees; the other schemes list it first.
+int rhs_default_variant(int scheme) { return scheme == SCH_ROE_WENO5 ? 7 : 0; }
 
 void rhs_variant_shape(int scheme, int v, int *gp, int *tpb, int *wpe, int *ptr) {
     if (scheme != SCH_ROE_WENO5) v = ALT_VARIANT[v];

@@ -301,11 +301,15 @@ hipError_t launch_update(int stage, const double *dt, T *U, T *U0, const T *L,
 // (all give the same result).
 // restrict_parents: leaves with meta.srestr also write the restriction of their new state
 // (all components) into their parent's octant of Uout.
+// stage < 0: no update; Uout (a padded field) receives the interior flux divergence
+// L = -sum_d dF_d / dx + S (local time stepping); U0 is not touched, restrict_parents and
+// cflmax must be 0 / null.
 hipError_t launch_rhs_update_f32(int scheme, int variant, int stage, const double *dt, const float *Uin,
                                  float *Uout, float *U0, const WorkList &leaves, const DevTables &tb,
                                  const InstDev *inst, float *FF, int32_t *err, int restrict_parents,
                                  double *cflmax, hipStream_t st);   // cflmax: null, or CFL block maxima out
 int rhs_variants(int scheme);
+int rhs_default_variant(int scheme);   // the shape fastest on the measured trees
 void rhs_variant_shape(int scheme, int v, int *gp, int *tpb, int *wpe, int *ptr);
 template <typename T>
 hipError_t launch_reflux_update(int stage, const double *dt, T *U, const T *FF,
@@ -409,7 +413,7 @@ struct mrfv_ctx {
     int64_t h_steps = 0;
     int32_t *d_slots = nullptr;        // [cap] scratch slot list
     int32_t *d_slots2 = nullptr;       // [cap] second scratch slot list
-    int rhs_variant = 0;               // launch shape of the fused kernel (autotuned)
+    int rhs_variant = 0;               // launch shape of the fused kernel (default or autotuned)
     double *d_prim = nullptr;          // IC staging [batch][5][16^3]
     int prim_batch = 0;
     int lists_cap = 0;

@@ -8,8 +8,10 @@ carried by a uniform flow, so that waves cross the jumps.
 Tolerances: FP64 -- 1e-12 relative on leaf states after the macro steps (the plain
 kernels' face fluxes differ from the oracle's in summation order at the 1e-16 level,
 carried through 8 micro steps), dt bitwise-close (1e-14), trees identical with
-adaptation; FP32 -- 5e-6 relative (FP32 rounding of O(1) states over 24 integrated
-stages).  Conservation on the GPU is checked against its own start, like the oracle's.
+adaptation; FP32 (flux divergence from the fused kernel, batched and per-block contexts)
+-- 5e-6 relative (FP32 rounding of O(1) states over 24 integrated stages), and 1e-6
+against the fused global step with one level.  Conservation on the GPU is checked
+against its own start, like the oracle's.
 """
 import numpy as np
 import pytest
@@ -60,7 +62,7 @@ def _worst(o, g):
     return max(np.abs(gl[k] - v).max() / np.abs(v).max() for k, v in ol.items())
 
 
-@pytest.mark.parametrize("dtype,batched,tol", [("f64", False, 1e-12), ("f32", True, 5e-6)])
+@pytest.mark.parametrize("dtype,batched,tol", [("f64", False, 1e-12), ("f32", True, 5e-6), ("f32", False, 5e-6)])
 def test_lts_static_tree(orc, torch_mod, dtype, batched, tol):
     o, g = _pair(orc, dtype, batched=batched)
     print(f"[lts] static tree {dtype} batched={batched}", flush=True)
@@ -130,6 +132,33 @@ def test_lts_single_level_is_the_global_step(orc, torch_mod):
     assert len(keys) == 8 and A.keys() == B.keys()
     for k in A:
         assert np.array_equal(A[k], B[k]), k
+
+
+def test_lts_single_level_fp32_is_the_fused_step(torch_mod):
+    # FP32 local time stepping takes L from the fused kernel's flux-divergence mode and
+    # integrates it in its own update; with one level that is the fused global step up to
+    # the rounding of the update's operation order
+    from paper_2012_04385_amd.mrfv import Solver
+    pb = W.uniform_flow(lmax=0, n0=(2, 2, 2))
+    sims = [Solver([pb], dtype="f32", batched=b, adapt=0).init() for b in (False, 2)]
+    for g in sims:
+        for r in g.blocks():
+            k = tuple(int(v) for v in r[2:6])
+            g.U[int(r[0]), :, H:H + N, H:H + N, H:H + N] = torch_mod.as_tensor(
+                _pulse(pb, k), dtype=g.tdtype, device=g.device)
+    a, b = sims
+    for _ in range(3):
+        a.step_lts()
+        b.step()
+        torch_mod.cuda.synchronize()
+        da, db = float(a.dt.cpu()[0]), float(b.dt.cpu()[0])
+        assert abs(da - db) <= 1e-6 * db, (da, db)
+    a.check()
+    A, B = a.leaf_states(), b.leaf_states()
+    assert A.keys() == B.keys()
+    worst = max(np.abs(A[k] - B[k]).max() / np.abs(B[k]).max() for k in A)
+    print(f"[lts] fp32 single level vs fused step {worst:.3e}", flush=True)
+    assert worst < 1e-6, worst
 
 
 def test_lts_rejects_mixed_lmax(torch_mod):

@@ -536,6 +536,7 @@ def test_rhs_variants_bitwise_and_autotune(torch_mod):
         assert len(shapes) >= 4 and all(abs(t) >= 256 and 16 % gp == 0 for gp, t, _, _ in shapes)
         assert any(t < 0 for _, t, _, _ in shapes) and any(w > 1 for _, _, w, _ in shapes)
         assert any(p == 1 for _, _, _, p in shapes)     # the per-lane pointer loads
+        assert shapes[g0.set_rhs_variant(-1)] == (2, 512, 1, 0)   # the untuned default
         del g0
         for v in range(len(shapes)):
             g = Solver([pb], dtype="f32", batched=batched).init()

@@ -146,7 +146,7 @@ def test_variants_bitwise(torch_mod, scheme):
     ref = None
     g0 = Solver([pb], dtype="f32", batched=1).init()
     n = len(g0.rhs_variants())
-    assert n == 3
+    assert n == 3 and g0.set_rhs_variant(-1) == 0 and g0.rhs_variants()[0] == (2, 512, 1, 0)
     del g0
     for v in range(n):
         g = Solver([pb], dtype="f32", batched=1).init()
