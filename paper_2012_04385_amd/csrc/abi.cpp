@@ -191,9 +191,11 @@ int do_fill(mrfv_ctx *ctx, T *U, int max_level, int mode = FILL_ALL, bool with_p
         } else {
             // a stage fills only the parents its predictions read; the fill before the
             // details (FILL_MISSING) all non-leaf blocks, whose details are judged too
+            // (of those only the halo regions the predictions read)
             const int pw = m == FILL_MISSING_FACES ? desc_pfill(l) : desc_par(l);
+            const int pm = m == FILL_MISSING_FACES ? FILL_MASKED : 0;
             if (with_parents && !merged)
-                HIP_OK(launch_fill_halos<T>(U, wlist(ctx, pw, 1024), ctx->tb, (FillMode)(FILL_ALL | qsel),
+                HIP_OK(launch_fill_halos<T>(U, wlist(ctx, pw, 1024), ctx->tb, (FillMode)(FILL_ALL | qsel | pm),
                                             ctx->stream));
             const int which = m == FILL_FACES ? desc_leaf(l)
                               : m == FILL_MISSING_FACES ? desc_jleaf(l) : desc_jleaf26(l);

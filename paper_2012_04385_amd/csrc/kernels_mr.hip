@@ -183,6 +183,7 @@ __global__ __launch_bounds__(TPB) void k_fill_halos(T *__restrict__ U, WorkList 
     __shared__ T Y[PR_Y];
     const int nb = wl.count();
     const int tid = threadIdx.x;
+    const int nreg = (mode & FILL_FACES) ? 6 : 26;
     // blocks in XCD-aware order, as in k_details
     for (int base = 0; base < nb; base += gridDim.x) {
         const int m_round = min(nb - base, (int)gridDim.x);
@@ -190,162 +191,166 @@ __global__ __launch_bounds__(TPB) void k_fill_halos(T *__restrict__ U, WorkList 
         if (bi >= m_round) continue;   // uniform per workgroup
         const int slot = wl.at(base + bi);
         const BlockMeta m = meta[slot];
-        const Region g = make_region(mode, blockIdx.y, EXT ? m.zg : (m.zg & 63));
-        // mirrored axes as bits (no run-time indexing into the region's arrays, which would
-        // put them in scratch memory)
-        const int mirbits = EXT ? g.mirbits : 0;
-        if (EXT && g.fix >= 0) {
-            // fixed values: the state of the layer (distance from the face) along the last
-            // fixed axis, with the normal momentum of later symmetry axes reversed
-            if (!bcfix) continue;
-            const int fa = g.fix & 3, fhi = g.fix >> 2;
-            const T *fv = bcfix + ((size_t)(m.inst * 6 + 2 * fa + fhi) * MAX_LEVELS + m.level) * 4 * 5;
+        // regions blockIdx.y, blockIdx.y + gridDim.y, ... of the block
+        for (int ridx = blockIdx.y; ridx < nreg; ridx += gridDim.y) {
+            if ((mode & FILL_MASKED) && !((m.pmask >> ridx) & 1)) continue;   // not read
+            const Region g = make_region(mode, ridx, EXT ? m.zg : (m.zg & 63));
+            // mirrored axes as bits (no run-time indexing into the region's arrays, which would
+            // put them in scratch memory)
+            const int mirbits = EXT ? g.mirbits : 0;
+            if (EXT && g.fix >= 0) {
+                // fixed values: the state of the layer (distance from the face) along the last
+                // fixed axis, with the normal momentum of later symmetry axes reversed
+                if (!bcfix) continue;
+                const int fa = g.fix & 3, fhi = g.fix >> 2;
+                const T *fv = bcfix + ((size_t)(m.inst * 6 + 2 * fa + fhi) * MAX_LEVELS + m.level) * 4 * 5;
+                T *dst = U + (size_t)slot * 5 * CELLS_P;
+                const int ncell = g.n[0] * g.n[1] * g.n[2];
+                const Div d0(g.n[0]), d1(g.n[1]);
+                const bool re = (mode & FILL_RHO_E) != 0;
+                const int flipbits = mirbits & ~((2 << fa) - 1);   // mirrored axes after fa
+                for (int e = tid; e < ncell; e += TPB) {
+                    const int e1 = d0.quot(e), e2 = d1.quot(e1);
+                    const int ci = g.lo[0] + e - e1 * g.n[0], cj = g.lo[1] + e1 - e2 * g.n[1], ck = g.lo[2] + e2;
+                    const int cf = fa == 0 ? ci : (fa == 1 ? cj : ck);
+                    const int layer = fhi ? cf - (HW + NI) : HW - 1 - cf;
+    #pragma unroll
+                    for (int q = 0; q < 5; ++q) {
+                        if (re && q != 0 && q != 4) continue;
+                        const bool flip = q >= 1 && q <= 3 && ((flipbits >> (q - 1)) & 1);
+                        const T v = fv[layer * 5 + q];
+                        dst[pidx(q, ck, cj, ci)] = flip ? -v : v;
+                    }
+                }
+                continue;
+            }
+            const bool clamped = g.clamp[0] >= 0 || g.clamp[1] >= 0 || g.clamp[2] >= 0;
+            const bool own = g.r[0] == 0 && g.r[1] == 0 && g.r[2] == 0;
+            const int src = own ? slot : nbr[(size_t)slot * 27 + (g.r[2] + 1) * 9 + (g.r[1] + 1) * 3 + (g.r[0] + 1)];
+            if ((mode & FILL_MISSING) && src >= 0 && !clamped) continue;   // read in place
+            if ((mode & FILL_PRESENT) && src < 0) continue;                // keeps its values
             T *dst = U + (size_t)slot * 5 * CELLS_P;
             const int ncell = g.n[0] * g.n[1] * g.n[2];
-            const Div d0(g.n[0]), d1(g.n[1]);
+            const Div dc(ncell), d0(g.n[0]), d1(g.n[1]);
             const bool re = (mode & FILL_RHO_E) != 0;
-            const int flipbits = mirbits & ~((2 << fa) - 1);   // mirrored axes after fa
-            for (int e = tid; e < ncell; e += TPB) {
-                const int e1 = d0.quot(e), e2 = d1.quot(e1);
-                const int ci = g.lo[0] + e - e1 * g.n[0], cj = g.lo[1] + e1 - e2 * g.n[1], ck = g.lo[2] + e2;
-                const int cf = fa == 0 ? ci : (fa == 1 ? cj : ck);
-                const int layer = fhi ? cf - (HW + NI) : HW - 1 - cf;
-#pragma unroll
-                for (int q = 0; q < 5; ++q) {
-                    if (re && q != 0 && q != 4) continue;
-                    const bool flip = q >= 1 && q <= 3 && ((flipbits >> (q - 1)) & 1);
-                    const T v = fv[layer * 5 + q];
-                    dst[pidx(q, ck, cj, ci)] = flip ? -v : v;
+            const int nq = re ? 2 : 5;
+            // symmetry: the momentum component normal to a mirrored boundary changes sign
+            // (mirrored on two axes: both components)
+            auto msign = [&](int q) {
+                return (q >= 1 && q <= 3 && ((mirbits >> (q - 1)) & 1)) ? (T)-1 : (T)1;
+            };
+            if (src >= 0) {
+                const T *sb = U + (size_t)src * 5 * CELLS_P;
+                if (mirbits == 0) {   // copies and zero-gradient clamps (uniform per workgroup)
+    #pragma unroll 4
+                    for (int t = tid; t < nq * ncell; t += TPB) {   // unrolled: several loads in flight
+                        const int qi = dc.quot(t), e = t - qi * ncell;
+                        const int q = re ? 4 * qi : qi;
+                        const int e1 = d0.quot(e), e2 = d1.quot(e1);
+                        const int i = g.lo[0] + e - e1 * g.n[0], j = g.lo[1] + e1 - e2 * g.n[1], k = g.lo[2] + e2;
+                        const int si = g.clamp[0] >= 0 ? g.clamp[0] : i - NI * g.r[0];
+                        const int sj = g.clamp[1] >= 0 ? g.clamp[1] : j - NI * g.r[1];
+                        const int sk = g.clamp[2] >= 0 ? g.clamp[2] : k - NI * g.r[2];
+                        dst[pidx(q, k, j, i)] = sb[pidx(q, sk, sj, si)];
+                    }
+                } else {              // some axis mirrored
+    #pragma unroll 4
+                    for (int t = tid; t < nq * ncell; t += TPB) {
+                        const int qi = dc.quot(t), e = t - qi * ncell;
+                        const int q = re ? 4 * qi : qi;
+                        const int e1 = d0.quot(e), e2 = d1.quot(e1);
+                        const int i = g.lo[0] + e - e1 * g.n[0], j = g.lo[1] + e1 - e2 * g.n[1], k = g.lo[2] + e2;
+                        const int si = (mirbits & 1) ? mir_index(g, 0) - i : (g.clamp[0] >= 0 ? g.clamp[0] : i - NI * g.r[0]);
+                        const int sj = (mirbits & 2) ? mir_index(g, 1) - j : (g.clamp[1] >= 0 ? g.clamp[1] : j - NI * g.r[1]);
+                        const int sk = (mirbits & 4) ? mir_index(g, 2) - k : (g.clamp[2] >= 0 ? g.clamp[2] : k - NI * g.r[2]);
+                        dst[pidx(q, k, j, i)] = msign(q) * sb[pidx(q, sk, sj, si)];
+                    }
                 }
+                continue;
             }
-            continue;
-        }
-        const bool clamped = g.clamp[0] >= 0 || g.clamp[1] >= 0 || g.clamp[2] >= 0;
-        const bool own = g.r[0] == 0 && g.r[1] == 0 && g.r[2] == 0;
-        const int src = own ? slot : nbr[(size_t)slot * 27 + (g.r[2] + 1) * 9 + (g.r[1] + 1) * 3 + (g.r[0] + 1)];
-        if ((mode & FILL_MISSING) && src >= 0 && !clamped) continue;   // read in place
-        if ((mode & FILL_PRESENT) && src < 0) continue;                // keeps its values
-        T *dst = U + (size_t)slot * 5 * CELLS_P;
-        const int ncell = g.n[0] * g.n[1] * g.n[2];
-        const Div dc(ncell), d0(g.n[0]), d1(g.n[1]);
-        const bool re = (mode & FILL_RHO_E) != 0;
-        const int nq = re ? 2 : 5;
-        // symmetry: the momentum component normal to a mirrored boundary changes sign
-        // (mirrored on two axes: both components)
-        auto msign = [&](int q) {
-            return (q >= 1 && q <= 3 && ((mirbits >> (q - 1)) & 1)) ? (T)-1 : (T)1;
-        };
-        if (src >= 0) {
-            const T *sb = U + (size_t)src * 5 * CELLS_P;
-            if (mirbits == 0) {   // copies and zero-gradient clamps (uniform per workgroup)
-#pragma unroll 4
-                for (int t = tid; t < nq * ncell; t += TPB) {   // unrolled: several loads in flight
-                    const int qi = dc.quot(t), e = t - qi * ncell;
-                    const int q = re ? 4 * qi : qi;
-                    const int e1 = d0.quot(e), e2 = d1.quot(e1);
-                    const int i = g.lo[0] + e - e1 * g.n[0], j = g.lo[1] + e1 - e2 * g.n[1], k = g.lo[2] + e2;
-                    const int si = g.clamp[0] >= 0 ? g.clamp[0] : i - NI * g.r[0];
-                    const int sj = g.clamp[1] >= 0 ? g.clamp[1] : j - NI * g.r[1];
-                    const int sk = g.clamp[2] >= 0 ? g.clamp[2] : k - NI * g.r[2];
-                    dst[pidx(q, k, j, i)] = sb[pidx(q, sk, sj, si)];
+            if (m.parent < 0) continue;   // level 0 is complete: does not happen
+            // prediction from the parent, separably through LDS (x, then y, then z: the
+            // operation order of predict_cell)
+            const int o[3] = {m.bx & 1, m.by & 1, m.bz & 1};
+            int me[3], c0[3], p0[3], np[3];
+    #pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                // evaluation points and the first child index: the boundary cell (zero
+                // gradient), the mirror images of the region's cells (symmetry), or the region
+                const bool ma = (mirbits >> a) & 1;
+                me[a] = ma ? g.n[a] : (g.clamp[a] >= 0 ? 1 : g.n[a]);
+                c0[a] = ma ? mir_index(g, a) - (g.lo[a] + g.n[a] - 1) : (g.clamp[a] >= 0 ? g.clamp[a] : g.lo[a]);
+                p0[a] = parent_of(c0[a], o[a]) - 2;
+                np[a] = parent_of(c0[a] + me[a] - 1, o[a]) + 2 - p0[a] + 1;
+            }
+            const T *pu = U + (size_t)m.parent * 5 * CELLS_P;
+            const Div dp0(np[0]), dp1(np[1]), dm0(me[0]), dm1(me[1]);
+            // the parent region of component qi is loaded into registers while component
+            // qi - 1 runs its passes (at most PR_A / TPB values per thread)
+            constexpr int NAT = (PR_A + TPB - 1) / TPB;
+            const int na = np[0] * np[1] * np[2];
+            int aoff[NAT];
+    #pragma unroll
+            for (int n = 0; n < NAT; ++n) {
+                const int t = tid + n * TPB;
+                const int t1 = dp0.quot(t), kk = dp1.quot(t1);
+                const int ii = t - t1 * np[0], jj = t1 - kk * np[1];
+                aoff[n] = pidx(0, p0[2] + kk, p0[1] + jj, p0[0] + ii);
+            }
+            T av[NAT];
+            auto load_a = [&](int q) {
+    #pragma unroll
+                for (int n = 0; n < NAT; ++n)
+                    if (tid + n * TPB < na) av[n] = pu[q * CELLS_P + aoff[n]];
+            };
+            load_a(0);
+            for (int qi = 0; qi < nq; ++qi) {
+                const int q = re ? 4 * qi : qi;
+    #pragma unroll
+                for (int n = 0; n < NAT; ++n)
+                    if (tid + n * TPB < na) A[tid + n * TPB] = av[n];
+                if (qi + 1 < nq) load_a(re ? 4 * (qi + 1) : qi + 1);
+                __syncthreads();
+                const int nx = np[2] * np[1] * me[0];
+                for (int t = tid; t < nx; t += TPB) {
+                    const int t1 = dm0.quot(t), kk = dp1.quot(t1);
+                    const int ex = t - t1 * me[0], jj = t1 - kk * np[1];
+                    const int c = c0[0] + ex;
+                    const int I = parent_of(c, o[0]) - p0[0];
+                    const T *row = A + (kk * np[1] + jj) * np[0] + I;
+                    const T sx = ((c - HW) & 1) ? (T)-1 : (T)1;
+                    X[t] = pred1<T>(row[-2], row[-1], row[0], row[1], row[2], sx);
                 }
-            } else {              // some axis mirrored
-#pragma unroll 4
-                for (int t = tid; t < nq * ncell; t += TPB) {
-                    const int qi = dc.quot(t), e = t - qi * ncell;
-                    const int q = re ? 4 * qi : qi;
-                    const int e1 = d0.quot(e), e2 = d1.quot(e1);
-                    const int i = g.lo[0] + e - e1 * g.n[0], j = g.lo[1] + e1 - e2 * g.n[1], k = g.lo[2] + e2;
-                    const int si = (mirbits & 1) ? mir_index(g, 0) - i : (g.clamp[0] >= 0 ? g.clamp[0] : i - NI * g.r[0]);
-                    const int sj = (mirbits & 2) ? mir_index(g, 1) - j : (g.clamp[1] >= 0 ? g.clamp[1] : j - NI * g.r[1]);
-                    const int sk = (mirbits & 4) ? mir_index(g, 2) - k : (g.clamp[2] >= 0 ? g.clamp[2] : k - NI * g.r[2]);
-                    dst[pidx(q, k, j, i)] = msign(q) * sb[pidx(q, sk, sj, si)];
+                __syncthreads();
+                const int ny = np[2] * me[1] * me[0];
+                for (int t = tid; t < ny; t += TPB) {
+                    const int t1 = dm0.quot(t), kk = dm1.quot(t1);
+                    const int ex = t - t1 * me[0], ey = t1 - kk * me[1];
+                    const int c = c0[1] + ey;
+                    const int J = parent_of(c, o[1]) - p0[1];
+                    const T *col = X + (kk * np[1] + J) * me[0] + ex;
+                    const int st = me[0];
+                    const T sy = ((c - HW) & 1) ? (T)-1 : (T)1;
+                    Y[t] = pred1<T>(col[-2 * st], col[-st], col[0], col[st], col[2 * st], sy);
                 }
+                __syncthreads();
+                for (int t = tid; t < ncell; t += TPB) {
+                    const int t1 = d0.quot(t), dz = d1.quot(t1);
+                    const int dx = t - t1 * g.n[0], dy = t1 - dz * g.n[1];
+                    // evaluation point of the cell: its mirror image runs backwards
+                    const int ex = (mirbits & 1) ? g.n[0] - 1 - dx : (g.clamp[0] >= 0 ? 0 : dx);
+                    const int ey = (mirbits & 2) ? g.n[1] - 1 - dy : (g.clamp[1] >= 0 ? 0 : dy);
+                    const int ez = (mirbits & 4) ? g.n[2] - 1 - dz : (g.clamp[2] >= 0 ? 0 : dz);
+                    const int c = c0[2] + ez;
+                    const int K = parent_of(c, o[2]) - p0[2];
+                    const int st = me[0] * me[1];
+                    const T *col = Y + (K * me[1] + ey) * me[0] + ex;
+                    const T sz = ((c - HW) & 1) ? (T)-1 : (T)1;
+                    dst[pidx(q, g.lo[2] + dz, g.lo[1] + dy, g.lo[0] + dx)] =
+                        msign(q) * pred1<T>(col[-2 * st], col[-st], col[0], col[st], col[2 * st], sz);
+                }
+                __syncthreads();
             }
-            continue;
-        }
-        if (m.parent < 0) continue;   // level 0 is complete: does not happen
-        // prediction from the parent, separably through LDS (x, then y, then z: the
-        // operation order of predict_cell)
-        const int o[3] = {m.bx & 1, m.by & 1, m.bz & 1};
-        int me[3], c0[3], p0[3], np[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            // evaluation points and the first child index: the boundary cell (zero
-            // gradient), the mirror images of the region's cells (symmetry), or the region
-            const bool ma = (mirbits >> a) & 1;
-            me[a] = ma ? g.n[a] : (g.clamp[a] >= 0 ? 1 : g.n[a]);
-            c0[a] = ma ? mir_index(g, a) - (g.lo[a] + g.n[a] - 1) : (g.clamp[a] >= 0 ? g.clamp[a] : g.lo[a]);
-            p0[a] = parent_of(c0[a], o[a]) - 2;
-            np[a] = parent_of(c0[a] + me[a] - 1, o[a]) + 2 - p0[a] + 1;
-        }
-        const T *pu = U + (size_t)m.parent * 5 * CELLS_P;
-        const Div dp0(np[0]), dp1(np[1]), dm0(me[0]), dm1(me[1]);
-        // the parent region of component qi is loaded into registers while component
-        // qi - 1 runs its passes (at most PR_A / TPB values per thread)
-        constexpr int NAT = (PR_A + TPB - 1) / TPB;
-        const int na = np[0] * np[1] * np[2];
-        int aoff[NAT];
-#pragma unroll
-        for (int n = 0; n < NAT; ++n) {
-            const int t = tid + n * TPB;
-            const int t1 = dp0.quot(t), kk = dp1.quot(t1);
-            const int ii = t - t1 * np[0], jj = t1 - kk * np[1];
-            aoff[n] = pidx(0, p0[2] + kk, p0[1] + jj, p0[0] + ii);
-        }
-        T av[NAT];
-        auto load_a = [&](int q) {
-#pragma unroll
-            for (int n = 0; n < NAT; ++n)
-                if (tid + n * TPB < na) av[n] = pu[q * CELLS_P + aoff[n]];
-        };
-        load_a(0);
-        for (int qi = 0; qi < nq; ++qi) {
-            const int q = re ? 4 * qi : qi;
-#pragma unroll
-            for (int n = 0; n < NAT; ++n)
-                if (tid + n * TPB < na) A[tid + n * TPB] = av[n];
-            if (qi + 1 < nq) load_a(re ? 4 * (qi + 1) : qi + 1);
-            __syncthreads();
-            const int nx = np[2] * np[1] * me[0];
-            for (int t = tid; t < nx; t += TPB) {
-                const int t1 = dm0.quot(t), kk = dp1.quot(t1);
-                const int ex = t - t1 * me[0], jj = t1 - kk * np[1];
-                const int c = c0[0] + ex;
-                const int I = parent_of(c, o[0]) - p0[0];
-                const T *row = A + (kk * np[1] + jj) * np[0] + I;
-                const T sx = ((c - HW) & 1) ? (T)-1 : (T)1;
-                X[t] = pred1<T>(row[-2], row[-1], row[0], row[1], row[2], sx);
-            }
-            __syncthreads();
-            const int ny = np[2] * me[1] * me[0];
-            for (int t = tid; t < ny; t += TPB) {
-                const int t1 = dm0.quot(t), kk = dm1.quot(t1);
-                const int ex = t - t1 * me[0], ey = t1 - kk * me[1];
-                const int c = c0[1] + ey;
-                const int J = parent_of(c, o[1]) - p0[1];
-                const T *col = X + (kk * np[1] + J) * me[0] + ex;
-                const int st = me[0];
-                const T sy = ((c - HW) & 1) ? (T)-1 : (T)1;
-                Y[t] = pred1<T>(col[-2 * st], col[-st], col[0], col[st], col[2 * st], sy);
-            }
-            __syncthreads();
-            for (int t = tid; t < ncell; t += TPB) {
-                const int t1 = d0.quot(t), dz = d1.quot(t1);
-                const int dx = t - t1 * g.n[0], dy = t1 - dz * g.n[1];
-                // evaluation point of the cell: its mirror image runs backwards
-                const int ex = (mirbits & 1) ? g.n[0] - 1 - dx : (g.clamp[0] >= 0 ? 0 : dx);
-                const int ey = (mirbits & 2) ? g.n[1] - 1 - dy : (g.clamp[1] >= 0 ? 0 : dy);
-                const int ez = (mirbits & 4) ? g.n[2] - 1 - dz : (g.clamp[2] >= 0 ? 0 : dz);
-                const int c = c0[2] + ez;
-                const int K = parent_of(c, o[2]) - p0[2];
-                const int st = me[0] * me[1];
-                const T *col = Y + (K * me[1] + ey) * me[0] + ex;
-                const T sz = ((c - HW) & 1) ? (T)-1 : (T)1;
-                dst[pidx(q, g.lo[2] + dz, g.lo[1] + dy, g.lo[0] + dx)] =
-                    msign(q) * pred1<T>(col[-2 * st], col[-st], col[0], col[st], col[2 * st], sz);
-            }
-            __syncthreads();
         }
     }
 }
@@ -951,7 +956,13 @@ template <typename T>
 hipError_t launch_fill_halos(T *U, const WorkList &wl, const DevTables &tb, FillMode mode,
                              hipStream_t st) {
     if (wl.grid <= 0) return hipSuccess;
-    const dim3 grid = grid2(round_xcd(wl.grid), (mode & FILL_FACES) ? 6 : 26);
+    // one workgroup per region, except in the mode before the details (all 26 regions of
+    // the jump leaves, most of them read in place and skipped): two per block, 13 regions
+    // each (0.42 -> 0.38 ms per step of config 5; one workgroup per block in the stages'
+    // missing-faces mode measured no faster)
+    const int nreg = (mode & FILL_FACES) ? 6 : 26;
+    const int gy = ((mode & FILL_MISSING) && !(mode & FILL_FACES)) ? 2 : nreg;
+    const dim3 grid = grid2(round_xcd(wl.grid), gy);
     if (tb.ext_bc)
         hipLaunchKernelGGL((k_fill_halos<T, true>), grid, dim3(TPB), 0, st, U, wl, tb.meta, tb.nbr, (int)mode,
                            (const T *)tb.bcfix);

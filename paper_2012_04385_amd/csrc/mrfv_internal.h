@@ -31,6 +31,8 @@ struct BlockMeta {
                       // (no jump correction): the fused stage writes its restriction into
                       // the parent's octant
     int32_t lpos;     // position in the all-leaves list (-1: not a leaf)
+    int32_t pmask;    // non-leaf blocks: bit i set when a stage's prediction of a finer halo
+                      // reads halo region i of this block (make_region's index of the 26)
 };
 
 // Per-instance parameters on the device.
@@ -218,8 +220,10 @@ constexpr int N_DESC = 5 + DESC_PER_LEVEL * MAX_LEVELS;
 // FILL_RHO_E limits any mode to the density and energy components (the details read
 // nothing else).  FILL_PRESENT (with FILL_FACES) copies only: faces without a same-level
 // neighbour keep their values (the integrated jump halos of local time stepping).
+// FILL_MASKED (with FILL_ALL, for the prediction sources of a stage) fills only the
+// regions in the block's pmask.
 enum FillMode { FILL_ALL = 0, FILL_FACES = 1, FILL_MISSING = 2, FILL_MISSING_FACES = 3, FILL_RHO_E = 4,
-                FILL_PRESENT = 8 };
+                FILL_PRESENT = 8, FILL_MASKED = 16 };
 
 // --------------------------------------------------------------- kernel launchers ----
 // All launchers enqueue on `st` and return hipGetLastError().

@@ -198,7 +198,7 @@ std::vector<int> Topology::alive_sorted() const {
 void Topology::build(std::vector<BlockMeta> &meta, std::vector<int32_t> &child,
                      std::vector<int32_t> &nbr, HostLists &L) const {
     const int cap = capacity();
-    meta.assign(cap, BlockMeta{0, 0, 0, 0, 0, -1, 0, 0, 0, -1});
+    meta.assign(cap, BlockMeta{0, 0, 0, 0, 0, -1, 0, 0, 0, -1, 0});
     child.assign((size_t)cap * 8, -1);
     nbr.assign((size_t)cap * 27, -2);
     const std::vector<int> order = alive_sorted();
@@ -207,7 +207,7 @@ void Topology::build(std::vector<BlockMeta> &meta, std::vector<int32_t> &child,
     for (int s : order) {
         const HostBlock &b = blocks_[s];
         const mrfv_instance &p = inst_[b.inst];
-        BlockMeta m{b.inst, b.level, b.bx, b.by, b.bz, b.parent, b.leaf ? 1 : 0, 0, 0, -1};
+        BlockMeta m{b.inst, b.level, b.bx, b.by, b.bz, b.parent, b.leaf ? 1 : 0, 0, 0, -1, 0};
         const int c[3] = {b.bx, b.by, b.bz};
         for (int a = 0; a < 3; ++a) {
             const int n = p.n0[a] << b.level;
@@ -252,6 +252,53 @@ void Topology::build(std::vector<BlockMeta> &meta, std::vector<int32_t> &child,
         }
         meta[s].srestr = coarse_side ? 0 : 1;
     }
+    // Halo regions of the prediction sources that a stage's predictions read.  A region of
+    // block s (direction r) is predicted from the parent when, with the axes that point at
+    // a clamped boundary taken out, it has no same-level neighbour (and no fixed values).
+    // Its cells, and the evaluation points of clamped axes, lie along axis a within the
+    // parent's cells (octant o): r_a = 0 -> the interior and the halo on side o_a (two
+    // layers); r_a pointing out of the parent -> that side's halo and the interior; r_a
+    // pointing at the sibling -> the interior only (the five-point stencils included).
+    // Leaves mark their parents for the predicted face regions of a stage's fill, then
+    // masked regions that are predicted themselves mark the next coarser level.
+    auto predicted = [&](int s, int reg) {
+        const int32_t zg = meta[s].zg;
+        const int r[3] = {reg % 3 - 1, (reg / 3) % 3 - 1, reg / 9 - 1};
+        int q[3];
+        for (int a = 0; a < 3; ++a) {
+            const int side = r[a] < 0 ? 0 : 1;
+            if (r[a] != 0 && ((zg >> (12 + 2 * a + side)) & 1)) return false;   // fixed values
+            q[a] = (r[a] != 0 && ((zg >> (2 * a + side)) & 1)) ? 0 : r[a];
+        }
+        if (q[0] == 0 && q[1] == 0 && q[2] == 0) return false;   // own cells (clamped)
+        return nbr[(size_t)s * 27 + (q[2] + 1) * 9 + (q[1] + 1) * 3 + (q[0] + 1)] < 0;
+    };
+    auto need = [&](int s, int reg) {
+        const HostBlock &b = blocks_[s];
+        const int o[3] = {b.bx & 1, b.by & 1, b.bz & 1};
+        const int r[3] = {reg % 3 - 1, (reg / 3) % 3 - 1, reg / 9 - 1};
+        int lo[3], hi[3];
+        for (int a = 0; a < 3; ++a) {
+            const int d = r[a] == 0 ? (o[a] ? 1 : -1) : ((r[a] > 0) == (o[a] == 1) ? r[a] : 0);
+            lo[a] = std::min(0, d);
+            hi[a] = std::max(0, d);
+        }
+        for (int z = lo[2]; z <= hi[2]; ++z)
+            for (int y = lo[1]; y <= hi[1]; ++y)
+                for (int x = lo[0]; x <= hi[0]; ++x) {
+                    const int g = (z + 1) * 9 + (y + 1) * 3 + (x + 1);
+                    if (g != 13) meta[b.parent].pmask |= 1 << (g < 13 ? g : g - 1);
+                }
+    };
+    for (int s : order)
+        if (blocks_[s].leaf && blocks_[s].parent >= 0)
+            for (int reg : {12, 14, 10, 16, 4, 22})
+                if (predicted(s, reg)) need(s, reg);
+    for (int l = maxl; l >= 1; --l)
+        for (int s : order)
+            if (blocks_[s].level == l && !blocks_[s].leaf && meta[s].pmask)
+                for (int i = 0; i < 26; ++i)
+                    if (((meta[s].pmask >> i) & 1) && predicted(s, i < 13 ? i : i + 1)) need(s, i < 13 ? i : i + 1);
     // work lists
     const int n_inst = (int)inst_.size();
     L.data.assign(2 * n_inst, 0);
@@ -368,7 +415,7 @@ void Topology::build(std::vector<BlockMeta> &meta, std::vector<int32_t> &child,
         L.j26_cnt[l] = (int32_t)L.data.size() - L.j26_off[l];
         L.pfill_off[l] = (int32_t)L.data.size();
         for (int s : order)
-            if (blocks_[s].level == l && !blocks_[s].leaf && pf[s]) L.data.push_back(s);
+            if (blocks_[s].level == l && !blocks_[s].leaf && pf[s] && meta[s].pmask) L.data.push_back(s);
         L.pfill_cnt[l] = (int32_t)L.data.size() - L.pfill_off[l];
         L.pproj_off[l] = (int32_t)L.data.size();
         for (int s : order)
