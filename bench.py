@@ -494,7 +494,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device copy of 512 MiB (calibrates HBM byte counters)")
     ap.add_argument("--lts", action="store_true",
-                    help="only run local time stepping against global steps (plain kernels)")
+                    help="only run local time stepping against global steps (per-block context; FP32 takes "
+                         "the flux divergence from the fused kernel)")
     ap.add_argument("--lts-macro-steps", type=int, default=2)
     ap.add_argument("--eos-compare", action="store_true",
                     help="only run the Sod tube with Tait's equation against the stiffened gas "

@@ -267,8 +267,10 @@ int mrfv_run(mrfv_ctx *ctx, void *U, void *U0, void *L, double *dt_dev, int32_t 
  * fluxes with the RK weights, and a coarse leaf next to a refined same-level neighbour
  * replaces its own sum by the fine average at the end of its step (coarse cell
  * adjustment).  Adaptive instances run mr_flag, commit_flags and mr_predict once, after
- * the last micro step.  Runs on the plain per-block kernels in the context's dtype (any
- * batched mode).  U0: dev scratch of mrfv_interior_bytes, as for mrfv_step; L is not used
+ * the last micro step.  Runs per tree level in the context's dtype (any batched mode):
+ * in FP32 the fused stage kernel evaluates the flux divergence (Tait's system: the plain
+ * flux kernel), in FP64 the plain flux kernel; separate kernels integrate it.  U0: dev
+ * scratch of mrfv_interior_bytes, as for mrfv_step; L is not used
  * (may be NULL); the library allocates its padded flux-divergence field, the jump-halo
  * stage state and the face-flux sums on first use (MRFV_ENOMEM if it cannot).  cell_updates_host (may be
  * NULL): leaf cells times their own steps in this macro step.  Every instance must have
