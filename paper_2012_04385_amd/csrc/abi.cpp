@@ -995,8 +995,10 @@ int do_lts_macro(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt, int64_t *cell_up
             for (int l = lo_rhs; l <= top; ++l) {
                 const WorkList w = wlist(ctx, desc_leaf(l));
                 if (fused) {
-                    HIP_OK(launch_fill_halos<T>(U, w, ctx->tb, (FillMode)(FILL_MISSING_FACES | FILL_PRESENT),
-                                                ctx->stream));
+                    // the boundary faces (nothing else) when some axis is not periodic
+                    if (ctx->bounded)
+                        HIP_OK(launch_fill_halos<T>(U, w, ctx->tb, (FillMode)(FILL_MISSING_FACES | FILL_PRESENT),
+                                                    ctx->stream));
                     HIP_OK(launch_rhs_update_f32(ctx->cfg.scheme, ctx->rhs_variant, -1, dt, (const float *)U, (float *)F,
                                                  (float *)U0, wlist(ctx, desc_leaf(l), 1 << 30), ctx->tb,
                                                  ctx->d_inst, (float *)FF, ctx->d_err, 0, nullptr, ctx->stream));
@@ -1114,9 +1116,11 @@ int mrfv_create(mrfv_ctx **out, const mrfv_config *cfg, const mrfv_instance *ins
     }
     ALLOC(ctx->d_inst, sizeof(InstDev) * id.size());
     for (int i = 0; i < cfg->n_instances; ++i)
-        for (int a = 0; a < 3; ++a)
+        for (int a = 0; a < 3; ++a) {
+            if (inst[i].bc[a] != MRFV_BC_PERIODIC) ctx->bounded = true;
             if (inst[i].bc[a] == MRFV_BC_SYMMETRY || inst[i].bc[a] == MRFV_BC_FIXED)
                 ctx->tb.ext_bc = ctx->tb2.ext_bc = true;
+        }
     {
         // fixed-value halo states, conservative in the context dtype
         bool any = false;

@@ -424,6 +424,7 @@ struct mrfv_ctx {
     // kernel timing
     bool has_jumps = false;            // some leaf has a non-leaf same-level face neighbour
     bool viscous = false;              // some instance has mu > 0 (plain path only)
+    bool bounded = false;              // some instance has a non-periodic axis
     bool capturing = false;            // recording a step graph
     // step graphs: the CFL pass takes the block maxima the previous step wrote after its
     // last stage (set by mrfv_run for a step that follows a step on the same tree)
