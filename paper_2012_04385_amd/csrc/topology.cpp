@@ -297,8 +297,10 @@ void Topology::build(std::vector<BlockMeta> &meta, std::vector<int32_t> &child,
     for (int l = maxl; l >= 1; --l)
         for (int s : order)
             if (blocks_[s].level == l && !blocks_[s].leaf && meta[s].pmask)
-                for (int i = 0; i < 26; ++i)
-                    if (((meta[s].pmask >> i) & 1) && predicted(s, i < 13 ? i : i + 1)) need(s, i < 13 ? i : i + 1);
+                for (int i = 0; i < 26; ++i) {
+                    const int reg = i < 13 ? i : i + 1;
+                    if (((meta[s].pmask >> i) & 1) && predicted(s, reg)) need(s, reg);
+                }
     // work lists
     const int n_inst = (int)inst_.size();
     L.data.assign(2 * n_inst, 0);
