@@ -3,7 +3,8 @@ algo:Integration) on the GPU with the oracle's, through the C ABI.
 
 Tree: four levels (a level-0 leaf next to level-1 leaves, one- and two-level jumps, a
 refined group touching the periodic boundary), a Gaussian pulse in density and pressure
-carried by a uniform flow, so that waves cross the jumps.
+carried by a uniform flow, so that waves cross the jumps; periodic, and once with
+zero-gradient, periodic and symmetry axes.
 
 Tolerances: FP64 -- 1e-12 relative on leaf states after the macro steps (the plain
 kernels' face fluxes differ from the oracle's in summation order at the 1e-16 level,
@@ -45,8 +46,9 @@ def _pulse(pb, key):
                      p / (GAMMA - 1) + 0.5 * rho * (u * u + v * v + w * w)])
 
 
-def _pair(orc, dtype, adapt=0, batched=False):
+def _pair(orc, dtype, adapt=0, batched=False, bc=(0, 0, 0)):
     pb = W.uniform_flow(lmax=3, n0=(2, 2, 2))
+    pb.bc = bc
     o, g = make_pair(orc, pb, REFS, dtype, batched, adapt=adapt)
     o.coarsen(0, 1, 0, 1)
     g.coarsen(0, 0, 1, 0, 1)
@@ -79,6 +81,25 @@ def test_lts_static_tree(orc, torch_mod, dtype, batched, tol):
         expect = sum((1 << k[0]) * N ** 3 for k in o.leaf_states())
         assert cells == expect
     np.testing.assert_array_equal(o.lts_steps()[:4], [2, 4, 8, 16])
+    worst = _worst(o, g)
+    print(f"[lts] worst relative difference {worst:.3e}", flush=True)
+    assert worst < tol, worst
+
+
+@pytest.mark.parametrize("dtype,batched,tol", [("f64", False, 1e-12), ("f32", False, 5e-6), ("f32", True, 5e-6)])
+def test_lts_bounded_tree(orc, torch_mod, dtype, batched, tol):
+    # zero-gradient x, periodic y, symmetry z: the boundary fill before each flux
+    # evaluation (FP32: before the fused kernel's flux-divergence mode) and the clamped and
+    # mirrored predictions of the flux divergence
+    o, g = _pair(orc, dtype, batched=batched, bc=(1, 0, 2))
+    print(f"[lts] bounded tree {dtype} batched={batched}", flush=True)
+    for m in range(2):
+        dt_o = o.step_lts()
+        g.step_lts()
+        torch_mod.cuda.synchronize()
+        g.check()
+        dt_g = float(g.dt.cpu()[0])
+        assert abs(dt_g - dt_o) <= (1e-14 if dtype == "f64" else 1e-6) * dt_o, m
     worst = _worst(o, g)
     print(f"[lts] worst relative difference {worst:.3e}", flush=True)
     assert worst < tol, worst
