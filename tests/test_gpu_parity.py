@@ -118,9 +118,9 @@ def test_rhs_with_jump_correction(orc, torch_mod, dtype, batched):
     assert worst < tol, worst
 
 
-def _stage_update_parity(orc, torch_mod, dtype, batched):
+def _stage_update_parity(orc, torch_mod, dtype, batched, bc=(0, 1, 0)):
     """One full time step without adaptation (cfl, 3 x {project, fill, rhs, update})."""
-    pb = jump_problem((0, 1, 0))
+    pb = jump_problem(bc)
     o, g = make_pair(orc, pb, REFS, dtype, batched)
     rng = np.random.default_rng(5)
     set_interiors(o, g, lambda k: random_physical(rng, (N, N, N), rough=0.01))
@@ -133,9 +133,12 @@ def _stage_update_parity(orc, torch_mod, dtype, batched):
     return o, g, dt_o, dt_g
 
 
+@pytest.mark.parametrize("bc", [(0, 1, 0), (2, 1, 0)])
 @pytest.mark.parametrize("dtype,batched", [("f64", False), ("f32", True), ("f32", False)])
-def test_full_step_with_jumps(orc, torch_mod, dtype, batched):
-    o, g, dt_o, dt_g = _stage_update_parity(orc, torch_mod, dtype, batched)
+def test_full_step_with_jumps(orc, torch_mod, dtype, batched, bc):
+    # one- and two-level jumps next to periodic, zero-gradient and (second case) symmetry
+    # sides: on the fused path the parents fill only the halo regions predictions read
+    o, g, dt_o, dt_g = _stage_update_parity(orc, torch_mod, dtype, batched, bc)
     assert abs(dt_g - dt_o) <= (1e-14 if dtype == "f64" else 1e-6) * dt_o
     ol, gl = o.leaf_states(), g.leaf_states()
     tol = 1e-12 if dtype == "f64" else 2e-6
