@@ -999,18 +999,24 @@ int do_lts_macro(mrfv_ctx *ctx, T *U, T *U0, T *Lb, double *dt, int64_t *cell_up
                     if (ctx->bounded)
                         HIP_OK(launch_fill_halos<T>(U, w, ctx->tb, (FillMode)(FILL_MISSING_FACES | FILL_PRESENT),
                                                     ctx->stream));
+                    // (leaves without a non-leaf same-level face neighbour also write the
+                    // restriction of their L into the parent's octant of F)
                     HIP_OK(launch_rhs_update_f32(ctx->cfg.scheme, ctx->rhs_variant, -1, dt, (const float *)U, (float *)F,
                                                  (float *)U0, wlist(ctx, desc_leaf(l), 1 << 30), ctx->tb,
-                                                 ctx->d_inst, (float *)FF, ctx->d_err, 0, nullptr, ctx->stream));
+                                                 ctx->d_inst, (float *)FF, ctx->d_err, 1, nullptr, ctx->stream));
                     continue;
                 }
                 HIP_OK(launch_fill_halos<T>(U, w, ctx->tb, (FillMode)(FILL_FACES | FILL_PRESENT), ctx->stream));
                 HIP_OK(launch_flux<T>(flux_kernel(ctx), U, w, ctx->tb, ctx->d_inst, D, FF, ctx->stream));
                 HIP_OK(launch_lts_combine<T>(D, F, w, ctx->tb, ctx->d_inst, U, ctx->stream));
             }
-            // averaged into the parents, predicted into the jump halos
-            for (int p = top - 1; p >= std::max(lo_rhs, 1) - 1; --p)
-                HIP_OK(launch_project<T>(F, wlist(ctx, desc_par(p)), ctx->tb, ctx->stream));
+            // averaged into the parents (in FP32 the octants the fused kernel wrote are
+            // skipped: every leaf below these parents was evaluated in this stage), predicted
+            // into the jump halos
+            for (int p = top - 1; p >= std::max(lo_rhs, 1) - 1; --p) {
+                if (fused && L.par_srestr[p]) continue;   // every child wrote its octant
+                HIP_OK(launch_project<T>(F, wlist(ctx, desc_par(p)), ctx->tb, ctx->stream, 31, fused));
+            }
             CALL(do_fill<T>(ctx, F, 1 << 20, FILL_MISSING_FACES, true));
             // algo:Integration of the levels that end a step at r
             for (int l = lo_end; l <= top; ++l)

@@ -1003,7 +1003,10 @@ void k_rhs_update(int stage, const double *__restrict__ dt,
             if (P.has_source) add_source(P, us, lq);   // uniform per workgroup
             if (stage < 0) {   // flux divergence only (local time stepping): L into Uout
 #pragma unroll
-                for (int q = 0; q < 5; ++q) ob[o + q * CELLS_P] = lq[q];
+                for (int q = 0; q < 5; ++q) {
+                    ob[o + q * CELLS_P] = lq[q];
+                    unew[p][q] = lq[q];   // restricted like a new state
+                }
                 continue;
             }
 #pragma unroll

@@ -306,8 +306,8 @@ hipError_t launch_update(int stage, const double *dt, T *U, T *U0, const T *L,
 // restrict_parents: leaves with meta.srestr also write the restriction of their new state
 // (all components) into their parent's octant of Uout.
 // stage < 0: no update; Uout (a padded field) receives the interior flux divergence
-// L = -sum_d dF_d / dx + S (local time stepping); U0 is not touched, restrict_parents and
-// cflmax must be 0 / null.
+// L = -sum_d dF_d / dx + S (local time stepping), and with restrict_parents its
+// restriction into the parents' octants of Uout; U0 is not touched, cflmax must be null.
 hipError_t launch_rhs_update_f32(int scheme, int variant, int stage, const double *dt, const float *Uin,
                                  float *Uout, float *U0, const WorkList &leaves, const DevTables &tb,
                                  const InstDev *inst, float *FF, int32_t *err, int restrict_parents,
