@@ -38,7 +38,7 @@ sys.path.insert(0, ROOT)
 # cell per axis; 40 per cell for the update.
 FACE_BASE, LLF_EXTRA, UPDATE = 734.0, 110.0, 40.0
 PEAK_FP32_VECTOR = 157.3e12       # MI355X FP32 vector with packed FP32 (FLOP/s)
-PEAK_FP32_UNPACKED = 78.6e12      # without packed FP32 instructions (this build)
+PEAK_FP32_UNPACKED = 78.6e12      # without packed FP32 instructions (compiled out here)
 PEAK_FP64_VECTOR = 78.6e12        # MI355X FP64 vector (FLOP/s)
 PEAK_HBM = 8.0e12                 # bytes/s
 # algorithmic bytes per FP32 cell-update of the fused kernel, every stage: read the interior
@@ -540,7 +540,8 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
+              "(the library runs on one GPU; how the path would shard across GPUs is described, "
+              "not implemented)", file=sys.stderr)
         sys.exit(2)
 
     name = args.workload
